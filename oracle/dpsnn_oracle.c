@@ -1,0 +1,433 @@
+/*
+ * dpsnn_oracle.c -- plain, slow CPU oracle of the DPSNN per-1 ms simulation step.
+ *
+ * TEST INFRASTRUCTURE ONLY (see dpsnn_oracle.h).  Written for readability, not speed:
+ * every neuron and every synapse is visited with ordinary loops, in the order the
+ * method describes.  Build with -O2 -ffp-contract=off so that float32 expressions are
+ * evaluated exactly as written.
+ */
+#include "dpsnn_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------------------
+ * Philox4x32-10, from its published definition (Salmon, Moraes, Dror, Shaw,
+ * "Parallel random numbers: as easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64
+ * multiplications with the constants below, the high halves xor-ed with the other
+ * two counter words and the key, the key bumped by the Weyl constants between rounds.
+ * ------------------------------------------------------------------------- */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(prod1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)prod1;
+    uint32_t n2 = (uint32_t)(prod0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)prod0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void draw(const orc_config_t* cfg, uint32_t a, uint32_t b, uint32_t c, uint32_t stream,
+                 uint32_t out[4]) {
+  uint32_t ctr[4] = {a, b, c, stream};
+  uint32_t key[2] = {(uint32_t)(cfg->seed & 0xffffffffu), (uint32_t)(cfg->seed >> 32)};
+  orc_philox(ctr, key, out);
+}
+
+/* ---------------------------------------------------------------------------
+ * Network (paper section 2, Methods).  Columns sit on a rows x cols grid, periodic in
+ * both directions.  Column c = y*cols + x, neuron j = c*npc + k, k < n_exc excitatory
+ * (80 % / 20 % split).  A neuron projects to its own column with pair probability p_own
+ * and to the 8 surrounding columns with a total share p_remote of the row, each
+ * neighbour weighted by exp(-r/decay) with r its centre distance (1 or sqrt 2 spacings).
+ * When the grid is so small that several stencil offsets land on the same column, the
+ * offsets' probabilities are added, in stencil order (dy = -1, 0, 1 outer; dx inner).
+ * ------------------------------------------------------------------------- */
+static double offset_probability(const orc_config_t* cfg, int dy, int dx) {
+  if (dy == 0 && dx == 0) return cfg->p_own;
+  double edge = exp(-(cfg->spacing_um / cfg->decay_um));
+  double diag = exp(-(sqrt(2.0) * cfg->spacing_um / cfg->decay_um));
+  double norm = 4.0 * edge + 4.0 * diag;
+  double one = (dy == 0 || dx == 0) ? edge : diag;
+  return cfg->p_remote * one / norm;
+}
+
+double orc_column_probability(const orc_config_t* cfg, int32_t src_col, int32_t tgt_col) {
+  int sy = src_col / cfg->cols, sx = src_col % cfg->cols;
+  double p = 0.0;
+  for (int dy = -1; dy <= 1; ++dy) {
+    for (int dx = -1; dx <= 1; ++dx) {
+      int ty = ((sy + dy) % cfg->rows + cfg->rows) % cfg->rows;
+      int tx = ((sx + dx) % cfg->cols + cfg->cols) % cfg->cols;
+      if (ty * cfg->cols + tx == tgt_col) p = p + offset_probability(cfg, dy, dx);
+    }
+  }
+  return p;
+}
+
+/* Integer threshold of a probability: connect iff the 32-bit uniform is below it. */
+static uint64_t prob_threshold(double p) {
+  double t = floor(p * 4294967296.0);
+  if (t <= 0.0) return 0;
+  if (t >= 4294967296.0) return (uint64_t)1 << 32;
+  return (uint64_t)t;
+}
+
+/* One pair: a Bernoulli trial with the column-pair probability, then an integer delay
+ * uniform on [d_min, d_max] and a normal weight (sum of twelve 16-bit uniforms, the
+ * Irwin-Hall approximation, bounded at 6 sigma) quantised to 2^-14 mV. */
+static int pair_given_threshold(const orc_config_t* cfg, int64_t i, int64_t j, uint64_t thr,
+                                int32_t* delay, int16_t* wq) {
+  if (i == j) return 0;
+  uint32_t r[4], r2[4];
+  draw(cfg, (uint32_t)j, (uint32_t)i, 0u, ORC_STREAM_SYN, r);
+  if ((uint64_t)r[0] >= thr) return 0;
+  uint32_t span = (uint32_t)(cfg->d_max - cfg->d_min + 1);
+  *delay = cfg->d_min + (int32_t)(((uint64_t)r[1] * (uint64_t)span) >> 32);
+  draw(cfg, (uint32_t)j, (uint32_t)i, 1u, ORC_STREAM_SYN, r2);
+  uint32_t words[6] = {r[2], r[3], r2[0], r2[1], r2[2], r2[3]};
+  int32_t sum = 0;
+  for (int q = 0; q < 6; ++q) sum += (int32_t)(words[q] & 0xffffu) + (int32_t)(words[q] >> 16);
+  double z = (double)(sum - 393210) / 65536.0;
+  int exc = (int32_t)(i % cfg->npc) < cfg->n_exc;
+  double mu = exc ? cfg->we_mu : cfg->wi_mu;
+  double sigma = exc ? cfg->we_sigma : cfg->wi_sigma;
+  double w = mu + sigma * z;
+  *wq = (int16_t)rint(w * 16384.0);
+  return 1;
+}
+
+int orc_pair(const orc_config_t* cfg, int64_t i, int64_t j, int32_t* delay, int16_t* wq) {
+  int32_t ci = (int32_t)(i / cfg->npc), cj = (int32_t)(j / cfg->npc);
+  uint64_t thr = prob_threshold(orc_column_probability(cfg, ci, cj));
+  return pair_given_threshold(cfg, i, j, thr, delay, wq);
+}
+
+typedef struct { int32_t d, j; int16_t w; } syn_t;
+
+static int syn_order(const void* a, const void* b) {
+  const syn_t* x = (const syn_t*)a;
+  const syn_t* y = (const syn_t*)b;
+  if (x->d != y->d) return x->d < y->d ? -1 : 1;
+  if (x->j != y->j) return x->j < y->j ? -1 : 1;
+  return 0;
+}
+
+int64_t orc_row(const orc_config_t* cfg, int64_t i, int32_t* tgt, uint8_t* dly, int16_t* wq,
+                int64_t cap) {
+  int32_t ncol = cfg->rows * cfg->cols;
+  int32_t ci = (int32_t)(i / cfg->npc);
+  syn_t* tmp = (syn_t*)malloc(sizeof(syn_t) * (size_t)(9 * cfg->npc + 1));
+  int64_t n = 0;
+  for (int32_t c = 0; c < ncol; ++c) {
+    double p = orc_column_probability(cfg, ci, c);
+    if (p <= 0.0) continue;
+    uint64_t thr = prob_threshold(p);
+    for (int32_t k = 0; k < cfg->npc; ++k) {
+      int64_t j = (int64_t)c * cfg->npc + k;
+      int32_t d; int16_t w;
+      if (pair_given_threshold(cfg, i, j, thr, &d, &w)) { tmp[n].d = d; tmp[n].j = (int32_t)j; tmp[n].w = w; ++n; }
+    }
+  }
+  qsort(tmp, (size_t)n, sizeof(syn_t), syn_order);
+  if (n > cap) { free(tmp); return -1; }
+  for (int64_t q = 0; q < n; ++q) { tgt[q] = tmp[q].j; dly[q] = (uint8_t)tmp[q].d; wq[q] = tmp[q].w; }
+  free(tmp);
+  return n;
+}
+
+int64_t orc_network(const orc_config_t* cfg, int64_t* row_ptr, int32_t* tgt, uint8_t* dly,
+                    int16_t* wq, int64_t cap) {
+  int64_t n = (int64_t)cfg->rows * cfg->cols * cfg->npc;
+  row_ptr[0] = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t len = orc_row(cfg, i, tgt + row_ptr[i], dly + row_ptr[i], wq + row_ptr[i],
+                          cap - row_ptr[i]);
+    if (len < 0) return -1;
+    row_ptr[i + 1] = row_ptr[i] + len;
+  }
+  return row_ptr[n];
+}
+
+/* ---------------------------------------------------------------------------
+ * External input (paper section 2: external synapses as extra excitatory input).  Each
+ * neuron has ext_syn independent Poisson synapses of rate ext_rate_hz, so the number of
+ * external events arriving in one step is Poisson with mean ext_syn * rate * dt.  The
+ * count is drawn by inverse CDF against integer thresholds, capped at 63.
+ * ------------------------------------------------------------------------- */
+void orc_poisson_table(double lam, uint64_t tab[63]) {
+  double pk = exp(-lam);
+  double cdf = 0.0;
+  for (int k = 0; k < 63; ++k) {
+    if (k > 0) pk = pk * lam / (double)k;
+    cdf = cdf + pk;
+    double t = floor(cdf * 4294967296.0);
+    tab[k] = t >= 4294967296.0 ? ((uint64_t)1 << 32) : (uint64_t)t;
+  }
+}
+
+int32_t orc_poisson_count(const uint64_t tab[63], uint32_t x) {
+  int32_t n = 0;
+  for (int k = 0; k < 63; ++k)
+    if (tab[k] <= (uint64_t)x) n += 1;
+  return n;
+}
+
+void orc_ext_counts(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n, int32_t* out) {
+  uint64_t tab[63];
+  orc_poisson_table((double)cfg->ext_syn * cfg->ext_rate_hz * cfg->dt * 1e-3, tab);
+  for (int64_t q = 0; q < n; ++q) {
+    uint32_t r[4];
+    draw(cfg, (uint32_t)(j0 + q), (uint32_t)u, 0u, ORC_STREAM_EXT, r);
+    out[q] = orc_poisson_count(tab, r[0]);
+  }
+}
+
+/* Initial potential uniform on [0, v_reset): 24 random bits scaled exactly, times v_reset. */
+float orc_initial_v(const orc_config_t* cfg, int64_t j) {
+  uint32_t r[4];
+  draw(cfg, (uint32_t)j, 0u, 0u, ORC_STREAM_INIT, r);
+  float unit = (float)(r[0] >> 8) * 0x1p-24f;
+  return (float)cfg->v_reset * unit;
+}
+
+/* ---------------------------------------------------------------------------
+ * Simulation state and the step (paper section 1: time-driven neuron update,
+ * event-driven synaptic delivery; section 2: LIF neurons with calcium-driven
+ * after-hyperpolarisation).
+ * ------------------------------------------------------------------------- */
+struct orc_sim {
+  orc_config_t cfg;
+  int64_t n;
+  const int64_t* row_ptr;
+  const int32_t* tgt;
+  const uint8_t* dly;
+  const int32_t* w32;
+  int32_t D;            /* ring slots: d_max + 1 */
+  float pm, pc, gam, alpha, theta, vreset;
+  int32_t jfx;          /* external efficacy, 2^-16 mV */
+  uint64_t ptab[63];
+  float* v;
+  float* ca;
+  uint8_t* ref;
+  uint32_t* ring;       /* [D][n]; slot u % D holds the input of step u */
+  int64_t now;
+  /* raster: spike ids of all steps, with per-step offsets */
+  int32_t* sp_ids; int64_t sp_n, sp_cap;
+  int64_t* sp_off; int64_t off_cap;
+  int64_t e_rec, e_ext;
+  int64_t consumed;     /* sum of all inputs taken out of the ring (checksum) */
+  /* trajectory recording */
+  int rec_on; int64_t rec_n, rec_cap;
+  float *r_vprev, *r_caprev, *r_vt; uint8_t *r_s, *r_r; int32_t* r_in;
+};
+
+orc_sim_t* orc_sim_create(const orc_config_t* cfg, int64_t n, const int64_t* row_ptr,
+                          const int32_t* tgt, const uint8_t* dly, const int32_t* w32) {
+  orc_sim_t* s = (orc_sim_t*)calloc(1, sizeof(orc_sim_t));
+  s->cfg = *cfg;
+  s->n = n;
+  s->row_ptr = row_ptr; s->tgt = tgt; s->dly = dly; s->w32 = w32;
+  s->D = cfg->d_max + 1;
+  /* constants: computed in double, rounded once to float */
+  s->pm = (float)exp(-cfg->dt / cfg->tau_m);
+  s->pc = (float)exp(-cfg->dt / cfg->tau_ca);
+  s->gam = (float)(cfg->g_ahp * cfg->dt);
+  s->alpha = (float)cfg->ca_inc;
+  s->theta = (float)cfg->theta;
+  s->vreset = (float)cfg->v_reset;
+  s->jfx = (int32_t)rint(cfg->j_ext * 65536.0);
+  orc_poisson_table((double)cfg->ext_syn * cfg->ext_rate_hz * cfg->dt * 1e-3, s->ptab);
+  s->v = (float*)malloc(sizeof(float) * (size_t)n);
+  s->ca = (float*)calloc((size_t)n, sizeof(float));
+  s->ref = (uint8_t*)calloc((size_t)n, 1);
+  s->ring = (uint32_t*)calloc((size_t)s->D * (size_t)n, sizeof(uint32_t));
+  for (int64_t j = 0; j < n; ++j) s->v[j] = orc_initial_v(cfg, j);
+  s->off_cap = 1024;
+  s->sp_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)s->off_cap);
+  s->sp_off[0] = 0;
+  s->sp_cap = 1024;
+  s->sp_ids = (int32_t*)malloc(sizeof(int32_t) * (size_t)s->sp_cap);
+  return s;
+}
+
+void orc_sim_destroy(orc_sim_t* s) {
+  if (!s) return;
+  free(s->v); free(s->ca); free(s->ref); free(s->ring);
+  free(s->sp_ids); free(s->sp_off);
+  free(s->r_vprev); free(s->r_caprev); free(s->r_vt); free(s->r_s); free(s->r_r);
+  free(s->r_in);
+  free(s);
+}
+
+void orc_sim_record(orc_sim_t* s, int on) { s->rec_on = on; }
+
+static void push_spike(orc_sim_t* s, int32_t j) {
+  if (s->sp_n == s->sp_cap) {
+    s->sp_cap *= 2;
+    s->sp_ids = (int32_t*)realloc(s->sp_ids, sizeof(int32_t) * (size_t)s->sp_cap);
+  }
+  s->sp_ids[s->sp_n++] = j;
+}
+
+static void grow_record(orc_sim_t* s) {
+  if (s->rec_n < s->rec_cap) return;
+  s->rec_cap = s->rec_cap ? 2 * s->rec_cap : 64;
+  size_t m = (size_t)s->rec_cap * (size_t)s->n;
+  s->r_vprev = (float*)realloc(s->r_vprev, sizeof(float) * m);
+  s->r_caprev = (float*)realloc(s->r_caprev, sizeof(float) * m);
+  s->r_vt = (float*)realloc(s->r_vt, sizeof(float) * m);
+  s->r_s = (uint8_t*)realloc(s->r_s, m);
+  s->r_r = (uint8_t*)realloc(s->r_r, m);
+  s->r_in = (int32_t*)realloc(s->r_in, sizeof(int32_t) * m);
+}
+
+/* One step u = now:
+ *  1. input: A_j = ring[u % D][j] + n_j(u) * J_ext (int32, wrap-around); the slot is cleared;
+ *     I_j = A_j * 2^-16 mV.
+ *  2. a refractory neuron counts down, stays at V_reset and discards its input;
+ *  3. otherwise V <- ((P_m V) - (gamma Ca)) + I, with P_m = exp(-dt/tau_m) and
+ *     gamma = g_AHP dt; a spike is emitted if V >= theta, then V <- V_reset and the
+ *     refractory counter is set;
+ *  4. Ca <- P_c Ca + alpha s, with P_c = exp(-dt/tau_Ca);
+ *  5. the spikes of the step are recorded in ascending order and counted as events
+ *     (each outgoing synapse of a spiking neuron is one recurrent event; each external
+ *     arrival is one external event);
+ *  6. every synapse i->j of delay d of a spiking neuron i adds its efficacy to
+ *     ring[(u + d) % D][j]. */
+int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
+  for (int64_t it = 0; it < n_steps; ++it) {
+    int64_t u = s->now;
+    int64_t slot = u % s->D;
+    uint32_t* in = s->ring + slot * s->n;
+    int64_t first = s->sp_n;
+    if (s->rec_on) grow_record(s);
+    for (int64_t j = 0; j < s->n; ++j) {
+      uint32_t r[4];
+      draw(&s->cfg, (uint32_t)j, (uint32_t)u, 0u, ORC_STREAM_EXT, r);
+      int32_t next = orc_poisson_count(s->ptab, r[0]);
+      uint32_t a = in[j] + (uint32_t)next * (uint32_t)s->jfx;
+      in[j] = 0;
+      s->consumed += (int64_t)(int32_t)a;
+      float cur = (float)(int32_t)a * 0x1p-16f;
+      float vprev = s->v[j], caprev = s->ca[j];
+      float vt = 0.0f;
+      int spike = 0, refr = 0;
+      if (s->ref[j] > 0) {
+        refr = 1;
+        s->ref[j] -= 1;
+        s->v[j] = s->vreset;
+      } else {
+        float leak = s->pm * vprev;
+        float ahp = s->gam * caprev;
+        float drop = leak - ahp;
+        vt = drop + cur;
+        if (vt >= s->theta) {
+          spike = 1;
+          s->v[j] = s->vreset;
+          s->ref[j] = (uint8_t)s->cfg.t_ref;
+        } else {
+          s->v[j] = vt;
+        }
+      }
+      float decayed = s->pc * caprev;
+      s->ca[j] = decayed + (spike ? s->alpha : 0.0f);
+      if (spike) push_spike(s, (int32_t)j);
+      s->e_ext += next;
+      if (s->rec_on) {
+        size_t o = (size_t)s->rec_n * (size_t)s->n + (size_t)j;
+        s->r_vprev[o] = vprev; s->r_caprev[o] = caprev; s->r_vt[o] = vt;
+        s->r_s[o] = (uint8_t)spike; s->r_r[o] = (uint8_t)refr; s->r_in[o] = (int32_t)a;
+      }
+    }
+    if (s->rec_on) s->rec_n += 1;
+    for (int64_t q = first; q < s->sp_n; ++q) {
+      int64_t i = s->sp_ids[q];
+      s->e_rec += s->row_ptr[i + 1] - s->row_ptr[i];
+      for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
+        int64_t dst = ((u + s->dly[k]) % s->D) * s->n + s->tgt[k];
+        s->ring[dst] += (uint32_t)s->w32[k];
+      }
+    }
+    s->now += 1;
+    if (s->now >= s->off_cap) {
+      s->off_cap *= 2;
+      s->sp_off = (int64_t*)realloc(s->sp_off, sizeof(int64_t) * (size_t)s->off_cap);
+    }
+    s->sp_off[s->now] = s->sp_n;
+  }
+  return 0;
+}
+
+int64_t orc_sim_now(const orc_sim_t* s) { return s->now; }
+int32_t orc_sim_ring_slots(const orc_sim_t* s) { return s->D; }
+
+int64_t orc_sim_spikes(const orc_sim_t* s, int64_t u, int32_t* ids, int64_t cap) {
+  if (u < 0 || u >= s->now) return 0;
+  int64_t a = s->sp_off[u], b = s->sp_off[u + 1];
+  if (b - a > cap) return -(b - a);
+  for (int64_t q = a; q < b; ++q) ids[q - a] = s->sp_ids[q];
+  return b - a;
+}
+
+void orc_sim_counts(const orc_sim_t* s, int64_t* spikes, int64_t* e_rec, int64_t* e_ext) {
+  *spikes = s->sp_n; *e_rec = s->e_rec; *e_ext = s->e_ext;
+}
+
+int64_t orc_sim_consumed(const orc_sim_t* s) { return s->consumed; }
+
+void orc_sim_get_state(const orc_sim_t* s, float* v, float* ca, uint8_t* ref, int32_t* pend) {
+  memcpy(v, s->v, sizeof(float) * (size_t)s->n);
+  memcpy(ca, s->ca, sizeof(float) * (size_t)s->n);
+  memcpy(ref, s->ref, (size_t)s->n);
+  for (int32_t q = 0; q < s->D; ++q) {
+    int64_t slot = (s->now + q) % s->D;
+    for (int64_t j = 0; j < s->n; ++j) pend[q * s->n + j] = (int32_t)s->ring[slot * s->n + j];
+  }
+}
+
+void orc_sim_set_state(orc_sim_t* s, int64_t now, const float* v, const float* ca,
+                       const uint8_t* ref, const int32_t* pend) {
+  /* the raster restarts at step `now`: earlier steps are reported empty */
+  if (now + 1 > s->off_cap) {
+    s->off_cap = now + 1024;
+    s->sp_off = (int64_t*)realloc(s->sp_off, sizeof(int64_t) * (size_t)s->off_cap);
+  }
+  for (int64_t q = 0; q <= now; ++q) s->sp_off[q] = s->sp_n;
+  s->now = now;
+  memcpy(s->v, v, sizeof(float) * (size_t)s->n);
+  memcpy(s->ca, ca, sizeof(float) * (size_t)s->n);
+  memcpy(s->ref, ref, (size_t)s->n);
+  for (int32_t q = 0; q < s->D; ++q) {
+    int64_t slot = (now + q) % s->D;
+    for (int64_t j = 0; j < s->n; ++j) s->ring[slot * s->n + j] = (uint32_t)pend[q * s->n + j];
+  }
+}
+
+void orc_sim_inject(orc_sim_t* s, int32_t q, int64_t j, int32_t value) {
+  int64_t slot = (s->now + q) % s->D;
+  s->ring[slot * s->n + j] += (uint32_t)value;
+}
+
+int64_t orc_sim_trajectory(const orc_sim_t* s, float* v_prev, float* ca_prev, float* v_tilde,
+                           uint8_t* spk, uint8_t* refr, int32_t* input, int64_t cap_steps) {
+  int64_t m = s->rec_n < cap_steps ? s->rec_n : cap_steps;
+  size_t cnt = (size_t)m * (size_t)s->n;
+  if (m > 0) {
+    memcpy(v_prev, s->r_vprev, sizeof(float) * cnt);
+    memcpy(ca_prev, s->r_caprev, sizeof(float) * cnt);
+    memcpy(v_tilde, s->r_vt, sizeof(float) * cnt);
+    memcpy(spk, s->r_s, cnt);
+    memcpy(refr, s->r_r, cnt);
+    memcpy(input, s->r_in, sizeof(int32_t) * cnt);
+  }
+  return m;
+}

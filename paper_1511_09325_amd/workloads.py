@@ -1,0 +1,72 @@
+"""Seeded synthetic workloads: parameter sets and recipes, no arithmetic of the method.
+
+This module is pure input description.  It is shared by the HIP path and by the CPU oracle
+(through the tests), so it holds nothing the simulation computes: only parameter values,
+grid shapes, seeds and the seeded draws that choose a workload (batch shapes, target rates).
+
+The column recipe follows the paper's networks (section 2, Methods; Table 1): 1240 point
+neurons per column, 80 % excitatory, grids of 2x2 up to 96x96 columns at 100 um spacing,
+about 1240 outgoing synapses per neuron.  The paper does not print the neuron parameters,
+the weights, the delays or the external rate; the values below are the workload's stated
+ones: E weights N(0.2, 0.02) mV, I weights -N(0.8, 0.08) mV, delays 1-20 ms,
+tau_m 20 ms, threshold 20 mV, reset 15 mV, refractory 2 ms, calcium +0.05 per spike with
+tau_Ca 300 ms and g_AHP 0.2, external input 1000 synapses x 3 Hz x 0.3 mV, dt 1 ms.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+#: Column recipe and neuron parameters of every plain configuration.
+COLUMN_RECIPE = dict(
+    npc=1240, n_exc=992,
+    p_own=0.6, p_remote=0.4, decay_um=100.0, spacing_um=100.0,
+    d_min=1, d_max=20,
+    we_mu=0.2, we_sigma=0.02, wi_mu=-0.8, wi_sigma=0.08,
+    tau_m=20.0, theta=20.0, v_reset=15.0, t_ref=2,
+    tau_ca=300.0, ca_inc=0.05, g_ahp=0.2, dt=1.0,
+    ext_rate_hz=3.0, ext_syn=1000, j_ext=0.3,
+)
+
+
+def grid(rows: int, cols: int, seed: int = 0, **overrides) -> dict:
+    """Parameters of one rows x cols network of the column recipe."""
+    p = dict(COLUMN_RECIPE)
+    p.update(rows=rows, cols=cols, seed=seed)
+    p.update(overrides)
+    return p
+
+
+#: The named workloads (steps are 1 ms each).
+PLAIN_2X2 = dict(params=grid(2, 2, 0), steps=1000, name="plain 2x2 (4,960 neurons), 1 s")
+PLAIN_24X24 = dict(params=grid(24, 24, 0), steps=10000, name="plain 24x24 (714,240 neurons), 10 s")
+PLAIN_96X96 = dict(params=grid(96, 96, 0), steps=2000, name="plain 96x96 (11,427,840 neurons), 2 s")
+FWD_BWD_4X4 = dict(params=grid(4, 4, 0), steps=500, ckpt_every=50,
+                   name="forward+backward 4x4 (19,840 neurons), 500 ms")
+
+
+def batched_networks(n_nets: int = 64, base_seed: int = 0) -> list[dict]:
+    """The batched workload: networks with seeds base_seed .. base_seed+n_nets-1, each grid
+    side drawn uniformly from 2..8 columns and the external rate uniformly from 2..6 Hz.
+    The draws come from numpy's PCG64 seeded with base_seed (a workload choice only)."""
+    rng = np.random.Generator(np.random.PCG64(base_seed))
+    rows = rng.integers(2, 9, size=n_nets)
+    cols = rng.integers(2, 9, size=n_nets)
+    rate = rng.uniform(2.0, 6.0, size=n_nets)
+    return [grid(int(rows[n]), int(cols[n]), base_seed + n, ext_rate_hz=float(rate[n]))
+            for n in range(n_nets)]
+
+
+def target_rates(n_cols: int, seed: int = 1) -> np.ndarray:
+    """Per-column target firing rates of the forward+backward loss, U(2, 8) Hz."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(2.0, 8.0, size=n_cols).astype(np.float32)
+
+
+def tiny(rows: int = 2, cols: int = 2, npc: int = 40, seed: int = 0, **overrides) -> dict:
+    """A small network of the same recipe with fewer neurons per column (80 % excitatory),
+    for tests that the oracle must finish in well under a second.  The weights keep their
+    values; the external drive is raised a little (3.4 Hz per synapse) so that the small
+    network, which lacks most of its recurrent excitation, still fires."""
+    p = grid(rows, cols, seed, npc=npc, n_exc=int(round(0.8 * npc)), ext_rate_hz=3.4)
+    p.update(overrides)
+    return p
