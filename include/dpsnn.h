@@ -1,0 +1,193 @@
+/*
+ * dpsnn.h -- C ABI of the MI355X (gfx950) DPSNN simulation library, libdpsnn.so.
+ *
+ * The library simulates grids of cortical columns of leaky integrate-and-fire neurons
+ * with calcium-driven spike-frequency adaptation, in 1 ms steps, the way the paper's
+ * distributed simulator does (Pastorelli et al., arXiv:1511.09325): mixed time- and
+ * event-driven (section 1) -- every neuron is integrated every step, and synaptic work
+ * follows the spikes -- over columns of point neurons, 80 % excitatory, with
+ * distance-decaying connectivity to the neighbouring columns and external Poisson
+ * synapses (section 2, Methods).  The cost unit is the synaptic event: every current
+ * reaching a neuron from a recurrent or an external synapse (section 3, Figure 2 caption).
+ *
+ * Conventions
+ *   - All functions return DPSNN_OK (0) or a negative DPSNN_E* code; no C++ exception
+ *     crosses the ABI.  After an error, sim_last_error() describes it.
+ *   - "device" pointers are HIP device addresses (for example torch CUDA-tensor data
+ *     pointers); "host" pointers are ordinary process memory.  The caller owns every
+ *     buffer it passes; the library owns the memory behind a sim_t.
+ *   - Work is enqueued on the HIP stream given at creation (NULL = the null stream).
+ *     Functions marked "synchronises" wait for that stream.
+ *   - A simulation holds one or more independent networks ("batched" form).  Neurons are
+ *     numbered per network: column c = y*cols + x, neuron j = c*npc + k, k < n_exc
+ *     excitatory.  Networks share the column recipe and neuron parameters and differ in
+ *     grid shape, seed and external rate.
+ *   - Synaptic input is integer fixed point (int32 at 2^-16 mV, wrap-around addition),
+ *     so results do not depend on the order in which spikes are delivered.
+ */
+#ifndef DPSNN_H
+#define DPSNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPSNN_OK 0
+#define DPSNN_EINVAL (-1) /* bad argument or configuration */
+#define DPSNN_ENOMEM (-2) /* device or host allocation failed */
+#define DPSNN_EHIP (-3)   /* a HIP runtime call failed */
+#define DPSNN_ESTATE (-4) /* call not valid in the current state */
+#define DPSNN_ETRUNC (-5) /* an output buffer is too small (size needed is reported) */
+
+/* Spike delivery strategy. Both give bit-identical results. */
+#define DPSNN_DELIVERY_AUTO 0
+#define DPSNN_DELIVERY_ARRIVAL 1 /* per target column: gather arrivals, fused with the update */
+#define DPSNN_DELIVERY_PUSH 2    /* per spike: scatter into a per-target delay ring (atomics) */
+
+typedef struct sim sim_t;
+
+/* One network of a simulation. */
+typedef struct {
+  int32_t rows, cols;  /* grid of columns, periodic (torus) */
+  uint64_t seed;       /* Philox4x32-10 key of every random draw of this network */
+  double ext_rate_hz;  /* rate of each external synapse */
+} sim_net_t;
+
+/* Configuration (copied by sim_create).  Units: mV, ms, Hz. */
+typedef struct {
+  /* column recipe (section 2, Methods) */
+  int32_t npc;           /* neurons per column (the paper: 1240); 1 <= npc <= 4096 */
+  int32_t n_exc;         /* excitatory neurons per column (the paper: 80 %) */
+  double p_own;          /* pair connection probability inside a column */
+  double p_remote;       /* share of a row spread over the 8 neighbour columns */
+  double decay_um;       /* neighbour weight exp(-distance / decay_um) */
+  double spacing_um;     /* column spacing (the paper: about 100 um) */
+  int32_t d_min, d_max;  /* uniform integer delays in steps; 1 <= d_min <= d_max <= 32 */
+  double we_mu, we_sigma; /* excitatory weights N(mu, sigma); |mu| + 6 sigma < 2 mV */
+  double wi_mu, wi_sigma; /* inhibitory weights, mu < 0 */
+  /* neuron (LIF with calcium-driven AHP) */
+  double tau_m, theta, v_reset;
+  int32_t t_ref;         /* refractory steps, 0..255 */
+  double tau_ca, ca_inc, g_ahp, dt;
+  /* external Poisson synapses */
+  int32_t ext_syn;
+  double j_ext;
+  /* networks */
+  int32_t n_nets;        /* >= 1 */
+  const sim_net_t* nets; /* host array of n_nets */
+  /* options */
+  int32_t delivery;      /* DPSNN_DELIVERY_* */
+  int32_t block;         /* threads per workgroup of the step kernels: 0 (auto), 64..1024 */
+  int64_t record_steps;  /* spike raster: number of steps recorded from step 0 (0 = off) */
+  int64_t raster_capacity; /* spike raster: capacity in spike ids */
+  int32_t train_mode;    /* 1: float32 master weights, trajectory recording, sim_backward */
+  int32_t ckpt_every;    /* train mode: checkpoint interval in steps (>= 1) */
+} sim_config_t;
+
+/* Sizes of a created simulation. */
+typedef struct {
+  int32_t n_nets;
+  int32_t n_cols;        /* all networks */
+  int64_t n_neurons;     /* all networks */
+  int64_t n_synapses;    /* all networks */
+  int32_t ring_slots;    /* d_max + 1 */
+  int64_t device_bytes;  /* device memory held */
+} sim_info_t;
+
+/* Per-network counters since creation (or the last restore). */
+typedef struct {
+  int64_t steps;
+  int64_t spikes;
+  int64_t events_recurrent; /* outgoing synapses of every emitted spike */
+  int64_t events_external;  /* external Poisson arrivals drawn */
+} sim_stats_t;
+
+/* Build the networks on the device (connectivity, delays, weights; the paper's section 2
+ * network recipe with integer delays) and set the initial state (V uniform on
+ * [0, v_reset), Ca = 0, no pending input).
+ * hip_stream: a hipStream_t or NULL.  On success *out receives the handle; on failure it
+ * is NULL and sim_last_error(NULL) tells why.  Synchronises. */
+int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out);
+
+/* Release everything the handle holds.  NULL is ignored. */
+void sim_destroy(sim_t* sim);
+
+/* Advance all networks by n_steps 1 ms steps (section 1: all neurons every step, synapses
+ * per spike).  Asynchronous.  A raster overflow is sticky and reported by the next
+ * synchronising call as DPSNN_ETRUNC. */
+int sim_step(sim_t* sim, int64_t n_steps);
+
+/* Wait for the stream; returns a sticky error if one is pending. */
+int sim_sync(sim_t* sim);
+
+/* Recorded spikes of network `net` for steps [t0, t1): step_offsets (host, t1-t0+1) and ids
+ * (host, network-local neuron ids, ascending within a step).  If ids_cap is too small,
+ * returns DPSNN_ETRUNC with the needed count in *n_ids.  Synchronises. */
+int sim_read_spikes(sim_t* sim, int32_t net, int64_t t0, int64_t t1, int64_t* step_offsets,
+                    int32_t* ids, int64_t ids_cap, int64_t* n_ids);
+
+/* Surrogate-gradient backward through the recorded window [0, now) (train mode only).
+ * grad_rates: device float32 [n_cols of all networks], dL/dR_c of each column's mean rate
+ *             R_c = 1000 / (npc * T * dt) * spikes of column c (Hz).
+ * grad_w:     device float32 [n_synapses], dL/dw in the canonical synapse order (per
+ *             network, per source neuron, sorted by (delay, target)), w in mV.
+ * grad_tau_m, grad_g_ahp: host doubles.
+ * Returns DPSNN_ESTATE if not in train mode or nothing was recorded.  Synchronises. */
+int sim_backward(sim_t* sim, const float* grad_rates, float* grad_w, double* grad_tau_m,
+                 double* grad_g_ahp);
+
+/* Error text of the last failing call on `sim`, or of the last failing sim_create of
+ * this thread when sim is NULL.  Never NULL. */
+const char* sim_last_error(const sim_t* sim);
+
+int sim_get_info(const sim_t* sim, sim_info_t* info);
+
+/* Counters of network `net`.  Synchronises. */
+int sim_get_stats(sim_t* sim, int32_t net, sim_stats_t* stats);
+
+/* Current step number (steps done).  Host-side, no synchronisation. */
+int64_t sim_now(const sim_t* sim);
+
+/* Debug/test view of network `net` (host buffers, n = neurons of the network):
+ * v, ca (float32 [n]), ref (uint8 [n]), pend (int32 [ring_slots][n]) where pend[q][j] is
+ * the recurrent input already emitted towards neuron j for step now+q (the delivery
+ * strategy's internal form is converted to this view).  Any pointer may be NULL.
+ * Synchronises. */
+int sim_read_state(sim_t* sim, int32_t net, float* v, float* ca, uint8_t* ref, int32_t* pend);
+
+/* Synapses of network `net`, source neurons [i0, i1), in canonical order: row_ptr (host,
+ * i1-i0+1, relative to the first), tgt (int32 network-local), dly (uint8), wq (int16, 2^-14
+ * mV).  Returns DPSNN_ETRUNC with row_ptr filled if cap is short.  Synchronises. */
+int sim_read_synapses(sim_t* sim, int32_t net, int64_t i0, int64_t i1, int64_t* row_ptr,
+                      int32_t* tgt, uint8_t* dly, int16_t* wq, int64_t cap);
+
+/* Snapshot slots: save or restore the whole dynamic state (V, Ca, refractory counters,
+ * pending input, step counter, event counters).  slot in [0, 64).  Asynchronous. */
+int sim_save(sim_t* sim, int32_t slot);
+int sim_restore(sim_t* sim, int32_t slot);
+
+/* Train mode: master weights (device float32 [n_synapses], mV, canonical order).  The
+ * forward uses rint(w * 2^16) as int32 efficacy.  set copies in, get copies out. */
+int sim_set_weights(sim_t* sim, const float* w);
+int sim_get_weights(sim_t* sim, float* w);
+/* Change tau_m and g_AHP (the constants are recomputed on the host). */
+int sim_set_params(sim_t* sim, double tau_m, double g_ahp);
+
+/* Delivery strategy and workgroup size in use (after autotuning, if any). */
+int sim_get_launch(const sim_t* sim, int32_t* delivery, int32_t* block);
+/* Change them; results are bit-identical for every choice. */
+int sim_set_launch(sim_t* sim, int32_t delivery, int32_t block);
+
+/* Per-kernel device time of the last sim_step call, measured with HIP events on the
+ * simulation's stream when timing is on: ms[0] update (+fused delivery), ms[1] push
+ * delivery, ms[2] raster.  Timing adds events around every launch. */
+int sim_set_timing(sim_t* sim, int32_t on);
+int sim_get_timing(sim_t* sim, double* ms, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -75,6 +75,7 @@ def lib():
             "orc_poisson_count": (C.c_int32, [u64p, C.c_uint32]),
             "orc_initial_v": (C.c_float, [cp, C.c_int64]),
             "orc_ext_counts": (None, [cp, C.c_int64, C.c_int64, C.c_int64, i32p]),
+            "orc_neuron_update": (C.c_int, [cp, C.c_int64, C.c_int64, C.c_int32, f32p, f32p, u8p]),
             "orc_sim_consumed": (C.c_int64, [C.c_void_p]),
             "orc_sim_create": (C.c_void_p, [cp, C.c_int64, i64p, i32p, u8p, i32p]),
             "orc_sim_destroy": (None, [C.c_void_p]),
@@ -195,6 +196,15 @@ def ext_counts(p: dict, u: int, j0: int = 0, n: int | None = None):
     out = np.zeros(n, np.int32)
     lib().orc_ext_counts(C.byref(cfg), u, j0, n, _ptr(out, C.c_int32))
     return out
+
+
+def neuron_update(p: dict, j: int, u: int, rec_input: int, v: float, ca: float, ref: int):
+    """One neuron's step from its state; returns (spike, v, ca, ref)."""
+    cfg = make_config(p)
+    vv, cc, rr = C.c_float(v), C.c_float(ca), C.c_uint8(ref)
+    s = lib().orc_neuron_update(C.byref(cfg), j, u, int(rec_input), C.byref(vv), C.byref(cc),
+                                C.byref(rr))
+    return bool(s), np.float32(vv.value), np.float32(cc.value), int(rr.value)
 
 
 def initial_v(p: dict, j: int) -> float:

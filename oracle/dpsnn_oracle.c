@@ -212,8 +212,6 @@ struct orc_sim {
   const uint8_t* dly;
   const int32_t* w32;
   int32_t D;            /* ring slots: d_max + 1 */
-  float pm, pc, gam, alpha, theta, vreset;
-  int32_t jfx;          /* external efficacy, 2^-16 mV */
   uint64_t ptab[63];
   float* v;
   float* ca;
@@ -237,14 +235,6 @@ orc_sim_t* orc_sim_create(const orc_config_t* cfg, int64_t n, const int64_t* row
   s->n = n;
   s->row_ptr = row_ptr; s->tgt = tgt; s->dly = dly; s->w32 = w32;
   s->D = cfg->d_max + 1;
-  /* constants: computed in double, rounded once to float */
-  s->pm = (float)exp(-cfg->dt / cfg->tau_m);
-  s->pc = (float)exp(-cfg->dt / cfg->tau_ca);
-  s->gam = (float)(cfg->g_ahp * cfg->dt);
-  s->alpha = (float)cfg->ca_inc;
-  s->theta = (float)cfg->theta;
-  s->vreset = (float)cfg->v_reset;
-  s->jfx = (int32_t)rint(cfg->j_ext * 65536.0);
   orc_poisson_table((double)cfg->ext_syn * cfg->ext_rate_hz * cfg->dt * 1e-3, s->ptab);
   s->v = (float*)malloc(sizeof(float) * (size_t)n);
   s->ca = (float*)calloc((size_t)n, sizeof(float));
@@ -290,20 +280,81 @@ static void grow_record(orc_sim_t* s) {
   s->r_in = (int32_t*)realloc(s->r_in, sizeof(int32_t) * m);
 }
 
-/* One step u = now:
- *  1. input: A_j = ring[u % D][j] + n_j(u) * J_ext (int32, wrap-around); the slot is cleared;
- *     I_j = A_j * 2^-16 mV.
- *  2. a refractory neuron counts down, stays at V_reset and discards its input;
- *  3. otherwise V <- ((P_m V) - (gamma Ca)) + I, with P_m = exp(-dt/tau_m) and
- *     gamma = g_AHP dt; a spike is emitted if V >= theta, then V <- V_reset and the
- *     refractory counter is set;
- *  4. Ca <- P_c Ca + alpha s, with P_c = exp(-dt/tau_Ca);
- *  5. the spikes of the step are recorded in ascending order and counted as events
- *     (each outgoing synapse of a spiking neuron is one recurrent event; each external
- *     arrival is one external event);
- *  6. every synapse i->j of delay d of a spiking neuron i adds its efficacy to
+/* Neuron constants, computed in double and rounded once to float. */
+typedef struct { float pm, pc, gam, alpha, theta, vreset; int32_t jfx, tref; } consts_t;
+
+static consts_t constants_of(const orc_config_t* cfg) {
+  consts_t k;
+  k.pm = (float)exp(-cfg->dt / cfg->tau_m);
+  k.pc = (float)exp(-cfg->dt / cfg->tau_ca);
+  k.gam = (float)(cfg->g_ahp * cfg->dt);
+  k.alpha = (float)cfg->ca_inc;
+  k.theta = (float)cfg->theta;
+  k.vreset = (float)cfg->v_reset;
+  k.jfx = (int32_t)rint(cfg->j_ext * 65536.0);
+  k.tref = cfg->t_ref;
+  return k;
+}
+
+/* The neuron part of a step (paper section 2: LIF with calcium-driven AHP):
+ *  - the input is A = recurrent input + n_ext * J_ext (int32, wrap-around), I = A 2^-16 mV;
+ *  - a refractory neuron counts down, stays at V_reset and discards its input;
+ *  - otherwise V~ = ((P_m V) - (gamma Ca)) + I, with P_m = exp(-dt/tau_m) and
+ *    gamma = g_AHP dt; a spike is emitted if V~ >= theta, then V <- V_reset and the
+ *    refractory counter is set;
+ *  - Ca <- P_c Ca + alpha s, with P_c = exp(-dt/tau_Ca).
+ * Returns the spike flag; *vt receives V~ (0 when refractory), *refr the refractory flag,
+ * *a_out the consumed input. */
+static int neuron_update(const consts_t* k, uint32_t rec_input, int32_t n_ext, float* v, float* ca,
+                         uint8_t* ref, float* vt_out, int* refr_out, uint32_t* a_out) {
+  uint32_t a = rec_input + (uint32_t)n_ext * (uint32_t)k->jfx;
+  float cur = (float)(int32_t)a * 0x1p-16f;
+  float vprev = *v, caprev = *ca;
+  float vt = 0.0f;
+  int spike = 0, refr = 0;
+  if (*ref > 0) {
+    refr = 1;
+    *ref -= 1;
+    *v = k->vreset;
+  } else {
+    float leak = k->pm * vprev;
+    float ahp = k->gam * caprev;
+    float drop = leak - ahp;
+    vt = drop + cur;
+    if (vt >= k->theta) {
+      spike = 1;
+      *v = k->vreset;
+      *ref = (uint8_t)k->tref;
+    } else {
+      *v = vt;
+    }
+  }
+  float decayed = k->pc * caprev;
+  *ca = decayed + (spike ? k->alpha : 0.0f);
+  *vt_out = vt; *refr_out = refr; *a_out = a;
+  return spike;
+}
+
+int orc_neuron_update(const orc_config_t* cfg, int64_t j, int64_t u, int32_t rec_input, float* v,
+                      float* ca, uint8_t* ref) {
+  consts_t k = constants_of(cfg);
+  int32_t n_ext;
+  orc_ext_counts(cfg, u, j, 1, &n_ext);
+  float vt; int refr; uint32_t a;
+  return neuron_update(&k, (uint32_t)rec_input, n_ext, v, ca, ref, &vt, &refr, &a);
+}
+
+/* One step u = now (paper section 1: every neuron is updated every step; synaptic work
+ * follows the spikes):
+ *  1. each neuron takes its input ring[u % D][j] (the slot is cleared), adds its external
+ *     Poisson count times J_ext and is updated as in neuron_update;
+ *  2. the spikes of the step are recorded in ascending order and counted as events (each
+ *     outgoing synapse of a spiking neuron is one recurrent event; each external arrival
+ *     is one external event);
+ *  3. every synapse i->j of delay d of a spiking neuron i adds its efficacy to
  *     ring[(u + d) % D][j]. */
 int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
+  consts_t k = constants_of(&s->cfg);
   for (int64_t it = 0; it < n_steps; ++it) {
     int64_t u = s->now;
     int64_t slot = u % s->D;
@@ -314,32 +365,12 @@ int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
       uint32_t r[4];
       draw(&s->cfg, (uint32_t)j, (uint32_t)u, 0u, ORC_STREAM_EXT, r);
       int32_t next = orc_poisson_count(s->ptab, r[0]);
-      uint32_t a = in[j] + (uint32_t)next * (uint32_t)s->jfx;
+      float vprev = s->v[j], caprev = s->ca[j], vt;
+      int refr;
+      uint32_t a;
+      int spike = neuron_update(&k, in[j], next, &s->v[j], &s->ca[j], &s->ref[j], &vt, &refr, &a);
       in[j] = 0;
       s->consumed += (int64_t)(int32_t)a;
-      float cur = (float)(int32_t)a * 0x1p-16f;
-      float vprev = s->v[j], caprev = s->ca[j];
-      float vt = 0.0f;
-      int spike = 0, refr = 0;
-      if (s->ref[j] > 0) {
-        refr = 1;
-        s->ref[j] -= 1;
-        s->v[j] = s->vreset;
-      } else {
-        float leak = s->pm * vprev;
-        float ahp = s->gam * caprev;
-        float drop = leak - ahp;
-        vt = drop + cur;
-        if (vt >= s->theta) {
-          spike = 1;
-          s->v[j] = s->vreset;
-          s->ref[j] = (uint8_t)s->cfg.t_ref;
-        } else {
-          s->v[j] = vt;
-        }
-      }
-      float decayed = s->pc * caprev;
-      s->ca[j] = decayed + (spike ? s->alpha : 0.0f);
       if (spike) push_spike(s, (int32_t)j);
       s->e_ext += next;
       if (s->rec_on) {
@@ -352,9 +383,9 @@ int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
     for (int64_t q = first; q < s->sp_n; ++q) {
       int64_t i = s->sp_ids[q];
       s->e_rec += s->row_ptr[i + 1] - s->row_ptr[i];
-      for (int64_t k = s->row_ptr[i]; k < s->row_ptr[i + 1]; ++k) {
-        int64_t dst = ((u + s->dly[k]) % s->D) * s->n + s->tgt[k];
-        s->ring[dst] += (uint32_t)s->w32[k];
+      for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
+        int64_t dst = ((u + s->dly[e]) % s->D) * s->n + s->tgt[e];
+        s->ring[dst] += (uint32_t)s->w32[e];
       }
     }
     s->now += 1;

@@ -90,6 +90,11 @@ int32_t orc_poisson_count(const uint64_t tab[63], uint32_t x);
 /* External counts n_j(u) of neurons j0 .. j0+n-1 at step u. */
 void orc_ext_counts(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n, int32_t* out);
 
+/* Update one neuron at step u from its state and recurrent input (2^-16 mV), drawing its
+ * external count; returns the spike flag.  Same arithmetic as a simulation step. */
+int orc_neuron_update(const orc_config_t* cfg, int64_t j, int64_t u, int32_t rec_input, float* v,
+                      float* ca, uint8_t* ref);
+
 /* Initial membrane potential of neuron j. */
 float orc_initial_v(const orc_config_t* cfg, int64_t j);
 

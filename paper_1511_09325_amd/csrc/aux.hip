@@ -1,0 +1,181 @@
+// aux.hip -- raster recording, the pending-input view, synapse export, weight quantiser.
+#include "dpsnn_internal.h"
+
+namespace dpsnn {
+namespace {
+
+constexpr int kMaxItems = kMaxDelay * kMaxNbr;
+
+// Raster: exclusive scan of this step's per-column spike counts (one workgroup), giving
+// each column its place in the ascending global id list of the step.
+__global__ __launch_bounds__(1024) void k_raster_scan(const int32_t* hist_cnt, int32_t n_cols,
+                                                      int32_t slot, int64_t u, int64_t* ras_off,
+                                                      int64_t* colofs, int64_t cap,
+                                                      int32_t* flags) {
+  __shared__ int64_t wsum[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t carry = ras_off[u];
+  for (int32_t b = 0; b < n_cols; b += 1024) {
+    const int32_t g = b + threadIdx.x;
+    const int64_t x = g < n_cols ? hist_cnt[(int64_t)slot * n_cols + g] : 0;
+    int64_t incl = x;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wave) before += wsum[w];
+      all += wsum[w];
+    }
+    __syncthreads();
+    if (g < n_cols) colofs[g] = carry + before + incl - x;
+    carry += all;
+  }
+  if (threadIdx.x == 0) {
+    ras_off[u + 1] = carry;
+    if (carry > cap) flags[0] = 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_raster_copy(const int32_t* hist_cnt,
+                                                     const uint16_t* hist_ids, int32_t n_cols,
+                                                     int32_t npc, int32_t slot,
+                                                     const int64_t* colofs, int32_t* ras_ids,
+                                                     int64_t cap) {
+  const int32_t g = blockIdx.x;
+  const int32_t n = hist_cnt[(int64_t)slot * n_cols + g];
+  const int64_t base = colofs[g];
+  if (base + n > cap) return;
+  const uint16_t* ids = hist_ids + ((int64_t)slot * n_cols + g) * npc;
+  for (int32_t q = threadIdx.x; q < n; q += 256) ras_ids[base + q] = g * npc + ids[q];
+}
+
+// Pending-input view of the arrival strategy: pend[q][j] = sum over spikes of steps
+// t in [now - d_max, now) and synapses of delay d with t + d = now + q, restricted to the
+// target columns [g0, g1) of one network (j relative to column g0).
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void k_pend_arrival(StepArgs a, int64_t now, int32_t* pend,
+                                                      int32_t g0, int32_t g1) {
+  __shared__ uint16_t segrow[4][kMaxItems + 2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nseg = a.nd * kMaxNbr;
+  const int64_t n_net = (int64_t)(g1 - g0) * a.npc;
+  const int32_t g = g0 + blockIdx.x;  // source columns of the same network
+  const int d_max = a.d_min + a.nd - 1;
+  for (int back = 1; back <= d_max; ++back) {
+    const int64_t t = now - back;
+    if (t < 0) break;
+    const int32_t slot = (int32_t)(t % a.dh);
+    const int32_t ns = a.hist_cnt[(int64_t)slot * a.n_cols + g];
+    const uint16_t* ids = a.hist_ids + ((int64_t)slot * a.n_cols + g) * a.npc;
+    for (int32_t q = wave; q < ns; q += 4) {
+      const int64_t i = (int64_t)g * a.npc + ids[q];
+      const uint16_t* sg = a.seg + i * a.segw;
+      for (int e = lane; e <= nseg; e += 64) segrow[wave][e] = sg[e];
+      __builtin_amdgcn_wave_barrier();
+      const int32_t len = segrow[wave][nseg];
+      const int64_t rb = a.row_base[i];
+      for (int32_t f = lane; f < len; f += 64) {
+        int lo = 0, hi = nseg;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if ((int32_t)segrow[wave][mid] <= f) lo = mid;
+          else hi = mid;
+        }
+        const int dd = lo / kMaxNbr, r = lo - dd * kMaxNbr;
+        const int64_t due = t + a.d_min + dd;
+        if (due < now) continue;
+        const int32_t tc = a.col_nbr[g * kMaxNbr + r];
+        const uint32_t w = a.syn[rb + f];
+        const int32_t val = TRAIN ? a.wfx[rb + f] : (((int32_t)w) >> 16) * 4;
+        atomicAdd(&pend[(due - now) * n_net + (int64_t)(tc - g0) * a.npc + (w & 0xffffu)], val);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+}
+
+// Export rows [i0, i1) (global neuron ids) in canonical order with network-local targets.
+__global__ __launch_bounds__(256) void k_export_rows(StepArgs a, int32_t g0, int64_t i0,
+                                                     int64_t i1, const int64_t* out_off,
+                                                     int32_t* tgt, uint8_t* dly, int16_t* wq) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nseg = a.nd * kMaxNbr;
+  for (int64_t i = i0 + (int64_t)blockIdx.x * 4 + wave; i < i1; i += (int64_t)gridDim.x * 4) {
+    const int32_t g = (int32_t)(i / a.npc);
+    const uint16_t* sg = a.seg + i * a.segw;
+    const int32_t len = sg[nseg];
+    const int64_t rb = a.row_base[i];
+    const int64_t ob = out_off[i - i0];
+    for (int32_t f = lane; f < len; f += 64) {
+      int lo = 0, hi = nseg;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int32_t)sg[mid] <= f) lo = mid;
+        else hi = mid;
+      }
+      const int dd = lo / kMaxNbr, r = lo - dd * kMaxNbr;
+      const int32_t tc = a.col_nbr[g * kMaxNbr + r];
+      const uint32_t w = a.syn[rb + f];
+      tgt[ob + f] = (tc - g0) * a.npc + (int32_t)(w & 0xffffu);
+      dly[ob + f] = (uint8_t)(a.d_min + dd);
+      wq[ob + f] = (int16_t)(w >> 16);
+    }
+  }
+}
+
+// Train mode: int32 efficacies rint(w * 2^16) from the float32 master weights (mV).
+__global__ void k_quantise(const float* w, int32_t* wfx, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    wfx[e] = (int32_t)__builtin_rintf(w[e] * 65536.0f);
+}
+
+}  // namespace
+
+hipError_t launch_raster(sim& s, int64_t u) {
+  const int32_t slot = (int32_t)(u % s.dh);
+  hipLaunchKernelGGL(k_raster_scan, dim3(1), dim3(1024), 0, s.stream, s.hist_cnt, s.n_cols, slot,
+                     u, s.ras_off, s.ras_colofs, s.cfg.raster_capacity, s.flags);
+  hipLaunchKernelGGL(k_raster_copy, dim3(s.n_cols), dim3(256), 0, s.stream, s.hist_cnt,
+                     s.hist_ids, s.n_cols, s.npc, slot, s.ras_colofs, s.ras_ids,
+                     s.cfg.raster_capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_pend_view(const sim& s, int32_t* pend, int32_t g0, int32_t g1) {
+  const StepArgs a = make_step_args(s);
+  if (s.wfx)
+    hipLaunchKernelGGL(k_pend_arrival<true>, dim3(g1 - g0), dim3(256), 0, s.stream, a, s.now,
+                       pend, g0, g1);
+  else
+    hipLaunchKernelGGL(k_pend_arrival<false>, dim3(g1 - g0), dim3(256), 0, s.stream, a, s.now,
+                       pend, g0, g1);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1, int32_t* tgt,
+                              uint8_t* dly, int16_t* wq, const int64_t* out_off) {
+  const StepArgs a = make_step_args(s);
+  const int32_t g0 = s.net_col0[net];
+  int64_t blocks = (i1 - i0 + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_export_rows, dim3((unsigned)blocks), dim3(256), 0, s.stream, a, g0, i0, i1,
+                     out_off, tgt, dly, wq);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantise(const sim& s) {
+  int64_t blocks = (s.n_syn + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_quantise, dim3((unsigned)blocks), dim3(256), 0, s.stream, s.wf32, s.wfx,
+                     s.n_syn);
+  return hipGetLastError();
+}
+
+}  // namespace dpsnn

@@ -1,0 +1,667 @@
+// capi.hip -- host side of libdpsnn: the C ABI declared in include/dpsnn.h.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "dpsnn_internal.h"
+
+using namespace dpsnn;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw Fail{DPSNN_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)};          \
+  } while (0)
+
+void* dalloc(sim& s, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  const hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Fail{DPSNN_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  s.bufs.push_back(DevBuf{p, bytes});
+  s.device_bytes += bytes;
+  return p;
+}
+
+void dfree(sim& s, void* p) {
+  if (!p) return;
+  for (size_t q = 0; q < s.bufs.size(); ++q) {
+    if (s.bufs[q].p == p) {
+      s.device_bytes -= s.bufs[q].bytes;
+      (void)hipFree(p);
+      s.bufs.erase(s.bufs.begin() + (long)q);
+      return;
+    }
+  }
+}
+
+template <typename T>
+T* upload(sim& s, const std::vector<T>& h) {
+  T* d = (T*)dalloc(s, sizeof(T) * std::max<size_t>(h.size(), 1));
+  if (!h.empty()) HIPCHK(hipMemcpyAsync(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, s.stream));
+  return d;
+}
+
+// Probability of one stencil offset: the own column, or a neighbour weighted by
+// exp(-distance / decay) with the remote share spread over the 8 neighbours
+// (section 2, Methods: connectivity decreasing with the distance between columns).
+double offset_prob(const sim_config_t& c, int dy, int dx) {
+  if (dy == 0 && dx == 0) return c.p_own;
+  const double edge = exp(-(c.spacing_um / c.decay_um));
+  const double diag = exp(-(sqrt(2.0) * c.spacing_um / c.decay_um));
+  const double norm = 4.0 * edge + 4.0 * diag;
+  const double one = (dy == 0 || dx == 0) ? edge : diag;
+  return c.p_remote * one / norm;
+}
+
+uint64_t threshold_of(double p) {
+  const double t = floor(p * 4294967296.0);
+  if (t <= 0.0) return 0;
+  if (t >= 4294967296.0) return (uint64_t)1 << 32;
+  return (uint64_t)t;
+}
+
+// Poisson(lam) inverse-CDF thresholds, floor(F(k) 2^32) capped at 2^32.
+void poisson_thresholds(double lam, uint64_t* tab) {
+  double pk = exp(-lam);
+  double cdf = 0.0;
+  for (int k = 0; k < kPoissonEntries; ++k) {
+    if (k > 0) pk = pk * lam / (double)k;
+    cdf = cdf + pk;
+    const double t = floor(cdf * 4294967296.0);
+    tab[k] = t >= 4294967296.0 ? ((uint64_t)1 << 32) : (uint64_t)t;
+  }
+}
+
+void validate(const sim_config_t* c) {
+  auto bad = [](const std::string& m) { throw Fail{DPSNN_EINVAL, m}; };
+  if (!c) bad("config is NULL");
+  if (c->npc < 1 || c->npc > kMaxNpc) bad("npc must be in [1, 4096]");
+  if (c->n_exc < 0 || c->n_exc > c->npc) bad("n_exc must be in [0, npc]");
+  if (c->d_min < 1 || c->d_max < c->d_min || c->d_max > kMaxDelay)
+    bad("delays must satisfy 1 <= d_min <= d_max <= 32");
+  if (!(c->p_own >= 0 && c->p_own <= 1 && c->p_remote >= 0 && c->p_own + c->p_remote <= 1.0 + 1e-12))
+    bad("p_own, p_remote must be probabilities with p_own + p_remote <= 1");
+  if (!(c->decay_um > 0 && c->spacing_um > 0)) bad("decay_um and spacing_um must be positive");
+  const double lim = 32767.0 / 16384.0;
+  if (!(fabs(c->we_mu) + 6 * c->we_sigma < lim && fabs(c->wi_mu) + 6 * c->wi_sigma < lim) ||
+      c->we_sigma < 0 || c->wi_sigma < 0)
+    bad("weights must satisfy |mu| + 6 sigma < 2 mV (int16 at 2^-14 mV)");
+  if (!(c->tau_m > 0 && c->tau_ca > 0 && c->dt > 0)) bad("time constants and dt must be positive");
+  if (c->t_ref < 0 || c->t_ref > 255) bad("t_ref must be in [0, 255]");
+  if (c->ext_syn < 0) bad("ext_syn must be >= 0");
+  if (c->n_nets < 1 || !c->nets) bad("need at least one network");
+  if (c->delivery < 0 || c->delivery > 2) bad("unknown delivery strategy");
+  if (!(c->block == 0 || c->block == 64 || c->block == 128 || c->block == 256 ||
+        c->block == 512 || c->block == 1024))
+    bad("block must be 0, 64, 128, 256, 512 or 1024");
+  if (c->record_steps < 0 || c->raster_capacity < 0) bad("raster sizes must be >= 0");
+  if (c->train_mode && c->ckpt_every < 1) bad("ckpt_every must be >= 1 in train mode");
+  int64_t cols = 0;
+  for (int n = 0; n < c->n_nets; ++n) {
+    const sim_net_t& t = c->nets[n];
+    if (t.rows < 1 || t.cols < 1) bad("grid sides must be >= 1");
+    if (!(t.ext_rate_hz >= 0)) bad("ext_rate_hz must be >= 0");
+    const double lam = (double)c->ext_syn * t.ext_rate_hz * c->dt * 1e-3;
+    if (lam > 20.0) bad("external mean count per step must be <= 20 (Poisson table cap 63)");
+    cols += (int64_t)t.rows * t.cols;
+  }
+  if (cols * c->npc >= ((int64_t)1 << 31)) bad("total neurons must be < 2^31");
+  if (cols * (c->d_max + 1) * c->npc >= ((int64_t)1 << 31)) bad("spike history exceeds 2^31 entries");
+}
+
+void set_constants(sim& s) {
+  const sim_config_t& c = s.cfg;
+  s.nk.pm = (float)exp(-c.dt / c.tau_m);
+  s.nk.pc = (float)exp(-c.dt / c.tau_ca);
+  s.nk.gam = (float)(c.g_ahp * c.dt);
+  s.nk.alpha = (float)c.ca_inc;
+  s.nk.theta = (float)c.theta;
+  s.nk.vreset = (float)c.v_reset;
+  s.nk.jfx = (int32_t)rint(c.j_ext * 65536.0);
+  s.nk.tref = c.t_ref;
+}
+
+void build_tables(sim& s) {
+  const sim_config_t& c = s.cfg;
+  s.net_col0.assign(1, 0);
+  for (const sim_net_t& t : s.nets) s.net_col0.push_back(s.net_col0.back() + t.rows * t.cols);
+  s.n_cols = s.net_col0.back();
+  s.n_neurons = (int64_t)s.n_cols * s.npc;
+  std::vector<int32_t> col_net(s.n_cols), col_local(s.n_cols), nn(s.n_cols);
+  std::vector<int32_t> nbr((size_t)s.n_cols * kMaxNbr, -1), rank((size_t)s.n_cols * kMaxNbr, -1);
+  std::vector<uint64_t> thr((size_t)s.n_cols * kMaxNbr, 0);
+  for (int n = 0; n < s.n_nets; ++n) {
+    const int rows = s.nets[n].rows, cols = s.nets[n].cols;
+    for (int cl = 0; cl < rows * cols; ++cl) {
+      const int32_t g = s.net_col0[n] + cl;
+      col_net[g] = n;
+      col_local[g] = cl;
+      const int y = cl / cols, x = cl % cols;
+      // distinct target columns, probabilities summed in stencil order
+      std::vector<std::pair<int, double>> tg;
+      for (int dy = -1; dy <= 1; ++dy) {
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int ty = ((y + dy) % rows + rows) % rows;
+          const int tx = ((x + dx) % cols + cols) % cols;
+          const int tcl = ty * cols + tx;
+          const double p = offset_prob(c, dy, dx);
+          auto it = std::find_if(tg.begin(), tg.end(), [&](const std::pair<int, double>& e) {
+            return e.first == tcl;
+          });
+          if (it == tg.end()) tg.push_back({tcl, 0.0 + p});
+          else it->second = it->second + p;
+        }
+      }
+      std::sort(tg.begin(), tg.end());
+      nn[g] = (int32_t)tg.size();
+      for (size_t r = 0; r < tg.size(); ++r) {
+        nbr[(size_t)g * kMaxNbr + r] = s.net_col0[n] + tg[r].first;
+        thr[(size_t)g * kMaxNbr + r] = threshold_of(tg[r].second);
+      }
+    }
+  }
+  for (int32_t g = 0; g < s.n_cols; ++g) {
+    for (int r = 0; r < nn[g]; ++r) {
+      const int32_t sc = nbr[(size_t)g * kMaxNbr + r];
+      for (int q = 0; q < nn[sc]; ++q)
+        if (nbr[(size_t)sc * kMaxNbr + q] == g) rank[(size_t)g * kMaxNbr + r] = q;
+      if (rank[(size_t)g * kMaxNbr + r] < 0) throw Fail{DPSNN_EINVAL, "asymmetric neighbourhood"};
+    }
+  }
+  std::vector<uint32_t> key(2 * (size_t)s.n_nets);
+  std::vector<uint64_t> ptab((size_t)s.n_nets * kPoissonEntries);
+  for (int n = 0; n < s.n_nets; ++n) {
+    key[2 * n] = (uint32_t)(s.nets[n].seed & 0xffffffffu);
+    key[2 * n + 1] = (uint32_t)(s.nets[n].seed >> 32);
+    const double lam = (double)c.ext_syn * s.nets[n].ext_rate_hz * c.dt * 1e-3;
+    poisson_thresholds(lam, &ptab[(size_t)n * kPoissonEntries]);
+  }
+  s.col_net = upload(s, col_net);
+  s.col_local = upload(s, col_local);
+  s.col_nn = upload(s, nn);
+  s.col_nbr = upload(s, nbr);
+  s.col_rank = upload(s, rank);
+  s.col_thr = upload(s, thr);
+  s.net_key = upload(s, key);
+  s.net_ptab = upload(s, ptab);
+}
+
+void generate(sim& s) {
+  const int64_t N = s.n_neurons;
+  int32_t* row_len = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)N);
+  s.seg = (uint16_t*)dalloc(s, sizeof(uint16_t) * (size_t)N * s.segw);
+  s.row_base = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)(N + 1));
+  const int64_t plen = scan_scratch_len(N);
+  int64_t* part = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)plen);
+  HIPCHK(launch_gen_count(s, 0, N, row_len));
+  HIPCHK(launch_scan_rows(s, row_len, N, s.row_base, part, plen));
+  int64_t total = 0;
+  HIPCHK(hipMemcpyAsync(&total, s.row_base + N, sizeof(int64_t), hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  s.n_syn = total;
+  s.syn = (uint32_t*)dalloc(s, sizeof(uint32_t) * (size_t)std::max<int64_t>(total, 1));
+  HIPCHK(launch_gen_fill(s, 0, N));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  dfree(s, part);
+  dfree(s, row_len);
+  // per-network synapse offsets (host copy of the network boundaries of row_base)
+  s.net_syn0.assign((size_t)s.n_nets + 1, 0);
+  for (int n = 0; n <= s.n_nets; ++n) {
+    const int64_t i = (int64_t)s.net_col0[n] * s.npc;
+    HIPCHK(hipMemcpy(&s.net_syn0[n], s.row_base + i, sizeof(int64_t), hipMemcpyDeviceToHost));
+  }
+}
+
+void ensure_ring(sim& s) {
+  if (s.ring) return;
+  const size_t bytes = sizeof(int32_t) * (size_t)s.dh * (size_t)s.n_neurons;
+  s.ring = (int32_t*)dalloc(s, bytes);
+  HIPCHK(hipMemsetAsync(s.ring, 0, bytes, s.stream));
+}
+
+// Materialise the push ring from the spike history (switching from arrival to push).
+void ring_from_history(sim& s) {
+  ensure_ring(s);
+  const size_t nall = (size_t)s.n_neurons;
+  int32_t* pend = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)s.dh * nall);
+  HIPCHK(hipMemsetAsync(pend, 0, sizeof(int32_t) * (size_t)s.dh * nall, s.stream));
+  for (int n = 0; n < s.n_nets; ++n) {
+    // the view is per network: targets relative to the network's first column
+    const int32_t g0 = s.net_col0[n], g1 = s.net_col0[n + 1];
+    const size_t nn = (size_t)(g1 - g0) * s.npc;
+    int32_t* tmp = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)s.dh * nn);
+    HIPCHK(hipMemsetAsync(tmp, 0, sizeof(int32_t) * (size_t)s.dh * nn, s.stream));
+    HIPCHK(launch_pend_view(s, tmp, g0, g1));
+    for (int q = 0; q < s.dh; ++q) {
+      const int64_t slot = (s.now + q) % s.dh;
+      HIPCHK(hipMemcpyAsync(s.ring + slot * (int64_t)nall + (int64_t)g0 * s.npc, tmp + q * nn,
+                            sizeof(int32_t) * nn, hipMemcpyDeviceToDevice, s.stream));
+    }
+    HIPCHK(hipStreamSynchronize(s.stream));
+    dfree(s, tmp);
+  }
+  dfree(s, pend);
+}
+
+// The dynamic state saved by a snapshot.  The push ring is not part of it: it is rebuilt
+// from the spike history on restore.
+void snapshot_parts(sim& s, size_t* parts, void** ptrs) {
+  const size_t N = (size_t)s.n_neurons;
+  parts[0] = sizeof(float) * N;                                    ptrs[0] = s.v;
+  parts[1] = sizeof(float) * N;                                    ptrs[1] = s.ca;
+  parts[2] = N;                                                    ptrs[2] = s.ref;
+  parts[3] = sizeof(int32_t) * (size_t)s.dh * s.n_cols;            ptrs[3] = s.hist_cnt;
+  parts[4] = sizeof(uint16_t) * (size_t)s.dh * s.n_cols * s.npc;   ptrs[4] = s.hist_ids;
+  parts[5] = sizeof(unsigned long long) * 4 * (size_t)s.n_nets;    ptrs[5] = s.net_cnt;
+}
+
+int finish(sim* s, const Fail& f) {
+  if (s) s->err = f.msg;
+  return f.code;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
+  if (out) *out = nullptr;
+  sim* s = nullptr;
+  try {
+    if (!out) throw Fail{DPSNN_EINVAL, "out is NULL"};
+    validate(cfg);
+    s = new sim();
+    s->cfg = *cfg;
+    s->nets.assign(cfg->nets, cfg->nets + cfg->n_nets);
+    s->cfg.nets = s->nets.data();
+    s->stream = (hipStream_t)hip_stream;
+    s->n_nets = cfg->n_nets;
+    s->npc = cfg->npc;
+    s->nd = cfg->d_max - cfg->d_min + 1;
+    s->dh = cfg->d_max + 1;
+    s->segw = (s->nd * kMaxNbr + 1 + 1) & ~1;
+    s->delivery = cfg->delivery == DPSNN_DELIVERY_PUSH ? DPSNN_DELIVERY_PUSH : DPSNN_DELIVERY_ARRIVAL;
+    s->block = cfg->block ? cfg->block : 256;
+    set_constants(*s);
+    build_tables(*s);
+    generate(*s);
+    const size_t N = (size_t)s->n_neurons;
+    s->v = (float*)dalloc(*s, sizeof(float) * N);
+    s->ca = (float*)dalloc(*s, sizeof(float) * N);
+    s->ref = (uint8_t*)dalloc(*s, N);
+    s->hist_cnt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)s->dh * s->n_cols);
+    s->hist_ids = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
+    s->net_cnt = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * 4 * (size_t)s->n_nets);
+    s->flags = (int32_t*)dalloc(*s, sizeof(int32_t) * 4);
+    HIPCHK(hipMemsetAsync(s->hist_cnt, 0, sizeof(int32_t) * (size_t)s->dh * s->n_cols, s->stream));
+    HIPCHK(hipMemsetAsync(s->net_cnt, 0, sizeof(unsigned long long) * 4 * (size_t)s->n_nets, s->stream));
+    HIPCHK(hipMemsetAsync(s->flags, 0, sizeof(int32_t) * 4, s->stream));
+    HIPCHK(launch_init_state(*s));
+    if (s->delivery == DPSNN_DELIVERY_PUSH) ensure_ring(*s);
+    if (cfg->record_steps > 0) {
+      s->ras_off = (int64_t*)dalloc(*s, sizeof(int64_t) * (size_t)(cfg->record_steps + 1));
+      s->ras_ids = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)std::max<int64_t>(cfg->raster_capacity, 1));
+      s->ras_colofs = (int64_t*)dalloc(*s, sizeof(int64_t) * (size_t)s->n_cols);
+      HIPCHK(hipMemsetAsync(s->ras_off, 0, sizeof(int64_t) * (size_t)(cfg->record_steps + 1), s->stream));
+    }
+    s->snaps.resize(64);
+    HIPCHK(hipStreamSynchronize(s->stream));
+    *out = s;
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    g_create_error = f.msg;
+    if (s) sim_destroy(s);
+    return f.code;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    if (s) sim_destroy(s);
+    return DPSNN_ENOMEM;
+  }
+}
+
+void sim_destroy(sim_t* s) {
+  if (!s) return;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  else (void)hipDeviceSynchronize();
+  for (DevBuf& b : s->bufs) (void)hipFree(b.p);
+  for (Snapshot& sn : s->snaps) (void)hipFree(sn.blob.p);
+  delete s;
+}
+
+int sim_step(sim_t* s, int64_t n_steps) {
+  if (!s) return DPSNN_EINVAL;
+  if (n_steps < 0) { s->err = "n_steps < 0"; return DPSNN_EINVAL; }
+  if (s->sticky) { s->err = "simulation is in a failed state"; return DPSNN_ESTATE; }
+  try {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (s->timing) {
+      HIPCHK(hipEventCreate(&ev[0]));
+      HIPCHK(hipEventCreate(&ev[1]));
+      HIPCHK(hipEventRecord(ev[0], s->stream));
+    }
+    for (int64_t q = 0; q < n_steps; ++q) {
+      const int64_t u = s->now;
+      HIPCHK(launch_step(*s, u, s->delivery, s->block));
+      if (s->ras_off && u < s->cfg.record_steps) HIPCHK(launch_raster(*s, u));
+      s->now = u + 1;
+    }
+    if (s->timing) {
+      HIPCHK(hipEventRecord(ev[1], s->stream));
+      HIPCHK(hipEventSynchronize(ev[1]));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      s->last_ms[0] = ms;
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+    }
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    s->sticky = f.code;
+    return finish(s, f);
+  }
+}
+
+int sim_sync(sim_t* s) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->ras_off) {
+      int32_t fl = 0;
+      HIPCHK(hipMemcpy(&fl, s->flags, sizeof(int32_t), hipMemcpyDeviceToHost));
+      if (fl) { s->err = "raster capacity exceeded"; return DPSNN_ETRUNC; }
+    }
+    if (s->sticky) return DPSNN_ESTATE;
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+int sim_read_spikes(sim_t* s, int32_t net, int64_t t0, int64_t t1, int64_t* step_offsets,
+                    int32_t* ids, int64_t ids_cap, int64_t* n_ids) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    if (net < 0 || net >= s->n_nets) throw Fail{DPSNN_EINVAL, "net out of range"};
+    if (!s->ras_off) throw Fail{DPSNN_ESTATE, "spike recording is off"};
+    const int64_t lim = std::min<int64_t>(s->now, s->cfg.record_steps);
+    if (t0 < 0 || t1 < t0 || t1 > lim) throw Fail{DPSNN_EINVAL, "steps outside the recorded window"};
+    if (!step_offsets || !n_ids) throw Fail{DPSNN_EINVAL, "NULL output"};
+    int rc = sim_sync(s);
+    if (rc == DPSNN_ETRUNC) return rc;
+    std::vector<int64_t> off((size_t)(t1 - t0 + 1));
+    HIPCHK(hipMemcpy(off.data(), s->ras_off + t0, sizeof(int64_t) * off.size(), hipMemcpyDeviceToHost));
+    std::vector<int32_t> all((size_t)(off.back() - off.front()));
+    if (!all.empty())
+      HIPCHK(hipMemcpy(all.data(), s->ras_ids + off.front(), sizeof(int32_t) * all.size(),
+                       hipMemcpyDeviceToHost));
+    const int32_t lo = s->net_col0[net] * s->npc, hi = s->net_col0[net + 1] * s->npc;
+    int64_t cnt = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+      step_offsets[t - t0] = cnt;
+      const int32_t* a = all.data() + (off[t - t0] - off.front());
+      const int32_t* b = all.data() + (off[t - t0 + 1] - off.front());
+      const int32_t* x = std::lower_bound(a, b, lo);
+      const int32_t* y = std::lower_bound(a, b, hi);
+      for (const int32_t* p = x; p < y; ++p) {
+        if (ids && cnt < ids_cap) ids[cnt] = *p - lo;
+        ++cnt;
+      }
+    }
+    step_offsets[t1 - t0] = cnt;
+    *n_ids = cnt;
+    if (cnt > ids_cap || (!ids && cnt > 0)) {
+      s->err = "ids buffer too small";
+      return DPSNN_ETRUNC;
+    }
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+const char* sim_last_error(const sim_t* s) {
+  return s ? s->err.c_str() : g_create_error.c_str();
+}
+
+int sim_get_info(const sim_t* s, sim_info_t* info) {
+  if (!s || !info) return DPSNN_EINVAL;
+  info->n_nets = s->n_nets;
+  info->n_cols = s->n_cols;
+  info->n_neurons = s->n_neurons;
+  info->n_synapses = s->n_syn;
+  info->ring_slots = s->dh;
+  info->device_bytes = (int64_t)s->device_bytes;
+  return DPSNN_OK;
+}
+
+int64_t sim_now(const sim_t* s) { return s ? s->now : -1; }
+
+int sim_get_stats(sim_t* s, int32_t net, sim_stats_t* st) {
+  if (!s || !st) return DPSNN_EINVAL;
+  try {
+    if (net < 0 || net >= s->n_nets) throw Fail{DPSNN_EINVAL, "net out of range"};
+    HIPCHK(hipStreamSynchronize(s->stream));
+    unsigned long long c[4];
+    HIPCHK(hipMemcpy(c, s->net_cnt + 4 * net, sizeof(c), hipMemcpyDeviceToHost));
+    st->steps = s->now;
+    st->spikes = (int64_t)c[0];
+    st->events_recurrent = (int64_t)c[1];
+    st->events_external = (int64_t)c[2];
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+int sim_read_state(sim_t* s, int32_t net, float* v, float* ca, uint8_t* ref, int32_t* pend) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    if (net < 0 || net >= s->n_nets) throw Fail{DPSNN_EINVAL, "net out of range"};
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const int32_t g0 = s->net_col0[net], g1 = s->net_col0[net + 1];
+    const int64_t n0 = (int64_t)g0 * s->npc;
+    const size_t nn = (size_t)(g1 - g0) * s->npc;
+    if (v) HIPCHK(hipMemcpy(v, s->v + n0, sizeof(float) * nn, hipMemcpyDeviceToHost));
+    if (ca) HIPCHK(hipMemcpy(ca, s->ca + n0, sizeof(float) * nn, hipMemcpyDeviceToHost));
+    if (ref) HIPCHK(hipMemcpy(ref, s->ref + n0, nn, hipMemcpyDeviceToHost));
+    if (pend) {
+      if (s->delivery == DPSNN_DELIVERY_PUSH) {
+        for (int q = 0; q < s->dh; ++q) {
+          const int64_t slot = (s->now + q) % s->dh;
+          HIPCHK(hipMemcpy(pend + q * nn, s->ring + slot * s->n_neurons + n0, sizeof(int32_t) * nn,
+                           hipMemcpyDeviceToHost));
+        }
+      } else {
+        int32_t* tmp = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)s->dh * nn);
+        HIPCHK(hipMemsetAsync(tmp, 0, sizeof(int32_t) * (size_t)s->dh * nn, s->stream));
+        HIPCHK(launch_pend_view(*s, tmp, g0, g1));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        HIPCHK(hipMemcpy(pend, tmp, sizeof(int32_t) * (size_t)s->dh * nn, hipMemcpyDeviceToHost));
+        dfree(*s, tmp);
+      }
+    }
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+int sim_read_synapses(sim_t* s, int32_t net, int64_t i0, int64_t i1, int64_t* row_ptr,
+                      int32_t* tgt, uint8_t* dly, int16_t* wq, int64_t cap) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    if (net < 0 || net >= s->n_nets) throw Fail{DPSNN_EINVAL, "net out of range"};
+    const int64_t nloc = (int64_t)(s->net_col0[net + 1] - s->net_col0[net]) * s->npc;
+    if (i0 < 0 || i1 < i0 || i1 > nloc || !row_ptr) throw Fail{DPSNN_EINVAL, "bad row range"};
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const int64_t g0 = (int64_t)s->net_col0[net] * s->npc + i0;
+    std::vector<int64_t> rb((size_t)(i1 - i0 + 1));
+    HIPCHK(hipMemcpy(rb.data(), s->row_base + g0, sizeof(int64_t) * rb.size(), hipMemcpyDeviceToHost));
+    for (size_t q = 0; q < rb.size(); ++q) row_ptr[q] = rb[q] - rb[0];
+    const int64_t total = rb.back() - rb.front();
+    if (total > cap) { s->err = "synapse buffers too small"; return DPSNN_ETRUNC; }
+    if (total == 0) return DPSNN_OK;
+    if (!tgt || !dly || !wq) throw Fail{DPSNN_EINVAL, "NULL output"};
+    int32_t* dt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)total);
+    uint8_t* dd = (uint8_t*)dalloc(*s, (size_t)total);
+    int16_t* dw = (int16_t*)dalloc(*s, sizeof(int16_t) * (size_t)total);
+    int64_t* doff = (int64_t*)dalloc(*s, sizeof(int64_t) * rb.size());
+    HIPCHK(hipMemcpy(doff, row_ptr, sizeof(int64_t) * rb.size(), hipMemcpyHostToDevice));
+    HIPCHK(launch_export_rows(*s, net, g0, g0 + (i1 - i0), dt, dd, dw, doff));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipMemcpy(tgt, dt, sizeof(int32_t) * (size_t)total, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(dly, dd, (size_t)total, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(wq, dw, sizeof(int16_t) * (size_t)total, hipMemcpyDeviceToHost));
+    dfree(*s, doff);
+    dfree(*s, dw);
+    dfree(*s, dd);
+    dfree(*s, dt);
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+int sim_save(sim_t* s, int32_t slot) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    if (slot < 0 || slot >= 64) throw Fail{DPSNN_EINVAL, "slot out of range"};
+    size_t parts[6];
+    void* srcs[6];
+    snapshot_parts(*s, parts, srcs);
+    size_t total = 0;
+    for (size_t p : parts) total += (p + 255) & ~(size_t)255;
+    Snapshot& sn = s->snaps[slot];
+    if (sn.blob.bytes < total) {
+      (void)hipFree(sn.blob.p);
+      sn.blob.p = nullptr;
+      if (hipMalloc(&sn.blob.p, total) != hipSuccess) {
+        (void)hipGetLastError();
+        sn.blob.bytes = 0;
+        throw Fail{DPSNN_ENOMEM, "snapshot allocation failed"};
+      }
+      sn.blob.bytes = total;
+    }
+    size_t off = 0;
+    for (int q = 0; q < 6; ++q) {
+      if (parts[q]) HIPCHK(hipMemcpyAsync((char*)sn.blob.p + off, srcs[q], parts[q], hipMemcpyDeviceToDevice, s->stream));
+      off += (parts[q] + 255) & ~(size_t)255;
+    }
+    sn.valid = true;
+    sn.now = s->now;
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+int sim_restore(sim_t* s, int32_t slot) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    if (slot < 0 || slot >= 64 || !s->snaps[slot].valid) throw Fail{DPSNN_ESTATE, "no snapshot in slot"};
+    Snapshot& sn = s->snaps[slot];
+    size_t parts[6];
+    void* dsts[6];
+    snapshot_parts(*s, parts, dsts);
+    size_t total = 0;
+    for (size_t p : parts) total += (p + 255) & ~(size_t)255;
+    if (total > sn.blob.bytes) throw Fail{DPSNN_ESTATE, "snapshot was taken with a different layout"};
+    size_t off = 0;
+    for (int q = 0; q < 6; ++q) {
+      if (parts[q]) HIPCHK(hipMemcpyAsync(dsts[q], (char*)sn.blob.p + off, parts[q], hipMemcpyDeviceToDevice, s->stream));
+      off += (parts[q] + 255) & ~(size_t)255;
+    }
+    s->now = sn.now;
+    // the push ring is a function of the spike history: rebuild it
+    if (s->delivery == DPSNN_DELIVERY_PUSH) ring_from_history(*s);
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+int sim_set_params(sim_t* s, double tau_m, double g_ahp) {
+  if (!s) return DPSNN_EINVAL;
+  if (!(tau_m > 0)) { s->err = "tau_m must be positive"; return DPSNN_EINVAL; }
+  s->cfg.tau_m = tau_m;
+  s->cfg.g_ahp = g_ahp;
+  set_constants(*s);
+  return DPSNN_OK;
+}
+
+int sim_get_launch(const sim_t* s, int32_t* delivery, int32_t* block) {
+  if (!s) return DPSNN_EINVAL;
+  if (delivery) *delivery = s->delivery;
+  if (block) *block = s->block;
+  return DPSNN_OK;
+}
+
+int sim_set_launch(sim_t* s, int32_t delivery, int32_t block) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    if (!(block == 64 || block == 128 || block == 256 || block == 512 || block == 1024))
+      throw Fail{DPSNN_EINVAL, "block must be 64, 128, 256, 512 or 1024"};
+    if (delivery != DPSNN_DELIVERY_ARRIVAL && delivery != DPSNN_DELIVERY_PUSH)
+      throw Fail{DPSNN_EINVAL, "delivery must be ARRIVAL or PUSH"};
+    if (delivery == DPSNN_DELIVERY_PUSH && s->delivery != DPSNN_DELIVERY_PUSH) ring_from_history(*s);
+    s->delivery = delivery;
+    s->block = block;
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+int sim_set_timing(sim_t* s, int32_t on) {
+  if (!s) return DPSNN_EINVAL;
+  s->timing = on != 0;
+  return DPSNN_OK;
+}
+
+int sim_get_timing(sim_t* s, double* ms, int32_t n) {
+  if (!s || !ms) return DPSNN_EINVAL;
+  for (int q = 0; q < n && q < 3; ++q) ms[q] = s->last_ms[q];
+  return DPSNN_OK;
+}
+
+int sim_set_weights(sim_t* s, const float* w) {
+  if (!s) return DPSNN_EINVAL;
+  s->err = "train mode is not available in this build";
+  (void)w;
+  return DPSNN_ESTATE;
+}
+
+int sim_get_weights(sim_t* s, float* w) {
+  if (!s) return DPSNN_EINVAL;
+  s->err = "train mode is not available in this build";
+  (void)w;
+  return DPSNN_ESTATE;
+}
+
+int sim_backward(sim_t* s, const float* grad_rates, float* grad_w, double* grad_tau_m,
+                 double* grad_g_ahp) {
+  if (!s) return DPSNN_EINVAL;
+  (void)grad_rates; (void)grad_w; (void)grad_tau_m; (void)grad_g_ahp;
+  s->err = "train mode is not available in this build";
+  return DPSNN_ESTATE;
+}
+
+}  // extern "C"

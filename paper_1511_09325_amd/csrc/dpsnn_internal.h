@@ -1,0 +1,205 @@
+// dpsnn_internal.h -- internal structures and device helpers of libdpsnn (gfx950).
+//
+// Device data layout (all networks of a simulation concatenated column by column; the
+// global neuron index is g*npc + k for global column g and local index k):
+//
+//   synapse store, canonical order: per source neuron, sorted by (delay, target);
+//   within one delay the targets come column by column in ascending column order, so a
+//   row splits into segments (delay d, target-column rank r), r indexing the source
+//   column's sorted list of distinct neighbour columns (at most 9: the 3x3 torus stencil)
+//     row_base  int64 [N+1]        first synapse of each row
+//     seg       uint16[N][segw]    seg[i][(d-d_min)*9 + r] = start of segment (d, r)
+//                                  relative to row_base[i]; entry nd*9 = row length
+//     syn       uint32[S]          (k : low 16 bits) | (w_q : high 16 bits), the target's
+//                                  index inside its column and the int16 weight (2^-14 mV)
+//     wfx       int32 [S]          train mode only: rint(w_f32 * 2^16) efficacies
+//   column tables
+//     col_nbr   int32 [C][9]       distinct neighbour columns, ascending, -1 padded
+//     col_rank  int32 [C][9]       rank of column g in the list of its neighbour col_nbr[g][r]
+//     col_thr   uint64[C][9]       pair connection threshold from g to col_nbr[g][r]
+//   spike history (shared by both delivery strategies)
+//     hist_cnt  int32 [DH][C]      spikes of column g at step t, in slot t % DH
+//     hist_ids  uint16[DH][C][npc] their local indices, ascending
+//   push-delivery ring (only with DPSNN_DELIVERY_PUSH)
+//     ring      int32 [DH][N]      input of step t in slot t % DH
+//
+// DH = d_max + 1 slots: a step reads slots of steps t-d_max .. t-1 and writes slot t.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dpsnn.h"
+
+namespace dpsnn {
+
+constexpr int kMaxNbr = 9;          // 3x3 stencil
+constexpr int kMaxNpc = 4096;
+constexpr int kMaxDelay = 32;
+constexpr int kPoissonEntries = 63;
+constexpr uint32_t kStreamSyn = 1;  // Philox counter word 3: purpose of the draw
+constexpr uint32_t kStreamExt = 2;
+constexpr uint32_t kStreamInit = 3;
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products, high halves
+// xor-ed with the other counter words and the key, key advanced by the Weyl increments.
+// ---------------------------------------------------------------------------------------
+struct Rand4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Rand4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Rand4{c0, c1, c2, c3};
+}
+
+// Neuron constants, rounded once from double on the host.
+struct NeuronK {
+  float pm;      // exp(-dt / tau_m)
+  float pc;      // exp(-dt / tau_ca)
+  float gam;     // g_ahp * dt
+  float alpha;   // calcium increment
+  float theta;
+  float vreset;
+  int32_t jfx;   // rint(j_ext * 2^16)
+  int32_t tref;
+};
+
+// Everything the step kernels read or write, by value.
+struct StepArgs {
+  // sizes
+  int32_t npc, nd, d_min, dh, segw, n_cols;
+  // column / network tables
+  const int32_t* col_net;
+  const int32_t* col_local;   // column index within its network
+  const int32_t* col_nbr;
+  const int32_t* col_nn;
+  const int32_t* col_rank;
+  const uint32_t* net_key;    // [n_nets][2]
+  const uint64_t* net_ptab;   // [n_nets][63]
+  // synapses
+  const int64_t* row_base;
+  const uint16_t* seg;
+  const uint32_t* syn;
+  const int32_t* wfx;         // train mode, else null
+  // state
+  float* v;
+  float* ca;
+  uint8_t* ref;
+  int32_t* hist_cnt;
+  uint16_t* hist_ids;
+  int32_t* ring;              // push only
+  unsigned long long* net_cnt;  // [n_nets][4]: spikes, e_rec, e_ext, steps
+  // train-mode trajectory recording (null when off): [rec_steps][N]
+  float* rec_vprev;
+  float* rec_caprev;
+  float* rec_vt;
+  uint8_t* rec_flags;         // bit0 spike, bit1 refractory
+  int64_t rec_base;           // first step held by the recording buffers
+  NeuronK k;
+};
+
+// ---------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Snapshot {
+  bool valid = false;
+  int64_t now = 0;
+  DevBuf blob;  // v | ca | ref | hist_cnt | hist_ids | ring | net_cnt
+};
+
+}  // namespace dpsnn
+
+struct sim {
+  sim_config_t cfg;
+  std::vector<sim_net_t> nets;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int sticky = 0;
+
+  // sizes
+  int32_t n_nets = 0, n_cols = 0, npc = 0, nd = 0, dh = 0, segw = 0;
+  int64_t n_neurons = 0, n_syn = 0;
+  std::vector<int32_t> net_col0;    // first global column of each network (n_nets+1)
+  std::vector<int64_t> net_syn0;    // first synapse of each network (n_nets+1)
+
+  // device memory
+  std::vector<dpsnn::DevBuf> bufs;
+  size_t device_bytes = 0;
+  int32_t *col_net = nullptr, *col_local = nullptr, *col_nbr = nullptr, *col_nn = nullptr,
+          *col_rank = nullptr;
+  uint64_t* col_thr = nullptr;
+  uint32_t* net_key = nullptr;
+  uint64_t* net_ptab = nullptr;
+  int64_t* row_base = nullptr;
+  uint16_t* seg = nullptr;
+  uint32_t* syn = nullptr;
+  int32_t* wfx = nullptr;
+  float* wf32 = nullptr;
+  float *v = nullptr, *ca = nullptr;
+  uint8_t* ref = nullptr;
+  int32_t* hist_cnt = nullptr;
+  uint16_t* hist_ids = nullptr;
+  int32_t* ring = nullptr;
+  unsigned long long* net_cnt = nullptr;
+  // raster
+  int64_t* ras_off = nullptr;      // [record_steps+1]
+  int32_t* ras_ids = nullptr;      // [raster_capacity], global neuron ids
+  int64_t* ras_colofs = nullptr;   // [C] scratch
+  int32_t* flags = nullptr;        // [4]: raster overflow
+  // train mode
+  float *rec_vprev = nullptr, *rec_caprev = nullptr, *rec_vt = nullptr;
+  uint8_t* rec_flags = nullptr;
+  int64_t rec_steps = 0;
+
+  int64_t now = 0;
+  int32_t delivery = DPSNN_DELIVERY_ARRIVAL;
+  int32_t block = 256;
+  dpsnn::NeuronK nk;
+  std::vector<dpsnn::Snapshot> snaps;
+
+  bool timing = false;
+  double last_ms[3] = {0, 0, 0};
+};
+
+namespace dpsnn {
+
+// launchers implemented in the .hip files (host functions)
+hipError_t launch_gen_count(const sim& s, int64_t row0, int64_t rows, int32_t* row_len);
+hipError_t launch_gen_fill(const sim& s, int64_t row0, int64_t rows);
+hipError_t launch_scan_rows(const sim& s, const int32_t* row_len, int64_t n, int64_t* out,
+                            int64_t* scratch, int64_t scratch_len);
+hipError_t launch_init_state(const sim& s);
+hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block);
+hipError_t launch_raster(sim& s, int64_t u);
+hipError_t launch_pend_view(const sim& s, int32_t* pend, int32_t g0, int32_t g1);
+hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1, int32_t* tgt,
+                              uint8_t* dly, int16_t* wq, const int64_t* out_off);
+hipError_t launch_quantise(const sim& s);
+int64_t scan_scratch_len(int64_t n);
+
+StepArgs make_step_args(const sim& s);
+
+}  // namespace dpsnn

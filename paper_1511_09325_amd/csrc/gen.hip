@@ -1,0 +1,304 @@
+// gen.hip -- network construction on the device.
+//
+// Follows the paper's network description (section 2, Methods): columns of point neurons,
+// 80 % excitatory, each neuron connected to neurons of its own column with a fixed pair
+// probability and to the neighbouring columns with a probability decaying with distance;
+// plus the workload's integer delays and normal weights.  Every pair (i, j) of a source
+// neuron i and a candidate target j in the 3x3 torus neighbourhood of i's column is one
+// Bernoulli trial decided by Philox4x32-10 at counter (j, i, 0, SYN) of the network's key:
+//   connected iff word x < threshold(column pair)       (threshold = floor(p 2^32))
+//   delay      d = d_min + floor(word y * nd / 2^32)
+//   weight     mu + sigma * z, z = (sum of 12 16-bit halves of words z, w and of the four
+//              words at counter (j, i, 1, SYN) - 393210) / 65536, in double, no FMA,
+//              quantised to int16 at 2^-14 mV with round-half-even.
+// Rows are written in canonical order (delay, target).  Two passes: counting per
+// (delay, target column) segment, then an exclusive scan over rows, then filling.
+#include "dpsnn_internal.h"
+
+namespace dpsnn {
+namespace {
+
+struct GenArgs {
+  int32_t npc, n_exc, nd, d_min, segw;
+  int64_t row0, rows;
+  const int32_t* col_net;
+  const int32_t* col_local;
+  const int32_t* col_nbr;
+  const int32_t* col_nn;
+  const uint64_t* col_thr;
+  const uint32_t* net_key;
+  double we_mu, we_sigma, wi_mu, wi_sigma;
+  int32_t* row_len;        // count pass output
+  uint16_t* seg;           // count pass output
+  const int64_t* row_base; // fill pass input
+  uint32_t* syn;           // fill pass output
+};
+
+constexpr int kGenWaves = 4;  // rows per workgroup (one wave each)
+
+__device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Decide one candidate: returns connected flag and delay index (0..nd-1).
+__device__ __forceinline__ bool decide(const GenArgs& a, int64_t i, int64_t jglob, uint32_t jl,
+                                       uint32_t il, uint32_t k0, uint32_t k1, uint64_t thr,
+                                       bool valid, int& dd, Rand4& r) {
+  r = philox10(jl, il, 0u, kStreamSyn, k0, k1);
+  const bool conn = valid && (jglob != i) && ((uint64_t)r.x < thr);
+  dd = (int)(((uint64_t)r.y * (uint64_t)a.nd) >> 32);
+  return conn;
+}
+
+__global__ __launch_bounds__(64 * kGenWaves) void k_gen_count(GenArgs a) {
+  __shared__ int32_t cnt[kGenWaves][kMaxNbr * kMaxDelay];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int nseg = a.nd * kMaxNbr;
+  for (int64_t rr = (int64_t)blockIdx.x * kGenWaves + wave; rr < a.rows;
+       rr += (int64_t)gridDim.x * kGenWaves) {
+    const int64_t i = a.row0 + rr;
+    const int32_t g = (int32_t)(i / a.npc);
+    const int32_t kk = (int32_t)(i - (int64_t)g * a.npc);
+    const int32_t net = a.col_net[g];
+    const uint32_t il = (uint32_t)(a.col_local[g] * a.npc + kk);
+    const uint32_t k0 = a.net_key[2 * net], k1 = a.net_key[2 * net + 1];
+    const int nn = a.col_nn[g];
+    for (int q = lane; q < nseg; q += 64) cnt[wave][q] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (int r = 0; r < nn; ++r) {
+      const int32_t tc = a.col_nbr[g * kMaxNbr + r];
+      const uint64_t thr = a.col_thr[g * kMaxNbr + r];
+      const uint32_t tl0 = (uint32_t)(a.col_local[tc] * a.npc);
+      int32_t mine = 0;
+      for (int kb = 0; kb < a.npc; kb += 64) {
+        const int k = kb + lane;
+        int dd;
+        Rand4 rr4;
+        const bool conn = decide(a, i, (int64_t)tc * a.npc + k, tl0 + (uint32_t)k, il, k0, k1,
+                                 thr, k < a.npc, dd, rr4);
+        for (int q = 0; q < a.nd; ++q) {
+          const unsigned long long m = __ballot(conn && dd == q);
+          if (lane == q) mine += __popcll(m);
+        }
+      }
+      if (lane < a.nd) cnt[wave][lane * kMaxNbr + r] = mine;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // exclusive prefix over the nd*9 segments in (delay, rank) order
+    const int per = (nseg + 63) / 64;
+    int32_t local = 0;
+    for (int q = 0; q < per; ++q) {
+      const int e = lane * per + q;
+      if (e < nseg) local += cnt[wave][e];
+    }
+    int32_t incl = local;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
+    }
+    int32_t run = incl - local;
+    uint16_t* out = a.seg + i * a.segw;
+    for (int q = 0; q < per; ++q) {
+      const int e = lane * per + q;
+      if (e < nseg) {
+        out[e] = (uint16_t)run;
+        run += cnt[wave][e];
+      }
+    }
+    const int32_t total = __shfl(incl, 63);
+    if (lane == 0) {
+      out[nseg] = (uint16_t)total;
+      a.row_len[i] = total;
+    }
+    for (int e = nseg + 1 + lane; e < a.segw; e += 64) out[e] = 0;
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = lanemask_lt(lane);
+  for (int64_t rr = (int64_t)blockIdx.x * kGenWaves + wave; rr < a.rows;
+       rr += (int64_t)gridDim.x * kGenWaves) {
+    const int64_t i = a.row0 + rr;
+    const int32_t g = (int32_t)(i / a.npc);
+    const int32_t kk = (int32_t)(i - (int64_t)g * a.npc);
+    const int32_t net = a.col_net[g];
+    const uint32_t il = (uint32_t)(a.col_local[g] * a.npc + kk);
+    const uint32_t k0 = a.net_key[2 * net], k1 = a.net_key[2 * net + 1];
+    const int nn = a.col_nn[g];
+    const bool exc = kk < a.n_exc;
+    const double mu = exc ? a.we_mu : a.wi_mu;
+    const double sigma = exc ? a.we_sigma : a.wi_sigma;
+    const uint16_t* sg = a.seg + i * a.segw;
+    uint32_t* out = a.syn + a.row_base[i];
+    for (int r = 0; r < nn; ++r) {
+      const int32_t tc = a.col_nbr[g * kMaxNbr + r];
+      const uint64_t thr = a.col_thr[g * kMaxNbr + r];
+      const uint32_t tl0 = (uint32_t)(a.col_local[tc] * a.npc);
+      // lane q holds the write cursor of segment (q, r)
+      int32_t cursor = lane < a.nd ? (int32_t)sg[lane * kMaxNbr + r] : 0;
+      for (int kb = 0; kb < a.npc; kb += 64) {
+        const int k = kb + lane;
+        int dd;
+        Rand4 r4;
+        const bool conn = decide(a, i, (int64_t)tc * a.npc + k, tl0 + (uint32_t)k, il, k0, k1,
+                                 thr, k < a.npc, dd, r4);
+        int32_t pos = 0;
+        for (int q = 0; q < a.nd; ++q) {
+          const unsigned long long m = __ballot(conn && dd == q);
+          const int32_t base = __shfl(cursor, q);
+          if (conn && dd == q) pos = base + __popcll(m & lt);
+          if (lane == q) cursor += __popcll(m);
+        }
+        if (conn) {
+          const Rand4 r2 = philox10(tl0 + (uint32_t)k, il, 1u, kStreamSyn, k0, k1);
+          const uint32_t words[6] = {r4.z, r4.w, r2.x, r2.y, r2.z, r2.w};
+          int32_t sum = 0;
+#pragma unroll
+          for (int q = 0; q < 6; ++q) sum += (int32_t)(words[q] & 0xffffu) + (int32_t)(words[q] >> 16);
+          const double z = (double)(sum - 393210) * (1.0 / 65536.0);
+          const double prod = sigma * z;
+          const double w = mu + prod;
+          const int16_t wq = (int16_t)__builtin_rint(w * 16384.0);
+          out[pos] = (uint32_t)(uint16_t)k | ((uint32_t)(uint16_t)wq << 16);
+        }
+      }
+    }
+  }
+}
+
+GenArgs gen_args(const sim& s, int64_t row0, int64_t rows) {
+  GenArgs a{};
+  a.npc = s.npc;
+  a.n_exc = s.cfg.n_exc;
+  a.nd = s.nd;
+  a.d_min = s.cfg.d_min;
+  a.segw = s.segw;
+  a.row0 = row0;
+  a.rows = rows;
+  a.col_net = s.col_net;
+  a.col_local = s.col_local;
+  a.col_nbr = s.col_nbr;
+  a.col_nn = s.col_nn;
+  a.col_thr = s.col_thr;
+  a.net_key = s.net_key;
+  a.we_mu = s.cfg.we_mu;
+  a.we_sigma = s.cfg.we_sigma;
+  a.wi_mu = s.cfg.wi_mu;
+  a.wi_sigma = s.cfg.wi_sigma;
+  a.seg = s.seg;
+  a.row_base = s.row_base;
+  a.syn = s.syn;
+  return a;
+}
+
+int gen_grid(int64_t rows) {
+  const int64_t wgs = (rows + kGenWaves - 1) / kGenWaves;
+  return (int)(wgs < 65536 ? wgs : 65536);
+}
+
+// ---- exclusive scan int32 -> int64 (three passes) ------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ int64_t block_exclusive_scan(int64_t x, int64_t* total) {
+  __shared__ int64_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t incl = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    if (w < wave) before += wsum[w];
+    all += wsum[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - x;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t* in, int64_t n,
+                                                              int64_t* part) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t acc = 0;
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t e = base + (int64_t)q * kScanThreads + threadIdx.x;
+    if (e < n) acc += in[e];
+  }
+  int64_t total;
+  block_exclusive_scan(acc, &total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(int64_t* part, int64_t np) {
+  int64_t carry = 0;
+  for (int64_t b = 0; b < np; b += kScanThreads) {
+    const int64_t e = b + threadIdx.x;
+    const int64_t x = e < np ? part[e] : 0;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan(x, &total);
+    if (e < np) part[e] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* in, int64_t n,
+                                                             const int64_t* part, int64_t* out) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  // each thread owns kScanItems consecutive elements
+  const int64_t my0 = base + (int64_t)threadIdx.x * kScanItems;
+  int64_t local = 0;
+  for (int q = 0; q < kScanItems; ++q)
+    if (my0 + q < n) local += in[my0 + q];
+  int64_t total;
+  int64_t run = part[blockIdx.x] + block_exclusive_scan(local, &total);
+  for (int q = 0; q < kScanItems; ++q) {
+    const int64_t e = my0 + q;
+    if (e < n) {
+      out[e] = run;
+      run += in[e];
+      if (e == n - 1) out[n] = run;  // the total, written by the owner of the last element
+    }
+  }
+}
+
+}  // namespace
+
+int64_t scan_scratch_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_gen_count(const sim& s, int64_t row0, int64_t rows, int32_t* row_len) {
+  GenArgs a = gen_args(s, row0, rows);
+  a.row_len = row_len;
+  hipLaunchKernelGGL(k_gen_count, dim3(gen_grid(rows)), dim3(64 * kGenWaves), 0, s.stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gen_fill(const sim& s, int64_t row0, int64_t rows) {
+  GenArgs a = gen_args(s, row0, rows);
+  hipLaunchKernelGGL(k_gen_fill, dim3(gen_grid(rows)), dim3(64 * kGenWaves), 0, s.stream, a);
+  return hipGetLastError();
+}
+
+// out[0..n] = exclusive prefix of in[0..n), out[n] = total.
+hipError_t launch_scan_rows(const sim& s, const int32_t* in, int64_t n, int64_t* out,
+                            int64_t* part, int64_t part_len) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb + 1 > part_len) return hipErrorInvalidValue;
+  if (nb == 0) return hipMemsetAsync(out, 0, sizeof(int64_t), s.stream);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s.stream, in, n,
+                     part);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, s.stream, part, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s.stream, in, n,
+                     part, out);
+  return hipGetLastError();
+}
+
+}  // namespace dpsnn

@@ -1,0 +1,187 @@
+"""Python front end of libdpsnn: one Simulation object per sim_t handle.
+
+Argument marshalling only -- every step of the simulation runs in the HIP kernels behind
+the C ABI.  PyTorch supplies the HIP stream (its current stream) and, in train mode, the
+device tensors that carry weights and gradients.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _stream_ptr(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return C.c_void_p(None)
+
+
+def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, block: int = 0,
+                record_steps: int = 0, raster_capacity: int = 0, train_mode: bool = False,
+                ckpt_every: int = 50):
+    """sim_config_t from one parameter dict, or a list of them (batched form: all share the
+    column recipe of the first; grid shape, seed and external rate are per network)."""
+    plist = params if isinstance(params, list) else [params]
+    p0 = plist[0]
+    nets = (L.SimNet * len(plist))()
+    for n, p in enumerate(plist):
+        nets[n].rows, nets[n].cols = int(p["rows"]), int(p["cols"])
+        nets[n].seed = int(p["seed"])
+        nets[n].ext_rate_hz = float(p["ext_rate_hz"])
+    c = L.SimConfig()
+    for name in ("npc", "n_exc", "d_min", "d_max", "t_ref", "ext_syn"):
+        setattr(c, name, int(p0[name]))
+    for name in ("p_own", "p_remote", "decay_um", "spacing_um", "we_mu", "we_sigma", "wi_mu",
+                 "wi_sigma", "tau_m", "theta", "v_reset", "tau_ca", "ca_inc", "g_ahp", "dt",
+                 "j_ext"):
+        setattr(c, name, float(p0[name]))
+    c.n_nets = len(plist)
+    c.nets = C.cast(nets, C.POINTER(L.SimNet))
+    c.delivery, c.block = int(delivery), int(block)
+    c.record_steps, c.raster_capacity = int(record_steps), int(raster_capacity)
+    c.train_mode, c.ckpt_every = int(bool(train_mode)), int(ckpt_every)
+    return c, nets
+
+
+class Simulation:
+    def __init__(self, params, *, delivery: int = L.DELIVERY_AUTO, block: int = 0,
+                 record_steps: int = 0, raster_capacity: int | None = None,
+                 train_mode: bool = False, ckpt_every: int = 50, stream=None):
+        self.params = params if isinstance(params, list) else [params]
+        if raster_capacity is None:
+            n = sum(p["rows"] * p["cols"] * p["npc"] for p in self.params)
+            raster_capacity = max(1, int(record_steps * n * 0.2)) if record_steps else 0
+        cfg, self._nets = make_config(params, delivery=delivery, block=block,
+                                      record_steps=record_steps, raster_capacity=raster_capacity,
+                                      train_mode=train_mode, ckpt_every=ckpt_every)
+        self._cfg = cfg
+        self.lib = L.lib()
+        h = C.c_void_p()
+        L.check(self.lib.sim_create(C.byref(cfg), _stream_ptr(stream), C.byref(h)), None)
+        self.h = h
+        info = L.SimInfo()
+        L.check(self.lib.sim_get_info(self.h, C.byref(info)), self.h)
+        self.n_nets = info.n_nets
+        self.n_cols = info.n_cols
+        self.n_neurons = info.n_neurons
+        self.n_synapses = info.n_synapses
+        self.ring_slots = info.ring_slots
+        self.device_bytes = info.device_bytes
+        self.record_steps = record_steps
+
+    # -- lifetime -------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping -------------------------------------------------------------------------
+    def step(self, n: int = 1):
+        L.check(self.lib.sim_step(self.h, int(n)), self.h)
+
+    def sync(self):
+        L.check(self.lib.sim_sync(self.h), self.h)
+
+    @property
+    def now(self) -> int:
+        return self.lib.sim_now(self.h)
+
+    # -- outputs --------------------------------------------------------------------------
+    def net_neurons(self, net: int = 0) -> int:
+        p = self.params[net]
+        return p["rows"] * p["cols"] * p["npc"]
+
+    def read_spikes(self, net: int = 0, t0: int = 0, t1: int | None = None):
+        """List (one array per step) of ascending network-local spike ids."""
+        if t1 is None:
+            t1 = min(self.now, self.record_steps)
+        off = np.zeros(t1 - t0 + 1, np.int64)
+        n = C.c_int64(0)
+        rc = self.lib.sim_read_spikes(self.h, net, t0, t1, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      None, 0, C.byref(n))
+        if rc not in (L.OK, L.ETRUNC):
+            L.check(rc, self.h)
+        ids = np.zeros(max(n.value, 1), np.int32)
+        L.check(self.lib.sim_read_spikes(self.h, net, t0, t1,
+                                         off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         ids.ctypes.data_as(C.POINTER(C.c_int32)), ids.size,
+                                         C.byref(n)), self.h)
+        return [ids[off[q]:off[q + 1]].copy() for q in range(t1 - t0)]
+
+    def stats(self, net: int = 0) -> dict:
+        s = L.SimStats()
+        L.check(self.lib.sim_get_stats(self.h, net, C.byref(s)), self.h)
+        return {"steps": s.steps, "spikes": s.spikes, "e_rec": s.events_recurrent,
+                "e_ext": s.events_external}
+
+    def state(self, net: int = 0, pend: bool = True) -> dict:
+        n = self.net_neurons(net)
+        v = np.zeros(n, np.float32)
+        ca = np.zeros(n, np.float32)
+        ref = np.zeros(n, np.uint8)
+        pd = np.zeros((self.ring_slots, n), np.int32) if pend else None
+        L.check(self.lib.sim_read_state(
+            self.h, net, v.ctypes.data_as(C.POINTER(C.c_float)),
+            ca.ctypes.data_as(C.POINTER(C.c_float)), ref.ctypes.data_as(C.POINTER(C.c_uint8)),
+            pd.ctypes.data_as(C.POINTER(C.c_int32)) if pend else None), self.h)
+        return {"v": v, "ca": ca, "ref": ref, "pend": pd, "now": self.now}
+
+    def synapses(self, net: int = 0, i0: int = 0, i1: int | None = None):
+        """(row_ptr, tgt, dly, wq) of source rows [i0, i1) in canonical order."""
+        if i1 is None:
+            i1 = self.net_neurons(net)
+        rp = np.zeros(i1 - i0 + 1, np.int64)
+        rc = self.lib.sim_read_synapses(self.h, net, i0, i1, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                        None, None, None, 0)
+        if rc not in (L.OK, L.ETRUNC):
+            L.check(rc, self.h)
+        total = int(rp[-1])
+        tgt = np.zeros(max(total, 1), np.int32)
+        dly = np.zeros(max(total, 1), np.uint8)
+        wq = np.zeros(max(total, 1), np.int16)
+        L.check(self.lib.sim_read_synapses(
+            self.h, net, i0, i1, rp.ctypes.data_as(C.POINTER(C.c_int64)),
+            tgt.ctypes.data_as(C.POINTER(C.c_int32)), dly.ctypes.data_as(C.POINTER(C.c_uint8)),
+            wq.ctypes.data_as(C.POINTER(C.c_int16)), total), self.h)
+        return rp, tgt[:total], dly[:total], wq[:total]
+
+    # -- state management ---------------------------------------------------------------------
+    def save(self, slot: int = 0):
+        L.check(self.lib.sim_save(self.h, slot), self.h)
+
+    def restore(self, slot: int = 0):
+        L.check(self.lib.sim_restore(self.h, slot), self.h)
+
+    def set_launch(self, delivery: int, block: int):
+        L.check(self.lib.sim_set_launch(self.h, int(delivery), int(block)), self.h)
+
+    def get_launch(self):
+        d, b = C.c_int32(), C.c_int32()
+        L.check(self.lib.sim_get_launch(self.h, C.byref(d), C.byref(b)), self.h)
+        return d.value, b.value
+
+    def set_params(self, tau_m: float, g_ahp: float):
+        L.check(self.lib.sim_set_params(self.h, float(tau_m), float(g_ahp)), self.h)
+
+    def set_timing(self, on: bool = True):
+        L.check(self.lib.sim_set_timing(self.h, 1 if on else 0), self.h)
+
+    def timing(self):
+        ms = (C.c_double * 3)()
+        L.check(self.lib.sim_get_timing(self.h, ms, 3), self.h)
+        return list(ms)

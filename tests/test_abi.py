@@ -1,0 +1,110 @@
+"""The C ABI library without a GPU: it loads, exports every entry point that
+include/dpsnn.h declares, the ctypes mirror of its structs matches the C layout, and
+configuration errors are rejected before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1511_09325_amd import _lib as L
+from paper_1511_09325_amd import workloads as W
+from paper_1511_09325_amd.sim import make_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpsnn.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libdpsnn.so is not built; run __graft_entry__.build()")
+    return L.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 20
+    assert sorted(names) == sorted(L.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_error_codes_match_header():
+    text = open(HEADER).read()
+    codes = dict(re.findall(r"#define (DPSNN_E[A-Z]+) \((-\d+)\)", text))
+    assert int(codes["DPSNN_EINVAL"]) == L.EINVAL
+    assert int(codes["DPSNN_ENOMEM"]) == L.ENOMEM
+    assert int(codes["DPSNN_EHIP"]) == L.EHIP
+    assert int(codes["DPSNN_ESTATE"]) == L.ESTATE
+    assert int(codes["DPSNN_ETRUNC"]) == L.ETRUNC
+
+
+_PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "dpsnn.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("sim_config_t %zu\nsim_net_t %zu\nsim_info_t %zu\nsim_stats_t %zu\n",
+         sizeof(sim_config_t), sizeof(sim_net_t), sizeof(sim_info_t), sizeof(sim_stats_t));
+  F(sim_config_t, nets) F(sim_config_t, delivery) F(sim_config_t, record_steps)
+  F(sim_config_t, ckpt_every) F(sim_config_t, j_ext) F(sim_net_t, ext_rate_hz)
+  F(sim_info_t, device_bytes)
+  return 0;
+}
+"""
+
+
+def test_struct_layout_matches_c():
+    with tempfile.TemporaryDirectory() as td:
+        src, exe = os.path.join(td, "p.c"), os.path.join(td, "p")
+        open(src, "w").write(_PROBE)
+        subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), src, "-o", exe])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(line.split() for line in out.strip().splitlines())
+    assert int(got["sim_config_t"]) == C.sizeof(L.SimConfig)
+    assert int(got["sim_net_t"]) == C.sizeof(L.SimNet)
+    assert int(got["sim_info_t"]) == C.sizeof(L.SimInfo)
+    assert int(got["sim_stats_t"]) == C.sizeof(L.SimStats)
+    for key, (cls, field) in {"sim_config_t.nets": (L.SimConfig, "nets"),
+                              "sim_config_t.delivery": (L.SimConfig, "delivery"),
+                              "sim_config_t.record_steps": (L.SimConfig, "record_steps"),
+                              "sim_config_t.ckpt_every": (L.SimConfig, "ckpt_every"),
+                              "sim_config_t.j_ext": (L.SimConfig, "j_ext"),
+                              "sim_net_t.ext_rate_hz": (L.SimNet, "ext_rate_hz"),
+                              "sim_info_t.device_bytes": (L.SimInfo, "device_bytes")}.items():
+        assert int(got[key]) == getattr(cls, field).offset, key
+
+
+@pytest.mark.parametrize("bad", [
+    dict(npc=0), dict(npc=5000), dict(n_exc=2000), dict(d_min=0), dict(d_max=40),
+    dict(d_min=5, d_max=4), dict(wi_mu=-1.9), dict(tau_m=0.0), dict(t_ref=300),
+    dict(p_own=0.9, p_remote=0.4), dict(rows=0), dict(ext_rate_hz=50.0),
+])
+def test_invalid_configs_are_rejected_before_device_work(lib, bad):
+    p = W.grid(2, 2)
+    p.update(bad)
+    cfg, nets = make_config(p)
+    h = C.c_void_p(123)
+    rc = lib.sim_create(C.byref(cfg), None, C.byref(h))
+    assert rc == L.EINVAL
+    assert h.value is None
+    assert lib.sim_last_error(None)
+
+
+def test_null_handles(lib):
+    assert lib.sim_step(None, 1) == L.EINVAL
+    assert lib.sim_sync(None) == L.EINVAL
+    assert lib.sim_now(None) == -1
+    lib.sim_destroy(None)
+    h = C.c_void_p(123)
+    assert lib.sim_create(None, None, C.byref(h)) == L.EINVAL
