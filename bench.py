@@ -1,0 +1,200 @@
+#!/usr/bin/env python
+"""bench.py -- throughput of the DPSNN per-1 ms step on one MI355X.
+
+Default workload: the plain 96x96 grid of 1240-neuron columns (11,427,840 neurons, about
+14.2G recurrent synapses generated on the GPU), 2 s simulated at dt = 1 ms, synthetic and
+seeded.  One "step" is one 1 ms step of the whole network: every neuron updated, every
+delayed spike delivered.
+
+Prints ONE JSON line.  `value` is synaptic events per second (recurrent events -- the
+outgoing synapses of every emitted spike -- plus external Poisson arrivals, the paper's
+event definition), with the network resident in HBM before the timed region starts.
+`roofline` prices the dominant kernel (the fused gather + update step kernel) against
+HBM bandwidth, with its duration measured by HIP events around every launch on the
+simulation's stream.  `cpu_baseline` times the plain CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SYNAPSE = 4       # one uint32 record: target index in column (16 b) + weight (16 b)
+BYTES_PER_NEURON = 18       # V, Ca (float32) and refractory counter (uint8), read and written
+
+WORKLOADS = {
+    "96x96": ("PLAIN_96X96", 2000),
+    "24x24": ("PLAIN_24X24", 10000),
+    "2x2": ("PLAIN_2X2", 1000),
+}
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("step.hip", "dpsnn_internal.h"):
+        with open(os.path.join(ROOT, "paper_1511_09325_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, delivery: str):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if they
+    were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get("%s/%s" % (workload, delivery))
+    except Exception:
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(sample_steps: int = 1000):
+    """The CPU oracle, as it stands, on a bounded sample of the same workload family: the
+    4x4 grid of the same column recipe (19,840 neurons, ~24.6M synapses), seed 0; only its
+    step loop is timed (network construction excluded); one thread."""
+    import oracle
+    from paper_1511_09325_amd import workloads as W
+    p = W.grid(4, 4, 0)
+    net = oracle.network(p)
+    sim = oracle.Sim(p, net)
+    sim.step(20)
+    c0 = sim.counts()
+    t0 = time.perf_counter()
+    sim.step(sample_steps)
+    dt = time.perf_counter() - t0
+    c1 = sim.counts()
+    ev = (c1["e_rec"] - c0["e_rec"]) + (c1["e_ext"] - c0["e_ext"])
+    return {"value": ev / dt, "unit": "synaptic events/s", "cores": 1, "kind": "oracle",
+            "sample": "4x4 grid of the same column recipe (19,840 neurons, %d synapses), "
+                      "seed 0, %d steps after 20 warm-up steps, step loop only, %.1f s"
+                      % (len(net[1]), sample_steps, dt),
+            "sim_ms_per_wall_s": sample_steps / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's)")
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="96x96", choices=sorted(WORKLOADS))
+    ap.add_argument("--delivery", default="arrival", choices=["arrival", "push"])
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the path is single-GPU by design "
+              "(no sharding, no collectives); --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1511_09325_amd import DELIVERY_ARRIVAL, DELIVERY_PUSH, Simulation
+    from paper_1511_09325_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    preset_name, default_steps = WORKLOADS[args.workload]
+    preset = getattr(W, preset_name)
+    p = preset["params"]
+    K = args.steps if args.steps is not None else default_steps
+    delivery = DELIVERY_ARRIVAL if args.delivery == "arrival" else DELIVERY_PUSH
+
+    log("generating %s on the GPU" % preset["name"])
+    t0 = time.perf_counter()
+    sim = Simulation(p, delivery=delivery, block=args.block)
+    sim.sync()
+    t_gen = time.perf_counter() - t0
+    log("generated %d neurons, %d synapses in %.1f s (%.1f GB on device)"
+        % (sim.n_neurons, sim.n_synapses, t_gen, sim.device_bytes / 1e9))
+
+    sim.step(args.warmup)
+    sim.sync()
+    log("warm-up %d steps done" % args.warmup)
+    s0 = sim.stats()
+    sim.set_timing(True)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    sim.step(K)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = ev0.elapsed_time(ev1)
+    sim.sync()
+    tm = sim.timing()
+    s1 = sim.stats()
+    log("timed %d steps in %.1f ms" % (K, wall_ms))
+
+    e_rec = s1["e_rec"] - s0["e_rec"]
+    e_ext = s1["e_ext"] - s0["e_ext"]
+    spikes = s1["spikes"] - s0["spikes"]
+    streamed = s1["streamed"] - s0["streamed"]
+    secs = wall_ms / 1e3
+    value = (e_rec + e_ext) / secs
+
+    kern = tm["update"]
+    dom_ms = kern["ms"] / max(kern["launches"], 1)
+    if args.delivery == "push":
+        # in the push form the delivery kernel streams the synapses; the update kernel the neurons
+        dk = tm["deliver"]
+        dom_ms = dk["ms"] / max(dk["launches"], 1)
+        bytes_per_launch = BYTES_PER_SYNAPSE * streamed / K
+        dom_name = "k_deliver_push"
+    else:
+        bytes_per_launch = (BYTES_PER_SYNAPSE * streamed + BYTES_PER_NEURON * sim.n_neurons * K) / K
+        dom_name = "k_step_arrival"
+    achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.delivery)
+
+    out = {
+        "metric": "synaptic events/s (recurrent + external) and sim-ms per wall-s",
+        "value": value,
+        "unit": "synaptic events/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": wall_ms / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32 input, f32 state",
+        "data": "synthetic (seeded network and Poisson input of the column recipe)",
+        "config": {"workload": preset["name"], "grid": args.workload, "neurons": sim.n_neurons,
+                   "synapses": sim.n_synapses, "dt_ms": p["dt"], "delivery": args.delivery,
+                   "block": args.block, "parallelism": "single GPU"},
+        "sim_ms_per_wall_s": K * p["dt"] / secs,
+        "recurrent_events_per_s": e_rec / secs,
+        "external_events_per_s": e_ext / secs,
+        "mean_rate_hz": spikes / (sim.n_neurons * K * p["dt"] * 1e-3),
+        "generation_s": t_gen,
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_launch_ms": dom_ms,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -103,6 +103,7 @@ typedef struct {
   int64_t spikes;
   int64_t events_recurrent; /* outgoing synapses of every emitted spike */
   int64_t events_external;  /* external Poisson arrivals drawn */
+  int64_t synapses_streamed; /* synapse records read by the delivery kernels */
 } sim_stats_t;
 
 /* Build the networks on the device (connectivity, delays, weights; the paper's section 2
@@ -181,9 +182,11 @@ int sim_get_launch(const sim_t* sim, int32_t* delivery, int32_t* block);
 /* Change them; results are bit-identical for every choice. */
 int sim_set_launch(sim_t* sim, int32_t delivery, int32_t block);
 
-/* Per-kernel device time of the last sim_step call, measured with HIP events on the
- * simulation's stream when timing is on: ms[0] update (+fused delivery), ms[1] push
- * delivery, ms[2] raster.  Timing adds events around every launch. */
+/* Per-kernel device time of the last sim_step call, measured with HIP events recorded on
+ * the simulation's stream around every kernel launch while timing is on.  ms[0..2]: total
+ * milliseconds of class 0 (the update kernel; in the arrival form it also gathers the
+ * delivered input), class 1 (push delivery) and class 2 (raster recording); ms[3..5]: the
+ * number of launches of each class.  n is the capacity of ms (up to 6 are written). */
 int sim_set_timing(sim_t* sim, int32_t on);
 int sim_get_timing(sim_t* sim, double* ms, int32_t n);
 

@@ -54,7 +54,7 @@ class SimInfo(C.Structure):
 
 class SimStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("spikes", C.c_int64), ("events_recurrent", C.c_int64),
-                ("events_external", C.c_int64)]
+                ("events_external", C.c_int64), ("synapses_streamed", C.c_int64)]
 
 
 _lib = None

@@ -343,6 +343,7 @@ void sim_destroy(sim_t* s) {
   else (void)hipDeviceSynchronize();
   for (DevBuf& b : s->bufs) (void)hipFree(b.p);
   for (Snapshot& sn : s->snaps) (void)hipFree(sn.blob.p);
+  for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -351,26 +352,53 @@ int sim_step(sim_t* s, int64_t n_steps) {
   if (n_steps < 0) { s->err = "n_steps < 0"; return DPSNN_EINVAL; }
   if (s->sticky) { s->err = "simulation is in a failed state"; return DPSNN_ESTATE; }
   try {
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    if (s->timing) {
-      HIPCHK(hipEventCreate(&ev[0]));
-      HIPCHK(hipEventCreate(&ev[1]));
-      HIPCHK(hipEventRecord(ev[0], s->stream));
-    }
+    // with timing on, every kernel launch of the step loop is bracketed by HIP events on
+    // the simulation's stream; class 0 = update (fused with delivery in the arrival form),
+    // class 1 = push delivery, class 2 = raster recording
+    std::vector<std::pair<int, size_t>> marks;  // (class, first event index)
+    size_t ev_used = 0;
+    auto mark = [&](int cls) -> hipEvent_t {
+      if (ev_used + 2 > s->events.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        s->events.push_back(e);
+        HIPCHK(hipEventCreate(&e));
+        s->events.push_back(e);
+      }
+      marks.push_back({cls, ev_used});
+      ev_used += 2;
+      return s->events[ev_used - 2];
+    };
     for (int64_t q = 0; q < n_steps; ++q) {
       const int64_t u = s->now;
-      HIPCHK(launch_step(*s, u, s->delivery, s->block));
-      if (s->ras_off && u < s->cfg.record_steps) HIPCHK(launch_raster(*s, u));
+      if (s->timing) {
+        HIPCHK(hipEventRecord(mark(0), s->stream));
+        HIPCHK(launch_step(*s, u, s->delivery, s->block, 0));
+        HIPCHK(hipEventRecord(s->events[marks.back().second + 1], s->stream));
+        if (s->delivery == DPSNN_DELIVERY_PUSH) {
+          HIPCHK(hipEventRecord(mark(1), s->stream));
+          HIPCHK(launch_step(*s, u, s->delivery, s->block, 1));
+          HIPCHK(hipEventRecord(s->events[marks.back().second + 1], s->stream));
+        }
+      } else {
+        HIPCHK(launch_step(*s, u, s->delivery, s->block, -1));
+      }
+      if (s->ras_off && u < s->cfg.record_steps) {
+        if (s->timing) HIPCHK(hipEventRecord(mark(2), s->stream));
+        HIPCHK(launch_raster(*s, u));
+        if (s->timing) HIPCHK(hipEventRecord(s->events[marks.back().second + 1], s->stream));
+      }
       s->now = u + 1;
     }
     if (s->timing) {
-      HIPCHK(hipEventRecord(ev[1], s->stream));
-      HIPCHK(hipEventSynchronize(ev[1]));
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, ev[0], ev[1]));
-      s->last_ms[0] = ms;
-      (void)hipEventDestroy(ev[0]);
-      (void)hipEventDestroy(ev[1]);
+      for (int c = 0; c < 6; ++c) s->last_ms[c] = 0.0;
+      if (!marks.empty()) HIPCHK(hipEventSynchronize(s->events[marks.back().second + 1]));
+      for (const auto& m : marks) {
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, s->events[m.second], s->events[m.second + 1]));
+        s->last_ms[m.first] += ms;
+        s->last_ms[3 + m.first] += 1.0;
+      }
     }
     return DPSNN_OK;
   } catch (const Fail& f) {
@@ -465,6 +493,7 @@ int sim_get_stats(sim_t* s, int32_t net, sim_stats_t* st) {
     st->spikes = (int64_t)c[0];
     st->events_recurrent = (int64_t)c[1];
     st->events_external = (int64_t)c[2];
+    st->synapses_streamed = (int64_t)c[3];
     return DPSNN_OK;
   } catch (const Fail& f) {
     return finish(s, f);
@@ -638,7 +667,7 @@ int sim_set_timing(sim_t* s, int32_t on) {
 
 int sim_get_timing(sim_t* s, double* ms, int32_t n) {
   if (!s || !ms) return DPSNN_EINVAL;
-  for (int q = 0; q < n && q < 3; ++q) ms[q] = s->last_ms[q];
+  for (int q = 0; q < n && q < 6; ++q) ms[q] = s->last_ms[q];
   return DPSNN_OK;
 }
 

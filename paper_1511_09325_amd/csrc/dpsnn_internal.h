@@ -106,7 +106,7 @@ struct StepArgs {
   int32_t* hist_cnt;
   uint16_t* hist_ids;
   int32_t* ring;              // push only
-  unsigned long long* net_cnt;  // [n_nets][4]: spikes, e_rec, e_ext, steps
+  unsigned long long* net_cnt;  // [n_nets][4]: spikes, e_rec, e_ext, synapses streamed
   // train-mode trajectory recording (null when off): [rec_steps][N]
   float* rec_vprev;
   float* rec_caprev;
@@ -181,7 +181,8 @@ struct sim {
   std::vector<dpsnn::Snapshot> snaps;
 
   bool timing = false;
-  double last_ms[3] = {0, 0, 0};
+  double last_ms[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<hipEvent_t> events;
 };
 
 namespace dpsnn {
@@ -192,7 +193,9 @@ hipError_t launch_gen_fill(const sim& s, int64_t row0, int64_t rows);
 hipError_t launch_scan_rows(const sim& s, const int32_t* row_len, int64_t n, int64_t* out,
                             int64_t* scratch, int64_t scratch_len);
 hipError_t launch_init_state(const sim& s);
-hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block);
+// part: -1 the whole step, 0 the update (fused with the gather in the arrival form),
+// 1 the push delivery
+hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block, int part);
 hipError_t launch_raster(sim& s, int64_t u);
 hipError_t launch_pend_view(const sim& s, int32_t* pend, int32_t g0, int32_t g1);
 hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1, int32_t* tgt,

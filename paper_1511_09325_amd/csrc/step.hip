@@ -221,6 +221,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_arrival(StepArgs a, int64_t u) {
     __syncthreads();
     const int32_t total = carry;
     // 2. chunks of BLOCK spike segments: locate, then stream their synapses into LDS
+    unsigned long long streamed = 0;
     for (int32_t base = 0; base < total; base += BLOCK) {
       const int32_t q = base + tid;
       int32_t len = 0;
@@ -244,6 +245,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_arrival(StepArgs a, int64_t u) {
       cs_start[tid] = start;
       cs_pref[tid] = ex;
       if (tid == 0) cs_pref[BLOCK] = tl;
+      streamed += (unsigned long long)tl;
       __syncthreads();
       for (int32_t f = tid; f < tl; f += BLOCK) {
         int lo = 0, hi = BLOCK;
@@ -259,6 +261,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_arrival(StepArgs a, int64_t u) {
       }
       __syncthreads();
     }
+    if (tid == 0 && streamed) atomicAdd(&a.net_cnt[4 * a.col_net[g] + 3], streamed);
     // 3. neuron update + compaction
     update_column<BLOCK>(a, g, u, ptab, [&](int k) { return acc[k]; }, wsum, red);
     __syncthreads();
@@ -304,6 +307,7 @@ __global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u) {
       __builtin_amdgcn_wave_barrier();
       const int32_t len = segrow[wave][nseg];
       const int64_t rb = a.row_base[i];
+      if (lane == 0 && len) atomicAdd(&a.net_cnt[4 * a.col_net[g] + 3], (unsigned long long)len);
       for (int32_t f = lane; f < len; f += 64) {
         int lo = 0, hi = nseg;  // last segment with start <= f
         while (hi - lo > 1) {
@@ -341,11 +345,12 @@ __global__ void k_init_state(StepArgs a) {
 }
 
 template <int BLOCK>
-hipError_t launch_step_t(sim& s, int64_t u, int32_t delivery) {
+hipError_t launch_step_t(sim& s, int64_t u, int32_t delivery, int part) {
   const StepArgs a = make_step_args(s);
   const bool train = s.wfx != nullptr;
   const int grid = s.n_cols;
   if (delivery == DPSNN_DELIVERY_ARRIVAL) {
+    if (part == 1) return hipSuccess;
     const size_t lds = sizeof(int32_t) * (size_t)s.npc;
     if (train)
       hipLaunchKernelGGL((k_step_arrival<BLOCK, true>), dim3(grid), dim3(BLOCK), lds, s.stream, a, u);
@@ -353,11 +358,13 @@ hipError_t launch_step_t(sim& s, int64_t u, int32_t delivery) {
       hipLaunchKernelGGL((k_step_arrival<BLOCK, false>), dim3(grid), dim3(BLOCK), lds, s.stream, a, u);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL((k_update_push<BLOCK>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
-  if (train)
-    hipLaunchKernelGGL((k_deliver_push<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
-  else
-    hipLaunchKernelGGL((k_deliver_push<BLOCK, false>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
+  if (part != 1) hipLaunchKernelGGL((k_update_push<BLOCK>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
+  if (part != 0) {
+    if (train)
+      hipLaunchKernelGGL((k_deliver_push<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
+    else
+      hipLaunchKernelGGL((k_deliver_push<BLOCK, false>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
+  }
   return hipGetLastError();
 }
 
@@ -393,13 +400,13 @@ StepArgs make_step_args(const sim& s) {
   return a;
 }
 
-hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block) {
+hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block, int part) {
   switch (block) {
-    case 64: return launch_step_t<64>(s, u, delivery);
-    case 128: return launch_step_t<128>(s, u, delivery);
-    case 256: return launch_step_t<256>(s, u, delivery);
-    case 512: return launch_step_t<512>(s, u, delivery);
-    case 1024: return launch_step_t<1024>(s, u, delivery);
+    case 64: return launch_step_t<64>(s, u, delivery, part);
+    case 128: return launch_step_t<128>(s, u, delivery, part);
+    case 256: return launch_step_t<256>(s, u, delivery, part);
+    case 512: return launch_step_t<512>(s, u, delivery, part);
+    case 1024: return launch_step_t<1024>(s, u, delivery, part);
     default: return hipErrorInvalidValue;
   }
 }

@@ -127,7 +127,7 @@ class Simulation:
         s = L.SimStats()
         L.check(self.lib.sim_get_stats(self.h, net, C.byref(s)), self.h)
         return {"steps": s.steps, "spikes": s.spikes, "e_rec": s.events_recurrent,
-                "e_ext": s.events_external}
+                "e_ext": s.events_external, "streamed": s.synapses_streamed}
 
     def state(self, net: int = 0, pend: bool = True) -> dict:
         n = self.net_neurons(net)
@@ -181,7 +181,9 @@ class Simulation:
     def set_timing(self, on: bool = True):
         L.check(self.lib.sim_set_timing(self.h, 1 if on else 0), self.h)
 
-    def timing(self):
-        ms = (C.c_double * 3)()
-        L.check(self.lib.sim_get_timing(self.h, ms, 3), self.h)
-        return list(ms)
+    def timing(self) -> dict:
+        """Per-kernel-class totals of the last step() call (timing must be on)."""
+        ms = (C.c_double * 6)()
+        L.check(self.lib.sim_get_timing(self.h, ms, 6), self.h)
+        names = ("update", "deliver", "raster")
+        return {names[c]: {"ms": ms[c], "launches": int(ms[3 + c])} for c in range(3)}
