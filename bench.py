@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--delivery", default="arrival", choices=["arrival", "push"])
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB once (a reference kernel of known "
+                         "traffic for hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -109,6 +112,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d MiB for counter calibration" % args.copy_calibration_mib)
+        del src, dst
     preset_name, default_steps = WORKLOADS[args.workload]
     preset = getattr(W, preset_name)
     p = preset["params"]

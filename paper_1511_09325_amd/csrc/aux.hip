@@ -4,8 +4,6 @@
 namespace dpsnn {
 namespace {
 
-constexpr int kMaxItems = kMaxDelay * kMaxNbr;
-
 // Raster: exclusive scan of this step's per-column spike counts (one workgroup), giving
 // each column its place in the ascending global id list of the step.
 __global__ __launch_bounds__(1024) void k_raster_scan(const int32_t* hist_cnt, int32_t n_cols,
@@ -53,15 +51,20 @@ __global__ __launch_bounds__(256) void k_raster_copy(const int32_t* hist_cnt,
   for (int32_t q = threadIdx.x; q < n; q += 256) ras_ids[base + q] = g * npc + ids[q];
 }
 
+__device__ __forceinline__ int rank_in_group(const GroupHdr& h, int32_t f) {
+  int r = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxNbr - 1; ++q) r += ((int32_t)h.end[q] <= f) ? 1 : 0;
+  return r;
+}
+
 // Pending-input view of the arrival strategy: pend[q][j] = sum over spikes of steps
 // t in [now - d_max, now) and synapses of delay d with t + d = now + q, restricted to the
 // target columns [g0, g1) of one network (j relative to column g0).
 template <bool TRAIN>
 __global__ __launch_bounds__(256) void k_pend_arrival(StepArgs a, int64_t now, int32_t* pend,
                                                       int32_t g0, int32_t g1) {
-  __shared__ uint16_t segrow[4][kMaxItems + 2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nseg = a.nd * kMaxNbr;
   const int64_t n_net = (int64_t)(g1 - g0) * a.npc;
   const int32_t g = g0 + blockIdx.x;  // source columns of the same network
   const int d_max = a.d_min + a.nd - 1;
@@ -73,27 +76,19 @@ __global__ __launch_bounds__(256) void k_pend_arrival(StepArgs a, int64_t now, i
     const uint16_t* ids = a.hist_ids + ((int64_t)slot * a.n_cols + g) * a.npc;
     for (int32_t q = wave; q < ns; q += 4) {
       const int64_t i = (int64_t)g * a.npc + ids[q];
-      const uint16_t* sg = a.seg + i * a.segw;
-      for (int e = lane; e <= nseg; e += 64) segrow[wave][e] = sg[e];
-      __builtin_amdgcn_wave_barrier();
-      const int32_t len = segrow[wave][nseg];
-      const int64_t rb = a.row_base[i];
-      for (int32_t f = lane; f < len; f += 64) {
-        int lo = 0, hi = nseg;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if ((int32_t)segrow[wave][mid] <= f) lo = mid;
-          else hi = mid;
-        }
-        const int dd = lo / kMaxNbr, r = lo - dd * kMaxNbr;
+      for (int dd = 0; dd < a.nd; ++dd) {
         const int64_t due = t + a.d_min + dd;
         if (due < now) continue;
-        const int32_t tc = a.col_nbr[g * kMaxNbr + r];
-        const uint32_t w = a.syn[rb + f];
-        const int32_t val = TRAIN ? a.wfx[rb + f] : (((int32_t)w) >> 16) * 4;
-        atomicAdd(&pend[(due - now) * n_net + (int64_t)(tc - g0) * a.npc + (w & 0xffffu)], val);
+        const GroupHdr h = a.hdr[i * a.nd + dd];
+        const int32_t len = h.end[kMaxNbr - 1];
+        for (int32_t f = lane; f < len; f += 64) {
+          const int r = rank_in_group(h, f);
+          const int32_t tc = a.col_nbr[g * kMaxNbr + r];
+          const uint32_t w = a.syn[h.start + f];
+          const int32_t val = TRAIN ? a.wfx[h.start + f] : (((int32_t)w) >> 16) * 4;
+          atomicAdd(&pend[(due - now) * n_net + (int64_t)(tc - g0) * a.npc + (w & 0xffffu)], val);
+        }
       }
-      __builtin_amdgcn_wave_barrier();
     }
   }
 }
@@ -103,26 +98,22 @@ __global__ __launch_bounds__(256) void k_export_rows(StepArgs a, int32_t g0, int
                                                      int64_t i1, const int64_t* out_off,
                                                      int32_t* tgt, uint8_t* dly, int16_t* wq) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nseg = a.nd * kMaxNbr;
   for (int64_t i = i0 + (int64_t)blockIdx.x * 4 + wave; i < i1; i += (int64_t)gridDim.x * 4) {
     const int32_t g = (int32_t)(i / a.npc);
-    const uint16_t* sg = a.seg + i * a.segw;
-    const int32_t len = sg[nseg];
     const int64_t rb = a.row_base[i];
     const int64_t ob = out_off[i - i0];
-    for (int32_t f = lane; f < len; f += 64) {
-      int lo = 0, hi = nseg;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if ((int32_t)sg[mid] <= f) lo = mid;
-        else hi = mid;
+    for (int dd = 0; dd < a.nd; ++dd) {
+      const GroupHdr h = a.hdr[i * a.nd + dd];
+      const int32_t len = h.end[kMaxNbr - 1];
+      for (int32_t f = lane; f < len; f += 64) {
+        const int r = rank_in_group(h, f);
+        const int32_t tc = a.col_nbr[g * kMaxNbr + r];
+        const int64_t e = h.start + f;
+        const uint32_t w = a.syn[e];
+        tgt[ob + (e - rb)] = (tc - g0) * a.npc + (int32_t)(w & 0xffffu);
+        dly[ob + (e - rb)] = (uint8_t)(a.d_min + dd);
+        wq[ob + (e - rb)] = (int16_t)(w >> 16);
       }
-      const int dd = lo / kMaxNbr, r = lo - dd * kMaxNbr;
-      const int32_t tc = a.col_nbr[g * kMaxNbr + r];
-      const uint32_t w = a.syn[rb + f];
-      tgt[ob + f] = (tc - g0) * a.npc + (int32_t)(w & 0xffffu);
-      dly[ob + f] = (uint8_t)(a.d_min + dd);
-      wq[ob + f] = (int16_t)(w >> 16);
     }
   }
 }

@@ -1,5 +1,6 @@
 // capi.hip -- host side of libdpsnn: the C ABI declared in include/dpsnn.h.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -112,6 +113,7 @@ void validate(const sim_config_t* c) {
   if (!(c->block == 0 || c->block == 64 || c->block == 128 || c->block == 256 ||
         c->block == 512 || c->block == 1024))
     bad("block must be 0, 64, 128, 256, 512 or 1024");
+  if (c->block && c->npc > 8 * c->block) bad("block must be at least npc / 8");
   if (c->record_steps < 0 || c->raster_capacity < 0) bad("raster sizes must be >= 0");
   if (c->train_mode && c->ckpt_every < 1) bad("ckpt_every must be >= 1 in train mode");
   int64_t cols = 0;
@@ -125,6 +127,14 @@ void validate(const sim_config_t* c) {
   }
   if (cols * c->npc >= ((int64_t)1 << 31)) bad("total neurons must be < 2^31");
   if (cols * (c->d_max + 1) * c->npc >= ((int64_t)1 << 31)) bad("spike history exceeds 2^31 entries");
+}
+
+// Default workgroup size of the step kernels: 256 threads, more for wide columns (each
+// thread holds at most 8 neurons of its column).
+int32_t default_block(int32_t npc) {
+  int32_t b = 256;
+  while (npc > 8 * b) b *= 2;
+  return b;
 }
 
 void set_constants(sim& s) {
@@ -186,6 +196,40 @@ void build_tables(sim& s) {
       if (rank[(size_t)g * kMaxNbr + r] < 0) throw Fail{DPSNN_EINVAL, "asymmetric neighbourhood"};
     }
   }
+  // Workgroup order.  Workgroups are dealt to the 8 XCDs (each with its own L2) in
+  // round-robin order of their index, and the 9 target columns around a source column
+  // all read that column's synapse groups; so columns are ordered such that workgroup b
+  // lands on XCD b % 8 together with its spatial neighbours: each network is cut into up
+  // to 8 vertical strips, strip s goes to XCD (s + rotation) % 8, and each strip is walked
+  // row by row.  Slots left over when strips differ in size are -1 (skipped).  This is a
+  // scheduling hint only: any order gives the same results.
+  {
+    std::vector<std::vector<int32_t>> lanes(8);
+    int rot = 0;
+    for (int n = 0; n < s.n_nets; ++n) {
+      const int rows = s.nets[n].rows, cols = s.nets[n].cols;
+      const int nstrip = std::min(8, cols);
+      for (int st = 0; st < nstrip; ++st) {
+        const int x0 = st * cols / nstrip, x1 = (st + 1) * cols / nstrip;
+        std::vector<int32_t>& L = lanes[(st + rot) % 8];
+        for (int y = 0; y < rows; ++y)
+          for (int x = x0; x < x1; ++x) L.push_back(s.net_col0[n] + y * cols + x);
+      }
+      rot = (rot + nstrip) % 8;
+    }
+    size_t longest = 0;
+    for (auto& L : lanes) longest = std::max(longest, L.size());
+    std::vector<int32_t> order;
+    for (size_t q = 0; q < longest; ++q)
+      for (int x = 0; x < 8; ++x) order.push_back(q < lanes[x].size() ? lanes[x][q] : -1);
+    std::vector<int32_t> rm((size_t)s.n_cols);
+    for (int32_t g = 0; g < s.n_cols; ++g) rm[g] = g;
+    s.grid_xcd = (int32_t)order.size();
+    s.col_order = upload(s, order);
+    s.col_order_rm = upload(s, rm);
+    const char* env = getenv("DPSNN_ROW_MAJOR");
+    s.xcd_order = !(env && env[0] == '1');
+  }
   std::vector<uint32_t> key(2 * (size_t)s.n_nets);
   std::vector<uint64_t> ptab((size_t)s.n_nets * kPoissonEntries);
   for (int n = 0; n < s.n_nets; ++n) {
@@ -217,11 +261,17 @@ void generate(sim& s) {
   HIPCHK(hipMemcpyAsync(&total, s.row_base + N, sizeof(int64_t), hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
   s.n_syn = total;
-  s.syn = (uint32_t*)dalloc(s, sizeof(uint32_t) * (size_t)std::max<int64_t>(total, 1));
+  // one spare uint4 after the last synapse: the delivery kernels may load whole 16-byte
+  // words that straddle the end of a segment
+  s.syn = (uint32_t*)dalloc(s, sizeof(uint32_t) * (size_t)(total + 4));
+  s.hdr = (GroupHdr*)dalloc(s, sizeof(GroupHdr) * (size_t)N * s.nd);
+  HIPCHK(hipMemsetAsync(s.syn + total, 0, 4 * sizeof(uint32_t), s.stream));
   HIPCHK(launch_gen_fill(s, 0, N));
   HIPCHK(hipStreamSynchronize(s.stream));
   dfree(s, part);
   dfree(s, row_len);
+  dfree(s, s.seg);
+  s.seg = nullptr;
   // per-network synapse offsets (host copy of the network boundaries of row_base)
   s.net_syn0.assign((size_t)s.n_nets + 1, 0);
   for (int n = 0; n <= s.n_nets; ++n) {
@@ -299,7 +349,7 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->dh = cfg->d_max + 1;
     s->segw = (s->nd * kMaxNbr + 1 + 1) & ~1;
     s->delivery = cfg->delivery == DPSNN_DELIVERY_PUSH ? DPSNN_DELIVERY_PUSH : DPSNN_DELIVERY_ARRIVAL;
-    s->block = cfg->block ? cfg->block : 256;
+    s->block = cfg->block ? cfg->block : default_block(cfg->npc);
     set_constants(*s);
     build_tables(*s);
     generate(*s);
@@ -650,6 +700,7 @@ int sim_set_launch(sim_t* s, int32_t delivery, int32_t block) {
       throw Fail{DPSNN_EINVAL, "block must be 64, 128, 256, 512 or 1024"};
     if (delivery != DPSNN_DELIVERY_ARRIVAL && delivery != DPSNN_DELIVERY_PUSH)
       throw Fail{DPSNN_EINVAL, "delivery must be ARRIVAL or PUSH"};
+    if (s->npc > 8 * block) throw Fail{DPSNN_EINVAL, "block must be at least npc / 8"};
     if (delivery == DPSNN_DELIVERY_PUSH && s->delivery != DPSNN_DELIVERY_PUSH) ring_from_history(*s);
     s->delivery = delivery;
     s->block = block;

@@ -3,25 +3,26 @@
 // Device data layout (all networks of a simulation concatenated column by column; the
 // global neuron index is g*npc + k for global column g and local index k):
 //
-//   synapse store, canonical order: per source neuron, sorted by (delay, target);
-//   within one delay the targets come column by column in ascending column order, so a
-//   row splits into segments (delay d, target-column rank r), r indexing the source
-//   column's sorted list of distinct neighbour columns (at most 9: the 3x3 torus stencil)
-//     row_base  int64 [N+1]        first synapse of each row
-//     seg       uint16[N][segw]    seg[i][(d-d_min)*9 + r] = start of segment (d, r)
-//                                  relative to row_base[i]; entry nd*9 = row length
-//     syn       uint32[S]          (k : low 16 bits) | (w_q : high 16 bits), the target's
-//                                  index inside its column and the int16 weight (2^-14 mV)
-//     wfx       int32 [S]          train mode only: rint(w_f32 * 2^16) efficacies
+//   synapse store, canonical order: per source neuron, sorted by (delay, target).  Within
+//   one delay the targets come column by column in ascending column order, so a row splits
+//   into groups (one per delay) and each group into segments (one per target column, r
+//   indexing the source column's sorted list of distinct neighbour columns -- at most 9,
+//   the 3x3 torus stencil)
+//     row_base  int64 [N+1]         first synapse of each row
+//     hdr       GroupHdr[N][nd]     group (i, delay): absolute start and the cumulative
+//                                   end of each target-column segment inside the group
+//     syn       uint32[S]           (k : low 16 bits) | (w_q : high 16 bits), the target's
+//                                   index inside its column and the int16 weight (2^-14 mV)
+//     wfx       int32 [S]           train mode only: rint(w_f32 * 2^16) efficacies
 //   column tables
-//     col_nbr   int32 [C][9]       distinct neighbour columns, ascending, -1 padded
-//     col_rank  int32 [C][9]       rank of column g in the list of its neighbour col_nbr[g][r]
-//     col_thr   uint64[C][9]       pair connection threshold from g to col_nbr[g][r]
+//     col_nbr   int32 [C][9]        distinct neighbour columns, ascending, -1 padded
+//     col_rank  int32 [C][9]        rank of column g in the list of its neighbour col_nbr[g][r]
+//     col_thr   uint64[C][9]        pair connection threshold from g to col_nbr[g][r]
 //   spike history (shared by both delivery strategies)
-//     hist_cnt  int32 [DH][C]      spikes of column g at step t, in slot t % DH
-//     hist_ids  uint16[DH][C][npc] their local indices, ascending
+//     hist_cnt  int32 [DH][C]       spikes of column g at step t, in slot t % DH
+//     hist_ids  uint16[DH][C][npc]  their local indices, ascending
 //   push-delivery ring (only with DPSNN_DELIVERY_PUSH)
-//     ring      int32 [DH][N]      input of step t in slot t % DH
+//     ring      int32 [DH][N]       input of step t in slot t % DH
 //
 // DH = d_max + 1 slots: a step reads slots of steps t-d_max .. t-1 and writes slot t.
 #pragma once
@@ -70,6 +71,15 @@ __device__ __forceinline__ Rand4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   return Rand4{c0, c1, c2, c3};
 }
 
+// Header of the synapse group of one (source neuron, delay): segment r (target column
+// col_nbr[source column][r]) is [start + (r ? end[r-1] : 0), start + end[r]).
+struct GroupHdr {
+  int64_t start;
+  uint16_t end[kMaxNbr];
+  uint16_t pad[3];
+};
+static_assert(sizeof(GroupHdr) == 32, "GroupHdr must be 32 bytes");
+
 // Neuron constants, rounded once from double on the host.
 struct NeuronK {
   float pm;      // exp(-dt / tau_m)
@@ -85,18 +95,20 @@ struct NeuronK {
 // Everything the step kernels read or write, by value.
 struct StepArgs {
   // sizes
-  int32_t npc, nd, d_min, dh, segw, n_cols;
+  int32_t npc, nd, d_min, dh, n_cols;
   // column / network tables
   const int32_t* col_net;
   const int32_t* col_local;   // column index within its network
   const int32_t* col_nbr;
   const int32_t* col_nn;
   const int32_t* col_rank;
+  const int32_t* col_order;   // [grid]: column processed by workgroup b (-1: none)
+  int32_t grid;               // workgroups of the per-column kernels
   const uint32_t* net_key;    // [n_nets][2]
   const uint64_t* net_ptab;   // [n_nets][63]
   // synapses
   const int64_t* row_base;
-  const uint16_t* seg;
+  const GroupHdr* hdr;
   const uint32_t* syn;
   const int32_t* wfx;         // train mode, else null
   // state
@@ -150,11 +162,16 @@ struct sim {
   size_t device_bytes = 0;
   int32_t *col_net = nullptr, *col_local = nullptr, *col_nbr = nullptr, *col_nn = nullptr,
           *col_rank = nullptr;
+  int32_t* col_order = nullptr;    // workgroup -> column (XCD-aware order)
+  int32_t* col_order_rm = nullptr; // workgroup -> column (row-major order)
+  int32_t grid_xcd = 0;
+  bool xcd_order = true;
   uint64_t* col_thr = nullptr;
   uint32_t* net_key = nullptr;
   uint64_t* net_ptab = nullptr;
   int64_t* row_base = nullptr;
-  uint16_t* seg = nullptr;
+  uint16_t* seg = nullptr;         // construction only: relative segment starts [N][segw]
+  dpsnn::GroupHdr* hdr = nullptr;
   uint32_t* syn = nullptr;
   int32_t* wfx = nullptr;
   float* wf32 = nullptr;

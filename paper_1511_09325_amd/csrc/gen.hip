@@ -32,6 +32,7 @@ struct GenArgs {
   uint16_t* seg;           // count pass output
   const int64_t* row_base; // fill pass input
   uint32_t* syn;           // fill pass output
+  GroupHdr* hdr;           // fill pass output
 };
 
 constexpr int kGenWaves = 4;  // rows per workgroup (one wave each)
@@ -133,7 +134,18 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
     const double mu = exc ? a.we_mu : a.wi_mu;
     const double sigma = exc ? a.we_sigma : a.wi_sigma;
     const uint16_t* sg = a.seg + i * a.segw;
-    uint32_t* out = a.syn + a.row_base[i];
+    const int64_t rb = a.row_base[i];
+    uint32_t* out = a.syn + rb;
+    // group headers: lane dd describes the group of delay d_min + dd
+    if (lane < a.nd) {
+      GroupHdr h;
+      const int32_t g0 = sg[lane * kMaxNbr];
+      h.start = rb + g0;
+#pragma unroll
+      for (int r = 0; r < kMaxNbr; ++r) h.end[r] = (uint16_t)(sg[lane * kMaxNbr + r + 1] - g0);
+      h.pad[0] = h.pad[1] = h.pad[2] = 0;
+      a.hdr[i * a.nd + lane] = h;
+    }
     for (int r = 0; r < nn; ++r) {
       const int32_t tc = a.col_nbr[g * kMaxNbr + r];
       const uint64_t thr = a.col_thr[g * kMaxNbr + r];
@@ -192,6 +204,7 @@ GenArgs gen_args(const sim& s, int64_t row0, int64_t rows) {
   a.seg = s.seg;
   a.row_base = s.row_base;
   a.syn = s.syn;
+  a.hdr = s.hdr;
   return a;
 }
 

@@ -82,34 +82,77 @@ __device__ __forceinline__ int32_t poisson_count(const uint64_t* tab, uint32_t x
   return lo;
 }
 
-// The neuron update and spike compaction of one column, shared by both strategies.
-// in_of(k) returns the recurrent int32 input of local neuron k at step u.
-template <int BLOCK, typename InputFn>
-__device__ __forceinline__ void update_column(const StepArgs& a, int32_t g, int64_t u,
-                                              const uint64_t* ptab, InputFn in_of, int32_t* wcnt,
-                                              unsigned long long* red) {
+// ---- the neuron update, shared by both strategies ------------------------------------------
+//
+// Each thread owns the neurons k = m * BLOCK + tid (m < NPT) of the column.  Their state
+// and external Poisson counts are fetched into registers first (prefetch_neurons), so that
+// the loads and the Philox draws overlap with the gather of the delivered input; then
+// finish_update applies the step and compacts the spikes in ascending order with one
+// workgroup barrier (wave ballots, counts per (m, wave) in LDS).
+template <int NPT>
+struct NeuronRegs {
+  float v[NPT];
+  float ca[NPT];
+  int32_t ref[NPT];
+  int32_t next[NPT];
+};
+
+template <int BLOCK, int NPT>
+__device__ __forceinline__ void prefetch_neurons(const StepArgs& a, int32_t g, int64_t u,
+                                                 const uint64_t* ptab, NeuronRegs<NPT>& r) {
+  const int32_t net = a.col_net[g];
+  const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
+  const uint32_t nl0 = (uint32_t)(a.col_local[g] * a.npc);
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int k = m * BLOCK + (int)threadIdx.x;
+    r.v[m] = 0.0f;
+    r.ca[m] = 0.0f;
+    r.ref[m] = 0;
+    r.next[m] = 0;
+    if (k < a.npc) {
+      const int64_t j = (int64_t)g * a.npc + k;
+      r.v[m] = a.v[j];
+      r.ca[m] = a.ca[j];
+      r.ref[m] = a.ref[j];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int k = m * BLOCK + (int)threadIdx.x;
+    if (k < a.npc) {
+      const Rand4 x = philox10(nl0 + (uint32_t)k, (uint32_t)u, 0u, kStreamExt, key0, key1);
+      r.next[m] = poisson_count(ptab, x.x);
+    }
+  }
+}
+
+// in_of(k) returns the recurrent int32 input of local neuron k at step u.  extra is added
+// to the synapse counter of the network (the gather's streamed synapses).
+template <int BLOCK, int NPT, typename InputFn>
+__device__ __forceinline__ void finish_update(const StepArgs& a, int32_t g, int64_t u,
+                                              NeuronRegs<NPT>& r, InputFn in_of, int32_t* wcnt,
+                                              unsigned long long* red,
+                                              unsigned long long extra) {
   constexpr int NW = BLOCK / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const unsigned long long lt = lanemask_lt(lane);
   const int32_t net = a.col_net[g];
-  const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
-  const uint32_t nl0 = (uint32_t)(a.col_local[g] * a.npc);
   const int32_t slot = (int32_t)(u % a.dh);
   uint16_t* out_ids = a.hist_ids + ((int64_t)slot * a.n_cols + g) * a.npc;
-  int32_t running = 0;
   unsigned long long my_ext = 0, my_rec = 0;
-  for (int k0 = 0; k0 < a.npc; k0 += BLOCK) {
-    const int k = k0 + (int)threadIdx.x;
-    bool spike = false;
+  bool sp[NPT];
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int k = m * BLOCK + (int)threadIdx.x;
+    sp[m] = false;
     if (k < a.npc) {
       const int64_t j = (int64_t)g * a.npc + k;
-      const Rand4 r = philox10(nl0 + (uint32_t)k, (uint32_t)u, 0u, kStreamExt, key0, key1);
-      const int32_t n_ext = poisson_count(ptab, r.x);
-      const uint32_t asum = (uint32_t)in_of(k) + (uint32_t)n_ext * (uint32_t)a.k.jfx;
+      const uint32_t asum = (uint32_t)in_of(k) + (uint32_t)r.next[m] * (uint32_t)a.k.jfx;
       const float cur = (float)(int32_t)asum * 0x1p-16f;
-      const float vprev = a.v[j];
-      const float caprev = a.ca[j];
-      int32_t rf = a.ref[j];
+      const float vprev = r.v[m];
+      const float caprev = r.ca[m];
+      int32_t rf = r.ref[m];
       float vnew, vt = 0.0f;
       bool refr = false;
       if (rf > 0) {
@@ -122,7 +165,7 @@ __device__ __forceinline__ void update_column(const StepArgs& a, int32_t g, int6
         const float drop = leak - ahp;
         vt = drop + cur;
         if (vt >= a.k.theta) {
-          spike = true;
+          sp[m] = true;
           vnew = a.k.vreset;
           rf = a.k.tref;
         } else {
@@ -130,41 +173,50 @@ __device__ __forceinline__ void update_column(const StepArgs& a, int32_t g, int6
         }
       }
       const float decayed = a.k.pc * caprev;
-      const float canew = decayed + (spike ? a.k.alpha : 0.0f);
+      const float canew = decayed + (sp[m] ? a.k.alpha : 0.0f);
       a.v[j] = vnew;
       a.ca[j] = canew;
       a.ref[j] = (uint8_t)rf;
-      my_ext += (unsigned long long)n_ext;
-      if (spike) my_rec += (unsigned long long)(a.row_base[j + 1] - a.row_base[j]);
+      my_ext += (unsigned long long)r.next[m];
+      if (sp[m]) my_rec += (unsigned long long)(a.row_base[j + 1] - a.row_base[j]);
       if (a.rec_vprev) {
         const int64_t o = (u - a.rec_base) * (int64_t)a.n_cols * a.npc + j;
         a.rec_vprev[o] = vprev;
         a.rec_caprev[o] = caprev;
         a.rec_vt[o] = vt;
-        a.rec_flags[o] = (uint8_t)((spike ? 1 : 0) | (refr ? 2 : 0));
+        a.rec_flags[o] = (uint8_t)((sp[m] ? 1 : 0) | (refr ? 2 : 0));
       }
     }
-    const unsigned long long m = __ballot(spike);
-    if (lane == 0) wcnt[wave] = __popcll(m);
-    __syncthreads();
+  }
+  unsigned long long bal[NPT];
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    bal[m] = __ballot(sp[m]);
+    if (lane == 0) wcnt[m * NW + wave] = __popcll(bal[m]);
+  }
+  __syncthreads();
+  int32_t running = 0;
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
     int32_t before = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-      const int32_t c = wcnt[w];
+      const int32_t c = wcnt[m * NW + w];
       if (w < wave) before += c;
       tot += c;
     }
-    if (spike) out_ids[running + before + __popcll(m & lt)] = (uint16_t)k;
+    if (sp[m]) out_ids[running + before + __popcll(bal[m] & lt)] = (uint16_t)(m * BLOCK + threadIdx.x);
     running += tot;
-    __syncthreads();
   }
   const unsigned long long ext_all = block_sum_u64<BLOCK>(my_ext, red);
   const unsigned long long rec_all = block_sum_u64<BLOCK>(my_rec, red);
+  const unsigned long long str_all = block_sum_u64<BLOCK>(extra, red);
   if (threadIdx.x == 0) {
     a.hist_cnt[(int64_t)slot * a.n_cols + g] = running;
     atomicAdd(&a.net_cnt[4 * net + 0], (unsigned long long)running);
     atomicAdd(&a.net_cnt[4 * net + 1], rec_all);
     atomicAdd(&a.net_cnt[4 * net + 2], ext_all);
+    if (str_all) atomicAdd(&a.net_cnt[4 * net + 3], str_all);
   }
 }
 
@@ -176,40 +228,67 @@ __device__ __forceinline__ void load_ptab(const StepArgs& a, int32_t g, uint64_t
 }
 
 // ---- ARRIVAL: gather + update, one workgroup per target column ------------------------
-template <int BLOCK, bool TRAIN>
+//
+// Work list of column g at step u: "items" (source column r, delay index dd), each the
+// spike list of source column col_nbr[g][r] at step u - d_min - dd; every spike i of an
+// item contributes one segment: the synapses of group (i, dd) that target column g.  Items
+// of the own column come first (long segments), then the 8 neighbours (short ones), so
+// that neighbouring segments have similar lengths.  Each wave takes batches of 64
+// consecutive segments: lane l locates segment l of the batch (binary search over the item
+// prefix, one spike id, one 32-byte group header) and then walks it in 16-byte pieces
+// (four synapses per load, kPiecesInFlight loads in flight), adding each synapse's
+// efficacy into the column's LDS accumulator with integer atomics.
+constexpr int kPiecesInFlight = 4;
+
+template <bool TRAIN>
+__device__ __forceinline__ void add_piece(const StepArgs& a, int32_t* acc, const uint32_t* w,
+                                          const int32_t* v, int32_t valid) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (e < valid) atomicAdd(&acc[w[e] & 0xffffu], TRAIN ? v[e] : (((int32_t)w[e]) >> 16) * 4);
+}
+
+template <int BLOCK, int NPT, bool TRAIN>
 __global__ __launch_bounds__(BLOCK) void k_step_arrival(StepArgs a, int64_t u) {
+  constexpr int NW = BLOCK / 64;
   extern __shared__ int32_t acc[];
   __shared__ uint64_t ptab[kPoissonEntries];
   __shared__ int32_t it_pref[kMaxItems + 1];
   __shared__ int32_t it_hist[kMaxItems];
   __shared__ int32_t it_nbase[kMaxItems];
-  __shared__ int32_t it_segc[kMaxItems];
-  __shared__ int64_t cs_start[BLOCK];
-  __shared__ int32_t cs_pref[BLOCK + 1];
-  __shared__ int32_t wsum[BLOCK / 64];
-  __shared__ unsigned long long red[BLOCK / 64];
+  __shared__ int32_t it_hdr[kMaxItems];
+  __shared__ int32_t it_rank[kMaxItems];
+  __shared__ int32_t wsum[NPT * NW];
+  __shared__ unsigned long long red[NW];
   const int tid = threadIdx.x;
-  const int n_items = a.nd * kMaxNbr;
-  for (int32_t g = blockIdx.x; g < a.n_cols; g += gridDim.x) {
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int32_t b = blockIdx.x; b < a.grid; b += gridDim.x) {
+    const int32_t g = a.col_order[b];
+    if (g < 0) continue;
     load_ptab<BLOCK>(a, g, ptab);
     for (int k = tid; k < a.npc; k += BLOCK) acc[k] = 0;
-    // 1. spike lists to gather: item (delay index dd, source rank r)
     const int nn = a.col_nn[g];
+    int own = 0;  // rank of the own column in g's ascending neighbour list
+    for (int r = 0; r < nn; ++r)
+      if (a.col_nbr[g * kMaxNbr + r] == g) own = r;
+    const int n_items = nn * a.nd;
+    // 1. items and their spike counts; item = ro * nd + dd, ro = 0 the own column
     int32_t carry = 0;
     for (int b = 0; b < n_items; b += BLOCK) {
       const int it = b + tid;
       int32_t cnt = 0;
       if (it < n_items) {
-        const int dd = it / kMaxNbr, r = it - dd * kMaxNbr;
+        const int ro = it / a.nd, dd = it - ro * a.nd;
+        const int r = ro == 0 ? own : (ro <= own ? ro - 1 : ro);
         const int64_t t = u - (a.d_min + dd);
-        if (r < nn && t >= 0) {
-          const int32_t s = a.col_nbr[g * kMaxNbr + r];
-          const int32_t rank = a.col_rank[g * kMaxNbr + r];
-          const int32_t hb = (int32_t)(t % a.dh) * a.n_cols + s;
+        if (t >= 0) {
+          const int32_t sc = a.col_nbr[g * kMaxNbr + r];
+          const int32_t hb = (int32_t)(t % a.dh) * a.n_cols + sc;
           cnt = a.hist_cnt[hb];
           it_hist[it] = hb * a.npc;
-          it_nbase[it] = s * a.npc;
-          it_segc[it] = dd * kMaxNbr + rank;
+          it_nbase[it] = sc * a.npc;
+          it_hdr[it] = dd;
+          it_rank[it] = a.col_rank[g * kMaxNbr + r];
         }
       }
       int32_t tot;
@@ -218,14 +297,16 @@ __global__ __launch_bounds__(BLOCK) void k_step_arrival(StepArgs a, int64_t u) {
       carry += tot;
     }
     if (tid == 0) it_pref[n_items] = carry;
-    __syncthreads();
+    __syncthreads();  // items, the Poisson table and the zeroed accumulator are ready
+    NeuronRegs<NPT> nr;
+    prefetch_neurons<BLOCK, NPT>(a, g, u, ptab, nr);
     const int32_t total = carry;
-    // 2. chunks of BLOCK spike segments: locate, then stream their synapses into LDS
     unsigned long long streamed = 0;
-    for (int32_t base = 0; base < total; base += BLOCK) {
-      const int32_t q = base + tid;
-      int32_t len = 0;
-      int64_t start = 0;
+    // 2. gather: waves take batches of 64 segments
+    for (int32_t b0 = wave * 64; b0 < total; b0 += NW * 64) {
+      const int32_t q = b0 + lane;
+      int64_t st = 0;
+      int32_t ln = 0;
       if (q < total) {
         int lo = 0, hi = n_items;
         while (hi - lo > 1) {
@@ -235,66 +316,82 @@ __global__ __launch_bounds__(BLOCK) void k_step_arrival(StepArgs a, int64_t u) {
         }
         const int32_t ksrc = a.hist_ids[it_hist[lo] + (q - it_pref[lo])];
         const int64_t i = (int64_t)it_nbase[lo] + ksrc;
-        const uint16_t* sg = a.seg + i * a.segw + it_segc[lo];
-        const int32_t o = sg[0], e = sg[1];
-        start = a.row_base[i] + o;
-        len = e - o;
+        const GroupHdr* h = a.hdr + i * a.nd + it_hdr[lo];
+        const int r = it_rank[lo];
+        const int32_t e1 = h->end[r];
+        const int32_t e0 = r ? (int32_t)h->end[r - 1] : 0;
+        st = h->start + e0;
+        ln = e1 - e0;
       }
-      int32_t tl;
-      const int32_t ex = block_excl_scan<BLOCK>(len, &tl, wsum);
-      cs_start[tid] = start;
-      cs_pref[tid] = ex;
-      if (tid == 0) cs_pref[BLOCK] = tl;
-      streamed += (unsigned long long)tl;
-      __syncthreads();
-      for (int32_t f = tid; f < tl; f += BLOCK) {
-        int lo = 0, hi = BLOCK;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (cs_pref[mid] <= f) lo = mid;
-          else hi = mid;
+      streamed += (unsigned long long)ln;
+      for (int32_t off = 0; __ballot(off < ln) != 0; off += 4 * kPiecesInFlight) {
+        uint32_t w[kPiecesInFlight][4];
+        int32_t v[kPiecesInFlight][4];
+#pragma unroll
+        for (int p = 0; p < kPiecesInFlight; ++p) {
+          const int32_t o = off + 4 * p;
+          if (o < ln) {
+            __builtin_memcpy(&w[p][0], a.syn + st + o, 16);
+            if (TRAIN) __builtin_memcpy(&v[p][0], a.wfx + st + o, 16);
+          }
         }
-        const int64_t addr = cs_start[lo] + (f - cs_pref[lo]);
-        const uint32_t w = a.syn[addr];
-        const int32_t val = TRAIN ? a.wfx[addr] : (((int32_t)w) >> 16) * 4;
-        atomicAdd(&acc[w & 0xffffu], val);
+#pragma unroll
+        for (int p = 0; p < kPiecesInFlight; ++p) {
+          const int32_t o = off + 4 * p;
+          if (o < ln) add_piece<TRAIN>(a, acc, w[p], v[p], ln - o);
+        }
       }
-      __syncthreads();
     }
-    if (tid == 0 && streamed) atomicAdd(&a.net_cnt[4 * a.col_net[g] + 3], streamed);
+    __syncthreads();  // all arrivals accumulated
     // 3. neuron update + compaction
-    update_column<BLOCK>(a, g, u, ptab, [&](int k) { return acc[k]; }, wsum, red);
+    finish_update<BLOCK, NPT>(a, g, u, nr, [&](int k) { return acc[k]; }, wsum, red, streamed);
     __syncthreads();
   }
 }
 
 // ---- PUSH: update from the ring, then scatter ----------------------------------------------
-template <int BLOCK>
+template <int BLOCK, int NPT>
 __global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u) {
+  constexpr int NW = BLOCK / 64;
   __shared__ uint64_t ptab[kPoissonEntries];
-  __shared__ int32_t wsum[BLOCK / 64];
-  __shared__ unsigned long long red[BLOCK / 64];
+  __shared__ int32_t wsum[NPT * NW];
+  __shared__ unsigned long long red[NW];
   const int64_t nall = (int64_t)a.n_cols * a.npc;
   int32_t* slot = a.ring + (u % a.dh) * nall;
-  for (int32_t g = blockIdx.x; g < a.n_cols; g += gridDim.x) {
+  for (int32_t b = blockIdx.x; b < a.grid; b += gridDim.x) {
+    const int32_t g = a.col_order[b];
+    if (g < 0) continue;
     load_ptab<BLOCK>(a, g, ptab);
     __syncthreads();
+    NeuronRegs<NPT> nr;
+    prefetch_neurons<BLOCK, NPT>(a, g, u, ptab, nr);
     int32_t* in = slot + (int64_t)g * a.npc;
-    update_column<BLOCK>(a, g, u, ptab, [&](int k) {
+    finish_update<BLOCK, NPT>(a, g, u, nr, [&](int k) {
       const int32_t x = in[k];
       in[k] = 0;
       return x;
-    }, wsum, red);
+    }, wsum, red, 0ull);
     __syncthreads();
   }
+}
+
+__device__ __forceinline__ int32_t syn_value(const StepArgs& a, uint32_t w, int64_t addr,
+                                             bool train) {
+  return train ? a.wfx[addr] : (((int32_t)w) >> 16) * 4;
+}
+
+// Segment (target-column rank) of position f inside a group.
+__device__ __forceinline__ int rank_in_group(const GroupHdr& h, int32_t f) {
+  int r = 0;
+#pragma unroll
+  for (int q = 0; q < kMaxNbr - 1; ++q) r += ((int32_t)h.end[q] <= f) ? 1 : 0;
+  return r;
 }
 
 template <int BLOCK, bool TRAIN>
 __global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u) {
   constexpr int NW = BLOCK / 64;
-  __shared__ uint16_t segrow[NW][kMaxItems + 2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nseg = a.nd * kMaxNbr;
   const int64_t nall = (int64_t)a.n_cols * a.npc;
   const int32_t uslot = (int32_t)(u % a.dh);
   for (int32_t g = blockIdx.x; g < a.n_cols; g += gridDim.x) {
@@ -302,27 +399,21 @@ __global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u) {
     const uint16_t* ids = a.hist_ids + ((int64_t)uslot * a.n_cols + g) * a.npc;
     for (int32_t q = wave; q < ns; q += NW) {
       const int64_t i = (int64_t)g * a.npc + ids[q];
-      const uint16_t* sg = a.seg + i * a.segw;
-      for (int e = lane; e <= nseg; e += 64) segrow[wave][e] = sg[e];
-      __builtin_amdgcn_wave_barrier();
-      const int32_t len = segrow[wave][nseg];
-      const int64_t rb = a.row_base[i];
-      if (lane == 0 && len) atomicAdd(&a.net_cnt[4 * a.col_net[g] + 3], (unsigned long long)len);
-      for (int32_t f = lane; f < len; f += 64) {
-        int lo = 0, hi = nseg;  // last segment with start <= f
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if ((int32_t)segrow[wave][mid] <= f) lo = mid;
-          else hi = mid;
-        }
-        const int dd = lo / kMaxNbr, r = lo - dd * kMaxNbr;
-        const int32_t tc = a.col_nbr[g * kMaxNbr + r];
-        const uint32_t w = a.syn[rb + f];
-        const int32_t val = TRAIN ? a.wfx[rb + f] : (((int32_t)w) >> 16) * 4;
+      unsigned long long pushed = 0;
+      for (int dd = 0; dd < a.nd; ++dd) {
+        const GroupHdr h = a.hdr[i * a.nd + dd];
+        const int32_t len = h.end[kMaxNbr - 1];
         const int64_t slot = (u + a.d_min + dd) % a.dh;
-        atomicAdd(&a.ring[slot * nall + (int64_t)tc * a.npc + (w & 0xffffu)], val);
+        pushed += (unsigned long long)len;
+        for (int32_t f = lane; f < len; f += 64) {
+          const int r = rank_in_group(h, f);
+          const int32_t tc = a.col_nbr[g * kMaxNbr + r];
+          const uint32_t w = a.syn[h.start + f];
+          atomicAdd(&a.ring[slot * nall + (int64_t)tc * a.npc + (w & 0xffffu)],
+                    syn_value(a, w, h.start + f, TRAIN));
+        }
       }
-      __builtin_amdgcn_wave_barrier();
+      if (lane == 0 && pushed) atomicAdd(&a.net_cnt[4 * a.col_net[g] + 3], pushed);
     }
   }
 }
@@ -344,21 +435,21 @@ __global__ void k_init_state(StepArgs a) {
   }
 }
 
-template <int BLOCK>
+template <int BLOCK, int NPT>
 hipError_t launch_step_t(sim& s, int64_t u, int32_t delivery, int part) {
   const StepArgs a = make_step_args(s);
   const bool train = s.wfx != nullptr;
-  const int grid = s.n_cols;
+  const int grid = a.grid;
   if (delivery == DPSNN_DELIVERY_ARRIVAL) {
     if (part == 1) return hipSuccess;
     const size_t lds = sizeof(int32_t) * (size_t)s.npc;
     if (train)
-      hipLaunchKernelGGL((k_step_arrival<BLOCK, true>), dim3(grid), dim3(BLOCK), lds, s.stream, a, u);
+      hipLaunchKernelGGL((k_step_arrival<BLOCK, NPT, true>), dim3(grid), dim3(BLOCK), lds, s.stream, a, u);
     else
-      hipLaunchKernelGGL((k_step_arrival<BLOCK, false>), dim3(grid), dim3(BLOCK), lds, s.stream, a, u);
+      hipLaunchKernelGGL((k_step_arrival<BLOCK, NPT, false>), dim3(grid), dim3(BLOCK), lds, s.stream, a, u);
     return hipGetLastError();
   }
-  if (part != 1) hipLaunchKernelGGL((k_update_push<BLOCK>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
+  if (part != 1) hipLaunchKernelGGL((k_update_push<BLOCK, NPT>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
   if (part != 0) {
     if (train)
       hipLaunchKernelGGL((k_deliver_push<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
@@ -366,6 +457,16 @@ hipError_t launch_step_t(sim& s, int64_t u, int32_t delivery, int part) {
       hipLaunchKernelGGL((k_deliver_push<BLOCK, false>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
   }
   return hipGetLastError();
+}
+
+template <int BLOCK>
+hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
+  const int npt = (s.npc + BLOCK - 1) / BLOCK;
+  if (npt <= 1) return launch_step_t<BLOCK, 1>(s, u, delivery, part);
+  if (npt <= 2) return launch_step_t<BLOCK, 2>(s, u, delivery, part);
+  if (npt <= 4) return launch_step_t<BLOCK, 4>(s, u, delivery, part);
+  if (npt <= 8) return launch_step_t<BLOCK, 8>(s, u, delivery, part);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -376,17 +477,18 @@ StepArgs make_step_args(const sim& s) {
   a.nd = s.nd;
   a.d_min = s.cfg.d_min;
   a.dh = s.dh;
-  a.segw = s.segw;
   a.n_cols = s.n_cols;
   a.col_net = s.col_net;
   a.col_local = s.col_local;
   a.col_nbr = s.col_nbr;
   a.col_nn = s.col_nn;
   a.col_rank = s.col_rank;
+  a.col_order = s.xcd_order ? s.col_order : s.col_order_rm;
+  a.grid = s.xcd_order ? s.grid_xcd : s.n_cols;
   a.net_key = s.net_key;
   a.net_ptab = s.net_ptab;
   a.row_base = s.row_base;
-  a.seg = s.seg;
+  a.hdr = s.hdr;
   a.syn = s.syn;
   a.wfx = s.wfx;
   a.v = s.v;
@@ -402,11 +504,11 @@ StepArgs make_step_args(const sim& s) {
 
 hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block, int part) {
   switch (block) {
-    case 64: return launch_step_t<64>(s, u, delivery, part);
-    case 128: return launch_step_t<128>(s, u, delivery, part);
-    case 256: return launch_step_t<256>(s, u, delivery, part);
-    case 512: return launch_step_t<512>(s, u, delivery, part);
-    case 1024: return launch_step_t<1024>(s, u, delivery, part);
+    case 64: return launch_step_b<64>(s, u, delivery, part);
+    case 128: return launch_step_b<128>(s, u, delivery, part);
+    case 256: return launch_step_b<256>(s, u, delivery, part);
+    case 512: return launch_step_b<512>(s, u, delivery, part);
+    case 1024: return launch_step_b<1024>(s, u, delivery, part);
     default: return hipErrorInvalidValue;
   }
 }
