@@ -93,7 +93,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="96x96", choices=sorted(WORKLOADS))
     ap.add_argument("--delivery", default="arrival", choices=["arrival", "push"])
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--block", type=int, default=0, help="workgroup size (0: library default)")
+    ap.add_argument("--tile", default="auto", help="arrival tile of target columns, e.g. 4x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB once (a reference kernel of known "
@@ -129,7 +130,9 @@ def main():
 
     log("generating %s on the GPU" % preset["name"])
     t0 = time.perf_counter()
-    sim = Simulation(p, delivery=delivery, block=args.block)
+    tile = (0, 0) if args.tile == "auto" else tuple(int(x) for x in args.tile.split("x"))
+    sim = Simulation(p, delivery=delivery, block=args.block, tile=tile)
+    launch = sim.get_launch()
     sim.sync()
     t_gen = time.perf_counter() - t0
     log("generated %d neurons, %d synapses in %.1f s (%.1f GB on device)"
@@ -157,6 +160,7 @@ def main():
     e_ext = s1["e_ext"] - s0["e_ext"]
     spikes = s1["spikes"] - s0["spikes"]
     streamed = s1["streamed"] - s0["streamed"]
+    delivered = s1["delivered"] - s0["delivered"]
     secs = wall_ms / 1e3
     value = (e_rec + e_ext) / secs
 
@@ -169,8 +173,8 @@ def main():
         bytes_per_launch = BYTES_PER_SYNAPSE * streamed / K
         dom_name = "k_deliver_push"
     else:
-        bytes_per_launch = (BYTES_PER_SYNAPSE * streamed + BYTES_PER_NEURON * sim.n_neurons * K) / K
-        dom_name = "k_step_arrival"
+        bytes_per_launch = (BYTES_PER_SYNAPSE * delivered + BYTES_PER_NEURON * sim.n_neurons * K) / K
+        dom_name = "k_step_tile"
     achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, args.delivery)
 
@@ -189,7 +193,8 @@ def main():
         "data": "synthetic (seeded network and Poisson input of the column recipe)",
         "config": {"workload": preset["name"], "grid": args.workload, "neurons": sim.n_neurons,
                    "synapses": sim.n_synapses, "dt_ms": p["dt"], "delivery": args.delivery,
-                   "block": args.block, "parallelism": "single GPU"},
+                   "block": launch["block"], "tile": "%dx%d" % launch["tile"],
+                   "parallelism": "single GPU"},
         "sim_ms_per_wall_s": K * p["dt"] / secs,
         "recurrent_events_per_s": e_rec / secs,
         "external_events_per_s": e_ext / secs,
@@ -198,7 +203,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_ms": dom_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "synapse_records_read_per_launch": streamed / K},
     }
     del sim
     torch.cuda.empty_cache()

@@ -81,6 +81,7 @@ typedef struct {
   /* options */
   int32_t delivery;      /* DPSNN_DELIVERY_* */
   int32_t block;         /* threads per workgroup of the step kernels: 0 (auto), 64..1024 */
+  int32_t tile_x, tile_y; /* arrival form: target columns per workgroup, 1..4 each; 0 0 = auto */
   int64_t record_steps;  /* spike raster: number of steps recorded from step 0 (0 = off) */
   int64_t raster_capacity; /* spike raster: capacity in spike ids */
   int32_t train_mode;    /* 1: float32 master weights, trajectory recording, sim_backward */
@@ -104,6 +105,7 @@ typedef struct {
   int64_t events_recurrent; /* outgoing synapses of every emitted spike */
   int64_t events_external;  /* external Poisson arrivals drawn */
   int64_t synapses_streamed; /* synapse records read by the delivery kernels */
+  int64_t synapses_delivered; /* arrival form: records that fell into their reader's tile */
 } sim_stats_t;
 
 /* Build the networks on the device (connectivity, delays, weights; the paper's section 2
@@ -177,10 +179,19 @@ int sim_get_weights(sim_t* sim, float* w);
 /* Change tau_m and g_AHP (the constants are recomputed on the host). */
 int sim_set_params(sim_t* sim, double tau_m, double g_ahp);
 
-/* Delivery strategy and workgroup size in use (after autotuning, if any). */
-int sim_get_launch(const sim_t* sim, int32_t* delivery, int32_t* block);
-/* Change them; results are bit-identical for every choice. */
-int sim_set_launch(sim_t* sim, int32_t delivery, int32_t block);
+/* Launch configuration of the step: delivery strategy, workgroup size and, for the arrival
+ * form, the tile of target columns one workgroup owns (its LDS accumulators must fit in
+ * 160 KB: tile_x * tile_y * npc * 4 bytes plus about 30 KB). */
+typedef struct {
+  int32_t delivery;  /* DPSNN_DELIVERY_ARRIVAL or DPSNN_DELIVERY_PUSH */
+  int32_t block;     /* 64, 128, 256, 512 or 1024 */
+  int32_t tile_x, tile_y;  /* 1..4 */
+} sim_launch_t;
+
+/* The launch configuration in use. */
+int sim_get_launch(const sim_t* sim, sim_launch_t* launch);
+/* Change it between steps (synchronises); results are bit-identical for every choice. */
+int sim_set_launch(sim_t* sim, const sim_launch_t* launch);
 
 /* Per-kernel device time of the last sim_step call, measured with HIP events recorded on
  * the simulation's stream around every kernel launch while timing is on.  ms[0..2]: total

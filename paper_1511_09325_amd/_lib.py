@@ -41,9 +41,15 @@ class SimConfig(C.Structure):
         ("ext_syn", C.c_int32), ("j_ext", C.c_double),
         ("n_nets", C.c_int32), ("nets", C.POINTER(SimNet)),
         ("delivery", C.c_int32), ("block", C.c_int32),
+        ("tile_x", C.c_int32), ("tile_y", C.c_int32),
         ("record_steps", C.c_int64), ("raster_capacity", C.c_int64),
         ("train_mode", C.c_int32), ("ckpt_every", C.c_int32),
     ]
+
+
+class SimLaunch(C.Structure):
+    _fields_ = [("delivery", C.c_int32), ("block", C.c_int32), ("tile_x", C.c_int32),
+                ("tile_y", C.c_int32)]
 
 
 class SimInfo(C.Structure):
@@ -54,7 +60,8 @@ class SimInfo(C.Structure):
 
 class SimStats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("spikes", C.c_int64), ("events_recurrent", C.c_int64),
-                ("events_external", C.c_int64), ("synapses_streamed", C.c_int64)]
+                ("events_external", C.c_int64), ("synapses_streamed", C.c_int64),
+                ("synapses_delivered", C.c_int64)]
 
 
 _lib = None
@@ -91,8 +98,8 @@ def lib():
         "sim_set_weights": (C.c_int, [vp, vp]),
         "sim_get_weights": (C.c_int, [vp, vp]),
         "sim_set_params": (C.c_int, [vp, C.c_double, C.c_double]),
-        "sim_get_launch": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
-        "sim_set_launch": (C.c_int, [vp, C.c_int32, C.c_int32]),
+        "sim_get_launch": (C.c_int, [vp, P(SimLaunch)]),
+        "sim_set_launch": (C.c_int, [vp, P(SimLaunch)]),
         "sim_set_timing": (C.c_int, [vp, C.c_int32]),
         "sim_get_timing": (C.c_int, [vp, P(C.c_double), C.c_int32]),
     }

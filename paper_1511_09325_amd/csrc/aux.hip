@@ -51,13 +51,6 @@ __global__ __launch_bounds__(256) void k_raster_copy(const int32_t* hist_cnt,
   for (int32_t q = threadIdx.x; q < n; q += 256) ras_ids[base + q] = g * npc + ids[q];
 }
 
-__device__ __forceinline__ int rank_in_group(const GroupHdr& h, int32_t f) {
-  int r = 0;
-#pragma unroll
-  for (int q = 0; q < kMaxNbr - 1; ++q) r += ((int32_t)h.end[q] <= f) ? 1 : 0;
-  return r;
-}
-
 // Pending-input view of the arrival strategy: pend[q][j] = sum over spikes of steps
 // t in [now - d_max, now) and synapses of delay d with t + d = now + q, restricted to the
 // target columns [g0, g1) of one network (j relative to column g0).
@@ -76,17 +69,17 @@ __global__ __launch_bounds__(256) void k_pend_arrival(StepArgs a, int64_t now, i
     const uint16_t* ids = a.hist_ids + ((int64_t)slot * a.n_cols + g) * a.npc;
     for (int32_t q = wave; q < ns; q += 4) {
       const int64_t i = (int64_t)g * a.npc + ids[q];
+      const int64_t st = idx_start(a, i);
+      const uint16_t* go = idx_goff(a, i);
       for (int dd = 0; dd < a.nd; ++dd) {
         const int64_t due = t + a.d_min + dd;
         if (due < now) continue;
-        const GroupHdr h = a.hdr[i * a.nd + dd];
-        const int32_t len = h.end[kMaxNbr - 1];
-        for (int32_t f = lane; f < len; f += 64) {
-          const int r = rank_in_group(h, f);
-          const int32_t tc = a.col_nbr[g * kMaxNbr + r];
-          const uint32_t w = a.syn[h.start + f];
-          const int32_t val = TRAIN ? a.wfx[h.start + f] : (((int32_t)w) >> 16) * 4;
-          atomicAdd(&pend[(due - now) * n_net + (int64_t)(tc - g0) * a.npc + (w & 0xffffu)], val);
+        for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+          const uint32_t w = a.syn[st + f];
+          if (rec_rank(w) == (uint32_t)kDummyRank) continue;
+          const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+          const int32_t val = TRAIN ? a.wfx[st + f] : rec_w32(w);
+          atomicAdd(&pend[(due - now) * n_net + (int64_t)(tc - g0) * a.npc + rec_k(w)], val);
         }
       }
     }
@@ -100,19 +93,22 @@ __global__ __launch_bounds__(256) void k_export_rows(StepArgs a, int32_t g0, int
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t i = i0 + (int64_t)blockIdx.x * 4 + wave; i < i1; i += (int64_t)gridDim.x * 4) {
     const int32_t g = (int32_t)(i / a.npc);
-    const int64_t rb = a.row_base[i];
+    const int64_t st = idx_start(a, i);
+    const uint16_t* go = idx_goff(a, i);
     const int64_t ob = out_off[i - i0];
     for (int dd = 0; dd < a.nd; ++dd) {
-      const GroupHdr h = a.hdr[i * a.nd + dd];
-      const int32_t len = h.end[kMaxNbr - 1];
-      for (int32_t f = lane; f < len; f += 64) {
-        const int r = rank_in_group(h, f);
-        const int32_t tc = a.col_nbr[g * kMaxNbr + r];
-        const int64_t e = h.start + f;
-        const uint32_t w = a.syn[e];
-        tgt[ob + (e - rb)] = (tc - g0) * a.npc + (int32_t)(w & 0xffffu);
-        dly[ob + (e - rb)] = (uint8_t)(a.d_min + dd);
-        wq[ob + (e - rb)] = (int16_t)(w >> 16);
+      for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+        const uint32_t w = a.syn[st + f];
+        if (rec_rank(w) == (uint32_t)kDummyRank) {  // padding: marked with delay 0
+          tgt[ob + f] = -1;
+          dly[ob + f] = 0;
+          wq[ob + f] = 0;
+          continue;
+        }
+        const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+        tgt[ob + f] = (tc - g0) * a.npc + (int32_t)rec_k(w);
+        dly[ob + f] = (uint8_t)(a.d_min + dd);
+        wq[ob + f] = (int16_t)(w >> 16);
       }
     }
   }

@@ -1,6 +1,5 @@
 // capi.hip -- host side of libdpsnn: the C ABI declared in include/dpsnn.h.
 #include <math.h>
-#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -113,7 +112,9 @@ void validate(const sim_config_t* c) {
   if (!(c->block == 0 || c->block == 64 || c->block == 128 || c->block == 256 ||
         c->block == 512 || c->block == 1024))
     bad("block must be 0, 64, 128, 256, 512 or 1024");
-  if (c->block && c->npc > 8 * c->block) bad("block must be at least npc / 8");
+  if (c->tile_x < 0 || c->tile_y < 0 || c->tile_x > kMaxTileSide || c->tile_y > kMaxTileSide ||
+      ((c->tile_x == 0) != (c->tile_y == 0)))
+    bad("tile sides must both be 0 (auto) or both in [1, 4]");
   if (c->record_steps < 0 || c->raster_capacity < 0) bad("raster sizes must be >= 0");
   if (c->train_mode && c->ckpt_every < 1) bad("ckpt_every must be >= 1 in train mode");
   int64_t cols = 0;
@@ -129,13 +130,9 @@ void validate(const sim_config_t* c) {
   if (cols * (c->d_max + 1) * c->npc >= ((int64_t)1 << 31)) bad("spike history exceeds 2^31 entries");
 }
 
-// Default workgroup size of the step kernels: 256 threads, more for wide columns (each
-// thread holds at most 8 neurons of its column).
-int32_t default_block(int32_t npc) {
-  int32_t b = 256;
-  while (npc > 8 * b) b *= 2;
-  return b;
-}
+// Default workgroup size: the tile kernel uses 1024 threads (one workgroup per CU holds a
+// 4x4 tile's accumulators), the per-column push kernels 256.
+int32_t default_block(int32_t delivery) { return delivery == DPSNN_DELIVERY_PUSH ? 256 : 1024; }
 
 void set_constants(sim& s) {
   const sim_config_t& c = s.cfg;
@@ -149,6 +146,127 @@ void set_constants(sim& s) {
   s.nk.tref = c.t_ref;
 }
 
+// Round-robin merge of per-XCD work lists (-1 where a list ran out).
+std::vector<int32_t> interleave(const std::vector<std::vector<int32_t>>& lanes) {
+  size_t longest = 0;
+  for (const auto& L : lanes) longest = std::max(longest, L.size());
+  std::vector<int32_t> order;
+  for (size_t q = 0; q < longest; ++q)
+    for (size_t x = 0; x < lanes.size(); ++x) order.push_back(q < lanes[x].size() ? lanes[x][q] : -1);
+  return order;
+}
+
+void release(sim& s, void* p) {
+  if (!p) return;
+  for (size_t q = 0; q < s.bufs.size(); ++q) {
+    if (s.bufs[q].p == p) {
+      s.device_bytes -= s.bufs[q].bytes;
+      (void)hipFree(p);
+      s.bufs.erase(s.bufs.begin() + (long)q);
+      return;
+    }
+  }
+}
+
+// Tiles of tx x ty target columns (clamped to each network's grid; edge tiles are smaller).
+// For each tile: its columns, every column with synapses into it (the union of the 3x3
+// neighbourhoods), and per source the tile slot of each of its neighbour ranks.  Tiles are
+// ordered like the columns: strips of each network per XCD.
+void build_tiles(sim& s, int tx, int ty) {
+  if (tx < 1 || ty < 1 || tx > kMaxTileSide || ty > kMaxTileSide)
+    throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4]"};
+  std::vector<int32_t> tcols, tncols, tsrc, tnsrc;
+  std::vector<uint64_t> tslots;
+  std::vector<std::vector<int32_t>> lanes(8);
+  int rot = 0, maxc = 0;
+  for (int n = 0; n < s.n_nets; ++n) {
+    const int rows = s.nets[n].rows, cols = s.nets[n].cols;
+    const int ttx = std::min(tx, cols), tty = std::min(ty, rows);
+    const int ntx = (cols + ttx - 1) / ttx, nty = (rows + tty - 1) / tty;
+    const int nstrip = std::min(8, ntx);
+    for (int st = 0; st < nstrip; ++st) {
+      const int a0 = st * ntx / nstrip, a1 = (st + 1) * ntx / nstrip;
+      for (int yi = 0; yi < nty; ++yi) {
+        for (int xi = a0; xi < a1; ++xi) {
+          std::vector<int32_t> tc;
+          for (int y = yi * tty; y < std::min(rows, (yi + 1) * tty); ++y)
+            for (int x = xi * ttx; x < std::min(cols, (xi + 1) * ttx); ++x)
+              tc.push_back(s.net_col0[n] + y * cols + x);
+          std::vector<int32_t> src;
+          for (int32_t g : tc)
+            for (int r = 0; r < s.h_nn[g]; ++r) src.push_back(s.h_nbr[(size_t)g * kMaxNbr + r]);
+          std::sort(src.begin(), src.end());
+          src.erase(std::unique(src.begin(), src.end()), src.end());
+          if ((int)tc.size() > kMaxTileCols || (int)src.size() > kMaxTileSrc)
+            throw Fail{DPSNN_EINVAL, "tile too large"};
+          const int32_t id = (int32_t)tncols.size();
+          maxc = std::max(maxc, (int)tc.size());
+          tncols.push_back((int32_t)tc.size());
+          tnsrc.push_back((int32_t)src.size());
+          for (int q = 0; q < kMaxTileCols; ++q) tcols.push_back(q < (int)tc.size() ? tc[q] : -1);
+          for (int q = 0; q < kMaxTileSrc; ++q) {
+            uint64_t packed = 0;
+            int32_t sc = -1;
+            for (int r = 0; r < kMaxNbr; ++r) {
+              uint64_t slot = kNoSlot;
+              if (q < (int)src.size()) {
+                sc = src[q];
+                if (r < s.h_nn[sc]) {
+                  const int32_t t = s.h_nbr[(size_t)sc * kMaxNbr + r];
+                  for (size_t z = 0; z < tc.size(); ++z)
+                    if (tc[z] == t) slot = z;
+                }
+              }
+              packed |= slot << (5 * r);
+            }
+            tsrc.push_back(q < (int)src.size() ? src[q] : -1);
+            tslots.push_back(packed);
+          }
+          lanes[(st + rot) % 8].push_back(id);
+        }
+      }
+    }
+    rot = (rot + nstrip) % 8;
+  }
+  const int32_t old_max = s.tile_max_cols;
+  s.tile_max_cols = maxc;
+  if (tile_chunk(s) < 256) {
+    s.tile_max_cols = old_max;
+    throw Fail{DPSNN_EINVAL, "tile accumulators exceed the 160 KB LDS of a workgroup"};
+  }
+  release(s, s.tile_order);
+  release(s, s.tile_cols);
+  release(s, s.tile_ncols);
+  release(s, s.tile_src);
+  release(s, s.tile_nsrc);
+  release(s, s.tile_slots);
+  const std::vector<int32_t> order = interleave(lanes);
+  s.tile_x = tx;
+  s.tile_y = ty;
+  s.n_tiles = (int32_t)tncols.size();
+  s.grid_tiles = (int32_t)order.size();
+  s.tile_order = upload(s, order);
+  s.tile_cols = upload(s, tcols);
+  s.tile_ncols = upload(s, tncols);
+  s.tile_src = upload(s, tsrc);
+  s.tile_nsrc = upload(s, tnsrc);
+  s.tile_slots = upload(s, tslots);
+}
+
+// Largest square-ish tile (sides <= 4) whose accumulators fit the LDS.
+void default_tiles(sim& s) {
+  static const int shapes[][2] = {{4, 4}, {4, 3}, {3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
+  for (const auto& sh : shapes) {
+    try {
+      build_tiles(s, sh[0], sh[1]);
+      return;
+    } catch (const Fail& f) {
+      if (f.code != DPSNN_EINVAL) throw;
+    }
+  }
+  throw Fail{DPSNN_EINVAL, "no tile shape fits the LDS"};
+}
+
 void build_tables(sim& s) {
   const sim_config_t& c = s.cfg;
   s.net_col0.assign(1, 0);
@@ -156,7 +274,7 @@ void build_tables(sim& s) {
   s.n_cols = s.net_col0.back();
   s.n_neurons = (int64_t)s.n_cols * s.npc;
   std::vector<int32_t> col_net(s.n_cols), col_local(s.n_cols), nn(s.n_cols);
-  std::vector<int32_t> nbr((size_t)s.n_cols * kMaxNbr, -1), rank((size_t)s.n_cols * kMaxNbr, -1);
+  std::vector<int32_t> nbr((size_t)s.n_cols * kMaxNbr, -1);
   std::vector<uint64_t> thr((size_t)s.n_cols * kMaxNbr, 0);
   for (int n = 0; n < s.n_nets; ++n) {
     const int rows = s.nets[n].rows, cols = s.nets[n].cols;
@@ -188,21 +306,11 @@ void build_tables(sim& s) {
       }
     }
   }
-  for (int32_t g = 0; g < s.n_cols; ++g) {
-    for (int r = 0; r < nn[g]; ++r) {
-      const int32_t sc = nbr[(size_t)g * kMaxNbr + r];
-      for (int q = 0; q < nn[sc]; ++q)
-        if (nbr[(size_t)sc * kMaxNbr + q] == g) rank[(size_t)g * kMaxNbr + r] = q;
-      if (rank[(size_t)g * kMaxNbr + r] < 0) throw Fail{DPSNN_EINVAL, "asymmetric neighbourhood"};
-    }
-  }
-  // Workgroup order.  Workgroups are dealt to the 8 XCDs (each with its own L2) in
-  // round-robin order of their index, and the 9 target columns around a source column
-  // all read that column's synapse groups; so columns are ordered such that workgroup b
-  // lands on XCD b % 8 together with its spatial neighbours: each network is cut into up
-  // to 8 vertical strips, strip s goes to XCD (s + rotation) % 8, and each strip is walked
-  // row by row.  Slots left over when strips differ in size are -1 (skipped).  This is a
-  // scheduling hint only: any order gives the same results.
+  // Workgroup order of the per-column kernels.  Workgroups are dealt to the 8 XCDs (each
+  // with its own L2) in round-robin order of their index; columns are ordered so that
+  // workgroup b lands on XCD b % 8 next to its spatial neighbours (vertical strips of each
+  // network, walked row by row).  Slots left over when strips differ in size are -1.
+  // A scheduling hint only: any order gives the same results.
   {
     std::vector<std::vector<int32_t>> lanes(8);
     int rot = 0;
@@ -217,19 +325,12 @@ void build_tables(sim& s) {
       }
       rot = (rot + nstrip) % 8;
     }
-    size_t longest = 0;
-    for (auto& L : lanes) longest = std::max(longest, L.size());
-    std::vector<int32_t> order;
-    for (size_t q = 0; q < longest; ++q)
-      for (int x = 0; x < 8; ++x) order.push_back(q < lanes[x].size() ? lanes[x][q] : -1);
-    std::vector<int32_t> rm((size_t)s.n_cols);
-    for (int32_t g = 0; g < s.n_cols; ++g) rm[g] = g;
-    s.grid_xcd = (int32_t)order.size();
+    std::vector<int32_t> order = interleave(lanes);
+    s.grid_cols = (int32_t)order.size();
     s.col_order = upload(s, order);
-    s.col_order_rm = upload(s, rm);
-    const char* env = getenv("DPSNN_ROW_MAJOR");
-    s.xcd_order = !(env && env[0] == '1');
   }
+  s.h_nbr = nbr;
+  s.h_nn = nn;
   std::vector<uint32_t> key(2 * (size_t)s.n_nets);
   std::vector<uint64_t> ptab((size_t)s.n_nets * kPoissonEntries);
   for (int n = 0; n < s.n_nets; ++n) {
@@ -242,7 +343,6 @@ void build_tables(sim& s) {
   s.col_local = upload(s, col_local);
   s.col_nn = upload(s, nn);
   s.col_nbr = upload(s, nbr);
-  s.col_rank = upload(s, rank);
   s.col_thr = upload(s, thr);
   s.net_key = upload(s, key);
   s.net_ptab = upload(s, ptab);
@@ -251,6 +351,7 @@ void build_tables(sim& s) {
 void generate(sim& s) {
   const int64_t N = s.n_neurons;
   int32_t* row_len = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)N);
+  s.deg = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)N);
   s.seg = (uint16_t*)dalloc(s, sizeof(uint16_t) * (size_t)N * s.segw);
   s.row_base = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)(N + 1));
   const int64_t plen = scan_scratch_len(N);
@@ -260,24 +361,28 @@ void generate(sim& s) {
   int64_t total = 0;
   HIPCHK(hipMemcpyAsync(&total, s.row_base + N, sizeof(int64_t), hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
-  s.n_syn = total;
   // one spare uint4 after the last synapse: the delivery kernels may load whole 16-byte
   // words that straddle the end of a segment
   s.syn = (uint32_t*)dalloc(s, sizeof(uint32_t) * (size_t)(total + 4));
-  s.hdr = (GroupHdr*)dalloc(s, sizeof(GroupHdr) * (size_t)N * s.nd);
+  s.idx = (uint8_t*)dalloc(s, (size_t)s.idxw * (size_t)N);
   HIPCHK(hipMemsetAsync(s.syn + total, 0, 4 * sizeof(uint32_t), s.stream));
   HIPCHK(launch_gen_fill(s, 0, N));
+  // the number of synapses (without the padding): scan of the out-degrees
+  int64_t* degscan = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)(N + 1));
+  HIPCHK(launch_scan_rows(s, s.deg, N, degscan, part, plen));
+  HIPCHK(hipMemcpyAsync(&s.n_syn, degscan + N, sizeof(int64_t), hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
+  s.n_syn_padded = total;
+  s.net_syn0.assign((size_t)s.n_nets + 1, 0);
+  for (int n = 0; n <= s.n_nets; ++n) {
+    const int64_t i = (int64_t)s.net_col0[n] * s.npc;
+    HIPCHK(hipMemcpy(&s.net_syn0[n], degscan + i, sizeof(int64_t), hipMemcpyDeviceToHost));
+  }
+  dfree(s, degscan);
   dfree(s, part);
   dfree(s, row_len);
   dfree(s, s.seg);
   s.seg = nullptr;
-  // per-network synapse offsets (host copy of the network boundaries of row_base)
-  s.net_syn0.assign((size_t)s.n_nets + 1, 0);
-  for (int n = 0; n <= s.n_nets; ++n) {
-    const int64_t i = (int64_t)s.net_col0[n] * s.npc;
-    HIPCHK(hipMemcpy(&s.net_syn0[n], s.row_base + i, sizeof(int64_t), hipMemcpyDeviceToHost));
-  }
 }
 
 void ensure_ring(sim& s) {
@@ -320,7 +425,7 @@ void snapshot_parts(sim& s, size_t* parts, void** ptrs) {
   parts[2] = N;                                                    ptrs[2] = s.ref;
   parts[3] = sizeof(int32_t) * (size_t)s.dh * s.n_cols;            ptrs[3] = s.hist_cnt;
   parts[4] = sizeof(uint16_t) * (size_t)s.dh * s.n_cols * s.npc;   ptrs[4] = s.hist_ids;
-  parts[5] = sizeof(unsigned long long) * 4 * (size_t)s.n_nets;    ptrs[5] = s.net_cnt;
+  parts[5] = sizeof(unsigned long long) * kCounters * (size_t)s.n_nets;    ptrs[5] = s.net_cnt;
 }
 
 int finish(sim* s, const Fail& f) {
@@ -347,11 +452,14 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->npc = cfg->npc;
     s->nd = cfg->d_max - cfg->d_min + 1;
     s->dh = cfg->d_max + 1;
-    s->segw = (s->nd * kMaxNbr + 1 + 1) & ~1;
+    s->segw = (s->nd * kSegPerDelay + 1 + 1) & ~1;
+    s->idxw = (8 + 2 * (s->nd + 1) + 15) & ~15;
     s->delivery = cfg->delivery == DPSNN_DELIVERY_PUSH ? DPSNN_DELIVERY_PUSH : DPSNN_DELIVERY_ARRIVAL;
-    s->block = cfg->block ? cfg->block : default_block(cfg->npc);
+    s->block = cfg->block ? cfg->block : default_block(s->delivery);
     set_constants(*s);
     build_tables(*s);
+    if (cfg->tile_x || cfg->tile_y) build_tiles(*s, cfg->tile_x, cfg->tile_y);
+    else default_tiles(*s);
     generate(*s);
     const size_t N = (size_t)s->n_neurons;
     s->v = (float*)dalloc(*s, sizeof(float) * N);
@@ -359,10 +467,10 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->ref = (uint8_t*)dalloc(*s, N);
     s->hist_cnt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)s->dh * s->n_cols);
     s->hist_ids = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
-    s->net_cnt = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * 4 * (size_t)s->n_nets);
+    s->net_cnt = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets);
     s->flags = (int32_t*)dalloc(*s, sizeof(int32_t) * 4);
     HIPCHK(hipMemsetAsync(s->hist_cnt, 0, sizeof(int32_t) * (size_t)s->dh * s->n_cols, s->stream));
-    HIPCHK(hipMemsetAsync(s->net_cnt, 0, sizeof(unsigned long long) * 4 * (size_t)s->n_nets, s->stream));
+    HIPCHK(hipMemsetAsync(s->net_cnt, 0, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets, s->stream));
     HIPCHK(hipMemsetAsync(s->flags, 0, sizeof(int32_t) * 4, s->stream));
     HIPCHK(launch_init_state(*s));
     if (s->delivery == DPSNN_DELIVERY_PUSH) ensure_ring(*s);
@@ -537,13 +645,14 @@ int sim_get_stats(sim_t* s, int32_t net, sim_stats_t* st) {
   try {
     if (net < 0 || net >= s->n_nets) throw Fail{DPSNN_EINVAL, "net out of range"};
     HIPCHK(hipStreamSynchronize(s->stream));
-    unsigned long long c[4];
-    HIPCHK(hipMemcpy(c, s->net_cnt + 4 * net, sizeof(c), hipMemcpyDeviceToHost));
+    unsigned long long c[kCounters];
+    HIPCHK(hipMemcpy(c, s->net_cnt + kCounters * net, sizeof(c), hipMemcpyDeviceToHost));
     st->steps = s->now;
     st->spikes = (int64_t)c[0];
     st->events_recurrent = (int64_t)c[1];
     st->events_external = (int64_t)c[2];
     st->synapses_streamed = (int64_t)c[3];
+    st->synapses_delivered = (int64_t)c[4];
     return DPSNN_OK;
   } catch (const Fail& f) {
     return finish(s, f);
@@ -592,27 +701,47 @@ int sim_read_synapses(sim_t* s, int32_t net, int64_t i0, int64_t i1, int64_t* ro
     if (i0 < 0 || i1 < i0 || i1 > nloc || !row_ptr) throw Fail{DPSNN_EINVAL, "bad row range"};
     HIPCHK(hipStreamSynchronize(s->stream));
     const int64_t g0 = (int64_t)s->net_col0[net] * s->npc + i0;
-    std::vector<int64_t> rb((size_t)(i1 - i0 + 1));
-    HIPCHK(hipMemcpy(rb.data(), s->row_base + g0, sizeof(int64_t) * rb.size(), hipMemcpyDeviceToHost));
-    for (size_t q = 0; q < rb.size(); ++q) row_ptr[q] = rb[q] - rb[0];
-    const int64_t total = rb.back() - rb.front();
+    const size_t nr = (size_t)(i1 - i0);
+    std::vector<int32_t> deg(nr);
+    if (nr) HIPCHK(hipMemcpy(deg.data(), s->deg + g0, sizeof(int32_t) * nr, hipMemcpyDeviceToHost));
+    row_ptr[0] = 0;
+    for (size_t q = 0; q < nr; ++q) row_ptr[q + 1] = row_ptr[q] + deg[q];
+    const int64_t total = row_ptr[nr];
     if (total > cap) { s->err = "synapse buffers too small"; return DPSNN_ETRUNC; }
     if (total == 0) return DPSNN_OK;
     if (!tgt || !dly || !wq) throw Fail{DPSNN_EINVAL, "NULL output"};
-    int32_t* dt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)total);
-    uint8_t* dd = (uint8_t*)dalloc(*s, (size_t)total);
-    int16_t* dw = (int16_t*)dalloc(*s, sizeof(int16_t) * (size_t)total);
-    int64_t* doff = (int64_t*)dalloc(*s, sizeof(int64_t) * rb.size());
-    HIPCHK(hipMemcpy(doff, row_ptr, sizeof(int64_t) * rb.size(), hipMemcpyHostToDevice));
-    HIPCHK(launch_export_rows(*s, net, g0, g0 + (i1 - i0), dt, dd, dw, doff));
+    // export the padded rows, then drop the padding (delay 0) on the host
+    std::vector<int64_t> rb(nr + 1);
+    HIPCHK(hipMemcpy(rb.data(), s->row_base + g0, sizeof(int64_t) * rb.size(), hipMemcpyDeviceToHost));
+    std::vector<int64_t> poff(nr + 1);
+    for (size_t q = 0; q <= nr; ++q) poff[q] = rb[q] - rb[0];
+    const int64_t ptotal = poff[nr];
+    int32_t* dt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)ptotal);
+    uint8_t* dd = (uint8_t*)dalloc(*s, (size_t)ptotal);
+    int16_t* dw = (int16_t*)dalloc(*s, sizeof(int16_t) * (size_t)ptotal);
+    int64_t* doff = (int64_t*)dalloc(*s, sizeof(int64_t) * poff.size());
+    HIPCHK(hipMemcpy(doff, poff.data(), sizeof(int64_t) * poff.size(), hipMemcpyHostToDevice));
+    HIPCHK(launch_export_rows(*s, net, g0, g0 + (int64_t)nr, dt, dd, dw, doff));
     HIPCHK(hipStreamSynchronize(s->stream));
-    HIPCHK(hipMemcpy(tgt, dt, sizeof(int32_t) * (size_t)total, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(dly, dd, (size_t)total, hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(wq, dw, sizeof(int16_t) * (size_t)total, hipMemcpyDeviceToHost));
+    std::vector<int32_t> ht((size_t)ptotal);
+    std::vector<uint8_t> hd((size_t)ptotal);
+    std::vector<int16_t> hw((size_t)ptotal);
+    HIPCHK(hipMemcpy(ht.data(), dt, sizeof(int32_t) * (size_t)ptotal, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hd.data(), dd, (size_t)ptotal, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hw.data(), dw, sizeof(int16_t) * (size_t)ptotal, hipMemcpyDeviceToHost));
     dfree(*s, doff);
     dfree(*s, dw);
     dfree(*s, dd);
     dfree(*s, dt);
+    int64_t o = 0;
+    for (int64_t e = 0; e < ptotal; ++e) {
+      if (hd[(size_t)e] == 0) continue;
+      tgt[o] = ht[(size_t)e];
+      dly[o] = hd[(size_t)e];
+      wq[o] = hw[(size_t)e];
+      ++o;
+    }
+    if (o != total) throw Fail{DPSNN_EHIP, "synapse export is inconsistent with the out-degrees"};
     return DPSNN_OK;
   } catch (const Fail& f) {
     return finish(s, f);
@@ -686,23 +815,28 @@ int sim_set_params(sim_t* s, double tau_m, double g_ahp) {
   return DPSNN_OK;
 }
 
-int sim_get_launch(const sim_t* s, int32_t* delivery, int32_t* block) {
-  if (!s) return DPSNN_EINVAL;
-  if (delivery) *delivery = s->delivery;
-  if (block) *block = s->block;
+int sim_get_launch(const sim_t* s, sim_launch_t* l) {
+  if (!s || !l) return DPSNN_EINVAL;
+  l->delivery = s->delivery;
+  l->block = s->block;
+  l->tile_x = s->tile_x;
+  l->tile_y = s->tile_y;
   return DPSNN_OK;
 }
 
-int sim_set_launch(sim_t* s, int32_t delivery, int32_t block) {
+int sim_set_launch(sim_t* s, const sim_launch_t* l) {
   if (!s) return DPSNN_EINVAL;
   try {
+    if (!l) throw Fail{DPSNN_EINVAL, "launch is NULL"};
+    const int32_t block = l->block;
     if (!(block == 64 || block == 128 || block == 256 || block == 512 || block == 1024))
       throw Fail{DPSNN_EINVAL, "block must be 64, 128, 256, 512 or 1024"};
-    if (delivery != DPSNN_DELIVERY_ARRIVAL && delivery != DPSNN_DELIVERY_PUSH)
+    if (l->delivery != DPSNN_DELIVERY_ARRIVAL && l->delivery != DPSNN_DELIVERY_PUSH)
       throw Fail{DPSNN_EINVAL, "delivery must be ARRIVAL or PUSH"};
-    if (s->npc > 8 * block) throw Fail{DPSNN_EINVAL, "block must be at least npc / 8"};
-    if (delivery == DPSNN_DELIVERY_PUSH && s->delivery != DPSNN_DELIVERY_PUSH) ring_from_history(*s);
-    s->delivery = delivery;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (l->tile_x != s->tile_x || l->tile_y != s->tile_y) build_tiles(*s, l->tile_x, l->tile_y);
+    if (l->delivery == DPSNN_DELIVERY_PUSH && s->delivery != DPSNN_DELIVERY_PUSH) ring_from_history(*s);
+    s->delivery = l->delivery;
     s->block = block;
     return DPSNN_OK;
   } catch (const Fail& f) {

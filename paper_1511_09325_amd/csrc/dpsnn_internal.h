@@ -4,20 +4,26 @@
 // global neuron index is g*npc + k for global column g and local index k):
 //
 //   synapse store, canonical order: per source neuron, sorted by (delay, target).  Within
-//   one delay the targets come column by column in ascending column order, so a row splits
-//   into groups (one per delay) and each group into segments (one per target column, r
-//   indexing the source column's sorted list of distinct neighbour columns -- at most 9,
+//   one delay the targets come column by column in ascending column order.  A row is a
+//   sequence of groups, one per delay; a synapse's target column is identified by its
+//   rank r in the source column's sorted list of distinct neighbour columns (at most 9:
 //   the 3x3 torus stencil)
-//     row_base  int64 [N+1]         first synapse of each row
-//     hdr       GroupHdr[N][nd]     group (i, delay): absolute start and the cumulative
-//                                   end of each target-column segment inside the group
-//     syn       uint32[S]           (k : low 16 bits) | (w_q : high 16 bits), the target's
-//                                   index inside its column and the int16 weight (2^-14 mV)
-//     wfx       int32 [S]           train mode only: rint(w_f32 * 2^16) efficacies
+//     idx       idxw bytes per neuron: int64 start of the row, then uint16 goff[nd + 1];
+//               group dd (delay d_min + dd) is [start + goff[dd], start + goff[dd + 1])
+//     syn       uint32[S' + 4]: k (bits 0-11, target index inside its column) | r (bits
+//               12-15) | w_q (bits 16-31, int16 weight at 2^-14 mV).  Every group is padded
+//               to a multiple of 4 records with dummies (r = 15, weight 0), so rows and
+//               groups start on 16-byte boundaries and are read in whole 16-byte words
+//     deg       int32 [N]    out-degree (records without the padding)
+//     wfx       int32 [S]   train mode only: rint(w_f32 * 2^16) efficacies
 //   column tables
-//     col_nbr   int32 [C][9]        distinct neighbour columns, ascending, -1 padded
-//     col_rank  int32 [C][9]        rank of column g in the list of its neighbour col_nbr[g][r]
-//     col_thr   uint64[C][9]        pair connection threshold from g to col_nbr[g][r]
+//     col_nbr   int32 [C][9]   distinct neighbour columns, ascending, -1 padded
+//     col_thr   uint64[C][9]   pair connection threshold from g to col_nbr[g][r]
+//   tiles (the unit of work of the arrival kernel): up to 4x4 target columns of one network
+//     tile_cols   int32 [tiles][16]   the tile's columns, -1 padded
+//     tile_src    int32 [tiles][36]   every column with a synapse into the tile
+//     tile_slots  uint64[tiles][36]   for each source and each rank r, the tile slot of its
+//                                     target column in bits 5r..5r+4 (31: not in the tile)
 //   spike history (shared by both delivery strategies)
 //     hist_cnt  int32 [DH][C]       spikes of column g at step t, in slot t % DH
 //     hist_ids  uint16[DH][C][npc]  their local indices, ascending
@@ -38,12 +44,26 @@
 namespace dpsnn {
 
 constexpr int kMaxNbr = 9;          // 3x3 stencil
-constexpr int kMaxNpc = 4096;
+constexpr int kMaxNpc = 4096;       // 12-bit target index
 constexpr int kMaxDelay = 32;
 constexpr int kPoissonEntries = 63;
+constexpr int kMaxTileSide = 4;
+constexpr int kMaxTileCols = kMaxTileSide * kMaxTileSide;
+constexpr int kMaxTileSrc = (kMaxTileSide + 2) * (kMaxTileSide + 2);
+constexpr int kNoSlot = 31;
+constexpr int kSegPerDelay = 10;    // construction table: 9 target ranks + group padding
+constexpr int kDummyRank = 15;
+constexpr uint32_t kDummyRecord = (uint32_t)kDummyRank << 12;  // k 0, rank 15, weight 0
+constexpr int kCounters = 8;        // per-network counters (see StepArgs::net_cnt)
+constexpr size_t kMaxLds = 160 * 1024;
 constexpr uint32_t kStreamSyn = 1;  // Philox counter word 3: purpose of the draw
 constexpr uint32_t kStreamExt = 2;
 constexpr uint32_t kStreamInit = 3;
+
+// record fields
+__host__ __device__ __forceinline__ uint32_t rec_k(uint32_t w) { return w & 0xfffu; }
+__host__ __device__ __forceinline__ uint32_t rec_rank(uint32_t w) { return (w >> 12) & 0xfu; }
+__host__ __device__ __forceinline__ int32_t rec_w32(uint32_t w) { return (((int32_t)w) >> 16) * 4; }
 
 // ---------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products, high halves
@@ -71,15 +91,6 @@ __device__ __forceinline__ Rand4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   return Rand4{c0, c1, c2, c3};
 }
 
-// Header of the synapse group of one (source neuron, delay): segment r (target column
-// col_nbr[source column][r]) is [start + (r ? end[r-1] : 0), start + end[r]).
-struct GroupHdr {
-  int64_t start;
-  uint16_t end[kMaxNbr];
-  uint16_t pad[3];
-};
-static_assert(sizeof(GroupHdr) == 32, "GroupHdr must be 32 bytes");
-
 // Neuron constants, rounded once from double on the host.
 struct NeuronK {
   float pm;      // exp(-dt / tau_m)
@@ -95,20 +106,28 @@ struct NeuronK {
 // Everything the step kernels read or write, by value.
 struct StepArgs {
   // sizes
-  int32_t npc, nd, d_min, dh, n_cols;
+  int32_t npc, nd, d_min, dh, n_cols, idxw;
   // column / network tables
   const int32_t* col_net;
   const int32_t* col_local;   // column index within its network
   const int32_t* col_nbr;
   const int32_t* col_nn;
-  const int32_t* col_rank;
-  const int32_t* col_order;   // [grid]: column processed by workgroup b (-1: none)
-  int32_t grid;               // workgroups of the per-column kernels
+  const int32_t* col_order;   // [grid_cols]: column of workgroup b of per-column kernels
+  int32_t grid_cols;
   const uint32_t* net_key;    // [n_nets][2]
   const uint64_t* net_ptab;   // [n_nets][63]
+  // tiles
+  const int32_t* tile_order;  // [grid_tiles]: tile of workgroup b (-1: none)
+  int32_t grid_tiles;
+  const int32_t* tile_cols;
+  const int32_t* tile_ncols;
+  const int32_t* tile_src;
+  const int32_t* tile_nsrc;
+  const uint64_t* tile_slots;
   // synapses
   const int64_t* row_base;
-  const GroupHdr* hdr;
+  const int32_t* deg;
+  const uint8_t* idx;
   const uint32_t* syn;
   const int32_t* wfx;         // train mode, else null
   // state
@@ -118,8 +137,9 @@ struct StepArgs {
   int32_t* hist_cnt;
   uint16_t* hist_ids;
   int32_t* ring;              // push only
-  unsigned long long* net_cnt;  // [n_nets][4]: spikes, e_rec, e_ext, synapses streamed
-  // train-mode trajectory recording (null when off): [rec_steps][N]
+  unsigned long long* net_cnt;  // [n_nets][kCounters]: spikes, e_rec, e_ext, synapse records
+                                // read, synapses delivered (arrival form)
+  // train-mode trajectory recording (null when off): [steps][N]
   float* rec_vprev;
   float* rec_caprev;
   float* rec_vt;
@@ -127,6 +147,14 @@ struct StepArgs {
   int64_t rec_base;           // first step held by the recording buffers
   NeuronK k;
 };
+
+// row index entry of neuron i
+__device__ __forceinline__ int64_t idx_start(const StepArgs& a, int64_t i) {
+  return *(const int64_t*)(a.idx + i * a.idxw);
+}
+__device__ __forceinline__ const uint16_t* idx_goff(const StepArgs& a, int64_t i) {
+  return (const uint16_t*)(a.idx + i * a.idxw + 8);
+}
 
 // ---------------------------------------------------------------------------------------
 // host side
@@ -139,7 +167,7 @@ struct DevBuf {
 struct Snapshot {
   bool valid = false;
   int64_t now = 0;
-  DevBuf blob;  // v | ca | ref | hist_cnt | hist_ids | ring | net_cnt
+  DevBuf blob;  // v | ca | ref | hist_cnt | hist_ids | net_cnt
 };
 
 }  // namespace dpsnn
@@ -152,26 +180,25 @@ struct sim {
   int sticky = 0;
 
   // sizes
-  int32_t n_nets = 0, n_cols = 0, npc = 0, nd = 0, dh = 0, segw = 0;
-  int64_t n_neurons = 0, n_syn = 0;
+  int32_t n_nets = 0, n_cols = 0, npc = 0, nd = 0, dh = 0, segw = 0, idxw = 0;
+  int64_t n_neurons = 0, n_syn = 0, n_syn_padded = 0;
   std::vector<int32_t> net_col0;    // first global column of each network (n_nets+1)
   std::vector<int64_t> net_syn0;    // first synapse of each network (n_nets+1)
+  std::vector<int32_t> h_nbr, h_nn; // host copies of the neighbour tables
 
   // device memory
   std::vector<dpsnn::DevBuf> bufs;
   size_t device_bytes = 0;
-  int32_t *col_net = nullptr, *col_local = nullptr, *col_nbr = nullptr, *col_nn = nullptr,
-          *col_rank = nullptr;
-  int32_t* col_order = nullptr;    // workgroup -> column (XCD-aware order)
-  int32_t* col_order_rm = nullptr; // workgroup -> column (row-major order)
-  int32_t grid_xcd = 0;
-  bool xcd_order = true;
+  int32_t *col_net = nullptr, *col_local = nullptr, *col_nbr = nullptr, *col_nn = nullptr;
+  int32_t* col_order = nullptr;
+  int32_t grid_cols = 0;
   uint64_t* col_thr = nullptr;
   uint32_t* net_key = nullptr;
   uint64_t* net_ptab = nullptr;
   int64_t* row_base = nullptr;
-  uint16_t* seg = nullptr;         // construction only: relative segment starts [N][segw]
-  dpsnn::GroupHdr* hdr = nullptr;
+  int32_t* deg = nullptr;
+  uint16_t* seg = nullptr;          // construction only: relative segment starts [N][segw]
+  uint8_t* idx = nullptr;
   uint32_t* syn = nullptr;
   int32_t* wfx = nullptr;
   float* wf32 = nullptr;
@@ -181,6 +208,11 @@ struct sim {
   uint16_t* hist_ids = nullptr;
   int32_t* ring = nullptr;
   unsigned long long* net_cnt = nullptr;
+  // tiles of the current shape
+  int32_t tile_x = 0, tile_y = 0, n_tiles = 0, grid_tiles = 0, tile_max_cols = 0;
+  int32_t *tile_order = nullptr, *tile_cols = nullptr, *tile_ncols = nullptr,
+          *tile_src = nullptr, *tile_nsrc = nullptr;
+  uint64_t* tile_slots = nullptr;
   // raster
   int64_t* ras_off = nullptr;      // [record_steps+1]
   int32_t* ras_ids = nullptr;      // [raster_capacity], global neuron ids
@@ -190,6 +222,8 @@ struct sim {
   float *rec_vprev = nullptr, *rec_caprev = nullptr, *rec_vt = nullptr;
   uint8_t* rec_flags = nullptr;
   int64_t rec_steps = 0;
+  int64_t rec_base = 0;
+  bool rec_on = false;
 
   int64_t now = 0;
   int32_t delivery = DPSNN_DELIVERY_ARRIVAL;
@@ -213,6 +247,8 @@ hipError_t launch_init_state(const sim& s);
 // part: -1 the whole step, 0 the update (fused with the gather in the arrival form),
 // 1 the push delivery
 hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block, int part);
+size_t tile_lds_bytes(const sim& s);
+int32_t tile_chunk(const sim& s);
 hipError_t launch_raster(sim& s, int64_t u);
 hipError_t launch_pend_view(const sim& s, int32_t* pend, int32_t g0, int32_t g1);
 hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1, int32_t* tgt,

@@ -11,8 +11,11 @@
 //   weight     mu + sigma * z, z = (sum of 12 16-bit halves of words z, w and of the four
 //              words at counter (j, i, 1, SYN) - 393210) / 65536, in double, no FMA,
 //              quantised to int16 at 2^-14 mV with round-half-even.
-// Rows are written in canonical order (delay, target).  Two passes: counting per
-// (delay, target column) segment, then an exclusive scan over rows, then filling.
+// Rows are written in canonical order (delay, target), each record carrying the rank of its
+// target column in the source column's neighbour list; each delay group is padded with
+// dummy records to a multiple of 4 so that 16-byte words never straddle two groups.  Two
+// passes: counting per (delay, target column) segment, then an exclusive scan over rows,
+// then filling.
 #include "dpsnn_internal.h"
 
 namespace dpsnn {
@@ -28,11 +31,13 @@ struct GenArgs {
   const uint64_t* col_thr;
   const uint32_t* net_key;
   double we_mu, we_sigma, wi_mu, wi_sigma;
-  int32_t* row_len;        // count pass output
+  int32_t* row_len;        // count pass output: padded row length
+  int32_t* deg;            // count pass output: out-degree
   uint16_t* seg;           // count pass output
   const int64_t* row_base; // fill pass input
   uint32_t* syn;           // fill pass output
-  GroupHdr* hdr;           // fill pass output
+  uint8_t* idx;            // fill pass output: row index entries
+  int32_t idxw;
 };
 
 constexpr int kGenWaves = 4;  // rows per workgroup (one wave each)
@@ -52,10 +57,10 @@ __device__ __forceinline__ bool decide(const GenArgs& a, int64_t i, int64_t jglo
 }
 
 __global__ __launch_bounds__(64 * kGenWaves) void k_gen_count(GenArgs a) {
-  __shared__ int32_t cnt[kGenWaves][kMaxNbr * kMaxDelay];
+  __shared__ int32_t cnt[kGenWaves][kSegPerDelay * kMaxDelay];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int nseg = a.nd * kMaxNbr;
+  const int nseg = a.nd * kSegPerDelay;
   for (int64_t rr = (int64_t)blockIdx.x * kGenWaves + wave; rr < a.rows;
        rr += (int64_t)gridDim.x * kGenWaves) {
     const int64_t i = a.row0 + rr;
@@ -83,10 +88,20 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_count(GenArgs a) {
           if (lane == q) mine += __popcll(m);
         }
       }
-      if (lane < a.nd) cnt[wave][lane * kMaxNbr + r] = mine;
+      if (lane < a.nd) cnt[wave][lane * kSegPerDelay + r] = mine;
     }
     __builtin_amdgcn_wave_barrier();
-    // exclusive prefix over the nd*9 segments in (delay, rank) order
+    // each group is padded to a multiple of 4 records (dummies in entry 9 of the delay)
+    int32_t used = 0;
+    if (lane < a.nd) {
+      int32_t glen = 0;
+      for (int r = 0; r < kMaxNbr; ++r) glen += cnt[wave][lane * kSegPerDelay + r];
+      cnt[wave][lane * kSegPerDelay + kMaxNbr] = ((glen + 3) & ~3) - glen;
+      used = glen;
+    }
+    for (int off = 32; off > 0; off >>= 1) used += __shfl_down(used, off);
+    __builtin_amdgcn_wave_barrier();
+    // exclusive prefix over the nd*10 entries in (delay, rank) order
     const int per = (nseg + 63) / 64;
     int32_t local = 0;
     for (int q = 0; q < per; ++q) {
@@ -111,6 +126,7 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_count(GenArgs a) {
     if (lane == 0) {
       out[nseg] = (uint16_t)total;
       a.row_len[i] = total;
+      a.deg[i] = used;
     }
     for (int e = nseg + 1 + lane; e < a.segw; e += 64) out[e] = 0;
     __builtin_amdgcn_wave_barrier();
@@ -136,22 +152,21 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
     const uint16_t* sg = a.seg + i * a.segw;
     const int64_t rb = a.row_base[i];
     uint32_t* out = a.syn + rb;
-    // group headers: lane dd describes the group of delay d_min + dd
-    if (lane < a.nd) {
-      GroupHdr h;
-      const int32_t g0 = sg[lane * kMaxNbr];
-      h.start = rb + g0;
-#pragma unroll
-      for (int r = 0; r < kMaxNbr; ++r) h.end[r] = (uint16_t)(sg[lane * kMaxNbr + r + 1] - g0);
-      h.pad[0] = h.pad[1] = h.pad[2] = 0;
-      a.hdr[i * a.nd + lane] = h;
-    }
+    // row index entry: start of the row, then the start of each delay group
+    uint8_t* ent = a.idx + i * a.idxw;
+    if (lane == 0) *(int64_t*)ent = rb;
+    for (int dd = lane; dd <= a.nd; dd += 64) ((uint16_t*)(ent + 8))[dd] = sg[dd * kSegPerDelay];
+    // dummy records (rank 15, weight 0) in the padding at the end of each group
+    for (int dd = 0; dd < a.nd; ++dd)
+      for (int32_t p = sg[dd * kSegPerDelay + kMaxNbr] + lane; p < sg[(dd + 1) * kSegPerDelay];
+           p += 64)
+        out[p] = kDummyRecord;
     for (int r = 0; r < nn; ++r) {
       const int32_t tc = a.col_nbr[g * kMaxNbr + r];
       const uint64_t thr = a.col_thr[g * kMaxNbr + r];
       const uint32_t tl0 = (uint32_t)(a.col_local[tc] * a.npc);
       // lane q holds the write cursor of segment (q, r)
-      int32_t cursor = lane < a.nd ? (int32_t)sg[lane * kMaxNbr + r] : 0;
+      int32_t cursor = lane < a.nd ? (int32_t)sg[lane * kSegPerDelay + r] : 0;
       for (int kb = 0; kb < a.npc; kb += 64) {
         const int k = kb + lane;
         int dd;
@@ -175,7 +190,7 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
           const double prod = sigma * z;
           const double w = mu + prod;
           const int16_t wq = (int16_t)__builtin_rint(w * 16384.0);
-          out[pos] = (uint32_t)(uint16_t)k | ((uint32_t)(uint16_t)wq << 16);
+          out[pos] = (uint32_t)k | ((uint32_t)r << 12) | ((uint32_t)(uint16_t)wq << 16);
         }
       }
     }
@@ -204,7 +219,9 @@ GenArgs gen_args(const sim& s, int64_t row0, int64_t rows) {
   a.seg = s.seg;
   a.row_base = s.row_base;
   a.syn = s.syn;
-  a.hdr = s.hdr;
+  a.idx = s.idx;
+  a.idxw = s.idxw;
+  a.deg = s.deg;
   return a;
 }
 

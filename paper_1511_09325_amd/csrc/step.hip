@@ -13,10 +13,11 @@
 //   delivery each synapse (delay d) of a spike at step u contributes at step u + d
 //
 // Two delivery strategies, bit-identical because the input is an integer sum:
-//   ARRIVAL  one workgroup per target column.  At step u it gathers, from the spike
-//            history of the 3x3 source columns, the (delay d, target column) segment of
-//            every row whose neuron spiked at u - d, accumulates into LDS with integer
-//            atomics, then updates its neurons -- one fused kernel, no ring in HBM.
+//   ARRIVAL  one workgroup per tile of up to 4x4 target columns.  At step u it gathers,
+//            from the spike history of every column with synapses into the tile, the delay
+//            group (i, d) of every neuron i that spiked at u - d, keeps the synapses whose
+//            target lies in the tile, accumulates them in LDS with integer atomics, then
+//            updates the tile's neurons -- one fused kernel, no ring in HBM.
 //   PUSH     update kernel reading a delay ring ring[u % DH][j], then a delivery kernel
 //            that scatters each spiking row into ring[(u + d) % DH][target] with
 //            device-scope integer atomics.
@@ -25,12 +26,18 @@
 namespace dpsnn {
 namespace {
 
-constexpr int kMaxItems = kMaxDelay * kMaxNbr;
+constexpr int kMaxItems = kMaxTileSrc * kMaxDelay;
+constexpr int kLanesPerGroup = 16;    // lanes streaming one group, 4 synapses each
+constexpr int kGroupsInFlight = 4;    // groups per lane set per round
+constexpr int kPiecesInFlight = 4;    // 16-byte loads per lane in flight
+constexpr int kUpd = 2;               // 64-neuron chunks per wave per round of the update
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Workgroup-wide exclusive scan: wave scans in registers, then the wave totals are scanned
+// by the first wave (no per-wave branches, so no per-wave masks are kept live).
 template <int BLOCK>
 __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t* total, int32_t* wsum) {
   constexpr int NW = BLOCK / 64;
@@ -43,15 +50,21 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t* total, in
   }
   if (lane == 63) wsum[wave] = incl;
   __syncthreads();
-  int32_t before = 0, all = 0;
+  if (wave == 0) {
+    const int32_t v = lane < NW ? wsum[lane] : 0;
+    int32_t c = v;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const int32_t v = wsum[w];
-    if (w < wave) before += v;
-    all += v;
+    for (int off = 1; off < NW; off <<= 1) {
+      const int32_t t = __shfl_up(c, off);
+      if (lane >= off) c += t;
+    }
+    if (lane < NW) wsum[NW + lane] = c - v;  // exclusive prefix of the wave totals
+    if (lane == NW - 1) wsum[2 * NW] = c;
   }
   __syncthreads();
-  *total = all;
+  const int32_t before = wsum[NW + wave];
+  *total = wsum[2 * NW];
+  __syncthreads();
   return before + incl - x;
 }
 
@@ -64,9 +77,10 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
   for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
   if (lane == 0) red[wave] = x;
   __syncthreads();
-  unsigned long long all = 0;
+  unsigned long long all = lane < NW ? red[lane] : 0ull;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) all += red[w];
+  for (int off = 32; off > 0; off >>= 1) all += __shfl_down(all, off);
+  all = __shfl(all, 0);
   __syncthreads();
   return all;
 }
@@ -82,214 +96,125 @@ __device__ __forceinline__ int32_t poisson_count(const uint64_t* tab, uint32_t x
   return lo;
 }
 
-// ---- the neuron update, shared by both strategies ------------------------------------------
+// One neuron's step from its state and input; returns the spike flag.
+__device__ __forceinline__ bool neuron_step(const StepArgs& a, int64_t j, int64_t u,
+                                            int32_t rec_in, int32_t n_ext, float vprev,
+                                            float caprev, int32_t rf) {
+  const uint32_t asum = (uint32_t)rec_in + (uint32_t)n_ext * (uint32_t)a.k.jfx;
+  const float cur = (float)(int32_t)asum * 0x1p-16f;
+  float vnew, vt = 0.0f;
+  bool spike = false, refr = false;
+  if (rf > 0) {
+    refr = true;
+    rf -= 1;
+    vnew = a.k.vreset;
+  } else {
+    const float leak = a.k.pm * vprev;
+    const float ahp = a.k.gam * caprev;
+    const float drop = leak - ahp;
+    vt = drop + cur;
+    if (vt >= a.k.theta) {
+      spike = true;
+      vnew = a.k.vreset;
+      rf = a.k.tref;
+    } else {
+      vnew = vt;
+    }
+  }
+  const float decayed = a.k.pc * caprev;
+  const float canew = decayed + (spike ? a.k.alpha : 0.0f);
+  a.v[j] = vnew;
+  a.ca[j] = canew;
+  a.ref[j] = (uint8_t)rf;
+  if (a.rec_vprev) {
+    const int64_t o = (u - a.rec_base) * (int64_t)a.n_cols * a.npc + j;
+    a.rec_vprev[o] = vprev;
+    a.rec_caprev[o] = caprev;
+    a.rec_vt[o] = vt;
+    a.rec_flags[o] = (uint8_t)((spike ? 1 : 0) | (refr ? 2 : 0));
+  }
+  return spike;
+}
+
+__device__ __forceinline__ int32_t external_count(const StepArgs& a, int32_t g, int k, int64_t u,
+                                                  const uint64_t* ptab, uint32_t key0,
+                                                  uint32_t key1) {
+  const Rand4 x = philox10((uint32_t)(a.col_local[g] * a.npc + k), (uint32_t)u, 0u, kStreamExt,
+                           key0, key1);
+  return poisson_count(ptab, x.x);
+}
+
+// ---- ARRIVAL: tiles of target columns ---------------------------------------------------
 //
-// Each thread owns the neurons k = m * BLOCK + tid (m < NPT) of the column.  Their state
-// and external Poisson counts are fetched into registers first (prefetch_neurons), so that
-// the loads and the Philox draws overlap with the gather of the delivered input; then
-// finish_update applies the step and compacts the spikes in ascending order with one
-// workgroup barrier (wave ballots, counts per (m, wave) in LDS).
-template <int NPT>
-struct NeuronRegs {
-  float v[NPT];
-  float ca[NPT];
-  int32_t ref[NPT];
-  int32_t next[NPT];
-};
-
-template <int BLOCK, int NPT>
-__device__ __forceinline__ void prefetch_neurons(const StepArgs& a, int32_t g, int64_t u,
-                                                 const uint64_t* ptab, NeuronRegs<NPT>& r) {
-  const int32_t net = a.col_net[g];
-  const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
-  const uint32_t nl0 = (uint32_t)(a.col_local[g] * a.npc);
-#pragma unroll
-  for (int m = 0; m < NPT; ++m) {
-    const int k = m * BLOCK + (int)threadIdx.x;
-    r.v[m] = 0.0f;
-    r.ca[m] = 0.0f;
-    r.ref[m] = 0;
-    r.next[m] = 0;
-    if (k < a.npc) {
-      const int64_t j = (int64_t)g * a.npc + k;
-      r.v[m] = a.v[j];
-      r.ca[m] = a.ca[j];
-      r.ref[m] = a.ref[j];
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < NPT; ++m) {
-    const int k = m * BLOCK + (int)threadIdx.x;
-    if (k < a.npc) {
-      const Rand4 x = philox10(nl0 + (uint32_t)k, (uint32_t)u, 0u, kStreamExt, key0, key1);
-      r.next[m] = poisson_count(ptab, x.x);
-    }
-  }
-}
-
-// in_of(k) returns the recurrent int32 input of local neuron k at step u.  extra is added
-// to the synapse counter of the network (the gather's streamed synapses).
-template <int BLOCK, int NPT, typename InputFn>
-__device__ __forceinline__ void finish_update(const StepArgs& a, int32_t g, int64_t u,
-                                              NeuronRegs<NPT>& r, InputFn in_of, int32_t* wcnt,
-                                              unsigned long long* red,
-                                              unsigned long long extra) {
+// Work list of a tile at step u: items (source column si, delay index dd), the spike list
+// of tile_src[si] at step u - d_min - dd.  Every spike i of an item is one group: the
+// contiguous synapses of (i, delay).  The groups are taken in chunks of kChunk: first each
+// thread locates groups (binary search over the item prefix, one spike id, one row-index
+// entry) into LDS, then sets of kLanesPerGroup lanes stream kGroupsInFlight groups at a
+// time in 16-byte words, keeping the synapses whose target column is in the tile (the
+// record's rank, looked up in the source's slot word) and adding them to the tile's LDS
+// accumulators with integer atomics.  Then the tile's neurons are updated in 64-neuron
+// chunks and the spikes compacted per column, in ascending order.
+template <int BLOCK, bool TRAIN>
+__global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u, int32_t maxc,
+                                                     int32_t chunk) {
   constexpr int NW = BLOCK / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned long long lt = lanemask_lt(lane);
-  const int32_t net = a.col_net[g];
-  const int32_t slot = (int32_t)(u % a.dh);
-  uint16_t* out_ids = a.hist_ids + ((int64_t)slot * a.n_cols + g) * a.npc;
-  unsigned long long my_ext = 0, my_rec = 0;
-  bool sp[NPT];
-#pragma unroll
-  for (int m = 0; m < NPT; ++m) {
-    const int k = m * BLOCK + (int)threadIdx.x;
-    sp[m] = false;
-    if (k < a.npc) {
-      const int64_t j = (int64_t)g * a.npc + k;
-      const uint32_t asum = (uint32_t)in_of(k) + (uint32_t)r.next[m] * (uint32_t)a.k.jfx;
-      const float cur = (float)(int32_t)asum * 0x1p-16f;
-      const float vprev = r.v[m];
-      const float caprev = r.ca[m];
-      int32_t rf = r.ref[m];
-      float vnew, vt = 0.0f;
-      bool refr = false;
-      if (rf > 0) {
-        refr = true;
-        rf -= 1;
-        vnew = a.k.vreset;
-      } else {
-        const float leak = a.k.pm * vprev;
-        const float ahp = a.k.gam * caprev;
-        const float drop = leak - ahp;
-        vt = drop + cur;
-        if (vt >= a.k.theta) {
-          sp[m] = true;
-          vnew = a.k.vreset;
-          rf = a.k.tref;
-        } else {
-          vnew = vt;
-        }
-      }
-      const float decayed = a.k.pc * caprev;
-      const float canew = decayed + (sp[m] ? a.k.alpha : 0.0f);
-      a.v[j] = vnew;
-      a.ca[j] = canew;
-      a.ref[j] = (uint8_t)rf;
-      my_ext += (unsigned long long)r.next[m];
-      if (sp[m]) my_rec += (unsigned long long)(a.row_base[j + 1] - a.row_base[j]);
-      if (a.rec_vprev) {
-        const int64_t o = (u - a.rec_base) * (int64_t)a.n_cols * a.npc + j;
-        a.rec_vprev[o] = vprev;
-        a.rec_caprev[o] = caprev;
-        a.rec_vt[o] = vt;
-        a.rec_flags[o] = (uint8_t)((sp[m] ? 1 : 0) | (refr ? 2 : 0));
-      }
-    }
-  }
-  unsigned long long bal[NPT];
-#pragma unroll
-  for (int m = 0; m < NPT; ++m) {
-    bal[m] = __ballot(sp[m]);
-    if (lane == 0) wcnt[m * NW + wave] = __popcll(bal[m]);
-  }
-  __syncthreads();
-  int32_t running = 0;
-#pragma unroll
-  for (int m = 0; m < NPT; ++m) {
-    int32_t before = 0, tot = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const int32_t c = wcnt[m * NW + w];
-      if (w < wave) before += c;
-      tot += c;
-    }
-    if (sp[m]) out_ids[running + before + __popcll(bal[m] & lt)] = (uint16_t)(m * BLOCK + threadIdx.x);
-    running += tot;
-  }
-  const unsigned long long ext_all = block_sum_u64<BLOCK>(my_ext, red);
-  const unsigned long long rec_all = block_sum_u64<BLOCK>(my_rec, red);
-  const unsigned long long str_all = block_sum_u64<BLOCK>(extra, red);
-  if (threadIdx.x == 0) {
-    a.hist_cnt[(int64_t)slot * a.n_cols + g] = running;
-    atomicAdd(&a.net_cnt[4 * net + 0], (unsigned long long)running);
-    atomicAdd(&a.net_cnt[4 * net + 1], rec_all);
-    atomicAdd(&a.net_cnt[4 * net + 2], ext_all);
-    if (str_all) atomicAdd(&a.net_cnt[4 * net + 3], str_all);
-  }
-}
-
-template <int BLOCK>
-__device__ __forceinline__ void load_ptab(const StepArgs& a, int32_t g, uint64_t* ptab) {
-  const int32_t net = a.col_net[g];
-  for (int q = threadIdx.x; q < kPoissonEntries; q += BLOCK)
-    ptab[q] = a.net_ptab[(int64_t)net * kPoissonEntries + q];
-}
-
-// ---- ARRIVAL: gather + update, one workgroup per target column ------------------------
-//
-// Work list of column g at step u: "items" (source column r, delay index dd), each the
-// spike list of source column col_nbr[g][r] at step u - d_min - dd; every spike i of an
-// item contributes one segment: the synapses of group (i, dd) that target column g.  Items
-// of the own column come first (long segments), then the 8 neighbours (short ones), so
-// that neighbouring segments have similar lengths.  Each wave takes batches of 64
-// consecutive segments: lane l locates segment l of the batch (binary search over the item
-// prefix, one spike id, one 32-byte group header) and then walks it in 16-byte pieces
-// (four synapses per load, kPiecesInFlight loads in flight), adding each synapse's
-// efficacy into the column's LDS accumulator with integer atomics.
-constexpr int kPiecesInFlight = 4;
-
-template <bool TRAIN>
-__device__ __forceinline__ void add_piece(const StepArgs& a, int32_t* acc, const uint32_t* w,
-                                          const int32_t* v, int32_t valid) {
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-    if (e < valid) atomicAdd(&acc[w[e] & 0xffffu], TRAIN ? v[e] : (((int32_t)w[e]) >> 16) * 4);
-}
-
-template <int BLOCK, int NPT, bool TRAIN>
-__global__ __launch_bounds__(BLOCK) void k_step_arrival(StepArgs a, int64_t u) {
-  constexpr int NW = BLOCK / 64;
-  extern __shared__ int32_t acc[];
+  constexpr int NSET = BLOCK / kLanesPerGroup;
+  constexpr int GIF = kGroupsInFlight;
+  extern __shared__ __align__(16) unsigned char lds[];
   __shared__ uint64_t ptab[kPoissonEntries];
   __shared__ int32_t it_pref[kMaxItems + 1];
-  __shared__ int32_t it_hist[kMaxItems];
-  __shared__ int32_t it_nbase[kMaxItems];
-  __shared__ int32_t it_hdr[kMaxItems];
-  __shared__ int32_t it_rank[kMaxItems];
-  __shared__ int32_t wsum[NPT * NW];
+  __shared__ int32_t s_src[kMaxTileSrc];
+  __shared__ int32_t s_base[kMaxTileSrc * 16];  // per (source, rank): slot * npc, or -1
+  __shared__ int32_t s_col[kMaxTileCols];
+  __shared__ int32_t wsum[2 * NW + 1];
   __shared__ unsigned long long red[NW];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  for (int32_t b = blockIdx.x; b < a.grid; b += gridDim.x) {
-    const int32_t g = a.col_order[b];
-    if (g < 0) continue;
-    load_ptab<BLOCK>(a, g, ptab);
-    for (int k = tid; k < a.npc; k += BLOCK) acc[k] = 0;
-    const int nn = a.col_nn[g];
-    int own = 0;  // rank of the own column in g's ascending neighbour list
-    for (int r = 0; r < nn; ++r)
-      if (a.col_nbr[g * kMaxNbr + r] == g) own = r;
-    const int n_items = nn * a.nd;
-    // 1. items and their spike counts; item = ro * nd + dd, ro = 0 the own column
+  const int npc = a.npc;
+  const int nch = (npc + 63) >> 6;
+  // dynamic LDS: acc[maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch] | group starts,
+  // lengths and sources of one chunk
+  int32_t* acc = (int32_t*)lds;
+  size_t off = ((size_t)maxc * npc * 4 + 15) & ~(size_t)15;
+  unsigned long long* smask = (unsigned long long*)(lds + off);
+  off += (size_t)maxc * nch * 8;
+  int32_t* scnt = (int32_t*)(lds + off);
+  off += ((size_t)maxc * nch * 4 + 15) & ~(size_t)15;
+  int64_t* g_start = (int64_t*)(lds + off);
+  off += (size_t)chunk * 8;
+  int32_t* g_len = (int32_t*)(lds + off);
+  off += (size_t)chunk * 4;
+  uint8_t* g_src = (uint8_t*)(lds + off);
+
+  for (int32_t b = blockIdx.x; b < a.grid_tiles; b += gridDim.x) {
+    const int32_t tile = a.tile_order[b];
+    if (tile < 0) continue;
+    const int T = a.tile_ncols[tile];
+    const int ns = a.tile_nsrc[tile];
+    if (tid < kMaxTileCols) s_col[tid] = a.tile_cols[tile * kMaxTileCols + tid];
+    if (tid < kMaxTileSrc) s_src[tid] = a.tile_src[tile * kMaxTileSrc + tid];
+    for (int e = tid; e < kMaxTileSrc * 16; e += BLOCK) {
+      const int si = e >> 4, r = e & 15;
+      const uint32_t slot =
+          r < kMaxNbr ? (uint32_t)(a.tile_slots[tile * kMaxTileSrc + si] >> (5 * r)) & 31u : kNoSlot;
+      s_base[e] = slot == (uint32_t)kNoSlot ? -1 : (int32_t)slot * npc;
+    }
+    const int32_t net = a.col_net[a.tile_cols[tile * kMaxTileCols]];
+    for (int q = tid; q < kPoissonEntries; q += BLOCK)
+      ptab[q] = a.net_ptab[(int64_t)net * kPoissonEntries + q];
+    for (int e = tid; e < T * npc; e += BLOCK) acc[e] = 0;
+    __syncthreads();
+    // 1. items and their spike counts
+    const int n_items = ns * a.nd;
     int32_t carry = 0;
-    for (int b = 0; b < n_items; b += BLOCK) {
-      const int it = b + tid;
+    for (int bb = 0; bb < n_items; bb += BLOCK) {
+      const int it = bb + tid;
       int32_t cnt = 0;
       if (it < n_items) {
-        const int ro = it / a.nd, dd = it - ro * a.nd;
-        const int r = ro == 0 ? own : (ro <= own ? ro - 1 : ro);
+        const int si = it / a.nd, dd = it - si * a.nd;
         const int64_t t = u - (a.d_min + dd);
-        if (t >= 0) {
-          const int32_t sc = a.col_nbr[g * kMaxNbr + r];
-          const int32_t hb = (int32_t)(t % a.dh) * a.n_cols + sc;
-          cnt = a.hist_cnt[hb];
-          it_hist[it] = hb * a.npc;
-          it_nbase[it] = sc * a.npc;
-          it_hdr[it] = dd;
-          it_rank[it] = a.col_rank[g * kMaxNbr + r];
-        }
+        if (t >= 0) cnt = a.hist_cnt[(int64_t)(t % a.dh) * a.n_cols + s_src[si]];
       }
       int32_t tot;
       const int32_t ex = block_excl_scan<BLOCK>(cnt, &tot, wsum);
@@ -297,95 +222,244 @@ __global__ __launch_bounds__(BLOCK) void k_step_arrival(StepArgs a, int64_t u) {
       carry += tot;
     }
     if (tid == 0) it_pref[n_items] = carry;
-    __syncthreads();  // items, the Poisson table and the zeroed accumulator are ready
-    NeuronRegs<NPT> nr;
-    prefetch_neurons<BLOCK, NPT>(a, g, u, ptab, nr);
+    __syncthreads();
     const int32_t total = carry;
     unsigned long long streamed = 0;
-    // 2. gather: waves take batches of 64 segments
-    for (int32_t b0 = wave * 64; b0 < total; b0 += NW * 64) {
-      const int32_t q = b0 + lane;
-      int64_t st = 0;
-      int32_t ln = 0;
-      if (q < total) {
+    // 2. gather, `chunk` groups at a time
+    uint32_t delivered = 0;
+    for (int32_t base = 0; base < total; base += chunk) {
+      const int32_t n = min(chunk, total - base);
+#pragma unroll 2
+      for (int32_t q = tid; q < n; q += BLOCK) {
+        const int32_t qq = base + q;
         int lo = 0, hi = n_items;
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
-          if (it_pref[mid] <= q) lo = mid;
+          if (it_pref[mid] <= qq) lo = mid;
           else hi = mid;
         }
-        const int32_t ksrc = a.hist_ids[it_hist[lo] + (q - it_pref[lo])];
-        const int64_t i = (int64_t)it_nbase[lo] + ksrc;
-        const GroupHdr* h = a.hdr + i * a.nd + it_hdr[lo];
-        const int r = it_rank[lo];
-        const int32_t e1 = h->end[r];
-        const int32_t e0 = r ? (int32_t)h->end[r - 1] : 0;
-        st = h->start + e0;
-        ln = e1 - e0;
+        const int si = lo / a.nd, dd = lo - si * a.nd;
+        const int64_t t = u - (a.d_min + dd);
+        const int32_t s = s_src[si];
+        const int64_t hb = (int64_t)(t % a.dh) * a.n_cols + s;
+        const int32_t k = a.hist_ids[hb * npc + (qq - it_pref[lo])];
+        const int64_t i = (int64_t)s * npc + k;
+        const uint8_t* ent = a.idx + i * a.idxw;
+        const uint16_t* go = (const uint16_t*)(ent + 8);
+        const int32_t g0 = go[dd], g1 = go[dd + 1];
+        g_start[q] = *(const int64_t*)ent + g0;
+        g_len[q] = g1 - g0;
+        g_src[q] = (uint8_t)si;
       }
-      streamed += (unsigned long long)ln;
-      for (int32_t off = 0; __ballot(off < ln) != 0; off += 4 * kPiecesInFlight) {
-        uint32_t w[kPiecesInFlight][4];
-        int32_t v[kPiecesInFlight][4];
+      __syncthreads();
+      // stream: a set of kLanesPerGroup lanes walks the concatenated 16-byte pieces of GIF
+      // groups; every piece lies inside one group (groups are padded to 4 records)
+      const int set = tid / kLanesPerGroup, gl = tid % kLanesPerGroup;
+      for (int32_t r0 = set; r0 < n; r0 += NSET * GIF) {
+        int64_t st[GIF];
+        int32_t pref[GIF + 1];
+        int32_t sb[GIF];
+        pref[0] = 0;
 #pragma unroll
-        for (int p = 0; p < kPiecesInFlight; ++p) {
-          const int32_t o = off + 4 * p;
-          if (o < ln) {
-            __builtin_memcpy(&w[p][0], a.syn + st + o, 16);
-            if (TRAIN) __builtin_memcpy(&v[p][0], a.wfx + st + o, 16);
+        for (int m = 0; m < GIF; ++m) {
+          const int32_t gi = r0 + m * NSET;
+          const int32_t ln = gi < n ? g_len[gi] : 0;
+          st[m] = gi < n ? g_start[gi] : 0;
+          sb[m] = gi < n ? (int32_t)g_src[gi] * 16 : 0;
+          pref[m + 1] = pref[m] + (ln >> 2);
+          if (gl == 0) streamed += (unsigned long long)ln;
+        }
+        const int32_t npieces = pref[GIF];
+        for (int32_t p0 = gl; p0 < npieces; p0 += kLanesPerGroup * kPiecesInFlight) {
+          uint32_t w[kPiecesInFlight][4];
+          int32_t v[kPiecesInFlight][4];
+          int32_t base[kPiecesInFlight];
+#pragma unroll
+          for (int q = 0; q < kPiecesInFlight; ++q) {
+            const int32_t p = p0 + q * kLanesPerGroup;
+            base[q] = -1;
+            if (p < npieces) {
+              int m = 0;
+#pragma unroll
+              for (int z = 1; z < GIF; ++z) m += (p >= pref[z]) ? 1 : 0;
+              int64_t s0 = st[0];
+              int32_t pr = pref[0], b0 = sb[0];
+#pragma unroll
+              for (int z = 1; z < GIF; ++z)
+                if (m == z) { s0 = st[z]; pr = pref[z]; b0 = sb[z]; }
+              const int64_t addr = s0 + 4 * (int64_t)(p - pr);
+              base[q] = b0;
+              *(uint4*)&w[q][0] = *(const uint4*)(a.syn + addr);
+              if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(a.wfx + addr);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < kPiecesInFlight; ++q) {
+            if (base[q] >= 0) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const uint32_t x = w[q][e];
+                const int32_t sbase = s_base[base[q] + (int)rec_rank(x)];
+                if (sbase >= 0) {
+                  atomicAdd(&acc[sbase + (int)rec_k(x)], TRAIN ? v[q][e] : rec_w32(x));
+                  delivered += 1;
+                }
+              }
+            }
           }
         }
+      }
+      __syncthreads();
+    }
+    // 3. update in 64-neuron chunks: chunk c is column c / nch, neurons (c % nch) * 64 + lane
+    const int nchunks = T * nch;
+    const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
+    unsigned long long my_ext = 0, my_rec = 0;
+    for (int c0 = wave * kUpd; c0 < nchunks; c0 += NW * kUpd) {
+      float vv[kUpd], cc[kUpd];
+      int32_t rr[kUpd], nx[kUpd];
+      bool ok[kUpd];
 #pragma unroll
-        for (int p = 0; p < kPiecesInFlight; ++p) {
-          const int32_t o = off + 4 * p;
-          if (o < ln) add_piece<TRAIN>(a, acc, w[p], v[p], ln - o);
+      for (int m = 0; m < kUpd; ++m) {
+        const int c = c0 + m;
+        ok[m] = false;
+        vv[m] = 0.0f;
+        cc[m] = 0.0f;
+        rr[m] = 0;
+        if (c < nchunks) {
+          const int col = c / nch, k = (c - col * nch) * 64 + lane;
+          if (k < npc) {
+            ok[m] = true;
+            const int64_t j = (int64_t)s_col[col] * npc + k;
+            vv[m] = a.v[j];
+            cc[m] = a.ca[j];
+            rr[m] = a.ref[j];
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kUpd; ++m) {
+        const int c = c0 + m;
+        nx[m] = 0;
+        if (ok[m]) {
+          const int col = c / nch, k = (c - col * nch) * 64 + lane;
+          nx[m] = external_count(a, s_col[col], k, u, ptab, key0, key1);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kUpd; ++m) {
+        const int c = c0 + m;
+        if (c < nchunks) {
+          bool sp = false;
+          if (ok[m]) {
+            const int col = c / nch, k = (c - col * nch) * 64 + lane;
+            const int64_t j = (int64_t)s_col[col] * npc + k;
+            sp = neuron_step(a, j, u, acc[col * npc + k], nx[m], vv[m], cc[m], rr[m]);
+            my_ext += (unsigned long long)nx[m];
+            if (sp) my_rec += (unsigned long long)a.deg[j];
+          }
+          const unsigned long long bal = __ballot(sp);
+          if (lane == 0) {
+            smask[c] = bal;
+            scnt[c] = __popcll(bal);
+          }
         }
       }
     }
-    __syncthreads();  // all arrivals accumulated
-    // 3. neuron update + compaction
-    finish_update<BLOCK, NPT>(a, g, u, nr, [&](int k) { return acc[k]; }, wsum, red, streamed);
+    __syncthreads();
+    // 4. compaction: ascending ids of each column into the history slot of step u
+    const int32_t slot_u = (int32_t)(u % a.dh);
+    const unsigned long long lt = lanemask_lt(lane);
+    for (int c = wave; c < nchunks; c += NW) {
+      const int col = c / nch, first = col * nch;
+      int32_t before = 0;
+      for (int q = first; q < c; ++q) before += scnt[q];
+      const unsigned long long m = smask[c];
+      if ((m >> lane) & 1ull) {
+        uint16_t* out = a.hist_ids + ((int64_t)slot_u * a.n_cols + s_col[col]) * npc;
+        out[before + __popcll(m & lt)] = (uint16_t)((c - first) * 64 + lane);
+      }
+    }
+    unsigned long long my_spk = 0;
+    if (tid < T) {
+      int32_t tot = 0;
+      for (int q = 0; q < nch; ++q) tot += scnt[tid * nch + q];
+      a.hist_cnt[(int64_t)slot_u * a.n_cols + s_col[tid]] = tot;
+      my_spk = (unsigned long long)tot;
+    }
+    const unsigned long long spk_all = block_sum_u64<BLOCK>(my_spk, red);
+    const unsigned long long ext_all = block_sum_u64<BLOCK>(my_ext, red);
+    const unsigned long long rec_all = block_sum_u64<BLOCK>(my_rec, red);
+    const unsigned long long str_all = block_sum_u64<BLOCK>(streamed, red);
+    const unsigned long long del_all = block_sum_u64<BLOCK>((unsigned long long)delivered, red);
+    if (tid == 0) {
+      atomicAdd(&a.net_cnt[kCounters * net + 0], spk_all);
+      atomicAdd(&a.net_cnt[kCounters * net + 1], rec_all);
+      atomicAdd(&a.net_cnt[kCounters * net + 2], ext_all);
+      if (str_all) atomicAdd(&a.net_cnt[kCounters * net + 3], str_all);
+      if (del_all) atomicAdd(&a.net_cnt[kCounters * net + 4], del_all);
+    }
     __syncthreads();
   }
 }
 
-// ---- PUSH: update from the ring, then scatter ----------------------------------------------
-template <int BLOCK, int NPT>
+// ---- PUSH: update from the ring, then scatter ------------------------------------------------
+template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u) {
   constexpr int NW = BLOCK / 64;
   __shared__ uint64_t ptab[kPoissonEntries];
-  __shared__ int32_t wsum[NPT * NW];
+  __shared__ int32_t wcnt[NW];
   __shared__ unsigned long long red[NW];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const unsigned long long lt = lanemask_lt(lane);
   const int64_t nall = (int64_t)a.n_cols * a.npc;
-  int32_t* slot = a.ring + (u % a.dh) * nall;
-  for (int32_t b = blockIdx.x; b < a.grid; b += gridDim.x) {
+  int32_t* in = a.ring + (u % a.dh) * nall;
+  const int32_t slot_u = (int32_t)(u % a.dh);
+  for (int32_t b = blockIdx.x; b < a.grid_cols; b += gridDim.x) {
     const int32_t g = a.col_order[b];
     if (g < 0) continue;
-    load_ptab<BLOCK>(a, g, ptab);
+    const int32_t net = a.col_net[g];
+    for (int q = threadIdx.x; q < kPoissonEntries; q += BLOCK)
+      ptab[q] = a.net_ptab[(int64_t)net * kPoissonEntries + q];
     __syncthreads();
-    NeuronRegs<NPT> nr;
-    prefetch_neurons<BLOCK, NPT>(a, g, u, ptab, nr);
-    int32_t* in = slot + (int64_t)g * a.npc;
-    finish_update<BLOCK, NPT>(a, g, u, nr, [&](int k) {
-      const int32_t x = in[k];
-      in[k] = 0;
-      return x;
-    }, wsum, red, 0ull);
+    const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
+    uint16_t* out = a.hist_ids + ((int64_t)slot_u * a.n_cols + g) * a.npc;
+    int32_t running = 0;
+    unsigned long long my_ext = 0, my_rec = 0;
+    for (int k0 = 0; k0 < a.npc; k0 += BLOCK) {
+      const int k = k0 + (int)threadIdx.x;
+      bool sp = false;
+      if (k < a.npc) {
+        const int64_t j = (int64_t)g * a.npc + k;
+        const int32_t x = in[j];
+        in[j] = 0;
+        const int32_t nx = external_count(a, g, k, u, ptab, key0, key1);
+        sp = neuron_step(a, j, u, x, nx, a.v[j], a.ca[j], a.ref[j]);
+        my_ext += (unsigned long long)nx;
+        if (sp) my_rec += (unsigned long long)a.deg[j];
+      }
+      const unsigned long long m = __ballot(sp);
+      if (lane == 0) wcnt[wave] = __popcll(m);
+      __syncthreads();
+      int32_t before = 0, tot = 0;
+      for (int w = 0; w < NW; ++w) {
+        if (w < wave) before += wcnt[w];
+        tot += wcnt[w];
+      }
+      if (sp) out[running + before + __popcll(m & lt)] = (uint16_t)k;
+      running += tot;
+      __syncthreads();
+    }
+    const unsigned long long ext_all = block_sum_u64<BLOCK>(my_ext, red);
+    const unsigned long long rec_all = block_sum_u64<BLOCK>(my_rec, red);
+    if (threadIdx.x == 0) {
+      a.hist_cnt[(int64_t)slot_u * a.n_cols + g] = running;
+      atomicAdd(&a.net_cnt[kCounters * net + 0], (unsigned long long)running);
+      atomicAdd(&a.net_cnt[kCounters * net + 1], rec_all);
+      atomicAdd(&a.net_cnt[kCounters * net + 2], ext_all);
+    }
     __syncthreads();
   }
-}
-
-__device__ __forceinline__ int32_t syn_value(const StepArgs& a, uint32_t w, int64_t addr,
-                                             bool train) {
-  return train ? a.wfx[addr] : (((int32_t)w) >> 16) * 4;
-}
-
-// Segment (target-column rank) of position f inside a group.
-__device__ __forceinline__ int rank_in_group(const GroupHdr& h, int32_t f) {
-  int r = 0;
-#pragma unroll
-  for (int q = 0; q < kMaxNbr - 1; ++q) r += ((int32_t)h.end[q] <= f) ? 1 : 0;
-  return r;
 }
 
 template <int BLOCK, bool TRAIN>
@@ -399,21 +473,20 @@ __global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u) {
     const uint16_t* ids = a.hist_ids + ((int64_t)uslot * a.n_cols + g) * a.npc;
     for (int32_t q = wave; q < ns; q += NW) {
       const int64_t i = (int64_t)g * a.npc + ids[q];
-      unsigned long long pushed = 0;
+      const int64_t st = idx_start(a, i);
+      const uint16_t* go = idx_goff(a, i);
+      const int32_t len = a.deg[i];
+      if (lane == 0 && len) atomicAdd(&a.net_cnt[kCounters * a.col_net[g] + 3], (unsigned long long)len);
       for (int dd = 0; dd < a.nd; ++dd) {
-        const GroupHdr h = a.hdr[i * a.nd + dd];
-        const int32_t len = h.end[kMaxNbr - 1];
         const int64_t slot = (u + a.d_min + dd) % a.dh;
-        pushed += (unsigned long long)len;
-        for (int32_t f = lane; f < len; f += 64) {
-          const int r = rank_in_group(h, f);
-          const int32_t tc = a.col_nbr[g * kMaxNbr + r];
-          const uint32_t w = a.syn[h.start + f];
-          atomicAdd(&a.ring[slot * nall + (int64_t)tc * a.npc + (w & 0xffffu)],
-                    syn_value(a, w, h.start + f, TRAIN));
+        for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+          const uint32_t w = a.syn[st + f];
+          if (rec_rank(w) == (uint32_t)kDummyRank) continue;
+          const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+          atomicAdd(&a.ring[slot * nall + (int64_t)tc * a.npc + rec_k(w)],
+                    TRAIN ? a.wfx[st + f] : rec_w32(w));
         }
       }
-      if (lane == 0 && pushed) atomicAdd(&a.net_cnt[4 * a.col_net[g] + 3], pushed);
     }
   }
 }
@@ -435,41 +508,70 @@ __global__ void k_init_state(StepArgs a) {
   }
 }
 
-template <int BLOCK, int NPT>
-hipError_t launch_step_t(sim& s, int64_t u, int32_t delivery, int part) {
+template <int BLOCK>
+hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
   const StepArgs a = make_step_args(s);
   const bool train = s.wfx != nullptr;
-  const int grid = a.grid;
   if (delivery == DPSNN_DELIVERY_ARRIVAL) {
     if (part == 1) return hipSuccess;
-    const size_t lds = sizeof(int32_t) * (size_t)s.npc;
+    const size_t lds = tile_lds_bytes(s);
+    // allow the dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup)
+    static bool attr_done[2] = {false, false};
+    if (!attr_done[train]) {
+      const void* fn = train ? (const void*)k_step_tile<BLOCK, true> : (const void*)k_step_tile<BLOCK, false>;
+      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)(kMaxLds - 16 * 1024));
+      if (e != hipSuccess) return e;
+      attr_done[train] = true;
+    }
     if (train)
-      hipLaunchKernelGGL((k_step_arrival<BLOCK, NPT, true>), dim3(grid), dim3(BLOCK), lds, s.stream, a, u);
+      hipLaunchKernelGGL((k_step_tile<BLOCK, true>), dim3(s.grid_tiles), dim3(BLOCK), lds,
+                         s.stream, a, u, s.tile_max_cols, tile_chunk(s));
     else
-      hipLaunchKernelGGL((k_step_arrival<BLOCK, NPT, false>), dim3(grid), dim3(BLOCK), lds, s.stream, a, u);
+      hipLaunchKernelGGL((k_step_tile<BLOCK, false>), dim3(s.grid_tiles), dim3(BLOCK), lds,
+                         s.stream, a, u, s.tile_max_cols, tile_chunk(s));
     return hipGetLastError();
   }
-  if (part != 1) hipLaunchKernelGGL((k_update_push<BLOCK, NPT>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
+  if (part != 1)
+    hipLaunchKernelGGL((k_update_push<BLOCK>), dim3(s.grid_cols), dim3(BLOCK), 0, s.stream, a, u);
   if (part != 0) {
     if (train)
-      hipLaunchKernelGGL((k_deliver_push<BLOCK, true>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
+      hipLaunchKernelGGL((k_deliver_push<BLOCK, true>), dim3(s.n_cols), dim3(BLOCK), 0, s.stream, a, u);
     else
-      hipLaunchKernelGGL((k_deliver_push<BLOCK, false>), dim3(grid), dim3(BLOCK), 0, s.stream, a, u);
+      hipLaunchKernelGGL((k_deliver_push<BLOCK, false>), dim3(s.n_cols), dim3(BLOCK), 0, s.stream, a, u);
   }
   return hipGetLastError();
 }
 
-template <int BLOCK>
-hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
-  const int npt = (s.npc + BLOCK - 1) / BLOCK;
-  if (npt <= 1) return launch_step_t<BLOCK, 1>(s, u, delivery, part);
-  if (npt <= 2) return launch_step_t<BLOCK, 2>(s, u, delivery, part);
-  if (npt <= 4) return launch_step_t<BLOCK, 4>(s, u, delivery, part);
-  if (npt <= 8) return launch_step_t<BLOCK, 8>(s, u, delivery, part);
-  return hipErrorInvalidValue;
+}  // namespace
+
+// LDS of the tile kernel: accumulators and spike masks for the largest tile, then the group
+// list of one gather pass, as long as the 160 KB allow (at most 4096 groups).
+static size_t tile_fixed_lds(const sim& s) {
+  const size_t nch = (size_t)(s.npc + 63) / 64;
+  size_t b = ((size_t)s.tile_max_cols * s.npc * 4 + 15) & ~(size_t)15;
+  b += (size_t)s.tile_max_cols * nch * 8;
+  b += ((size_t)s.tile_max_cols * nch * 4 + 15) & ~(size_t)15;
+  return b;
 }
 
-}  // namespace
+static size_t tile_static_bytes() {
+  return sizeof(uint64_t) * kPoissonEntries + sizeof(int32_t) * (kMaxItems + 1) +
+         (sizeof(int32_t) + sizeof(uint64_t)) * kMaxTileSrc + sizeof(int32_t) * kMaxTileCols +
+         (sizeof(int32_t) * 2 + 1 + sizeof(uint64_t)) * 16 + 64;
+}
+
+int32_t tile_chunk(const sim& s) {
+  const size_t used = tile_fixed_lds(s) + tile_static_bytes();
+  if (used + 13 * 256 > kMaxLds) return 0;
+  size_t c = (kMaxLds - used) / 13;
+  if (c > 4096) c = 4096;
+  return (int32_t)(c & ~(size_t)255);
+}
+
+size_t tile_lds_bytes(const sim& s) {
+  return tile_fixed_lds(s) + (size_t)tile_chunk(s) * (8 + 4 + 1);
+}
 
 StepArgs make_step_args(const sim& s) {
   StepArgs a{};
@@ -478,17 +580,25 @@ StepArgs make_step_args(const sim& s) {
   a.d_min = s.cfg.d_min;
   a.dh = s.dh;
   a.n_cols = s.n_cols;
+  a.idxw = s.idxw;
   a.col_net = s.col_net;
   a.col_local = s.col_local;
   a.col_nbr = s.col_nbr;
   a.col_nn = s.col_nn;
-  a.col_rank = s.col_rank;
-  a.col_order = s.xcd_order ? s.col_order : s.col_order_rm;
-  a.grid = s.xcd_order ? s.grid_xcd : s.n_cols;
+  a.col_order = s.col_order;
+  a.grid_cols = s.grid_cols;
   a.net_key = s.net_key;
   a.net_ptab = s.net_ptab;
+  a.tile_order = s.tile_order;
+  a.grid_tiles = s.grid_tiles;
+  a.tile_cols = s.tile_cols;
+  a.tile_ncols = s.tile_ncols;
+  a.tile_src = s.tile_src;
+  a.tile_nsrc = s.tile_nsrc;
+  a.tile_slots = s.tile_slots;
   a.row_base = s.row_base;
-  a.hdr = s.hdr;
+  a.deg = s.deg;
+  a.idx = s.idx;
   a.syn = s.syn;
   a.wfx = s.wfx;
   a.v = s.v;
@@ -498,6 +608,13 @@ StepArgs make_step_args(const sim& s) {
   a.hist_ids = s.hist_ids;
   a.ring = s.ring;
   a.net_cnt = s.net_cnt;
+  if (s.rec_on) {
+    a.rec_vprev = s.rec_vprev;
+    a.rec_caprev = s.rec_caprev;
+    a.rec_vt = s.rec_vt;
+    a.rec_flags = s.rec_flags;
+    a.rec_base = s.rec_base;
+  }
   a.k = s.nk;
   return a;
 }

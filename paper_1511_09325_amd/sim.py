@@ -26,8 +26,8 @@ def _stream_ptr(stream):
 
 
 def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, block: int = 0,
-                record_steps: int = 0, raster_capacity: int = 0, train_mode: bool = False,
-                ckpt_every: int = 50):
+                tile: tuple[int, int] = (0, 0), record_steps: int = 0, raster_capacity: int = 0,
+                train_mode: bool = False, ckpt_every: int = 50):
     """sim_config_t from one parameter dict, or a list of them (batched form: all share the
     column recipe of the first; grid shape, seed and external rate are per network)."""
     plist = params if isinstance(params, list) else [params]
@@ -47,6 +47,7 @@ def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, b
     c.n_nets = len(plist)
     c.nets = C.cast(nets, C.POINTER(L.SimNet))
     c.delivery, c.block = int(delivery), int(block)
+    c.tile_x, c.tile_y = int(tile[0]), int(tile[1])
     c.record_steps, c.raster_capacity = int(record_steps), int(raster_capacity)
     c.train_mode, c.ckpt_every = int(bool(train_mode)), int(ckpt_every)
     return c, nets
@@ -54,13 +55,14 @@ def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, b
 
 class Simulation:
     def __init__(self, params, *, delivery: int = L.DELIVERY_AUTO, block: int = 0,
-                 record_steps: int = 0, raster_capacity: int | None = None,
-                 train_mode: bool = False, ckpt_every: int = 50, stream=None):
+                 tile: tuple[int, int] = (0, 0), record_steps: int = 0,
+                 raster_capacity: int | None = None, train_mode: bool = False,
+                 ckpt_every: int = 50, stream=None):
         self.params = params if isinstance(params, list) else [params]
         if raster_capacity is None:
             n = sum(p["rows"] * p["cols"] * p["npc"] for p in self.params)
             raster_capacity = max(1, int(record_steps * n * 0.2)) if record_steps else 0
-        cfg, self._nets = make_config(params, delivery=delivery, block=block,
+        cfg, self._nets = make_config(params, delivery=delivery, block=block, tile=tile,
                                       record_steps=record_steps, raster_capacity=raster_capacity,
                                       train_mode=train_mode, ckpt_every=ckpt_every)
         self._cfg = cfg
@@ -127,7 +129,8 @@ class Simulation:
         s = L.SimStats()
         L.check(self.lib.sim_get_stats(self.h, net, C.byref(s)), self.h)
         return {"steps": s.steps, "spikes": s.spikes, "e_rec": s.events_recurrent,
-                "e_ext": s.events_external, "streamed": s.synapses_streamed}
+                "e_ext": s.events_external, "streamed": s.synapses_streamed,
+                "delivered": s.synapses_delivered}
 
     def state(self, net: int = 0, pend: bool = True) -> dict:
         n = self.net_neurons(net)
@@ -167,13 +170,21 @@ class Simulation:
     def restore(self, slot: int = 0):
         L.check(self.lib.sim_restore(self.h, slot), self.h)
 
-    def set_launch(self, delivery: int, block: int):
-        L.check(self.lib.sim_set_launch(self.h, int(delivery), int(block)), self.h)
+    def set_launch(self, delivery: int | None = None, block: int | None = None,
+                   tile: tuple[int, int] | None = None):
+        """Change the launch configuration; None keeps the current value."""
+        cur = self.get_launch()
+        lc = L.SimLaunch()
+        lc.delivery = cur["delivery"] if delivery is None else int(delivery)
+        lc.block = cur["block"] if block is None else int(block)
+        tx, ty = cur["tile"] if tile is None else tile
+        lc.tile_x, lc.tile_y = int(tx), int(ty)
+        L.check(self.lib.sim_set_launch(self.h, C.byref(lc)), self.h)
 
-    def get_launch(self):
-        d, b = C.c_int32(), C.c_int32()
-        L.check(self.lib.sim_get_launch(self.h, C.byref(d), C.byref(b)), self.h)
-        return d.value, b.value
+    def get_launch(self) -> dict:
+        lc = L.SimLaunch()
+        L.check(self.lib.sim_get_launch(self.h, C.byref(lc)), self.h)
+        return {"delivery": lc.delivery, "block": lc.block, "tile": (lc.tile_x, lc.tile_y)}
 
     def set_params(self, tau_m: float, g_ahp: float):
         L.check(self.lib.sim_set_params(self.h, float(tau_m), float(g_ahp)), self.h)

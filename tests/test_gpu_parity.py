@@ -65,12 +65,15 @@ def test_generator_bitwise_2x2_recipe():
     _check_network(sim, p)
 
 
-@pytest.mark.parametrize("delivery", [DELIVERY_ARRIVAL, DELIVERY_PUSH], ids=["arrival", "push"])
-@pytest.mark.parametrize("block", [64, 256, 1024])
-def test_tiny_run_bit_exact(delivery, block):
-    p = W.tiny(2, 3, npc=40, seed=11)
+@pytest.mark.parametrize("delivery,block,tile", [
+    (DELIVERY_ARRIVAL, 64, (1, 1)), (DELIVERY_ARRIVAL, 256, (2, 3)),
+    (DELIVERY_ARRIVAL, 1024, (4, 4)), (DELIVERY_ARRIVAL, 128, (3, 1)),
+    (DELIVERY_PUSH, 64, (0, 0)), (DELIVERY_PUSH, 1024, (0, 0)),
+], ids=["arr-64-1x1", "arr-256-2x3", "arr-1024-4x4", "arr-128-3x1", "push-64", "push-1024"])
+def test_tiny_run_bit_exact(delivery, block, tile):
+    p = W.tiny(5, 7, npc=40, seed=11)
     T = 300
-    sim = Simulation(p, delivery=delivery, block=block, record_steps=T)
+    sim = Simulation(p, delivery=delivery, block=block, tile=tile, record_steps=T)
     sim.step(T)
     ref = oracle.Sim(p)
     ref.step(T)
@@ -116,7 +119,7 @@ def test_save_restore_and_switching_delivery():
     sim.step(25)
     sim.set_launch(DELIVERY_PUSH, 512)     # ring rebuilt from the spike history
     sim.step(40)
-    sim.set_launch(DELIVERY_ARRIVAL, 64)
+    sim.set_launch(DELIVERY_ARRIVAL, 64, (1, 2))
     sim.step(T - 115)
     got = sim.read_spikes(0, 0, T)
     for u in range(T):
