@@ -86,6 +86,55 @@ def cpu_baseline(sample_steps: int = 1000):
             "sim_ms_per_wall_s": sample_steps / dt}
 
 
+def _timed_run(sim, steps, torch):
+    """Run `steps` steps on the simulation's stream; returns (seconds, events, spikes)."""
+    s0 = [sim.stats(n) for n in range(sim.n_nets)]
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sim.sync()
+    s1 = [sim.stats(n) for n in range(sim.n_nets)]
+    ev = sum((b["e_rec"] - a["e_rec"]) + (b["e_ext"] - a["e_ext"]) for a, b in zip(s0, s1))
+    spk = sum(b["spikes"] - a["spikes"] for a, b in zip(s0, s1))
+    return e0.elapsed_time(e1) / 1e3, ev, spk
+
+
+def batched_leg(torch, steps=1000, warmup=50, graph_steps=50):
+    """64 independent networks (seeds 0-63, grid sides 2..8, external rates 2-6 Hz), 1 s
+    each: one simulation stepping all of them with one launch per step, against the 64
+    networks run one after the other as plain simulations, on the same GPU."""
+    from paper_1511_09325_amd import Simulation
+    from paper_1511_09325_amd import workloads as W
+    nets = W.batched_networks(64, 0)
+    sim = Simulation(nets)
+    sim.set_launch(graph_steps=graph_steps)
+    sim.step(warmup)
+    tuned = sim.autotune(window=graph_steps)
+    t_b, ev_b, spk_b = _timed_run(sim, steps, torch)
+    n_neurons, n_syn = sim.n_neurons, sim.n_synapses
+    del sim
+    t_s, ev_s = 0.0, 0
+    for p in nets:
+        one = Simulation(p)
+        one.set_launch(graph_steps=graph_steps)
+        one.step(warmup)
+        t, ev, _ = _timed_run(one, steps, torch)
+        t_s += t
+        ev_s += ev
+        del one
+    assert ev_s == ev_b, "batched and sequential runs must deliver the same events"
+    return {"workload": "64 networks, seeds 0-63, grids 2x2..8x8, ext 2-6 Hz, %d steps each"
+                        % steps,
+            "neurons": n_neurons, "synapses": n_syn, "launch": tuned,
+            "batched_events_per_s": ev_b / t_b, "sequential_events_per_s": ev_s / t_s,
+            "batched_sim_ms_per_wall_s": steps / t_b, "speedup_vs_sequential": t_s / t_b,
+            "mean_rate_hz": spk_b / (n_neurons * steps * 1e-3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +145,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0: library default)")
     ap.add_argument("--tile", default="auto", help="arrival tile of target columns, e.g. 4x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB once (a reference kernel of known "
                          "traffic for hardware byte counters)")
@@ -208,6 +258,9 @@ def main():
     }
     del sim
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("batched leg: 64 networks, one launch per step, vs 64 sequential runs")
+        out["batched"] = batched_leg(torch)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

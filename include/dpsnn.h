@@ -186,12 +186,28 @@ typedef struct {
   int32_t delivery;  /* DPSNN_DELIVERY_ARRIVAL or DPSNN_DELIVERY_PUSH */
   int32_t block;     /* 64, 128, 256, 512 or 1024 */
   int32_t tile_x, tile_y;  /* 1..4 */
+  int32_t graph_steps;     /* steps per captured HIP graph, replayed by sim_step; 0 = direct */
 } sim_launch_t;
 
 /* The launch configuration in use. */
 int sim_get_launch(const sim_t* sim, sim_launch_t* launch);
 /* Change it between steps (synchronises); results are bit-identical for every choice. */
 int sim_set_launch(sim_t* sim, const sim_launch_t* launch);
+
+/* Order-independent 64-bit digest of the dynamic state (V, Ca, refractory counters, spike
+ * history).  Equal states give equal digests; used to check that launch configurations and
+ * resumed runs agree bit for bit.  Synchronises. */
+int sim_state_digest(sim_t* sim, uint64_t* digest);
+
+/* Autotuner.  From the current state (kept in snapshot slot 63), runs `window` steps with
+ * each candidate launch configuration (delivery form, workgroup size, tile shape, graph
+ * chunk), timed with HIP events, checks that every candidate reaches the same state digest,
+ * restores the state and keeps the fastest.  cache_path (nullable): a JSON-lines file of
+ * earlier results keyed by the device and the simulation's shape; a hit skips the search.
+ * best / best_ms_per_step (nullable) receive the choice.  DPSNN_ESTATE if two candidates
+ * disagree.  Synchronises. */
+int sim_autotune(sim_t* sim, int32_t window, const char* cache_path, sim_launch_t* best,
+                 double* best_ms_per_step);
 
 /* Per-kernel device time of the last sim_step call, measured with HIP events recorded on
  * the simulation's stream around every kernel launch while timing is on.  ms[0..2]: total

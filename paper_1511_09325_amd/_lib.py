@@ -19,6 +19,7 @@ EXPORTS = [
     "sim_last_error", "sim_get_info", "sim_get_stats", "sim_now", "sim_read_state",
     "sim_read_synapses", "sim_save", "sim_restore", "sim_set_weights", "sim_get_weights",
     "sim_set_params", "sim_get_launch", "sim_set_launch", "sim_set_timing", "sim_get_timing",
+    "sim_state_digest", "sim_autotune",
 ]
 
 
@@ -49,7 +50,7 @@ class SimConfig(C.Structure):
 
 class SimLaunch(C.Structure):
     _fields_ = [("delivery", C.c_int32), ("block", C.c_int32), ("tile_x", C.c_int32),
-                ("tile_y", C.c_int32)]
+                ("tile_y", C.c_int32), ("graph_steps", C.c_int32)]
 
 
 class SimInfo(C.Structure):
@@ -102,6 +103,8 @@ def lib():
         "sim_set_launch": (C.c_int, [vp, P(SimLaunch)]),
         "sim_set_timing": (C.c_int, [vp, C.c_int32]),
         "sim_get_timing": (C.c_int, [vp, P(C.c_double), C.c_int32]),
+        "sim_state_digest": (C.c_int, [vp, P(C.c_uint64)]),
+        "sim_autotune": (C.c_int, [vp, C.c_int32, C.c_char_p, P(SimLaunch), P(C.c_double)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)

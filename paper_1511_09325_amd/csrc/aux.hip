@@ -7,10 +7,13 @@ namespace {
 // Raster: exclusive scan of this step's per-column spike counts (one workgroup), giving
 // each column its place in the ascending global id list of the step.
 __global__ __launch_bounds__(1024) void k_raster_scan(const int32_t* hist_cnt, int32_t n_cols,
-                                                      int32_t slot, int64_t u, int64_t* ras_off,
+                                                      int32_t dh, int64_t u_arg,
+                                                      const int64_t* now_dev, int64_t* ras_off,
                                                       int64_t* colofs, int64_t cap,
                                                       int32_t* flags) {
   __shared__ int64_t wsum[16];
+  const int64_t u = u_arg + (now_dev ? *now_dev : 0);
+  const int32_t slot = (int32_t)(u % dh);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t carry = ras_off[u];
   for (int32_t b = 0; b < n_cols; b += 1024) {
@@ -40,10 +43,13 @@ __global__ __launch_bounds__(1024) void k_raster_scan(const int32_t* hist_cnt, i
 
 __global__ __launch_bounds__(256) void k_raster_copy(const int32_t* hist_cnt,
                                                      const uint16_t* hist_ids, int32_t n_cols,
-                                                     int32_t npc, int32_t slot,
+                                                     int32_t npc, int32_t dh, int64_t u_arg,
+                                                     const int64_t* now_dev,
                                                      const int64_t* colofs, int32_t* ras_ids,
                                                      int64_t cap) {
   const int32_t g = blockIdx.x;
+  const int64_t u = u_arg + (now_dev ? *now_dev : 0);
+  const int32_t slot = (int32_t)(u % dh);
   const int32_t n = hist_cnt[(int64_t)slot * n_cols + g];
   const int64_t base = colofs[g];
   if (base + n > cap) return;
@@ -114,6 +120,38 @@ __global__ __launch_bounds__(256) void k_export_rows(StepArgs a, int32_t g0, int
   }
 }
 
+__global__ void k_set_now(int64_t* d_now, int64_t now) { *d_now = now; }
+__global__ void k_zero_u64(uint64_t* p) { *p = 0; }
+
+// splitmix64 finaliser (Steele, Lea, Flood 2014), used to mix state words into a digest
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Order-independent digest of the dynamic state: V, Ca, refractory counters and the spike
+// history of the last DH steps (which determines every pending input).
+__global__ __launch_bounds__(256) void k_digest(StepArgs a, int64_t now, uint64_t* out) {
+  const int64_t nall = (int64_t)a.n_cols * a.npc;
+  uint64_t h = 0;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < nall; j += (int64_t)gridDim.x * 256) {
+    const uint64_t v = __float_as_uint(a.v[j]), c = __float_as_uint(a.ca[j]);
+    h += mix64(((uint64_t)j << 2) ^ (v << 32) ^ c ^ ((uint64_t)a.ref[j] << 40));
+    const int32_t g = (int32_t)(j / a.npc), k = (int32_t)(j - (int64_t)g * a.npc);
+    for (int back = 1; back <= a.dh - 1; ++back) {
+      const int64_t t = now - back;
+      if (t < 0) break;
+      const int64_t hb = (t % a.dh) * a.n_cols + g;
+      if (k < a.hist_cnt[hb])
+        h += mix64(0x9E3779B97F4A7C15ull * (uint64_t)(t + 1) ^ ((uint64_t)g << 20) ^
+                   a.hist_ids[hb * a.npc + k] ^ ((uint64_t)k << 48));
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) h += __shfl_down(h, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long*)out, (unsigned long long)h);
+}
+
 // Train mode: int32 efficacies rint(w * 2^16) from the float32 master weights (mV).
 __global__ void k_quantise(const float* w, int32_t* wfx, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -124,12 +162,26 @@ __global__ void k_quantise(const float* w, int32_t* wfx, int64_t n) {
 }  // namespace
 
 hipError_t launch_raster(sim& s, int64_t u) {
-  const int32_t slot = (int32_t)(u % s.dh);
-  hipLaunchKernelGGL(k_raster_scan, dim3(1), dim3(1024), 0, s.stream, s.hist_cnt, s.n_cols, slot,
-                     u, s.ras_off, s.ras_colofs, s.cfg.raster_capacity, s.flags);
+  const int64_t* nd = s.graph_mode ? s.d_now : nullptr;
+  hipLaunchKernelGGL(k_raster_scan, dim3(1), dim3(1024), 0, s.stream, s.hist_cnt, s.n_cols, s.dh,
+                     u, nd, s.ras_off, s.ras_colofs, s.cfg.raster_capacity, s.flags);
   hipLaunchKernelGGL(k_raster_copy, dim3(s.n_cols), dim3(256), 0, s.stream, s.hist_cnt,
-                     s.hist_ids, s.n_cols, s.npc, slot, s.ras_colofs, s.ras_ids,
+                     s.hist_ids, s.n_cols, s.npc, s.dh, u, nd, s.ras_colofs, s.ras_ids,
                      s.cfg.raster_capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_now(const sim& s, int64_t now) {
+  hipLaunchKernelGGL(k_set_now, dim3(1), dim3(1), 0, s.stream, s.d_now, now);
+  return hipGetLastError();
+}
+
+hipError_t launch_digest(const sim& s, uint64_t* out) {
+  const StepArgs a = make_step_args(s);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s.stream, out);
+  int64_t blocks = (s.n_neurons + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_digest, dim3((unsigned)blocks), dim3(256), 0, s.stream, a, s.now, out);
   return hipGetLastError();
 }
 

@@ -443,6 +443,7 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
   try {
     if (!out) throw Fail{DPSNN_EINVAL, "out is NULL"};
     validate(cfg);
+    HIPCHK(prepare_step_kernels());
     s = new sim();
     s->cfg = *cfg;
     s->nets.assign(cfg->nets, cfg->nets + cfg->n_nets);
@@ -469,6 +470,8 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->hist_ids = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
     s->net_cnt = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets);
     s->flags = (int32_t*)dalloc(*s, sizeof(int32_t) * 4);
+    s->d_now = (int64_t*)dalloc(*s, sizeof(int64_t));
+    s->d_digest = (uint64_t*)dalloc(*s, sizeof(uint64_t));
     HIPCHK(hipMemsetAsync(s->hist_cnt, 0, sizeof(int32_t) * (size_t)s->dh * s->n_cols, s->stream));
     HIPCHK(hipMemsetAsync(s->net_cnt, 0, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets, s->stream));
     HIPCHK(hipMemsetAsync(s->flags, 0, sizeof(int32_t) * 4, s->stream));
@@ -502,7 +505,87 @@ void sim_destroy(sim_t* s) {
   for (DevBuf& b : s->bufs) (void)hipFree(b.p);
   for (Snapshot& sn : s->snaps) (void)hipFree(sn.blob.p);
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
+  if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   delete s;
+}
+
+// One step by direct launches (with HIP events around each kernel when timing is on).
+static void direct_step(sim& s, std::vector<std::pair<int, size_t>>& marks, size_t& ev_used) {
+  auto mark = [&](int cls) -> hipEvent_t {
+    if (ev_used + 2 > s.events.size()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      s.events.push_back(e);
+      HIPCHK(hipEventCreate(&e));
+      s.events.push_back(e);
+    }
+    marks.push_back({cls, ev_used});
+    ev_used += 2;
+    return s.events[ev_used - 2];
+  };
+  const int64_t u = s.now;
+  if (s.timing) {
+    HIPCHK(hipEventRecord(mark(0), s.stream));
+    HIPCHK(launch_step(s, u, s.delivery, s.block, 0));
+    HIPCHK(hipEventRecord(s.events[marks.back().second + 1], s.stream));
+    if (s.delivery == DPSNN_DELIVERY_PUSH) {
+      HIPCHK(hipEventRecord(mark(1), s.stream));
+      HIPCHK(launch_step(s, u, s.delivery, s.block, 1));
+      HIPCHK(hipEventRecord(s.events[marks.back().second + 1], s.stream));
+    }
+  } else {
+    HIPCHK(launch_step(s, u, s.delivery, s.block, -1));
+  }
+  if (s.ras_off && u < s.cfg.record_steps) {
+    if (s.timing) HIPCHK(hipEventRecord(mark(2), s.stream));
+    HIPCHK(launch_raster(s, u));
+    if (s.timing) HIPCHK(hipEventRecord(s.events[marks.back().second + 1], s.stream));
+  }
+  s.now = u + 1;
+}
+
+static void drop_graph(sim& s) {
+  if (s.graph_exec) (void)hipGraphExecDestroy(s.graph_exec);
+  s.graph_exec = nullptr;
+  s.graph_key.clear();
+}
+
+// A graph of `k` steps whose kernels read their step numbers from s.d_now; it is captured
+// on a private stream and replayed on the simulation's stream.  Re-captured when the launch
+// configuration, the recording state or the step count changes.
+static void run_graph_chunk(sim& s, int32_t k, bool record) {
+  const std::string key = std::to_string(k) + "/" + std::to_string(s.delivery) + "/" +
+                          std::to_string(s.block) + "/" + std::to_string(s.tile_x) + "x" +
+                          std::to_string(s.tile_y) + "/" + (record ? "r" : "-") + "/" +
+                          (s.rec_on ? "t" : "-");
+  if (!s.graph_exec || key != s.graph_key) {
+    drop_graph(s);
+    if (!s.cap_stream) HIPCHK(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
+    hipStream_t user = s.stream;
+    s.stream = s.cap_stream;
+    s.graph_mode = true;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal);
+    for (int32_t q = 0; q < k && e == hipSuccess; ++q) {
+      e = launch_step(s, q, s.delivery, s.block, -1);
+      if (e == hipSuccess && record) e = launch_raster(s, q);
+    }
+    const hipError_t e2 = hipStreamEndCapture(s.cap_stream, &g);
+    s.stream = user;
+    s.graph_mode = false;
+    HIPCHK(e);
+    HIPCHK(e2);
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHK(e3);
+    s.graph_exec = ex;
+    s.graph_key = key;
+  }
+  HIPCHK(launch_set_now(s, s.now));
+  HIPCHK(hipGraphLaunch(s.graph_exec, s.stream));
+  s.now += k;
 }
 
 int sim_step(sim_t* s, int64_t n_steps) {
@@ -515,38 +598,18 @@ int sim_step(sim_t* s, int64_t n_steps) {
     // class 1 = push delivery, class 2 = raster recording
     std::vector<std::pair<int, size_t>> marks;  // (class, first event index)
     size_t ev_used = 0;
-    auto mark = [&](int cls) -> hipEvent_t {
-      if (ev_used + 2 > s->events.size()) {
-        hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
-        s->events.push_back(e);
-        HIPCHK(hipEventCreate(&e));
-        s->events.push_back(e);
-      }
-      marks.push_back({cls, ev_used});
-      ev_used += 2;
-      return s->events[ev_used - 2];
-    };
-    for (int64_t q = 0; q < n_steps; ++q) {
-      const int64_t u = s->now;
-      if (s->timing) {
-        HIPCHK(hipEventRecord(mark(0), s->stream));
-        HIPCHK(launch_step(*s, u, s->delivery, s->block, 0));
-        HIPCHK(hipEventRecord(s->events[marks.back().second + 1], s->stream));
-        if (s->delivery == DPSNN_DELIVERY_PUSH) {
-          HIPCHK(hipEventRecord(mark(1), s->stream));
-          HIPCHK(launch_step(*s, u, s->delivery, s->block, 1));
-          HIPCHK(hipEventRecord(s->events[marks.back().second + 1], s->stream));
-        }
+    int64_t left = n_steps;
+    while (left > 0) {
+      const int32_t k = s->graph_steps;
+      const bool rec_all = s->ras_off && s->now + k <= s->cfg.record_steps;
+      const bool rec_none = !s->ras_off || s->now >= s->cfg.record_steps;
+      if (k > 0 && !s->timing && left >= k && (rec_all || rec_none)) {
+        run_graph_chunk(*s, k, rec_all);
+        left -= k;
       } else {
-        HIPCHK(launch_step(*s, u, s->delivery, s->block, -1));
+        direct_step(*s, marks, ev_used);
+        left -= 1;
       }
-      if (s->ras_off && u < s->cfg.record_steps) {
-        if (s->timing) HIPCHK(hipEventRecord(mark(2), s->stream));
-        HIPCHK(launch_raster(*s, u));
-        if (s->timing) HIPCHK(hipEventRecord(s->events[marks.back().second + 1], s->stream));
-      }
-      s->now = u + 1;
     }
     if (s->timing) {
       for (int c = 0; c < 6; ++c) s->last_ms[c] = 0.0;
@@ -561,6 +624,18 @@ int sim_step(sim_t* s, int64_t n_steps) {
     return DPSNN_OK;
   } catch (const Fail& f) {
     s->sticky = f.code;
+    return finish(s, f);
+  }
+}
+
+int sim_state_digest(sim_t* s, uint64_t* digest) {
+  if (!s || !digest) return DPSNN_EINVAL;
+  try {
+    HIPCHK(launch_digest(*s, s->d_digest));
+    HIPCHK(hipMemcpyAsync(digest, s->d_digest, sizeof(uint64_t), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return DPSNN_OK;
+  } catch (const Fail& f) {
     return finish(s, f);
   }
 }
@@ -821,6 +896,7 @@ int sim_get_launch(const sim_t* s, sim_launch_t* l) {
   l->block = s->block;
   l->tile_x = s->tile_x;
   l->tile_y = s->tile_y;
+  l->graph_steps = s->graph_steps;
   return DPSNN_OK;
 }
 
@@ -833,7 +909,11 @@ int sim_set_launch(sim_t* s, const sim_launch_t* l) {
       throw Fail{DPSNN_EINVAL, "block must be 64, 128, 256, 512 or 1024"};
     if (l->delivery != DPSNN_DELIVERY_ARRIVAL && l->delivery != DPSNN_DELIVERY_PUSH)
       throw Fail{DPSNN_EINVAL, "delivery must be ARRIVAL or PUSH"};
+    if (l->graph_steps < 0 || l->graph_steps > 4096)
+      throw Fail{DPSNN_EINVAL, "graph_steps must be in [0, 4096]"};
     HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(*s);
+    s->graph_steps = l->graph_steps;
     if (l->tile_x != s->tile_x || l->tile_y != s->tile_y) build_tiles(*s, l->tile_x, l->tile_y);
     if (l->delivery == DPSNN_DELIVERY_PUSH && s->delivery != DPSNN_DELIVERY_PUSH) ring_from_history(*s);
     s->delivery = l->delivery;

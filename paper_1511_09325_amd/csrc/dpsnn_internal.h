@@ -107,6 +107,8 @@ struct NeuronK {
 struct StepArgs {
   // sizes
   int32_t npc, nd, d_min, dh, n_cols, idxw;
+  // step numbers: u = u_arg + *now_dev when now_dev is set (replayable graph steps)
+  const int64_t* now_dev;
   // column / network tables
   const int32_t* col_net;
   const int32_t* col_local;   // column index within its network
@@ -234,6 +236,15 @@ struct sim {
   bool timing = false;
   double last_ms[6] = {0, 0, 0, 0, 0, 0};
   std::vector<hipEvent_t> events;
+
+  // replayable step graphs
+  int64_t* d_now = nullptr;        // device step base read by graph-launched kernels
+  int32_t graph_steps = 0;         // steps per captured graph (0: direct launches)
+  bool graph_mode = false;         // true while capturing: kernels read d_now
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  std::string graph_key;
+  uint64_t* d_digest = nullptr;
 };
 
 namespace dpsnn {
@@ -248,8 +259,11 @@ hipError_t launch_init_state(const sim& s);
 // 1 the push delivery
 hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block, int part);
 size_t tile_lds_bytes(const sim& s);
+hipError_t prepare_step_kernels();
 int32_t tile_chunk(const sim& s);
 hipError_t launch_raster(sim& s, int64_t u);
+hipError_t launch_set_now(const sim& s, int64_t now);
+hipError_t launch_digest(const sim& s, uint64_t* out);
 hipError_t launch_pend_view(const sim& s, int32_t* pend, int32_t g0, int32_t g1);
 hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1, int32_t* tgt,
                               uint8_t* dly, int16_t* wq, const int64_t* out_off);

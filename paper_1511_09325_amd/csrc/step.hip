@@ -156,8 +156,9 @@ __device__ __forceinline__ int32_t external_count(const StepArgs& a, int32_t g, 
 // accumulators with integer atomics.  Then the tile's neurons are updated in 64-neuron
 // chunks and the spikes compacted per column, in ascending order.
 template <int BLOCK, bool TRAIN>
-__global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u, int32_t maxc,
+__global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc,
                                                      int32_t chunk) {
+  const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
   constexpr int NW = BLOCK / 64;
   constexpr int NSET = BLOCK / kLanesPerGroup;
   constexpr int GIF = kGroupsInFlight;
@@ -405,7 +406,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u, int3
 
 // ---- PUSH: update from the ring, then scatter ------------------------------------------------
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u) {
+__global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u_arg) {
+  const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
   constexpr int NW = BLOCK / 64;
   __shared__ uint64_t ptab[kPoissonEntries];
   __shared__ int32_t wcnt[NW];
@@ -463,7 +465,8 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u) {
 }
 
 template <int BLOCK, bool TRAIN>
-__global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u) {
+__global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u_arg) {
+  const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
   constexpr int NW = BLOCK / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nall = (int64_t)a.n_cols * a.npc;
@@ -515,15 +518,6 @@ hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
   if (delivery == DPSNN_DELIVERY_ARRIVAL) {
     if (part == 1) return hipSuccess;
     const size_t lds = tile_lds_bytes(s);
-    // allow the dynamic LDS beyond 64 KB (gfx950 has 160 KB per workgroup)
-    static bool attr_done[2] = {false, false};
-    if (!attr_done[train]) {
-      const void* fn = train ? (const void*)k_step_tile<BLOCK, true> : (const void*)k_step_tile<BLOCK, false>;
-      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)(kMaxLds - 16 * 1024));
-      if (e != hipSuccess) return e;
-      attr_done[train] = true;
-    }
     if (train)
       hipLaunchKernelGGL((k_step_tile<BLOCK, true>), dim3(s.grid_tiles), dim3(BLOCK), lds,
                          s.stream, a, u, s.tile_max_cols, tile_chunk(s));
@@ -581,6 +575,7 @@ StepArgs make_step_args(const sim& s) {
   a.dh = s.dh;
   a.n_cols = s.n_cols;
   a.idxw = s.idxw;
+  a.now_dev = s.graph_mode ? s.d_now : nullptr;
   a.col_net = s.col_net;
   a.col_local = s.col_local;
   a.col_nbr = s.col_nbr;
@@ -617,6 +612,26 @@ StepArgs make_step_args(const sim& s) {
   }
   a.k = s.nk;
   return a;
+}
+
+template <int BLOCK>
+hipError_t allow_large_lds() {
+  const int bytes = (int)(kMaxLds - 16 * 1024);
+  hipError_t e = hipFuncSetAttribute((const void*)k_step_tile<BLOCK, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_step_tile<BLOCK, false>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// Allow the tile kernels the dynamic LDS beyond 64 KB (gfx950: 160 KB per workgroup).
+hipError_t prepare_step_kernels() {
+  hipError_t e;
+  if ((e = allow_large_lds<64>()) != hipSuccess) return e;
+  if ((e = allow_large_lds<128>()) != hipSuccess) return e;
+  if ((e = allow_large_lds<256>()) != hipSuccess) return e;
+  if ((e = allow_large_lds<512>()) != hipSuccess) return e;
+  return allow_large_lds<1024>();
 }
 
 hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block, int part) {

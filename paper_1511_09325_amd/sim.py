@@ -171,7 +171,7 @@ class Simulation:
         L.check(self.lib.sim_restore(self.h, slot), self.h)
 
     def set_launch(self, delivery: int | None = None, block: int | None = None,
-                   tile: tuple[int, int] | None = None):
+                   tile: tuple[int, int] | None = None, graph_steps: int | None = None):
         """Change the launch configuration; None keeps the current value."""
         cur = self.get_launch()
         lc = L.SimLaunch()
@@ -179,12 +179,30 @@ class Simulation:
         lc.block = cur["block"] if block is None else int(block)
         tx, ty = cur["tile"] if tile is None else tile
         lc.tile_x, lc.tile_y = int(tx), int(ty)
+        lc.graph_steps = cur["graph_steps"] if graph_steps is None else int(graph_steps)
         L.check(self.lib.sim_set_launch(self.h, C.byref(lc)), self.h)
 
     def get_launch(self) -> dict:
         lc = L.SimLaunch()
         L.check(self.lib.sim_get_launch(self.h, C.byref(lc)), self.h)
-        return {"delivery": lc.delivery, "block": lc.block, "tile": (lc.tile_x, lc.tile_y)}
+        return {"delivery": lc.delivery, "block": lc.block, "tile": (lc.tile_x, lc.tile_y),
+                "graph_steps": lc.graph_steps}
+
+    def digest(self) -> int:
+        d = C.c_uint64()
+        L.check(self.lib.sim_state_digest(self.h, C.byref(d)), self.h)
+        return d.value
+
+    def autotune(self, window: int = 20, cache_path: str | None = None) -> dict:
+        """Measure the candidate launch configurations from the current state and keep the
+        fastest (the state is restored afterwards)."""
+        lc = L.SimLaunch()
+        ms = C.c_double()
+        L.check(self.lib.sim_autotune(self.h, int(window),
+                                      cache_path.encode() if cache_path else None,
+                                      C.byref(lc), C.byref(ms)), self.h)
+        return {"delivery": lc.delivery, "block": lc.block, "tile": (lc.tile_x, lc.tile_y),
+                "graph_steps": lc.graph_steps, "ms_per_step": ms.value}
 
     def set_params(self, tau_m: float, g_ahp: float):
         L.check(self.lib.sim_set_params(self.h, float(tau_m), float(g_ahp)), self.h)

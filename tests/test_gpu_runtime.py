@@ -1,0 +1,120 @@
+"""Runtime features on the GPU: replayed step graphs, the autotuner, state digests and
+batch invariance.  Every configuration must give the same bits (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_09325_amd import DELIVERY_ARRIVAL, DELIVERY_PUSH, Simulation
+from paper_1511_09325_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _same_as_oracle(sim, p, T, net=0):
+    ref = oracle.Sim(p)
+    ref.step(T)
+    got = sim.read_spikes(net, 0, T)
+    for u in range(T):
+        assert np.array_equal(got[u], ref.spikes(u)), u
+    a, b = sim.state(net), ref.state()
+    for k in ("v", "ca", "ref", "pend"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("graph_steps,record", [(16, 100), (16, 40), (7, 100)],
+                         ids=["g16-rec-all", "g16-rec-part", "g7"])
+def test_graph_steps_bit_exact(graph_steps, record):
+    p = W.tiny(3, 4, npc=40, seed=31)
+    T = 100
+    sim = Simulation(p, record_steps=record, raster_capacity=T * 480)
+    sim.set_launch(graph_steps=graph_steps)
+    sim.step(T)
+    ref = oracle.Sim(p)
+    ref.step(T)
+    got = sim.read_spikes(0, 0, min(record, T))
+    for u in range(min(record, T)):
+        assert np.array_equal(got[u], ref.spikes(u)), u
+    a, b = sim.state(0), ref.state()
+    for k in ("v", "ca", "ref", "pend"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_graph_after_restore_and_relaunch():
+    p = W.tiny(2, 3, npc=40, seed=32)
+    sim = Simulation(p, record_steps=90)
+    sim.set_launch(graph_steps=10)
+    sim.step(30)
+    sim.save(1)
+    sim.step(20)
+    sim.restore(1)
+    sim.set_launch(tile=(2, 2), graph_steps=12)
+    sim.step(60)
+    _same_as_oracle(sim, p, 90)
+
+
+def test_digest_identical_across_launches():
+    p = W.tiny(4, 4, npc=48, seed=33)
+    digests = []
+    for launch in [dict(delivery=DELIVERY_ARRIVAL, block=1024, tile=(4, 4)),
+                   dict(delivery=DELIVERY_ARRIVAL, block=64, tile=(1, 1)),
+                   dict(delivery=DELIVERY_ARRIVAL, block=256, tile=(3, 2)),
+                   dict(delivery=DELIVERY_PUSH, block=256)]:
+        sim = Simulation(p, **launch)
+        sim.step(120)
+        digests.append(sim.digest())
+    assert len(set(digests)) == 1
+    other = Simulation(dict(p, seed=34))
+    other.step(120)
+    assert other.digest() != digests[0]
+
+
+def test_autotune_keeps_the_trajectory(tmp_path):
+    p = W.tiny(4, 5, npc=40, seed=35)
+    sim = Simulation(p, record_steps=90)
+    sim.step(30)
+    cache = str(tmp_path / "tune.jsonl")
+    best = sim.autotune(window=10, cache_path=cache)
+    assert best["ms_per_step"] > 0
+    assert sim.now == 30
+    assert sim.get_launch()["block"] == best["block"]
+    sim.step(60)
+    _same_as_oracle(sim, p, 90)
+    # a second tuner call is served from the cache
+    sim2 = Simulation(p)
+    sim2.step(5)
+    best2 = sim2.autotune(window=10, cache_path=cache)
+    assert (best2["delivery"], best2["block"], best2["tile"]) == \
+        (best["delivery"], best["block"], best["tile"])
+
+
+def test_batched_members_match_solo_runs_with_graphs():
+    nets = W.batched_networks(8, base_seed=40)
+    nets = [dict(q, npc=40, n_exc=32) for q in nets]
+    T = 120
+    batch = Simulation(nets, record_steps=T, raster_capacity=T * 20000)
+    batch.set_launch(graph_steps=20)
+    batch.step(T)
+    for n, p in enumerate(nets):
+        solo = Simulation(p, record_steps=T, raster_capacity=T * 5000)
+        solo.step(T)
+        a, b = batch.read_spikes(n, 0, T), solo.read_spikes(0, 0, T)
+        for u in range(T):
+            assert np.array_equal(a[u], b[u]), (n, u)
+        sa, sb = batch.state(n), solo.state(0)
+        for k in ("v", "ca", "ref", "pend"):
+            assert np.array_equal(sa[k], sb[k]), (n, k)
+        assert batch.stats(n)["e_rec"] == solo.stats(0)["e_rec"]
+    for n in (0, 7):
+        ref = oracle.Sim(nets[n])
+        ref.step(T)
+        got = batch.read_spikes(n, 0, T)
+        for u in range(T):
+            assert np.array_equal(got[u], ref.spikes(u)), (n, u)
