@@ -51,6 +51,12 @@ class _Cfg(C.Structure):
     ]
 
 
+class _AdjParams(C.Structure):
+    _fields_ = [("pm", C.c_double), ("pc", C.c_double), ("gamma", C.c_double),
+                ("alpha", C.c_double), ("theta", C.c_double), ("vreset", C.c_double),
+                ("beta", C.c_double)]
+
+
 _lib = None
 
 
@@ -91,15 +97,13 @@ def lib():
             "orc_sim_trajectory": (C.c_int64, [C.c_void_p, f32p, f32p, f32p, u8p, u8p, i32p,
                                                C.c_int64]),
         }
-        if hasattr(L, "orc_adjoint"):
-            sig["orc_adjoint"] = (C.c_int, [
-                cp, C.c_int64, C.c_int64, i64p, i32p, u8p, f64p,   # cfg, n, T, csr, w (mV)
-                f64p, f64p, f64p, u8p, u8p,                         # v_prev, ca_prev, v_tilde, s, r
-                f64p, C.c_double, C.c_double,                       # dL/ds, beta, surrogate kind
-                f64p, f64p, f64p])                                  # grad_w, grad_pm, grad_gamma
-            sig["orc_soft_forward"] = (C.c_int, [
-                cp, C.c_int64, C.c_int64, i64p, i32p, u8p, f64p, C.c_double, C.c_double,
-                C.c_double, f64p, f64p, f64p, f64p, f64p])
+        ap = P(_AdjParams)
+        sig["orc_adjoint"] = (C.c_int, [
+            ap, C.c_int64, C.c_int64, i64p, i32p, u8p, f64p,   # params, n, T, csr, w (mV)
+            f64p, f64p, f64p, f64p, u8p,                        # v_prev, ca_prev, v_tilde, s, r
+            f64p, f64p, f64p, f64p])                            # dL/ds, grad_w, grad_pm, grad_gamma
+        sig["orc_soft_forward"] = (C.c_int, [
+            cp, ap, C.c_int64, C.c_int64, i64p, i32p, u8p, f64p, f64p, f64p, f64p, f64p])
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
             fn.restype = res
@@ -306,3 +310,67 @@ class Sim:
                                      _ptr(a, C.c_int32), steps)
         return {"v_prev": vp[:m], "ca_prev": cp[:m], "v_tilde": vt[:m], "s": s[:m], "r": r[:m],
                 "input": a[:m]}
+
+
+# ---------------------------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------------------------
+def step_constants(p: dict, single: bool):
+    """Step constants; single=True gives the float32-rounded values the hard step uses."""
+    pm = np.exp(-p["dt"] / p["tau_m"])
+    pc = np.exp(-p["dt"] / p["tau_ca"])
+    gam = p["g_ahp"] * p["dt"]
+    vals = dict(pm=pm, pc=pc, gamma=gam, alpha=p["ca_inc"], theta=p["theta"], vreset=p["v_reset"])
+    if single:
+        vals = {k: float(np.float32(v)) for k, v in vals.items()}
+    return vals
+
+
+def _adj_params(consts: dict, beta: float):
+    a = _AdjParams()
+    for k, v in consts.items():
+        setattr(a, k, float(v))
+    a.beta = float(beta)
+    return a
+
+
+def adjoint(consts: dict, beta: float, net, w_mv, traj: dict, dl_ds):
+    """FP64 reverse recursion over a trajectory; returns (grad_w, grad_pm, grad_gamma)."""
+    row_ptr, tgt, dly = (np.ascontiguousarray(net[0], np.int64),
+                         np.ascontiguousarray(net[1], np.int32),
+                         np.ascontiguousarray(net[2], np.uint8))
+    n = len(row_ptr) - 1
+    T = traj["v_tilde"].shape[0]
+    f = lambda a: np.ascontiguousarray(a, np.float64)
+    vp, cp, vt, s = f(traj["v_prev"]), f(traj["ca_prev"]), f(traj["v_tilde"]), f(traj["s"])
+    r = np.ascontiguousarray(traj.get("r", np.zeros((T, n), np.uint8)), np.uint8)
+    w = f(w_mv)
+    dl = f(dl_ds)
+    gw = np.zeros(len(tgt), np.float64)
+    gpm, ggam = C.c_double(), C.c_double()
+    k = _adj_params(consts, beta)
+    rc = lib().orc_adjoint(C.byref(k), n, T, _ptr(row_ptr, C.c_int64), _ptr(tgt, C.c_int32),
+                           _ptr(dly, C.c_uint8), _ptr(w, C.c_double), _ptr(vp, C.c_double),
+                           _ptr(cp, C.c_double), _ptr(vt, C.c_double), _ptr(s, C.c_double),
+                           _ptr(r, C.c_uint8), _ptr(dl, C.c_double), _ptr(gw, C.c_double),
+                           C.byref(gpm), C.byref(ggam))
+    assert rc == 0
+    return gw, gpm.value, ggam.value
+
+
+def soft_forward(p: dict, consts: dict, beta: float, net, w_mv, T: int):
+    """FP64 soft-spike forward; returns the trajectory dict ([T][n] arrays)."""
+    cfg = make_config(p)
+    row_ptr, tgt, dly = (np.ascontiguousarray(net[0], np.int64),
+                         np.ascontiguousarray(net[1], np.int32),
+                         np.ascontiguousarray(net[2], np.uint8))
+    n = len(row_ptr) - 1
+    w = np.ascontiguousarray(w_mv, np.float64)
+    out = {k: np.zeros((T, n), np.float64) for k in ("v_prev", "ca_prev", "v_tilde", "s")}
+    k = _adj_params(consts, beta)
+    rc = lib().orc_soft_forward(C.byref(cfg), C.byref(k), n, T, _ptr(row_ptr, C.c_int64),
+                                _ptr(tgt, C.c_int32), _ptr(dly, C.c_uint8), _ptr(w, C.c_double),
+                                _ptr(out["v_prev"], C.c_double), _ptr(out["ca_prev"], C.c_double),
+                                _ptr(out["v_tilde"], C.c_double), _ptr(out["s"], C.c_double))
+    assert rc == 0
+    return out

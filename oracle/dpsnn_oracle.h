@@ -133,6 +133,27 @@ void orc_sim_record(orc_sim_t* s, int on);
 int64_t orc_sim_trajectory(const orc_sim_t* s, float* v_prev, float* ca_prev, float* v_tilde,
                            uint8_t* spk, uint8_t* refr, int32_t* input, int64_t cap_steps);
 
+/* ---- adjoint (dpsnn_adjoint.c) ---------------------------------------------- */
+typedef struct {
+  double pm, pc, gamma, alpha, theta, vreset; /* step constants as used by the forward */
+  double beta;                                /* surrogate slope, 1/mV */
+} orc_adj_params_t;
+
+/* Reverse recursion over a recorded trajectory ([T][n] arrays; s may be soft, r = refractory
+ * flags).  w in mV per synapse of the CSR.  dl_ds: direct dL/ds, [T][n].  Outputs: dL/dw per
+ * synapse, dL/dP_m, dL/dgamma.  Returns 0, or -1 if out of memory. */
+int orc_adjoint(const orc_adj_params_t* k, int64_t n, int64_t T, const int64_t* row_ptr,
+                const int32_t* tgt, const uint8_t* dly, const double* w, const double* v_prev,
+                const double* ca_prev, const double* v_tilde, const double* s, const uint8_t* r,
+                const double* dl_ds, double* grad_w, double* grad_pm, double* grad_gamma);
+
+/* Smooth version of the step in FP64 (soft spike, soft reset and delivery, no refractory
+ * period); records the trajectory ([T][n] outputs). */
+int orc_soft_forward(const orc_config_t* cfg, const orc_adj_params_t* k, int64_t n, int64_t T,
+                     const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly,
+                     const double* w, double* v_prev, double* ca_prev, double* v_tilde,
+                     double* s);
+
 #ifdef __cplusplus
 }
 #endif
