@@ -86,6 +86,7 @@ typedef struct {
   int64_t raster_capacity; /* spike raster: capacity in spike ids */
   int32_t train_mode;    /* 1: float32 master weights, trajectory recording, sim_backward */
   int32_t ckpt_every;    /* train mode: checkpoint interval in steps (>= 1) */
+  double surrogate_beta; /* train mode: slope of the fast-sigmoid surrogate, 1/mV (> 0) */
 } sim_config_t;
 
 /* Sizes of a created simulation. */
@@ -131,6 +132,14 @@ int sim_sync(sim_t* sim);
  * returns DPSNN_ETRUNC with the needed count in *n_ids.  Synchronises. */
 int sim_read_spikes(sim_t* sim, int32_t net, int64_t t0, int64_t t1, int64_t* step_offsets,
                     int32_t* ids, int64_t ids_cap, int64_t* n_ids);
+
+/* Train mode: go back to the state at step 0 (the initial state) and start a new recorded
+ * window; counters and per-column spike counts restart from zero. */
+int sim_rewind(sim_t* sim);
+
+/* Mean firing rate of every column since step 0 (or the last rewind), in Hz:
+ * R_c = 1000 * spikes_c / (npc * now * dt).  rates: device float32 [n_cols]. Asynchronous. */
+int sim_column_rates(sim_t* sim, float* rates);
 
 /* Surrogate-gradient backward through the recorded window [0, now) (train mode only).
  * grad_rates: device float32 [n_cols of all networks], dL/dR_c of each column's mean rate

@@ -19,7 +19,7 @@ EXPORTS = [
     "sim_last_error", "sim_get_info", "sim_get_stats", "sim_now", "sim_read_state",
     "sim_read_synapses", "sim_save", "sim_restore", "sim_set_weights", "sim_get_weights",
     "sim_set_params", "sim_get_launch", "sim_set_launch", "sim_set_timing", "sim_get_timing",
-    "sim_state_digest", "sim_autotune",
+    "sim_state_digest", "sim_autotune", "sim_rewind", "sim_column_rates",
 ]
 
 
@@ -45,6 +45,7 @@ class SimConfig(C.Structure):
         ("tile_x", C.c_int32), ("tile_y", C.c_int32),
         ("record_steps", C.c_int64), ("raster_capacity", C.c_int64),
         ("train_mode", C.c_int32), ("ckpt_every", C.c_int32),
+        ("surrogate_beta", C.c_double),
     ]
 
 
@@ -105,6 +106,8 @@ def lib():
         "sim_get_timing": (C.c_int, [vp, P(C.c_double), C.c_int32]),
         "sim_state_digest": (C.c_int, [vp, P(C.c_uint64)]),
         "sim_autotune": (C.c_int, [vp, C.c_int32, C.c_char_p, P(SimLaunch), P(C.c_double)]),
+        "sim_rewind": (C.c_int, [vp]),
+        "sim_column_rates": (C.c_int, [vp, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(L, name)

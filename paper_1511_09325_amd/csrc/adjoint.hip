@@ -1,0 +1,216 @@
+// adjoint.hip -- surrogate-gradient backpropagation through time of the step (train mode).
+//
+// Forward quantities of neuron j at step u (recorded during the recompute of a checkpoint
+// segment): V(u-1), Ca(u-1), the pre-threshold potential V~(u), the spike s(u) and the
+// refractory flag r(u).  With nu(u) = dL/dV~(u), lambda(u) = dL/dV(u), mu(u) = dL/dCa(u):
+//     e(u)  = dL/ds(u) + sum_{k in row(j)} w_k nu_{tgt k}(u + d_k)
+//             + lambda(u) (V_reset - V~(u)) + alpha mu(u)
+//     nu(u) = (1 - r(u)) [ lambda(u) (1 - s(u)) + e(u) sigma'(V~(u) - theta) ]
+//     lambda(u-1) = P_m nu(u),   mu(u-1) = -gamma nu(u) + P_c mu(u)
+//     dL/dw_k += nu_{tgt k}(u + d_k) at every spike of k's source,
+//     dL/dP_m += V(u-1) nu(u),   dL/dgamma -= Ca(u-1) nu(u)
+// with sigma'(x) = 1 / (1 + beta |x|)^2 (fast-sigmoid surrogate).  Per reverse step two
+// kernels: k_adj_row (one wave per neuron: the gather over its outgoing row from the ring
+// of future nu, and the weight gradient when it spiked) and k_adj_neuron (the recursion).
+// Everything is float32 except the per-neuron float64 partials of the two scalar
+// gradients; every sum has a fixed order, so the result is deterministic.
+#include "dpsnn_internal.h"
+
+namespace dpsnn {
+namespace {
+
+struct AdjArgs {
+  StepArgs a;
+  const float* wf32;
+  float* gw;
+  float* nu_ring;     // [dh][N]
+  float* gsum;        // [N]
+  float* lam;         // [N]
+  float* mu;          // [N]
+  double* part;       // [2][N]: dL/dP_m, dL/dgamma partials
+  const float* grad_rates;  // [n_cols]
+  float dlds_scale;   // dR_c / ds = 1000 / (npc T dt)
+  float beta;
+};
+
+__global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
+  const StepArgs& a = x.a;
+  const int lane = threadIdx.x & 63;
+  const int64_t nall = (int64_t)a.n_cols * a.npc;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nall) return;
+  const int32_t g = (int32_t)(j / a.npc);
+  const bool spiked = (a.rec_flags[(u - a.rec_base) * nall + j] & 1) != 0;
+  const int64_t st = idx_start(a, j);
+  const uint16_t* go = idx_goff(a, j);
+  float acc = 0.0f;
+  for (int dd = 0; dd < a.nd; ++dd) {
+    const float* nus = x.nu_ring + ((u + a.d_min + dd) % a.dh) * nall;
+    for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+      const uint32_t w = a.syn[st + f];
+      if (rec_rank(w) == (uint32_t)kDummyRank) continue;
+      const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+      const float nu = nus[(int64_t)tc * a.npc + rec_k(w)];
+      const float prod = x.wf32[st + f] * nu;
+      acc = acc + prod;
+      if (spiked) x.gw[st + f] = x.gw[st + f] + nu;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc = acc + __shfl_down(acc, off);
+  if (lane == 0) x.gsum[j] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_adj_neuron(AdjArgs x, int64_t u) {
+  const StepArgs& a = x.a;
+  const int64_t nall = (int64_t)a.n_cols * a.npc;
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < nall;
+       j += (int64_t)gridDim.x * 256) {
+    const int64_t o = (u - a.rec_base) * nall + j;
+    const uint8_t fl = a.rec_flags[o];
+    const float s = (fl & 1) ? 1.0f : 0.0f;
+    const float vt = a.rec_vt[o];
+    const float lam = x.lam[j], mu = x.mu[j];
+    const float dlds = x.grad_rates[j / a.npc] * x.dlds_scale;
+    const float reset_term = lam * (a.k.vreset - vt);
+    const float e = ((dlds + x.gsum[j]) + reset_term) + a.k.alpha * mu;
+    float nu = 0.0f;
+    if (!(fl & 2)) {
+      const float den = 1.0f + x.beta * fabsf(vt - a.k.theta);
+      const float sig = 1.0f / (den * den);
+      nu = lam * (1.0f - s) + e * sig;
+    }
+    x.nu_ring[(u % a.dh) * nall + j] = nu;
+    x.part[j] += (double)a.rec_vprev[o] * (double)nu;
+    x.part[nall + j] -= (double)a.rec_caprev[o] * (double)nu;
+    x.lam[j] = a.k.pm * nu;
+    x.mu[j] = a.k.pc * mu - a.k.gam * nu;
+  }
+}
+
+// Sums of the two partial arrays in a fixed order (one workgroup).
+__global__ __launch_bounds__(1024) void k_reduce_parts(const double* part, int64_t n,
+                                                       double* out) {
+  __shared__ double buf[2][1024];
+  for (int c = 0; c < 2; ++c) {
+    double acc = 0.0;
+    for (int64_t e = threadIdx.x; e < n; e += 1024) acc += part[c * n + e];
+    buf[c][threadIdx.x] = acc;
+  }
+  __syncthreads();
+  for (int width = 512; width > 0; width >>= 1) {
+    if ((int)threadIdx.x < width) {
+      buf[0][threadIdx.x] += buf[0][threadIdx.x + width];
+      buf[1][threadIdx.x] += buf[1][threadIdx.x + width];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = buf[0][0];
+    out[1] = buf[1][0];
+  }
+}
+
+// Canonical synapse order (per source neuron: the real records, sorted by (delay, target))
+// <-> the padded device layout.  mode 0: dst_padded[p] = src_canon[c]; mode 1: the reverse.
+// Padding records receive 0 in mode 0.
+__global__ __launch_bounds__(256) void k_canon_map(StepArgs a, const int64_t* canon_start,
+                                                   int mode, const float* src, float* dst) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nall = (int64_t)a.n_cols * a.npc;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nall;
+       i += (int64_t)gridDim.x * 4) {
+    const int64_t st = idx_start(a, i);
+    const uint16_t* go = idx_goff(a, i);
+    int64_t c = canon_start[i];
+    for (int dd = 0; dd < a.nd; ++dd) {
+      const int32_t g0 = go[dd], g1 = go[dd + 1];
+      int32_t real = g1 - g0;
+      while (real > 0 && rec_rank(a.syn[st + g0 + real - 1]) == (uint32_t)kDummyRank) --real;
+      for (int32_t f = g0 + lane; f < g1; f += 64) {
+        const int32_t q = f - g0;
+        if (mode == 0) dst[st + f] = q < real ? src[c + q] : 0.0f;
+        else if (q < real) dst[c + q] = src[st + f];
+      }
+      c += real;
+    }
+  }
+}
+
+// Initial master weights from the int16 records: w = w_q * 2^-14 mV (dummies 0).
+__global__ void k_weights_from_records(const uint32_t* syn, float* w, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t r = syn[e];
+    w[e] = rec_rank(r) == (uint32_t)kDummyRank ? 0.0f
+                                               : (float)(int16_t)(r >> 16) * 0x1p-14f;
+  }
+}
+
+__global__ void k_column_rates(const unsigned long long* col_spk, int32_t n_cols, float scale,
+                               float* rates) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n_cols) rates[c] = (float)((double)col_spk[c] * (double)scale);
+}
+
+int grid_of(int64_t items, int per_block) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates, float scale,
+                               float beta) {
+  AdjArgs x{};
+  x.a = make_step_args(s);
+  // the trajectory of the segment being reversed (recorded by its recompute)
+  x.a.rec_vprev = s.rec_vprev;
+  x.a.rec_caprev = s.rec_caprev;
+  x.a.rec_vt = s.rec_vt;
+  x.a.rec_flags = s.rec_flags;
+  x.a.rec_base = s.rec_base;
+  x.wf32 = s.wf32;
+  x.gw = s.gw;
+  x.nu_ring = s.nu_ring;
+  x.gsum = s.adj_gsum;
+  x.lam = s.adj_lam;
+  x.mu = s.adj_mu;
+  x.part = s.adj_part;
+  x.grad_rates = grad_rates;
+  x.dlds_scale = scale;
+  x.beta = beta;
+  hipLaunchKernelGGL(k_adj_row, dim3((unsigned)((s.n_neurons + 3) / 4)), dim3(256), 0, s.stream,
+                     x, u);
+  hipLaunchKernelGGL(k_adj_neuron, dim3(grid_of(s.n_neurons, 256)), dim3(256), 0, s.stream, x, u);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const sim& s, double* out) {
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(1024), 0, s.stream, s.adj_part, s.n_neurons,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst) {
+  const StepArgs a = make_step_args(s);
+  hipLaunchKernelGGL(k_canon_map, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a,
+                     s.canon_start, mode, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_weights_from_records(const sim& s) {
+  hipLaunchKernelGGL(k_weights_from_records, dim3(grid_of(s.n_syn_padded, 256)), dim3(256), 0,
+                     s.stream, s.syn, s.wf32, s.n_syn_padded);
+  return hipGetLastError();
+}
+
+hipError_t launch_column_rates(const sim& s, float scale, float* rates) {
+  hipLaunchKernelGGL(k_column_rates, dim3(grid_of(s.n_cols, 256)), dim3(256), 0, s.stream,
+                     s.col_spk, s.n_cols, scale, rates);
+  return hipGetLastError();
+}
+
+}  // namespace dpsnn

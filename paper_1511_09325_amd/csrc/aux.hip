@@ -209,11 +209,12 @@ hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1,
 }
 
 hipError_t launch_quantise(const sim& s) {
-  int64_t blocks = (s.n_syn + 255) / 256;
+  // the padded layout, dummies included (their master weight is 0)
+  int64_t blocks = (s.n_syn_padded + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_quantise, dim3((unsigned)blocks), dim3(256), 0, s.stream, s.wf32, s.wfx,
-                     s.n_syn);
+                     s.n_syn_padded);
   return hipGetLastError();
 }
 

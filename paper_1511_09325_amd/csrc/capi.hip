@@ -117,6 +117,7 @@ void validate(const sim_config_t* c) {
     bad("tile sides must both be 0 (auto) or both in [1, 4]");
   if (c->record_steps < 0 || c->raster_capacity < 0) bad("raster sizes must be >= 0");
   if (c->train_mode && c->ckpt_every < 1) bad("ckpt_every must be >= 1 in train mode");
+  if (c->train_mode && !(c->surrogate_beta > 0)) bad("surrogate_beta must be > 0 in train mode");
   int64_t cols = 0;
   for (int n = 0; n < c->n_nets; ++n) {
     const sim_net_t& t = c->nets[n];
@@ -378,7 +379,8 @@ void generate(sim& s) {
     const int64_t i = (int64_t)s.net_col0[n] * s.npc;
     HIPCHK(hipMemcpy(&s.net_syn0[n], degscan + i, sizeof(int64_t), hipMemcpyDeviceToHost));
   }
-  dfree(s, degscan);
+  if (s.cfg.train_mode) s.canon_start = degscan;  // canonical order of the weights
+  else dfree(s, degscan);
   dfree(s, part);
   dfree(s, row_len);
   dfree(s, s.seg);
@@ -396,8 +398,6 @@ void ensure_ring(sim& s) {
 void ring_from_history(sim& s) {
   ensure_ring(s);
   const size_t nall = (size_t)s.n_neurons;
-  int32_t* pend = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)s.dh * nall);
-  HIPCHK(hipMemsetAsync(pend, 0, sizeof(int32_t) * (size_t)s.dh * nall, s.stream));
   for (int n = 0; n < s.n_nets; ++n) {
     // the view is per network: targets relative to the network's first column
     const int32_t g0 = s.net_col0[n], g1 = s.net_col0[n + 1];
@@ -413,19 +413,51 @@ void ring_from_history(sim& s) {
     HIPCHK(hipStreamSynchronize(s.stream));
     dfree(s, tmp);
   }
-  dfree(s, pend);
 }
 
 // The dynamic state saved by a snapshot.  The push ring is not part of it: it is rebuilt
 // from the spike history on restore.
+constexpr int kSnapParts = 7;
+
 void snapshot_parts(sim& s, size_t* parts, void** ptrs) {
   const size_t N = (size_t)s.n_neurons;
+  parts[6] = sizeof(unsigned long long) * (size_t)s.n_cols;         ptrs[6] = s.col_spk;
   parts[0] = sizeof(float) * N;                                    ptrs[0] = s.v;
   parts[1] = sizeof(float) * N;                                    ptrs[1] = s.ca;
   parts[2] = N;                                                    ptrs[2] = s.ref;
   parts[3] = sizeof(int32_t) * (size_t)s.dh * s.n_cols;            ptrs[3] = s.hist_cnt;
   parts[4] = sizeof(uint16_t) * (size_t)s.dh * s.n_cols * s.npc;   ptrs[4] = s.hist_ids;
   parts[5] = sizeof(unsigned long long) * kCounters * (size_t)s.n_nets;    ptrs[5] = s.net_cnt;
+}
+
+void save_into_ckpt(sim& s, size_t m);
+
+// Train mode: float32 master weights (initially the int16 weights), their int32 efficacies,
+// the adjoint buffers, trajectory recording for one checkpoint segment, checkpoint 0.
+void setup_train(sim& s) {
+  const size_t sp = (size_t)s.n_syn_padded + 4;
+  const size_t N = (size_t)s.n_neurons;
+  s.wf32 = (float*)dalloc(s, sizeof(float) * sp);
+  s.wfx = (int32_t*)dalloc(s, sizeof(int32_t) * sp);
+  s.gw = (float*)dalloc(s, sizeof(float) * sp);
+  HIPCHK(hipMemsetAsync(s.wf32, 0, sizeof(float) * sp, s.stream));
+  HIPCHK(hipMemsetAsync(s.wfx, 0, sizeof(int32_t) * sp, s.stream));
+  HIPCHK(launch_weights_from_records(s));
+  HIPCHK(launch_quantise(s));
+  s.nu_ring = (float*)dalloc(s, sizeof(float) * (size_t)s.dh * N);
+  s.adj_gsum = (float*)dalloc(s, sizeof(float) * N);
+  s.adj_lam = (float*)dalloc(s, sizeof(float) * N);
+  s.adj_mu = (float*)dalloc(s, sizeof(float) * N);
+  s.adj_part = (double*)dalloc(s, sizeof(double) * 2 * N);
+  s.adj_out = (double*)dalloc(s, sizeof(double) * 2);
+  s.rec_steps = s.cfg.ckpt_every;
+  const size_t rn = (size_t)s.rec_steps * N;
+  s.rec_vprev = (float*)dalloc(s, sizeof(float) * rn);
+  s.rec_caprev = (float*)dalloc(s, sizeof(float) * rn);
+  s.rec_vt = (float*)dalloc(s, sizeof(float) * rn);
+  s.rec_flags = (uint8_t*)dalloc(s, rn);
+  save_into_ckpt(s, 0);
+  s.ckpts[0].epoch = s.epoch;
 }
 
 int finish(sim* s, const Fail& f) {
@@ -472,6 +504,8 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->flags = (int32_t*)dalloc(*s, sizeof(int32_t) * 4);
     s->d_now = (int64_t*)dalloc(*s, sizeof(int64_t));
     s->d_digest = (uint64_t*)dalloc(*s, sizeof(uint64_t));
+    s->col_spk = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * (size_t)s->n_cols);
+    HIPCHK(hipMemsetAsync(s->col_spk, 0, sizeof(unsigned long long) * (size_t)s->n_cols, s->stream));
     HIPCHK(hipMemsetAsync(s->hist_cnt, 0, sizeof(int32_t) * (size_t)s->dh * s->n_cols, s->stream));
     HIPCHK(hipMemsetAsync(s->net_cnt, 0, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets, s->stream));
     HIPCHK(hipMemsetAsync(s->flags, 0, sizeof(int32_t) * 4, s->stream));
@@ -484,6 +518,7 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
       HIPCHK(hipMemsetAsync(s->ras_off, 0, sizeof(int64_t) * (size_t)(cfg->record_steps + 1), s->stream));
     }
     s->snaps.resize(64);
+    if (cfg->train_mode) setup_train(*s);
     HIPCHK(hipStreamSynchronize(s->stream));
     *out = s;
     return DPSNN_OK;
@@ -504,6 +539,7 @@ void sim_destroy(sim_t* s) {
   else (void)hipDeviceSynchronize();
   for (DevBuf& b : s->bufs) (void)hipFree(b.p);
   for (Snapshot& sn : s->snaps) (void)hipFree(sn.blob.p);
+  for (Snapshot& sn : s->ckpts) (void)hipFree(sn.blob.p);
   for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
   if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -537,7 +573,7 @@ static void direct_step(sim& s, std::vector<std::pair<int, size_t>>& marks, size
   } else {
     HIPCHK(launch_step(s, u, s.delivery, s.block, -1));
   }
-  if (s.ras_off && u < s.cfg.record_steps) {
+  if (s.ras_off && u < s.cfg.record_steps && !s.recompute) {
     if (s.timing) HIPCHK(hipEventRecord(mark(2), s.stream));
     HIPCHK(launch_raster(s, u));
     if (s.timing) HIPCHK(hipEventRecord(s.events[marks.back().second + 1], s.stream));
@@ -600,6 +636,15 @@ int sim_step(sim_t* s, int64_t n_steps) {
     size_t ev_used = 0;
     int64_t left = n_steps;
     while (left > 0) {
+      if (s->wfx) {  // train mode: direct launches, a checkpoint every ckpt_every steps
+        direct_step(*s, marks, ev_used);
+        left -= 1;
+        if (s->now % s->cfg.ckpt_every == 0) {
+          save_into_ckpt(*s, (size_t)(s->now / s->cfg.ckpt_every));
+          s->ckpts[(size_t)(s->now / s->cfg.ckpt_every)].epoch = s->epoch;
+        }
+        continue;
+      }
       const int32_t k = s->graph_steps;
       const bool rec_all = s->ras_off && s->now + k <= s->cfg.record_steps;
       const bool rec_none = !s->ras_off || s->now >= s->cfg.record_steps;
@@ -823,33 +868,77 @@ int sim_read_synapses(sim_t* s, int32_t net, int64_t i0, int64_t i1, int64_t* ro
   }
 }
 
+}  // extern "C"
+
+namespace {
+
+void save_into(sim& s, Snapshot& sn) {
+  size_t parts[kSnapParts];
+  void* srcs[kSnapParts];
+  snapshot_parts(s, parts, srcs);
+  size_t total = 0;
+  for (size_t p : parts) total += (p + 255) & ~(size_t)255;
+  if (sn.blob.bytes < total) {
+    (void)hipFree(sn.blob.p);
+    sn.blob.p = nullptr;
+    if (hipMalloc(&sn.blob.p, total) != hipSuccess) {
+      (void)hipGetLastError();
+      sn.blob.bytes = 0;
+      throw Fail{DPSNN_ENOMEM, "snapshot allocation failed"};
+    }
+    sn.blob.bytes = total;
+  }
+  size_t off = 0;
+  for (int q = 0; q < kSnapParts; ++q) {
+    if (parts[q])
+      HIPCHK(hipMemcpyAsync((char*)sn.blob.p + off, srcs[q], parts[q], hipMemcpyDeviceToDevice, s.stream));
+    off += (parts[q] + 255) & ~(size_t)255;
+  }
+  sn.valid = true;
+  sn.now = s.now;
+}
+
+void restore_from(sim& s, const Snapshot& sn) {
+  if (!sn.valid) throw Fail{DPSNN_ESTATE, "no snapshot in slot"};
+  size_t parts[kSnapParts];
+  void* dsts[kSnapParts];
+  snapshot_parts(s, parts, dsts);
+  size_t total = 0;
+  for (size_t p : parts) total += (p + 255) & ~(size_t)255;
+  if (total > sn.blob.bytes) throw Fail{DPSNN_ESTATE, "snapshot was taken with a different layout"};
+  size_t off = 0;
+  for (int q = 0; q < kSnapParts; ++q) {
+    if (parts[q])
+      HIPCHK(hipMemcpyAsync(dsts[q], (char*)sn.blob.p + off, parts[q], hipMemcpyDeviceToDevice, s.stream));
+    off += (parts[q] + 255) & ~(size_t)255;
+  }
+  s.now = sn.now;
+  // the push ring is a function of the spike history: rebuild it
+  if (s.delivery == DPSNN_DELIVERY_PUSH) ring_from_history(s);
+}
+
+// Train mode: a state from another recorded window (or a change of weights or parameters
+// after step 0) breaks the window; sim_backward then refuses until sim_rewind.
+void break_window(sim& s) {
+  ++s.epoch;
+  if (s.now == 0 && !s.ckpts.empty()) s.ckpts[0].epoch = s.epoch;
+}
+
+void save_into_ckpt(sim& s, size_t m) {
+  if (s.ckpts.size() <= m) s.ckpts.resize(m + 1);
+  save_into(s, s.ckpts[m]);
+}
+
+}  // namespace
+
+extern "C" {
+
 int sim_save(sim_t* s, int32_t slot) {
   if (!s) return DPSNN_EINVAL;
   try {
     if (slot < 0 || slot >= 64) throw Fail{DPSNN_EINVAL, "slot out of range"};
-    size_t parts[6];
-    void* srcs[6];
-    snapshot_parts(*s, parts, srcs);
-    size_t total = 0;
-    for (size_t p : parts) total += (p + 255) & ~(size_t)255;
-    Snapshot& sn = s->snaps[slot];
-    if (sn.blob.bytes < total) {
-      (void)hipFree(sn.blob.p);
-      sn.blob.p = nullptr;
-      if (hipMalloc(&sn.blob.p, total) != hipSuccess) {
-        (void)hipGetLastError();
-        sn.blob.bytes = 0;
-        throw Fail{DPSNN_ENOMEM, "snapshot allocation failed"};
-      }
-      sn.blob.bytes = total;
-    }
-    size_t off = 0;
-    for (int q = 0; q < 6; ++q) {
-      if (parts[q]) HIPCHK(hipMemcpyAsync((char*)sn.blob.p + off, srcs[q], parts[q], hipMemcpyDeviceToDevice, s->stream));
-      off += (parts[q] + 255) & ~(size_t)255;
-    }
-    sn.valid = true;
-    sn.now = s->now;
+    save_into(*s, s->snaps[slot]);
+    s->snaps[slot].epoch = s->epoch;
     return DPSNN_OK;
   } catch (const Fail& f) {
     return finish(s, f);
@@ -859,22 +948,10 @@ int sim_save(sim_t* s, int32_t slot) {
 int sim_restore(sim_t* s, int32_t slot) {
   if (!s) return DPSNN_EINVAL;
   try {
-    if (slot < 0 || slot >= 64 || !s->snaps[slot].valid) throw Fail{DPSNN_ESTATE, "no snapshot in slot"};
-    Snapshot& sn = s->snaps[slot];
-    size_t parts[6];
-    void* dsts[6];
-    snapshot_parts(*s, parts, dsts);
-    size_t total = 0;
-    for (size_t p : parts) total += (p + 255) & ~(size_t)255;
-    if (total > sn.blob.bytes) throw Fail{DPSNN_ESTATE, "snapshot was taken with a different layout"};
-    size_t off = 0;
-    for (int q = 0; q < 6; ++q) {
-      if (parts[q]) HIPCHK(hipMemcpyAsync(dsts[q], (char*)sn.blob.p + off, parts[q], hipMemcpyDeviceToDevice, s->stream));
-      off += (parts[q] + 255) & ~(size_t)255;
-    }
-    s->now = sn.now;
-    // the push ring is a function of the spike history: rebuild it
-    if (s->delivery == DPSNN_DELIVERY_PUSH) ring_from_history(*s);
+    if (slot < 0 || slot >= 64) throw Fail{DPSNN_EINVAL, "slot out of range"};
+    const bool same_window = s->snaps[slot].epoch == s->epoch;
+    restore_from(*s, s->snaps[slot]);
+    if (s->wfx && !same_window) break_window(*s);
     return DPSNN_OK;
   } catch (const Fail& f) {
     return finish(s, f);
@@ -887,6 +964,7 @@ int sim_set_params(sim_t* s, double tau_m, double g_ahp) {
   s->cfg.tau_m = tau_m;
   s->cfg.g_ahp = g_ahp;
   set_constants(*s);
+  if (s->wfx) break_window(*s);
   return DPSNN_OK;
 }
 
@@ -936,26 +1014,129 @@ int sim_get_timing(sim_t* s, double* ms, int32_t n) {
   return DPSNN_OK;
 }
 
+static void need_train(const sim& s) {
+  if (!s.wfx) throw Fail{DPSNN_ESTATE, "not in train mode"};
+}
+
 int sim_set_weights(sim_t* s, const float* w) {
   if (!s) return DPSNN_EINVAL;
-  s->err = "train mode is not available in this build";
-  (void)w;
-  return DPSNN_ESTATE;
+  try {
+    need_train(*s);
+    if (!w) throw Fail{DPSNN_EINVAL, "w is NULL"};
+    HIPCHK(launch_canon_map(*s, 0, w, s->wf32));
+    HIPCHK(launch_quantise(*s));
+    break_window(*s);
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
 }
 
 int sim_get_weights(sim_t* s, float* w) {
   if (!s) return DPSNN_EINVAL;
-  s->err = "train mode is not available in this build";
-  (void)w;
-  return DPSNN_ESTATE;
+  try {
+    need_train(*s);
+    if (!w) throw Fail{DPSNN_EINVAL, "w is NULL"};
+    HIPCHK(launch_canon_map(*s, 1, s->wf32, w));
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
 }
 
+int sim_rewind(sim_t* s) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    need_train(*s);
+    restore_from(*s, s->ckpts[0]);
+    ++s->epoch;
+    s->ckpts[0].epoch = s->epoch;
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+int sim_column_rates(sim_t* s, float* rates) {
+  if (!s) return DPSNN_EINVAL;
+  try {
+    if (!rates) throw Fail{DPSNN_EINVAL, "rates is NULL"};
+    if (s->now == 0) throw Fail{DPSNN_ESTATE, "no steps since step 0"};
+    const double scale = 1000.0 / ((double)s->npc * (double)s->now * s->cfg.dt);
+    HIPCHK(launch_column_rates(*s, (float)scale, rates));
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+}
+
+// Reverse pass over the recorded window [0, T): the end state is set aside, then for each
+// checkpoint segment from the last to the first the forward is re-run from its checkpoint
+// with the trajectory recorded, and the adjoint recursion runs backwards through it.  The
+// adjoint ring carries nu across segment boundaries.  Finally the end state comes back.
 int sim_backward(sim_t* s, const float* grad_rates, float* grad_w, double* grad_tau_m,
                  double* grad_g_ahp) {
   if (!s) return DPSNN_EINVAL;
-  (void)grad_rates; (void)grad_w; (void)grad_tau_m; (void)grad_g_ahp;
-  s->err = "train mode is not available in this build";
-  return DPSNN_ESTATE;
+  if (s->sticky) { s->err = "simulation is in a failed state"; return DPSNN_ESTATE; }
+  try {
+    need_train(*s);
+    if (!grad_rates || !grad_w) throw Fail{DPSNN_EINVAL, "grad_rates and grad_w are required"};
+    const int64_t T = s->now, K = s->cfg.ckpt_every;
+    if (T == 0) throw Fail{DPSNN_ESTATE, "nothing recorded: no steps since step 0"};
+    const int64_t M = (T + K - 1) / K;
+    if ((int64_t)s->ckpts.size() < M) throw Fail{DPSNN_ESTATE, "recorded window is incomplete; call sim_rewind"};
+    for (int64_t m = 0; m < M; ++m)
+      if (!s->ckpts[(size_t)m].valid || s->ckpts[(size_t)m].epoch != s->epoch)
+        throw Fail{DPSNN_ESTATE, "recorded window was broken by a restore, a weight or a "
+                                 "parameter change; call sim_rewind"};
+    const size_t N = (size_t)s->n_neurons;
+    save_into(*s, s->bwd_end);
+    HIPCHK(hipMemsetAsync(s->nu_ring, 0, sizeof(float) * (size_t)s->dh * N, s->stream));
+    HIPCHK(hipMemsetAsync(s->adj_lam, 0, sizeof(float) * N, s->stream));
+    HIPCHK(hipMemsetAsync(s->adj_mu, 0, sizeof(float) * N, s->stream));
+    HIPCHK(hipMemsetAsync(s->adj_part, 0, sizeof(double) * 2 * N, s->stream));
+    HIPCHK(hipMemsetAsync(s->gw, 0, sizeof(float) * ((size_t)s->n_syn_padded + 4), s->stream));
+    const float scale = (float)(1000.0 / ((double)s->npc * (double)T * s->cfg.dt));
+    const bool timing = s->timing;
+    s->timing = false;
+    std::vector<std::pair<int, size_t>> marks;
+    size_t ev_used = 0;
+    for (int64_t m = M - 1; m >= 0; --m) {
+      const int64_t u0 = m * K, u1 = std::min(T, u0 + K);
+      restore_from(*s, s->ckpts[(size_t)m]);
+      s->rec_on = true;
+      s->recompute = true;
+      s->rec_base = u0;
+      try {
+        while (s->now < u1) direct_step(*s, marks, ev_used);
+      } catch (...) {
+        s->rec_on = false;
+        s->recompute = false;
+        s->timing = timing;
+        throw;
+      }
+      s->rec_on = false;
+      s->recompute = false;
+      s->rec_base = u0;
+      for (int64_t u = u1 - 1; u >= u0; --u)
+        HIPCHK(launch_adjoint_step(*s, u, grad_rates, scale, (float)s->cfg.surrogate_beta));
+    }
+    s->timing = timing;
+    HIPCHK(launch_reduce_parts(*s, s->adj_out));
+    double out[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(out, s->adj_out, sizeof(out), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(launch_canon_map(*s, 1, s->gw, grad_w));
+    restore_from(*s, s->bwd_end);
+    HIPCHK(hipStreamSynchronize(s->stream));
+    // P_m = exp(-dt / tau_m): dP_m/dtau_m = P_m dt / tau_m^2;  gamma = g_AHP dt
+    const double dt = s->cfg.dt, tau = s->cfg.tau_m;
+    const double pm = exp(-dt / tau);
+    if (grad_tau_m) *grad_tau_m = out[0] * pm * dt / (tau * tau);
+    if (grad_g_ahp) *grad_g_ahp = out[1] * dt;
+    return DPSNN_OK;
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
 }
 
 }  // extern "C"

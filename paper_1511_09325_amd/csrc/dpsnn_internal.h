@@ -141,6 +141,7 @@ struct StepArgs {
   int32_t* ring;              // push only
   unsigned long long* net_cnt;  // [n_nets][kCounters]: spikes, e_rec, e_ext, synapse records
                                 // read, synapses delivered (arrival form)
+  unsigned long long* col_spk;  // [n_cols]: spikes per column
   // train-mode trajectory recording (null when off): [steps][N]
   float* rec_vprev;
   float* rec_caprev;
@@ -169,7 +170,8 @@ struct DevBuf {
 struct Snapshot {
   bool valid = false;
   int64_t now = 0;
-  DevBuf blob;  // v | ca | ref | hist_cnt | hist_ids | net_cnt
+  int64_t epoch = 0;  // train mode: recorded window the state belongs to
+  DevBuf blob;  // v | ca | ref | hist_cnt | hist_ids | net_cnt | col_spk
 };
 
 }  // namespace dpsnn
@@ -220,12 +222,23 @@ struct sim {
   int32_t* ras_ids = nullptr;      // [raster_capacity], global neuron ids
   int64_t* ras_colofs = nullptr;   // [C] scratch
   int32_t* flags = nullptr;        // [4]: raster overflow
+  unsigned long long* col_spk = nullptr;
   // train mode
   float *rec_vprev = nullptr, *rec_caprev = nullptr, *rec_vt = nullptr;
   uint8_t* rec_flags = nullptr;
   int64_t rec_steps = 0;
   int64_t rec_base = 0;
   bool rec_on = false;
+  float* gw = nullptr;             // weight gradient, padded layout
+  float* nu_ring = nullptr;        // [dh][N] adjoint of V~ of the last dh steps
+  float *adj_gsum = nullptr, *adj_lam = nullptr, *adj_mu = nullptr;
+  double* adj_part = nullptr;      // [2][N]
+  double* adj_out = nullptr;       // [2]
+  int64_t* canon_start = nullptr;  // [N+1] first canonical synapse index of each row
+  std::vector<dpsnn::Snapshot> ckpts;  // state at steps 0, K, 2K, ... of the recorded window
+  dpsnn::Snapshot bwd_end;             // state at the end of the window during sim_backward
+  int64_t epoch = 0;               // recorded-window counter (rewind, weight or parameter change)
+  bool recompute = false;          // re-running a checkpoint segment: no raster recording
 
   int64_t now = 0;
   int32_t delivery = DPSNN_DELIVERY_ARRIVAL;
@@ -268,6 +281,12 @@ hipError_t launch_pend_view(const sim& s, int32_t* pend, int32_t g0, int32_t g1)
 hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1, int32_t* tgt,
                               uint8_t* dly, int16_t* wq, const int64_t* out_off);
 hipError_t launch_quantise(const sim& s);
+hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates, float scale,
+                               float beta);
+hipError_t launch_reduce_parts(const sim& s, double* out);
+hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst);
+hipError_t launch_weights_from_records(const sim& s);
+hipError_t launch_column_rates(const sim& s, float scale, float* rates);
 int64_t scan_scratch_len(int64_t n);
 
 StepArgs make_step_args(const sim& s);

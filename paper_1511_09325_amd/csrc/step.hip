@@ -386,6 +386,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       int32_t tot = 0;
       for (int q = 0; q < nch; ++q) tot += scnt[tid * nch + q];
       a.hist_cnt[(int64_t)slot_u * a.n_cols + s_col[tid]] = tot;
+      if (tot) a.col_spk[s_col[tid]] += (unsigned long long)tot;
       my_spk = (unsigned long long)tot;
     }
     const unsigned long long spk_all = block_sum_u64<BLOCK>(my_spk, red);
@@ -456,6 +457,7 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u_arg
     const unsigned long long rec_all = block_sum_u64<BLOCK>(my_rec, red);
     if (threadIdx.x == 0) {
       a.hist_cnt[(int64_t)slot_u * a.n_cols + g] = running;
+      if (running) a.col_spk[g] += (unsigned long long)running;
       atomicAdd(&a.net_cnt[kCounters * net + 0], (unsigned long long)running);
       atomicAdd(&a.net_cnt[kCounters * net + 1], rec_all);
       atomicAdd(&a.net_cnt[kCounters * net + 2], ext_all);
@@ -603,6 +605,7 @@ StepArgs make_step_args(const sim& s) {
   a.hist_ids = s.hist_ids;
   a.ring = s.ring;
   a.net_cnt = s.net_cnt;
+  a.col_spk = s.col_spk;
   if (s.rec_on) {
     a.rec_vprev = s.rec_vprev;
     a.rec_caprev = s.rec_caprev;

@@ -27,7 +27,7 @@ def _stream_ptr(stream):
 
 def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, block: int = 0,
                 tile: tuple[int, int] = (0, 0), record_steps: int = 0, raster_capacity: int = 0,
-                train_mode: bool = False, ckpt_every: int = 50):
+                train_mode: bool = False, ckpt_every: int = 50, surrogate_beta: float = 5.0):
     """sim_config_t from one parameter dict, or a list of them (batched form: all share the
     column recipe of the first; grid shape, seed and external rate are per network)."""
     plist = params if isinstance(params, list) else [params]
@@ -50,6 +50,7 @@ def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, b
     c.tile_x, c.tile_y = int(tile[0]), int(tile[1])
     c.record_steps, c.raster_capacity = int(record_steps), int(raster_capacity)
     c.train_mode, c.ckpt_every = int(bool(train_mode)), int(ckpt_every)
+    c.surrogate_beta = float(surrogate_beta)
     return c, nets
 
 
@@ -57,15 +58,17 @@ class Simulation:
     def __init__(self, params, *, delivery: int = L.DELIVERY_AUTO, block: int = 0,
                  tile: tuple[int, int] = (0, 0), record_steps: int = 0,
                  raster_capacity: int | None = None, train_mode: bool = False,
-                 ckpt_every: int = 50, stream=None):
+                 ckpt_every: int = 50, surrogate_beta: float = 5.0, stream=None):
         self.params = params if isinstance(params, list) else [params]
         if raster_capacity is None:
             n = sum(p["rows"] * p["cols"] * p["npc"] for p in self.params)
             raster_capacity = max(1, int(record_steps * n * 0.2)) if record_steps else 0
         cfg, self._nets = make_config(params, delivery=delivery, block=block, tile=tile,
                                       record_steps=record_steps, raster_capacity=raster_capacity,
-                                      train_mode=train_mode, ckpt_every=ckpt_every)
+                                      train_mode=train_mode, ckpt_every=ckpt_every,
+                                      surrogate_beta=surrogate_beta)
         self._cfg = cfg
+        self.train_mode = bool(train_mode)
         self.lib = L.lib()
         h = C.c_void_p()
         L.check(self.lib.sim_create(C.byref(cfg), _stream_ptr(stream), C.byref(h)), None)
@@ -216,3 +219,76 @@ class Simulation:
         L.check(self.lib.sim_get_timing(self.h, ms, 6), self.h)
         names = ("update", "deliver", "raster")
         return {names[c]: {"ms": ms[c], "launches": int(ms[3 + c])} for c in range(3)}
+
+    # -- train mode ---------------------------------------------------------------------------
+    @staticmethod
+    def _dev(t, dtype_name: str, n: int):
+        import torch
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == getattr(torch, dtype_name)
+                and t.numel() == n):
+            raise ValueError(f"expected a contiguous device {dtype_name} tensor of {n} elements")
+        return C.c_void_p(t.data_ptr())
+
+    def rewind(self):
+        L.check(self.lib.sim_rewind(self.h), self.h)
+
+    def set_weights(self, w):
+        """Master weights (device float32 [n_synapses], mV, canonical order)."""
+        L.check(self.lib.sim_set_weights(self.h, self._dev(w, "float32", self.n_synapses)), self.h)
+
+    def get_weights(self):
+        import torch
+        w = torch.empty(self.n_synapses, dtype=torch.float32, device="cuda")
+        L.check(self.lib.sim_get_weights(self.h, self._dev(w, "float32", self.n_synapses)), self.h)
+        return w
+
+    def column_rates(self):
+        """Mean rate of every column since step 0 (Hz), device float32 [n_cols]."""
+        import torch
+        r = torch.empty(self.n_cols, dtype=torch.float32, device="cuda")
+        L.check(self.lib.sim_column_rates(self.h, self._dev(r, "float32", self.n_cols)), self.h)
+        return r
+
+    def backward(self, grad_rates):
+        """Surrogate-gradient backward through [0, now): returns (dL/dw as device float32
+        [n_synapses] in canonical order, dL/dtau_m, dL/dg_AHP)."""
+        import torch
+        gr = grad_rates.detach().to(torch.float32).contiguous()
+        gw = torch.empty(self.n_synapses, dtype=torch.float32, device="cuda")
+        gt, gg = C.c_double(), C.c_double()
+        L.check(self.lib.sim_backward(self.h, self._dev(gr, "float32", self.n_cols),
+                                      self._dev(gw, "float32", self.n_synapses), C.byref(gt),
+                                      C.byref(gg)), self.h)
+        return gw, gt.value, gg.value
+
+
+def _column_rates_fn():
+    import torch
+
+    class ColumnRates(torch.autograd.Function):
+        """rates = simulate(w, tau_m, g_AHP) over `steps` steps from the initial state;
+        the backward is the library's surrogate-gradient adjoint."""
+
+        @staticmethod
+        def forward(ctx, w, tau_m, g_ahp, sim, steps):
+            ctx.devs = tuple(x.device if torch.is_tensor(x) else None for x in (tau_m, g_ahp))
+            sim.rewind()
+            sim.set_params(float(tau_m), float(g_ahp))
+            sim.set_weights(w.detach().contiguous())
+            sim.step(int(steps))
+            ctx.sim = sim
+            return sim.column_rates()
+
+        @staticmethod
+        def backward(ctx, grad_rates):
+            gw, gt, gg = ctx.sim.backward(grad_rates)
+            scal = [None if d is None else torch.tensor(v, dtype=torch.float64, device=d)
+                    for v, d in zip((gt, gg), ctx.devs)]
+            return gw, scal[0], scal[1], None, None
+
+    return ColumnRates
+
+
+def column_rates(sim: Simulation, w, tau_m, g_ahp, steps: int):
+    """Differentiable mean column rates of a train-mode Simulation (see ColumnRates)."""
+    return _column_rates_fn().apply(w, tau_m, g_ahp, sim, steps)

@@ -1,0 +1,222 @@
+"""Train mode on the GPU: the surrogate-gradient backward against the FP64 oracle adjoint.
+
+The forward of train mode must reproduce the plain simulation bit for bit while the master
+weights are the int16 weights (rint(w_q 2^-14 2^16) = 4 w_q).  The GPU reverse recursion runs
+in float32 (FP64 only for the two scalar partial sums) over the trajectory it re-records
+from its checkpoints; the oracle runs the same recursion in FP64 over the oracle's own
+float32 trajectory, which is bit-identical to the GPU's.  The float32 recursion has about
+T * 2^-24 relative error per adjoint value plus summation error over at most a few
+hundred terms per weight, so 1e-4 relative (L2 over the weight gradient, and per scalar)
+has two orders of magnitude of headroom while still catching any wrong term: a dropped
+reset, leak or calcium term changes the result by 1e-2 or more.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1511_09325_amd import DELIVERY_ARRIVAL, DELIVERY_PUSH, Simulation
+from paper_1511_09325_amd import sim as S
+from paper_1511_09325_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BETA = 5.0
+RTOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _targets(n_cols, seed=0):
+    return np.random.default_rng(seed).uniform(2.0, 8.0, size=n_cols)
+
+
+def _grad_rates(rates, targets):
+    """dL/dR for L = mean_c (R_c - target_c)^2."""
+    return 2.0 * (rates - targets) / len(rates)
+
+
+def _oracle_grads(p, T, grad_rates):
+    """FP64 adjoint over the oracle's hard trajectory with dL/ds = dL/dR_c * dR_c/ds."""
+    net = oracle.network(p)
+    ref = oracle.Sim(p, net)
+    ref.record(True)
+    ref.step(T)
+    traj = ref.trajectory(T)
+    traj = dict(traj, s=traj["s"].astype(np.float64))
+    npc = p["npc"]
+    scale = 1000.0 / (npc * T * p["dt"])
+    dl_ds = np.repeat(np.asarray(grad_rates, np.float64) * scale, npc)[None, :].repeat(T, 0)
+    consts = oracle.step_constants(p, single=True)
+    w = net[3].astype(np.float64) / 16384.0
+    gw, gpm, ggam = oracle.adjoint(consts, BETA, net, w, traj, dl_ds)
+    g_tau = gpm * consts["pm"] * p["dt"] / p["tau_m"] ** 2
+    g_g = ggam * p["dt"]
+    rates = traj["s"].reshape(T, -1, npc).sum(axis=(0, 2)) * scale
+    return gw, g_tau, g_g, rates
+
+
+def _rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _gpu_grads(sim, T, grad_rates):
+    import torch
+    sim.rewind()
+    sim.step(T)
+    rates = sim.column_rates().cpu().numpy()
+    gr = torch.tensor(np.asarray(grad_rates, np.float32), device="cuda")
+    gw, gt, gg = sim.backward(gr)
+    return gw.cpu().numpy().astype(np.float64), gt, gg, rates
+
+
+def test_train_forward_is_the_plain_forward():
+    p = W.tiny(3, 3, npc=37, seed=2)
+    T = 120
+    plain = Simulation(p, record_steps=T)
+    train = Simulation(p, record_steps=T, train_mode=True, ckpt_every=16, surrogate_beta=BETA)
+    plain.step(T)
+    train.step(T)
+    assert plain.digest() == train.digest()
+    a, b = plain.read_spikes(0, 0, T), train.read_spikes(0, 0, T)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    # master weights start at the int16 weights
+    w = train.get_weights().cpu().numpy()
+    assert np.array_equal(w, oracle.network(p)[3].astype(np.float32) / np.float32(16384.0))
+
+
+def test_weights_round_trip_and_forward_uses_them():
+    import torch
+    p = W.tiny(2, 2, npc=40, seed=5)
+    T = 80
+    sim = Simulation(p, train_mode=True, ckpt_every=10)
+    w0 = sim.get_weights()
+    rnd = torch.randn(sim.n_synapses, device="cuda", dtype=torch.float32) * 0.05
+    sim.set_weights(rnd)
+    assert torch.equal(sim.get_weights(), rnd)
+    # weights that are exactly the int16 values reproduce the plain run
+    sim.set_weights(w0)
+    sim.rewind()
+    sim.step(T)
+    plain = Simulation(p)
+    plain.step(T)
+    assert sim.digest() == plain.digest()
+
+
+@pytest.mark.parametrize("p,T,K,delivery,tile", [
+    (W.tiny(2, 2, npc=40, seed=3, ext_rate_hz=3.4), 100, 16, DELIVERY_ARRIVAL, (0, 0)),
+    (W.tiny(3, 4, npc=50, seed=6, ext_rate_hz=3.4), 150, 40, DELIVERY_ARRIVAL, (2, 3)),
+    (W.tiny(2, 3, npc=40, seed=9, d_min=2, d_max=6, ext_rate_hz=3.6), 90, 7, DELIVERY_PUSH,
+     (0, 0)),
+], ids=["2x2-K16", "3x4-K40-tile2x3", "2x3-d2..6-K7-push"])
+def test_gpu_adjoint_matches_fp64_oracle(p, T, K, delivery, tile):
+    C = p["rows"] * p["cols"]
+    sim = Simulation(p, train_mode=True, ckpt_every=K, surrogate_beta=BETA, delivery=delivery,
+                     tile=tile)
+    sim.step(T)
+    rates = sim.column_rates().cpu().numpy()
+    gr = _grad_rates(rates.astype(np.float64), _targets(C))
+    ogw, ogt, ogg, orates = _oracle_grads(p, T, gr.astype(np.float32))
+    assert np.allclose(rates, orates, rtol=1e-6, atol=0)
+    assert orates.sum() > 0
+    gw, gt, gg, _ = _gpu_grads(sim, T, gr)
+    assert np.count_nonzero(ogw) > 0.05 * len(ogw)
+    assert _rel_l2(gw, ogw) <= RTOL, _rel_l2(gw, ogw)
+    assert abs(gt - ogt) <= RTOL * abs(ogt), (gt, ogt)
+    assert abs(gg - ogg) <= RTOL * abs(ogg), (gg, ogg)
+
+
+def test_batched_networks_backward_per_network():
+    """Two networks in one handle: each network's slice of the gradient is its own."""
+    import torch
+    p1 = W.tiny(2, 2, npc=40, seed=3, ext_rate_hz=3.4)
+    p2 = W.tiny(2, 3, npc=40, seed=4, ext_rate_hz=3.6)
+    T = 100
+    sim = Simulation([p1, p2], train_mode=True, ckpt_every=25, surrogate_beta=BETA)
+    sim.step(T)
+    rates = sim.column_rates().cpu().numpy().astype(np.float64)
+    gr = _grad_rates(rates, _targets(len(rates), seed=4)).astype(np.float32)
+    gw, _, _ = sim.backward(torch.tensor(gr, device="cuda"))
+    gw = gw.cpu().numpy().astype(np.float64)
+    s1 = len(oracle.network(p1)[1])
+    o1 = _oracle_grads(p1, T, gr[:4])[0]
+    o2 = _oracle_grads(p2, T, gr[4:])[0]
+    assert _rel_l2(gw[:s1], o1) <= RTOL
+    assert _rel_l2(gw[s1:], o2) <= RTOL
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    p = W.tiny(3, 3, npc=40, seed=12, ext_rate_hz=3.4)
+    T = 96
+    gr = _targets(9, seed=2).astype(np.float32) - 5.0
+    outs = []
+    for K in (1, 13, 96, 500):
+        sim = Simulation(p, train_mode=True, ckpt_every=K, surrogate_beta=BETA)
+        outs.append(_gpu_grads(sim, T, gr))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert (o[1], o[2]) == (outs[0][1], outs[0][2])
+
+
+def test_backward_restores_the_end_state_and_is_repeatable():
+    import torch
+    p = W.tiny(2, 3, npc=40, seed=21, ext_rate_hz=3.4)
+    T = 70
+    sim = Simulation(p, train_mode=True, ckpt_every=9, record_steps=T + 30)
+    sim.step(T)
+    d_end = sim.digest()
+    gr = torch.ones(sim.n_cols, device="cuda")
+    g1 = sim.backward(gr)
+    assert sim.digest() == d_end and sim.now == T
+    g2 = sim.backward(gr)
+    assert torch.equal(g1[0], g2[0]) and g1[1:] == g2[1:]
+    # stepping on after a backward continues the same trajectory as a plain run
+    sim.step(30)
+    plain = Simulation(p, record_steps=T + 30)
+    plain.step(T + 30)
+    assert sim.digest() == plain.digest()
+    a, b = sim.read_spikes(0, 0, T + 30), plain.read_spikes(0, 0, T + 30)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_broken_window_is_refused_until_rewind():
+    import torch
+    p = W.tiny(2, 2, npc=40, seed=3)
+    sim = Simulation(p, train_mode=True, ckpt_every=10)
+    sim.step(20)
+    sim.set_weights(sim.get_weights())
+    gr = torch.ones(sim.n_cols, device="cuda")
+    with pytest.raises(RuntimeError, match="sim_rewind"):
+        sim.backward(gr)
+    sim.rewind()
+    with pytest.raises(RuntimeError, match="nothing recorded"):
+        sim.backward(gr)
+    sim.step(20)
+    sim.backward(gr)
+    plain = Simulation(p)
+    with pytest.raises(RuntimeError, match="train mode"):
+        plain.backward(gr)
+
+
+def test_autograd_function_matches_backward():
+    import torch
+    p = W.tiny(2, 2, npc=40, seed=3, ext_rate_hz=3.4)
+    T = 100
+    sim = Simulation(p, train_mode=True, ckpt_every=20, surrogate_beta=BETA)
+    w = sim.get_weights().clone().requires_grad_(True)
+    tau = torch.tensor(p["tau_m"], dtype=torch.float64, requires_grad=True)
+    g = torch.tensor(p["g_ahp"], dtype=torch.float64, requires_grad=True)
+    rates = S.column_rates(sim, w, tau, g, T)
+    seen = []
+    rates.register_hook(lambda t: seen.append(t.detach().clone()))
+    tgt = torch.tensor(_targets(4), dtype=torch.float32, device="cuda")
+    loss = ((rates - tgt) ** 2).mean()
+    loss.backward()
+    gw, gt, gg = sim.backward(seen[0])
+    assert torch.equal(w.grad, gw)
+    assert float(tau.grad) == gt and float(g.grad) == gg
