@@ -135,6 +135,58 @@ def batched_leg(torch, steps=1000, warmup=50, graph_steps=50):
             "mean_rate_hz": spk_b / (n_neurons * steps * 1e-3)}
 
 
+def fwd_bwd_leg(torch, iters=3):
+    """Forward+backward on the 4x4 grid (19,840 neurons), 500 ms, checkpoints every 50
+    steps: loss = mean over columns of (rate - target)^2 with seeded U(2, 8) Hz targets,
+    surrogate-gradient backward to the float32 weights, tau_m and g_AHP.  Timed per
+    training iteration (rewind, forward, rates, loss, backward), against the plain forward
+    of the same network on the same GPU."""
+    from paper_1511_09325_amd import Simulation
+    from paper_1511_09325_amd import sim as S
+    from paper_1511_09325_amd import workloads as W
+    preset = W.FWD_BWD_4X4
+    p, T, K = preset["params"], preset["steps"], preset["ckpt_every"]
+    plain = Simulation(p)
+    plain.save(0)
+    plain.step(T)                       # warm-up pass
+    plain.restore(0)
+    t_plain, ev_plain, _ = _timed_run(plain, T, torch)
+    del plain
+    sim = Simulation(p, train_mode=True, ckpt_every=K, surrogate_beta=5.0)
+    target = torch.tensor(W.target_rates(sim.n_cols, 1), device="cuda")
+    w = sim.get_weights().clone().requires_grad_(True)
+    tau = torch.tensor(p["tau_m"], dtype=torch.float64, requires_grad=True)
+    g = torch.tensor(p["g_ahp"], dtype=torch.float64, requires_grad=True)
+
+    def iteration():
+        for x in (w, tau, g):
+            x.grad = None
+        rates = S.column_rates(sim, w, tau, g, T)
+        loss = ((rates - target) ** 2).mean()
+        loss.backward()
+        return float(loss)
+
+    iteration()                          # warm-up
+    torch.cuda.synchronize()
+    times, losses = [], []
+    for _ in range(iters):
+        t0 = time.perf_counter()
+        losses.append(iteration())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    st = sim.stats()
+    t_it = min(times)
+    return {"workload": preset["name"] + ", checkpoints every %d steps" % K,
+            "neurons": sim.n_neurons, "synapses": sim.n_synapses, "steps": T,
+            "loss": losses[-1], "grad_w_norm": float(w.grad.norm()),
+            "grad_tau_m": float(tau.grad), "grad_g_ahp": float(g.grad),
+            "plain_forward_ms": t_plain * 1e3, "fwd_bwd_ms": t_it * 1e3,
+            "fwd_bwd_over_plain": t_it / t_plain,
+            "plain_events_per_s": ev_plain / t_plain,
+            "fwd_bwd_events_per_s": (st["e_rec"] + st["e_ext"]) / t_it,
+            "fwd_bwd_sim_ms_per_wall_s": T * p["dt"] / t_it}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +198,7 @@ def main():
     ap.add_argument("--tile", default="auto", help="arrival tile of target columns, e.g. 4x4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB once (a reference kernel of known "
                          "traffic for hardware byte counters)")
@@ -261,6 +314,9 @@ def main():
     if not args.no_batched:
         log("batched leg: 64 networks, one launch per step, vs 64 sequential runs")
         out["batched"] = batched_leg(torch)
+    if not args.no_fwd_bwd:
+        log("forward+backward leg: 4x4, 500 steps, vs the plain forward")
+        out["fwd_bwd"] = fwd_bwd_leg(torch)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline()

@@ -82,6 +82,10 @@ def lib():
             "orc_initial_v": (C.c_float, [cp, C.c_int64]),
             "orc_ext_counts": (None, [cp, C.c_int64, C.c_int64, C.c_int64, i32p]),
             "orc_neuron_update": (C.c_int, [cp, C.c_int64, C.c_int64, C.c_int32, f32p, f32p, u8p]),
+            "orc_update_many": (None, [cp, C.c_int64, C.c_int64, C.c_int64, i32p, f32p, f32p,
+                                       u8p, u8p]),
+            "orc_input_brute": (None, [cp, C.c_int64, i64p, C.c_int64, C.c_int64, u8p,
+                                       C.c_int64, C.c_int64, i32p]),
             "orc_sim_consumed": (C.c_int64, [C.c_void_p]),
             "orc_sim_create": (C.c_void_p, [cp, C.c_int64, i64p, i32p, u8p, i32p]),
             "orc_sim_destroy": (None, [C.c_void_p]),
@@ -209,6 +213,35 @@ def neuron_update(p: dict, j: int, u: int, rec_input: int, v: float, ca: float, 
     s = lib().orc_neuron_update(C.byref(cfg), j, u, int(rec_input), C.byref(vv), C.byref(cc),
                                 C.byref(rr))
     return bool(s), np.float32(vv.value), np.float32(cc.value), int(rr.value)
+
+
+def update_many(p: dict, u: int, rec_input, v, ca, ref, j0: int = 0):
+    """neuron_update for neurons j0 .. j0+n-1 at step u on copies of the given state;
+    returns (spike flags, v, ca, ref)."""
+    cfg = make_config(p)
+    ri = np.ascontiguousarray(rec_input, np.int32)
+    v2 = np.array(v, np.float32)
+    c2 = np.array(ca, np.float32)
+    r2 = np.array(ref, np.uint8)
+    spk = np.zeros(len(ri), np.uint8)
+    lib().orc_update_many(C.byref(cfg), u, j0, len(ri), _ptr(ri, C.c_int32),
+                          _ptr(v2, C.c_float), _ptr(c2, C.c_float), _ptr(r2, C.c_uint8),
+                          _ptr(spk, C.c_uint8))
+    return spk, v2, c2, r2
+
+
+def input_brute(p: dict, targets, t_arr: int, t_emit_max: int, mask, mask_t0: int):
+    """Recurrent input arriving at step t_arr at each target, summed over every synapse
+    (decided again pair by pair) whose source spiked at an emission step <= t_emit_max;
+    mask[e - mask_t0][i] marks the spikes of step e."""
+    cfg = make_config(p)
+    t = np.ascontiguousarray(targets, np.int64)
+    m = np.ascontiguousarray(mask, np.uint8)
+    assert m.ndim == 2 and m.shape[1] == n_neurons(p)
+    out = np.zeros(len(t), np.int32)
+    lib().orc_input_brute(C.byref(cfg), len(t), _ptr(t, C.c_int64), t_arr, t_emit_max,
+                          _ptr(m, C.c_uint8), mask_t0, m.shape[0], _ptr(out, C.c_int32))
+    return out
 
 
 def initial_v(p: dict, j: int) -> float:

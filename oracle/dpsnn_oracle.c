@@ -344,6 +344,58 @@ int orc_neuron_update(const orc_config_t* cfg, int64_t j, int64_t u, int32_t rec
   return neuron_update(&k, (uint32_t)rec_input, n_ext, v, ca, ref, &vt, &refr, &a);
 }
 
+void orc_update_many(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n,
+                     const int32_t* rec_input, float* v, float* ca, uint8_t* ref, uint8_t* spk) {
+  consts_t k = constants_of(cfg);
+  int32_t* n_ext = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  orc_ext_counts(cfg, u, j0, n, n_ext);
+  for (int64_t q = 0; q < n; ++q) {
+    float vt; int refr; uint32_t a;
+    spk[q] = (uint8_t)neuron_update(&k, (uint32_t)rec_input[q], n_ext[q], &v[q], &ca[q], &ref[q],
+                                    &vt, &refr, &a);
+  }
+  free(n_ext);
+}
+
+/* Recurrent input by its definition, without a ring: the sum of the efficacies 4 w_q of
+ * every synapse i -> j of delay d whose source spiked at step e = t_arr - d, over the
+ * emission steps e <= t_emit_max covered by the spike mask.  The candidate sources are
+ * all neurons of the (unique) columns of the 3x3 torus neighbourhood of j's column; each
+ * pair is decided again from the generator's definition. */
+void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets, int64_t t_arr,
+                     int64_t t_emit_max, const uint8_t* mask, int64_t mask_t0, int64_t mask_steps,
+                     int32_t* out) {
+  const int64_t n = (int64_t)cfg->rows * cfg->cols * cfg->npc;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t j = targets[t];
+    const int32_t cj = (int32_t)(j / cfg->npc);
+    const int32_t y = cj / cfg->cols, x = cj % cfg->cols;
+    int32_t cols_seen[9];
+    int nseen = 0;
+    uint32_t acc = 0;
+    for (int dy = -1; dy <= 1; ++dy) {
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int32_t sy = ((y + dy) % cfg->rows + cfg->rows) % cfg->rows;
+        const int32_t sx = ((x + dx) % cfg->cols + cfg->cols) % cfg->cols;
+        const int32_t c = sy * cfg->cols + sx;
+        int dup = 0;
+        for (int q = 0; q < nseen; ++q) dup |= cols_seen[q] == c;
+        if (dup) continue;
+        cols_seen[nseen++] = c;
+        for (int32_t k = 0; k < cfg->npc; ++k) {
+          const int64_t i = (int64_t)c * cfg->npc + k;
+          int32_t d; int16_t w;
+          if (!orc_pair(cfg, i, j, &d, &w)) continue;
+          const int64_t e = t_arr - d;
+          if (e > t_emit_max || e < mask_t0 || e >= mask_t0 + mask_steps) continue;
+          if (mask[(size_t)(e - mask_t0) * (size_t)n + (size_t)i]) acc += (uint32_t)(4 * (int32_t)w);
+        }
+      }
+    }
+    out[t] = (int32_t)acc;
+  }
+}
+
 /* One step u = now (paper section 1: every neuron is updated every step; synaptic work
  * follows the spikes):
  *  1. each neuron takes its input ring[u % D][j] (the slot is cleared), adds its external

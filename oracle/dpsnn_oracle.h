@@ -95,6 +95,18 @@ void orc_ext_counts(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n, i
 int orc_neuron_update(const orc_config_t* cfg, int64_t j, int64_t u, int32_t rec_input, float* v,
                       float* ca, uint8_t* ref);
 
+/* orc_neuron_update for neurons j0 .. j0+n-1 at step u (arrays of n, updated in place;
+ * spk receives the spike flags). */
+void orc_update_many(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n,
+                     const int32_t* rec_input, float* v, float* ca, uint8_t* ref, uint8_t* spk);
+
+/* Brute-force recurrent input (2^-16 mV) arriving at step t_arr at each of nt target
+ * neurons, from the spikes emitted at steps e <= t_emit_max: mask[e - mask_t0][i] != 0 iff
+ * neuron i spiked at step e, for e in [mask_t0, mask_t0 + mask_steps) (no spikes outside). */
+void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets, int64_t t_arr,
+                     int64_t t_emit_max, const uint8_t* mask, int64_t mask_t0, int64_t mask_steps,
+                     int32_t* out);
+
 /* Initial membrane potential of neuron j. */
 float orc_initial_v(const orc_config_t* cfg, int64_t j);
 

@@ -245,3 +245,38 @@ def test_synapse_order_does_not_matter():
     sa, sb = a.state(), b.state()
     for k in ("v", "ca", "ref", "pend"):
         assert np.array_equal(sa[k], sb[k])
+
+
+def test_brute_force_helper_matches_consumed_and_pending_input(tiny_run):
+    """The pair-by-pair brute-force input (used for spot checks of large networks) equals
+    every recurrent input the simulation consumed and everything still pending at the end."""
+    p, _, sim, T = tiny_run
+    n = oracle.n_neurons(p)
+    mask = np.zeros((T, n), np.uint8)
+    for u in range(T):
+        mask[u, sim.spikes(u)] = 1
+    traj = sim.trajectory(T)
+    jfx = np.int64(round(0.3 * 65536))
+    targets = np.arange(n)
+    for u in range(0, T, 7):
+        rec = oracle.input_brute(p, targets, u, u - 1, mask, 0)
+        ext = oracle.ext_counts(p, u).astype(np.int64) * jfx
+        want = (traj["input"][u].astype(np.int64) - ext).astype(np.int32)
+        assert np.array_equal(rec, want), u
+    pend = sim.state()["pend"]
+    for q in range(pend.shape[0]):
+        assert np.array_equal(oracle.input_brute(p, targets, T + q, T - 1, mask, 0), pend[q]), q
+
+
+def test_bulk_update_matches_the_simulation_step():
+    p = W.tiny(2, 3, npc=40, seed=4)
+    sim = oracle.Sim(p)
+    for u in (0, 37, 90):
+        sim.step(u - sim.now)
+        st = sim.state()
+        spk, v, ca, ref = oracle.update_many(p, u, st["pend"][0], st["v"], st["ca"], st["ref"])
+        sim.step(1)
+        after = sim.state()
+        assert np.array_equal(np.flatnonzero(spk), sim.spikes(u))
+        assert np.array_equal(v, after["v"]) and np.array_equal(ca, after["ca"])
+        assert np.array_equal(ref, after["ref"])
