@@ -121,7 +121,8 @@ void sim_destroy(sim_t* sim);
 
 /* Advance all networks by n_steps 1 ms steps (section 1: all neurons every step, synapses
  * per spike).  Asynchronous.  A raster overflow is sticky and reported by the next
- * synchronising call as DPSNN_ETRUNC. */
+ * synchronising call as DPSNN_ETRUNC.  In train mode the steps are launched one by one
+ * (graph_steps is not used) and the state is checkpointed every ckpt_every steps. */
 int sim_step(sim_t* sim, int64_t n_steps);
 
 /* Wait for the stream; returns a sticky error if one is pending. */
@@ -147,7 +148,14 @@ int sim_column_rates(sim_t* sim, float* rates);
  * grad_w:     device float32 [n_synapses], dL/dw in the canonical synapse order (per
  *             network, per source neuron, sorted by (delay, target)), w in mV.
  * grad_tau_m, grad_g_ahp: host doubles.
- * Returns DPSNN_ESTATE if not in train mode or nothing was recorded.  Synchronises. */
+ * The reverse pass re-runs each checkpoint segment forward to record its trajectory, so
+ * it costs about one forward plus the adjoint; afterwards the state is the end state again.
+ * The adjoint (float32; float64 partial sums for the two scalars) follows the surrogate
+ * recursion: nu = dL/dV~ = (1 - r)[lambda (1 - s) + e sigma'(V~ - theta)], sigma'(x) =
+ * 1/(1 + beta|x|)^2, with lambda = dL/dV and e = dL/ds including the delayed synapses.
+ * Returns DPSNN_ESTATE if not in train mode, if nothing was recorded, or if the window was
+ * broken (restore of another window, weight or parameter change after step 0; call
+ * sim_rewind).  Synchronises. */
 int sim_backward(sim_t* sim, const float* grad_rates, float* grad_w, double* grad_tau_m,
                  double* grad_g_ahp);
 
@@ -177,15 +185,21 @@ int sim_read_synapses(sim_t* sim, int32_t net, int64_t i0, int64_t i1, int64_t* 
                       int32_t* tgt, uint8_t* dly, int16_t* wq, int64_t cap);
 
 /* Snapshot slots: save or restore the whole dynamic state (V, Ca, refractory counters,
- * pending input, step counter, event counters).  slot in [0, 64).  Asynchronous. */
+ * pending input, step counter, event counters, per-column spike counts).  slot in [0, 64).
+ * Asynchronous.  In train mode, restoring a state saved in another recorded window (before
+ * the last sim_rewind, weight or parameter change) makes sim_backward fail until the next
+ * sim_rewind; slot 63 is used by sim_autotune. */
 int sim_save(sim_t* sim, int32_t slot);
 int sim_restore(sim_t* sim, int32_t slot);
 
 /* Train mode: master weights (device float32 [n_synapses], mV, canonical order).  The
- * forward uses rint(w * 2^16) as int32 efficacy.  set copies in, get copies out. */
+ * forward uses rint(w * 2^16) as int32 efficacy.  set copies in, get copies out; both are
+ * asynchronous.  Initially the master weights are the generated int16 weights times 2^-14.
+ * A set after step 0 of the recorded window breaks the window (see sim_backward). */
 int sim_set_weights(sim_t* sim, const float* w);
 int sim_get_weights(sim_t* sim, float* w);
-/* Change tau_m and g_AHP (the constants are recomputed on the host). */
+/* Change tau_m and g_AHP (the constants are recomputed on the host).  In train mode a
+ * change after step 0 of the recorded window breaks the window (see sim_backward). */
 int sim_set_params(sim_t* sim, double tau_m, double g_ahp);
 
 /* Launch configuration of the step: delivery strategy, workgroup size and, for the arrival

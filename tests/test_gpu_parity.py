@@ -159,3 +159,17 @@ def test_raster_overflow_is_reported():
     with pytest.raises(DpsnnError) as e:
         sim.sync()
     assert e.value.code == -5
+
+
+def test_plain_4x4_half_second_bit_exact():
+    """The forward+backward workload's network (4x4 grid, full column recipe, 24.6M
+    synapses), 500 steps, against the oracle; the train-mode forward too."""
+    p = W.FWD_BWD_4X4["params"]
+    T = W.FWD_BWD_4X4["steps"]
+    ref = oracle.Sim(p)
+    ref.step(T)
+    for train in (False, True):
+        sim = Simulation(p, record_steps=T, train_mode=train, ckpt_every=50)
+        sim.step(T)
+        _check_run(sim, ref, T)
+        sim.close()
