@@ -40,20 +40,24 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
   const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (j >= nall) return;
   const int32_t g = (int32_t)(j / a.npc);
+  const int32_t kk = (int32_t)(j - (int64_t)g * a.npc);
   const bool spiked = (a.rec_flags[(u - a.rec_base) * nall + j] & 1) != 0;
-  const int64_t st = idx_start(a, j);
-  const uint16_t* go = idx_goff(a, j);
   float acc = 0.0f;
-  for (int dd = 0; dd < a.nd; ++dd) {
-    const float* nus = x.nu_ring + ((u + a.d_min + dd) % a.dh) * nall;
-    for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
-      const uint32_t w = a.syn[st + f];
-      if (rec_rank(w) == (uint32_t)kDummyRank) continue;
-      const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
-      const float nu = nus[(int64_t)tc * a.npc + rec_k(w)];
-      const float prod = x.wf32[st + f] * nu;
-      acc = acc + prod;
-      if (spiked) x.gw[st + f] = x.gw[st + f] + nu;
+  for (int p = 0; p < a.col_np[g]; ++p) {
+    const uint8_t* ent = idx_entry(a, g, kk, p);
+    const int64_t st = ent_start(ent);
+    const uint16_t* go = ent_goff(ent);
+    for (int dd = 0; dd < a.nd; ++dd) {
+      const float* nus = x.nu_ring + ((u + a.d_min + dd) % a.dh) * nall;
+      for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+        const uint32_t w = a.syn[st + f];
+        if (rec_rank(w) == (uint32_t)kDummyRank) continue;
+        const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+        const float nu = nus[(int64_t)tc * a.npc + rec_k(w)];
+        const float prod = x.wf32[st + f] * nu;
+        acc = acc + prod;
+        if (spiked) x.gw[st + f] = x.gw[st + f] + nu;
+      }
     }
   }
 #pragma unroll
@@ -111,29 +115,64 @@ __global__ __launch_bounds__(1024) void k_reduce_parts(const double* part, int64
   }
 }
 
-// Canonical synapse order (per source neuron: the real records, sorted by (delay, target))
+// Canonical synapse order (per source neuron: the real records sorted by (delay, target))
 // <-> the padded device layout.  mode 0: dst_padded[p] = src_canon[c]; mode 1: the reverse.
-// Padding records receive 0 in mode 0.
+// Padding records receive 0 in mode 0.  One wave per neuron: the counts of its synapses per
+// (delay, rank) give the canonical start of every (delay, rank) run; inside a device group
+// (part, delay) the runs of the part's ranks follow each other in rank order.
 __global__ __launch_bounds__(256) void k_canon_map(StepArgs a, const int64_t* canon_start,
                                                    int mode, const float* src, float* dst) {
-  const int lane = threadIdx.x & 63;
+  __shared__ int32_t cnt[4][kMaxDelay * kMaxNbr];
+  __shared__ int64_t cst[4][kMaxDelay * kMaxNbr];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t nall = (int64_t)a.n_cols * a.npc;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nall;
-       i += (int64_t)gridDim.x * 4) {
-    const int64_t st = idx_start(a, i);
-    const uint16_t* go = idx_goff(a, i);
-    int64_t c = canon_start[i];
-    for (int dd = 0; dd < a.nd; ++dd) {
-      const int32_t g0 = go[dd], g1 = go[dd + 1];
-      int32_t real = g1 - g0;
-      while (real > 0 && rec_rank(a.syn[st + g0 + real - 1]) == (uint32_t)kDummyRank) --real;
-      for (int32_t f = g0 + lane; f < g1; f += 64) {
-        const int32_t q = f - g0;
-        if (mode == 0) dst[st + f] = q < real ? src[c + q] : 0.0f;
-        else if (q < real) dst[c + q] = src[st + f];
-      }
-      c += real;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < nall; i += (int64_t)gridDim.x * 4) {
+    const int32_t g = (int32_t)(i / a.npc);
+    const int32_t kk = (int32_t)(i - (int64_t)g * a.npc);
+    const int np = a.col_np[g], nn = a.col_nn[g];
+    const int32_t* part = a.col_part + g * kMaxNbr;
+    for (int q = lane; q < kMaxDelay * kMaxNbr; q += 64) cnt[wave][q] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (int p = 0; p < np; ++p) {
+      const uint8_t* ent = idx_entry(a, g, kk, p);
+      const int64_t st = ent_start(ent);
+      const uint16_t* go = ent_goff(ent);
+      for (int dd = 0; dd < a.nd; ++dd)
+        for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+          const uint32_t r = rec_rank(a.syn[st + f]);
+          if (r != (uint32_t)kDummyRank) atomicAdd(&cnt[wave][dd * kMaxNbr + (int)r], 1);
+        }
     }
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) {
+      int64_t c = canon_start[i];
+      for (int dd = 0; dd < a.nd; ++dd)
+        for (int r = 0; r < nn; ++r) {
+          cst[wave][dd * kMaxNbr + r] = c;
+          c += cnt[wave][dd * kMaxNbr + r];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int p = 0; p < np; ++p) {
+      const uint8_t* ent = idx_entry(a, g, kk, p);
+      const int64_t st = ent_start(ent);
+      const uint16_t* go = ent_goff(ent);
+      for (int dd = 0; dd < a.nd; ++dd)
+        for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+          const uint32_t r = rec_rank(a.syn[st + f]);
+          if (r == (uint32_t)kDummyRank) {
+            if (mode == 0) dst[st + f] = 0.0f;
+            continue;
+          }
+          int32_t run0 = go[dd];
+          for (int r2 = 0; r2 < (int)r; ++r2)
+            if (part[r2] == p) run0 += cnt[wave][dd * kMaxNbr + r2];
+          const int64_t c = cst[wave][dd * kMaxNbr + (int)r] + (f - run0);
+          if (mode == 0) dst[st + f] = src[c];
+          else dst[c] = src[st + f];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 

@@ -73,48 +73,58 @@ __global__ __launch_bounds__(256) void k_pend_arrival(StepArgs a, int64_t now, i
     const int32_t slot = (int32_t)(t % a.dh);
     const int32_t ns = a.hist_cnt[(int64_t)slot * a.n_cols + g];
     const uint16_t* ids = a.hist_ids + ((int64_t)slot * a.n_cols + g) * a.npc;
+    const int np = a.col_np[g];
     for (int32_t q = wave; q < ns; q += 4) {
-      const int64_t i = (int64_t)g * a.npc + ids[q];
-      const int64_t st = idx_start(a, i);
-      const uint16_t* go = idx_goff(a, i);
-      for (int dd = 0; dd < a.nd; ++dd) {
-        const int64_t due = t + a.d_min + dd;
-        if (due < now) continue;
-        for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
-          const uint32_t w = a.syn[st + f];
-          if (rec_rank(w) == (uint32_t)kDummyRank) continue;
-          const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
-          const int32_t val = TRAIN ? a.wfx[st + f] : rec_w32(w);
-          atomicAdd(&pend[(due - now) * n_net + (int64_t)(tc - g0) * a.npc + rec_k(w)], val);
+      for (int p = 0; p < np; ++p) {
+        const uint8_t* ent = idx_entry(a, g, ids[q], p);
+        const int64_t st = ent_start(ent);
+        const uint16_t* go = ent_goff(ent);
+        for (int dd = 0; dd < a.nd; ++dd) {
+          const int64_t due = t + a.d_min + dd;
+          if (due < now) continue;
+          for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+            const uint32_t w = a.syn[st + f];
+            if (rec_rank(w) == (uint32_t)kDummyRank) continue;
+            const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+            const int32_t val = TRAIN ? a.wfx[st + f] : rec_w32(w);
+            atomicAdd(&pend[(due - now) * n_net + (int64_t)(tc - g0) * a.npc + rec_k(w)], val);
+          }
         }
       }
     }
   }
 }
 
-// Export rows [i0, i1) (global neuron ids) in canonical order with network-local targets.
+// Export rows [i0, i1) (global neuron ids) in device order with network-local targets, the
+// padding marked with delay 0 (the host drops it and sorts each row into canonical order).
 __global__ __launch_bounds__(256) void k_export_rows(StepArgs a, int32_t g0, int64_t i0,
                                                      int64_t i1, const int64_t* out_off,
                                                      int32_t* tgt, uint8_t* dly, int16_t* wq) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t i = i0 + (int64_t)blockIdx.x * 4 + wave; i < i1; i += (int64_t)gridDim.x * 4) {
     const int32_t g = (int32_t)(i / a.npc);
-    const int64_t st = idx_start(a, i);
-    const uint16_t* go = idx_goff(a, i);
+    const int32_t k = (int32_t)(i - (int64_t)g * a.npc);
     const int64_t ob = out_off[i - i0];
-    for (int dd = 0; dd < a.nd; ++dd) {
-      for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
-        const uint32_t w = a.syn[st + f];
-        if (rec_rank(w) == (uint32_t)kDummyRank) {  // padding: marked with delay 0
-          tgt[ob + f] = -1;
-          dly[ob + f] = 0;
-          wq[ob + f] = 0;
-          continue;
+    const int64_t rb = a.row_base[i];
+    for (int p = 0; p < a.col_np[g]; ++p) {
+      const uint8_t* ent = idx_entry(a, g, k, p);
+      const int64_t st = ent_start(ent);
+      const uint16_t* go = ent_goff(ent);
+      for (int dd = 0; dd < a.nd; ++dd) {
+        for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+          const uint32_t w = a.syn[st + f];
+          const int64_t o = ob + (st - rb) + f;
+          if (rec_rank(w) == (uint32_t)kDummyRank) {
+            tgt[o] = -1;
+            dly[o] = 0;
+            wq[o] = 0;
+            continue;
+          }
+          const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+          tgt[o] = (tc - g0) * a.npc + (int32_t)rec_k(w);
+          dly[o] = (uint8_t)(a.d_min + dd);
+          wq[o] = (int16_t)(w >> 16);
         }
-        const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
-        tgt[ob + f] = (tc - g0) * a.npc + (int32_t)rec_k(w);
-        dly[ob + f] = (uint8_t)(a.d_min + dd);
-        wq[ob + f] = (int16_t)(w >> 16);
       }
     }
   }

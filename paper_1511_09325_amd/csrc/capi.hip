@@ -169,14 +169,74 @@ void release(sim& s, void* p) {
   }
 }
 
+// Native tile (x, y index) of a column of network n under a tx x ty tiling (clamped to the
+// network's grid; edge tiles are smaller).
+static void tile_of(const sim& s, int n, int tx, int ty, int cl, int* txi, int* tyi) {
+  const int rows = s.nets[n].rows, cols = s.nets[n].cols;
+  const int ttx = std::min(tx, cols), tty = std::min(ty, rows);
+  (void)rows;
+  *txi = (cl % cols) / ttx;
+  *tyi = (cl / cols) / tty;
+}
+
+// Does a tx x ty tiling fit the LDS of the tile kernel?
+bool tile_fits(sim& s, int tx, int ty) {
+  if (tx < 1 || ty < 1 || tx > kMaxTileSide || ty > kMaxTileSide) return false;
+  int maxc = 0;
+  for (int n = 0; n < s.n_nets; ++n)
+    maxc = std::max(maxc, std::min(tx, s.nets[n].cols) * std::min(ty, s.nets[n].rows));
+  const int32_t old = s.tile_max_cols;
+  s.tile_max_cols = maxc;
+  const bool ok = tile_chunk(s) >= 256;
+  s.tile_max_cols = old;
+  return ok;
+}
+
+// Parts of every source column under the native tx x ty tiling: the ranks whose target
+// columns lie in one tile form one part, parts numbered by first appearance in rank order.
+void build_parts(sim& s, int tx, int ty) {
+  std::vector<int32_t> part((size_t)s.n_cols * kMaxNbr, -1), np(s.n_cols, 0);
+  std::vector<int64_t> pbase((size_t)s.n_cols + 1, 0);
+  for (int n = 0; n < s.n_nets; ++n) {
+    for (int cl = 0; cl < s.nets[n].rows * s.nets[n].cols; ++cl) {
+      const int32_t g = s.net_col0[n] + cl;
+      std::vector<int> seen;
+      for (int r = 0; r < s.h_nn[g]; ++r) {
+        const int32_t t = s.h_nbr[(size_t)g * kMaxNbr + r] - s.net_col0[n];
+        int xi, yi;
+        tile_of(s, n, tx, ty, t, &xi, &yi);
+        const int key = yi * 65536 + xi;
+        int p = -1;
+        for (size_t q = 0; q < seen.size(); ++q)
+          if (seen[q] == key) p = (int)q;
+        if (p < 0) {
+          p = (int)seen.size();
+          seen.push_back(key);
+        }
+        part[(size_t)g * kMaxNbr + r] = p;
+      }
+      np[g] = (int32_t)seen.size();
+    }
+  }
+  for (int32_t g = 0; g < s.n_cols; ++g) pbase[g + 1] = pbase[g] + (int64_t)s.npc * np[g];
+  s.h_part = part;
+  s.h_np = np;
+  s.n_idx = pbase[s.n_cols];
+  s.native_tx = tx;
+  s.native_ty = ty;
+  s.col_part = upload(s, part);
+  s.col_np = upload(s, np);
+  s.col_pbase = upload(s, pbase);
+}
+
 // Tiles of tx x ty target columns (clamped to each network's grid; edge tiles are smaller).
-// For each tile: its columns, every column with synapses into it (the union of the 3x3
-// neighbourhoods), and per source the tile slot of each of its neighbour ranks.  Tiles are
-// ordered like the columns: strips of each network per XCD.
+// For each tile: its columns, every (source column, part) with synapses into it, and per
+// pair the tile slot of each rank of the part.  Tiles are ordered like the columns: strips
+// of each network per XCD.
 void build_tiles(sim& s, int tx, int ty) {
   if (tx < 1 || ty < 1 || tx > kMaxTileSide || ty > kMaxTileSide)
     throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4]"};
-  std::vector<int32_t> tcols, tncols, tsrc, tnsrc;
+  std::vector<int32_t> tcols, tncols, pcol, ppart, npairs;
   std::vector<uint64_t> tslots;
   std::vector<std::vector<int32_t>> lanes(8);
   int rot = 0, maxc = 0;
@@ -198,30 +258,41 @@ void build_tiles(sim& s, int tx, int ty) {
             for (int r = 0; r < s.h_nn[g]; ++r) src.push_back(s.h_nbr[(size_t)g * kMaxNbr + r]);
           std::sort(src.begin(), src.end());
           src.erase(std::unique(src.begin(), src.end()), src.end());
-          if ((int)tc.size() > kMaxTileCols || (int)src.size() > kMaxTileSrc)
+          // the source columns of the tile are the columns whose neighbourhood meets it
+          // (the stencil is symmetric); each contributes the parts that reach the tile
+          std::vector<std::pair<int32_t, int32_t>> pairs;
+          std::vector<uint64_t> packs;
+          for (int32_t sc : src) {
+            for (int p = 0; p < s.h_np[sc]; ++p) {
+              uint64_t packed = 0;
+              bool any = false;
+              for (int r = 0; r < kMaxNbr; ++r) {
+                uint64_t slot = kNoSlot;
+                if (r < s.h_nn[sc] && s.h_part[(size_t)sc * kMaxNbr + r] == p) {
+                  const int32_t t = s.h_nbr[(size_t)sc * kMaxNbr + r];
+                  for (size_t z = 0; z < tc.size(); ++z)
+                    if (tc[z] == t) { slot = z; any = true; }
+                }
+                packed |= slot << (5 * r);
+              }
+              if (any) {
+                pairs.push_back({sc, p});
+                packs.push_back(packed);
+              }
+            }
+          }
+          if ((int)tc.size() > kMaxTileCols || (int)pairs.size() > kMaxTilePairs)
             throw Fail{DPSNN_EINVAL, "tile too large"};
           const int32_t id = (int32_t)tncols.size();
           maxc = std::max(maxc, (int)tc.size());
           tncols.push_back((int32_t)tc.size());
-          tnsrc.push_back((int32_t)src.size());
+          npairs.push_back((int32_t)pairs.size());
           for (int q = 0; q < kMaxTileCols; ++q) tcols.push_back(q < (int)tc.size() ? tc[q] : -1);
-          for (int q = 0; q < kMaxTileSrc; ++q) {
-            uint64_t packed = 0;
-            int32_t sc = -1;
-            for (int r = 0; r < kMaxNbr; ++r) {
-              uint64_t slot = kNoSlot;
-              if (q < (int)src.size()) {
-                sc = src[q];
-                if (r < s.h_nn[sc]) {
-                  const int32_t t = s.h_nbr[(size_t)sc * kMaxNbr + r];
-                  for (size_t z = 0; z < tc.size(); ++z)
-                    if (tc[z] == t) slot = z;
-                }
-              }
-              packed |= slot << (5 * r);
-            }
-            tsrc.push_back(q < (int)src.size() ? src[q] : -1);
-            tslots.push_back(packed);
+          for (int q = 0; q < kMaxTilePairs; ++q) {
+            const bool in = q < (int)pairs.size();
+            pcol.push_back(in ? pairs[q].first : -1);
+            ppart.push_back(in ? pairs[q].second : 0);
+            tslots.push_back(in ? packs[q] : ~(uint64_t)0);
           }
           lanes[(st + rot) % 8].push_back(id);
         }
@@ -238,8 +309,9 @@ void build_tiles(sim& s, int tx, int ty) {
   release(s, s.tile_order);
   release(s, s.tile_cols);
   release(s, s.tile_ncols);
-  release(s, s.tile_src);
-  release(s, s.tile_nsrc);
+  release(s, s.tile_pcol);
+  release(s, s.tile_ppart);
+  release(s, s.tile_npairs);
   release(s, s.tile_slots);
   const std::vector<int32_t> order = interleave(lanes);
   s.tile_x = tx;
@@ -249,20 +321,27 @@ void build_tiles(sim& s, int tx, int ty) {
   s.tile_order = upload(s, order);
   s.tile_cols = upload(s, tcols);
   s.tile_ncols = upload(s, tncols);
-  s.tile_src = upload(s, tsrc);
-  s.tile_nsrc = upload(s, tnsrc);
+  s.tile_pcol = upload(s, pcol);
+  s.tile_ppart = upload(s, ppart);
+  s.tile_npairs = upload(s, npairs);
   s.tile_slots = upload(s, tslots);
 }
 
-// Largest square-ish tile (sides <= 4) whose accumulators fit the LDS.
-void default_tiles(sim& s) {
+// Native tiling: the configured one, else the largest square-ish tile (sides <= 4) whose
+// accumulators fit the LDS.
+void choose_native(sim& s, int tx, int ty) {
+  if (tx || ty) {
+    if (!tile_fits(s, tx, ty)) throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4] and fit the LDS"};
+    s.native_tx = tx;
+    s.native_ty = ty;
+    return;
+  }
   static const int shapes[][2] = {{4, 4}, {4, 3}, {3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
   for (const auto& sh : shapes) {
-    try {
-      build_tiles(s, sh[0], sh[1]);
+    if (tile_fits(s, sh[0], sh[1])) {
+      s.native_tx = sh[0];
+      s.native_ty = sh[1];
       return;
-    } catch (const Fail& f) {
-      if (f.code != DPSNN_EINVAL) throw;
     }
   }
   throw Fail{DPSNN_EINVAL, "no tile shape fits the LDS"};
@@ -353,7 +432,6 @@ void generate(sim& s) {
   const int64_t N = s.n_neurons;
   int32_t* row_len = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)N);
   s.deg = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)N);
-  s.seg = (uint16_t*)dalloc(s, sizeof(uint16_t) * (size_t)N * s.segw);
   s.row_base = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)(N + 1));
   const int64_t plen = scan_scratch_len(N);
   int64_t* part = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)plen);
@@ -365,7 +443,7 @@ void generate(sim& s) {
   // one spare uint4 after the last synapse: the delivery kernels may load whole 16-byte
   // words that straddle the end of a segment
   s.syn = (uint32_t*)dalloc(s, sizeof(uint32_t) * (size_t)(total + 4));
-  s.idx = (uint8_t*)dalloc(s, (size_t)s.idxw * (size_t)N);
+  s.idx = (uint8_t*)dalloc(s, (size_t)s.idxw * (size_t)s.n_idx);
   HIPCHK(hipMemsetAsync(s.syn + total, 0, 4 * sizeof(uint32_t), s.stream));
   HIPCHK(launch_gen_fill(s, 0, N));
   // the number of synapses (without the padding): scan of the out-degrees
@@ -383,8 +461,6 @@ void generate(sim& s) {
   else dfree(s, degscan);
   dfree(s, part);
   dfree(s, row_len);
-  dfree(s, s.seg);
-  s.seg = nullptr;
 }
 
 void ensure_ring(sim& s) {
@@ -485,14 +561,14 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->npc = cfg->npc;
     s->nd = cfg->d_max - cfg->d_min + 1;
     s->dh = cfg->d_max + 1;
-    s->segw = (s->nd * kSegPerDelay + 1 + 1) & ~1;
     s->idxw = (8 + 2 * (s->nd + 1) + 15) & ~15;
     s->delivery = cfg->delivery == DPSNN_DELIVERY_PUSH ? DPSNN_DELIVERY_PUSH : DPSNN_DELIVERY_ARRIVAL;
     s->block = cfg->block ? cfg->block : default_block(s->delivery);
     set_constants(*s);
     build_tables(*s);
-    if (cfg->tile_x || cfg->tile_y) build_tiles(*s, cfg->tile_x, cfg->tile_y);
-    else default_tiles(*s);
+    choose_native(*s, cfg->tile_x, cfg->tile_y);
+    build_parts(*s, s->native_tx, s->native_ty);
+    build_tiles(*s, s->native_tx, s->native_ty);
     generate(*s);
     const size_t N = (size_t)s->n_neurons;
     s->v = (float*)dalloc(*s, sizeof(float) * N);
@@ -853,13 +929,25 @@ int sim_read_synapses(sim_t* s, int32_t net, int64_t i0, int64_t i1, int64_t* ro
     dfree(*s, dw);
     dfree(*s, dd);
     dfree(*s, dt);
+    // drop the padding and sort each row by (delay, target): the canonical order
     int64_t o = 0;
-    for (int64_t e = 0; e < ptotal; ++e) {
-      if (hd[(size_t)e] == 0) continue;
-      tgt[o] = ht[(size_t)e];
-      dly[o] = hd[(size_t)e];
-      wq[o] = hw[(size_t)e];
-      ++o;
+    std::vector<std::pair<uint64_t, int16_t>> row;
+    for (size_t q = 0; q < nr; ++q) {
+      row.clear();
+      for (int64_t e = poff[q]; e < poff[q + 1]; ++e)
+        if (hd[(size_t)e] != 0)
+          row.push_back({((uint64_t)hd[(size_t)e] << 32) | (uint32_t)ht[(size_t)e], hw[(size_t)e]});
+      std::sort(row.begin(), row.end(),
+                [](const std::pair<uint64_t, int16_t>& x, const std::pair<uint64_t, int16_t>& y) {
+                  return x.first < y.first;
+                });
+      if (o + (int64_t)row.size() > total) throw Fail{DPSNN_EHIP, "synapse export overflow"};
+      for (const auto& r : row) {
+        tgt[o] = (int32_t)(uint32_t)(r.first & 0xffffffffu);
+        dly[o] = (uint8_t)(r.first >> 32);
+        wq[o] = r.second;
+        ++o;
+      }
     }
     if (o != total) throw Fail{DPSNN_EHIP, "synapse export is inconsistent with the out-degrees"};
     return DPSNN_OK;

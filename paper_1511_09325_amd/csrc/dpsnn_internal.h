@@ -3,27 +3,36 @@
 // Device data layout (all networks of a simulation concatenated column by column; the
 // global neuron index is g*npc + k for global column g and local index k):
 //
-//   synapse store, canonical order: per source neuron, sorted by (delay, target).  Within
-//   one delay the targets come column by column in ascending column order.  A row is a
-//   sequence of groups, one per delay; a synapse's target column is identified by its
-//   rank r in the source column's sorted list of distinct neighbour columns (at most 9:
-//   the 3x3 torus stencil)
-//     idx       idxw bytes per neuron: int64 start of the row, then uint16 goff[nd + 1];
-//               group dd (delay d_min + dd) is [start + goff[dd], start + goff[dd + 1])
+//   synapse store: the canonical order of a row is (delay, target); the device keeps each
+//   row split into parts, one per target tile of the tiling chosen at creation (the
+//   "native" tiling): part p of a source column holds the synapses whose target column
+//   lies in the p-th distinct tile touched by the column's 3x3 neighbourhood.  A part is a
+//   sequence of groups, one per delay; inside a group the targets come in canonical order.
+//   A synapse's target column is identified by its rank r in the source column's sorted
+//   list of distinct neighbour columns (at most 9: the 3x3 torus stencil)
+//     idx       idxw bytes per (neuron, part): int64 start of the part, then uint16
+//               goff[nd + 1]; group dd (delay d_min + dd) is [start + goff[dd], start +
+//               goff[dd + 1]).  Entry of (column g, neuron k, part p): col_pbase[g] +
+//               k * col_np[g] + p.  The parts of one neuron are contiguous (row_base[i])
 //     syn       uint32[S' + 4]: k (bits 0-11, target index inside its column) | r (bits
 //               12-15) | w_q (bits 16-31, int16 weight at 2^-14 mV).  Every group is padded
-//               to a multiple of 4 records with dummies (r = 15, weight 0), so rows and
+//               to a multiple of 4 records with dummies (r = 15, weight 0), so parts and
 //               groups start on 16-byte boundaries and are read in whole 16-byte words
 //     deg       int32 [N]    out-degree (records without the padding)
-//     wfx       int32 [S]   train mode only: rint(w_f32 * 2^16) efficacies
+//     wfx       int32 [S']   train mode only: rint(w_f32 * 2^16) efficacies
 //   column tables
 //     col_nbr   int32 [C][9]   distinct neighbour columns, ascending, -1 padded
 //     col_thr   uint64[C][9]   pair connection threshold from g to col_nbr[g][r]
+//     col_part  int32 [C][9]   part of rank r (-1 padded); col_np int32 [C] parts per
+//                              column; col_pbase int64 [C+1] first idx entry of the column
 //   tiles (the unit of work of the arrival kernel): up to 4x4 target columns of one network
 //     tile_cols   int32 [tiles][16]   the tile's columns, -1 padded
-//     tile_src    int32 [tiles][36]   every column with a synapse into the tile
-//     tile_slots  uint64[tiles][36]   for each source and each rank r, the tile slot of its
-//                                     target column in bits 5r..5r+4 (31: not in the tile)
+//     tile_pcol, tile_ppart int32 [tiles][64]  every (source column, part) with a synapse
+//                                     into the tile (one part per source in the native
+//                                     tiling; a part may reach several tiles otherwise)
+//     tile_slots  uint64[tiles][64]   for each pair and each rank r of its part, the tile
+//                                     slot of its target column in bits 5r..5r+4 (31: not
+//                                     in the tile or not in the part)
 //   spike history (shared by both delivery strategies)
 //     hist_cnt  int32 [DH][C]       spikes of column g at step t, in slot t % DH
 //     hist_ids  uint16[DH][C][npc]  their local indices, ascending
@@ -50,8 +59,9 @@ constexpr int kPoissonEntries = 63;
 constexpr int kMaxTileSide = 4;
 constexpr int kMaxTileCols = kMaxTileSide * kMaxTileSide;
 constexpr int kMaxTileSrc = (kMaxTileSide + 2) * (kMaxTileSide + 2);
+constexpr int kMaxTilePairs = 64;   // (source column, part) pairs of one tile
+constexpr int kMaxParts = kMaxNbr;  // parts of one source column (9 with 1x1 tiles)
 constexpr int kNoSlot = 31;
-constexpr int kSegPerDelay = 10;    // construction table: 9 target ranks + group padding
 constexpr int kDummyRank = 15;
 constexpr uint32_t kDummyRecord = (uint32_t)kDummyRank << 12;  // k 0, rank 15, weight 0
 constexpr int kCounters = 8;        // per-network counters (see StepArgs::net_cnt)
@@ -114,6 +124,9 @@ struct StepArgs {
   const int32_t* col_local;   // column index within its network
   const int32_t* col_nbr;
   const int32_t* col_nn;
+  const int32_t* col_np;      // parts per column
+  const int32_t* col_part;    // [C][9]: part of each neighbour rank
+  const int64_t* col_pbase;   // first row-index entry of each column
   const int32_t* col_order;   // [grid_cols]: column of workgroup b of per-column kernels
   int32_t grid_cols;
   const uint32_t* net_key;    // [n_nets][2]
@@ -123,8 +136,9 @@ struct StepArgs {
   int32_t grid_tiles;
   const int32_t* tile_cols;
   const int32_t* tile_ncols;
-  const int32_t* tile_src;
-  const int32_t* tile_nsrc;
+  const int32_t* tile_pcol;
+  const int32_t* tile_ppart;
+  const int32_t* tile_npairs;
   const uint64_t* tile_slots;
   // synapses
   const int64_t* row_base;
@@ -151,12 +165,14 @@ struct StepArgs {
   NeuronK k;
 };
 
-// row index entry of neuron i
-__device__ __forceinline__ int64_t idx_start(const StepArgs& a, int64_t i) {
-  return *(const int64_t*)(a.idx + i * a.idxw);
+// row-index entry of part p of neuron k of column g
+__device__ __forceinline__ const uint8_t* idx_entry(const StepArgs& a, int32_t g, int32_t k,
+                                                     int p) {
+  return a.idx + (a.col_pbase[g] + (int64_t)k * a.col_np[g] + p) * a.idxw;
 }
-__device__ __forceinline__ const uint16_t* idx_goff(const StepArgs& a, int64_t i) {
-  return (const uint16_t*)(a.idx + i * a.idxw + 8);
+__device__ __forceinline__ int64_t ent_start(const uint8_t* e) { return *(const int64_t*)e; }
+__device__ __forceinline__ const uint16_t* ent_goff(const uint8_t* e) {
+  return (const uint16_t*)(e + 8);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -184,7 +200,7 @@ struct sim {
   int sticky = 0;
 
   // sizes
-  int32_t n_nets = 0, n_cols = 0, npc = 0, nd = 0, dh = 0, segw = 0, idxw = 0;
+  int32_t n_nets = 0, n_cols = 0, npc = 0, nd = 0, dh = 0, idxw = 0;
   int64_t n_neurons = 0, n_syn = 0, n_syn_padded = 0;
   std::vector<int32_t> net_col0;    // first global column of each network (n_nets+1)
   std::vector<int64_t> net_syn0;    // first synapse of each network (n_nets+1)
@@ -194,6 +210,11 @@ struct sim {
   std::vector<dpsnn::DevBuf> bufs;
   size_t device_bytes = 0;
   int32_t *col_net = nullptr, *col_local = nullptr, *col_nbr = nullptr, *col_nn = nullptr;
+  int32_t *col_part = nullptr, *col_np = nullptr;
+  int64_t* col_pbase = nullptr;
+  std::vector<int32_t> h_part, h_np;  // host copies of the part tables
+  int64_t n_idx = 0;                  // row-index entries (neuron, part)
+  int32_t native_tx = 0, native_ty = 0;  // tiling of the synapse parts
   int32_t* col_order = nullptr;
   int32_t grid_cols = 0;
   uint64_t* col_thr = nullptr;
@@ -201,7 +222,6 @@ struct sim {
   uint64_t* net_ptab = nullptr;
   int64_t* row_base = nullptr;
   int32_t* deg = nullptr;
-  uint16_t* seg = nullptr;          // construction only: relative segment starts [N][segw]
   uint8_t* idx = nullptr;
   uint32_t* syn = nullptr;
   int32_t* wfx = nullptr;
@@ -215,7 +235,7 @@ struct sim {
   // tiles of the current shape
   int32_t tile_x = 0, tile_y = 0, n_tiles = 0, grid_tiles = 0, tile_max_cols = 0;
   int32_t *tile_order = nullptr, *tile_cols = nullptr, *tile_ncols = nullptr,
-          *tile_src = nullptr, *tile_nsrc = nullptr;
+          *tile_pcol = nullptr, *tile_ppart = nullptr, *tile_npairs = nullptr;
   uint64_t* tile_slots = nullptr;
   // raster
   int64_t* ras_off = nullptr;      // [record_steps+1]

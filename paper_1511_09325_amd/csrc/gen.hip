@@ -11,36 +11,49 @@
 //   weight     mu + sigma * z, z = (sum of 12 16-bit halves of words z, w and of the four
 //              words at counter (j, i, 1, SYN) - 393210) / 65536, in double, no FMA,
 //              quantised to int16 at 2^-14 mV with round-half-even.
-// Rows are written in canonical order (delay, target), each record carrying the rank of its
-// target column in the source column's neighbour list; each delay group is padded with
-// dummy records to a multiple of 4 so that 16-byte words never straddle two groups.  Two
-// passes: counting per (delay, target column) segment, then an exclusive scan over rows,
-// then filling.
+// Each row is split into parts, one per tile of the native tiling that the source
+// column's neighbourhood touches (the part of each neighbour rank is in col_part); a part
+// holds one group per delay, each record carrying the rank of its target column, targets
+// in canonical order inside a group, and each group padded with dummy records to a
+// multiple of 4 so that 16-byte words never straddle two groups.  Two passes over the
+// candidates: the first counts each row's padded length and out-degree (then an exclusive
+// scan over rows gives the row starts), the second counts again, lays the row out and
+// fills it.
 #include "dpsnn_internal.h"
 
 namespace dpsnn {
 namespace {
 
 struct GenArgs {
-  int32_t npc, n_exc, nd, d_min, segw;
+  int32_t npc, n_exc, nd, d_min;
   int64_t row0, rows;
   const int32_t* col_net;
   const int32_t* col_local;
   const int32_t* col_nbr;
   const int32_t* col_nn;
+  const int32_t* col_part;
+  const int32_t* col_np;
+  const int64_t* col_pbase;
   const uint64_t* col_thr;
   const uint32_t* net_key;
   double we_mu, we_sigma, wi_mu, wi_sigma;
   int32_t* row_len;        // count pass output: padded row length
   int32_t* deg;            // count pass output: out-degree
-  uint16_t* seg;           // count pass output
   const int64_t* row_base; // fill pass input
   uint32_t* syn;           // fill pass output
-  uint8_t* idx;            // fill pass output: row index entries
+  uint8_t* idx;            // fill pass output: row-index entries
   int32_t idxw;
 };
 
 constexpr int kGenWaves = 4;  // rows per workgroup (one wave each)
+
+// per-wave LDS of the construction kernels
+struct RowLayout {
+  int32_t cnt[kMaxDelay][kMaxNbr];        // synapses of (delay, rank)
+  int32_t seg[kMaxDelay][kMaxNbr];        // fill: first record of (delay, rank) in the row
+  int32_t gst[kMaxParts][kMaxDelay + 1];  // fill: start of group (part, delay); [nd] = end
+  int32_t pad[kMaxParts][kMaxDelay];      // fill: first padding record of group (part, delay)
+};
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -56,11 +69,41 @@ __device__ __forceinline__ bool decide(const GenArgs& a, int64_t i, int64_t jglo
   return conn;
 }
 
+// Synapse counts of row i per (delay, rank) into L.cnt (one wave).
+__device__ void count_row(const GenArgs& a, int64_t i, int32_t g, uint32_t il, uint32_t k0,
+                          uint32_t k1, RowLayout& L) {
+  const int lane = threadIdx.x & 63;
+  const int nn = a.col_nn[g];
+  for (int q = lane; q < kMaxDelay * kMaxNbr; q += 64) (&L.cnt[0][0])[q] = 0;
+  __builtin_amdgcn_wave_barrier();
+  for (int r = 0; r < nn; ++r) {
+    const int32_t tc = a.col_nbr[g * kMaxNbr + r];
+    const uint64_t thr = a.col_thr[g * kMaxNbr + r];
+    const uint32_t tl0 = (uint32_t)(a.col_local[tc] * a.npc);
+    int32_t mine = 0;
+    for (int kb = 0; kb < a.npc; kb += 64) {
+      const int k = kb + lane;
+      int dd;
+      Rand4 rr4;
+      const bool conn = decide(a, i, (int64_t)tc * a.npc + k, tl0 + (uint32_t)k, il, k0, k1,
+                               thr, k < a.npc, dd, rr4);
+      for (int q = 0; q < a.nd; ++q) {
+        const unsigned long long m = __ballot(conn && dd == q);
+        if (lane == q) mine += __popcll(m);
+      }
+    }
+    if (lane < a.nd) L.cnt[lane][r] = mine;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ int32_t padded(int32_t n) { return (n + 3) & ~3; }
+
 __global__ __launch_bounds__(64 * kGenWaves) void k_gen_count(GenArgs a) {
-  __shared__ int32_t cnt[kGenWaves][kSegPerDelay * kMaxDelay];
+  __shared__ RowLayout lay[kGenWaves];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int nseg = a.nd * kSegPerDelay;
+  RowLayout& L = lay[wave];
   for (int64_t rr = (int64_t)blockIdx.x * kGenWaves + wave; rr < a.rows;
        rr += (int64_t)gridDim.x * kGenWaves) {
     const int64_t i = a.row0 + rr;
@@ -68,75 +111,37 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_count(GenArgs a) {
     const int32_t kk = (int32_t)(i - (int64_t)g * a.npc);
     const int32_t net = a.col_net[g];
     const uint32_t il = (uint32_t)(a.col_local[g] * a.npc + kk);
-    const uint32_t k0 = a.net_key[2 * net], k1 = a.net_key[2 * net + 1];
-    const int nn = a.col_nn[g];
-    for (int q = lane; q < nseg; q += 64) cnt[wave][q] = 0;
-    __builtin_amdgcn_wave_barrier();
-    for (int r = 0; r < nn; ++r) {
-      const int32_t tc = a.col_nbr[g * kMaxNbr + r];
-      const uint64_t thr = a.col_thr[g * kMaxNbr + r];
-      const uint32_t tl0 = (uint32_t)(a.col_local[tc] * a.npc);
-      int32_t mine = 0;
-      for (int kb = 0; kb < a.npc; kb += 64) {
-        const int k = kb + lane;
-        int dd;
-        Rand4 rr4;
-        const bool conn = decide(a, i, (int64_t)tc * a.npc + k, tl0 + (uint32_t)k, il, k0, k1,
-                                 thr, k < a.npc, dd, rr4);
-        for (int q = 0; q < a.nd; ++q) {
-          const unsigned long long m = __ballot(conn && dd == q);
-          if (lane == q) mine += __popcll(m);
-        }
-      }
-      if (lane < a.nd) cnt[wave][lane * kSegPerDelay + r] = mine;
-    }
-    __builtin_amdgcn_wave_barrier();
-    // each group is padded to a multiple of 4 records (dummies in entry 9 of the delay)
-    int32_t used = 0;
+    count_row(a, i, g, il, a.net_key[2 * net], a.net_key[2 * net + 1], L);
+    const int nn = a.col_nn[g], np = a.col_np[g];
+    // lane dd: padded length of every group (part, dd) and the out-degree of delay dd
+    int32_t len = 0, used = 0;
     if (lane < a.nd) {
-      int32_t glen = 0;
-      for (int r = 0; r < kMaxNbr; ++r) glen += cnt[wave][lane * kSegPerDelay + r];
-      cnt[wave][lane * kSegPerDelay + kMaxNbr] = ((glen + 3) & ~3) - glen;
-      used = glen;
-    }
-    for (int off = 32; off > 0; off >>= 1) used += __shfl_down(used, off);
-    __builtin_amdgcn_wave_barrier();
-    // exclusive prefix over the nd*10 entries in (delay, rank) order
-    const int per = (nseg + 63) / 64;
-    int32_t local = 0;
-    for (int q = 0; q < per; ++q) {
-      const int e = lane * per + q;
-      if (e < nseg) local += cnt[wave][e];
-    }
-    int32_t incl = local;
-    for (int off = 1; off < 64; off <<= 1) {
-      const int32_t t = __shfl_up(incl, off);
-      if (lane >= off) incl += t;
-    }
-    int32_t run = incl - local;
-    uint16_t* out = a.seg + i * a.segw;
-    for (int q = 0; q < per; ++q) {
-      const int e = lane * per + q;
-      if (e < nseg) {
-        out[e] = (uint16_t)run;
-        run += cnt[wave][e];
+      for (int p = 0; p < np; ++p) {
+        int32_t glen = 0;
+        for (int r = 0; r < nn; ++r)
+          if (a.col_part[g * kMaxNbr + r] == p) glen += L.cnt[lane][r];
+        len += padded(glen);
+        used += glen;
       }
     }
-    const int32_t total = __shfl(incl, 63);
+    for (int off = 32; off > 0; off >>= 1) {
+      len += __shfl_down(len, off);
+      used += __shfl_down(used, off);
+    }
     if (lane == 0) {
-      out[nseg] = (uint16_t)total;
-      a.row_len[i] = total;
+      a.row_len[i] = len;
       a.deg[i] = used;
     }
-    for (int e = nseg + 1 + lane; e < a.segw; e += 64) out[e] = 0;
     __builtin_amdgcn_wave_barrier();
   }
 }
 
 __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
+  __shared__ RowLayout lay[kGenWaves];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = lanemask_lt(lane);
+  RowLayout& L = lay[wave];
   for (int64_t rr = (int64_t)blockIdx.x * kGenWaves + wave; rr < a.rows;
        rr += (int64_t)gridDim.x * kGenWaves) {
     const int64_t i = a.row0 + rr;
@@ -145,28 +150,63 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
     const int32_t net = a.col_net[g];
     const uint32_t il = (uint32_t)(a.col_local[g] * a.npc + kk);
     const uint32_t k0 = a.net_key[2 * net], k1 = a.net_key[2 * net + 1];
-    const int nn = a.col_nn[g];
+    count_row(a, i, g, il, k0, k1, L);
+    const int nn = a.col_nn[g], np = a.col_np[g];
+    // layout: parts in order, inside a part the groups by delay; lane dd owns delay dd
+    int32_t base = 0;
+    for (int p = 0; p < np; ++p) {
+      int32_t glen = 0;
+      if (lane < a.nd)
+        for (int r = 0; r < nn; ++r)
+          if (a.col_part[g * kMaxNbr + r] == p) glen += L.cnt[lane][r];
+      const int32_t plen = lane < a.nd ? padded(glen) : 0;
+      int32_t incl = plen;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+      }
+      if (lane < a.nd) {
+        L.gst[p][lane] = base + incl - plen;
+        L.pad[p][lane] = base + incl - plen + glen;
+      }
+      const int32_t tot = __shfl(incl, 63);
+      if (lane == 0) L.gst[p][a.nd] = base + tot;
+      base += tot;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (lane < a.nd) {
+      // segment (dd, r) follows the earlier ranks of the same part inside group (part, dd)
+      for (int r = 0; r < nn; ++r) {
+        const int p = a.col_part[g * kMaxNbr + r];
+        int32_t at = L.gst[p][lane];
+        for (int r2 = 0; r2 < r; ++r2)
+          if (a.col_part[g * kMaxNbr + r2] == p) at += L.cnt[lane][r2];
+        L.seg[lane][r] = at;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int64_t rb = a.row_base[i];
+    uint32_t* out = a.syn + rb;
+    // row-index entries of the parts: start of the part, then the start of each group
+    for (int p = 0; p < np; ++p) {
+      uint8_t* ent = a.idx + (a.col_pbase[g] + (int64_t)kk * np + p) * a.idxw;
+      const int32_t p0 = L.gst[p][0];
+      if (lane == 0) *(int64_t*)ent = rb + p0;
+      for (int dd = lane; dd <= a.nd; dd += 64) ((uint16_t*)(ent + 8))[dd] = (uint16_t)(L.gst[p][dd] - p0);
+    }
+    // dummy records (rank 15, weight 0) in the padding at the end of each group
+    for (int p = 0; p < np; ++p)
+      for (int dd = 0; dd < a.nd; ++dd)
+        for (int32_t q = L.pad[p][dd] + lane; q < L.gst[p][dd + 1]; q += 64) out[q] = kDummyRecord;
     const bool exc = kk < a.n_exc;
     const double mu = exc ? a.we_mu : a.wi_mu;
     const double sigma = exc ? a.we_sigma : a.wi_sigma;
-    const uint16_t* sg = a.seg + i * a.segw;
-    const int64_t rb = a.row_base[i];
-    uint32_t* out = a.syn + rb;
-    // row index entry: start of the row, then the start of each delay group
-    uint8_t* ent = a.idx + i * a.idxw;
-    if (lane == 0) *(int64_t*)ent = rb;
-    for (int dd = lane; dd <= a.nd; dd += 64) ((uint16_t*)(ent + 8))[dd] = sg[dd * kSegPerDelay];
-    // dummy records (rank 15, weight 0) in the padding at the end of each group
-    for (int dd = 0; dd < a.nd; ++dd)
-      for (int32_t p = sg[dd * kSegPerDelay + kMaxNbr] + lane; p < sg[(dd + 1) * kSegPerDelay];
-           p += 64)
-        out[p] = kDummyRecord;
     for (int r = 0; r < nn; ++r) {
       const int32_t tc = a.col_nbr[g * kMaxNbr + r];
       const uint64_t thr = a.col_thr[g * kMaxNbr + r];
       const uint32_t tl0 = (uint32_t)(a.col_local[tc] * a.npc);
       // lane q holds the write cursor of segment (q, r)
-      int32_t cursor = lane < a.nd ? (int32_t)sg[lane * kSegPerDelay + r] : 0;
+      int32_t cursor = lane < a.nd ? L.seg[lane][r] : 0;
       for (int kb = 0; kb < a.npc; kb += 64) {
         const int k = kb + lane;
         int dd;
@@ -176,8 +216,8 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
         int32_t pos = 0;
         for (int q = 0; q < a.nd; ++q) {
           const unsigned long long m = __ballot(conn && dd == q);
-          const int32_t base = __shfl(cursor, q);
-          if (conn && dd == q) pos = base + __popcll(m & lt);
+          const int32_t cb = __shfl(cursor, q);
+          if (conn && dd == q) pos = cb + __popcll(m & lt);
           if (lane == q) cursor += __popcll(m);
         }
         if (conn) {
@@ -194,6 +234,7 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
         }
       }
     }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -203,20 +244,21 @@ GenArgs gen_args(const sim& s, int64_t row0, int64_t rows) {
   a.n_exc = s.cfg.n_exc;
   a.nd = s.nd;
   a.d_min = s.cfg.d_min;
-  a.segw = s.segw;
   a.row0 = row0;
   a.rows = rows;
   a.col_net = s.col_net;
   a.col_local = s.col_local;
   a.col_nbr = s.col_nbr;
   a.col_nn = s.col_nn;
+  a.col_part = s.col_part;
+  a.col_np = s.col_np;
+  a.col_pbase = s.col_pbase;
   a.col_thr = s.col_thr;
   a.net_key = s.net_key;
   a.we_mu = s.cfg.we_mu;
   a.we_sigma = s.cfg.we_sigma;
   a.wi_mu = s.cfg.wi_mu;
   a.wi_sigma = s.cfg.wi_sigma;
-  a.seg = s.seg;
   a.row_base = s.row_base;
   a.syn = s.syn;
   a.idx = s.idx;

@@ -26,7 +26,7 @@
 namespace dpsnn {
 namespace {
 
-constexpr int kMaxItems = kMaxTileSrc * kMaxDelay;
+constexpr int kMaxItems = kMaxTilePairs * kMaxDelay;
 constexpr int kLanesPerGroup = 16;    // lanes streaming one group, 4 synapses each
 constexpr int kGroupsInFlight = 4;    // groups per lane set per round
 constexpr int kPiecesInFlight = 4;    // 16-byte loads per lane in flight
@@ -146,15 +146,17 @@ __device__ __forceinline__ int32_t external_count(const StepArgs& a, int32_t g, 
 
 // ---- ARRIVAL: tiles of target columns ---------------------------------------------------
 //
-// Work list of a tile at step u: items (source column si, delay index dd), the spike list
-// of tile_src[si] at step u - d_min - dd.  Every spike i of an item is one group: the
-// contiguous synapses of (i, delay).  The groups are taken in chunks of kChunk: first each
-// thread locates groups (binary search over the item prefix, one spike id, one row-index
-// entry) into LDS, then sets of kLanesPerGroup lanes stream kGroupsInFlight groups at a
-// time in 16-byte words, keeping the synapses whose target column is in the tile (the
-// record's rank, looked up in the source's slot word) and adding them to the tile's LDS
-// accumulators with integer atomics.  Then the tile's neurons are updated in 64-neuron
-// chunks and the spikes compacted per column, in ascending order.
+// Work list of a tile at step u: items (pair si, delay index dd) where a pair is a source
+// column with synapses into the tile and the part of its rows that holds them (in the
+// tiling the synapse store was built for, exactly the synapses into this tile); an item is
+// the spike list of the source column at step u - d_min - dd, and every spike i of an item
+// is one group: the contiguous synapses of (i, part, delay).  The groups are taken in
+// chunks: first each thread locates groups (binary search over the item prefix, one spike
+// id, one row-index entry) into LDS, then sets of kLanesPerGroup lanes stream
+// kGroupsInFlight groups at a time in 16-byte words, keeping the synapses whose target
+// column is in the tile (the record's rank, looked up in the pair's slot table) and adding
+// them to the tile's LDS accumulators with integer atomics.  Then the tile's neurons are
+// updated in 64-neuron chunks and the spikes compacted per column, in ascending order.
 template <int BLOCK, bool TRAIN>
 __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc,
                                                      int32_t chunk) {
@@ -165,8 +167,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ uint64_t ptab[kPoissonEntries];
   __shared__ int32_t it_pref[kMaxItems + 1];
-  __shared__ int32_t s_src[kMaxTileSrc];
-  __shared__ int32_t s_base[kMaxTileSrc * 16];  // per (source, rank): slot * npc, or -1
+  __shared__ int32_t s_src[kMaxTilePairs];      // source column of each pair
+  __shared__ int32_t s_part[kMaxTilePairs];     // part of each pair
+  __shared__ int32_t s_base[kMaxTilePairs * 16];  // per (pair, rank): slot * npc, or -1
   __shared__ int32_t s_col[kMaxTileCols];
   __shared__ int32_t wsum[2 * NW + 1];
   __shared__ unsigned long long red[NW];
@@ -192,13 +195,16 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     const int32_t tile = a.tile_order[b];
     if (tile < 0) continue;
     const int T = a.tile_ncols[tile];
-    const int ns = a.tile_nsrc[tile];
+    const int ns = a.tile_npairs[tile];
     if (tid < kMaxTileCols) s_col[tid] = a.tile_cols[tile * kMaxTileCols + tid];
-    if (tid < kMaxTileSrc) s_src[tid] = a.tile_src[tile * kMaxTileSrc + tid];
-    for (int e = tid; e < kMaxTileSrc * 16; e += BLOCK) {
+    if (tid < kMaxTilePairs) {
+      s_src[tid] = a.tile_pcol[tile * kMaxTilePairs + tid];
+      s_part[tid] = a.tile_ppart[tile * kMaxTilePairs + tid];
+    }
+    for (int e = tid; e < kMaxTilePairs * 16; e += BLOCK) {
       const int si = e >> 4, r = e & 15;
       const uint32_t slot =
-          r < kMaxNbr ? (uint32_t)(a.tile_slots[tile * kMaxTileSrc + si] >> (5 * r)) & 31u : kNoSlot;
+          r < kMaxNbr ? (uint32_t)(a.tile_slots[tile * kMaxTilePairs + si] >> (5 * r)) & 31u : kNoSlot;
       s_base[e] = slot == (uint32_t)kNoSlot ? -1 : (int32_t)slot * npc;
     }
     const int32_t net = a.col_net[a.tile_cols[tile * kMaxTileCols]];
@@ -244,11 +250,10 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
         const int32_t s = s_src[si];
         const int64_t hb = (int64_t)(t % a.dh) * a.n_cols + s;
         const int32_t k = a.hist_ids[hb * npc + (qq - it_pref[lo])];
-        const int64_t i = (int64_t)s * npc + k;
-        const uint8_t* ent = a.idx + i * a.idxw;
-        const uint16_t* go = (const uint16_t*)(ent + 8);
+        const uint8_t* ent = idx_entry(a, s, k, s_part[si]);
+        const uint16_t* go = ent_goff(ent);
         const int32_t g0 = go[dd], g1 = go[dd + 1];
-        g_start[q] = *(const int64_t*)ent + g0;
+        g_start[q] = ent_start(ent) + g0;
         g_len[q] = g1 - g0;
         g_src[q] = (uint8_t)si;
       }
@@ -476,20 +481,25 @@ __global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u_ar
   for (int32_t g = blockIdx.x; g < a.n_cols; g += gridDim.x) {
     const int32_t ns = a.hist_cnt[(int64_t)uslot * a.n_cols + g];
     const uint16_t* ids = a.hist_ids + ((int64_t)uslot * a.n_cols + g) * a.npc;
+    const int np = a.col_np[g];
     for (int32_t q = wave; q < ns; q += NW) {
-      const int64_t i = (int64_t)g * a.npc + ids[q];
-      const int64_t st = idx_start(a, i);
-      const uint16_t* go = idx_goff(a, i);
+      const int32_t k = ids[q];
+      const int64_t i = (int64_t)g * a.npc + k;
       const int32_t len = a.deg[i];
       if (lane == 0 && len) atomicAdd(&a.net_cnt[kCounters * a.col_net[g] + 3], (unsigned long long)len);
-      for (int dd = 0; dd < a.nd; ++dd) {
-        const int64_t slot = (u + a.d_min + dd) % a.dh;
-        for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
-          const uint32_t w = a.syn[st + f];
-          if (rec_rank(w) == (uint32_t)kDummyRank) continue;
-          const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
-          atomicAdd(&a.ring[slot * nall + (int64_t)tc * a.npc + rec_k(w)],
-                    TRAIN ? a.wfx[st + f] : rec_w32(w));
+      for (int p = 0; p < np; ++p) {
+        const uint8_t* ent = idx_entry(a, g, k, p);
+        const int64_t st = ent_start(ent);
+        const uint16_t* go = ent_goff(ent);
+        for (int dd = 0; dd < a.nd; ++dd) {
+          const int64_t slot = (u + a.d_min + dd) % a.dh;
+          for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
+            const uint32_t w = a.syn[st + f];
+            if (rec_rank(w) == (uint32_t)kDummyRank) continue;
+            const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+            atomicAdd(&a.ring[slot * nall + (int64_t)tc * a.npc + rec_k(w)],
+                      TRAIN ? a.wfx[st + f] : rec_w32(w));
+          }
         }
       }
     }
@@ -553,7 +563,7 @@ static size_t tile_fixed_lds(const sim& s) {
 
 static size_t tile_static_bytes() {
   return sizeof(uint64_t) * kPoissonEntries + sizeof(int32_t) * (kMaxItems + 1) +
-         (sizeof(int32_t) + sizeof(uint64_t)) * kMaxTileSrc + sizeof(int32_t) * kMaxTileCols +
+         sizeof(int32_t) * 18 * kMaxTilePairs + sizeof(int32_t) * kMaxTileCols +
          (sizeof(int32_t) * 2 + 1 + sizeof(uint64_t)) * 16 + 64;
 }
 
@@ -590,8 +600,12 @@ StepArgs make_step_args(const sim& s) {
   a.grid_tiles = s.grid_tiles;
   a.tile_cols = s.tile_cols;
   a.tile_ncols = s.tile_ncols;
-  a.tile_src = s.tile_src;
-  a.tile_nsrc = s.tile_nsrc;
+  a.tile_pcol = s.tile_pcol;
+  a.tile_ppart = s.tile_ppart;
+  a.tile_npairs = s.tile_npairs;
+  a.col_np = s.col_np;
+  a.col_part = s.col_part;
+  a.col_pbase = s.col_pbase;
   a.tile_slots = s.tile_slots;
   a.row_base = s.row_base;
   a.deg = s.deg;

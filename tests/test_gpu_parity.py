@@ -173,3 +173,19 @@ def test_plain_4x4_half_second_bit_exact():
         sim.step(T)
         _check_run(sim, ref, T)
         sim.close()
+
+
+@pytest.mark.parametrize("native,other", [((2, 2), (3, 3)), ((3, 2), (1, 1)), ((4, 4), (2, 3))],
+                         ids=["2x2->3x3", "3x2->1x1", "4x4->2x3"])
+def test_tiles_other_than_the_storage_tiling(native, other):
+    """The synapse store is split by the tiling chosen at creation; a different tiling
+    later reads parts that reach several of its tiles and keeps only its own synapses."""
+    p = W.tiny(6, 7, npc=40, seed=17)
+    T = 160
+    ref = oracle.Sim(p)
+    ref.step(T)
+    sim = Simulation(p, record_steps=T, tile=native)
+    sim.step(60)
+    sim.set_launch(tile=other)
+    sim.step(T - 60)
+    _check_run(sim, ref, T)
