@@ -130,6 +130,14 @@ __global__ __launch_bounds__(256) void k_export_rows(StepArgs a, int32_t g0, int
   }
 }
 
+// Spike-history entries of every spike held in the history (after a restore).
+__global__ __launch_bounds__(256) void k_fill_entries(StepArgs a) {
+  const int32_t g = blockIdx.x, slot = blockIdx.y;
+  const int32_t ns = a.hist_cnt[(int64_t)slot * a.n_cols + g];
+  const uint16_t* ids = a.hist_ids + ((int64_t)slot * a.n_cols + g) * a.npc;
+  for (int32_t q = threadIdx.x; q < ns; q += 256) write_entries(a, g, ids[q], slot, q);
+}
+
 __global__ void k_set_now(int64_t* d_now, int64_t now) { *d_now = now; }
 __global__ void k_zero_u64(uint64_t* p) { *p = 0; }
 
@@ -178,6 +186,12 @@ hipError_t launch_raster(sim& s, int64_t u) {
   hipLaunchKernelGGL(k_raster_copy, dim3(s.n_cols), dim3(256), 0, s.stream, s.hist_cnt,
                      s.hist_ids, s.n_cols, s.npc, s.dh, u, nd, s.ras_colofs, s.ras_ids,
                      s.cfg.raster_capacity);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_entries(const sim& s) {
+  const StepArgs a = make_step_args(s);
+  hipLaunchKernelGGL(k_fill_entries, dim3(s.n_cols, s.dh), dim3(256), 0, s.stream, a);
   return hipGetLastError();
 }
 

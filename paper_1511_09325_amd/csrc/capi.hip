@@ -187,7 +187,7 @@ bool tile_fits(sim& s, int tx, int ty) {
     maxc = std::max(maxc, std::min(tx, s.nets[n].cols) * std::min(ty, s.nets[n].rows));
   const int32_t old = s.tile_max_cols;
   s.tile_max_cols = maxc;
-  const bool ok = tile_chunk(s) >= 256;
+  const bool ok = tile_lds_ok(s);
   s.tile_max_cols = old;
   return ok;
 }
@@ -218,7 +218,13 @@ void build_parts(sim& s, int tx, int ty) {
       np[g] = (int32_t)seen.size();
     }
   }
-  for (int32_t g = 0; g < s.n_cols; ++g) pbase[g + 1] = pbase[g] + (int64_t)s.npc * np[g];
+  std::vector<int32_t> pfirst((size_t)s.n_cols + 1, 0);
+  for (int32_t g = 0; g < s.n_cols; ++g) {
+    pbase[g + 1] = pbase[g] + (int64_t)s.npc * np[g];
+    pfirst[g + 1] = pfirst[g] + np[g];
+  }
+  s.n_parts = pfirst[s.n_cols];
+  s.col_pfirst = upload(s, pfirst);
   s.h_part = part;
   s.h_np = np;
   s.n_idx = pbase[s.n_cols];
@@ -302,7 +308,7 @@ void build_tiles(sim& s, int tx, int ty) {
   }
   const int32_t old_max = s.tile_max_cols;
   s.tile_max_cols = maxc;
-  if (tile_chunk(s) < 256) {
+  if (!tile_lds_ok(s)) {
     s.tile_max_cols = old_max;
     throw Fail{DPSNN_EINVAL, "tile accumulators exceed the 160 KB LDS of a workgroup"};
   }
@@ -576,6 +582,8 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->ref = (uint8_t*)dalloc(*s, N);
     s->hist_cnt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)s->dh * s->n_cols);
     s->hist_ids = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
+    s->hist_st = (int64_t*)dalloc(*s, sizeof(int64_t) * (size_t)s->dh * s->n_parts * s->npc);
+    s->hist_go = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_parts * (s->nd + 1) * s->npc);
     s->net_cnt = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets);
     s->flags = (int32_t*)dalloc(*s, sizeof(int32_t) * 4);
     s->d_now = (int64_t*)dalloc(*s, sizeof(int64_t));
@@ -1001,7 +1009,8 @@ void restore_from(sim& s, const Snapshot& sn) {
     off += (parts[q] + 255) & ~(size_t)255;
   }
   s.now = sn.now;
-  // the push ring is a function of the spike history: rebuild it
+  // the history entries and the push ring are functions of the spike history: rebuild them
+  HIPCHK(launch_fill_entries(s));
   if (s.delivery == DPSNN_DELIVERY_PUSH) ring_from_history(s);
 }
 

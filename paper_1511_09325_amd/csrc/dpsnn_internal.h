@@ -36,6 +36,12 @@
 //   spike history (shared by both delivery strategies)
 //     hist_cnt  int32 [DH][C]       spikes of column g at step t, in slot t % DH
 //     hist_ids  uint16[DH][C][npc]  their local indices, ascending
+//     hist_st   int64 [DH][P][npc]  per part (P = parts of all columns, part q of column g
+//                                   is col_pfirst[g] + q) and spike position: the start of
+//                                   the spiking neuron's part
+//     hist_go   uint16[DH][P][nd+1][npc]  its group offsets (copied from the row index when
+//                                   the neuron spiked, so that the readers of one source
+//                                   column's spikes load them contiguously)
 //   push-delivery ring (only with DPSNN_DELIVERY_PUSH)
 //     ring      int32 [DH][N]       input of step t in slot t % DH
 //
@@ -127,6 +133,8 @@ struct StepArgs {
   const int32_t* col_np;      // parts per column
   const int32_t* col_part;    // [C][9]: part of each neighbour rank
   const int64_t* col_pbase;   // first row-index entry of each column
+  const int32_t* col_pfirst;  // first part index of each column
+  int32_t n_parts;
   const int32_t* col_order;   // [grid_cols]: column of workgroup b of per-column kernels
   int32_t grid_cols;
   const uint32_t* net_key;    // [n_nets][2]
@@ -152,6 +160,8 @@ struct StepArgs {
   uint8_t* ref;
   int32_t* hist_cnt;
   uint16_t* hist_ids;
+  int64_t* hist_st;
+  uint16_t* hist_go;
   int32_t* ring;              // push only
   unsigned long long* net_cnt;  // [n_nets][kCounters]: spikes, e_rec, e_ext, synapse records
                                 // read, synapses delivered (arrival form)
@@ -173,6 +183,21 @@ __device__ __forceinline__ const uint8_t* idx_entry(const StepArgs& a, int32_t g
 __device__ __forceinline__ int64_t ent_start(const uint8_t* e) { return *(const int64_t*)e; }
 __device__ __forceinline__ const uint16_t* ent_goff(const uint8_t* e) {
   return (const uint16_t*)(e + 8);
+}
+
+// Spike-history entries of a spike of neuron k of column g at position pos of slot `slot`:
+// for every part, the part's start and group offsets, copied from the row index.
+__device__ __forceinline__ void write_entries(const StepArgs& a, int32_t g, int32_t k,
+                                              int32_t slot, int32_t pos) {
+  const int np = a.col_np[g];
+  for (int p = 0; p < np; ++p) {
+    const uint8_t* ent = idx_entry(a, g, k, p);
+    const int64_t pid = (int64_t)slot * a.n_parts + a.col_pfirst[g] + p;
+    a.hist_st[pid * a.npc + pos] = ent_start(ent);
+    const uint16_t* go = ent_goff(ent);
+    uint16_t* out = a.hist_go + pid * (int64_t)(a.nd + 1) * a.npc + pos;
+    for (int dd = 0; dd <= a.nd; ++dd) out[(int64_t)dd * a.npc] = go[dd];
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -212,6 +237,8 @@ struct sim {
   int32_t *col_net = nullptr, *col_local = nullptr, *col_nbr = nullptr, *col_nn = nullptr;
   int32_t *col_part = nullptr, *col_np = nullptr;
   int64_t* col_pbase = nullptr;
+  int32_t* col_pfirst = nullptr;
+  int32_t n_parts = 0;
   std::vector<int32_t> h_part, h_np;  // host copies of the part tables
   int64_t n_idx = 0;                  // row-index entries (neuron, part)
   int32_t native_tx = 0, native_ty = 0;  // tiling of the synapse parts
@@ -230,6 +257,8 @@ struct sim {
   uint8_t* ref = nullptr;
   int32_t* hist_cnt = nullptr;
   uint16_t* hist_ids = nullptr;
+  int64_t* hist_st = nullptr;
+  uint16_t* hist_go = nullptr;
   int32_t* ring = nullptr;
   unsigned long long* net_cnt = nullptr;
   // tiles of the current shape
@@ -293,7 +322,7 @@ hipError_t launch_init_state(const sim& s);
 hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block, int part);
 size_t tile_lds_bytes(const sim& s);
 hipError_t prepare_step_kernels();
-int32_t tile_chunk(const sim& s);
+bool tile_lds_ok(const sim& s);
 hipError_t launch_raster(sim& s, int64_t u);
 hipError_t launch_set_now(const sim& s, int64_t now);
 hipError_t launch_digest(const sim& s, uint64_t* out);
@@ -307,6 +336,7 @@ hipError_t launch_reduce_parts(const sim& s, double* out);
 hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst);
 hipError_t launch_weights_from_records(const sim& s);
 hipError_t launch_column_rates(const sim& s, float scale, float* rates);
+hipError_t launch_fill_entries(const sim& s);
 int64_t scan_scratch_len(int64_t n);
 
 StepArgs make_step_args(const sim& s);

@@ -27,9 +27,7 @@ namespace dpsnn {
 namespace {
 
 constexpr int kMaxItems = kMaxTilePairs * kMaxDelay;
-constexpr int kLanesPerGroup = 16;    // lanes streaming one group, 4 synapses each
-constexpr int kGroupsInFlight = 4;    // groups per lane set per round
-constexpr int kPiecesInFlight = 4;    // 16-byte loads per lane in flight
+constexpr int kPIF = 8;               // 16-byte synapse loads per lane in flight
 constexpr int kUpd = 2;               // 64-neuron chunks per wave per round of the update
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
@@ -151,45 +149,36 @@ __device__ __forceinline__ int32_t external_count(const StepArgs& a, int32_t g, 
 // tiling the synapse store was built for, exactly the synapses into this tile); an item is
 // the spike list of the source column at step u - d_min - dd, and every spike i of an item
 // is one group: the contiguous synapses of (i, part, delay).  The groups are taken in
-// chunks: first each thread locates groups (binary search over the item prefix, one spike
-// id, one row-index entry) into LDS, then sets of kLanesPerGroup lanes stream
-// kGroupsInFlight groups at a time in 16-byte words, keeping the synapses whose target
+// batches of 64 per wave, without workgroup barriers: each lane locates one group (binary
+// search over the item prefix, one spike id, one row-index entry), then each quad of lanes
+// streams the four groups of its lanes in 16-byte words, keeping the synapses whose target
 // column is in the tile (the record's rank, looked up in the pair's slot table) and adding
 // them to the tile's LDS accumulators with integer atomics.  Then the tile's neurons are
 // updated in 64-neuron chunks and the spikes compacted per column, in ascending order.
 template <int BLOCK, bool TRAIN>
-__global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc,
-                                                     int32_t chunk) {
+__global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc) {
   const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
   constexpr int NW = BLOCK / 64;
-  constexpr int NSET = BLOCK / kLanesPerGroup;
-  constexpr int GIF = kGroupsInFlight;
   extern __shared__ __align__(16) unsigned char lds[];
   __shared__ uint64_t ptab[kPoissonEntries];
   __shared__ int32_t it_pref[kMaxItems + 1];
   __shared__ int32_t s_src[kMaxTilePairs];      // source column of each pair
-  __shared__ int32_t s_part[kMaxTilePairs];     // part of each pair
+  __shared__ int32_t s_part[kMaxTilePairs];     // global part index of each pair
   __shared__ int32_t s_base[kMaxTilePairs * 16];  // per (pair, rank): slot * npc, or -1
   __shared__ int32_t s_col[kMaxTileCols];
+  __shared__ int32_t s_tot[kMaxTileCols];       // spikes of each column at this step
   __shared__ int32_t wsum[2 * NW + 1];
   __shared__ unsigned long long red[NW];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int npc = a.npc;
   const int nch = (npc + 63) >> 6;
-  // dynamic LDS: acc[maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch] | group starts,
-  // lengths and sources of one chunk
+  // dynamic LDS: acc[maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch]
   int32_t* acc = (int32_t*)lds;
   size_t off = ((size_t)maxc * npc * 4 + 15) & ~(size_t)15;
   unsigned long long* smask = (unsigned long long*)(lds + off);
   off += (size_t)maxc * nch * 8;
   int32_t* scnt = (int32_t*)(lds + off);
-  off += ((size_t)maxc * nch * 4 + 15) & ~(size_t)15;
-  int64_t* g_start = (int64_t*)(lds + off);
-  off += (size_t)chunk * 8;
-  int32_t* g_len = (int32_t*)(lds + off);
-  off += (size_t)chunk * 4;
-  uint8_t* g_src = (uint8_t*)(lds + off);
 
   for (int32_t b = blockIdx.x; b < a.grid_tiles; b += gridDim.x) {
     const int32_t tile = a.tile_order[b];
@@ -199,7 +188,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     if (tid < kMaxTileCols) s_col[tid] = a.tile_cols[tile * kMaxTileCols + tid];
     if (tid < kMaxTilePairs) {
       s_src[tid] = a.tile_pcol[tile * kMaxTilePairs + tid];
-      s_part[tid] = a.tile_ppart[tile * kMaxTilePairs + tid];
+      const int32_t pc = a.tile_pcol[tile * kMaxTilePairs + tid];
+      s_part[tid] = pc < 0 ? 0 : a.col_pfirst[pc] + a.tile_ppart[tile * kMaxTilePairs + tid];
     }
     for (int e = tid; e < kMaxTilePairs * 16; e += BLOCK) {
       const int si = e >> 4, r = e & 15;
@@ -232,13 +222,17 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     __syncthreads();
     const int32_t total = carry;
     unsigned long long streamed = 0;
-    // 2. gather, `chunk` groups at a time
     uint32_t delivered = 0;
-    for (int32_t base = 0; base < total; base += chunk) {
-      const int32_t n = min(chunk, total - base);
-#pragma unroll 2
-      for (int32_t q = tid; q < n; q += BLOCK) {
-        const int32_t qq = base + q;
+    // 2. gather.  Each wave independently takes batches of 64 groups (group q of the tile's
+    // list is spike q - it_pref[item] of item `item`): every lane locates one group, then
+    // every quad of lanes streams the four groups of its lanes in 16-byte pieces, kPIF
+    // loads in flight per lane, and adds the synapses into the LDS accumulators.
+    const int quad0 = lane & ~3, ql = lane & 3;
+    for (int32_t bt = wave; bt * 64 < total; bt += NW) {
+      const int32_t qq = bt * 64 + lane;
+      int64_t gst = 0;
+      int32_t glen = 0, gsb = 0;
+      if (qq < total) {
         int lo = 0, hi = n_items;
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
@@ -247,76 +241,60 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
         }
         const int si = lo / a.nd, dd = lo - si * a.nd;
         const int64_t t = u - (a.d_min + dd);
-        const int32_t s = s_src[si];
-        const int64_t hb = (int64_t)(t % a.dh) * a.n_cols + s;
-        const int32_t k = a.hist_ids[hb * npc + (qq - it_pref[lo])];
-        const uint8_t* ent = idx_entry(a, s, k, s_part[si]);
-        const uint16_t* go = ent_goff(ent);
-        const int32_t g0 = go[dd], g1 = go[dd + 1];
-        g_start[q] = ent_start(ent) + g0;
-        g_len[q] = g1 - g0;
-        g_src[q] = (uint8_t)si;
+        const int32_t pos = qq - it_pref[lo];
+        const int64_t pid = (int64_t)(t % a.dh) * a.n_parts + s_part[si];
+        const uint16_t* go = a.hist_go + pid * (int64_t)(a.nd + 1) * npc + pos;
+        const int32_t g0 = go[(int64_t)dd * npc], g1 = go[(int64_t)(dd + 1) * npc];
+        gst = a.hist_st[pid * npc + pos] + g0;
+        glen = (g1 - g0) >> 2;
+        gsb = si * 16;
       }
-      __syncthreads();
-      // stream: a set of kLanesPerGroup lanes walks the concatenated 16-byte pieces of GIF
-      // groups; every piece lies inside one group (groups are padded to 4 records)
-      const int set = tid / kLanesPerGroup, gl = tid % kLanesPerGroup;
-      for (int32_t r0 = set; r0 < n; r0 += NSET * GIF) {
-        int64_t st[GIF];
-        int32_t pref[GIF + 1];
-        int32_t sb[GIF];
-        pref[0] = 0;
+      streamed += (unsigned long long)(glen * 4);
+      int64_t st[4];
+      int32_t pref[5], sb[4];
+      pref[0] = 0;
 #pragma unroll
-        for (int m = 0; m < GIF; ++m) {
-          const int32_t gi = r0 + m * NSET;
-          const int32_t ln = gi < n ? g_len[gi] : 0;
-          st[m] = gi < n ? g_start[gi] : 0;
-          sb[m] = gi < n ? (int32_t)g_src[gi] * 16 : 0;
-          pref[m + 1] = pref[m] + (ln >> 2);
-          if (gl == 0) streamed += (unsigned long long)ln;
-        }
-        const int32_t npieces = pref[GIF];
-        for (int32_t p0 = gl; p0 < npieces; p0 += kLanesPerGroup * kPiecesInFlight) {
-          uint32_t w[kPiecesInFlight][4];
-          int32_t v[kPiecesInFlight][4];
-          int32_t base[kPiecesInFlight];
+      for (int m = 0; m < 4; ++m) {
+        st[m] = __shfl(gst, quad0 + m);
+        sb[m] = __shfl(gsb, quad0 + m);
+        pref[m + 1] = pref[m] + __shfl(glen, quad0 + m);
+      }
+      const int32_t npieces = pref[4];
+      for (int32_t p0 = ql; p0 < npieces; p0 += 4 * kPIF) {
+        uint32_t w[kPIF][4];
+        int32_t v[kPIF][4];
+        int32_t base[kPIF];
 #pragma unroll
-          for (int q = 0; q < kPiecesInFlight; ++q) {
-            const int32_t p = p0 + q * kLanesPerGroup;
-            base[q] = -1;
-            if (p < npieces) {
-              int m = 0;
-#pragma unroll
-              for (int z = 1; z < GIF; ++z) m += (p >= pref[z]) ? 1 : 0;
-              int64_t s0 = st[0];
-              int32_t pr = pref[0], b0 = sb[0];
-#pragma unroll
-              for (int z = 1; z < GIF; ++z)
-                if (m == z) { s0 = st[z]; pr = pref[z]; b0 = sb[z]; }
-              const int64_t addr = s0 + 4 * (int64_t)(p - pr);
-              base[q] = b0;
-              *(uint4*)&w[q][0] = *(const uint4*)(a.syn + addr);
-              if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(a.wfx + addr);
-            }
+        for (int q = 0; q < kPIF; ++q) {
+          const int32_t p = p0 + 4 * q;
+          base[q] = -1;
+          if (p < npieces) {
+            const int m = (p >= pref[1]) + (p >= pref[2]) + (p >= pref[3]);
+            const int64_t s0 = m == 0 ? st[0] : m == 1 ? st[1] : m == 2 ? st[2] : st[3];
+            const int32_t pr = m == 0 ? pref[0] : m == 1 ? pref[1] : m == 2 ? pref[2] : pref[3];
+            base[q] = m == 0 ? sb[0] : m == 1 ? sb[1] : m == 2 ? sb[2] : sb[3];
+            const int64_t addr = s0 + 4 * (int64_t)(p - pr);
+            *(uint4*)&w[q][0] = *(const uint4*)(a.syn + addr);
+            if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(a.wfx + addr);
           }
+        }
 #pragma unroll
-          for (int q = 0; q < kPiecesInFlight; ++q) {
-            if (base[q] >= 0) {
+        for (int q = 0; q < kPIF; ++q) {
+          if (base[q] >= 0) {
 #pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const uint32_t x = w[q][e];
-                const int32_t sbase = s_base[base[q] + (int)rec_rank(x)];
-                if (sbase >= 0) {
-                  atomicAdd(&acc[sbase + (int)rec_k(x)], TRAIN ? v[q][e] : rec_w32(x));
-                  delivered += 1;
-                }
+            for (int e = 0; e < 4; ++e) {
+              const uint32_t x = w[q][e];
+              const int32_t sbase = s_base[base[q] + (int)rec_rank(x)];
+              if (sbase >= 0) {
+                atomicAdd(&acc[sbase + (int)rec_k(x)], TRAIN ? v[q][e] : rec_w32(x));
+                delivered += 1;
               }
             }
           }
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
     // 3. update in 64-neuron chunks: chunk c is column c / nch, neurons (c % nch) * 64 + lane
     const int nchunks = T * nch;
     const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
@@ -383,7 +361,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       const unsigned long long m = smask[c];
       if ((m >> lane) & 1ull) {
         uint16_t* out = a.hist_ids + ((int64_t)slot_u * a.n_cols + s_col[col]) * npc;
-        out[before + __popcll(m & lt)] = (uint16_t)((c - first) * 64 + lane);
+        const int32_t pos = before + __popcll(m & lt);
+        const int32_t k = (c - first) * 64 + lane;
+        out[pos] = (uint16_t)k;
       }
     }
     unsigned long long my_spk = 0;
@@ -393,6 +373,27 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       a.hist_cnt[(int64_t)slot_u * a.n_cols + s_col[tid]] = tot;
       if (tot) a.col_spk[s_col[tid]] += (unsigned long long)tot;
       my_spk = (unsigned long long)tot;
+      s_tot[tid] = tot;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // 5. history entries of the step's spikes: for every column, part and field (start,
+    // group offsets) one row over the spike positions, written contiguously
+    for (int col = 0; col < T; ++col) {
+      const int32_t cnt = s_tot[col];
+      if (cnt == 0) continue;
+      const int32_t g = s_col[col];
+      const int32_t fields = a.nd + 2;
+      const int32_t rows = a.col_np[g] * fields;
+      const uint16_t* ids = a.hist_ids + ((int64_t)slot_u * a.n_cols + g) * npc;
+      for (int32_t e = tid; e < rows * cnt; e += BLOCK) {
+        const int32_t row = e / cnt, pos = e - row * cnt;
+        const int p = row / fields, f = row - p * fields;
+        const uint8_t* ent = idx_entry(a, g, ids[pos], p);
+        const int64_t pid = (int64_t)slot_u * a.n_parts + a.col_pfirst[g] + p;
+        if (f == 0) a.hist_st[pid * npc + pos] = ent_start(ent);
+        else a.hist_go[(pid * (a.nd + 1) + (f - 1)) * npc + pos] = ent_goff(ent)[f - 1];
+      }
     }
     const unsigned long long spk_all = block_sum_u64<BLOCK>(my_spk, red);
     const unsigned long long ext_all = block_sum_u64<BLOCK>(my_ext, red);
@@ -454,7 +455,11 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u_arg
         if (w < wave) before += wcnt[w];
         tot += wcnt[w];
       }
-      if (sp) out[running + before + __popcll(m & lt)] = (uint16_t)k;
+      if (sp) {
+        const int32_t pos = running + before + __popcll(m & lt);
+        out[pos] = (uint16_t)k;
+        write_entries(a, g, k, slot_u, pos);
+      }
       running += tot;
       __syncthreads();
     }
@@ -532,10 +537,10 @@ hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
     const size_t lds = tile_lds_bytes(s);
     if (train)
       hipLaunchKernelGGL((k_step_tile<BLOCK, true>), dim3(s.grid_tiles), dim3(BLOCK), lds,
-                         s.stream, a, u, s.tile_max_cols, tile_chunk(s));
+                         s.stream, a, u, s.tile_max_cols);
     else
       hipLaunchKernelGGL((k_step_tile<BLOCK, false>), dim3(s.grid_tiles), dim3(BLOCK), lds,
-                         s.stream, a, u, s.tile_max_cols, tile_chunk(s));
+                         s.stream, a, u, s.tile_max_cols);
     return hipGetLastError();
   }
   if (part != 1)
@@ -551,8 +556,8 @@ hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
 
 }  // namespace
 
-// LDS of the tile kernel: accumulators and spike masks for the largest tile, then the group
-// list of one gather pass, as long as the 160 KB allow (at most 4096 groups).
+// LDS of the tile kernel: accumulators and spike masks of the largest tile (dynamic), plus
+// the kernel's static tables; together at most the 160 KB of a workgroup.
 static size_t tile_fixed_lds(const sim& s) {
   const size_t nch = (size_t)(s.npc + 63) / 64;
   size_t b = ((size_t)s.tile_max_cols * s.npc * 4 + 15) & ~(size_t)15;
@@ -563,21 +568,13 @@ static size_t tile_fixed_lds(const sim& s) {
 
 static size_t tile_static_bytes() {
   return sizeof(uint64_t) * kPoissonEntries + sizeof(int32_t) * (kMaxItems + 1) +
-         sizeof(int32_t) * 18 * kMaxTilePairs + sizeof(int32_t) * kMaxTileCols +
+         sizeof(int32_t) * 18 * kMaxTilePairs + sizeof(int32_t) * 2 * kMaxTileCols +
          (sizeof(int32_t) * 2 + 1 + sizeof(uint64_t)) * 16 + 64;
 }
 
-int32_t tile_chunk(const sim& s) {
-  const size_t used = tile_fixed_lds(s) + tile_static_bytes();
-  if (used + 13 * 256 > kMaxLds) return 0;
-  size_t c = (kMaxLds - used) / 13;
-  if (c > 4096) c = 4096;
-  return (int32_t)(c & ~(size_t)255);
-}
+bool tile_lds_ok(const sim& s) { return tile_fixed_lds(s) + tile_static_bytes() <= kMaxLds; }
 
-size_t tile_lds_bytes(const sim& s) {
-  return tile_fixed_lds(s) + (size_t)tile_chunk(s) * (8 + 4 + 1);
-}
+size_t tile_lds_bytes(const sim& s) { return tile_fixed_lds(s); }
 
 StepArgs make_step_args(const sim& s) {
   StepArgs a{};
@@ -606,6 +603,10 @@ StepArgs make_step_args(const sim& s) {
   a.col_np = s.col_np;
   a.col_part = s.col_part;
   a.col_pbase = s.col_pbase;
+  a.col_pfirst = s.col_pfirst;
+  a.n_parts = s.n_parts;
+  a.hist_st = s.hist_st;
+  a.hist_go = s.hist_go;
   a.tile_slots = s.tile_slots;
   a.row_base = s.row_base;
   a.deg = s.deg;
