@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--delivery", default="arrival", choices=["arrival", "push"])
     ap.add_argument("--block", type=int, default=0, help="workgroup size (0: library default)")
     ap.add_argument("--tile", default="auto", help="arrival tile of target columns, e.g. 4x4")
+    ap.add_argument("--gather", type=int, default=0,
+                    help="arrival form: steps gathered per pass (0: library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fwd-bwd", action="store_true")
@@ -234,7 +236,7 @@ def main():
     log("generating %s on the GPU" % preset["name"])
     t0 = time.perf_counter()
     tile = (0, 0) if args.tile == "auto" else tuple(int(x) for x in args.tile.split("x"))
-    sim = Simulation(p, delivery=delivery, block=args.block, tile=tile)
+    sim = Simulation(p, delivery=delivery, block=args.block, tile=tile, gather_steps=args.gather)
     launch = sim.get_launch()
     sim.sync()
     t_gen = time.perf_counter() - t0
@@ -297,6 +299,7 @@ def main():
         "config": {"workload": preset["name"], "grid": args.workload, "neurons": sim.n_neurons,
                    "synapses": sim.n_synapses, "dt_ms": p["dt"], "delivery": args.delivery,
                    "block": launch["block"], "tile": "%dx%d" % launch["tile"],
+                   "gather_steps": launch["gather_steps"],
                    "parallelism": "single GPU"},
         "sim_ms_per_wall_s": K * p["dt"] / secs,
         "recurrent_events_per_s": e_rec / secs,

@@ -204,15 +204,19 @@ int sim_set_params(sim_t* sim, double tau_m, double g_ahp);
 
 /* Launch configuration of the step: delivery strategy, workgroup size and, for the arrival
  * form, the tile of target columns one workgroup owns (its LDS accumulators must fit in
- * 160 KB: tile_x * tile_y * npc * 4 bytes plus about 30 KB). */
+ * 160 KB: gather_steps * tile_x * tile_y * npc * 4 bytes plus about 20 KB).  The synapse
+ * store is split by the tiling chosen at creation; other tilings work but read more. */
 typedef struct {
   int32_t delivery;  /* DPSNN_DELIVERY_ARRIVAL or DPSNN_DELIVERY_PUSH */
   int32_t block;     /* 64, 128, 256, 512 or 1024 */
   int32_t tile_x, tile_y;  /* 1..4 */
   int32_t graph_steps;     /* steps per captured HIP graph, replayed by sim_step; 0 = direct */
+  int32_t gather_steps;    /* arrival form: steps whose input one pass over the spike history
+                              gathers (adjacent delay groups read together), 1..8; 0 = the
+                              largest that fits the LDS, at most 4 */
 } sim_launch_t;
 
-/* The launch configuration in use. */
+/* The launch configuration in use (gather_steps: the window in effect). */
 int sim_get_launch(const sim_t* sim, sim_launch_t* launch);
 /* Change it between steps (synchronises); results are bit-identical for every choice. */
 int sim_set_launch(sim_t* sim, const sim_launch_t* launch);
@@ -223,8 +227,8 @@ int sim_set_launch(sim_t* sim, const sim_launch_t* launch);
 int sim_state_digest(sim_t* sim, uint64_t* digest);
 
 /* Autotuner.  From the current state (kept in snapshot slot 63), runs `window` steps with
- * each candidate launch configuration (delivery form, workgroup size, tile shape, graph
- * chunk), timed with HIP events, checks that every candidate reaches the same state digest,
+ * each candidate launch configuration (delivery form, workgroup size, gather window, graph
+ * chunk; the arrival form keeps the tiling of creation), timed with HIP events, checks that every candidate reaches the same state digest,
  * restores the state and keeps the fastest.  cache_path (nullable): a JSON-lines file of
  * earlier results keyed by the device and the simulation's shape; a hit skips the search.
  * best / best_ms_per_step (nullable) receive the choice.  DPSNN_ESTATE if two candidates

@@ -51,7 +51,8 @@ class SimConfig(C.Structure):
 
 class SimLaunch(C.Structure):
     _fields_ = [("delivery", C.c_int32), ("block", C.c_int32), ("tile_x", C.c_int32),
-                ("tile_y", C.c_int32), ("graph_steps", C.c_int32)]
+                ("tile_y", C.c_int32), ("graph_steps", C.c_int32),
+                ("gather_steps", C.c_int32)]
 
 
 class SimInfo(C.Structure):

@@ -46,8 +46,9 @@ bool cache_lookup(const char* path, const std::string& key, sim_launch_t* out, d
     double t = 0;
     const char* p = strstr(line.c_str(), "\"delivery\":");
     if (!p || sscanf(p, "\"delivery\": %d, \"block\": %d, \"tile_x\": %d, \"tile_y\": %d, "
-                        "\"graph_steps\": %d, \"ms_per_step\": %lf",
-                     &l.delivery, &l.block, &l.tile_x, &l.tile_y, &l.graph_steps, &t) != 6)
+                        "\"graph_steps\": %d, \"gather_steps\": %d, \"ms_per_step\": %lf",
+                     &l.delivery, &l.block, &l.tile_x, &l.tile_y, &l.graph_steps,
+                     &l.gather_steps, &t) != 7)
       continue;
     *out = l;
     *ms = t;
@@ -62,8 +63,8 @@ void cache_store(const char* path, const std::string& key, const sim_launch_t& l
   if (!f) return;
   fprintf(f,
           "{\"key\": \"%s\", \"delivery\": %d, \"block\": %d, \"tile_x\": %d, \"tile_y\": %d, "
-          "\"graph_steps\": %d, \"ms_per_step\": %.6f}\n",
-          key.c_str(), l.delivery, l.block, l.tile_x, l.tile_y, l.graph_steps, ms);
+          "\"graph_steps\": %d, \"gather_steps\": %d, \"ms_per_step\": %.6f}\n",
+          key.c_str(), l.delivery, l.block, l.tile_x, l.tile_y, l.graph_steps, l.gather_steps, ms);
   fclose(f);
 }
 
@@ -94,16 +95,19 @@ extern "C" int sim_autotune(sim_t* s, int32_t window, const char* cache_path, si
   if ((rc = sim_save(s, kTuneSlot)) != DPSNN_OK) return rc;
 
   std::vector<sim_launch_t> cands;
+  // the arrival form keeps the tiling its synapse store was split for; other tilings read
+  // more synapses than they keep, so only the workgroup size, the gather window and graph
+  // chunks are searched
   const int blocks[] = {256, 512, 1024};
-  const int tiles[][2] = {{1, 1}, {2, 2}, {3, 3}, {4, 3}, {4, 4}};
   for (int b : blocks)
-    for (const auto& t : tiles)
-      for (int gs : {0, window}) cands.push_back(sim_launch_t{DPSNN_DELIVERY_ARRIVAL, b, t[0], t[1], gs});
+    for (int gw : {1, 2, 4})
+      for (int gs : {0, window})
+        cands.push_back(sim_launch_t{DPSNN_DELIVERY_ARRIVAL, b, s->native_tx, s->native_ty, gs, gw});
   // the push form scatters with device-scope atomics; only worth trying on small networks
   if (s->n_neurons <= 200000)
     for (int b : {256, 1024})
       for (int gs : {0, window})
-        cands.push_back(sim_launch_t{DPSNN_DELIVERY_PUSH, b, original.tile_x, original.tile_y, gs});
+        cands.push_back(sim_launch_t{DPSNN_DELIVERY_PUSH, b, original.tile_x, original.tile_y, gs, 1});
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
@@ -137,7 +141,8 @@ extern "C" int sim_autotune(sim_t* s, int32_t window, const char* cache_path, si
     } else if (d != ref_digest) {
       mismatch = "candidate delivery " + std::to_string(c.delivery) + " block " +
                  std::to_string(c.block) + " tile " + std::to_string(c.tile_x) + "x" +
-                 std::to_string(c.tile_y) + " reached a different state";
+                 std::to_string(c.tile_y) + " gather " + std::to_string(c.gather_steps) +
+                 " reached a different state";
       break;
     }
     if (!have_best || ms < best_t) {

@@ -306,9 +306,12 @@ void build_tiles(sim& s, int tx, int ty) {
     }
     rot = (rot + nstrip) % 8;
   }
-  const int32_t old_max = s.tile_max_cols;
+  const int32_t old_max = s.tile_max_cols, old_gk = s.gk;
   s.tile_max_cols = maxc;
-  if (!tile_lds_ok(s)) {
+  s.gk = 1;  // the fit of one accumulator; the gather window is chosen afterwards
+  const bool fits = tile_lds_ok(s);
+  s.gk = old_gk;
+  if (!fits) {
     s.tile_max_cols = old_max;
     throw Fail{DPSNN_EINVAL, "tile accumulators exceed the 160 KB LDS of a workgroup"};
   }
@@ -351,6 +354,37 @@ void choose_native(sim& s, int tx, int ty) {
     }
   }
   throw Fail{DPSNN_EINVAL, "no tile shape fits the LDS"};
+}
+
+// Arrival form: the saved accumulators are derived from the spike history; anything that
+// changes the history, the weights or the delivery makes them stale.
+void invalidate_gather(sim& s) {
+  if (s.d_gath) HIPCHK(hipMemsetAsync(s.d_gath, 0xff, sizeof(int64_t), s.stream));
+}
+
+constexpr int kMaxGather = 8;
+constexpr int kAutoGather = 4;
+
+// Steps gathered per window: the requested number (0: the largest that fits, at most
+// kAutoGather), reduced until the accumulators fit the LDS.
+void set_gather(sim& s, int want) {
+  if (want < 0 || want > kMaxGather) throw Fail{DPSNN_EINVAL, "gather_steps must be in [0, 8]"};
+  const int old = s.gk;
+  int k = want ? want : kAutoGather;
+  for (; k > 1; --k) {
+    s.gk = k;
+    if (tile_lds_ok(s)) break;
+  }
+  if (want && k != want) {
+    s.gk = old;
+    throw Fail{DPSNN_EINVAL, "gather_steps accumulators exceed the LDS"};
+  }
+  s.gk = k;
+  release(s, s.acc_save);
+  s.acc_save = nullptr;
+  if (k > 1) s.acc_save = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)k * (size_t)s.n_neurons);
+  s.gather_req = want;
+  invalidate_gather(s);
 }
 
 void build_tables(sim& s) {
@@ -589,6 +623,10 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->d_now = (int64_t*)dalloc(*s, sizeof(int64_t));
     s->d_digest = (uint64_t*)dalloc(*s, sizeof(uint64_t));
     s->col_spk = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * (size_t)s->n_cols);
+    s->d_gath = (int64_t*)dalloc(*s, sizeof(int64_t));
+    s->d_gdone = (uint32_t*)dalloc(*s, sizeof(uint32_t));
+    HIPCHK(hipMemsetAsync(s->d_gdone, 0, sizeof(uint32_t), s->stream));
+    set_gather(*s, 0);
     HIPCHK(hipMemsetAsync(s->col_spk, 0, sizeof(unsigned long long) * (size_t)s->n_cols, s->stream));
     HIPCHK(hipMemsetAsync(s->hist_cnt, 0, sizeof(int32_t) * (size_t)s->dh * s->n_cols, s->stream));
     HIPCHK(hipMemsetAsync(s->net_cnt, 0, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets, s->stream));
@@ -1011,6 +1049,7 @@ void restore_from(sim& s, const Snapshot& sn) {
   s.now = sn.now;
   // the history entries and the push ring are functions of the spike history: rebuild them
   HIPCHK(launch_fill_entries(s));
+  invalidate_gather(s);
   if (s.delivery == DPSNN_DELIVERY_PUSH) ring_from_history(s);
 }
 
@@ -1072,6 +1111,7 @@ int sim_get_launch(const sim_t* s, sim_launch_t* l) {
   l->tile_x = s->tile_x;
   l->tile_y = s->tile_y;
   l->graph_steps = s->graph_steps;
+  l->gather_steps = s->gk;
   return DPSNN_OK;
 }
 
@@ -1086,13 +1126,19 @@ int sim_set_launch(sim_t* s, const sim_launch_t* l) {
       throw Fail{DPSNN_EINVAL, "delivery must be ARRIVAL or PUSH"};
     if (l->graph_steps < 0 || l->graph_steps > 4096)
       throw Fail{DPSNN_EINVAL, "graph_steps must be in [0, 4096]"};
+    if (l->gather_steps < 0 || l->gather_steps > kMaxGather)
+      throw Fail{DPSNN_EINVAL, "gather_steps must be in [0, 8]"};
     HIPCHK(hipStreamSynchronize(s->stream));
     drop_graph(*s);
     s->graph_steps = l->graph_steps;
-    if (l->tile_x != s->tile_x || l->tile_y != s->tile_y) build_tiles(*s, l->tile_x, l->tile_y);
+    if (l->tile_x != s->tile_x || l->tile_y != s->tile_y) {
+      s->gk = 1;
+      build_tiles(*s, l->tile_x, l->tile_y);
+    }
     if (l->delivery == DPSNN_DELIVERY_PUSH && s->delivery != DPSNN_DELIVERY_PUSH) ring_from_history(*s);
     s->delivery = l->delivery;
     s->block = block;
+    set_gather(*s, l->gather_steps);
     return DPSNN_OK;
   } catch (const Fail& f) {
     return finish(s, f);
@@ -1122,6 +1168,7 @@ int sim_set_weights(sim_t* s, const float* w) {
     if (!w) throw Fail{DPSNN_EINVAL, "w is NULL"};
     HIPCHK(launch_canon_map(*s, 0, w, s->wf32));
     HIPCHK(launch_quantise(*s));
+    invalidate_gather(*s);
     break_window(*s);
     return DPSNN_OK;
   } catch (const Fail& f) {

@@ -162,6 +162,12 @@ struct StepArgs {
   uint16_t* hist_ids;
   int64_t* hist_st;
   uint16_t* hist_go;
+  // arrival form: steps gathered per window, accumulators of later steps, last gathering
+  // step, finished-workgroup counter
+  int32_t gk;
+  int32_t* acc_save;          // [gk][N]
+  int64_t* gath;
+  uint32_t* gdone;
   int32_t* ring;              // push only
   unsigned long long* net_cnt;  // [n_nets][kCounters]: spikes, e_rec, e_ext, synapse records
                                 // read, synapses delivered (arrival form)
@@ -259,6 +265,11 @@ struct sim {
   uint16_t* hist_ids = nullptr;
   int64_t* hist_st = nullptr;
   uint16_t* hist_go = nullptr;
+  int32_t gk = 1;                  // steps gathered per window (arrival form)
+  int32_t gather_req = 0;          // requested gather_steps (0: automatic)
+  int32_t* acc_save = nullptr;     // [gk][N] accumulators of the later steps of a window
+  int64_t* d_gath = nullptr;       // last gathering step, -1 when acc_save is not valid
+  uint32_t* d_gdone = nullptr;     // finished workgroups of a gathering launch
   int32_t* ring = nullptr;
   unsigned long long* net_cnt = nullptr;
   // tiles of the current shape

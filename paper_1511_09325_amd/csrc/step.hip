@@ -21,6 +21,8 @@
 //   PUSH     update kernel reading a delay ring ring[u % DH][j], then a delivery kernel
 //            that scatters each spiking row into ring[(u + d) % DH][target] with
 //            device-scope integer atomics.
+#include <algorithm>
+
 #include "dpsnn_internal.h"
 
 namespace dpsnn {
@@ -142,6 +144,25 @@ __device__ __forceinline__ int32_t external_count(const StepArgs& a, int32_t g, 
   return poisson_count(ptab, x.x);
 }
 
+// Delays read for spikes of age b (emitted at u - b): at a light step only the spikes
+// emitted since the gathering step (b <= jnew), with delay b; at a gathering step with
+// window W the delays b .. b + W - 1.  Clipped to [d_min, d_max].  Returns how many, and
+// the first in *dlo.
+__device__ __forceinline__ int32_t item_delays(const StepArgs& a, bool light, int32_t jnew,
+                                               int32_t W, int32_t b, int32_t* dlo) {
+  const int32_t d_max = a.d_min + a.nd - 1;
+  int32_t lo = b, hi = b;
+  if (light) {
+    if (b > jnew) return 0;
+  } else {
+    hi = b + W - 1;
+  }
+  if (lo < a.d_min) lo = a.d_min;
+  if (hi > d_max) hi = d_max;
+  *dlo = lo;
+  return hi >= lo ? hi - lo + 1 : 0;
+}
+
 // ---- ARRIVAL: tiles of target columns ---------------------------------------------------
 //
 // Work list of a tile at step u: items (pair si, delay index dd) where a pair is a source
@@ -173,13 +194,26 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   const int lane = tid & 63, wave = tid >> 6;
   const int npc = a.npc;
   const int nch = (npc + 63) >> 6;
-  // dynamic LDS: acc[maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch]
+  // dynamic LDS: acc[K][maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch]
+  const int32_t K = a.gk;
   int32_t* acc = (int32_t*)lds;
-  size_t off = ((size_t)maxc * npc * 4 + 15) & ~(size_t)15;
+  size_t off = ((size_t)K * maxc * npc * 4 + 15) & ~(size_t)15;
   unsigned long long* smask = (unsigned long long*)(lds + off);
   off += (size_t)maxc * nch * 8;
   int32_t* scnt = (int32_t*)(lds + off);
 
+  // Steps are gathered in windows of up to K: a gathering step reads, for every spike, the
+  // delay groups due at its own step and at the following steps of its window (adjacent in
+  // memory), keeping one accumulator per step; the accumulators of later steps go to
+  // acc_save.  The other steps of the window ("light" steps) read only the spikes emitted
+  // since the gathering step, plus their saved accumulator.  *gath is the last gathering
+  // step (-1 after anything that invalidates acc_save).
+  const int64_t g_last = *a.gath;
+  const bool light = K > 1 && g_last >= 0 && u > g_last && u < g_last + (K - (int32_t)(g_last % K));
+  const int32_t W = light ? 1 : K - (int32_t)(u % K);
+  const int32_t jnew = light ? (int32_t)(u - g_last) : 0;
+  const int32_t NB = a.dh - 1;  // spike ages b = u - t in [1, d_max]
+  const int64_t nall = (int64_t)a.n_cols * npc;
   for (int32_t b = blockIdx.x; b < a.grid_tiles; b += gridDim.x) {
     const int32_t tile = a.tile_order[b];
     if (tile < 0) continue;
@@ -200,18 +234,21 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     const int32_t net = a.col_net[a.tile_cols[tile * kMaxTileCols]];
     for (int q = tid; q < kPoissonEntries; q += BLOCK)
       ptab[q] = a.net_ptab[(int64_t)net * kPoissonEntries + q];
-    for (int e = tid; e < T * npc; e += BLOCK) acc[e] = 0;
+    const int32_t TN = T * npc;
+    for (int e = tid; e < W * TN; e += BLOCK) acc[e] = 0;
     __syncthreads();
-    // 1. items and their spike counts
-    const int n_items = ns * a.nd;
+    // 1. items (pair, spike age b) and their group counts: spikes x delays read
+    const int n_items = ns * NB;
     int32_t carry = 0;
     for (int bb = 0; bb < n_items; bb += BLOCK) {
       const int it = bb + tid;
       int32_t cnt = 0;
       if (it < n_items) {
-        const int si = it / a.nd, dd = it - si * a.nd;
-        const int64_t t = u - (a.d_min + dd);
-        if (t >= 0) cnt = a.hist_cnt[(int64_t)(t % a.dh) * a.n_cols + s_src[si]];
+        const int si = it / NB, ag = it - si * NB + 1;
+        const int64_t t = u - ag;
+        int32_t dlo;
+        const int32_t ndel = item_delays(a, light, jnew, W, ag, &dlo);
+        if (t >= 0 && ndel > 0) cnt = ndel * a.hist_cnt[(int64_t)(t % a.dh) * a.n_cols + s_src[si]];
       }
       int32_t tot;
       const int32_t ex = block_excl_scan<BLOCK>(cnt, &tot, wsum);
@@ -239,15 +276,20 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
           if (it_pref[mid] <= qq) lo = mid;
           else hi = mid;
         }
-        const int si = lo / a.nd, dd = lo - si * a.nd;
-        const int64_t t = u - (a.d_min + dd);
-        const int32_t pos = qq - it_pref[lo];
+        const int si = lo / NB, ag = lo - si * NB + 1;
+        const int64_t t = u - ag;
+        int32_t dlo;
+        const int32_t ndel = item_delays(a, light, jnew, W, ag, &dlo);
+        const int32_t r = qq - it_pref[lo];
+        const int32_t pos = r / ndel;
+        const int32_t d = dlo + (r - pos * ndel);
+        const int32_t dd = d - a.d_min;
         const int64_t pid = (int64_t)(t % a.dh) * a.n_parts + s_part[si];
         const uint16_t* go = a.hist_go + pid * (int64_t)(a.nd + 1) * npc + pos;
         const int32_t g0 = go[(int64_t)dd * npc], g1 = go[(int64_t)(dd + 1) * npc];
         gst = a.hist_st[pid * npc + pos] + g0;
         glen = (g1 - g0) >> 2;
-        gsb = si * 16;
+        gsb = si * 16 + ((d - ag) << 16);
       }
       streamed += (unsigned long long)(glen * 4);
       int64_t st[4];
@@ -284,9 +326,10 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const uint32_t x = w[q][e];
-              const int32_t sbase = s_base[base[q] + (int)rec_rank(x)];
+              const int32_t sbase = s_base[(base[q] & 0xffff) + (int)rec_rank(x)];
               if (sbase >= 0) {
-                atomicAdd(&acc[sbase + (int)rec_k(x)], TRAIN ? v[q][e] : rec_w32(x));
+                atomicAdd(&acc[(base[q] >> 16) * TN + sbase + (int)rec_k(x)],
+                          TRAIN ? v[q][e] : rec_w32(x));
                 delivered += 1;
               }
             }
@@ -295,6 +338,12 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       }
     }
     __syncthreads();
+    // the accumulators of the later steps of the window, for their light steps
+    for (int e = tid; e < (W - 1) * TN; e += BLOCK) {
+      const int w = 1 + e / TN, rem = e - (w - 1) * TN;
+      const int col = rem / npc, k = rem - col * npc;
+      a.acc_save[((u + w) % K) * nall + (int64_t)s_col[col] * npc + k] = acc[w * TN + rem];
+    }
     // 3. update in 64-neuron chunks: chunk c is column c / nch, neurons (c % nch) * 64 + lane
     const int nchunks = T * nch;
     const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
@@ -338,7 +387,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
           if (ok[m]) {
             const int col = c / nch, k = (c - col * nch) * 64 + lane;
             const int64_t j = (int64_t)s_col[col] * npc + k;
-            sp = neuron_step(a, j, u, acc[col * npc + k], nx[m], vv[m], cc[m], rr[m]);
+            int32_t in = acc[col * npc + k];
+            if (light) in = (int32_t)((uint32_t)in + (uint32_t)a.acc_save[(u % K) * nall + j]);
+            sp = neuron_step(a, j, u, in, nx[m], vv[m], cc[m], rr[m]);
             my_ext += (unsigned long long)nx[m];
             if (sp) my_rec += (unsigned long long)a.deg[j];
           }
@@ -408,6 +459,15 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       if (del_all) atomicAdd(&a.net_cnt[kCounters * net + 4], del_all);
     }
     __syncthreads();
+  }
+  // the last workgroup to finish records a gathering step (every workgroup has read *gath)
+  if (K > 1 && !light && tid == 0) {
+    __threadfence();
+    if (atomicAdd(a.gdone, 1u) == gridDim.x - 1) {
+      *a.gath = u;
+      *a.gdone = 0u;
+      __threadfence();
+    }
   }
 }
 
@@ -560,7 +620,7 @@ hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
 // the kernel's static tables; together at most the 160 KB of a workgroup.
 static size_t tile_fixed_lds(const sim& s) {
   const size_t nch = (size_t)(s.npc + 63) / 64;
-  size_t b = ((size_t)s.tile_max_cols * s.npc * 4 + 15) & ~(size_t)15;
+  size_t b = ((size_t)std::max(s.gk, 1) * s.tile_max_cols * s.npc * 4 + 15) & ~(size_t)15;
   b += (size_t)s.tile_max_cols * nch * 8;
   b += ((size_t)s.tile_max_cols * nch * 4 + 15) & ~(size_t)15;
   return b;
@@ -607,6 +667,10 @@ StepArgs make_step_args(const sim& s) {
   a.n_parts = s.n_parts;
   a.hist_st = s.hist_st;
   a.hist_go = s.hist_go;
+  a.gk = std::max(s.gk, 1);
+  a.acc_save = s.acc_save;
+  a.gath = s.d_gath;
+  a.gdone = s.d_gdone;
   a.tile_slots = s.tile_slots;
   a.row_base = s.row_base;
   a.deg = s.deg;

@@ -58,7 +58,8 @@ class Simulation:
     def __init__(self, params, *, delivery: int = L.DELIVERY_AUTO, block: int = 0,
                  tile: tuple[int, int] = (0, 0), record_steps: int = 0,
                  raster_capacity: int | None = None, train_mode: bool = False,
-                 ckpt_every: int = 50, surrogate_beta: float = 5.0, stream=None):
+                 ckpt_every: int = 50, surrogate_beta: float = 5.0, gather_steps: int = 0,
+                 stream=None):
         self.params = params if isinstance(params, list) else [params]
         if raster_capacity is None:
             n = sum(p["rows"] * p["cols"] * p["npc"] for p in self.params)
@@ -82,6 +83,8 @@ class Simulation:
         self.ring_slots = info.ring_slots
         self.device_bytes = info.device_bytes
         self.record_steps = record_steps
+        if gather_steps:
+            self.set_launch(gather_steps=gather_steps)
 
     # -- lifetime -------------------------------------------------------------------------
     def close(self):
@@ -174,7 +177,8 @@ class Simulation:
         L.check(self.lib.sim_restore(self.h, slot), self.h)
 
     def set_launch(self, delivery: int | None = None, block: int | None = None,
-                   tile: tuple[int, int] | None = None, graph_steps: int | None = None):
+                   tile: tuple[int, int] | None = None, graph_steps: int | None = None,
+                   gather_steps: int | None = None):
         """Change the launch configuration; None keeps the current value."""
         cur = self.get_launch()
         lc = L.SimLaunch()
@@ -183,13 +187,16 @@ class Simulation:
         tx, ty = cur["tile"] if tile is None else tile
         lc.tile_x, lc.tile_y = int(tx), int(ty)
         lc.graph_steps = cur["graph_steps"] if graph_steps is None else int(graph_steps)
+        if gather_steps is None:  # keep the window, unless the tile changes: then automatic
+            gather_steps = cur["gather_steps"] if tile is None else 0
+        lc.gather_steps = int(gather_steps)
         L.check(self.lib.sim_set_launch(self.h, C.byref(lc)), self.h)
 
     def get_launch(self) -> dict:
         lc = L.SimLaunch()
         L.check(self.lib.sim_get_launch(self.h, C.byref(lc)), self.h)
         return {"delivery": lc.delivery, "block": lc.block, "tile": (lc.tile_x, lc.tile_y),
-                "graph_steps": lc.graph_steps}
+                "graph_steps": lc.graph_steps, "gather_steps": lc.gather_steps}
 
     def digest(self) -> int:
         d = C.c_uint64()
@@ -205,7 +212,8 @@ class Simulation:
                                       cache_path.encode() if cache_path else None,
                                       C.byref(lc), C.byref(ms)), self.h)
         return {"delivery": lc.delivery, "block": lc.block, "tile": (lc.tile_x, lc.tile_y),
-                "graph_steps": lc.graph_steps, "ms_per_step": ms.value}
+                "graph_steps": lc.graph_steps, "gather_steps": lc.gather_steps,
+                "ms_per_step": ms.value}
 
     def set_params(self, tau_m: float, g_ahp: float):
         L.check(self.lib.sim_set_params(self.h, float(tau_m), float(g_ahp)), self.h)

@@ -189,3 +189,36 @@ def test_tiles_other_than_the_storage_tiling(native, other):
     sim.set_launch(tile=other)
     sim.step(T - 60)
     _check_run(sim, ref, T)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 8])
+def test_gather_windows_bit_exact(K):
+    """Gathering the input of K steps in one pass over the spike history (adjacent delay
+    groups, one accumulator per step) gives the same run for every window."""
+    p = W.tiny(5, 7, npc=40, seed=11)
+    T = 230
+    ref = oracle.Sim(p)
+    ref.step(T)
+    sim = Simulation(p, record_steps=T, gather_steps=K)
+    assert sim.get_launch()["gather_steps"] == K
+    sim.step(T)
+    _check_run(sim, ref, T)
+
+
+def test_gather_window_interrupted():
+    """Restores, launch changes and graph chunks that start inside a gather window."""
+    p = W.tiny(4, 5, npc=40, seed=19)
+    T = 200
+    ref = oracle.Sim(p)
+    ref.step(T)
+    sim = Simulation(p, record_steps=T, gather_steps=4)
+    sim.step(41)                      # inside the window that starts at step 40
+    sim.save(1)
+    sim.step(23)
+    sim.restore(1)                    # back to step 41
+    sim.step(6)
+    sim.set_launch(graph_steps=7)     # chunks of 7 steps across windows of 4
+    sim.step(70)
+    sim.set_launch(gather_steps=3, graph_steps=0)
+    sim.step(T - 117)
+    _check_run(sim, ref, T)
