@@ -135,6 +135,25 @@ def batched_leg(torch, steps=1000, warmup=50, graph_steps=50):
             "mean_rate_hz": spk_b / (n_neurons * steps * 1e-3)}
 
 
+def rate_matched_leg(torch, steps=1000, warmup=50):
+    """The 96x96 grid with inhibitory weights -N(1.2, 0.12) mV (a few Hz instead of the tens
+    of Hz of the literal parameters), same launch defaults: the low-rate end of the step."""
+    from paper_1511_09325_amd import Simulation
+    from paper_1511_09325_amd import workloads as W
+    preset = W.PLAIN_96X96_RATE_MATCHED
+    p = preset["params"]
+    sim = Simulation(p)
+    sim.step(warmup)
+    sim.sync()
+    t, ev, spk = _timed_run(sim, steps, torch)
+    out = {"workload": preset["name"], "steps": steps, "ms_per_step": t * 1e3 / steps,
+           "events_per_s": ev / t, "sim_ms_per_wall_s": steps * p["dt"] / t,
+           "mean_rate_hz": spk / (sim.n_neurons * steps * p["dt"] * 1e-3)}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def fwd_bwd_leg(torch, iters=3):
     """Forward+backward on the 4x4 grid (19,840 neurons), 500 ms, checkpoints every 50
     steps: loss = mean over columns of (rate - target)^2 with seeded U(2, 8) Hz targets,
@@ -201,6 +220,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fwd-bwd", action="store_true")
+    ap.add_argument("--no-rate-matched", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB once (a reference kernel of known "
                          "traffic for hardware byte counters)")
@@ -317,6 +337,9 @@ def main():
     if not args.no_batched:
         log("batched leg: 64 networks, one launch per step, vs 64 sequential runs")
         out["batched"] = batched_leg(torch)
+    if not args.no_rate_matched and args.workload == "96x96":
+        log("rate-matched leg: 96x96 with stronger inhibition")
+        out["rate_matched"] = rate_matched_leg(torch)
     if not args.no_fwd_bwd:
         log("forward+backward leg: 4x4, 500 steps, vs the plain forward")
         out["fwd_bwd"] = fwd_bwd_leg(torch)

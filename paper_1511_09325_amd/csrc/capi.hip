@@ -283,7 +283,7 @@ void build_tiles(sim& s, int tx, int ty) {
               }
               if (any) {
                 pairs.push_back({sc, p});
-                packs.push_back(packed);
+                packs.push_back(packed | ~(((uint64_t)1 << (5 * kMaxNbr)) - 1));  // ranks >= 9: 31
               }
             }
           }
@@ -336,8 +336,9 @@ void build_tiles(sim& s, int tx, int ty) {
   s.tile_slots = upload(s, tslots);
 }
 
-// Native tiling: the configured one, else the largest square-ish tile (sides <= 4) whose
-// accumulators fit the LDS.
+// Native tiling: the configured one, else the first of the shapes below whose accumulators
+// fit the LDS.  4x3 comes first: with 1240-neuron columns it leaves room for two gather
+// accumulators, and 96x96 gives 768 tiles, three full waves of 256 workgroups.
 void choose_native(sim& s, int tx, int ty) {
   if (tx || ty) {
     if (!tile_fits(s, tx, ty)) throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4] and fit the LDS"};
@@ -345,7 +346,7 @@ void choose_native(sim& s, int tx, int ty) {
     s.native_ty = ty;
     return;
   }
-  static const int shapes[][2] = {{4, 4}, {4, 3}, {3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
+  static const int shapes[][2] = {{4, 3}, {4, 4}, {3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
   for (const auto& sh : shapes) {
     if (tile_fits(s, sh[0], sh[1])) {
       s.native_tx = sh[0];
@@ -480,6 +481,9 @@ void generate(sim& s) {
   int64_t total = 0;
   HIPCHK(hipMemcpyAsync(&total, s.row_base + N, sizeof(int64_t), hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
+  // the tile kernel addresses 16-byte pieces of the store with 32-bit indices
+  if (total / 4 >= ((int64_t)1 << 32))
+    throw Fail{DPSNN_EINVAL, "synapse store exceeds 2^34 records"};
   // one spare uint4 after the last synapse: the delivery kernels may load whole 16-byte
   // words that straddle the end of a segment
   s.syn = (uint32_t*)dalloc(s, sizeof(uint32_t) * (size_t)(total + 4));

@@ -32,7 +32,7 @@
 //                                     tiling; a part may reach several tiles otherwise)
 //     tile_slots  uint64[tiles][64]   for each pair and each rank r of its part, the tile
 //                                     slot of its target column in bits 5r..5r+4 (31: not
-//                                     in the tile or not in the part)
+//                                     in the tile or not in the part); bits 45-63 are set
 //   spike history (shared by both delivery strategies)
 //     hist_cnt  int32 [DH][C]       spikes of column g at step t, in slot t % DH
 //     hist_ids  uint16[DH][C][npc]  their local indices, ascending

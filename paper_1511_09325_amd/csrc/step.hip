@@ -29,7 +29,8 @@ namespace dpsnn {
 namespace {
 
 constexpr int kMaxItems = kMaxTilePairs * kMaxDelay;
-constexpr int kPIF = 8;               // 16-byte synapse loads per lane in flight
+constexpr int kPIF = 4;               // 16-byte synapse loads per lane in flight
+constexpr int kIdxWords = (8 + 2 * (kMaxDelay + 1) + 15) / 16;  // 16-byte words of an entry
 constexpr int kUpd = 2;               // 64-neuron chunks per wave per round of the update
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
@@ -185,9 +186,10 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   __shared__ int32_t it_pref[kMaxItems + 1];
   __shared__ int32_t s_src[kMaxTilePairs];      // source column of each pair
   __shared__ int32_t s_part[kMaxTilePairs];     // global part index of each pair
-  __shared__ int32_t s_base[kMaxTilePairs * 16];  // per (pair, rank): slot * npc, or -1
+  __shared__ uint64_t s_slots[kMaxTilePairs];    // per pair: 5-bit tile slot of each rank
   __shared__ int32_t s_col[kMaxTileCols];
   __shared__ int32_t s_tot[kMaxTileCols];       // spikes of each column at this step
+  __shared__ int32_t s_epre[kMaxTileCols + 1];  // prefix of (parts x spikes) over columns
   __shared__ int32_t wsum[2 * NW + 1];
   __shared__ unsigned long long red[NW];
   const int tid = threadIdx.x;
@@ -225,12 +227,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       const int32_t pc = a.tile_pcol[tile * kMaxTilePairs + tid];
       s_part[tid] = pc < 0 ? 0 : a.col_pfirst[pc] + a.tile_ppart[tile * kMaxTilePairs + tid];
     }
-    for (int e = tid; e < kMaxTilePairs * 16; e += BLOCK) {
-      const int si = e >> 4, r = e & 15;
-      const uint32_t slot =
-          r < kMaxNbr ? (uint32_t)(a.tile_slots[tile * kMaxTilePairs + si] >> (5 * r)) & 31u : kNoSlot;
-      s_base[e] = slot == (uint32_t)kNoSlot ? -1 : (int32_t)slot * npc;
-    }
+    if (tid < kMaxTilePairs) s_slots[tid] = a.tile_slots[tile * kMaxTilePairs + tid];
     const int32_t net = a.col_net[a.tile_cols[tile * kMaxTileCols]];
     for (int q = tid; q < kPoissonEntries; q += BLOCK)
       ptab[q] = a.net_ptab[(int64_t)net * kPoissonEntries + q];
@@ -265,10 +262,16 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     // every quad of lanes streams the four groups of its lanes in 16-byte pieces, kPIF
     // loads in flight per lane, and adds the synapses into the LDS accumulators.
     const int quad0 = lane & ~3, ql = lane & 3;
+    // exact small-integer quotients through float reciprocals (operands < 2^16)
+    const float inv_nb = 1.0f / (float)NB;
+    const int32_t u_slot = (int32_t)(u % a.dh);
     for (int32_t bt = wave; bt * 64 < total; bt += NW) {
       const int32_t qq = bt * 64 + lane;
-      int64_t gst = 0;
+      // this lane's group: first 16-byte piece, length in pieces, the offset of the
+      // accumulator of its step and its pair's slot word
+      uint32_t gpc = 0;
       int32_t glen = 0, gsb = 0;
+      uint64_t gsl = ~(uint64_t)0;
       if (qq < total) {
         int lo = 0, hi = n_items;
         while (hi - lo > 1) {
@@ -276,62 +279,72 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
           if (it_pref[mid] <= qq) lo = mid;
           else hi = mid;
         }
-        const int si = lo / NB, ag = lo - si * NB + 1;
-        const int64_t t = u - ag;
+        const int si = (int)(((float)lo + 0.5f) * inv_nb);
+        const int ag = lo - si * NB + 1;
         int32_t dlo;
         const int32_t ndel = item_delays(a, light, jnew, W, ag, &dlo);
         const int32_t r = qq - it_pref[lo];
-        const int32_t pos = r / ndel;
+        const int32_t pos = (int32_t)(((float)r + 0.5f) * __builtin_amdgcn_rcpf((float)ndel));
         const int32_t d = dlo + (r - pos * ndel);
-        const int32_t dd = d - a.d_min;
-        const int64_t pid = (int64_t)(t % a.dh) * a.n_parts + s_part[si];
-        const uint16_t* go = a.hist_go + pid * (int64_t)(a.nd + 1) * npc + pos;
-        const int32_t g0 = go[(int64_t)dd * npc], g1 = go[(int64_t)(dd + 1) * npc];
-        gst = a.hist_st[pid * npc + pos] + g0;
+        int32_t slot = u_slot - ag;
+        if (slot < 0) slot += a.dh;
+        const int64_t pid = (int64_t)slot * a.n_parts + s_part[si];
+        const uint16_t* go = a.hist_go + (pid * (a.nd + 1) + (d - a.d_min)) * npc + pos;
+        const int32_t g0 = go[0], g1 = go[npc];
+        gpc = (uint32_t)((a.hist_st[pid * npc + pos] + g0) >> 2);
         glen = (g1 - g0) >> 2;
-        gsb = si * 16 + ((d - ag) << 16);
+        gsb = (d - ag) * TN;
+        gsl = s_slots[si];
       }
       streamed += (unsigned long long)(glen * 4);
-      int64_t st[4];
-      int32_t pref[5], sb[4];
+      // the quad streams the pieces of its four groups: piece p of the quad lies in group m
+      // where pref[m] <= p < pref[m + 1], at piece index bias[m] + p
+      int32_t pref[5], sbq[4];
+      uint32_t bias[4];
+      uint64_t slq[4];
       pref[0] = 0;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        st[m] = __shfl(gst, quad0 + m);
-        sb[m] = __shfl(gsb, quad0 + m);
+        bias[m] = (uint32_t)__shfl((int32_t)gpc, quad0 + m) - (uint32_t)pref[m];
+        sbq[m] = __shfl(gsb, quad0 + m);
+        slq[m] = ((uint64_t)(uint32_t)__shfl((int32_t)(gsl >> 32), quad0 + m) << 32) |
+                 (uint32_t)__shfl((int32_t)(uint32_t)gsl, quad0 + m);
         pref[m + 1] = pref[m] + __shfl(glen, quad0 + m);
       }
       const int32_t npieces = pref[4];
       for (int32_t p0 = ql; p0 < npieces; p0 += 4 * kPIF) {
-        uint32_t w[kPIF][4];
+        uint4 w[kPIF];
         int32_t v[kPIF][4];
-        int32_t base[kPIF];
+        int32_t aoff[kPIF];
+        uint64_t sw[kPIF];
 #pragma unroll
         for (int q = 0; q < kPIF; ++q) {
           const int32_t p = p0 + 4 * q;
-          base[q] = -1;
-          if (p < npieces) {
-            const int m = (p >= pref[1]) + (p >= pref[2]) + (p >= pref[3]);
-            const int64_t s0 = m == 0 ? st[0] : m == 1 ? st[1] : m == 2 ? st[2] : st[3];
-            const int32_t pr = m == 0 ? pref[0] : m == 1 ? pref[1] : m == 2 ? pref[2] : pref[3];
-            base[q] = m == 0 ? sb[0] : m == 1 ? sb[1] : m == 2 ? sb[2] : sb[3];
-            const int64_t addr = s0 + 4 * (int64_t)(p - pr);
-            *(uint4*)&w[q][0] = *(const uint4*)(a.syn + addr);
-            if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(a.wfx + addr);
+          const bool valid = p < npieces;
+          const bool m1 = p >= pref[1], m2 = p >= pref[2], m3 = p >= pref[3];
+          const uint32_t b = m3 ? bias[3] : m2 ? bias[2] : m1 ? bias[1] : bias[0];
+          aoff[q] = m3 ? sbq[3] : m2 ? sbq[2] : m1 ? sbq[1] : sbq[0];
+          sw[q] = m3 ? slq[3] : m2 ? slq[2] : m1 ? slq[1] : slq[0];
+          w[q] = make_uint4(kDummyRecord, kDummyRecord, kDummyRecord, kDummyRecord);
+          if (valid) {
+            const uint64_t piece = (uint64_t)(b + (uint32_t)p);
+            w[q] = *(const uint4*)(a.syn + 4 * piece);
+            if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(a.wfx + 4 * piece);
           }
         }
+        // tile slot of each record from its pair's slot word (rank r in bits 5r..5r+4; the
+        // bits above the ninth rank are set, so dummies and absent ranks read 31)
 #pragma unroll
         for (int q = 0; q < kPIF; ++q) {
-          if (base[q] >= 0) {
+          const uint32_t x[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const uint32_t x = w[q][e];
-              const int32_t sbase = s_base[(base[q] & 0xffff) + (int)rec_rank(x)];
-              if (sbase >= 0) {
-                atomicAdd(&acc[(base[q] >> 16) * TN + sbase + (int)rec_k(x)],
-                          TRAIN ? v[q][e] : rec_w32(x));
-                delivered += 1;
-              }
+          for (int e = 0; e < 4; ++e) {
+            const uint32_t rk = rec_rank(x[e]);
+            const uint32_t sl = (uint32_t)(sw[q] >> min(5u * rk, 59u)) & 31u;
+            if (sl != (uint32_t)kNoSlot) {
+              atomicAdd(&acc[aoff[q] + (int)__umul24(sl, (uint32_t)npc) + (int)rec_k(x[e])],
+                        TRAIN ? v[q][e] : rec_w32(x[e]));
+              delivered += 1u;
             }
           }
         }
@@ -339,10 +352,12 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     }
     __syncthreads();
     // the accumulators of the later steps of the window, for their light steps
-    for (int e = tid; e < (W - 1) * TN; e += BLOCK) {
-      const int w = 1 + e / TN, rem = e - (w - 1) * TN;
-      const int col = rem / npc, k = rem - col * npc;
-      a.acc_save[((u + w) % K) * nall + (int64_t)s_col[col] * npc + k] = acc[w * TN + rem];
+    for (int w = 1; w < W; ++w) {
+      int32_t* dst = a.acc_save + ((u + w) % K) * nall;
+      for (int c = wave; c < T * nch; c += NW) {
+        const int col = c / nch, k = (c - col * nch) * 64 + lane;
+        if (k < npc) dst[(int64_t)s_col[col] * npc + k] = acc[w * TN + col * npc + k];
+      }
     }
     // 3. update in 64-neuron chunks: chunk c is column c / nch, neurons (c % nch) * 64 + lane
     const int nchunks = T * nch;
@@ -428,23 +443,37 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     }
     __threadfence_block();
     __syncthreads();
-    // 5. history entries of the step's spikes: for every column, part and field (start,
-    // group offsets) one row over the spike positions, written contiguously
-    for (int col = 0; col < T; ++col) {
-      const int32_t cnt = s_tot[col];
-      if (cnt == 0) continue;
-      const int32_t g = s_col[col];
-      const int32_t fields = a.nd + 2;
-      const int32_t rows = a.col_np[g] * fields;
-      const uint16_t* ids = a.hist_ids + ((int64_t)slot_u * a.n_cols + g) * npc;
-      for (int32_t e = tid; e < rows * cnt; e += BLOCK) {
-        const int32_t row = e / cnt, pos = e - row * cnt;
-        const int p = row / fields, f = row - p * fields;
-        const uint8_t* ent = idx_entry(a, g, ids[pos], p);
-        const int64_t pid = (int64_t)slot_u * a.n_parts + a.col_pfirst[g] + p;
-        if (f == 0) a.hist_st[pid * npc + pos] = ent_start(ent);
-        else a.hist_go[(pid * (a.nd + 1) + (f - 1)) * npc + pos] = ent_goff(ent)[f - 1];
+    // 5. history entries of the step's spikes: one lane per (column, part, spike) copies the
+    // part's row-index entry (loaded once) into the rows of the history, consecutive lanes
+    // writing consecutive spike positions of each row
+    if (tid == 0) {
+      int32_t run = 0;
+      for (int col = 0; col < T; ++col) {
+        s_epre[col] = run;
+        run += a.col_np[s_col[col]] * s_tot[col];
       }
+      s_epre[T] = run;
+    }
+    __syncthreads();
+    for (int32_t e = tid; e < s_epre[T]; e += BLOCK) {
+      int col = 0;
+      while (col + 1 < T && s_epre[col + 1] <= e) ++col;
+      const int32_t g = s_col[col], cnt = s_tot[col];
+      const int32_t r = e - s_epre[col];
+      const int p = r / cnt, pos = r - p * cnt;
+      const int32_t k = a.hist_ids[((int64_t)slot_u * a.n_cols + g) * npc + pos];
+      const uint4* ent = (const uint4*)idx_entry(a, g, k, p);
+      uint4 buf[kIdxWords];
+#pragma unroll
+      for (int q = 0; q < kIdxWords; ++q)
+        if (q * 16 < a.idxw) buf[q] = ent[q];
+      const int64_t pid = (int64_t)slot_u * a.n_parts + a.col_pfirst[g] + p;
+      a.hist_st[pid * npc + pos] = *(const int64_t*)&buf[0];
+      const uint16_t* go = (const uint16_t*)&buf[0] + 4;
+      uint16_t* out = a.hist_go + pid * (int64_t)(a.nd + 1) * npc + pos;
+#pragma unroll
+      for (int f = 0; f <= kMaxDelay; ++f)
+        if (f <= a.nd) out[(int64_t)f * npc] = go[f];
     }
     const unsigned long long spk_all = block_sum_u64<BLOCK>(my_spk, red);
     const unsigned long long ext_all = block_sum_u64<BLOCK>(my_ext, red);
@@ -628,7 +657,7 @@ static size_t tile_fixed_lds(const sim& s) {
 
 static size_t tile_static_bytes() {
   return sizeof(uint64_t) * kPoissonEntries + sizeof(int32_t) * (kMaxItems + 1) +
-         sizeof(int32_t) * 18 * kMaxTilePairs + sizeof(int32_t) * 2 * kMaxTileCols +
+         (sizeof(int32_t) * 2 + sizeof(uint64_t)) * kMaxTilePairs + sizeof(int32_t) * 3 * kMaxTileCols +
          (sizeof(int32_t) * 2 + 1 + sizeof(uint64_t)) * 16 + 64;
 }
 

@@ -40,6 +40,10 @@ def grid(rows: int, cols: int, seed: int = 0, **overrides) -> dict:
 PLAIN_2X2 = dict(params=grid(2, 2, 0), steps=1000, name="plain 2x2 (4,960 neurons), 1 s")
 PLAIN_24X24 = dict(params=grid(24, 24, 0), steps=10000, name="plain 24x24 (714,240 neurons), 10 s")
 PLAIN_96X96 = dict(params=grid(96, 96, 0), steps=2000, name="plain 96x96 (11,427,840 neurons), 2 s")
+#: The same grid with inhibitory weights -N(1.2, 0.12) mV, which brings the mean rate from the
+#: tens of Hz of the literal parameters down to a few Hz.
+PLAIN_96X96_RATE_MATCHED = dict(params=grid(96, 96, 0, wi_mu=-1.2, wi_sigma=0.12), steps=2000,
+                                name="plain 96x96, inhibitory weights -N(1.2, 0.12) mV, 2 s")
 FWD_BWD_4X4 = dict(params=grid(4, 4, 0), steps=500, ckpt_every=50,
                    name="forward+backward 4x4 (19,840 neurons), 500 ms")
 
