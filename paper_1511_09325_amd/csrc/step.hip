@@ -191,7 +191,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   __shared__ int32_t s_tot[kMaxTileCols];       // spikes of each column at this step
   __shared__ int32_t s_epre[kMaxTileCols + 1];  // prefix of (parts x spikes) over columns
   __shared__ int32_t wsum[2 * NW + 1];
-  __shared__ unsigned long long red[NW];
+  __shared__ unsigned long long red5[5][NW];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int npc = a.npc;
@@ -417,29 +417,36 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       }
     }
     __syncthreads();
-    // 4. compaction: ascending ids of each column into the history slot of step u
+    // 4. compaction: ascending ids of each column into the history slot of step u.  One
+    // wave per column turns the per-chunk spike counts into exclusive offsets (nch <= 64).
     const int32_t slot_u = (int32_t)(u % a.dh);
     const unsigned long long lt = lanemask_lt(lane);
+    for (int col = wave; col < T; col += NW) {
+      const int32_t x = lane < nch ? scnt[col * nch + lane] : 0;
+      int32_t incl = x;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+      }
+      if (lane < nch) scnt[col * nch + lane] = incl - x;
+      if (lane == 63) s_tot[col] = incl;
+    }
+    __syncthreads();
     for (int c = wave; c < nchunks; c += NW) {
       const int col = c / nch, first = col * nch;
-      int32_t before = 0;
-      for (int q = first; q < c; ++q) before += scnt[q];
       const unsigned long long m = smask[c];
       if ((m >> lane) & 1ull) {
         uint16_t* out = a.hist_ids + ((int64_t)slot_u * a.n_cols + s_col[col]) * npc;
-        const int32_t pos = before + __popcll(m & lt);
-        const int32_t k = (c - first) * 64 + lane;
-        out[pos] = (uint16_t)k;
+        out[scnt[c] + __popcll(m & lt)] = (uint16_t)((c - first) * 64 + lane);
       }
     }
     unsigned long long my_spk = 0;
     if (tid < T) {
-      int32_t tot = 0;
-      for (int q = 0; q < nch; ++q) tot += scnt[tid * nch + q];
+      const int32_t tot = s_tot[tid];
       a.hist_cnt[(int64_t)slot_u * a.n_cols + s_col[tid]] = tot;
       if (tot) a.col_spk[s_col[tid]] += (unsigned long long)tot;
       my_spk = (unsigned long long)tot;
-      s_tot[tid] = tot;
     }
     __threadfence_block();
     __syncthreads();
@@ -475,17 +482,19 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       for (int f = 0; f <= kMaxDelay; ++f)
         if (f <= a.nd) out[(int64_t)f * npc] = go[f];
     }
-    const unsigned long long spk_all = block_sum_u64<BLOCK>(my_spk, red);
-    const unsigned long long ext_all = block_sum_u64<BLOCK>(my_ext, red);
-    const unsigned long long rec_all = block_sum_u64<BLOCK>(my_rec, red);
-    const unsigned long long str_all = block_sum_u64<BLOCK>(streamed, red);
-    const unsigned long long del_all = block_sum_u64<BLOCK>((unsigned long long)delivered, red);
-    if (tid == 0) {
-      atomicAdd(&a.net_cnt[kCounters * net + 0], spk_all);
-      atomicAdd(&a.net_cnt[kCounters * net + 1], rec_all);
-      atomicAdd(&a.net_cnt[kCounters * net + 2], ext_all);
-      if (str_all) atomicAdd(&a.net_cnt[kCounters * net + 3], str_all);
-      if (del_all) atomicAdd(&a.net_cnt[kCounters * net + 4], del_all);
+    // the tile's counters: wave sums, then one sum per counter
+    unsigned long long cv[5] = {my_spk, my_rec, my_ext, streamed, (unsigned long long)delivered};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) cv[q] += __shfl_down(cv[q], off);
+      if (lane == 0) red5[q][wave] = cv[q];
+    }
+    __syncthreads();
+    if (tid < 5) {
+      unsigned long long all = 0;
+      for (int w = 0; w < NW; ++w) all += red5[tid][w];
+      if (all) atomicAdd(&a.net_cnt[kCounters * net + tid], all);
     }
     __syncthreads();
   }
@@ -658,7 +667,7 @@ static size_t tile_fixed_lds(const sim& s) {
 static size_t tile_static_bytes() {
   return sizeof(uint64_t) * kPoissonEntries + sizeof(int32_t) * (kMaxItems + 1) +
          (sizeof(int32_t) * 2 + sizeof(uint64_t)) * kMaxTilePairs + sizeof(int32_t) * 3 * kMaxTileCols +
-         (sizeof(int32_t) * 2 + 1 + sizeof(uint64_t)) * 16 + 64;
+         (sizeof(int32_t) * 2 + 1 + 5 * sizeof(uint64_t)) * 16 + 64;
 }
 
 bool tile_lds_ok(const sim& s) { return tile_fixed_lds(s) + tile_static_bytes() <= kMaxLds; }
