@@ -337,8 +337,8 @@ void build_tiles(sim& s, int tx, int ty) {
 }
 
 // Native tiling: the configured one, else the first of the shapes below whose accumulators
-// fit the LDS.  4x3 comes first: with 1240-neuron columns it leaves room for two gather
-// accumulators, and 96x96 gives 768 tiles, three full waves of 256 workgroups.
+// fit the LDS.  3x3 comes first: with 1240-neuron columns it leaves room for three gather
+// accumulators, and 96x96 gives 1024 tiles, four full waves of 256 workgroups.
 void choose_native(sim& s, int tx, int ty) {
   if (tx || ty) {
     if (!tile_fits(s, tx, ty)) throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4] and fit the LDS"};
@@ -346,7 +346,7 @@ void choose_native(sim& s, int tx, int ty) {
     s.native_ty = ty;
     return;
   }
-  static const int shapes[][2] = {{4, 3}, {4, 4}, {3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
+  static const int shapes[][2] = {{3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
   for (const auto& sh : shapes) {
     if (tile_fits(s, sh[0], sh[1])) {
       s.native_tx = sh[0];
