@@ -24,6 +24,7 @@ struct AdjArgs {
   const float* wf32;
   float* gw;
   float* nu_ring;     // [dh][N]
+  const uint8_t* dly; // [S'] delay index of each record
   float* gsum;        // [N]
   float* lam;         // [N]
   float* mu;          // [N]
@@ -33,31 +34,57 @@ struct AdjArgs {
   float beta;
 };
 
+constexpr int kAdjUnroll = 8;  // records per lane in flight
+
+// One wave per neuron.  The whole row (all parts, contiguous in the store) is streamed 64 x
+// kAdjUnroll records at a time with each record's delay index from the train-mode delay
+// array, which selects the slot of the adjoint ring.
 __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
   const StepArgs& a = x.a;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t nall = (int64_t)a.n_cols * a.npc;
-  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t j = (int64_t)blockIdx.x * 4 + wv;
   if (j >= nall) return;
   const int32_t g = (int32_t)(j / a.npc);
-  const int32_t kk = (int32_t)(j - (int64_t)g * a.npc);
   const bool spiked = (a.rec_flags[(u - a.rec_base) * nall + j] & 1) != 0;
+  const int64_t rb = a.row_base[j];
+  const int32_t rlen = (int32_t)(a.row_base[j + 1] - rb);
+  const int32_t ubase = (int32_t)((u + a.d_min) % a.dh);  // ring slot of delay index 0
   float acc = 0.0f;
-  for (int p = 0; p < a.col_np[g]; ++p) {
-    const uint8_t* ent = idx_entry(a, g, kk, p);
-    const int64_t st = ent_start(ent);
-    const uint16_t* go = ent_goff(ent);
-    for (int dd = 0; dd < a.nd; ++dd) {
-      const float* nus = x.nu_ring + ((u + a.d_min + dd) % a.dh) * nall;
-      for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
-        const uint32_t w = a.syn[st + f];
-        if (rec_rank(w) == (uint32_t)kDummyRank) continue;
-        const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
-        const float nu = nus[(int64_t)tc * a.npc + rec_k(w)];
-        const float prod = x.wf32[st + f] * nu;
-        acc = acc + prod;
-        if (spiked) x.gw[st + f] = x.gw[st + f] + nu;
+  for (int32_t f0 = 0; f0 < rlen; f0 += 64 * kAdjUnroll) {
+    uint32_t w[kAdjUnroll];
+    float wf[kAdjUnroll];
+    int32_t dd[kAdjUnroll];
+#pragma unroll
+    for (int i = 0; i < kAdjUnroll; ++i) {
+      const int32_t f = f0 + lane + 64 * i;
+      w[i] = kDummyRecord;
+      wf[i] = 0.0f;
+      dd[i] = 0;
+      if (f < rlen) {
+        w[i] = a.syn[rb + f];
+        wf[i] = x.wf32[rb + f];
+        dd[i] = x.dly[rb + f];
       }
+    }
+    float nu[kAdjUnroll];
+#pragma unroll
+    for (int i = 0; i < kAdjUnroll; ++i) {
+      nu[i] = 0.0f;
+      if (rec_rank(w[i]) != (uint32_t)kDummyRank) {
+        const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w[i])];
+        int32_t slot = ubase + dd[i];
+        if (slot >= a.dh) slot -= a.dh;
+        nu[i] = x.nu_ring[slot * nall + (int64_t)tc * a.npc + rec_k(w[i])];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kAdjUnroll; ++i) {
+      const int32_t f = f0 + lane + 64 * i;
+      if (rec_rank(w[i]) == (uint32_t)kDummyRank) continue;
+      const float prod = wf[i] * nu[i];
+      acc = acc + prod;
+      if (spiked) x.gw[rb + f] = x.gw[rb + f] + nu[i];
     }
   }
 #pragma unroll
@@ -65,9 +92,28 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
   if (lane == 0) x.gsum[j] = acc;
 }
 
+// Delay index of every record (train mode): one wave per neuron over its parts and groups.
+__global__ __launch_bounds__(256) void k_fill_dly(StepArgs a, uint8_t* dly) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nall = (int64_t)a.n_cols * a.npc;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nall;
+       i += (int64_t)gridDim.x * 4) {
+    const int32_t g = (int32_t)(i / a.npc);
+    const int32_t kk = (int32_t)(i - (int64_t)g * a.npc);
+    for (int p = 0; p < a.col_np[g]; ++p) {
+      const uint8_t* ent = idx_entry(a, g, kk, p);
+      const int64_t st = ent_start(ent);
+      const uint16_t* go = ent_goff(ent);
+      for (int d = 0; d < a.nd; ++d)
+        for (int32_t f = go[d] + lane; f < go[d + 1]; f += 64) dly[st + f] = (uint8_t)d;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_adj_neuron(AdjArgs x, int64_t u) {
   const StepArgs& a = x.a;
   const int64_t nall = (int64_t)a.n_cols * a.npc;
+  const int64_t uslot = u % a.dh;
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < nall;
        j += (int64_t)gridDim.x * 256) {
     const int64_t o = (u - a.rec_base) * nall + j;
@@ -84,7 +130,7 @@ __global__ __launch_bounds__(256) void k_adj_neuron(AdjArgs x, int64_t u) {
       const float sig = 1.0f / (den * den);
       nu = lam * (1.0f - s) + e * sig;
     }
-    x.nu_ring[(u % a.dh) * nall + j] = nu;
+    x.nu_ring[uslot * nall + j] = nu;
     x.part[j] += (double)a.rec_vprev[o] * (double)nu;
     x.part[nall + j] -= (double)a.rec_caprev[o] * (double)nu;
     x.lam[j] = a.k.pm * nu;
@@ -214,6 +260,7 @@ hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates,
   x.wf32 = s.wf32;
   x.gw = s.gw;
   x.nu_ring = s.nu_ring;
+  x.dly = s.dly8;
   x.gsum = s.adj_gsum;
   x.lam = s.adj_lam;
   x.mu = s.adj_mu;
@@ -237,6 +284,12 @@ hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst
   const StepArgs a = make_step_args(s);
   hipLaunchKernelGGL(k_canon_map, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a,
                      s.canon_start, mode, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_dly(const sim& s) {
+  const StepArgs a = make_step_args(s);
+  hipLaunchKernelGGL(k_fill_dly, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a, s.dly8);
   return hipGetLastError();
 }
 

@@ -336,9 +336,20 @@ void build_tiles(sim& s, int tx, int ty) {
   s.tile_slots = upload(s, tslots);
 }
 
+int64_t tile_count(const sim& s, int tx, int ty) {
+  int64_t n = 0;
+  for (const sim_net_t& t : s.nets) {
+    const int ttx = std::min(tx, t.cols), tty = std::min(ty, t.rows);
+    n += (int64_t)((t.cols + ttx - 1) / ttx) * ((t.rows + tty - 1) / tty);
+  }
+  return n;
+}
+
 // Native tiling: the configured one, else the first of the shapes below whose accumulators
-// fit the LDS.  3x3 comes first: with 1240-neuron columns it leaves room for three gather
-// accumulators, and 96x96 gives 1024 tiles, four full waves of 256 workgroups.
+// fit the LDS and that gives at least one tile per compute unit (else the smallest that
+// fits: small networks need every workgroup they can get).  3x3 comes first: with
+// 1240-neuron columns it leaves room for three gather accumulators, and 96x96 gives 1024
+// tiles, four full waves of 256 workgroups.
 void choose_native(sim& s, int tx, int ty) {
   if (tx || ty) {
     if (!tile_fits(s, tx, ty)) throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4] and fit the LDS"};
@@ -346,15 +357,21 @@ void choose_native(sim& s, int tx, int ty) {
     s.native_ty = ty;
     return;
   }
+  int dev = 0, n_cu = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+      prop.multiProcessorCount > 0)
+    n_cu = prop.multiProcessorCount;
   static const int shapes[][2] = {{3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
-  for (const auto& sh : shapes) {
-    if (tile_fits(s, sh[0], sh[1])) {
-      s.native_tx = sh[0];
-      s.native_ty = sh[1];
-      return;
-    }
+  int last = -1;
+  for (int q = 0; q < 5; ++q) {
+    if (!tile_fits(s, shapes[q][0], shapes[q][1])) continue;
+    last = q;
+    if (tile_count(s, shapes[q][0], shapes[q][1]) >= n_cu) break;
   }
-  throw Fail{DPSNN_EINVAL, "no tile shape fits the LDS"};
+  if (last < 0) throw Fail{DPSNN_EINVAL, "no tile shape fits the LDS"};
+  s.native_tx = shapes[last][0];
+  s.native_ty = shapes[last][1];
 }
 
 // Arrival form: the saved accumulators are derived from the spike history; anything that
@@ -560,6 +577,9 @@ void setup_train(sim& s) {
   s.wf32 = (float*)dalloc(s, sizeof(float) * sp);
   s.wfx = (int32_t*)dalloc(s, sizeof(int32_t) * sp);
   s.gw = (float*)dalloc(s, sizeof(float) * sp);
+  s.dly8 = (uint8_t*)dalloc(s, sp);
+  HIPCHK(hipMemsetAsync(s.dly8, 0, sp, s.stream));
+  HIPCHK(launch_fill_dly(s));
   HIPCHK(hipMemsetAsync(s.wf32, 0, sizeof(float) * sp, s.stream));
   HIPCHK(hipMemsetAsync(s.wfx, 0, sizeof(int32_t) * sp, s.stream));
   HIPCHK(launch_weights_from_records(s));

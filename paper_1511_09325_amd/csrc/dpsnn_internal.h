@@ -290,6 +290,7 @@ struct sim {
   int64_t rec_base = 0;
   bool rec_on = false;
   float* gw = nullptr;             // weight gradient, padded layout
+  uint8_t* dly8 = nullptr;         // delay index of each record, padded layout
   float* nu_ring = nullptr;        // [dh][N] adjoint of V~ of the last dh steps
   float *adj_gsum = nullptr, *adj_lam = nullptr, *adj_mu = nullptr;
   double* adj_part = nullptr;      // [2][N]
@@ -348,6 +349,7 @@ hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst
 hipError_t launch_weights_from_records(const sim& s);
 hipError_t launch_column_rates(const sim& s, float scale, float* rates);
 hipError_t launch_fill_entries(const sim& s);
+hipError_t launch_fill_dly(const sim& s);
 int64_t scan_scratch_len(int64_t n);
 
 StepArgs make_step_args(const sim& s);

@@ -216,6 +216,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   const int32_t jnew = light ? (int32_t)(u - g_last) : 0;
   const int32_t NB = a.dh - 1;  // spike ages b = u - t in [1, d_max]
   const int64_t nall = (int64_t)a.n_cols * npc;
+  const int32_t u_slot = (int32_t)(u % a.dh);
+  const int64_t light_save = light ? (u % K) * nall : 0;  // this step's saved accumulator
   for (int32_t b = blockIdx.x; b < a.grid_tiles; b += gridDim.x) {
     const int32_t tile = a.tile_order[b];
     if (tile < 0) continue;
@@ -245,7 +247,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
         const int64_t t = u - ag;
         int32_t dlo;
         const int32_t ndel = item_delays(a, light, jnew, W, ag, &dlo);
-        if (t >= 0 && ndel > 0) cnt = ndel * a.hist_cnt[(int64_t)(t % a.dh) * a.n_cols + s_src[si]];
+        int32_t slot = u_slot - ag;
+        if (slot < 0) slot += a.dh;
+        if (t >= 0 && ndel > 0) cnt = ndel * a.hist_cnt[(int64_t)slot * a.n_cols + s_src[si]];
       }
       int32_t tot;
       const int32_t ex = block_excl_scan<BLOCK>(cnt, &tot, wsum);
@@ -264,7 +268,6 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     const int quad0 = lane & ~3, ql = lane & 3;
     // exact small-integer quotients through float reciprocals (operands < 2^16)
     const float inv_nb = 1.0f / (float)NB;
-    const int32_t u_slot = (int32_t)(u % a.dh);
     for (int32_t bt = wave; bt * 64 < total; bt += NW) {
       const int32_t qq = bt * 64 + lane;
       // this lane's group: first 16-byte piece, length in pieces, the offset of the
@@ -403,7 +406,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
             const int col = c / nch, k = (c - col * nch) * 64 + lane;
             const int64_t j = (int64_t)s_col[col] * npc + k;
             int32_t in = acc[col * npc + k];
-            if (light) in = (int32_t)((uint32_t)in + (uint32_t)a.acc_save[(u % K) * nall + j]);
+            if (light) in = (int32_t)((uint32_t)in + (uint32_t)a.acc_save[light_save + j]);
             sp = neuron_step(a, j, u, in, nx[m], vv[m], cc[m], rr[m]);
             my_ext += (unsigned long long)nx[m];
             if (sp) my_rec += (unsigned long long)a.deg[j];
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     __syncthreads();
     // 4. compaction: ascending ids of each column into the history slot of step u.  One
     // wave per column turns the per-chunk spike counts into exclusive offsets (nch <= 64).
-    const int32_t slot_u = (int32_t)(u % a.dh);
+    const int32_t slot_u = u_slot;
     const unsigned long long lt = lanemask_lt(lane);
     for (int col = wave; col < T; col += NW) {
       const int32_t x = lane < nch ? scnt[col * nch + lane] : 0;
@@ -595,7 +598,8 @@ __global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u_ar
         const int64_t st = ent_start(ent);
         const uint16_t* go = ent_goff(ent);
         for (int dd = 0; dd < a.nd; ++dd) {
-          const int64_t slot = (u + a.d_min + dd) % a.dh;
+          int64_t slot = uslot + a.d_min + dd;
+          if (slot >= a.dh) slot -= a.dh;
           for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
             const uint32_t w = a.syn[st + f];
             if (rec_rank(w) == (uint32_t)kDummyRank) continue;
