@@ -89,7 +89,8 @@ int orc_adjoint(const orc_adj_params_t* k, int64_t n, int64_t T, const int64_t* 
 
 /* Soft model forward in FP64: same step with the spike S(V~ - theta), soft reset and soft
  * delivery, no refractory period.  External input: the same Poisson counts as the hard
- * model (Philox at counter (j, u, 0, EXT)), times J_ext.  Outputs are [T][n]. */
+ * model (word j mod 4 of Philox at counter (j / 4, u, 0, EXT)), times J_ext.  Outputs are
+ * [T][n]. */
 int orc_soft_forward(const orc_config_t* cfg, const orc_adj_params_t* k, int64_t n, int64_t T,
                      const int64_t* row_ptr, const int32_t* tgt, const uint8_t* dly,
                      const double* w, double* v_prev, double* ca_prev, double* v_tilde,

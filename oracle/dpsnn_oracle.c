@@ -181,14 +181,18 @@ int32_t orc_poisson_count(const uint64_t tab[63], uint32_t x) {
   return n;
 }
 
+/* The 32-bit uniform of neuron j at step u: one Philox block serves four consecutive
+ * neurons, neuron j taking word j mod 4 of the block at counter (j / 4, u, 0, EXT). */
+static uint32_t ext_uniform(const orc_config_t* cfg, int64_t j, int64_t u) {
+  uint32_t r[4];
+  draw(cfg, (uint32_t)(j >> 2), (uint32_t)u, 0u, ORC_STREAM_EXT, r);
+  return r[j & 3];
+}
+
 void orc_ext_counts(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n, int32_t* out) {
   uint64_t tab[63];
   orc_poisson_table((double)cfg->ext_syn * cfg->ext_rate_hz * cfg->dt * 1e-3, tab);
-  for (int64_t q = 0; q < n; ++q) {
-    uint32_t r[4];
-    draw(cfg, (uint32_t)(j0 + q), (uint32_t)u, 0u, ORC_STREAM_EXT, r);
-    out[q] = orc_poisson_count(tab, r[0]);
-  }
+  for (int64_t q = 0; q < n; ++q) out[q] = orc_poisson_count(tab, ext_uniform(cfg, j0 + q, u));
 }
 
 /* Initial potential uniform on [0, v_reset): 24 random bits scaled exactly, times v_reset. */
@@ -414,9 +418,7 @@ int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
     int64_t first = s->sp_n;
     if (s->rec_on) grow_record(s);
     for (int64_t j = 0; j < s->n; ++j) {
-      uint32_t r[4];
-      draw(&s->cfg, (uint32_t)j, (uint32_t)u, 0u, ORC_STREAM_EXT, r);
-      int32_t next = orc_poisson_count(s->ptab, r[0]);
+      int32_t next = orc_poisson_count(s->ptab, ext_uniform(&s->cfg, j, u));
       float vprev = s->v[j], caprev = s->ca[j], vt;
       int refr;
       uint32_t a;

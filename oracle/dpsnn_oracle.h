@@ -36,7 +36,7 @@ extern "C" {
 
 enum {
   ORC_STREAM_SYN = 1,  /* counter (j, i, sub, 1): pair i->j connection, delay, weight */
-  ORC_STREAM_EXT = 2,  /* counter (j, u, 0, 2):   external Poisson count of neuron j at step u */
+  ORC_STREAM_EXT = 2,  /* counter (j/4, u, 0, 2), word j%4: external Poisson count of neuron j at step u */
   ORC_STREAM_INIT = 3  /* counter (j, 0, 0, 3):   initial membrane potential of neuron j */
 };
 

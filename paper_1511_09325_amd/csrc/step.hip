@@ -3,7 +3,8 @@
 // The paper's simulator is mixed time- and event-driven (section 1): every neuron is
 // integrated every step, and synaptic work is proportional to the spikes.  One step u:
 //   input    A_j = (recurrent input due at step u) + n_j(u) * J_ext   (int32, 2^-16 mV)
-//            n_j(u) ~ Poisson(ext_syn * rate * dt) from Philox at counter (j, u, 0, EXT),
+//            n_j(u) ~ Poisson(ext_syn * rate * dt) from word j mod 4 of Philox at counter
+//            (j / 4, u, 0, EXT), j the network-local index,
 //            inverse CDF against 63 integer thresholds
 //   neuron   refractory: count down, V = V_reset, input discarded;
 //            else V~ = ((P_m V) - (gamma Ca)) + A 2^-16, spike if V~ >= theta, then
@@ -31,7 +32,6 @@ namespace {
 constexpr int kMaxItems = kMaxTilePairs * kMaxDelay;
 constexpr int kPIF = 4;               // 16-byte synapse loads per lane in flight
 constexpr int kIdxWords = (8 + 2 * (kMaxDelay + 1) + 15) / 16;  // 16-byte words of an entry
-constexpr int kUpd = 2;               // 64-neuron chunks per wave per round of the update
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -137,12 +137,18 @@ __device__ __forceinline__ bool neuron_step(const StepArgs& a, int64_t j, int64_
   return spike;
 }
 
+// The external count of neuron k of column g: one Philox block serves four consecutive
+// network-local neurons jl, each taking word jl mod 4 of the block at counter (jl / 4, u).
+__device__ __forceinline__ uint32_t block_word(const Rand4& x, uint32_t w) {
+  return w == 0 ? x.x : w == 1 ? x.y : w == 2 ? x.z : x.w;
+}
+
 __device__ __forceinline__ int32_t external_count(const StepArgs& a, int32_t g, int k, int64_t u,
                                                   const uint64_t* ptab, uint32_t key0,
                                                   uint32_t key1) {
-  const Rand4 x = philox10((uint32_t)(a.col_local[g] * a.npc + k), (uint32_t)u, 0u, kStreamExt,
-                           key0, key1);
-  return poisson_count(ptab, x.x);
+  const uint32_t jl = (uint32_t)(a.col_local[g] * a.npc + k);
+  const Rand4 x = philox10(jl >> 2, (uint32_t)u, 0u, kStreamExt, key0, key1);
+  return poisson_count(ptab, block_word(x, jl & 3u));
 }
 
 // Delays read for spikes of age b (emitted at u - b): at a light step only the spikes
@@ -362,49 +368,59 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
         if (k < npc) dst[(int64_t)s_col[col] * npc + k] = acc[w * TN + col * npc + k];
       }
     }
-    // 3. update in 64-neuron chunks: chunk c is column c / nch, neurons (c % nch) * 64 + lane
+    // 3. update, in rounds of four 64-neuron chunks of one column: chunk c is column c / nch,
+    // neurons (c % nch) * 64 + lane.  When the column size is a multiple of 4, the 256
+    // neurons of a round draw their external counts from 64 Philox blocks, one per lane,
+    // handed to the neurons by lane shuffles; otherwise each lane draws its own block.
     const int nchunks = T * nch;
+    const int nr = (nch + 3) >> 2;
+    const bool shared_draw = (npc & 3) == 0;
     const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
     unsigned long long my_ext = 0, my_rec = 0;
-    for (int c0 = wave * kUpd; c0 < nchunks; c0 += NW * kUpd) {
-      float vv[kUpd], cc[kUpd];
-      int32_t rr[kUpd], nx[kUpd];
-      bool ok[kUpd];
+    for (int rd = wave; rd < T * nr; rd += NW) {
+      const int col = rd / nr, q0 = (rd - col * nr) * 4;
+      const int32_t g = s_col[col];
+      float vv[4], cc[4];
+      int32_t rr[4], nx[4];
+      bool ok[4];
 #pragma unroll
-      for (int m = 0; m < kUpd; ++m) {
-        const int c = c0 + m;
-        ok[m] = false;
+      for (int m = 0; m < 4; ++m) {
+        const int k = (q0 + m) * 64 + lane;
+        ok[m] = q0 + m < nch && k < npc;
         vv[m] = 0.0f;
         cc[m] = 0.0f;
         rr[m] = 0;
-        if (c < nchunks) {
-          const int col = c / nch, k = (c - col * nch) * 64 + lane;
-          if (k < npc) {
-            ok[m] = true;
-            const int64_t j = (int64_t)s_col[col] * npc + k;
-            vv[m] = a.v[j];
-            cc[m] = a.ca[j];
-            rr[m] = a.ref[j];
-          }
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < kUpd; ++m) {
-        const int c = c0 + m;
-        nx[m] = 0;
         if (ok[m]) {
-          const int col = c / nch, k = (c - col * nch) * 64 + lane;
-          nx[m] = external_count(a, s_col[col], k, u, ptab, key0, key1);
+          const int64_t j = (int64_t)g * npc + k;
+          vv[m] = a.v[j];
+          cc[m] = a.ca[j];
+          rr[m] = a.ref[j];
+        }
+      }
+      Rand4 blk{0u, 0u, 0u, 0u};
+      if (shared_draw)
+        blk = philox10(((uint32_t)(a.col_local[g] * npc + q0 * 64) >> 2) + (uint32_t)lane,
+                       (uint32_t)u, 0u, kStreamExt, key0, key1);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        nx[m] = 0;
+        if (shared_draw) {
+          const int src = 16 * m + (lane >> 2);
+          const Rand4 b{(uint32_t)__shfl((int32_t)blk.x, src), (uint32_t)__shfl((int32_t)blk.y, src),
+                        (uint32_t)__shfl((int32_t)blk.z, src), (uint32_t)__shfl((int32_t)blk.w, src)};
+          if (ok[m]) nx[m] = poisson_count(ptab, block_word(b, (uint32_t)lane & 3u));
+        } else if (ok[m]) {
+          nx[m] = external_count(a, g, (q0 + m) * 64 + lane, u, ptab, key0, key1);
         }
       }
 #pragma unroll
-      for (int m = 0; m < kUpd; ++m) {
-        const int c = c0 + m;
-        if (c < nchunks) {
+      for (int m = 0; m < 4; ++m) {
+        if (q0 + m < nch) {
+          const int c = col * nch + q0 + m;
           bool sp = false;
           if (ok[m]) {
-            const int col = c / nch, k = (c - col * nch) * 64 + lane;
-            const int64_t j = (int64_t)s_col[col] * npc + k;
+            const int k = (q0 + m) * 64 + lane;
+            const int64_t j = (int64_t)g * npc + k;
             int32_t in = acc[col * npc + k];
             if (light) in = (int32_t)((uint32_t)in + (uint32_t)a.acc_save[light_save + j]);
             sp = neuron_step(a, j, u, in, nx[m], vv[m], cc[m], rr[m]);

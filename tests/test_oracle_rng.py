@@ -115,3 +115,16 @@ def test_external_counts_follow_poisson():
     exp[kmax] = stats.poisson.sf(kmax - 1, lam) * m
     chi2 = ((obs - exp) ** 2 / exp).sum()
     assert stats.chi2.sf(chi2, kmax) > 1e-4
+
+
+def test_external_counts_of_one_block_are_independent():
+    """Four consecutive neurons share a Philox block (one word each): their counts over many
+    steps must be uncorrelated, and neighbours across block boundaries too."""
+    p = dict(__import__("paper_1511_09325_amd.workloads", fromlist=["grid"]).grid(1, 1, 7))
+    T = 4000
+    draws = np.stack([oracle.ext_counts(p, u, 0, 8) for u in range(T)]).astype(np.float64)
+    c = np.corrcoef(draws.T)
+    bound = 4.0 / np.sqrt(T)
+    for i in range(8):
+        for j in range(i + 1, 8):
+            assert abs(c[i, j]) < bound, (i, j, c[i, j])
