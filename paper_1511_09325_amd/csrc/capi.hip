@@ -147,6 +147,16 @@ void set_constants(sim& s) {
   s.nk.tref = c.t_ref;
 }
 
+// Compute units of the current device (256 on an MI355X when the query fails).
+static int device_cu_count() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+      prop.multiProcessorCount > 0)
+    return prop.multiProcessorCount;
+  return 256;
+}
+
 // Round-robin merge of per-XCD work lists (-1 where a list ran out).
 std::vector<int32_t> interleave(const std::vector<std::vector<int32_t>>& lanes) {
   size_t longest = 0;
@@ -322,6 +332,7 @@ void build_tiles(sim& s, int tx, int ty) {
   release(s, s.tile_ppart);
   release(s, s.tile_npairs);
   release(s, s.tile_slots);
+  release(s, s.tile_work);
   const std::vector<int32_t> order = interleave(lanes);
   s.tile_x = tx;
   s.tile_y = ty;
@@ -334,6 +345,9 @@ void build_tiles(sim& s, int tx, int ty) {
   s.tile_ppart = upload(s, ppart);
   s.tile_npairs = upload(s, npairs);
   s.tile_slots = upload(s, tslots);
+  s.tile_work = upload(s, std::vector<uint32_t>((size_t)s.n_tiles, 0u));
+  // when every tile has its own compute unit the order does not matter
+  s.order_by_work = s.n_tiles > device_cu_count();
 }
 
 int64_t tile_count(const sim& s, int tx, int ty) {
@@ -357,11 +371,7 @@ void choose_native(sim& s, int tx, int ty) {
     s.native_ty = ty;
     return;
   }
-  int dev = 0, n_cu = 256;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
-      prop.multiProcessorCount > 0)
-    n_cu = prop.multiProcessorCount;
+  const int n_cu = device_cu_count();
   static const int shapes[][2] = {{3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
   int last = -1;
   for (int q = 0; q < 5; ++q) {

@@ -140,8 +140,11 @@ struct StepArgs {
   const uint32_t* net_key;    // [n_nets][2]
   const uint64_t* net_ptab;   // [n_nets][63]
   // tiles
-  const int32_t* tile_order;  // [grid_tiles]: tile of workgroup b (-1: none)
+  int32_t* tile_order;        // [grid_tiles]: tile of workgroup b (-1: none)
   int32_t grid_tiles;
+  int32_t n_tiles;
+  uint32_t* tile_work;        // [n_tiles]: synapse records read at the last gathering step
+  int32_t order_by_work;      // reorder tiles by work after each gathering step
   const int32_t* tile_cols;
   const int32_t* tile_ncols;
   const int32_t* tile_pcol;
@@ -277,6 +280,8 @@ struct sim {
   int32_t *tile_order = nullptr, *tile_cols = nullptr, *tile_ncols = nullptr,
           *tile_pcol = nullptr, *tile_ppart = nullptr, *tile_npairs = nullptr;
   uint64_t* tile_slots = nullptr;
+  uint32_t* tile_work = nullptr;   // [n_tiles] records read per tile at the last gathering step
+  int32_t order_by_work = 0;       // more tiles than compute units: order them by work
   // raster
   int64_t* ras_off = nullptr;      // [record_steps+1]
   int32_t* ras_ids = nullptr;      // [raster_capacity], global neuron ids

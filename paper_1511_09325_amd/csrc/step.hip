@@ -30,6 +30,7 @@ namespace dpsnn {
 namespace {
 
 constexpr int kMaxItems = kMaxTilePairs * kMaxDelay;
+static_assert(kMaxItems + 1 >= 1024, "the tile order's buckets reuse the item prefix array");
 constexpr int kPIF = 4;               // 16-byte synapse loads per lane in flight
 constexpr int kIdxWords = (8 + 2 * (kMaxDelay + 1) + 15) / 16;  // 16-byte words of an entry
 
@@ -168,6 +169,45 @@ __device__ __forceinline__ int32_t item_delays(const StepArgs& a, bool light, in
   if (hi > d_max) hi = d_max;
   *dlo = lo;
   return hi >= lo ? hi - lo + 1 : 0;
+}
+
+// Workgroup order of the tile kernel: tiles by decreasing synapse records read at the last
+// gathering step.  Workgroups start in index order as compute units free up, so the largest
+// tiles start first and the smallest fill the end (longest-first list scheduling); the spread
+// of work between tiles follows the spatial spread of firing rates.  A counting sort over
+// BLOCK buckets of the work scaled to the largest.  Run by one workgroup, after every other
+// workgroup of the launch has finished; the results do not depend on the order.
+template <int BLOCK>
+__device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
+  constexpr int NW = BLOCK / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t mx = 0;
+  for (int32_t t = tid; t < a.n_tiles; t += BLOCK)
+    mx = max(mx, __hip_atomic_load(&a.tile_work[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int32_t)mx, off));
+  if (lane == 0) wsum[wave] = (int32_t)mx;
+  cnt[tid] = 0;
+  __syncthreads();
+  mx = 0;
+  for (int w = 0; w < NW; ++w) mx = max(mx, (uint32_t)wsum[w]);
+  const uint64_t den = (uint64_t)mx + 1;
+  __syncthreads();
+  for (int32_t t = tid; t < a.n_tiles; t += BLOCK) {
+    const uint32_t w = __hip_atomic_load(&a.tile_work[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicAdd(&cnt[BLOCK - 1 - (int)((uint64_t)w * BLOCK / den)], 1);
+  }
+  __syncthreads();
+  int32_t tot;
+  const int32_t mine = cnt[tid];
+  const int32_t ex = block_excl_scan<BLOCK>(mine, &tot, wsum);
+  cnt[tid] = ex;
+  __syncthreads();
+  for (int32_t t = tid; t < a.n_tiles; t += BLOCK) {
+    const uint32_t w = __hip_atomic_load(&a.tile_work[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a.tile_order[atomicAdd(&cnt[BLOCK - 1 - (int)((uint64_t)w * BLOCK / den)], 1)] = t;
+  }
+  for (int32_t b = a.n_tiles + tid; b < a.grid_tiles; b += BLOCK) a.tile_order[b] = -1;
 }
 
 // ---- ARRIVAL: tiles of target columns ---------------------------------------------------
@@ -514,17 +554,29 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       unsigned long long all = 0;
       for (int w = 0; w < NW; ++w) all += red5[tid][w];
       if (all) atomicAdd(&a.net_cnt[kCounters * net + tid], all);
+      if (tid == 0 && !light) {
+        unsigned long long rd = 0;
+        for (int w = 0; w < NW; ++w) rd += red5[3][w];
+        a.tile_work[tile] = (uint32_t)min(rd, 0xffffffffull);
+      }
     }
     __syncthreads();
   }
-  // the last workgroup to finish records a gathering step (every workgroup has read *gath)
-  if (K > 1 && !light && tid == 0) {
-    __threadfence();
-    if (atomicAdd(a.gdone, 1u) == gridDim.x - 1) {
-      *a.gath = u;
-      *a.gdone = 0u;
+  // The last workgroup to finish a gathering step records it (every workgroup has read
+  // *gath) and orders the tiles by the work just measured for the following steps.
+  if (!light) {
+    __shared__ int32_t s_last;
+    if (tid == 0) {
       __threadfence();
+      s_last = atomicAdd(a.gdone, 1u) == gridDim.x - 1;
+      if (s_last) {
+        if (K > 1) *a.gath = u;
+        *a.gdone = 0u;
+        __threadfence();
+      }
     }
+    __syncthreads();
+    if (s_last && a.order_by_work) order_tiles<BLOCK>(a, it_pref, wsum);
   }
 }
 
@@ -713,6 +765,9 @@ StepArgs make_step_args(const sim& s) {
   a.net_ptab = s.net_ptab;
   a.tile_order = s.tile_order;
   a.grid_tiles = s.grid_tiles;
+  a.n_tiles = s.n_tiles;
+  a.tile_work = s.tile_work;
+  a.order_by_work = s.order_by_work;
   a.tile_cols = s.tile_cols;
   a.tile_ncols = s.tile_ncols;
   a.tile_pcol = s.tile_pcol;
