@@ -98,44 +98,61 @@ __device__ __forceinline__ int32_t poisson_count(const uint64_t* tab, uint32_t x
   return lo;
 }
 
-// One neuron's step from its state and input; returns the spike flag.
-__device__ __forceinline__ bool neuron_step(const StepArgs& a, int64_t j, int64_t u,
-                                            int32_t rec_in, int32_t n_ext, float vprev,
-                                            float caprev, int32_t rf) {
+// One neuron's step from its state and input (no memory access).
+struct NeuronOut {
+  float v, ca, vt;
+  int32_t rf;
+  bool spike, refr;
+};
+
+__device__ __forceinline__ NeuronOut neuron_update(const StepArgs& a, int32_t rec_in, int32_t n_ext,
+                                                  float vprev, float caprev, int32_t rf) {
   const uint32_t asum = (uint32_t)rec_in + (uint32_t)n_ext * (uint32_t)a.k.jfx;
   const float cur = (float)(int32_t)asum * 0x1p-16f;
-  float vnew, vt = 0.0f;
-  bool spike = false, refr = false;
+  NeuronOut o{0.0f, 0.0f, 0.0f, rf, false, false};
   if (rf > 0) {
-    refr = true;
-    rf -= 1;
-    vnew = a.k.vreset;
+    o.refr = true;
+    o.rf = rf - 1;
+    o.v = a.k.vreset;
   } else {
     const float leak = a.k.pm * vprev;
     const float ahp = a.k.gam * caprev;
     const float drop = leak - ahp;
-    vt = drop + cur;
-    if (vt >= a.k.theta) {
-      spike = true;
-      vnew = a.k.vreset;
-      rf = a.k.tref;
+    o.vt = drop + cur;
+    if (o.vt >= a.k.theta) {
+      o.spike = true;
+      o.v = a.k.vreset;
+      o.rf = a.k.tref;
     } else {
-      vnew = vt;
+      o.v = o.vt;
     }
   }
   const float decayed = a.k.pc * caprev;
-  const float canew = decayed + (spike ? a.k.alpha : 0.0f);
-  a.v[j] = vnew;
-  a.ca[j] = canew;
-  a.ref[j] = (uint8_t)rf;
+  o.ca = decayed + (o.spike ? a.k.alpha : 0.0f);
+  return o;
+}
+
+// Stores a neuron's new state (and its trajectory in train mode).
+__device__ __forceinline__ void neuron_store(const StepArgs& a, int64_t j, int64_t u,
+                                             const NeuronOut& o, float vprev, float caprev) {
+  a.v[j] = o.v;
+  a.ca[j] = o.ca;
+  a.ref[j] = (uint8_t)o.rf;
   if (a.rec_vprev) {
-    const int64_t o = (u - a.rec_base) * (int64_t)a.n_cols * a.npc + j;
-    a.rec_vprev[o] = vprev;
-    a.rec_caprev[o] = caprev;
-    a.rec_vt[o] = vt;
-    a.rec_flags[o] = (uint8_t)((spike ? 1 : 0) | (refr ? 2 : 0));
+    const int64_t r = (u - a.rec_base) * (int64_t)a.n_cols * a.npc + j;
+    a.rec_vprev[r] = vprev;
+    a.rec_caprev[r] = caprev;
+    a.rec_vt[r] = o.vt;
+    a.rec_flags[r] = (uint8_t)((o.spike ? 1 : 0) | (o.refr ? 2 : 0));
   }
-  return spike;
+}
+
+__device__ __forceinline__ bool neuron_step(const StepArgs& a, int64_t j, int64_t u,
+                                            int32_t rec_in, int32_t n_ext, float vprev,
+                                            float caprev, int32_t rf) {
+  const NeuronOut o = neuron_update(a, rec_in, n_ext, vprev, caprev, rf);
+  neuron_store(a, j, u, o, vprev, caprev);
+  return o.spike;
 }
 
 // The external count of neuron k of column g: one Philox block serves four consecutive
@@ -144,10 +161,10 @@ __device__ __forceinline__ uint32_t block_word(const Rand4& x, uint32_t w) {
   return w == 0 ? x.x : w == 1 ? x.y : w == 2 ? x.z : x.w;
 }
 
-__device__ __forceinline__ int32_t external_count(const StepArgs& a, int32_t g, int k, int64_t u,
+__device__ __forceinline__ int32_t external_count(const StepArgs& a, int32_t cloc, int k, int64_t u,
                                                   const uint64_t* ptab, uint32_t key0,
                                                   uint32_t key1) {
-  const uint32_t jl = (uint32_t)(a.col_local[g] * a.npc + k);
+  const uint32_t jl = (uint32_t)(cloc * a.npc + k);
   const Rand4 x = philox10(jl >> 2, (uint32_t)u, 0u, kStreamExt, key0, key1);
   return poisson_count(ptab, block_word(x, jl & 3u));
 }
@@ -234,6 +251,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   __shared__ int32_t s_part[kMaxTilePairs];     // global part index of each pair
   __shared__ uint64_t s_slots[kMaxTilePairs];    // per pair: 5-bit tile slot of each rank
   __shared__ int32_t s_col[kMaxTileCols];
+  __shared__ int32_t s_cloc[kMaxTileCols];      // index of each column within its network
+  __shared__ uint32_t s_key[2];                 // the network's Philox key
   __shared__ int32_t s_tot[kMaxTileCols];       // spikes of each column at this step
   __shared__ int32_t s_epre[kMaxTileCols + 1];  // prefix of (parts x spikes) over columns
   __shared__ int32_t wsum[2 * NW + 1];
@@ -269,7 +288,11 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     if (tile < 0) continue;
     const int T = a.tile_ncols[tile];
     const int ns = a.tile_npairs[tile];
-    if (tid < kMaxTileCols) s_col[tid] = a.tile_cols[tile * kMaxTileCols + tid];
+    if (tid < kMaxTileCols) {
+      const int32_t c = a.tile_cols[tile * kMaxTileCols + tid];
+      s_col[tid] = c;
+      s_cloc[tid] = c < 0 ? 0 : a.col_local[c];
+    }
     if (tid < kMaxTilePairs) {
       s_src[tid] = a.tile_pcol[tile * kMaxTilePairs + tid];
       const int32_t pc = a.tile_pcol[tile * kMaxTilePairs + tid];
@@ -279,6 +302,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     const int32_t net = a.col_net[a.tile_cols[tile * kMaxTileCols]];
     for (int q = tid; q < kPoissonEntries; q += BLOCK)
       ptab[q] = a.net_ptab[(int64_t)net * kPoissonEntries + q];
+    if (tid < 2) s_key[tid] = a.net_key[2 * net + tid];
     const int32_t TN = T * npc;
     for (int e = tid; e < W * TN; e += BLOCK) acc[e] = 0;
     __syncthreads();
@@ -415,14 +439,16 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     const int nchunks = T * nch;
     const int nr = (nch + 3) >> 2;
     const bool shared_draw = (npc & 3) == 0;
-    const uint32_t key0 = a.net_key[2 * net], key1 = a.net_key[2 * net + 1];
+    const uint32_t key0 = s_key[0], key1 = s_key[1];
     unsigned long long my_ext = 0, my_rec = 0;
     for (int rd = wave; rd < T * nr; rd += NW) {
       const int col = rd / nr, q0 = (rd - col * nr) * 4;
       const int32_t g = s_col[col];
       float vv[4], cc[4];
-      int32_t rr[4], nx[4];
+      int32_t rr[4], nx[4], sv[4], dg[4];
       bool ok[4];
+      // every global load of the round first, so that their latencies overlap: state, out
+      // degree (for the emitted-events counter) and, at a light step, the saved input
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int k = (q0 + m) * 64 + lane;
@@ -430,16 +456,21 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
         vv[m] = 0.0f;
         cc[m] = 0.0f;
         rr[m] = 0;
+        sv[m] = 0;
+        dg[m] = 0;
         if (ok[m]) {
           const int64_t j = (int64_t)g * npc + k;
           vv[m] = a.v[j];
           cc[m] = a.ca[j];
           rr[m] = a.ref[j];
+          dg[m] = a.deg[j];
+          if (light) sv[m] = a.acc_save[light_save + j];
         }
       }
+      const int32_t cloc = s_cloc[col];
       Rand4 blk{0u, 0u, 0u, 0u};
       if (shared_draw)
-        blk = philox10(((uint32_t)(a.col_local[g] * npc + q0 * 64) >> 2) + (uint32_t)lane,
+        blk = philox10(((uint32_t)(cloc * npc + q0 * 64) >> 2) + (uint32_t)lane,
                        (uint32_t)u, 0u, kStreamExt, key0, key1);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -450,24 +481,26 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
                         (uint32_t)__shfl((int32_t)blk.z, src), (uint32_t)__shfl((int32_t)blk.w, src)};
           if (ok[m]) nx[m] = poisson_count(ptab, block_word(b, (uint32_t)lane & 3u));
         } else if (ok[m]) {
-          nx[m] = external_count(a, g, (q0 + m) * 64 + lane, u, ptab, key0, key1);
+          nx[m] = external_count(a, cloc, (q0 + m) * 64 + lane, u, ptab, key0, key1);
         }
+      }
+      // the four chunks' new states, then their stores (no load waits behind a store)
+      NeuronOut o[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = (q0 + m) * 64 + lane;
+        const int32_t in = ok[m] ? (int32_t)((uint32_t)acc[col * npc + k] + (uint32_t)sv[m]) : 0;
+        o[m] = neuron_update(a, in, nx[m], vv[m], cc[m], rr[m]);
+        o[m].spike = o[m].spike && ok[m];
+        if (ok[m]) my_ext += (unsigned long long)nx[m];
+        if (o[m].spike) my_rec += (unsigned long long)dg[m];
       }
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         if (q0 + m < nch) {
           const int c = col * nch + q0 + m;
-          bool sp = false;
-          if (ok[m]) {
-            const int k = (q0 + m) * 64 + lane;
-            const int64_t j = (int64_t)g * npc + k;
-            int32_t in = acc[col * npc + k];
-            if (light) in = (int32_t)((uint32_t)in + (uint32_t)a.acc_save[light_save + j]);
-            sp = neuron_step(a, j, u, in, nx[m], vv[m], cc[m], rr[m]);
-            my_ext += (unsigned long long)nx[m];
-            if (sp) my_rec += (unsigned long long)a.deg[j];
-          }
-          const unsigned long long bal = __ballot(sp);
+          if (ok[m]) neuron_store(a, (int64_t)g * npc + (q0 + m) * 64 + lane, u, o[m], vv[m], cc[m]);
+          const unsigned long long bal = __ballot(o[m].spike);
           if (lane == 0) {
             smask[c] = bal;
             scnt[c] = __popcll(bal);
@@ -611,7 +644,7 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u_arg
         const int64_t j = (int64_t)g * a.npc + k;
         const int32_t x = in[j];
         in[j] = 0;
-        const int32_t nx = external_count(a, g, k, u, ptab, key0, key1);
+        const int32_t nx = external_count(a, a.col_local[g], k, u, ptab, key0, key1);
         sp = neuron_step(a, j, u, x, nx, a.v[j], a.ca[j], a.ref[j]);
         my_ext += (unsigned long long)nx;
         if (sp) my_rec += (unsigned long long)a.deg[j];
