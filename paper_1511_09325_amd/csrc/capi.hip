@@ -252,7 +252,9 @@ void build_parts(sim& s, int tx, int ty) {
 void build_tiles(sim& s, int tx, int ty) {
   if (tx < 1 || ty < 1 || tx > kMaxTileSide || ty > kMaxTileSide)
     throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4]"};
-  std::vector<int32_t> tcols, tncols, pcol, ppart, npairs;
+  std::vector<int32_t> cinfo, tncols, pinfo, tnet, npairs;
+  std::vector<int32_t> pfirst((size_t)s.n_cols + 1, 0);
+  for (int32_t g = 0; g < s.n_cols; ++g) pfirst[g + 1] = pfirst[g] + s.h_np[g];
   std::vector<uint64_t> tslots;
   std::vector<std::vector<int32_t>> lanes(8);
   int rot = 0, maxc = 0;
@@ -303,11 +305,18 @@ void build_tiles(sim& s, int tx, int ty) {
           maxc = std::max(maxc, (int)tc.size());
           tncols.push_back((int32_t)tc.size());
           npairs.push_back((int32_t)pairs.size());
-          for (int q = 0; q < kMaxTileCols; ++q) tcols.push_back(q < (int)tc.size() ? tc[q] : -1);
+          tnet.push_back(n);
+          for (int q = 0; q < kMaxTileCols; ++q) {
+            const bool in = q < (int)tc.size();
+            cinfo.push_back(in ? tc[q] : -1);
+            cinfo.push_back(in ? tc[q] - s.net_col0[n] : 0);
+            cinfo.push_back(in ? s.h_np[tc[q]] : 0);
+            cinfo.push_back(in ? pfirst[tc[q]] : 0);
+          }
           for (int q = 0; q < kMaxTilePairs; ++q) {
             const bool in = q < (int)pairs.size();
-            pcol.push_back(in ? pairs[q].first : -1);
-            ppart.push_back(in ? pairs[q].second : 0);
+            pinfo.push_back(in ? pairs[q].first : -1);
+            pinfo.push_back(in ? pfirst[pairs[q].first] + pairs[q].second : 0);
             tslots.push_back(in ? packs[q] : ~(uint64_t)0);
           }
           lanes[(st + rot) % 8].push_back(id);
@@ -326,10 +335,10 @@ void build_tiles(sim& s, int tx, int ty) {
     throw Fail{DPSNN_EINVAL, "tile accumulators exceed the 160 KB LDS of a workgroup"};
   }
   release(s, s.tile_order);
-  release(s, s.tile_cols);
+  release(s, s.tile_cinfo);
   release(s, s.tile_ncols);
-  release(s, s.tile_pcol);
-  release(s, s.tile_ppart);
+  release(s, s.tile_pinfo);
+  release(s, s.tile_net);
   release(s, s.tile_npairs);
   release(s, s.tile_slots);
   release(s, s.tile_work);
@@ -339,10 +348,10 @@ void build_tiles(sim& s, int tx, int ty) {
   s.n_tiles = (int32_t)tncols.size();
   s.grid_tiles = (int32_t)order.size();
   s.tile_order = upload(s, order);
-  s.tile_cols = upload(s, tcols);
+  s.tile_cinfo = upload(s, cinfo);
   s.tile_ncols = upload(s, tncols);
-  s.tile_pcol = upload(s, pcol);
-  s.tile_ppart = upload(s, ppart);
+  s.tile_pinfo = upload(s, pinfo);
+  s.tile_net = upload(s, tnet);
   s.tile_npairs = upload(s, npairs);
   s.tile_slots = upload(s, tslots);
   s.tile_work = upload(s, std::vector<uint32_t>((size_t)s.n_tiles, 0u));

@@ -26,10 +26,13 @@
 //     col_part  int32 [C][9]   part of rank r (-1 padded); col_np int32 [C] parts per
 //                              column; col_pbase int64 [C+1] first idx entry of the column
 //   tiles (the unit of work of the arrival kernel): up to 4x4 target columns of one network
-//     tile_cols   int32 [tiles][16]   the tile's columns, -1 padded
-//     tile_pcol, tile_ppart int32 [tiles][64]  every (source column, part) with a synapse
-//                                     into the tile (one part per source in the native
-//                                     tiling; a part may reach several tiles otherwise)
+//     tile_cinfo  int32x4 [tiles][16] per column of the tile: column (-1 padded), index
+//                                     within its network, parts, first part index
+//     tile_pinfo  int32x2 [tiles][64] every (source column, global part index) with a
+//                                     synapse into the tile, -1 padded (one part per source
+//                                     in the native tiling; a part may reach several tiles
+//                                     otherwise)
+//     tile_net    int32 [tiles]       the tile's network
 //     tile_slots  uint64[tiles][64]   for each pair and each rank r of its part, the tile
 //                                     slot of its target column in bits 5r..5r+4 (31: not
 //                                     in the tile or not in the part); bits 45-63 are set
@@ -145,10 +148,10 @@ struct StepArgs {
   int32_t n_tiles;
   uint32_t* tile_work;        // [n_tiles]: synapse records read at the last gathering step
   int32_t order_by_work;      // reorder tiles by work after each gathering step
-  const int32_t* tile_cols;
+  const int4* tile_cinfo;
   const int32_t* tile_ncols;
-  const int32_t* tile_pcol;
-  const int32_t* tile_ppart;
+  const int2* tile_pinfo;
+  const int32_t* tile_net;
   const int32_t* tile_npairs;
   const uint64_t* tile_slots;
   // synapses
@@ -277,8 +280,8 @@ struct sim {
   unsigned long long* net_cnt = nullptr;
   // tiles of the current shape
   int32_t tile_x = 0, tile_y = 0, n_tiles = 0, grid_tiles = 0, tile_max_cols = 0;
-  int32_t *tile_order = nullptr, *tile_cols = nullptr, *tile_ncols = nullptr,
-          *tile_pcol = nullptr, *tile_ppart = nullptr, *tile_npairs = nullptr;
+  int32_t *tile_order = nullptr, *tile_cinfo = nullptr, *tile_ncols = nullptr,
+          *tile_pinfo = nullptr, *tile_net = nullptr, *tile_npairs = nullptr;
   uint64_t* tile_slots = nullptr;
   uint32_t* tile_work = nullptr;   // [n_tiles] records read per tile at the last gathering step
   int32_t order_by_work = 0;       // more tiles than compute units: order them by work

@@ -240,6 +240,8 @@ __device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
 // column is in the tile (the record's rank, looked up in the pair's slot table) and adding
 // them to the tile's LDS accumulators with integer atomics.  Then the tile's neurons are
 // updated in 64-neuron chunks and the spikes compacted per column, in ascending order.
+static_assert(kPoissonEntries <= 64, "one Poisson threshold per lane of the first wave");
+
 template <int BLOCK, bool TRAIN>
 __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc) {
   const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
@@ -253,6 +255,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   __shared__ int32_t s_col[kMaxTileCols];
   __shared__ int32_t s_cloc[kMaxTileCols];      // index of each column within its network
   __shared__ uint32_t s_key[2];                 // the network's Philox key
+  __shared__ int32_t s_cnp[kMaxTileCols];       // parts of each column
+  __shared__ int32_t s_cpf[kMaxTileCols];       // first part index of each column
   __shared__ int32_t s_tot[kMaxTileCols];       // spikes of each column at this step
   __shared__ int32_t s_epre[kMaxTileCols + 1];  // prefix of (parts x spikes) over columns
   __shared__ int32_t wsum[2 * NW + 1];
@@ -289,20 +293,23 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     const int T = a.tile_ncols[tile];
     const int ns = a.tile_npairs[tile];
     if (tid < kMaxTileCols) {
-      const int32_t c = a.tile_cols[tile * kMaxTileCols + tid];
-      s_col[tid] = c;
-      s_cloc[tid] = c < 0 ? 0 : a.col_local[c];
+      const int4 ci = a.tile_cinfo[tile * kMaxTileCols + tid];
+      s_col[tid] = ci.x;
+      s_cloc[tid] = ci.y;
+      s_cnp[tid] = ci.z;
+      s_cpf[tid] = ci.w;
     }
     if (tid < kMaxTilePairs) {
-      s_src[tid] = a.tile_pcol[tile * kMaxTilePairs + tid];
-      const int32_t pc = a.tile_pcol[tile * kMaxTilePairs + tid];
-      s_part[tid] = pc < 0 ? 0 : a.col_pfirst[pc] + a.tile_ppart[tile * kMaxTilePairs + tid];
+      const int2 pi = a.tile_pinfo[tile * kMaxTilePairs + tid];
+      s_src[tid] = pi.x;
+      s_part[tid] = pi.y;
+      s_slots[tid] = a.tile_slots[tile * kMaxTilePairs + tid];
     }
-    if (tid < kMaxTilePairs) s_slots[tid] = a.tile_slots[tile * kMaxTilePairs + tid];
-    const int32_t net = a.col_net[a.tile_cols[tile * kMaxTileCols]];
-    for (int q = tid; q < kPoissonEntries; q += BLOCK)
-      ptab[q] = a.net_ptab[(int64_t)net * kPoissonEntries + q];
-    if (tid < 2) s_key[tid] = a.net_key[2 * net + tid];
+    // the network's Poisson table and key, needed from the update on: loaded now, stored
+    // to LDS after the item prefix so that the load overlaps it
+    const int32_t net = a.tile_net[tile];
+    const uint64_t ptab_q = tid < kPoissonEntries ? a.net_ptab[(int64_t)net * kPoissonEntries + tid] : 0;
+    const uint32_t key_q = tid < 2 ? a.net_key[2 * net + tid] : 0u;
     const int32_t TN = T * npc;
     for (int e = tid; e < W * TN; e += BLOCK) acc[e] = 0;
     __syncthreads();
@@ -327,6 +334,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       carry += tot;
     }
     if (tid == 0) it_pref[n_items] = carry;
+    if (tid < kPoissonEntries) ptab[tid] = ptab_q;
+    if (tid < 2) s_key[tid] = key_q;
     __syncthreads();
     const int32_t total = carry;
     unsigned long long streamed = 0;
@@ -525,22 +534,25 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       if (lane == 63) s_tot[col] = incl;
     }
     __syncthreads();
+    // the ids also go to LDS (over the accumulators, no longer needed) for the entries below
+    uint16_t* s_ids = (uint16_t*)acc;
     for (int c = wave; c < nchunks; c += NW) {
       const int col = c / nch, first = col * nch;
       const unsigned long long m = smask[c];
       if ((m >> lane) & 1ull) {
-        uint16_t* out = a.hist_ids + ((int64_t)slot_u * a.n_cols + s_col[col]) * npc;
-        out[scnt[c] + __popcll(m & lt)] = (uint16_t)((c - first) * 64 + lane);
+        const int32_t pos = scnt[c] + __popcll(m & lt);
+        const uint16_t id = (uint16_t)((c - first) * 64 + lane);
+        a.hist_ids[((int64_t)slot_u * a.n_cols + s_col[col]) * npc + pos] = id;
+        s_ids[col * npc + pos] = id;
       }
     }
     unsigned long long my_spk = 0;
     if (tid < T) {
       const int32_t tot = s_tot[tid];
       a.hist_cnt[(int64_t)slot_u * a.n_cols + s_col[tid]] = tot;
-      if (tot) a.col_spk[s_col[tid]] += (unsigned long long)tot;
+      if (tot) atomicAdd(&a.col_spk[s_col[tid]], (unsigned long long)tot);
       my_spk = (unsigned long long)tot;
     }
-    __threadfence_block();
     __syncthreads();
     // 5. history entries of the step's spikes: one lane per (column, part, spike) copies the
     // part's row-index entry (loaded once) into the rows of the history, consecutive lanes
@@ -549,7 +561,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       int32_t run = 0;
       for (int col = 0; col < T; ++col) {
         s_epre[col] = run;
-        run += a.col_np[s_col[col]] * s_tot[col];
+        run += s_cnp[col] * s_tot[col];
       }
       s_epre[T] = run;
     }
@@ -557,16 +569,18 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     for (int32_t e = tid; e < s_epre[T]; e += BLOCK) {
       int col = 0;
       while (col + 1 < T && s_epre[col + 1] <= e) ++col;
-      const int32_t g = s_col[col], cnt = s_tot[col];
+      const int32_t cnt = s_tot[col];
       const int32_t r = e - s_epre[col];
       const int p = r / cnt, pos = r - p * cnt;
-      const int32_t k = a.hist_ids[((int64_t)slot_u * a.n_cols + g) * npc + pos];
-      const uint4* ent = (const uint4*)idx_entry(a, g, k, p);
+      const int32_t k = s_ids[col * npc + pos];
+      // entry (column's first entry npc * first part) + k * parts + p; every word is loaded
+      // (the ones past the entry repeat its last word), so that the loads leave together
+      const uint4* ent = (const uint4*)(a.idx + ((int64_t)npc * s_cpf[col] + (int64_t)k * s_cnp[col] + p) * a.idxw);
+      const int nw = a.idxw >> 4;
       uint4 buf[kIdxWords];
 #pragma unroll
-      for (int q = 0; q < kIdxWords; ++q)
-        if (q * 16 < a.idxw) buf[q] = ent[q];
-      const int64_t pid = (int64_t)slot_u * a.n_parts + a.col_pfirst[g] + p;
+      for (int q = 0; q < kIdxWords; ++q) buf[q] = ent[q < nw ? q : nw - 1];
+      const int64_t pid = (int64_t)slot_u * a.n_parts + s_cpf[col] + p;
       a.hist_st[pid * npc + pos] = *(const int64_t*)&buf[0];
       const uint16_t* go = (const uint16_t*)&buf[0] + 4;
       uint16_t* out = a.hist_go + pid * (int64_t)(a.nd + 1) * npc + pos;
@@ -801,10 +815,10 @@ StepArgs make_step_args(const sim& s) {
   a.n_tiles = s.n_tiles;
   a.tile_work = s.tile_work;
   a.order_by_work = s.order_by_work;
-  a.tile_cols = s.tile_cols;
+  a.tile_cinfo = (const int4*)s.tile_cinfo;
   a.tile_ncols = s.tile_ncols;
-  a.tile_pcol = s.tile_pcol;
-  a.tile_ppart = s.tile_ppart;
+  a.tile_pinfo = (const int2*)s.tile_pinfo;
+  a.tile_net = s.tile_net;
   a.tile_npairs = s.tile_npairs;
   a.col_np = s.col_np;
   a.col_part = s.col_part;
