@@ -16,7 +16,7 @@
 //               k * col_np[g] + p.  The parts of one neuron are contiguous (row_base[i])
 //     syn       uint32[S' + 4]: k (bits 0-11, target index inside its column) | r (bits
 //               12-15) | w_q (bits 16-31, int16 weight at 2^-14 mV).  Every group is padded
-//               to a multiple of 4 records with dummies (r = 15, weight 0), so parts and
+//               to a multiple of 4 records with dummies (r = 9, weight 0), so parts and
 //               groups start on 16-byte boundaries and are read in whole 16-byte words
 //     deg       int32 [N]    out-degree (records without the padding)
 //     wfx       int32 [S']   train mode only: rint(w_f32 * 2^16) efficacies
@@ -71,8 +71,10 @@ constexpr int kMaxTileSrc = (kMaxTileSide + 2) * (kMaxTileSide + 2);
 constexpr int kMaxTilePairs = 64;   // (source column, part) pairs of one tile
 constexpr int kMaxParts = kMaxNbr;  // parts of one source column (9 with 1x1 tiles)
 constexpr int kNoSlot = 31;
-constexpr int kDummyRank = 15;
-constexpr uint32_t kDummyRecord = (uint32_t)kDummyRank << 12;  // k 0, rank 15, weight 0
+// dummy records carry rank 9, one past the last neighbour rank: the slot words' fields from
+// the tenth up read 31, so a dummy decodes as "not in the tile" without clamping its rank
+constexpr int kDummyRank = kMaxNbr;
+constexpr uint32_t kDummyRecord = (uint32_t)kDummyRank << 12;  // k 0, rank 9, weight 0
 constexpr int kCounters = 8;        // per-network counters (see StepArgs::net_cnt)
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr uint32_t kStreamSyn = 1;  // Philox counter word 3: purpose of the draw
@@ -83,6 +85,8 @@ constexpr uint32_t kStreamInit = 3;
 __host__ __device__ __forceinline__ uint32_t rec_k(uint32_t w) { return w & 0xfffu; }
 __host__ __device__ __forceinline__ uint32_t rec_rank(uint32_t w) { return (w >> 12) & 0xfu; }
 __host__ __device__ __forceinline__ int32_t rec_w32(uint32_t w) { return (((int32_t)w) >> 16) * 4; }
+// the weight in its own 2^-14 mV units
+__host__ __device__ __forceinline__ int32_t rec_wq(uint32_t w) { return ((int32_t)w) >> 16; }
 
 // ---------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products, high halves

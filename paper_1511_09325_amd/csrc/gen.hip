@@ -194,7 +194,7 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
       if (lane == 0) *(int64_t*)ent = rb + p0;
       for (int dd = lane; dd <= a.nd; dd += 64) ((uint16_t*)(ent + 8))[dd] = (uint16_t)(L.gst[p][dd] - p0);
     }
-    // dummy records (rank 15, weight 0) in the padding at the end of each group
+    // dummy records (rank 9, weight 0) in the padding at the end of each group
     for (int p = 0; p < np; ++p)
       for (int dd = 0; dd < a.nd; ++dd)
         for (int32_t q = L.pad[p][dd] + lane; q < L.gst[p][dd + 1]; q += 64) out[q] = kDummyRecord;

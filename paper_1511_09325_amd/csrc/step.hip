@@ -345,6 +345,8 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     // every quad of lanes streams the four groups of its lanes in 16-byte pieces, kPIF
     // loads in flight per lane, and adds the synapses into the LDS accumulators.
     const int quad0 = lane & ~3, ql = lane & 3;
+    const uint32_t npc4 = (uint32_t)npc * 4u;
+    uint32_t dwave = 0;  // records delivered by the wave (uniform)
     // exact small-integer quotients through float reciprocals (operands < 2^16)
     const float inv_nb = 1.0f / (float)NB;
     for (int32_t bt = wave; bt * 64 < total; bt += NW) {
@@ -375,12 +377,13 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
         const int32_t g0 = go[0], g1 = go[npc];
         gpc = (uint32_t)((a.hist_st[pid * npc + pos] + g0) >> 2);
         glen = (g1 - g0) >> 2;
-        gsb = (d - ag) * TN;
+        gsb = (d - ag) * TN * 4;
         gsl = s_slots[si];
       }
       streamed += (unsigned long long)(glen * 4);
       // the quad streams the pieces of its four groups: piece p of the quad lies in group m
-      // where pref[m] <= p < pref[m + 1], at piece index bias[m] + p
+      // where pref[m] <= p < pref[m + 1], at piece index bias[m] + p; sbq is the byte offset
+      // of the group's step accumulator
       int32_t pref[5], sbq[4];
       uint32_t bias[4];
       uint64_t slq[4];
@@ -415,23 +418,26 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
           }
         }
         // tile slot of each record from its pair's slot word (rank r in bits 5r..5r+4; the
-        // bits above the ninth rank are set, so dummies and absent ranks read 31)
+        // bits from the tenth field up are set, so dummies and absent ranks read 31); the
+        // weights are added in their 2^-14 mV units (train mode: the float efficacies, in
+        // 2^-16 mV), the wave's delivered records counted from the ballot
 #pragma unroll
         for (int q = 0; q < kPIF; ++q) {
           const uint32_t x[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const uint32_t rk = rec_rank(x[e]);
-            const uint32_t sl = (uint32_t)(sw[q] >> min(5u * rk, 59u)) & 31u;
-            if (sl != (uint32_t)kNoSlot) {
-              atomicAdd(&acc[aoff[q] + (int)__umul24(sl, (uint32_t)npc) + (int)rec_k(x[e])],
-                        TRAIN ? v[q][e] : rec_w32(x[e]));
-              delivered += 1u;
+            const uint32_t sl = (uint32_t)(sw[q] >> (5u * rec_rank(x[e]))) & 31u;
+            const bool in = sl != (uint32_t)kNoSlot;
+            dwave += (uint32_t)__popcll(__ballot(in));
+            if (in) {
+              const uint32_t off = __umul24(sl, npc4) + (uint32_t)aoff[q] + (rec_k(x[e]) << 2);
+              atomicAdd((int32_t*)((unsigned char*)acc + off), TRAIN ? v[q][e] : rec_wq(x[e]));
             }
           }
         }
       }
     }
+    delivered = lane == 0 ? dwave : 0u;
     __syncthreads();
     // the accumulators of the later steps of the window, for their light steps
     for (int w = 1; w < W; ++w) {
@@ -498,7 +504,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int k = (q0 + m) * 64 + lane;
-        const int32_t in = ok[m] ? (int32_t)((uint32_t)acc[col * npc + k] + (uint32_t)sv[m]) : 0;
+        // accumulated recurrent input, to 2^-16 mV (train mode accumulates in those units)
+        const uint32_t ai = (uint32_t)acc[col * npc + k] + (uint32_t)sv[m];
+        const int32_t in = ok[m] ? (int32_t)(TRAIN ? ai : ai << 2) : 0;
         o[m] = neuron_update(a, in, nx[m], vv[m], cc[m], rr[m]);
         o[m].spike = o[m].spike && ok[m];
         if (ok[m]) my_ext += (unsigned long long)nx[m];
