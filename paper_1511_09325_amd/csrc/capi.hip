@@ -759,13 +759,15 @@ static void run_graph_chunk(sim& s, int32_t k, bool record) {
   const std::string key = std::to_string(k) + "/" + std::to_string(s.delivery) + "/" +
                           std::to_string(s.block) + "/" + std::to_string(s.tile_x) + "x" +
                           std::to_string(s.tile_y) + "/" + (record ? "r" : "-") + "/" +
-                          (s.rec_on ? "t" : "-");
+                          (s.rec_on ? "t" : "-") + "/" +
+                          std::to_string(s.gk > 1 ? s.now % s.gk : 0);
   if (!s.graph_exec || key != s.graph_key) {
     drop_graph(s);
     if (!s.cap_stream) HIPCHK(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
     hipStream_t user = s.stream;
     s.stream = s.cap_stream;
     s.graph_mode = true;
+    s.graph_base = s.now;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal);
     for (int32_t q = 0; q < k && e == hipSuccess; ++q) {

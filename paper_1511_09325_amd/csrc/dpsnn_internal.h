@@ -327,6 +327,7 @@ struct sim {
   int64_t* d_now = nullptr;        // device step base read by graph-launched kernels
   int32_t graph_steps = 0;         // steps per captured graph (0: direct launches)
   bool graph_mode = false;         // true while capturing: kernels read d_now
+  int64_t graph_base = 0;          // while capturing: the step the graph's first step stands for
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   std::string graph_key;
@@ -344,7 +345,7 @@ hipError_t launch_init_state(const sim& s);
 // part: -1 the whole step, 0 the update (fused with the gather in the arrival form),
 // 1 the push delivery
 hipError_t launch_step(sim& s, int64_t u, int32_t delivery, int32_t block, int part);
-size_t tile_lds_bytes(const sim& s);
+size_t tile_lds_bytes(const sim& s, int32_t kacc);
 hipError_t prepare_step_kernels();
 bool tile_lds_ok(const sim& s);
 hipError_t launch_raster(sim& s, int64_t u);

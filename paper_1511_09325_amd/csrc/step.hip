@@ -243,7 +243,8 @@ __device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
 static_assert(kPoissonEntries <= 64, "one Poisson threshold per lane of the first wave");
 
 template <int BLOCK, bool TRAIN>
-__global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc) {
+__global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc,
+                                                     int32_t kacc) {
   const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
   constexpr int NW = BLOCK / 64;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -265,10 +266,11 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   const int lane = tid & 63, wave = tid >> 6;
   const int npc = a.npc;
   const int nch = (npc + 63) >> 6;
-  // dynamic LDS: acc[K][maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch]
+  // dynamic LDS: acc[kacc][maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch], kacc the
+  // accumulators this launch has room for (the window's K, or 1 for a light step's launch)
   const int32_t K = a.gk;
   int32_t* acc = (int32_t*)lds;
-  size_t off = ((size_t)K * maxc * npc * 4 + 15) & ~(size_t)15;
+  size_t off = ((size_t)kacc * maxc * npc * 4 + 15) & ~(size_t)15;
   unsigned long long* smask = (unsigned long long*)(lds + off);
   off += (size_t)maxc * nch * 8;
   int32_t* scnt = (int32_t*)(lds + off);
@@ -278,10 +280,12 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   // memory), keeping one accumulator per step; the accumulators of later steps go to
   // acc_save.  The other steps of the window ("light" steps) read only the spikes emitted
   // since the gathering step, plus their saved accumulator.  *gath is the last gathering
-  // step (-1 after anything that invalidates acc_save).
+  // step (-1 after anything that invalidates acc_save).  A launch with room for fewer
+  // accumulators than its window needs gathers its own step only and records no window.
   const int64_t g_last = *a.gath;
   const bool light = K > 1 && g_last >= 0 && u > g_last && u < g_last + (K - (int32_t)(g_last % K));
-  const int32_t W = light ? 1 : K - (int32_t)(u % K);
+  const int32_t W = light ? 1 : min(K - (int32_t)(u % K), kacc);
+  const bool full_window = K > 1 && !light && W == K - (int32_t)(u % K);
   const int32_t jnew = light ? (int32_t)(u - g_last) : 0;
   const int32_t NB = a.dh - 1;  // spike ages b = u - t in [1, d_max]
   const int64_t nall = (int64_t)a.n_cols * npc;
@@ -625,7 +629,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       __threadfence();
       s_last = atomicAdd(a.gdone, 1u) == gridDim.x - 1;
       if (s_last) {
-        if (K > 1) *a.gath = u;
+        if (full_window) *a.gath = u;
         *a.gdone = 0u;
         __threadfence();
       }
@@ -754,18 +758,33 @@ __global__ void k_init_state(StepArgs a) {
 }
 
 template <int BLOCK>
+void launch_tile(const sim& s, const StepArgs& a, int64_t u, int32_t kacc, bool train) {
+  const size_t lds = tile_lds_bytes(s, kacc);
+  if (train)
+    hipLaunchKernelGGL((k_step_tile<BLOCK, true>), dim3(s.grid_tiles), dim3(BLOCK), lds,
+                       s.stream, a, u, s.tile_max_cols, kacc);
+  else
+    hipLaunchKernelGGL((k_step_tile<BLOCK, false>), dim3(s.grid_tiles), dim3(BLOCK), lds,
+                       s.stream, a, u, s.tile_max_cols, kacc);
+}
+
+template <int BLOCK>
 hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
   const StepArgs a = make_step_args(s);
   const bool train = s.wfx != nullptr;
   if (delivery == DPSNN_DELIVERY_ARRIVAL) {
     if (part == 1) return hipSuccess;
-    const size_t lds = tile_lds_bytes(s);
-    if (train)
-      hipLaunchKernelGGL((k_step_tile<BLOCK, true>), dim3(s.grid_tiles), dim3(BLOCK), lds,
-                         s.stream, a, u, s.tile_max_cols);
-    else
-      hipLaunchKernelGGL((k_step_tile<BLOCK, false>), dim3(s.grid_tiles), dim3(BLOCK), lds,
-                         s.stream, a, u, s.tile_max_cols);
+    // Steps inside a gather window (u mod K != 0) are light: their launch reserves one
+    // accumulator and uses workgroups of at most 512 threads, so that two tiles share a
+    // compute unit and hide each other's latencies.  (Should the window not be valid on
+    // the device, such a launch gathers its own step alone.)
+    const int64_t uabs = s.graph_mode ? s.graph_base + u : u;
+    if (s.gk > 1 && uabs % s.gk != 0) {
+      if (BLOCK > 512) launch_tile<512>(s, a, u, 1, train);
+      else launch_tile<BLOCK>(s, a, u, 1, train);
+    } else {
+      launch_tile<BLOCK>(s, a, u, s.gk, train);
+    }
     return hipGetLastError();
   }
   if (part != 1)
@@ -783,9 +802,9 @@ hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
 
 // LDS of the tile kernel: accumulators and spike masks of the largest tile (dynamic), plus
 // the kernel's static tables; together at most the 160 KB of a workgroup.
-static size_t tile_fixed_lds(const sim& s) {
+static size_t tile_fixed_lds(const sim& s, int32_t kacc) {
   const size_t nch = (size_t)(s.npc + 63) / 64;
-  size_t b = ((size_t)std::max(s.gk, 1) * s.tile_max_cols * s.npc * 4 + 15) & ~(size_t)15;
+  size_t b = ((size_t)std::max(kacc, 1) * s.tile_max_cols * s.npc * 4 + 15) & ~(size_t)15;
   b += (size_t)s.tile_max_cols * nch * 8;
   b += ((size_t)s.tile_max_cols * nch * 4 + 15) & ~(size_t)15;
   return b;
@@ -797,9 +816,9 @@ static size_t tile_static_bytes() {
          (sizeof(int32_t) * 2 + 1 + 5 * sizeof(uint64_t)) * 16 + 64;
 }
 
-bool tile_lds_ok(const sim& s) { return tile_fixed_lds(s) + tile_static_bytes() <= kMaxLds; }
+bool tile_lds_ok(const sim& s) { return tile_fixed_lds(s, s.gk) + tile_static_bytes() <= kMaxLds; }
 
-size_t tile_lds_bytes(const sim& s) { return tile_fixed_lds(s); }
+size_t tile_lds_bytes(const sim& s, int32_t kacc) { return tile_fixed_lds(s, kacc); }
 
 StepArgs make_step_args(const sim& s) {
   StepArgs a{};
