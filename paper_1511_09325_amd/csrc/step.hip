@@ -132,13 +132,15 @@ __device__ __forceinline__ NeuronOut neuron_update(const StepArgs& a, int32_t re
   return o;
 }
 
-// Stores a neuron's new state (and its trajectory in train mode).
+// Stores a neuron's new state (and its trajectory when recording: REC false compiles the
+// recording out, for kernels that never run with it).
+template <bool REC>
 __device__ __forceinline__ void neuron_store(const StepArgs& a, int64_t j, int64_t u,
                                              const NeuronOut& o, float vprev, float caprev) {
   a.v[j] = o.v;
   a.ca[j] = o.ca;
   a.ref[j] = (uint8_t)o.rf;
-  if (a.rec_vprev) {
+  if (REC && a.rec_vprev) {
     const int64_t r = (u - a.rec_base) * (int64_t)a.n_cols * a.npc + j;
     a.rec_vprev[r] = vprev;
     a.rec_caprev[r] = caprev;
@@ -151,7 +153,7 @@ __device__ __forceinline__ bool neuron_step(const StepArgs& a, int64_t j, int64_
                                             int32_t rec_in, int32_t n_ext, float vprev,
                                             float caprev, int32_t rf) {
   const NeuronOut o = neuron_update(a, rec_in, n_ext, vprev, caprev, rf);
-  neuron_store(a, j, u, o, vprev, caprev);
+  neuron_store<true>(a, j, u, o, vprev, caprev);
   return o.spike;
 }
 
@@ -520,7 +522,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       for (int m = 0; m < 4; ++m) {
         if (q0 + m < nch) {
           const int c = col * nch + q0 + m;
-          if (ok[m]) neuron_store(a, (int64_t)g * npc + (q0 + m) * 64 + lane, u, o[m], vv[m], cc[m]);
+          if (ok[m]) neuron_store<TRAIN>(a, (int64_t)g * npc + (q0 + m) * 64 + lane, u, o[m], vv[m], cc[m]);
           const unsigned long long bal = __ballot(o[m].spike);
           if (lane == 0) {
             smask[c] = bal;
@@ -774,6 +776,7 @@ hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
   const bool train = s.wfx != nullptr;
   if (delivery == DPSNN_DELIVERY_ARRIVAL) {
     if (part == 1) return hipSuccess;
+    if (s.rec_on && !train) return hipErrorInvalidValue;  // only the train kernel records
     // Steps inside a gather window (u mod K != 0) are light: their launch reserves one
     // accumulator and uses workgroups of at most 512 threads, so that two tiles share a
     // compute unit and hide each other's latencies.  (Should the window not be valid on
