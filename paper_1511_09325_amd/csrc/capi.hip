@@ -659,7 +659,7 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->ref = (uint8_t*)dalloc(*s, N);
     s->hist_cnt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)s->dh * s->n_cols);
     s->hist_ids = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
-    s->hist_st = (int64_t*)dalloc(*s, sizeof(int64_t) * (size_t)s->dh * s->n_parts * s->npc);
+    s->hist_st = (uint32_t*)dalloc(*s, sizeof(uint32_t) * (size_t)s->dh * s->n_parts * s->npc);
     s->hist_go = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_parts * (s->nd + 1) * s->npc);
     s->net_cnt = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets);
     s->flags = (int32_t*)dalloc(*s, sizeof(int32_t) * 4);

@@ -39,9 +39,10 @@
 //   spike history (shared by both delivery strategies)
 //     hist_cnt  int32 [DH][C]       spikes of column g at step t, in slot t % DH
 //     hist_ids  uint16[DH][C][npc]  their local indices, ascending
-//     hist_st   int64 [DH][P][npc]  per part (P = parts of all columns, part q of column g
+//     hist_st   uint32 [DH][P][npc] per part (P = parts of all columns, part q of column g
 //                                   is col_pfirst[g] + q) and spike position: the start of
-//                                   the spiking neuron's part
+//                                   the spiking neuron's part in 16-byte pieces (parts start
+//                                   on 16-byte boundaries; fewer than 2^32 pieces)
 //     hist_go   uint16[DH][P][nd+1][npc]  its group offsets (copied from the row index when
 //                                   the neuron spiked, so that the readers of one source
 //                                   column's spikes load them contiguously)
@@ -170,7 +171,7 @@ struct StepArgs {
   uint8_t* ref;
   int32_t* hist_cnt;
   uint16_t* hist_ids;
-  int64_t* hist_st;
+  uint32_t* hist_st;
   uint16_t* hist_go;
   // arrival form: steps gathered per window, accumulators of later steps, last gathering
   // step, finished-workgroup counter
@@ -209,7 +210,7 @@ __device__ __forceinline__ void write_entries(const StepArgs& a, int32_t g, int3
   for (int p = 0; p < np; ++p) {
     const uint8_t* ent = idx_entry(a, g, k, p);
     const int64_t pid = (int64_t)slot * a.n_parts + a.col_pfirst[g] + p;
-    a.hist_st[pid * a.npc + pos] = ent_start(ent);
+    a.hist_st[pid * a.npc + pos] = (uint32_t)(ent_start(ent) >> 2);
     const uint16_t* go = ent_goff(ent);
     uint16_t* out = a.hist_go + pid * (int64_t)(a.nd + 1) * a.npc + pos;
     for (int dd = 0; dd <= a.nd; ++dd) out[(int64_t)dd * a.npc] = go[dd];
@@ -273,7 +274,7 @@ struct sim {
   uint8_t* ref = nullptr;
   int32_t* hist_cnt = nullptr;
   uint16_t* hist_ids = nullptr;
-  int64_t* hist_st = nullptr;
+  uint32_t* hist_st = nullptr;
   uint16_t* hist_go = nullptr;
   int32_t gk = 1;                  // steps gathered per window (arrival form)
   int32_t gather_req = 0;          // requested gather_steps (0: automatic)

@@ -381,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
         const int64_t pid = (int64_t)slot * a.n_parts + s_part[si];
         const uint16_t* go = a.hist_go + (pid * (a.nd + 1) + (d - a.d_min)) * npc + pos;
         const int32_t g0 = go[0], g1 = go[npc];
-        gpc = (uint32_t)((a.hist_st[pid * npc + pos] + g0) >> 2);
+        gpc = a.hist_st[pid * npc + pos] + ((uint32_t)g0 >> 2);
         glen = (g1 - g0) >> 2;
         gsb = (d - ag) * TN * 4;
         gsl = s_slots[si];
@@ -595,7 +595,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
 #pragma unroll
       for (int q = 0; q < kIdxWords; ++q) buf[q] = ent[q < nw ? q : nw - 1];
       const int64_t pid = (int64_t)slot_u * a.n_parts + s_cpf[col] + p;
-      a.hist_st[pid * npc + pos] = *(const int64_t*)&buf[0];
+      a.hist_st[pid * npc + pos] = (uint32_t)(*(const int64_t*)&buf[0] >> 2);
       const uint16_t* go = (const uint16_t*)&buf[0] + 4;
       uint16_t* out = a.hist_go + pid * (int64_t)(a.nd + 1) * npc + pos;
 #pragma unroll
