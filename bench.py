@@ -63,7 +63,7 @@ def measured_traffic(workload: str, delivery: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(sample_steps: int = 1000):
+def cpu_baseline(sample_steps: int = 5000):
     """The CPU oracle, as it stands, on a bounded sample of the same workload family: the
     4x4 grid of the same column recipe (19,840 neurons, ~24.6M synapses), seed 0; only its
     step loop is timed (network construction excluded); one thread."""
