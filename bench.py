@@ -86,6 +86,25 @@ def cpu_baseline(sample_steps: int = 5000):
             "sim_ms_per_wall_s": sample_steps / dt}
 
 
+def device_copy_gbs(torch, mib: int = 2048, reps: int = 10) -> float:
+    """Bandwidth of a plain device-to-device copy (bytes read + written per second), the
+    practical HBM ceiling the roofline fraction is also quoted against."""
+    n = (mib << 20) // 4
+    src = torch.empty(n, dtype=torch.int32, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * (mib << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def _timed_run(sim, steps, torch):
     """Run `steps` steps on the simulation's stream; returns (seconds, events, spikes)."""
     s0 = [sim.stats(n) for n in range(sim.n_nets)]
@@ -302,6 +321,7 @@ def main():
         dom_name = "k_step_tile"
     achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, args.delivery)
+    copy_gbs = device_copy_gbs(torch)
 
     out = {
         "metric": "synaptic events/s (recurrent + external) and sim-ms per wall-s",
@@ -330,7 +350,8 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_ms": dom_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "synapse_records_read_per_launch": streamed / K},
+                     "synapse_records_read_per_launch": streamed / K,
+                     "device_copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
     }
     del sim
     torch.cuda.empty_cache()
