@@ -10,8 +10,11 @@
 //     dL/dw_k += nu_{tgt k}(u + d_k) at every spike of k's source,
 //     dL/dP_m += V(u-1) nu(u),   dL/dgamma -= Ca(u-1) nu(u)
 // with sigma'(x) = 1 / (1 + beta |x|)^2 (fast-sigmoid surrogate).  Per reverse step two
-// kernels: k_adj_row (one wave per neuron: the gather over its outgoing row from the ring
-// of future nu, and the weight gradient when it spiked) and k_adj_neuron (the recursion).
+// kernels: the gather over every outgoing row from the ring of future nu (with the weight
+// gradient of the rows whose neuron spiked) and k_adj_neuron (the recursion).  The gather is
+// k_adj_col when every part of a row holds the synapses into one column (single-column
+// native tiles: one workgroup per target column stages that column's future nu in LDS, one
+// lane per part), else k_adj_row (one wave per neuron, nu gathered from the ring).
 // Everything is float32 except the per-neuron float64 partials of the two scalar
 // gradients; every sum has a fixed order, so the result is deterministic.
 #include "dpsnn_internal.h"
@@ -30,6 +33,10 @@ struct AdjArgs {
   float* mu;          // [N]
   double* part;       // [2][N]: dL/dP_m, dL/dgamma partials
   const float* grad_rates;  // [n_cols]
+  const int4* in_part;      // [C][9]: i-th source column of column C: (column, its global part
+                            // into C, its first part, its part count)
+  const int32_t* in_own;    // [C]: position of C itself among its source columns
+  float* psum;              // [parts][npc]: sum over each part (k_adj_col), else null
   float dlds_scale;   // dR_c / ds = 1000 / (npc T dt)
   float beta;
 };
@@ -92,6 +99,180 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
   if (lane == 0) x.gsum[j] = acc;
 }
 
+// Gather by target column (single-column parts).  Workgroup (x, tc): nu of column tc at steps
+// u + d_min .. u + d_max goes to LDS; then groups of LPP lanes take parts into tc (the
+// synapses of one source neuron into tc) and stream them in 16-byte words (lane l of the
+// group: words l, l + LPP, ...), summing w nu per lane in record order and then over the
+// group by a fixed butterfly; where the source neuron spiked at u, nu is added to each
+// synapse's gradient.  The part's sum goes to psum.  A column's own part holds most of a
+// row (the in-column connection probability is the largest), so the first workgroups give
+// a wave to each part of the own column and the rest a quad to each part of a neighbour.
+constexpr int kAdjWords = 4;      // 16-byte words per lane in flight
+constexpr int kAdjOwnPerWave = 16;   // own-column parts per wave
+constexpr int kAdjNbrPerQuad = 8;    // neighbour parts per quad
+
+// One lane's share of a part's stream (see k_adj_col): returns the lane's sum of w nu.
+template <int LPP>
+__device__ __forceinline__ float adj_stream(const AdjArgs& x, const float* nus, int npc,
+                                            int64_t base, int32_t nwords, bool spiked, int gl) {
+  float acc = 0.0f;
+  for (int32_t w0 = gl; w0 < nwords; w0 += LPP * kAdjWords) {
+    uint4 w[kAdjWords];
+    float4 wf[kAdjWords];
+    uint32_t dd4[kAdjWords];
+#pragma unroll
+    for (int m = 0; m < kAdjWords; ++m) {
+      const int32_t wi = w0 + LPP * m;
+      const int64_t r = base + 4 * (int64_t)wi;
+      w[m] = make_uint4(kDummyRecord, kDummyRecord, kDummyRecord, kDummyRecord);
+      wf[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      dd4[m] = 0u;
+      if (wi < nwords) {
+        w[m] = *(const uint4*)(x.a.syn + r);
+        wf[m] = *(const float4*)(x.wf32 + r);
+        dd4[m] = *(const uint32_t*)(x.dly + r);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kAdjWords; ++m) {
+      const uint32_t rw[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
+      const float rf[4] = {wf[m].x, wf[m].y, wf[m].z, wf[m].w};
+      float nu[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        nu[c] = 0.0f;
+        if (rec_rank(rw[c]) != (uint32_t)kDummyRank) {
+          nu[c] = nus[(int)((dd4[m] >> (8 * c)) & 0xffu) * npc + (int)rec_k(rw[c])];
+          acc = acc + rf[c] * nu[c];
+        }
+      }
+      const int32_t wi = w0 + LPP * m;
+      if (spiked && wi < nwords) {
+        float4* gp = (float4*)(x.gw + base + 4 * (int64_t)wi);
+        float4 gv = *gp;
+        gv.x = gv.x + nu[0];
+        gv.y = gv.y + nu[1];
+        gv.z = gv.z + nu[2];
+        gv.w = gv.w + nu[3];
+        *gp = gv;
+      }
+    }
+  }
+  return acc;
+}
+
+// A lane's part, looked up ahead: first record, length in 16-byte words, whether the source
+// neuron spiked at u, and where the part's sum goes.
+struct AdjPart {
+  int64_t base;
+  int32_t nwords;
+  int32_t spiked;
+  int64_t out;
+};
+
+__device__ __forceinline__ AdjPart adj_lookup(const AdjArgs& x, int64_t u, int4 in, int32_t kk) {
+  const StepArgs& a = x.a;
+  const int npc = a.npc;
+  const int64_t nall = (int64_t)a.n_cols * npc;
+  const int32_t src = in.x, q = in.y, pf = in.z, np = in.w;
+  const uint8_t* ent = a.idx + ((int64_t)npc * pf + (int64_t)kk * np + (q - pf)) * a.idxw;
+  AdjPart P;
+  P.base = ent_start(ent) + ent_goff(ent)[0];
+  P.nwords = (ent_goff(ent)[a.nd] - ent_goff(ent)[0]) >> 2;
+  P.spiked = a.rec_flags[(u - a.rec_base) * nall + (int64_t)src * npc + kk] & 1;
+  P.out = (int64_t)q * npc + kk;
+  return P;
+}
+
+// Group of LPP lanes taking PPG parts, one after the other: lane gl < PPG looks up part gl
+// first (all the lookups in one round of loads), then the group streams part r with lane r's
+// lookup, sums over the group by a fixed butterfly and stores the part's sum.
+template <int LPP, int PPG>
+__device__ __forceinline__ void adj_group(const AdjArgs& x, const float* nus, const AdjPart& mine,
+                                          bool mine_ok) {
+  const int lane = threadIdx.x & 63, gl = lane & (LPP - 1), g0 = lane - gl;
+  const int npc = x.a.npc;
+  for (int r = 0; r < PPG; ++r) {
+    const int okr = __shfl((int32_t)mine_ok, g0 + r);
+    if (!okr) break;  // uniform over the group; parts are assigned in order
+    const int64_t base = ((int64_t)__shfl((int32_t)(mine.base >> 32), g0 + r) << 32) |
+                         (uint32_t)__shfl((int32_t)(uint32_t)mine.base, g0 + r);
+    const int32_t nwords = __shfl(mine.nwords, g0 + r);
+    const bool spiked = __shfl(mine.spiked, g0 + r) != 0;
+    float acc = adj_stream<LPP>(x, nus, npc, base, nwords, spiked, gl);
+#pragma unroll
+    for (int off = LPP / 2; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off, LPP);
+    const int64_t out = ((int64_t)__shfl((int32_t)(mine.out >> 32), g0 + r) << 32) |
+                        (uint32_t)__shfl((int32_t)(uint32_t)mine.out, g0 + r);
+    if (gl == 0) x.psum[out] = acc;
+  }
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_adj_col(AdjArgs x, int64_t u, int32_t nbw) {
+  extern __shared__ float nus[];  // [nd][npc]
+  const StepArgs& a = x.a;
+  constexpr int NW = BLOCK / 64, NQ = BLOCK / 4;
+  const int32_t tc = blockIdx.y;
+  const int npc = a.npc, nd = a.nd;
+  const int nn = a.col_nn[tc];
+  const bool own = (int32_t)blockIdx.x < nbw;
+  const int32_t first = own ? (int32_t)blockIdx.x * NW * kAdjOwnPerWave
+                            : ((int32_t)blockIdx.x - nbw) * NQ * kAdjNbrPerQuad;
+  const int32_t nparts = own ? npc : (nn - 1) * npc;
+  if (first >= nparts) return;
+  const int i_own = x.in_own[tc];
+  // this lane's part, looked up before the staging so that the loads overlap
+  const int lane = threadIdx.x & 63;
+  AdjPart mine{0, 0, 0, 0};
+  bool mine_ok = false;
+  if (own) {
+    const int gl = lane;
+    const int32_t kk = first + (threadIdx.x >> 6) * kAdjOwnPerWave + gl;
+    if (gl < kAdjOwnPerWave && kk < npc) {
+      mine = adj_lookup(x, u, x.in_part[tc * kMaxNbr + i_own], kk);
+      mine_ok = true;
+    }
+  } else {
+    const int gl = lane & 3;
+    const int32_t e = first + gl * NQ + (threadIdx.x >> 2);
+    if (e < nparts) {
+      int i = e / npc;
+      const int32_t kk = e - i * npc;
+      if (i >= i_own) ++i;  // skip the own column
+      mine = adj_lookup(x, u, x.in_part[tc * kMaxNbr + i], kk);
+      mine_ok = true;
+    }
+  }
+  // staging, kStage loads in flight per thread; e / npc through a float reciprocal (exact:
+  // e < 2^16)
+  const int64_t nall = (int64_t)a.n_cols * npc;
+  const int32_t slot0 = (int32_t)((u + a.d_min) % a.dh);
+  const float inv_npc = 1.0f / (float)npc;
+  const int32_t ntot = nd * npc;
+  constexpr int kStage = 8;
+  for (int32_t e0 = threadIdx.x; e0 < ntot; e0 += BLOCK * kStage) {
+    float v[kStage];
+#pragma unroll
+    for (int m = 0; m < kStage; ++m) {
+      const int32_t e = e0 + m * BLOCK;
+      v[m] = 0.0f;
+      if (e < ntot) {
+        const int dd = (int)(((float)e + 0.5f) * inv_npc), k = e - dd * npc;
+        int32_t slot = slot0 + dd;
+        if (slot >= a.dh) slot -= a.dh;
+        v[m] = x.nu_ring[(int64_t)slot * nall + (int64_t)tc * npc + k];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kStage; ++m)
+      if (e0 + m * BLOCK < ntot) nus[e0 + m * BLOCK] = v[m];
+  }
+  __syncthreads();
+  if (own) adj_group<64, kAdjOwnPerWave>(x, nus, mine, mine_ok);
+  else adj_group<4, kAdjNbrPerQuad>(x, nus, mine, mine_ok);
+}
+
 // Delay index of every record (train mode): one wave per neuron over its parts and groups.
 __global__ __launch_bounds__(256) void k_fill_dly(StepArgs a, uint8_t* dly) {
   const int lane = threadIdx.x & 63;
@@ -121,9 +302,18 @@ __global__ __launch_bounds__(256) void k_adj_neuron(AdjArgs x, int64_t u) {
     const float s = (fl & 1) ? 1.0f : 0.0f;
     const float vt = a.rec_vt[o];
     const float lam = x.lam[j], mu = x.mu[j];
-    const float dlds = x.grad_rates[j / a.npc] * x.dlds_scale;
+    const int32_t g = (int32_t)(j / a.npc);
+    const float dlds = x.grad_rates[g] * x.dlds_scale;
+    float gsum;
+    if (x.psum) {  // the parts' sums, in part order
+      const int32_t kk = (int32_t)(j - (int64_t)g * a.npc), pf = a.col_pfirst[g];
+      gsum = 0.0f;
+      for (int p = 0; p < a.col_np[g]; ++p) gsum = gsum + x.psum[(int64_t)(pf + p) * a.npc + kk];
+    } else {
+      gsum = x.gsum[j];
+    }
     const float reset_term = lam * (a.k.vreset - vt);
-    const float e = ((dlds + x.gsum[j]) + reset_term) + a.k.alpha * mu;
+    const float e = ((dlds + gsum) + reset_term) + a.k.alpha * mu;
     float nu = 0.0f;
     if (!(fl & 2)) {
       const float den = 1.0f + x.beta * fabsf(vt - a.k.theta);
@@ -268,8 +458,26 @@ hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates,
   x.grad_rates = grad_rates;
   x.dlds_scale = scale;
   x.beta = beta;
-  hipLaunchKernelGGL(k_adj_row, dim3((unsigned)((s.n_neurons + 3) / 4)), dim3(256), 0, s.stream,
-                     x, u);
+  if (s.adj_psum) {
+    static bool lds_set = false;
+    const size_t lds = sizeof(float) * (size_t)s.nd * s.npc;
+    if (!lds_set) {
+      const hipError_t e = hipFuncSetAttribute((const void*)k_adj_col<1024>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+      if (e != hipSuccess) return e;
+      lds_set = true;
+    }
+    x.in_part = (const int4*)s.in_part;
+    x.in_own = s.in_own;
+    x.psum = s.adj_psum;
+    const int nbw = (s.npc + 16 * kAdjOwnPerWave - 1) / (16 * kAdjOwnPerWave);
+    const int nbq = ((kMaxNbr - 1) * s.npc + 256 * kAdjNbrPerQuad - 1) / (256 * kAdjNbrPerQuad);
+    hipLaunchKernelGGL(k_adj_col<1024>, dim3((unsigned)(nbw + nbq), (unsigned)s.n_cols), dim3(1024),
+                       lds, s.stream, x, u, nbw);
+  } else {
+    hipLaunchKernelGGL(k_adj_row, dim3((unsigned)((s.n_neurons + 3) / 4)), dim3(256), 0, s.stream,
+                       x, u);
+  }
   hipLaunchKernelGGL(k_adj_neuron, dim3(grid_of(s.n_neurons, 256)), dim3(256), 0, s.stream, x, u);
   return hipGetLastError();
 }

@@ -609,6 +609,32 @@ void setup_train(sim& s) {
   s.adj_mu = (float*)dalloc(s, sizeof(float) * N);
   s.adj_part = (double*)dalloc(s, sizeof(double) * 2 * N);
   s.adj_out = (double*)dalloc(s, sizeof(double) * 2);
+  // single-column native tiles: every part of a row holds the synapses into one column, and
+  // the reverse gather can run by target column with that column's future nu in LDS
+  if (s.native_tx == 1 && s.native_ty == 1 &&
+      sizeof(float) * (size_t)s.nd * s.npc + 1024 <= kMaxLds) {
+    std::vector<int32_t> pfirst((size_t)s.n_cols + 1, 0), inp((size_t)s.n_cols * kMaxNbr * 4, -1),
+        own((size_t)s.n_cols, -1);
+    for (int32_t g = 0; g < s.n_cols; ++g) pfirst[g + 1] = pfirst[g] + s.h_np[g];
+    for (int32_t tc = 0; tc < s.n_cols; ++tc)
+      for (int i = 0; i < s.h_nn[tc]; ++i) {
+        const int32_t src = s.h_nbr[(size_t)tc * kMaxNbr + i];
+        int r = 0;
+        while (r < s.h_nn[src] && s.h_nbr[(size_t)src * kMaxNbr + r] != tc) ++r;
+        if (r == s.h_nn[src]) throw Fail{DPSNN_EINVAL, "column neighbourhoods are not symmetric"};
+        int32_t* e = &inp[((size_t)tc * kMaxNbr + i) * 4];
+        e[0] = src;
+        e[1] = pfirst[src] + s.h_part[(size_t)src * kMaxNbr + r];
+        e[2] = pfirst[src];
+        e[3] = s.h_np[src];
+        if (src == tc) own[tc] = i;
+      }
+    for (int32_t tc = 0; tc < s.n_cols; ++tc)
+      if (own[tc] < 0) throw Fail{DPSNN_EINVAL, "a column is not among its own neighbours"};
+    s.in_part = upload(s, inp);
+    s.in_own = upload(s, own);
+    s.adj_psum = (float*)dalloc(s, sizeof(float) * (size_t)s.n_idx);
+  }
   s.rec_steps = s.cfg.ckpt_every;
   const size_t rn = (size_t)s.rec_steps * N;
   s.rec_vprev = (float*)dalloc(s, sizeof(float) * rn);

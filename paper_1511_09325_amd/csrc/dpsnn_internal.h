@@ -307,6 +307,11 @@ struct sim {
   float* nu_ring = nullptr;        // [dh][N] adjoint of V~ of the last dh steps
   float *adj_gsum = nullptr, *adj_lam = nullptr, *adj_mu = nullptr;
   double* adj_part = nullptr;      // [2][N]
+  int32_t* in_part = nullptr;      // [C][9][4] single-column parts: the i-th source column
+                                   // of column C, its global part into C, its first part and
+                                   // part count (null otherwise)
+  int32_t* in_own = nullptr;       // [C] position of C among its own source columns
+  float* adj_psum = nullptr;       // [parts][npc] adjoint gather per part (with in_part)
   double* adj_out = nullptr;       // [2]
   int64_t* canon_start = nullptr;  // [N+1] first canonical synapse index of each row
   std::vector<dpsnn::Snapshot> ckpts;  // state at steps 0, K, 2K, ... of the recorded window
