@@ -262,6 +262,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
   __shared__ int32_t s_cpf[kMaxTileCols];       // first part index of each column
   __shared__ int32_t s_tot[kMaxTileCols];       // spikes of each column at this step
   __shared__ int32_t s_epre[kMaxTileCols + 1];  // prefix of (parts x spikes) over columns
+  __shared__ int32_t s_next_bt;                 // next batch of the gather to be taken
   __shared__ int32_t wsum[2 * NW + 1];
   __shared__ unsigned long long red5[5][NW];
   const int tid = threadIdx.x;
@@ -340,6 +341,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
       carry += tot;
     }
     if (tid == 0) it_pref[n_items] = carry;
+    if (tid == 0) s_next_bt = NW;
     if (tid < kPoissonEntries) ptab[tid] = ptab_q;
     if (tid < 2) s_key[tid] = key_q;
     __syncthreads();
@@ -355,7 +357,10 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
     uint32_t dwave = 0;  // records delivered by the wave (uniform)
     // exact small-integer quotients through float reciprocals (operands < 2^16)
     const float inv_nb = 1.0f / (float)NB;
-    for (int32_t bt = wave; bt * 64 < total; bt += NW) {
+    for (int32_t bt = wave; bt * 64 < total;) {
+      // the wave's next batch, taken now so that the atomic's latency hides under this one
+      int32_t bt_next = 0;
+      if (lane == 0) bt_next = atomicAdd(&s_next_bt, 1);
       const int32_t qq = bt * 64 + lane;
       // this lane's group: first 16-byte piece, length in pieces, the offset of the
       // accumulator of its step and its pair's slot word
@@ -442,6 +447,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, 
           }
         }
       }
+      bt = __shfl(bt_next, 0);
     }
     delivered = lane == 0 ? dwave : 0u;
     __syncthreads();
