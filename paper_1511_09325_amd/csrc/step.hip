@@ -87,15 +87,15 @@ __device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long x
   return all;
 }
 
-// Number of thresholds <= x (the thresholds are non-decreasing).
+// Number of thresholds <= x (the thresholds are non-decreasing): a branch-free binary search
+// of fixed depth, so that the searches of several neurons interleave.
+static_assert(kPoissonEntries == 63, "six halvings cover the 63 thresholds");
 __device__ __forceinline__ int32_t poisson_count(const uint64_t* tab, uint32_t x) {
-  int lo = 0, hi = kPoissonEntries;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (tab[mid] <= (uint64_t)x) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
+  int pos = 0;
+#pragma unroll
+  for (int step = 32; step > 0; step >>= 1)
+    if (tab[pos + step - 1] <= (uint64_t)x) pos += step;
+  return pos;
 }
 
 // One neuron's step from its state and input (no memory access).
@@ -245,7 +245,9 @@ __device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
 static_assert(kPoissonEntries <= 64, "one Poisson threshold per lane of the first wave");
 
 template <int BLOCK, bool TRAIN>
-__global__ __launch_bounds__(BLOCK) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc,
+// At least four waves per SIMD for every workgroup size (at most 128 VGPRs), so that two
+// 512-thread workgroups of the steps inside a window share a compute unit.
+__global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc,
                                                      int32_t kacc) {
   const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
   constexpr int NW = BLOCK / 64;
