@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
 // a wave to each part of the own column and the rest a quad to each part of a neighbour.
 constexpr int kAdjWords = 4;      // 16-byte words per lane in flight
 constexpr int kAdjOwnPerWave = 16;   // own-column parts per wave
-constexpr int kAdjNbrPerQuad = 8;    // neighbour parts per quad
+constexpr int kAdjNbrPerQuad = 4;    // neighbour parts per quad (one looked up per lane)
 
 // One lane's share of a part's stream (see k_adj_col): returns the lane's sum of w nu.
 template <int LPP>
@@ -190,6 +190,7 @@ __device__ __forceinline__ AdjPart adj_lookup(const AdjArgs& x, int64_t u, int4 
 template <int LPP, int PPG>
 __device__ __forceinline__ void adj_group(const AdjArgs& x, const float* nus, const AdjPart& mine,
                                           bool mine_ok) {
+  static_assert(PPG <= LPP, "each lane of a group looks up one of its parts");
   const int lane = threadIdx.x & 63, gl = lane & (LPP - 1), g0 = lane - gl;
   const int npc = x.a.npc;
   for (int r = 0; r < PPG; ++r) {

@@ -113,7 +113,10 @@ def test_weights_round_trip_and_forward_uses_them():
     (W.tiny(3, 4, npc=50, seed=6, ext_rate_hz=3.4), 150, 40, DELIVERY_ARRIVAL, (2, 3)),
     (W.tiny(2, 3, npc=40, seed=9, d_min=2, d_max=6, ext_rate_hz=3.6), 90, 7, DELIVERY_PUSH,
      (0, 0)),
-], ids=["2x2-K16", "3x4-K40-tile2x3", "2x3-d2..6-K7-push"])
+    # 160-neuron columns: the 8 x 160 parts into the centre column from its neighbours fill
+    # more than one workgroup of the column-wise reverse gather, four parts per quad
+    (W.tiny(3, 3, npc=160, seed=11, ext_rate_hz=3.4), 60, 20, DELIVERY_ARRIVAL, (0, 0)),
+], ids=["2x2-K16", "3x4-K40-tile2x3", "2x3-d2..6-K7-push", "3x3-npc160-K20"])
 def test_gpu_adjoint_matches_fp64_oracle(p, T, K, delivery, tile):
     C = p["rows"] * p["cols"]
     sim = Simulation(p, train_mode=True, ckpt_every=K, surrogate_beta=BETA, delivery=delivery,
