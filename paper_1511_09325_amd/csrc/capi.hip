@@ -634,6 +634,7 @@ void setup_train(sim& s) {
     s.in_part = upload(s, inp);
     s.in_own = upload(s, own);
     s.adj_psum = (float*)dalloc(s, sizeof(float) * (size_t)s.n_idx);
+    HIPCHK(hipMemsetAsync(s.adj_psum, 0, sizeof(float) * (size_t)s.n_idx, s.stream));
   }
   s.rec_steps = s.cfg.ckpt_every;
   const size_t rn = (size_t)s.rec_steps * N;
