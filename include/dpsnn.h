@@ -208,7 +208,9 @@ int sim_set_params(sim_t* sim, double tau_m, double g_ahp);
  * store is split by the tiling chosen at creation; other tilings work but read more. */
 typedef struct {
   int32_t delivery;  /* DPSNN_DELIVERY_ARRIVAL or DPSNN_DELIVERY_PUSH */
-  int32_t block;     /* 64, 128, 256, 512 or 1024 */
+  int32_t block;     /* 64, 128, 256, 512 or 1024 (arrival form: the gathering steps; the
+                        steps inside a gather window launch with at most 512 threads and one
+                        accumulator, two workgroups per compute unit) */
   int32_t tile_x, tile_y;  /* 1..4 */
   int32_t graph_steps;     /* steps per captured HIP graph, replayed by sim_step; 0 = direct */
   int32_t gather_steps;    /* arrival form: steps whose input one pass over the spike history
