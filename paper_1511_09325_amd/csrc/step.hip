@@ -194,8 +194,10 @@ __device__ __forceinline__ int32_t item_delays(const StepArgs& a, bool light, in
 // gathering step.  Workgroups start in index order as compute units free up, so the largest
 // tiles start first and the smallest fill the end (longest-first list scheduling); the spread
 // of work between tiles follows the spatial spread of firing rates.  A counting sort over
-// BLOCK buckets of the work scaled to the largest.  Run by one workgroup, after every other
-// workgroup of the launch has finished; the results do not depend on the order.
+// BLOCK buckets of the work scaled to the largest.  Workgroup b runs on XCD b mod 8, so the
+// ranks are dealt to the XCDs in a snake (ranks 8k .. 8k + 7 to XCDs 0..7 for even k, 7..0
+// for odd k), which keeps their shares of the work even.  Run by one workgroup, after every
+// other workgroup of the launch has finished; the results do not depend on the order.
 template <int BLOCK>
 __device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
   constexpr int NW = BLOCK / 64;
@@ -224,7 +226,9 @@ __device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
   __syncthreads();
   for (int32_t t = tid; t < a.n_tiles; t += BLOCK) {
     const uint32_t w = __hip_atomic_load(&a.tile_work[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a.tile_order[atomicAdd(&cnt[BLOCK - 1 - (int)((uint64_t)w * BLOCK / den)], 1)] = t;
+    int32_t pos = atomicAdd(&cnt[BLOCK - 1 - (int)((uint64_t)w * BLOCK / den)], 1);
+    if (((pos >> 3) & 1) && pos < (a.n_tiles & ~7)) pos ^= 7;  // odd full blocks of 8 reversed
+    a.tile_order[pos] = t;
   }
   for (int32_t b = a.n_tiles + tid; b < a.grid_tiles; b += BLOCK) a.tile_order[b] = -1;
 }
