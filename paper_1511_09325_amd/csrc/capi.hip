@@ -671,7 +671,7 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->npc = cfg->npc;
     s->nd = cfg->d_max - cfg->d_min + 1;
     s->dh = cfg->d_max + 1;
-    s->idxw = (8 + 2 * (s->nd + 1) + 15) & ~15;
+    s->idxw = (8 + 2 * (s->nd + 2) + 15) & ~15;
     s->delivery = cfg->delivery == DPSNN_DELIVERY_PUSH ? DPSNN_DELIVERY_PUSH : DPSNN_DELIVERY_ARRIVAL;
     s->block = cfg->block ? cfg->block : default_block(s->delivery);
     set_constants(*s);

@@ -11,7 +11,8 @@
 //   A synapse's target column is identified by its rank r in the source column's sorted
 //   list of distinct neighbour columns (at most 9: the 3x3 torus stencil)
 //     idx       idxw bytes per (neuron, part): int64 start of the part, then uint16
-//               goff[nd + 1]; group dd (delay d_min + dd) is [start + goff[dd], start +
+//               goff[nd + 1], then the uint16 count of the part's synapses (without the
+//               padding); group dd (delay d_min + dd) is [start + goff[dd], start +
 //               goff[dd + 1]).  Entry of (column g, neuron k, part p): col_pbase[g] +
 //               k * col_np[g] + p.  The parts of one neuron are contiguous (row_base[i])
 //     syn       uint32[S' + 4]: k (bits 0-11, target index inside its column) | r (bits

@@ -187,12 +187,16 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
     __builtin_amdgcn_wave_barrier();
     const int64_t rb = a.row_base[i];
     uint32_t* out = a.syn + rb;
-    // row-index entries of the parts: start of the part, then the start of each group
+    // row-index entries of the parts: start of the part, the start of each group, then the
+    // number of the part's synapses (without the padding)
     for (int p = 0; p < np; ++p) {
       uint8_t* ent = a.idx + (a.col_pbase[g] + (int64_t)kk * np + p) * a.idxw;
       const int32_t p0 = L.gst[p][0];
       if (lane == 0) *(int64_t*)ent = rb + p0;
       for (int dd = lane; dd <= a.nd; dd += 64) ((uint16_t*)(ent + 8))[dd] = (uint16_t)(L.gst[p][dd] - p0);
+      int32_t real = lane < a.nd ? L.pad[p][lane] - L.gst[p][lane] : 0;
+      for (int off = 32; off > 0; off >>= 1) real += __shfl_down(real, off);
+      if (lane == 0) ((uint16_t*)(ent + 8))[a.nd + 1] = (uint16_t)real;
     }
     // dummy records (rank 9, weight 0) in the padding at the end of each group
     for (int p = 0; p < np; ++p)

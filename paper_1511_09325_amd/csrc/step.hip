@@ -32,7 +32,7 @@ namespace {
 constexpr int kMaxItems = kMaxTilePairs * kMaxDelay;
 static_assert(kMaxItems + 1 >= 1024, "the tile order's buckets reuse the item prefix array");
 constexpr int kPIF = 4;               // 16-byte synapse loads per lane in flight
-constexpr int kIdxWords = (8 + 2 * (kMaxDelay + 1) + 15) / 16;  // 16-byte words of an entry
+constexpr int kIdxWords = (8 + 2 * (kMaxDelay + 2) + 15) / 16;  // 16-byte words of an entry
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -478,10 +478,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
       const int col = rd / nr, q0 = (rd - col * nr) * 4;
       const int32_t g = s_col[col];
       float vv[4], cc[4];
-      int32_t rr[4], nx[4], sv[4], dg[4];
+      int32_t rr[4], nx[4], sv[4];
       bool ok[4];
-      // every global load of the round first, so that their latencies overlap: state, out
-      // degree (for the emitted-events counter) and, at a light step, the saved input
+      // every global load of the round first, so that their latencies overlap: state and, at
+      // a light step, the saved input
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         const int k = (q0 + m) * 64 + lane;
@@ -490,13 +490,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         cc[m] = 0.0f;
         rr[m] = 0;
         sv[m] = 0;
-        dg[m] = 0;
         if (ok[m]) {
           const int64_t j = (int64_t)g * npc + k;
           vv[m] = a.v[j];
           cc[m] = a.ca[j];
           rr[m] = a.ref[j];
-          dg[m] = a.deg[j];
           if (light) sv[m] = a.acc_save[light_save + j];
         }
       }
@@ -528,7 +526,6 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         o[m] = neuron_update(a, in, nx[m], vv[m], cc[m], rr[m]);
         o[m].spike = o[m].spike && ok[m];
         if (ok[m]) my_ext += (unsigned long long)nx[m];
-        if (o[m].spike) my_rec += (unsigned long long)dg[m];
       }
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -611,8 +608,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
       const uint16_t* go = (const uint16_t*)&buf[0] + 4;
       uint16_t* out = a.hist_go + pid * (int64_t)(a.nd + 1) * npc + pos;
 #pragma unroll
-      for (int f = 0; f <= kMaxDelay; ++f)
+      for (int f = 0; f <= kMaxDelay + 1; ++f) {
         if (f <= a.nd) out[(int64_t)f * npc] = go[f];
+        if (f == a.nd + 1) my_rec += (unsigned long long)go[f];  // the part's synapses
+      }
     }
     // the tile's counters: wave sums, then one sum per counter
     unsigned long long cv[5] = {my_spk, my_rec, my_ext, streamed, (unsigned long long)delivered};
