@@ -460,14 +460,7 @@ hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates,
   x.dlds_scale = scale;
   x.beta = beta;
   if (s.adj_psum) {
-    static bool lds_set = false;
     const size_t lds = sizeof(float) * (size_t)s.nd * s.npc;
-    if (!lds_set) {
-      const hipError_t e = hipFuncSetAttribute((const void*)k_adj_col<1024>,
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-      if (e != hipSuccess) return e;
-      lds_set = true;
-    }
     x.in_part = (const int4*)s.in_part;
     x.in_own = s.in_own;
     x.psum = s.adj_psum;
@@ -481,6 +474,12 @@ hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates,
   }
   hipLaunchKernelGGL(k_adj_neuron, dim3(grid_of(s.n_neurons, 256)), dim3(256), 0, s.stream, x, u);
   return hipGetLastError();
+}
+
+// Allow the column-wise reverse gather the dynamic LDS beyond 64 KB (its nu staging).
+hipError_t prepare_adjoint_kernels() {
+  return hipFuncSetAttribute((const void*)k_adj_col<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kMaxLds);
 }
 
 hipError_t launch_reduce_parts(const sim& s, double* out) {

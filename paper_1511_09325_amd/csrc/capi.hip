@@ -633,6 +633,7 @@ void setup_train(sim& s) {
       if (own[tc] < 0) throw Fail{DPSNN_EINVAL, "a column is not among its own neighbours"};
     s.in_part = upload(s, inp);
     s.in_own = upload(s, own);
+    HIPCHK(prepare_adjoint_kernels());
     s.adj_psum = (float*)dalloc(s, sizeof(float) * (size_t)s.n_idx);
     HIPCHK(hipMemsetAsync(s.adj_psum, 0, sizeof(float) * (size_t)s.n_idx, s.stream));
   }

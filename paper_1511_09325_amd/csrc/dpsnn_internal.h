@@ -364,6 +364,7 @@ hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1,
 hipError_t launch_quantise(const sim& s);
 hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates, float scale,
                                float beta);
+hipError_t prepare_adjoint_kernels();
 hipError_t launch_reduce_parts(const sim& s, double* out);
 hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst);
 hipError_t launch_weights_from_records(const sim& s);
