@@ -353,12 +353,14 @@ __global__ __launch_bounds__(1024) void k_reduce_parts(const double* part, int64
 }
 
 // Canonical synapse order (per source neuron: the real records sorted by (delay, target))
-// <-> the padded device layout.  mode 0: dst_padded[p] = src_canon[c]; mode 1: the reverse.
+// <-> the padded device layout.  mode 0: dst_padded[p] = src_canon[c]; mode 1: the reverse;
+// mode 2: rel[p] = c - canon_start[row] (the permutation that k_canon_apply replays).
 // Padding records receive 0 in mode 0.  One wave per neuron: the counts of its synapses per
 // (delay, rank) give the canonical start of every (delay, rank) run; inside a device group
 // (part, delay) the runs of the part's ranks follow each other in rank order.
 __global__ __launch_bounds__(256) void k_canon_map(StepArgs a, const int64_t* canon_start,
-                                                   int mode, const float* src, float* dst) {
+                                                   int mode, const float* src, float* dst,
+                                                   uint16_t* rel) {
   __shared__ int32_t cnt[4][kMaxDelay * kMaxNbr];
   __shared__ int64_t cst[4][kMaxDelay * kMaxNbr];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -406,10 +408,34 @@ __global__ __launch_bounds__(256) void k_canon_map(StepArgs a, const int64_t* ca
             if (part[r2] == p) run0 += cnt[wave][dd * kMaxNbr + r2];
           const int64_t c = cst[wave][dd * kMaxNbr + (int)r] + (f - run0);
           if (mode == 0) dst[st + f] = src[c];
-          else dst[c] = src[st + f];
+          else if (mode == 1) dst[c] = src[st + f];
+          else rel[st + f] = (uint16_t)(c - canon_start[i]);
         }
     }
     __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// The same maps from the stored permutation: one wave per row, its padded records in order
+// (the parts of a row are contiguous); rel 0xffff marks padding.
+static_assert((int64_t)kMaxNbr * kMaxNpc < 0xffff, "a row's canonical offsets fit 16 bits");
+__global__ __launch_bounds__(256) void k_canon_apply(const int64_t* row_base,
+                                                     const int64_t* canon_start,
+                                                     const uint16_t* rel, int64_t n_rows,
+                                                     int mode, const float* src, float* dst) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n_rows;
+       i += (int64_t)gridDim.x * 4) {
+    const int64_t r0 = row_base[i], r1 = row_base[i + 1], c0 = canon_start[i];
+    for (int64_t q = r0 + lane; q < r1; q += 64) {
+      const uint32_t o = rel[q];
+      if (o == 0xffffu) {
+        if (mode == 0) dst[q] = 0.0f;
+        continue;
+      }
+      if (mode == 0) dst[q] = src[c0 + o];
+      else dst[c0 + o] = src[q];
+    }
   }
 }
 
@@ -489,9 +515,21 @@ hipError_t launch_reduce_parts(const sim& s, double* out) {
 }
 
 hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst) {
+  if (s.canon_rel) {
+    hipLaunchKernelGGL(k_canon_apply, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream,
+                       s.row_base, s.canon_start, s.canon_rel, s.n_neurons, mode, src, dst);
+    return hipGetLastError();
+  }
   const StepArgs a = make_step_args(s);
   hipLaunchKernelGGL(k_canon_map, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a,
-                     s.canon_start, mode, src, dst);
+                     s.canon_start, mode, src, dst, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_canon_perm(const sim& s, uint16_t* rel) {
+  const StepArgs a = make_step_args(s);
+  hipLaunchKernelGGL(k_canon_map, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a,
+                     s.canon_start, 2, nullptr, nullptr, rel);
   return hipGetLastError();
 }
 

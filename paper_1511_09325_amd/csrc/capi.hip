@@ -603,6 +603,12 @@ void setup_train(sim& s) {
   HIPCHK(hipMemsetAsync(s.wfx, 0, sizeof(int32_t) * sp, s.stream));
   HIPCHK(launch_weights_from_records(s));
   HIPCHK(launch_quantise(s));
+  // the canonical order of the weights as a stored permutation (2 B per record), so that the
+  // weight and gradient exchanges of every iteration are plain gathers and scatters
+  uint16_t* rel = (uint16_t*)dalloc(s, sizeof(uint16_t) * sp);
+  HIPCHK(hipMemsetAsync(rel, 0xff, sizeof(uint16_t) * sp, s.stream));
+  HIPCHK(launch_canon_perm(s, rel));
+  s.canon_rel = rel;
   s.nu_ring = (float*)dalloc(s, sizeof(float) * (size_t)s.dh * N);
   s.adj_gsum = (float*)dalloc(s, sizeof(float) * N);
   s.adj_lam = (float*)dalloc(s, sizeof(float) * N);
@@ -832,7 +838,24 @@ int sim_step(sim_t* s, int64_t n_steps) {
     int64_t left = n_steps;
     while (left > 0) {
       if (s->wfx) {  // train mode: direct launches, a checkpoint every ckpt_every steps
-        direct_step(*s, marks, ev_used);
+        // the trajectory of the current segment is recorded on the way, so that the reverse
+        // pass need not re-run the last segment when the recording covers all of it
+        const int64_t u = s->now, seg = u - u % s->cfg.ckpt_every;
+        if (s->rec_base != seg || s->fwd_rec_to != u || s->fwd_rec_epoch != s->epoch) {
+          s->rec_base = seg;
+          s->fwd_rec_from = u;
+          s->fwd_rec_epoch = s->epoch;
+        }
+        s->fwd_rec_to = -1;
+        s->rec_on = true;
+        try {
+          direct_step(*s, marks, ev_used);
+        } catch (...) {
+          s->rec_on = false;
+          throw;
+        }
+        s->rec_on = false;
+        s->fwd_rec_to = u + 1;
         left -= 1;
         if (s->now % s->cfg.ckpt_every == 0) {
           save_into_ckpt(*s, (size_t)(s->now / s->cfg.ckpt_every));
@@ -1289,7 +1312,8 @@ int sim_column_rates(sim_t* s, float* rates) {
 
 // Reverse pass over the recorded window [0, T): the end state is set aside, then for each
 // checkpoint segment from the last to the first the forward is re-run from its checkpoint
-// with the trajectory recorded, and the adjoint recursion runs backwards through it.  The
+// with the trajectory recorded (the last segment only when the forward's own recording does
+// not hold all of it), and the adjoint recursion runs backwards through it.  The
 // adjoint ring carries nu across segment boundaries.  Finally the end state comes back.
 int sim_backward(sim_t* s, const float* grad_rates, float* grad_w, double* grad_tau_m,
                  double* grad_g_ahp) {
@@ -1318,22 +1342,28 @@ int sim_backward(sim_t* s, const float* grad_rates, float* grad_w, double* grad_
     s->timing = false;
     std::vector<std::pair<int, size_t>> marks;
     size_t ev_used = 0;
+    // the forward's own recording serves the last segment when it covers all of it
+    const bool have_last = s->rec_base == (M - 1) * K && s->fwd_rec_from == s->rec_base &&
+                           s->fwd_rec_to == T && s->fwd_rec_epoch == s->epoch;
+    s->fwd_rec_to = -1;  // the recording buffers are rewritten below
     for (int64_t m = M - 1; m >= 0; --m) {
       const int64_t u0 = m * K, u1 = std::min(T, u0 + K);
-      restore_from(*s, s->ckpts[(size_t)m]);
-      s->rec_on = true;
-      s->recompute = true;
-      s->rec_base = u0;
-      try {
-        while (s->now < u1) direct_step(*s, marks, ev_used);
-      } catch (...) {
+      if (!(m == M - 1 && have_last)) {
+        restore_from(*s, s->ckpts[(size_t)m]);
+        s->rec_on = true;
+        s->recompute = true;
+        s->rec_base = u0;
+        try {
+          while (s->now < u1) direct_step(*s, marks, ev_used);
+        } catch (...) {
+          s->rec_on = false;
+          s->recompute = false;
+          s->timing = timing;
+          throw;
+        }
         s->rec_on = false;
         s->recompute = false;
-        s->timing = timing;
-        throw;
       }
-      s->rec_on = false;
-      s->recompute = false;
       s->rec_base = u0;
       for (int64_t u = u1 - 1; u >= u0; --u)
         HIPCHK(launch_adjoint_step(*s, u, grad_rates, scale, (float)s->cfg.surrogate_beta));

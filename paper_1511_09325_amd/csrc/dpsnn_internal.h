@@ -303,6 +303,9 @@ struct sim {
   int64_t rec_steps = 0;
   int64_t rec_base = 0;
   bool rec_on = false;
+  // the train-mode forward records its current checkpoint segment as it steps: steps
+  // [fwd_rec_from, fwd_rec_to) of the segment at rec_base, in window epoch fwd_rec_epoch
+  int64_t fwd_rec_from = -1, fwd_rec_to = -1, fwd_rec_epoch = -1;
   float* gw = nullptr;             // weight gradient, padded layout
   uint8_t* dly8 = nullptr;         // delay index of each record, padded layout
   float* nu_ring = nullptr;        // [dh][N] adjoint of V~ of the last dh steps
@@ -315,6 +318,8 @@ struct sim {
   float* adj_psum = nullptr;       // [parts][npc] adjoint gather per part (with in_part)
   double* adj_out = nullptr;       // [2]
   int64_t* canon_start = nullptr;  // [N+1] first canonical synapse index of each row
+  uint16_t* canon_rel = nullptr;   // [S'+4] canonical index of each record minus its row's
+                                   // canon_start (0xffff: padding)
   std::vector<dpsnn::Snapshot> ckpts;  // state at steps 0, K, 2K, ... of the recorded window
   dpsnn::Snapshot bwd_end;             // state at the end of the window during sim_backward
   int64_t epoch = 0;               // recorded-window counter (rewind, weight or parameter change)
@@ -367,6 +372,7 @@ hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates,
 hipError_t prepare_adjoint_kernels();
 hipError_t launch_reduce_parts(const sim& s, double* out);
 hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst);
+hipError_t launch_canon_perm(const sim& s, uint16_t* rel);
 hipError_t launch_weights_from_records(const sim& s);
 hipError_t launch_column_rates(const sim& s, float scale, float* rates);
 hipError_t launch_fill_entries(const sim& s);

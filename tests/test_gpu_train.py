@@ -187,6 +187,28 @@ def test_backward_restores_the_end_state_and_is_repeatable():
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
 
 
+@pytest.mark.parametrize("restore_at", [60, 50, 63])
+def test_restore_inside_the_window_keeps_the_gradient(restore_at):
+    """The forward records its last checkpoint segment as it goes and the reverse pass uses
+    that recording instead of re-running the segment; a restore to an earlier step of the same
+    window (inside the segment, at its start, or past it) must leave the gradient unchanged."""
+    import torch
+    p = W.tiny(2, 3, npc=40, seed=23, ext_rate_hz=3.4)
+    T, K = 70, 50
+    gr = torch.tensor(_targets(6, seed=5).astype(np.float32) - 5.0, device="cuda")
+    ref = Simulation(p, train_mode=True, ckpt_every=K, surrogate_beta=BETA)
+    ref.step(T)
+    want = ref.backward(gr)
+    sim = Simulation(p, train_mode=True, ckpt_every=K, surrogate_beta=BETA)
+    sim.step(restore_at)
+    sim.save(1)
+    sim.step(T - restore_at)
+    sim.restore(1)
+    sim.step(T - restore_at)
+    got = sim.backward(gr)
+    assert torch.equal(got[0], want[0]) and got[1:] == want[1:]
+
+
 def test_broken_window_is_refused_until_rewind():
     import torch
     p = W.tiny(2, 2, npc=40, seed=3)
