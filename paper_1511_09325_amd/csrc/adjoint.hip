@@ -27,7 +27,8 @@ struct AdjArgs {
   const float* wf32;
   float* gw;
   float* nu_ring;     // [dh][N]
-  const uint8_t* dly; // [S'] delay index of each record
+  const uint8_t* dlyw; // [S'/4] delay index of each 16-byte word of records (groups are
+                       // padded to whole words, so the four records of a word share it)
   float* gsum;        // [N]
   float* lam;         // [N]
   float* mu;          // [N]
@@ -45,7 +46,7 @@ constexpr int kAdjUnroll = 8;  // records per lane in flight
 
 // One wave per neuron.  The whole row (all parts, contiguous in the store) is streamed 64 x
 // kAdjUnroll records at a time with each record's delay index from the train-mode delay
-// array, which selects the slot of the adjoint ring.
+// array (one byte per 16-byte word), which selects the slot of the adjoint ring.
 __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
   const StepArgs& a = x.a;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
       if (f < rlen) {
         w[i] = a.syn[rb + f];
         wf[i] = x.wf32[rb + f];
-        dd[i] = x.dly[rb + f];
+        dd[i] = x.dlyw[(rb + f) >> 2];
       }
     }
     float nu[kAdjUnroll];
@@ -119,18 +120,18 @@ __device__ __forceinline__ float adj_stream(const AdjArgs& x, const float* nus, 
   for (int32_t w0 = gl; w0 < nwords; w0 += LPP * kAdjWords) {
     uint4 w[kAdjWords];
     float4 wf[kAdjWords];
-    uint32_t dd4[kAdjWords];
+    int32_t ddw[kAdjWords];
 #pragma unroll
     for (int m = 0; m < kAdjWords; ++m) {
       const int32_t wi = w0 + LPP * m;
       const int64_t r = base + 4 * (int64_t)wi;
       w[m] = make_uint4(kDummyRecord, kDummyRecord, kDummyRecord, kDummyRecord);
       wf[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      dd4[m] = 0u;
+      ddw[m] = 0;
       if (wi < nwords) {
         w[m] = *(const uint4*)(x.a.syn + r);
         wf[m] = *(const float4*)(x.wf32 + r);
-        dd4[m] = *(const uint32_t*)(x.dly + r);
+        ddw[m] = x.dlyw[r >> 2];
       }
     }
 #pragma unroll
@@ -142,7 +143,7 @@ __device__ __forceinline__ float adj_stream(const AdjArgs& x, const float* nus, 
       for (int c = 0; c < 4; ++c) {
         nu[c] = 0.0f;
         if (rec_rank(rw[c]) != (uint32_t)kDummyRank) {
-          nu[c] = nus[(int)((dd4[m] >> (8 * c)) & 0xffu) * npc + (int)rec_k(rw[c])];
+          nu[c] = nus[ddw[m] * npc + (int)rec_k(rw[c])];
           acc = acc + rf[c] * nu[c];
         }
       }
@@ -274,8 +275,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_col(AdjArgs x, int64_t u, int32_t
   else adj_group<4, kAdjNbrPerQuad>(x, nus, mine, mine_ok);
 }
 
-// Delay index of every record (train mode): one wave per neuron over its parts and groups.
-__global__ __launch_bounds__(256) void k_fill_dly(StepArgs a, uint8_t* dly) {
+// Delay index of every 16-byte word of records (train mode): one wave per neuron over its
+// parts and groups (parts and groups start on whole words).
+__global__ __launch_bounds__(256) void k_fill_dly(StepArgs a, uint8_t* dlyw) {
   const int lane = threadIdx.x & 63;
   const int64_t nall = (int64_t)a.n_cols * a.npc;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nall;
@@ -287,7 +289,8 @@ __global__ __launch_bounds__(256) void k_fill_dly(StepArgs a, uint8_t* dly) {
       const int64_t st = ent_start(ent);
       const uint16_t* go = ent_goff(ent);
       for (int d = 0; d < a.nd; ++d)
-        for (int32_t f = go[d] + lane; f < go[d + 1]; f += 64) dly[st + f] = (uint8_t)d;
+        for (int32_t f = go[d] + 4 * lane; f < go[d + 1]; f += 4 * 64)
+          dlyw[(st + f) >> 2] = (uint8_t)d;
     }
   }
 }
@@ -477,7 +480,7 @@ hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates,
   x.wf32 = s.wf32;
   x.gw = s.gw;
   x.nu_ring = s.nu_ring;
-  x.dly = s.dly8;
+  x.dlyw = s.dlyw;
   x.gsum = s.adj_gsum;
   x.lam = s.adj_lam;
   x.mu = s.adj_mu;
@@ -535,7 +538,7 @@ hipError_t launch_canon_perm(const sim& s, uint16_t* rel) {
 
 hipError_t launch_fill_dly(const sim& s) {
   const StepArgs a = make_step_args(s);
-  hipLaunchKernelGGL(k_fill_dly, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a, s.dly8);
+  hipLaunchKernelGGL(k_fill_dly, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a, s.dlyw);
   return hipGetLastError();
 }
 

@@ -596,8 +596,8 @@ void setup_train(sim& s) {
   s.wf32 = (float*)dalloc(s, sizeof(float) * sp);
   s.wfx = (int32_t*)dalloc(s, sizeof(int32_t) * sp);
   s.gw = (float*)dalloc(s, sizeof(float) * sp);
-  s.dly8 = (uint8_t*)dalloc(s, sp);
-  HIPCHK(hipMemsetAsync(s.dly8, 0, sp, s.stream));
+  s.dlyw = (uint8_t*)dalloc(s, sp / 4 + 1);
+  HIPCHK(hipMemsetAsync(s.dlyw, 0, sp / 4 + 1, s.stream));
   HIPCHK(launch_fill_dly(s));
   HIPCHK(hipMemsetAsync(s.wf32, 0, sizeof(float) * sp, s.stream));
   HIPCHK(hipMemsetAsync(s.wfx, 0, sizeof(int32_t) * sp, s.stream));

@@ -307,7 +307,7 @@ struct sim {
   // [fwd_rec_from, fwd_rec_to) of the segment at rec_base, in window epoch fwd_rec_epoch
   int64_t fwd_rec_from = -1, fwd_rec_to = -1, fwd_rec_epoch = -1;
   float* gw = nullptr;             // weight gradient, padded layout
-  uint8_t* dly8 = nullptr;         // delay index of each record, padded layout
+  uint8_t* dlyw = nullptr;         // delay index of each 16-byte word of records
   float* nu_ring = nullptr;        // [dh][N] adjoint of V~ of the last dh steps
   float *adj_gsum = nullptr, *adj_lam = nullptr, *adj_mu = nullptr;
   double* adj_part = nullptr;      // [2][N]
