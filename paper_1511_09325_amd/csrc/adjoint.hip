@@ -1,7 +1,7 @@
 // adjoint.hip -- surrogate-gradient backpropagation through time of the step (train mode).
 //
-// Forward quantities of neuron j at step u (recorded during the recompute of a checkpoint
-// segment): V(u-1), Ca(u-1), the pre-threshold potential V~(u), the spike s(u) and the
+// Forward quantities of neuron j at step u (recorded by the forward or by the recompute of a
+// checkpoint segment): V(u-1), Ca(u-1), the pre-threshold potential V~(u), the spike s(u) and the
 // refractory flag r(u).  With nu(u) = dL/dV~(u), lambda(u) = dL/dV(u), mu(u) = dL/dCa(u):
 //     e(u)  = dL/ds(u) + sum_{k in row(j)} w_k nu_{tgt k}(u + d_k)
 //             + lambda(u) (V_reset - V~(u)) + alpha mu(u)
@@ -9,14 +9,18 @@
 //     lambda(u-1) = P_m nu(u),   mu(u-1) = -gamma nu(u) + P_c mu(u)
 //     dL/dw_k += nu_{tgt k}(u + d_k) at every spike of k's source,
 //     dL/dP_m += V(u-1) nu(u),   dL/dgamma -= Ca(u-1) nu(u)
-// with sigma'(x) = 1 / (1 + beta |x|)^2 (fast-sigmoid surrogate).  Per reverse step two
-// kernels: the gather over every outgoing row from the ring of future nu (with the weight
-// gradient of the rows whose neuron spiked) and k_adj_neuron (the recursion).  The gather is
-// k_adj_col when every part of a row holds the synapses into one column (single-column
-// native tiles: one workgroup per target column stages that column's future nu in LDS, one
-// lane per part), else k_adj_row (one wave per neuron, nu gathered from the ring).
+// with sigma'(x) = 1 / (1 + beta |x|)^2 (fast-sigmoid surrogate).  Per reverse step: the
+// gather over every outgoing row from the ring of future nu (with the weight gradient of the
+// rows whose neuron spiked) and k_adj_neuron (the recursion).  The gather is k_adj_col when
+// every part of a row holds the synapses into one column (single-column native tiles: one
+// workgroup per target column stages that column's future nu in LDS, one lane group per
+// part; the synapses of delays of at least kAdjWindow are streamed once per window of
+// kAdjWindow reverse steps, the shorter ones once per step), else k_adj_row (one wave per
+// neuron, nu gathered from the ring).
 // Everything is float32 except the per-neuron float64 partials of the two scalar
 // gradients; every sum has a fixed order, so the result is deterministic.
+#include <algorithm>
+
 #include "dpsnn_internal.h"
 
 namespace dpsnn {
@@ -38,6 +42,8 @@ struct AdjArgs {
                             // into C, its first part, its part count)
   const int32_t* in_own;    // [C]: position of C itself among its source columns
   float* psum;              // [parts][npc]: sum over each part (k_adj_col), else null
+  float* hsum;              // [kAdjWindow][parts][npc]: heavy-pass sums of a window
+  int64_t n_idx;            // parts * npc
   float dlds_scale;   // dR_c / ds = 1000 / (npc T dt)
   float beta;
 };
@@ -100,23 +106,36 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
   if (lane == 0) x.gsum[j] = acc;
 }
 
-// Gather by target column (single-column parts).  Workgroup (x, tc): nu of column tc at steps
-// u + d_min .. u + d_max goes to LDS; then groups of LPP lanes take parts into tc (the
-// synapses of one source neuron into tc) and stream them in 16-byte words (lane l of the
-// group: words l, l + LPP, ...), summing w nu per lane in record order and then over the
-// group by a fixed butterfly; where the source neuron spiked at u, nu is added to each
-// synapse's gradient.  The part's sum goes to psum.  A column's own part holds most of a
-// row (the in-column connection probability is the largest), so the first workgroups give
-// a wave to each part of the own column and the rest a quad to each part of a neighbour.
+// Gather by target column (single-column parts).  Workgroup (x, tc) stages nu of column tc
+// for a range of steps in LDS; then groups of LPP lanes take parts into tc (the synapses of
+// one source neuron into tc) and stream them in 16-byte words (lane l of the group: words l,
+// l + LPP, ...), summing w nu per lane in record order and then over the group by a fixed
+// butterfly; where the source neuron spiked, nu is added to each synapse's gradient.  A
+// column's own part holds most of a row (the in-column connection probability is the
+// largest), so the first workgroups give a wave to each part of the own column and the rest a
+// quad to each part of a neighbour.
+//
+// The reverse steps go in windows of up to kAdjWindow steps, top down to top - kw + 1.  A
+// synapse of delay d >= kAdjWindow reaches, from every step t of the window, nu(t + d) with
+// t + d > top: known when the window starts.  So the heavy pass streams the groups of those
+// delays once per window with one sum per step of the window (nu of steps top + 1 + sb ..
+// top + d_max staged), and a light pass per step streams only the groups of the shorter
+// delays (nu of steps t + d_min .. t + kAdjWindow - 1, computed inside the window) and stores
+// the part's sum as heavy + light.  Every step's sum is split the same way whatever window it
+// falls in, and each synapse's gradient receives its terms one step after the other in
+// decreasing step order, so the result does not depend on where windows or checkpoint
+// segments begin.
 constexpr int kAdjWords = 4;      // 16-byte words per lane in flight
 constexpr int kAdjOwnPerWave = 16;   // own-column parts per wave
 constexpr int kAdjNbrPerQuad = 4;    // neighbour parts per quad (one looked up per lane)
 
-// One lane's share of a part's stream (see k_adj_col): returns the lane's sum of w nu.
+// One lane's share of a part's stream (see k_adj_col): adds the lane's w nu to acc[j] for
+// every step j of the window (nu at staged index dd + ioff - j); spk bit j says the source
+// neuron spiked at step top - j.
 template <int LPP>
-__device__ __forceinline__ float adj_stream(const AdjArgs& x, const float* nus, int npc,
-                                            int64_t base, int32_t nwords, bool spiked, int gl) {
-  float acc = 0.0f;
+__device__ __forceinline__ void adj_stream(const AdjArgs& x, const float* nus, int npc,
+                                           int64_t base, int32_t nwords, uint32_t spk, int gl,
+                                           int kw, int32_t ioff, float (&acc)[kAdjWindow]) {
   for (int32_t w0 = gl; w0 < nwords; w0 += LPP * kAdjWords) {
     uint4 w[kAdjWords];
     float4 wf[kAdjWords];
@@ -127,7 +146,7 @@ __device__ __forceinline__ float adj_stream(const AdjArgs& x, const float* nus, 
       const int64_t r = base + 4 * (int64_t)wi;
       w[m] = make_uint4(kDummyRecord, kDummyRecord, kDummyRecord, kDummyRecord);
       wf[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      ddw[m] = 0;
+      ddw[m] = kAdjWindow - 1 - ioff;  // an in-range index for absent words
       if (wi < nwords) {
         w[m] = *(const uint4*)(x.a.syn + r);
         wf[m] = *(const float4*)(x.wf32 + r);
@@ -138,59 +157,70 @@ __device__ __forceinline__ float adj_stream(const AdjArgs& x, const float* nus, 
     for (int m = 0; m < kAdjWords; ++m) {
       const uint32_t rw[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
       const float rf[4] = {wf[m].x, wf[m].y, wf[m].z, wf[m].w};
-      float nu[4];
+      const int32_t wi = w0 + LPP * m;
+      const bool upd = spk != 0u && wi < nwords;
+      float4* gp = (float4*)(x.gw + base + 4 * (int64_t)wi);
+      float g[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (upd) {
+        const float4 gv = *gp;
+        g[0] = gv.x;
+        g[1] = gv.y;
+        g[2] = gv.z;
+        g[3] = gv.w;
+      }
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        nu[c] = 0.0f;
-        if (rec_rank(rw[c]) != (uint32_t)kDummyRank) {
-          nu[c] = nus[ddw[m] * npc + (int)rec_k(rw[c])];
-          acc = acc + rf[c] * nu[c];
+      for (int j = 0; j < kAdjWindow; ++j) {
+        if (j >= kw) break;
+        const float* nj = nus + (ddw[m] + ioff - j) * npc;
+        const bool sj = ((spk >> j) & 1u) != 0u;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (rec_rank(rw[c]) != (uint32_t)kDummyRank) {
+            const float nu = nj[(int)rec_k(rw[c])];
+            acc[j] = acc[j] + rf[c] * nu;
+            if (sj) g[c] = g[c] + nu;
+          }
         }
       }
-      const int32_t wi = w0 + LPP * m;
-      if (spiked && wi < nwords) {
-        float4* gp = (float4*)(x.gw + base + 4 * (int64_t)wi);
-        float4 gv = *gp;
-        gv.x = gv.x + nu[0];
-        gv.y = gv.y + nu[1];
-        gv.z = gv.z + nu[2];
-        gv.w = gv.w + nu[3];
-        *gp = gv;
-      }
+      if (upd) *gp = make_float4(g[0], g[1], g[2], g[3]);
     }
   }
-  return acc;
 }
 
-// A lane's part, looked up ahead: first record, length in 16-byte words, whether the source
-// neuron spiked at u, and where the part's sum goes.
+// A lane's part, looked up ahead: first word of its groups g_lo .. g_hi - 1, their length in
+// 16-byte words, the source neuron's spikes at steps u, u - 1, .. u - kw + 1 (bit j), and
+// where the part's sum goes.
 struct AdjPart {
   int64_t base;
   int32_t nwords;
-  int32_t spiked;
+  uint32_t spk;
   int64_t out;
 };
 
-__device__ __forceinline__ AdjPart adj_lookup(const AdjArgs& x, int64_t u, int4 in, int32_t kk) {
+__device__ __forceinline__ AdjPart adj_lookup(const AdjArgs& x, int64_t u, int4 in, int32_t kk,
+                                              int g_lo, int g_hi, int kw) {
   const StepArgs& a = x.a;
   const int npc = a.npc;
   const int64_t nall = (int64_t)a.n_cols * npc;
   const int32_t src = in.x, q = in.y, pf = in.z, np = in.w;
   const uint8_t* ent = a.idx + ((int64_t)npc * pf + (int64_t)kk * np + (q - pf)) * a.idxw;
   AdjPart P;
-  P.base = ent_start(ent) + ent_goff(ent)[0];
-  P.nwords = (ent_goff(ent)[a.nd] - ent_goff(ent)[0]) >> 2;
-  P.spiked = a.rec_flags[(u - a.rec_base) * nall + (int64_t)src * npc + kk] & 1;
+  P.base = ent_start(ent) + ent_goff(ent)[g_lo];
+  P.nwords = (ent_goff(ent)[g_hi] - ent_goff(ent)[g_lo]) >> 2;
+  P.spk = 0u;
+  for (int j = 0; j < kw; ++j)
+    P.spk |= (uint32_t)(a.rec_flags[(u - j - a.rec_base) * nall + (int64_t)src * npc + kk] & 1) << j;
   P.out = (int64_t)q * npc + kk;
   return P;
 }
 
 // Group of LPP lanes taking PPG parts, one after the other: lane gl < PPG looks up part gl
 // first (all the lookups in one round of loads), then the group streams part r with lane r's
-// lookup, sums over the group by a fixed butterfly and stores the part's sum.
+// lookup, sums over the group by a fixed butterfly and stores the part's sums, one per step
+// of the window, into hsum.
 template <int LPP, int PPG>
 __device__ __forceinline__ void adj_group(const AdjArgs& x, const float* nus, const AdjPart& mine,
-                                          bool mine_ok) {
+                                          bool mine_ok, int kw, int32_t ioff) {
   static_assert(PPG <= LPP, "each lane of a group looks up one of its parts");
   const int lane = threadIdx.x & 63, gl = lane & (LPP - 1), g0 = lane - gl;
   const int npc = x.a.npc;
@@ -200,23 +230,37 @@ __device__ __forceinline__ void adj_group(const AdjArgs& x, const float* nus, co
     const int64_t base = ((int64_t)__shfl((int32_t)(mine.base >> 32), g0 + r) << 32) |
                          (uint32_t)__shfl((int32_t)(uint32_t)mine.base, g0 + r);
     const int32_t nwords = __shfl(mine.nwords, g0 + r);
-    const bool spiked = __shfl(mine.spiked, g0 + r) != 0;
-    float acc = adj_stream<LPP>(x, nus, npc, base, nwords, spiked, gl);
+    const uint32_t spk = (uint32_t)__shfl((int32_t)mine.spk, g0 + r);
+    float acc[kAdjWindow];
 #pragma unroll
-    for (int off = LPP / 2; off > 0; off >>= 1) acc = acc + __shfl_xor(acc, off, LPP);
+    for (int j = 0; j < kAdjWindow; ++j) acc[j] = 0.0f;
+    adj_stream<LPP>(x, nus, npc, base, nwords, spk, gl, kw, ioff, acc);
+#pragma unroll
+    for (int j = 0; j < kAdjWindow; ++j)
+#pragma unroll
+      for (int off = LPP / 2; off > 0; off >>= 1) acc[j] = acc[j] + __shfl_xor(acc[j], off, LPP);
     const int64_t out = ((int64_t)__shfl((int32_t)(mine.out >> 32), g0 + r) << 32) |
                         (uint32_t)__shfl((int32_t)(uint32_t)mine.out, g0 + r);
-    if (gl == 0) x.psum[out] = acc;
+    if (gl == 0) {
+#pragma unroll
+      for (int j = 0; j < kAdjWindow; ++j)
+        if (j < kw) x.hsum[(int64_t)j * x.n_idx + out] = acc[j];
+    }
   }
 }
 
+// Heavy pass, workgroup (x, tc): stages nu of column tc for nst steps from step st0, then
+// streams its share of the parts into tc, groups g_lo .. g_hi - 1 of each, for the steps u ..
+// u - kw + 1 of a window.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_adj_col(AdjArgs x, int64_t u, int32_t nbw) {
-  extern __shared__ float nus[];  // [nd][npc]
+__global__ __launch_bounds__(BLOCK) void k_adj_col(AdjArgs x, int64_t u, int32_t nbw, int32_t g_lo,
+                                                   int32_t g_hi, int32_t kw, int32_t nst,
+                                                   int64_t st0, int32_t ioff) {
+  extern __shared__ float nus[];  // [nst][npc]
   const StepArgs& a = x.a;
   constexpr int NW = BLOCK / 64, NQ = BLOCK / 4;
   const int32_t tc = blockIdx.y;
-  const int npc = a.npc, nd = a.nd;
+  const int npc = a.npc;
   const int nn = a.col_nn[tc];
   const bool own = (int32_t)blockIdx.x < nbw;
   const int32_t first = own ? (int32_t)blockIdx.x * NW * kAdjOwnPerWave
@@ -226,13 +270,13 @@ __global__ __launch_bounds__(BLOCK) void k_adj_col(AdjArgs x, int64_t u, int32_t
   const int i_own = x.in_own[tc];
   // this lane's part, looked up before the staging so that the loads overlap
   const int lane = threadIdx.x & 63;
-  AdjPart mine{0, 0, 0, 0};
+  AdjPart mine{0, 0, 0u, 0};
   bool mine_ok = false;
   if (own) {
     const int gl = lane;
     const int32_t kk = first + (threadIdx.x >> 6) * kAdjOwnPerWave + gl;
     if (gl < kAdjOwnPerWave && kk < npc) {
-      mine = adj_lookup(x, u, x.in_part[tc * kMaxNbr + i_own], kk);
+      mine = adj_lookup(x, u, x.in_part[tc * kMaxNbr + i_own], kk, g_lo, g_hi, kw);
       mine_ok = true;
     }
   } else {
@@ -242,16 +286,16 @@ __global__ __launch_bounds__(BLOCK) void k_adj_col(AdjArgs x, int64_t u, int32_t
       int i = e / npc;
       const int32_t kk = e - i * npc;
       if (i >= i_own) ++i;  // skip the own column
-      mine = adj_lookup(x, u, x.in_part[tc * kMaxNbr + i], kk);
+      mine = adj_lookup(x, u, x.in_part[tc * kMaxNbr + i], kk, g_lo, g_hi, kw);
       mine_ok = true;
     }
   }
   // staging, kStage loads in flight per thread; e / npc through a float reciprocal (exact:
   // e < 2^16)
   const int64_t nall = (int64_t)a.n_cols * npc;
-  const int32_t slot0 = (int32_t)((u + a.d_min) % a.dh);
+  const int32_t slot0 = (int32_t)(st0 % a.dh);
   const float inv_npc = 1.0f / (float)npc;
-  const int32_t ntot = nd * npc;
+  const int32_t ntot = nst * npc;
   constexpr int kStage = 8;
   for (int32_t e0 = threadIdx.x; e0 < ntot; e0 += BLOCK * kStage) {
     float v[kStage];
@@ -271,8 +315,84 @@ __global__ __launch_bounds__(BLOCK) void k_adj_col(AdjArgs x, int64_t u, int32_t
       if (e0 + m * BLOCK < ntot) nus[e0 + m * BLOCK] = v[m];
   }
   __syncthreads();
-  if (own) adj_group<64, kAdjOwnPerWave>(x, nus, mine, mine_ok);
-  else adj_group<4, kAdjNbrPerQuad>(x, nus, mine, mine_ok);
+  if (own) adj_group<64, kAdjOwnPerWave>(x, nus, mine, mine_ok, kw, ioff);
+  else adj_group<4, kAdjNbrPerQuad>(x, nus, mine, mine_ok, kw, ioff);
+}
+
+// Light pass of step t, the jl-th of its window: a quad per part into column tc (blockIdx.y)
+// streams the part's groups 0 .. hsplit - 1 (the delays shorter than the window) with nu read
+// from the ring (the steps t + d_min .. t + kAdjWindow - 1, computed inside the window), adds
+// nu to the gradient where the source neuron spiked at t, and stores heavy + light as the
+// part's sum.  The quad's sum is its lanes' sums in word order by a fixed butterfly.
+__global__ __launch_bounds__(256) void k_adj_light(AdjArgs x, int64_t t, int32_t hsplit,
+                                                   int32_t jl) {
+  const StepArgs& a = x.a;
+  const int npc = a.npc;
+  const int32_t tc = blockIdx.y;
+  const int32_t e = (int32_t)blockIdx.x * 64 + (int32_t)(threadIdx.x >> 2);
+  const int gl = threadIdx.x & 3;
+  if (e >= a.col_nn[tc] * npc) return;  // whole quads
+  const int i = e / npc;
+  const int32_t kk = e - i * npc;
+  const int4 in = x.in_part[tc * kMaxNbr + i];
+  const int64_t nall = (int64_t)a.n_cols * npc;
+  const uint8_t* ent = a.idx + ((int64_t)npc * in.z + (int64_t)kk * in.w + (in.y - in.z)) * a.idxw;
+  const int64_t base = ent_start(ent) + ent_goff(ent)[0];
+  const int32_t nwords = (ent_goff(ent)[hsplit] - ent_goff(ent)[0]) >> 2;
+  const bool spiked = (a.rec_flags[(t - a.rec_base) * nall + (int64_t)in.x * npc + kk] & 1) != 0;
+  const int64_t out = (int64_t)in.y * npc + kk;
+  const float h = x.hsum[(int64_t)jl * x.n_idx + out];
+  const int32_t slot0 = (int32_t)((t + a.d_min) % a.dh);
+  const float* col_nu = x.nu_ring + (int64_t)tc * npc;
+  float acc = 0.0f;
+  for (int32_t w0 = gl; w0 < nwords; w0 += 4 * kAdjWords) {
+    uint4 w[kAdjWords];
+    float4 wf[kAdjWords];
+    int32_t ddw[kAdjWords];
+#pragma unroll
+    for (int m = 0; m < kAdjWords; ++m) {
+      const int32_t wi = w0 + 4 * m;
+      const int64_t r = base + 4 * (int64_t)wi;
+      w[m] = make_uint4(kDummyRecord, kDummyRecord, kDummyRecord, kDummyRecord);
+      wf[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      ddw[m] = 0;
+      if (wi < nwords) {
+        w[m] = *(const uint4*)(a.syn + r);
+        wf[m] = *(const float4*)(x.wf32 + r);
+        ddw[m] = x.dlyw[r >> 2];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kAdjWords; ++m) {
+      const uint32_t rw[4] = {w[m].x, w[m].y, w[m].z, w[m].w};
+      const float rf[4] = {wf[m].x, wf[m].y, wf[m].z, wf[m].w};
+      int32_t slot = slot0 + ddw[m];
+      if (slot >= a.dh) slot -= a.dh;
+      const float* nu_s = col_nu + (int64_t)slot * nall;
+      float nu[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        nu[c] = 0.0f;
+        if (rec_rank(rw[c]) != (uint32_t)kDummyRank) {
+          nu[c] = nu_s[(int)rec_k(rw[c])];
+          acc = acc + rf[c] * nu[c];
+        }
+      }
+      const int32_t wi = w0 + 4 * m;
+      if (spiked && wi < nwords) {
+        float4* gp = (float4*)(x.gw + base + 4 * (int64_t)wi);
+        float4 gv = *gp;
+        if (rec_rank(rw[0]) != (uint32_t)kDummyRank) gv.x = gv.x + nu[0];
+        if (rec_rank(rw[1]) != (uint32_t)kDummyRank) gv.y = gv.y + nu[1];
+        if (rec_rank(rw[2]) != (uint32_t)kDummyRank) gv.z = gv.z + nu[2];
+        if (rec_rank(rw[3]) != (uint32_t)kDummyRank) gv.w = gv.w + nu[3];
+        *gp = gv;
+      }
+    }
+  }
+  acc = acc + __shfl_xor(acc, 2, 4);
+  acc = acc + __shfl_xor(acc, 1, 4);
+  if (gl == 0) x.psum[out] = h + acc;
 }
 
 // Delay index of every 16-byte word of records (train mode): one wave per neuron over its
@@ -467,11 +587,27 @@ int grid_of(int64_t items, int per_block) {
 
 }  // namespace
 
-hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates, float scale,
-                               float beta) {
+namespace {
+
+// Split of the delays between the heavy pass and the light passes of a window: groups
+// dd < hsplit (delays below kAdjWindow) are light; the heavy pass stages nu of steps
+// top + 1 + sb .. top + d_max.
+struct AdjSplit {
+  int32_t hsplit, sb, nst;
+};
+
+AdjSplit adj_split(int32_t nd, int32_t d_min, int32_t d_max) {
+  AdjSplit p;
+  p.hsplit = std::min(nd, std::max(0, kAdjWindow - d_min));
+  p.sb = std::max(d_min, kAdjWindow) - kAdjWindow;
+  p.nst = d_max - p.sb;
+  return p;
+}
+
+AdjArgs adj_args(const sim& s, const float* grad_rates, float scale, float beta) {
   AdjArgs x{};
   x.a = make_step_args(s);
-  // the trajectory of the segment being reversed (recorded by its recompute)
+  // the trajectory of the segment being reversed
   x.a.rec_vprev = s.rec_vprev;
   x.a.rec_caprev = s.rec_caprev;
   x.a.rec_vt = s.rec_vt;
@@ -489,19 +625,56 @@ hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates,
   x.dlds_scale = scale;
   x.beta = beta;
   if (s.adj_psum) {
-    const size_t lds = sizeof(float) * (size_t)s.nd * s.npc;
     x.in_part = (const int4*)s.in_part;
     x.in_own = s.in_own;
     x.psum = s.adj_psum;
-    const int nbw = (s.npc + 16 * kAdjOwnPerWave - 1) / (16 * kAdjOwnPerWave);
-    const int nbq = ((kMaxNbr - 1) * s.npc + 256 * kAdjNbrPerQuad - 1) / (256 * kAdjNbrPerQuad);
-    hipLaunchKernelGGL(k_adj_col<1024>, dim3((unsigned)(nbw + nbq), (unsigned)s.n_cols), dim3(1024),
-                       lds, s.stream, x, u, nbw);
-  } else {
-    hipLaunchKernelGGL(k_adj_row, dim3((unsigned)((s.n_neurons + 3) / 4)), dim3(256), 0, s.stream,
-                       x, u);
+    x.hsum = s.adj_hsum;
+    x.n_idx = s.n_idx;
   }
-  hipLaunchKernelGGL(k_adj_neuron, dim3(grid_of(s.n_neurons, 256)), dim3(256), 0, s.stream, x, u);
+  return x;
+}
+
+}  // namespace
+
+// Does the column-wise gather's heavy staging (nu of one column over up to d_max steps) fit
+// the LDS?
+bool adjoint_col_fits(int32_t npc, int32_t d_min, int32_t d_max) {
+  const AdjSplit p = adj_split(d_max - d_min + 1, d_min, d_max);
+  return sizeof(float) * (size_t)p.nst * (size_t)npc + 1024 <= kMaxLds;
+}
+
+// Reverse steps top, top - 1, .. down to at most lo (a window of up to kAdjWindow steps with
+// the column-wise gather, one step otherwise); *next is the next step to reverse.  The steps
+// must lie in the recorded segment.
+hipError_t launch_adjoint_window(const sim& s, int64_t top, int64_t lo, const float* grad_rates,
+                                 float scale, float beta, int64_t* next) {
+  const AdjArgs x = adj_args(s, grad_rates, scale, beta);
+  const dim3 gn(grid_of(s.n_neurons, 256));
+  if (!s.adj_psum) {
+    hipLaunchKernelGGL(k_adj_row, dim3((unsigned)((s.n_neurons + 3) / 4)), dim3(256), 0, s.stream,
+                       x, top);
+    hipLaunchKernelGGL(k_adj_neuron, gn, dim3(256), 0, s.stream, x, top);
+    *next = top - 1;
+    return hipGetLastError();
+  }
+  const int32_t kw = (int32_t)std::min<int64_t>(kAdjWindow, top - lo + 1);
+  const int32_t d_min = s.cfg.d_min, d_max = s.cfg.d_max;
+  const AdjSplit p = adj_split(s.nd, d_min, d_max);
+  const int nbw = (s.npc + 16 * kAdjOwnPerWave - 1) / (16 * kAdjOwnPerWave);
+  const int nbq = ((kMaxNbr - 1) * s.npc + 256 * kAdjNbrPerQuad - 1) / (256 * kAdjNbrPerQuad);
+  const dim3 gc((unsigned)(nbw + nbq), (unsigned)s.n_cols);
+  // heavy pass: groups hsplit .. nd - 1 for the kw steps, staged index dd + d_min - 1 - sb - j
+  hipLaunchKernelGGL(k_adj_col<1024>, gc, dim3(1024), sizeof(float) * (size_t)p.nst * s.npc,
+                     s.stream, x, top, nbw, p.hsplit, s.nd, kw, p.nst, top + 1 + p.sb,
+                     d_min - 1 - p.sb);
+  // light passes: groups 0 .. hsplit - 1, a quad per part, 64 parts per workgroup
+  const dim3 gl((unsigned)((kMaxNbr * s.npc + 63) / 64), (unsigned)s.n_cols);
+  for (int32_t j = 0; j < kw; ++j) {
+    const int64_t t = top - j;
+    hipLaunchKernelGGL(k_adj_light, gl, dim3(256), 0, s.stream, x, t, p.hsplit, j);
+    hipLaunchKernelGGL(k_adj_neuron, gn, dim3(256), 0, s.stream, x, t);
+  }
+  *next = top - kw;
   return hipGetLastError();
 }
 

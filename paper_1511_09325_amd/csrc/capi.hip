@@ -618,7 +618,7 @@ void setup_train(sim& s) {
   // single-column native tiles: every part of a row holds the synapses into one column, and
   // the reverse gather can run by target column with that column's future nu in LDS
   if (s.native_tx == 1 && s.native_ty == 1 &&
-      sizeof(float) * (size_t)s.nd * s.npc + 1024 <= kMaxLds) {
+      adjoint_col_fits(s.npc, s.cfg.d_min, s.cfg.d_max)) {
     std::vector<int32_t> pfirst((size_t)s.n_cols + 1, 0), inp((size_t)s.n_cols * kMaxNbr * 4, -1),
         own((size_t)s.n_cols, -1);
     for (int32_t g = 0; g < s.n_cols; ++g) pfirst[g + 1] = pfirst[g] + s.h_np[g];
@@ -642,6 +642,8 @@ void setup_train(sim& s) {
     HIPCHK(prepare_adjoint_kernels());
     s.adj_psum = (float*)dalloc(s, sizeof(float) * (size_t)s.n_idx);
     HIPCHK(hipMemsetAsync(s.adj_psum, 0, sizeof(float) * (size_t)s.n_idx, s.stream));
+    s.adj_hsum = (float*)dalloc(s, sizeof(float) * kAdjWindow * (size_t)s.n_idx);
+    HIPCHK(hipMemsetAsync(s.adj_hsum, 0, sizeof(float) * kAdjWindow * (size_t)s.n_idx, s.stream));
   }
   s.rec_steps = s.cfg.ckpt_every;
   const size_t rn = (size_t)s.rec_steps * N;
@@ -1365,8 +1367,9 @@ int sim_backward(sim_t* s, const float* grad_rates, float* grad_w, double* grad_
         s->recompute = false;
       }
       s->rec_base = u0;
-      for (int64_t u = u1 - 1; u >= u0; --u)
-        HIPCHK(launch_adjoint_step(*s, u, grad_rates, scale, (float)s->cfg.surrogate_beta));
+      for (int64_t u = u1 - 1; u >= u0;)
+        HIPCHK(launch_adjoint_window(*s, u, u0, grad_rates, scale, (float)s->cfg.surrogate_beta,
+                                     &u));
     }
     s->timing = timing;
     HIPCHK(launch_reduce_parts(*s, s->adj_out));

@@ -78,6 +78,7 @@ constexpr int kNoSlot = 31;
 constexpr int kDummyRank = kMaxNbr;
 constexpr uint32_t kDummyRecord = (uint32_t)kDummyRank << 12;  // k 0, rank 9, weight 0
 constexpr int kCounters = 8;        // per-network counters (see StepArgs::net_cnt)
+constexpr int kAdjWindow = 4;       // reverse steps per window of the column-wise adjoint gather
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr uint32_t kStreamSyn = 1;  // Philox counter word 3: purpose of the draw
 constexpr uint32_t kStreamExt = 2;
@@ -316,6 +317,7 @@ struct sim {
                                    // part count (null otherwise)
   int32_t* in_own = nullptr;       // [C] position of C among its own source columns
   float* adj_psum = nullptr;       // [parts][npc] adjoint gather per part (with in_part)
+  float* adj_hsum = nullptr;       // [kAdjWindow][parts][npc] its heavy-pass sums per window
   double* adj_out = nullptr;       // [2]
   int64_t* canon_start = nullptr;  // [N+1] first canonical synapse index of each row
   uint16_t* canon_rel = nullptr;   // [S'+4] canonical index of each record minus its row's
@@ -367,8 +369,9 @@ hipError_t launch_pend_view(const sim& s, int32_t* pend, int32_t g0, int32_t g1)
 hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1, int32_t* tgt,
                               uint8_t* dly, int16_t* wq, const int64_t* out_off);
 hipError_t launch_quantise(const sim& s);
-hipError_t launch_adjoint_step(const sim& s, int64_t u, const float* grad_rates, float scale,
-                               float beta);
+hipError_t launch_adjoint_window(const sim& s, int64_t top, int64_t lo, const float* grad_rates,
+                                 float scale, float beta, int64_t* next);
+bool adjoint_col_fits(int32_t npc, int32_t d_min, int32_t d_max);
 hipError_t prepare_adjoint_kernels();
 hipError_t launch_reduce_parts(const sim& s, double* out);
 hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst);

@@ -116,7 +116,11 @@ def test_weights_round_trip_and_forward_uses_them():
     # 160-neuron columns: the 8 x 160 parts into the centre column from its neighbours fill
     # more than one workgroup of the column-wise reverse gather, four parts per quad
     (W.tiny(3, 3, npc=160, seed=11, ext_rate_hz=3.4), 60, 20, DELIVERY_ARRIVAL, (0, 0)),
-], ids=["2x2-K16", "3x4-K40-tile2x3", "2x3-d2..6-K7-push", "3x3-npc160-K20"])
+    # every delay at least the reverse window: no short-delay groups, the window's staging
+    # starts past the first future step
+    (W.tiny(2, 2, npc=40, seed=14, d_min=5, d_max=9, ext_rate_hz=3.6), 80, 30, DELIVERY_ARRIVAL,
+     (0, 0)),
+], ids=["2x2-K16", "3x4-K40-tile2x3", "2x3-d2..6-K7-push", "3x3-npc160-K20", "2x2-d5..9-K30"])
 def test_gpu_adjoint_matches_fp64_oracle(p, T, K, delivery, tile):
     C = p["rows"] * p["cols"]
     sim = Simulation(p, train_mode=True, ckpt_every=K, surrogate_beta=BETA, delivery=delivery,
