@@ -78,7 +78,7 @@ constexpr int kNoSlot = 31;
 constexpr int kDummyRank = kMaxNbr;
 constexpr uint32_t kDummyRecord = (uint32_t)kDummyRank << 12;  // k 0, rank 9, weight 0
 constexpr int kCounters = 8;        // per-network counters (see StepArgs::net_cnt)
-constexpr int kAdjWindow = 4;       // reverse steps per window of the column-wise adjoint gather
+constexpr int kAdjWindow = 3;       // reverse steps per window of the column-wise adjoint gather
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr uint32_t kStreamSyn = 1;  // Philox counter word 3: purpose of the draw
 constexpr uint32_t kStreamExt = 2;
