@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kMaxItems = kMaxTilePairs * kMaxDelay;
 static_assert(kMaxItems + 1 >= 1024, "the tile order's buckets reuse the item prefix array");
-constexpr int kPIF = 4;               // 16-byte synapse loads per lane in flight
+constexpr int kPIF = 4;               // 16-byte synapse loads per lane in flight (plain mode)
 constexpr int kIdxWords = (8 + 2 * (kMaxDelay + 2) + 15) / 16;  // 16-byte words of an entry
 
 __device__ __forceinline__ unsigned long long lanemask_lt(int lane) {
@@ -414,13 +414,16 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         pref[m + 1] = pref[m] + __shfl(glen, quad0 + m);
       }
       const int32_t npieces = pref[4];
-      for (int32_t p0 = ql; p0 < npieces; p0 += 4 * kPIF) {
-        uint4 w[kPIF];
-        int32_t v[kPIF][4];
-        int32_t aoff[kPIF];
-        uint64_t sw[kPIF];
+      // train mode carries each piece's four efficacies as well: two pieces in flight keep
+      // its registers from spilling (measured faster than one, three or four)
+      constexpr int PIF = TRAIN ? 2 : kPIF;
+      for (int32_t p0 = ql; p0 < npieces; p0 += 4 * PIF) {
+        uint4 w[PIF];
+        int32_t v[PIF][4];
+        int32_t aoff[PIF];
+        uint64_t sw[PIF];
 #pragma unroll
-        for (int q = 0; q < kPIF; ++q) {
+        for (int q = 0; q < PIF; ++q) {
           const int32_t p = p0 + 4 * q;
           const bool valid = p < npieces;
           const bool m1 = p >= pref[1], m2 = p >= pref[2], m3 = p >= pref[3];
@@ -439,7 +442,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         // weights are added in their 2^-14 mV units (train mode: the float efficacies, in
         // 2^-16 mV), the wave's delivered records counted from the ballot
 #pragma unroll
-        for (int q = 0; q < kPIF; ++q) {
+        for (int q = 0; q < PIF; ++q) {
           const uint32_t x[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
