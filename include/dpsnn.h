@@ -148,8 +148,10 @@ int sim_column_rates(sim_t* sim, float* rates);
  * grad_w:     device float32 [n_synapses], dL/dw in the canonical synapse order (per
  *             network, per source neuron, sorted by (delay, target)), w in mV.
  * grad_tau_m, grad_g_ahp: host doubles.
- * The reverse pass re-runs each checkpoint segment forward to record its trajectory, so
- * it costs about one forward plus the adjoint; afterwards the state is the end state again.
+ * The reverse pass re-runs each checkpoint segment forward to record its trajectory (all
+ * but the last, which the train-mode forward records as it steps, when nothing has
+ * interrupted that recording), so it costs up to one forward plus the adjoint; afterwards
+ * the state is the end state again.  The result does not depend on ckpt_every.
  * The adjoint (float32; float64 partial sums for the two scalars) follows the surrogate
  * recursion: nu = dL/dV~ = (1 - r)[lambda (1 - s) + e sigma'(V~ - theta)], sigma'(x) =
  * 1/(1 + beta|x|)^2, with lambda = dL/dV and e = dL/ds including the delayed synapses.
