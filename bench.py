@@ -83,7 +83,20 @@ def cpu_baseline(sample_steps: int = 5000):
             "sample": "4x4 grid of the same column recipe (19,840 neurons, %d synapses), "
                       "seed 0, %d steps after 20 warm-up steps, step loop only, %.1f s"
                       % (len(net[1]), sample_steps, dt),
-            "sim_ms_per_wall_s": sample_steps / dt}
+            "sim_ms_per_wall_s": sample_steps / dt,
+            "host_cpu": host_cpu_model(), "host_threads": os.cpu_count()}
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name as /proc/cpuinfo gives it (empty if unavailable)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 def device_copy_gbs(torch, mib: int = 2048, reps: int = 10) -> float:
