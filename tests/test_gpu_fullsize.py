@@ -114,3 +114,28 @@ def test_96x96_spot_steps(sim96, u):
     p, sim = sim96
     spikes = _spot_step(sim, p, u, np.random.default_rng(u), 300)
     assert spikes > 0
+
+
+def test_batched_workload_members_equal_their_plain_runs():
+    """The batched workload itself (64 networks of the full column recipe, grids 2x2..8x8,
+    external rates 2-6 Hz, 2.5G synapses), stepped with the bench's launch (one launch per
+    step, graph chunks of 50): after 100 steps every member's raster, V, Ca, refractory
+    counters, pending input and counters equal those of the same network run alone."""
+    nets = W.batched_networks(64, 0)
+    T = 100
+    batch = Simulation(nets, record_steps=T)
+    batch.set_launch(graph_steps=50)
+    batch.step(T)
+    batch.sync()
+    for n, p in enumerate(nets):
+        solo = Simulation(p, record_steps=T)
+        solo.step(T)
+        a, b = batch.read_spikes(n, 0, T), solo.read_spikes(0, 0, T)
+        assert all(np.array_equal(x, y) for x, y in zip(a, b)), n
+        sa, sb = batch.state(n), solo.state(0)
+        for k in ("v", "ca", "ref", "pend"):
+            assert np.array_equal(sa[k], sb[k]), (n, k)
+        ca, cb = batch.stats(n), solo.stats(0)
+        assert (ca["spikes"], ca["e_rec"], ca["e_ext"]) == (cb["spikes"], cb["e_rec"], cb["e_ext"]), n
+        solo.close()
+    batch.close()
