@@ -249,3 +249,23 @@ def test_autograd_function_matches_backward():
     gw, gt, gg = sim.backward(seen[0])
     assert torch.equal(w.grad, gw)
     assert float(tau.grad) == gt and float(g.grad) == gg
+
+
+def test_fwd_bwd_workload_adjoint_matches_fp64_oracle():
+    """The forward+backward workload itself (4x4 grid of the full column recipe, 24.6M
+    synapses, 500 steps, checkpoints every 50) with the bench's loss gradient: the GPU
+    adjoint against the FP64 oracle adjoint over the same trajectory (about 25 s of oracle)."""
+    p = W.FWD_BWD_4X4["params"]
+    T, K = W.FWD_BWD_4X4["steps"], W.FWD_BWD_4X4["ckpt_every"]
+    C = p["rows"] * p["cols"]
+    sim = Simulation(p, train_mode=True, ckpt_every=K, surrogate_beta=BETA)
+    sim.step(T)
+    rates = sim.column_rates().cpu().numpy()
+    gr = _grad_rates(rates.astype(np.float64), W.target_rates(C, 1)).astype(np.float32)
+    ogw, ogt, ogg, orates = _oracle_grads(p, T, gr)
+    assert np.allclose(rates, orates, rtol=1e-6, atol=0)
+    gw, gt, gg, _ = _gpu_grads(sim, T, gr)
+    assert np.count_nonzero(ogw) > 0.5 * len(ogw)
+    assert _rel_l2(gw, ogw) <= RTOL, _rel_l2(gw, ogw)
+    assert abs(gt - ogt) <= RTOL * abs(ogt), (gt, ogt)
+    assert abs(gg - ogg) <= RTOL * abs(ogg), (gg, ogg)
