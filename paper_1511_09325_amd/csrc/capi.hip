@@ -935,6 +935,22 @@ int sim_read_spikes(sim_t* s, int32_t net, int64_t t0, int64_t t1, int64_t* step
     if (rc == DPSNN_ETRUNC) return rc;
     std::vector<int64_t> off((size_t)(t1 - t0 + 1));
     HIPCHK(hipMemcpy(off.data(), s->ras_off + t0, sizeof(int64_t) * off.size(), hipMemcpyDeviceToHost));
+    if (s->n_nets == 1) {
+      // one network holds every id: the recorded rows are the answer as they stand, copied
+      // once into the caller's buffer (and not at all for a size query)
+      const int64_t cnt = off.back() - off.front();
+      for (int64_t t = t0; t <= t1; ++t) step_offsets[t - t0] = off[t - t0] - off.front();
+      *n_ids = cnt;
+      const int64_t n = ids ? std::min(cnt, ids_cap) : 0;
+      if (n > 0)
+        HIPCHK(hipMemcpy(ids, s->ras_ids + off.front(), sizeof(int32_t) * (size_t)n,
+                         hipMemcpyDeviceToHost));
+      if (cnt > ids_cap || (!ids && cnt > 0)) {
+        s->err = "ids buffer too small";
+        return DPSNN_ETRUNC;
+      }
+      return DPSNN_OK;
+    }
     std::vector<int32_t> all((size_t)(off.back() - off.front()));
     if (!all.empty())
       HIPCHK(hipMemcpy(all.data(), s->ras_ids + off.front(), sizeof(int32_t) * all.size(),

@@ -115,7 +115,8 @@ class Simulation:
         return p["rows"] * p["cols"] * p["npc"]
 
     def read_spikes(self, net: int = 0, t0: int = 0, t1: int | None = None):
-        """List (one array per step) of ascending network-local spike ids."""
+        """List (one array per step) of ascending network-local spike ids (views of one
+        buffer that holds the whole range)."""
         if t1 is None:
             t1 = min(self.now, self.record_steps)
         off = np.zeros(t1 - t0 + 1, np.int64)
@@ -124,12 +125,12 @@ class Simulation:
                                       None, 0, C.byref(n))
         if rc not in (L.OK, L.ETRUNC):
             L.check(rc, self.h)
-        ids = np.zeros(max(n.value, 1), np.int32)
+        ids = np.empty(max(n.value, 1), np.int32)
         L.check(self.lib.sim_read_spikes(self.h, net, t0, t1,
                                          off.ctypes.data_as(C.POINTER(C.c_int64)),
                                          ids.ctypes.data_as(C.POINTER(C.c_int32)), ids.size,
                                          C.byref(n)), self.h)
-        return [ids[off[q]:off[q + 1]].copy() for q in range(t1 - t0)]
+        return [ids[off[q]:off[q + 1]] for q in range(t1 - t0)]
 
     def stats(self, net: int = 0) -> dict:
         s = L.SimStats()

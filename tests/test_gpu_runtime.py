@@ -118,3 +118,37 @@ def test_batched_members_match_solo_runs_with_graphs():
         got = batch.read_spikes(n, 0, T)
         for u in range(T):
             assert np.array_equal(got[u], ref.spikes(u)), (n, u)
+
+
+@pytest.mark.parametrize("nets", [1, 2], ids=["one-network", "two-networks"])
+def test_read_spikes_through_the_abi(nets):
+    """sim_read_spikes: a size query (no buffer) answers ETRUNC with the count, a short
+    buffer receives its first ids and ETRUNC, and a window in the middle of the record gives
+    per-step offsets from zero and the oracle's ids."""
+    import ctypes as C
+    from paper_1511_09325_amd import _lib as L
+    ps = [W.tiny(2, 3, npc=40, seed=51), W.tiny(2, 2, npc=40, seed=52)][:nets]
+    T, t0, t1 = 60, 17, 49
+    sim = Simulation(ps if nets > 1 else ps[0], record_steps=T)
+    sim.step(T)
+    ref = oracle.Sim(ps[-1])
+    ref.step(T)
+    want = np.concatenate([ref.spikes(u) for u in range(t0, t1)]).astype(np.int32)
+    off = np.zeros(t1 - t0 + 1, np.int64)
+    n = C.c_int64(-1)
+    P64, P32 = C.POINTER(C.c_int64), C.POINTER(C.c_int32)
+    rc = sim.lib.sim_read_spikes(sim.h, nets - 1, t0, t1, off.ctypes.data_as(P64), None, 0,
+                                 C.byref(n))
+    assert rc == L.ETRUNC and n.value == len(want) > 10
+    short = np.full(10, -7, np.int32)
+    rc = sim.lib.sim_read_spikes(sim.h, nets - 1, t0, t1, off.ctypes.data_as(P64),
+                                 short.ctypes.data_as(P32), short.size, C.byref(n))
+    assert rc == L.ETRUNC and n.value == len(want)
+    assert np.array_equal(short, want[:10])
+    ids = np.full(len(want), -7, np.int32)
+    rc = sim.lib.sim_read_spikes(sim.h, nets - 1, t0, t1, off.ctypes.data_as(P64),
+                                 ids.ctypes.data_as(P32), ids.size, C.byref(n))
+    assert rc == L.OK and np.array_equal(ids, want)
+    assert off[0] == 0 and off[-1] == len(want)
+    for u in range(t0, t1):
+        assert np.array_equal(ids[off[u - t0]:off[u - t0 + 1]], ref.spikes(u)), u
