@@ -177,7 +177,64 @@ __global__ void k_quantise(const float* w, int32_t* wfx, int64_t n) {
     wfx[e] = (int32_t)__builtin_rintf(w[e] * 65536.0f);
 }
 
+// One network's share of the recorded raster: per step t0 + i the range of its ids [lo, hi)
+// within the step's ascending global ids, by binary search (one thread per step).
+__global__ __launch_bounds__(256) void k_raster_bounds(const int64_t* ras_off,
+                                                       const int32_t* ras_ids, int64_t t0,
+                                                       int64_t nsteps, int32_t lo, int32_t hi,
+                                                       int64_t* bounds) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nsteps) return;
+  const int64_t a = ras_off[t0 + i], b = ras_off[t0 + i + 1];
+  int64_t x = a, n = b - a;  // first id >= lo
+  while (n > 0) {
+    const int64_t h = n >> 1;
+    if (ras_ids[x + h] < lo) { x += h + 1; n -= h + 1; } else n = h;
+  }
+  int64_t y = x, m = b - x;  // first id >= hi
+  while (m > 0) {
+    const int64_t h = m >> 1;
+    if (ras_ids[y + h] < hi) { y += h + 1; m -= h + 1; } else m = h;
+  }
+  bounds[2 * i] = x;
+  bounds[2 * i + 1] = y;
+}
+
+// Gathers those ranges, made network-local (minus lo), into out at the steps' offsets
+// (dst_off[i], exclusive prefix of the range lengths); ids past n are dropped.  One
+// workgroup per step.
+__global__ __launch_bounds__(256) void k_raster_take(const int32_t* ras_ids,
+                                                     const int64_t* bounds,
+                                                     const int64_t* dst_off, int32_t lo,
+                                                     int64_t n, int32_t* out) {
+  const int64_t i = blockIdx.x;
+  const int64_t x = bounds[2 * i], y = bounds[2 * i + 1], d = dst_off[i];
+  for (int64_t k = x + threadIdx.x; k < y; k += blockDim.x) {
+    const int64_t o = d + (k - x);
+    if (o < n) out[o] = ras_ids[k] - lo;
+  }
+}
+
 }  // namespace
+
+// One network's spikes of steps [t0, t0 + nsteps) from the raster (synchronous): bounds
+// receives the per-step ranges (device, 2 * nsteps), then, when out is given, the first n ids
+// go to out (device) at the offsets dst_off (device, nsteps).
+hipError_t launch_raster_bounds(const sim& s, int64_t t0, int64_t nsteps, int32_t lo, int32_t hi,
+                                int64_t* bounds) {
+  if (nsteps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_raster_bounds, dim3((unsigned)((nsteps + 255) / 256)), dim3(256), 0,
+                     s.stream, s.ras_off, s.ras_ids, t0, nsteps, lo, hi, bounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_take(const sim& s, int64_t nsteps, const int64_t* bounds,
+                              const int64_t* dst_off, int32_t lo, int64_t n, int32_t* out) {
+  if (nsteps <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_raster_take, dim3((unsigned)nsteps), dim3(256), 0, s.stream, s.ras_ids,
+                     bounds, dst_off, lo, n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_raster(sim& s, int64_t u) {
   const int64_t* nd = s.graph_mode ? s.d_now : nullptr;

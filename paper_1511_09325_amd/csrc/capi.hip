@@ -951,25 +951,46 @@ int sim_read_spikes(sim_t* s, int32_t net, int64_t t0, int64_t t1, int64_t* step
       }
       return DPSNN_OK;
     }
-    std::vector<int32_t> all((size_t)(off.back() - off.front()));
-    if (!all.empty())
-      HIPCHK(hipMemcpy(all.data(), s->ras_ids + off.front(), sizeof(int32_t) * all.size(),
-                       hipMemcpyDeviceToHost));
+    // several networks: the per-step ranges of this network's ids are found on the device
+    // and only those ids cross to the host
     const int32_t lo = s->net_col0[net] * s->npc, hi = s->net_col0[net + 1] * s->npc;
-    int64_t cnt = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-      step_offsets[t - t0] = cnt;
-      const int32_t* a = all.data() + (off[t - t0] - off.front());
-      const int32_t* b = all.data() + (off[t - t0 + 1] - off.front());
-      const int32_t* x = std::lower_bound(a, b, lo);
-      const int32_t* y = std::lower_bound(a, b, hi);
-      for (const int32_t* p = x; p < y; ++p) {
-        if (ids && cnt < ids_cap) ids[cnt] = *p - lo;
-        ++cnt;
+    const int64_t ns = t1 - t0;
+    struct Scratch {
+      void* p = nullptr;
+      ~Scratch() { if (p) (void)hipFree(p); }
+    } bnd, take;
+    std::vector<int64_t> hb((size_t)(2 * ns));
+    if (ns > 0) {
+      if (hipMalloc(&bnd.p, sizeof(int64_t) * 3 * (size_t)ns) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Fail{DPSNN_ENOMEM, "raster read scratch allocation failed"};
       }
+      HIPCHK(launch_raster_bounds(*s, t0, ns, lo, hi, (int64_t*)bnd.p));
+      HIPCHK(hipMemcpyAsync(hb.data(), bnd.p, sizeof(int64_t) * hb.size(), hipMemcpyDeviceToHost,
+                            s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
     }
-    step_offsets[t1 - t0] = cnt;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < ns; ++i) {
+      step_offsets[i] = cnt;
+      cnt += hb[(size_t)(2 * i + 1)] - hb[(size_t)(2 * i)];
+    }
+    step_offsets[ns] = cnt;
     *n_ids = cnt;
+    const int64_t n = ids ? std::min(cnt, ids_cap) : 0;
+    if (n > 0) {
+      int64_t* doff = (int64_t*)bnd.p + 2 * ns;
+      if (hipMalloc(&take.p, sizeof(int32_t) * (size_t)n) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Fail{DPSNN_ENOMEM, "raster read scratch allocation failed"};
+      }
+      HIPCHK(hipMemcpyAsync(doff, step_offsets, sizeof(int64_t) * (size_t)ns,
+                            hipMemcpyHostToDevice, s->stream));
+      HIPCHK(launch_raster_take(*s, ns, (const int64_t*)bnd.p, doff, lo, n, (int32_t*)take.p));
+      HIPCHK(hipMemcpyAsync(ids, take.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost,
+                            s->stream));
+      HIPCHK(hipStreamSynchronize(s->stream));
+    }
     if (cnt > ids_cap || (!ids && cnt > 0)) {
       s->err = "ids buffer too small";
       return DPSNN_ETRUNC;

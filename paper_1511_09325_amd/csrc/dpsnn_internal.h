@@ -369,6 +369,10 @@ hipError_t launch_pend_view(const sim& s, int32_t* pend, int32_t g0, int32_t g1)
 hipError_t launch_export_rows(const sim& s, int32_t net, int64_t i0, int64_t i1, int32_t* tgt,
                               uint8_t* dly, int16_t* wq, const int64_t* out_off);
 hipError_t launch_quantise(const sim& s);
+hipError_t launch_raster_bounds(const sim& s, int64_t t0, int64_t nsteps, int32_t lo, int32_t hi,
+                                int64_t* bounds);
+hipError_t launch_raster_take(const sim& s, int64_t nsteps, const int64_t* bounds,
+                              const int64_t* dst_off, int32_t lo, int64_t n, int32_t* out);
 hipError_t launch_adjoint_window(const sim& s, int64_t top, int64_t lo, const float* grad_rates,
                                  float scale, float beta, int64_t* next);
 bool adjoint_col_fits(int32_t npc, int32_t d_min, int32_t d_max);
