@@ -84,7 +84,23 @@ def cpu_baseline(sample_steps: int = 5000):
                       "seed 0, %d steps after 20 warm-up steps, step loop only, %.1f s"
                       % (len(net[1]), sample_steps, dt),
             "sim_ms_per_wall_s": sample_steps / dt,
-            "host_cpu": host_cpu_model(), "host_threads": os.cpu_count()}
+            "host_cpu": host_cpu_model(), "host_threads": os.cpu_count(),
+            "plain_2x2_1s": _oracle_2x2_full()}
+
+
+def _oracle_2x2_full():
+    """The oracle over the whole small plain workload (2x2 grid, 4,960 neurons, 1000 steps),
+    one thread, step loop only."""
+    import oracle
+    from paper_1511_09325_amd import workloads as W
+    p, steps = W.PLAIN_2X2["params"], W.PLAIN_2X2["steps"]
+    sim = oracle.Sim(p)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    c = sim.counts()
+    return {"events_per_s": (c["e_rec"] + c["e_ext"]) / dt, "seconds": dt,
+            "sim_ms_per_wall_s": steps * p["dt"] / dt}
 
 
 def host_cpu_model() -> str:
