@@ -9,7 +9,9 @@
 //     lambda(u-1) = P_m nu(u),   mu(u-1) = -gamma nu(u) + P_c mu(u)
 //     dL/dw_k += nu_{tgt k}(u + d_k) at every spike of k's source,
 //     dL/dP_m += V(u-1) nu(u),   dL/dgamma -= Ca(u-1) nu(u)
-// with sigma'(x) = 1 / (1 + beta |x|)^2 (fast-sigmoid surrogate).  Per reverse step: the
+// with sigma'(x) = 1 / (1 + beta |x|)^2 (fast-sigmoid surrogate) and w_k the efficacy the
+// forward delivered (the int32 rint(w 2^16) of the master weight, back in mV: straight-through
+// rounding, so the recursion is the exact one of the forward that ran).  Per reverse step: the
 // gather over every outgoing row from the ring of future nu (with the weight gradient of the
 // rows whose neuron spiked) and k_adj_neuron (the recursion).  The gather is k_adj_col when
 // every part of a row holds the synapses into one column (single-column native tiles: one
@@ -28,7 +30,7 @@ namespace {
 
 struct AdjArgs {
   StepArgs a;
-  const float* wf32;
+  const int32_t* wfx;  // int32 efficacies of the forward, 2^-16 mV (rint of the master weight)
   float* gw;
   float* nu_ring;     // [dh][N]
   const uint8_t* dlyw; // [S'/4] delay index of each 16-byte word of records (groups are
@@ -49,6 +51,14 @@ struct AdjArgs {
 };
 
 constexpr int kAdjUnroll = 8;  // records per lane in flight
+
+// The weights the adjoint multiplies by are the ones the forward used: its int32 efficacies
+// (rint of the master weight at 2^-16 mV) back in mV, exactly (|efficacy| < 2^24).  The
+// gradient still goes to the float32 master weight unchanged (straight-through rounding).
+__device__ __forceinline__ float4 efficacies_mv(int4 q) {
+  return make_float4((float)q.x * 0x1p-16f, (float)q.y * 0x1p-16f, (float)q.z * 0x1p-16f,
+                     (float)q.w * 0x1p-16f);
+}
 
 // One wave per neuron.  The whole row (all parts, contiguous in the store) is streamed 64 x
 // kAdjUnroll records at a time with each record's delay index from the train-mode delay
@@ -77,7 +87,7 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
       dd[i] = 0;
       if (f < rlen) {
         w[i] = a.syn[rb + f];
-        wf[i] = x.wf32[rb + f];
+        wf[i] = (float)x.wfx[rb + f] * 0x1p-16f;
         dd[i] = x.dlyw[(rb + f) >> 2];
       }
     }
@@ -149,7 +159,7 @@ __device__ __forceinline__ void adj_stream(const AdjArgs& x, const float* nus, i
       ddw[m] = kAdjWindow - 1 - ioff;  // an in-range index for absent words
       if (wi < nwords) {
         w[m] = *(const uint4*)(x.a.syn + r);
-        wf[m] = *(const float4*)(x.wf32 + r);
+        wf[m] = efficacies_mv(*(const int4*)(x.wfx + r));
         ddw[m] = x.dlyw[r >> 2];
       }
     }
@@ -358,7 +368,7 @@ __global__ __launch_bounds__(256) void k_adj_light(AdjArgs x, int64_t t, int32_t
       ddw[m] = 0;
       if (wi < nwords) {
         w[m] = *(const uint4*)(a.syn + r);
-        wf[m] = *(const float4*)(x.wf32 + r);
+        wf[m] = efficacies_mv(*(const int4*)(x.wfx + r));
         ddw[m] = x.dlyw[r >> 2];
       }
     }
@@ -613,7 +623,7 @@ AdjArgs adj_args(const sim& s, const float* grad_rates, float scale, float beta)
   x.a.rec_vt = s.rec_vt;
   x.a.rec_flags = s.rec_flags;
   x.a.rec_base = s.rec_base;
-  x.wf32 = s.wf32;
+  x.wfx = s.wfx;
   x.gw = s.gw;
   x.nu_ring = s.nu_ring;
   x.dlyw = s.dlyw;

@@ -1236,6 +1236,8 @@ int sim_set_params(sim_t* s, double tau_m, double g_ahp) {
   s->cfg.tau_m = tau_m;
   s->cfg.g_ahp = g_ahp;
   set_constants(*s);
+  // the constants reach the kernels by value: a captured step graph holds the old ones
+  drop_graph(*s);
   if (s->wfx) break_window(*s);
   return DPSNN_OK;
 }

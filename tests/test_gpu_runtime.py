@@ -47,6 +47,36 @@ def test_graph_steps_bit_exact(graph_steps, record):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("graph_steps", [0, 10])
+def test_set_params_reaches_the_next_steps(graph_steps):
+    """tau_m and g_AHP changed between steps reach every later step, also when the steps run
+    from a captured graph (the constants are kernel arguments by value, so the graph must be
+    captured again): the run equals the oracle stepped with the old parameters and then,
+    from the same state, with the new ones."""
+    p = W.tiny(2, 3, npc=40, seed=33)
+    q = dict(p, tau_m=14.0, g_ahp=0.6)
+    T1, T2 = 30, 40
+    sim = Simulation(p, record_steps=T1 + T2)
+    sim.set_launch(graph_steps=graph_steps)
+    sim.step(T1)
+    sim.set_params(q["tau_m"], q["g_ahp"])
+    sim.step(T2)
+    a = oracle.Sim(p)
+    a.step(T1)
+    st = a.state()
+    b = oracle.Sim(q)
+    b.set_state(T1, st["v"], st["ca"], st["ref"], st["pend"])
+    b.step(T2)
+    got = sim.read_spikes(0, 0, T1 + T2)
+    for u in range(T1):
+        assert np.array_equal(got[u], a.spikes(u)), u
+    for u in range(T1, T1 + T2):
+        assert np.array_equal(got[u], b.spikes(u)), u
+    x, y = sim.state(0), b.state()
+    for k in ("v", "ca", "ref", "pend"):
+        assert np.array_equal(x[k], y[k]), k
+
+
 def test_graph_after_restore_and_relaunch():
     p = W.tiny(2, 3, npc=40, seed=32)
     sim = Simulation(p, record_steps=90)

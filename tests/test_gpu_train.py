@@ -41,10 +41,14 @@ def _grad_rates(rates, targets):
     return 2.0 * (rates - targets) / len(rates)
 
 
-def _oracle_grads(p, T, grad_rates):
-    """FP64 adjoint over the oracle's hard trajectory with dL/ds = dL/dR_c * dR_c/ds."""
+def _oracle_grads(p, T, grad_rates, w32=None):
+    """FP64 adjoint over the oracle's hard trajectory with dL/ds = dL/dR_c * dR_c/ds.
+    w32: the forward's int32 efficacies at 2^-16 mV (default: the generated weights); the
+    adjoint multiplies by the same efficacies in mV (straight-through rounding)."""
     net = oracle.network(p)
-    ref = oracle.Sim(p, net)
+    if w32 is None:
+        w32 = net[3].astype(np.int32) * 4
+    ref = oracle.Sim(p, net, w32=w32)
     ref.record(True)
     ref.step(T)
     traj = ref.trajectory(T)
@@ -53,7 +57,7 @@ def _oracle_grads(p, T, grad_rates):
     scale = 1000.0 / (npc * T * p["dt"])
     dl_ds = np.repeat(np.asarray(grad_rates, np.float64) * scale, npc)[None, :].repeat(T, 0)
     consts = oracle.step_constants(p, single=True)
-    w = net[3].astype(np.float64) / 16384.0
+    w = np.asarray(w32, np.float64) / 65536.0
     gw, gpm, ggam = oracle.adjoint(consts, BETA, net, w, traj, dl_ds)
     g_tau = gpm * consts["pm"] * p["dt"] / p["tau_m"] ** 2
     g_g = ggam * p["dt"]
@@ -63,6 +67,13 @@ def _oracle_grads(p, T, grad_rates):
 
 def _rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _elementwise(g, o):
+    """Largest |g - o| / (1e-3 |o| + 1e-5 max|o|) over all weights: <= 1 passes.  Beside the
+    relative L2 norm it catches a small set of wrong gradients (one delay class, one part)."""
+    bound = 1e-3 * np.abs(o) + 1e-5 * float(np.abs(o).max())
+    return float((np.abs(g - o) / bound).max())
 
 
 def _gpu_grads(sim, T, grad_rates):
@@ -134,6 +145,46 @@ def test_gpu_adjoint_matches_fp64_oracle(p, T, K, delivery, tile):
     gw, gt, gg, _ = _gpu_grads(sim, T, gr)
     assert np.count_nonzero(ogw) > 0.05 * len(ogw)
     assert _rel_l2(gw, ogw) <= RTOL, _rel_l2(gw, ogw)
+    assert _elementwise(gw, ogw) <= 1.0, _elementwise(gw, ogw)
+    assert abs(gt - ogt) <= RTOL * abs(ogt), (gt, ogt)
+    assert abs(gg - ogg) <= RTOL * abs(ogg), (gg, ogg)
+
+
+def test_off_grid_master_weights():
+    """Master weights off the 2^-16 mV grid (what any optimiser step leaves): the forward
+    runs on rint(w 2^16) and equals the oracle stepped with those efficacies bit for bit, and
+    the adjoint equals the FP64 oracle adjoint with the same efficacies as its weights."""
+    import torch
+    p = W.tiny(3, 3, npc=40, seed=17, ext_rate_hz=3.4)
+    T, C = 100, 9
+    sim = Simulation(p, train_mode=True, ckpt_every=25, surrogate_beta=BETA, record_steps=T)
+    w0 = sim.get_weights()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    w = (w0 * (1.0 + 0.2 * torch.randn(w0.shape, device="cuda", generator=g))
+         + 1e-3 * torch.randn(w0.shape, device="cuda", generator=g)).contiguous()
+    w_host = w.cpu().numpy()
+    w32 = np.rint(w_host.astype(np.float64) * 65536.0).astype(np.int32)
+    assert np.mean(w_host * 65536.0 != w32) > 0.99  # off the grid
+    sim.set_weights(w)
+    sim.rewind()
+    sim.step(T)
+    net = oracle.network(p)
+    ref = oracle.Sim(p, net, w32=w32)
+    ref.step(T)
+    got = sim.read_spikes(0, 0, T)
+    for u in range(T):
+        assert np.array_equal(got[u], ref.spikes(u)), u
+    a, b = sim.state(0), ref.state()
+    for k in ("v", "ca", "ref", "pend"):
+        assert np.array_equal(a[k], b[k]), k
+    rates = sim.column_rates().cpu().numpy()
+    gr = _grad_rates(rates.astype(np.float64), _targets(C, seed=7)).astype(np.float32)
+    ogw, ogt, ogg, orates = _oracle_grads(p, T, gr, w32=w32)
+    assert np.allclose(rates, orates, rtol=1e-6, atol=0) and orates.sum() > 0
+    gw, gt, gg = sim.backward(torch.tensor(gr, device="cuda"))
+    gw = gw.cpu().numpy().astype(np.float64)
+    assert _rel_l2(gw, ogw) <= RTOL, _rel_l2(gw, ogw)
+    assert _elementwise(gw, ogw) <= 1.0, _elementwise(gw, ogw)
     assert abs(gt - ogt) <= RTOL * abs(ogt), (gt, ogt)
     assert abs(gg - ogg) <= RTOL * abs(ogg), (gg, ogg)
 
@@ -267,5 +318,6 @@ def test_fwd_bwd_workload_adjoint_matches_fp64_oracle():
     gw, gt, gg, _ = _gpu_grads(sim, T, gr)
     assert np.count_nonzero(ogw) > 0.5 * len(ogw)
     assert _rel_l2(gw, ogw) <= RTOL, _rel_l2(gw, ogw)
+    assert _elementwise(gw, ogw) <= 1.0, _elementwise(gw, ogw)
     assert abs(gt - ogt) <= RTOL * abs(ogt), (gt, ogt)
     assert abs(gg - ogg) <= RTOL * abs(ogg), (gg, ogg)
