@@ -26,8 +26,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_SYNAPSE = 4       # one uint32 record: target index in column (16 b) + weight (16 b)
-BYTES_PER_NEURON = 18       # V, Ca (float32) and refractory counter (uint8), read and written
+# Algorithmic bytes of the step (the per-unit figures of the scope table's measurement):
+# 7 B per recurrent synaptic event (int32 target + int16 weight + uint8 delay of the plain
+# record layout) and 26 B per neuron per step (V, Ca and refractory state read and written,
+# pending input read and cleared).  External events cost no bytes (drawn on the fly).
+BYTES_PER_EVENT = 7
+BYTES_PER_NEURON = 26
+# The bytes this kernel's own layout needs: one 4-byte record per delivered synapse (delay
+# implied by its group, target column by a rank) and 18 B per neuron (V, Ca float32 and the
+# refractory counter, read and written; the input lives in LDS).
+RECORD_BYTES_PER_SYNAPSE = 4
+RECORD_BYTES_PER_NEURON = 18
 
 WORKLOADS = {
     "96x96": ("PLAIN_96X96", 2000),
@@ -48,14 +57,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, delivery: str):
-    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE runs, if they
-    were taken on the current kernel source; else None."""
+def traffic_key(workload: str, delivery: str, first: int, last: int) -> str:
+    return "%s/%s/steps %d-%d" % (workload, delivery, first, last)
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs of the same workload and the same timed step range, if they were taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get("%s/%s" % (workload, delivery))
+        rec = json.load(open(path)).get(key)
     except Exception:
         return None
     if not rec or rec.get("source_hash") != kernel_source_hash():
@@ -63,29 +77,84 @@ def measured_traffic(workload: str, delivery: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(sample_steps: int = 5000):
-    """The CPU oracle, as it stands, on a bounded sample of the same workload family: the
-    4x4 grid of the same column recipe (19,840 neurons, ~24.6M synapses), seed 0; only its
-    step loop is timed (network construction excluded); one thread."""
-    import oracle
-    from paper_1511_09325_amd import workloads as W
-    p = W.grid(4, 4, 0)
-    net = oracle.network(p)
-    sim = oracle.Sim(p, net)
-    sim.step(20)
+def _oracle_sample(sim, steps):
+    """Time `steps` oracle steps (step loop only); returns (seconds, events)."""
     c0 = sim.counts()
     t0 = time.perf_counter()
-    sim.step(sample_steps)
+    sim.step(steps)
     dt = time.perf_counter() - t0
     c1 = sim.counts()
-    ev = (c1["e_rec"] - c0["e_rec"]) + (c1["e_ext"] - c0["e_ext"])
-    return {"value": ev / dt, "unit": "synaptic events/s", "cores": 1, "kind": "oracle",
-            "sample": "4x4 grid of the same column recipe (19,840 neurons, %d synapses), "
-                      "seed 0, %d steps after 20 warm-up steps, step loop only, %.1f s"
-                      % (len(net[1]), sample_steps, dt),
-            "sim_ms_per_wall_s": sample_steps / dt,
-            "host_cpu": host_cpu_model(), "host_threads": os.cpu_count(),
-            "plain_2x2_1s": _oracle_2x2_full()}
+    return dt, (c1["e_rec"] - c0["e_rec"]) + (c1["e_ext"] - c0["e_ext"])
+
+
+def cpu_baseline(sample_steps: int = 5000):
+    """The CPU oracle, as it stands, on bounded samples of the same workload family (network
+    construction excluded from every timing):
+      * value: the 4x4 grid of the same column recipe (19,840 neurons, ~24.6M synapses),
+        seed 0, `sample_steps` steps after 20 warm-up steps, one thread;
+      * all_cores: the same sample with the oracle's loops over neurons and spikes on every
+        host thread (OpenMP);
+      * plain_24x24: the 24x24 workload's first 200 steps on every host thread, and its first
+        40 steps on one thread;
+      * plain_2x2_1s: the whole 2x2 workload (1000 steps), one thread."""
+    import oracle
+    from paper_1511_09325_amd import workloads as W
+    nthreads = host_threads()
+    oracle.set_threads(nthreads)
+    p = W.grid(4, 4, 0)
+    net = oracle.network(p)
+    oracle.set_threads(1)
+    sim = oracle.Sim(p, net)
+    sim.step(20)
+    dt, ev = _oracle_sample(sim, sample_steps)
+    oracle.set_threads(nthreads)
+    sim_all = oracle.Sim(p, net)
+    sim_all.step(20)
+    dt_all, ev_all = _oracle_sample(sim_all, sample_steps)
+    assert ev_all == ev, "the oracle's result must not depend on its thread count"
+    del sim, sim_all, net
+    out = {"value": ev / dt, "unit": "synaptic events/s", "cores": 1, "kind": "oracle",
+           "sample": "4x4 grid of the same column recipe (19,840 neurons, 24.6M synapses), "
+                     "seed 0, %d steps after 20 warm-up steps, step loop only, one thread, "
+                     "%.1f s" % (sample_steps, dt),
+           "sim_ms_per_wall_s": sample_steps / dt,
+           "host_cpu": host_cpu_model(), "host_lscpu": host_lscpu(),
+           "nproc": os.cpu_count(), "threads_used": nthreads,
+           "all_cores": {"value": ev_all / dt_all, "unit": "synaptic events/s",
+                         "cores": nthreads, "seconds": dt_all,
+                         "sim_ms_per_wall_s": sample_steps / dt_all,
+                         "sample": "the same 4x4 sample, the oracle's loops on %d threads"
+                                   % nthreads},
+           "plain_24x24": _oracle_24x24(nthreads),
+           "plain_2x2_1s": _oracle_2x2_full()}
+    return out
+
+
+def _oracle_24x24(nthreads: int):
+    """The 24x24 workload (714,240 neurons, 885M synapses) in the oracle: its first 200 steps
+    on every host thread, and its first 40 steps (a separate run from the initial state) on
+    one thread."""
+    import oracle
+    from paper_1511_09325_amd import workloads as W
+    p = W.PLAIN_24X24["params"]
+    oracle.set_threads(nthreads)
+    t0 = time.perf_counter()
+    net = oracle.network(p)
+    t_net = time.perf_counter() - t0
+    sim = oracle.Sim(p, net)
+    dt_all, ev_all = _oracle_sample(sim, 200)
+    del sim
+    oracle.set_threads(1)
+    one = oracle.Sim(p, net)
+    dt_one, ev_one = _oracle_sample(one, 40)
+    oracle.set_threads(nthreads)
+    del one, net
+    return {"network_s_all_threads": t_net,
+            "first_200_steps_all_threads": {"events_per_s": ev_all / dt_all, "seconds": dt_all,
+                                            "cores": nthreads,
+                                            "sim_ms_per_wall_s": 200 / dt_all},
+            "first_40_steps_one_thread": {"events_per_s": ev_one / dt_one, "seconds": dt_one,
+                                          "cores": 1, "sim_ms_per_wall_s": 40 / dt_one}}
 
 
 def _oracle_2x2_full():
@@ -94,13 +163,27 @@ def _oracle_2x2_full():
     import oracle
     from paper_1511_09325_amd import workloads as W
     p, steps = W.PLAIN_2X2["params"], W.PLAIN_2X2["steps"]
+    oracle.set_threads(1)
     sim = oracle.Sim(p)
-    t0 = time.perf_counter()
-    sim.step(steps)
-    dt = time.perf_counter() - t0
-    c = sim.counts()
-    return {"events_per_s": (c["e_rec"] + c["e_ext"]) / dt, "seconds": dt,
+    dt, ev = _oracle_sample(sim, steps)
+    oracle.set_threads(host_threads())
+    return {"events_per_s": ev / dt, "seconds": dt, "cores": 1,
             "sim_ms_per_wall_s": steps * p["dt"] / dt}
+
+
+def host_threads() -> int:
+    """Host threads this process may use: OMP_NUM_THREADS when set (the host's share for the
+    job), else the CPUs of its affinity mask."""
+    try:
+        n = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        n = 0
+    if n > 0:
+        return n
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
 
 
 def host_cpu_model() -> str:
@@ -113,6 +196,26 @@ def host_cpu_model() -> str:
     except OSError:
         pass
     return ""
+
+
+def host_lscpu() -> dict:
+    """The host CPU as lscpu describes it (model, family, sockets, cores, caches, clocks)."""
+    import subprocess
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except Exception:
+        return {}
+    keep = ("Architecture", "CPU(s)", "On-line CPU(s) list", "Vendor ID", "Model name",
+            "CPU family", "Model", "Stepping", "Thread(s) per core", "Core(s) per socket",
+            "Socket(s)", "CPU max MHz", "CPU min MHz", "BogoMIPS", "L1d cache", "L2 cache",
+            "L3 cache", "NUMA node(s)", "Hypervisor vendor", "Virtualization type")
+    out = {}
+    for line in txt.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            if k.strip() in keep:
+                out[k.strip()] = v.strip()
+    return out
 
 
 def device_copy_gbs(torch, mib: int = 2048, reps: int = 10) -> float:
@@ -231,7 +334,7 @@ def fwd_bwd_leg(torch, iters=3):
         rates = S.column_rates(sim, w, tau, g, T)
         loss = ((rates - target) ** 2).mean()
         loss.backward()
-        return float(loss)
+        return float(loss.detach())
 
     iteration()                          # warm-up
     torch.cuda.synchronize()
@@ -254,66 +357,37 @@ def fwd_bwd_leg(torch, iters=3):
             "fwd_bwd_sim_ms_per_wall_s": T * p["dt"] / t_it}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's)")
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="96x96", choices=sorted(WORKLOADS))
-    ap.add_argument("--delivery", default="arrival", choices=["arrival", "push"])
-    ap.add_argument("--block", type=int, default=0, help="workgroup size (0: library default)")
-    ap.add_argument("--tile", default="auto", help="arrival tile of target columns, e.g. 4x4")
-    ap.add_argument("--gather", type=int, default=0,
-                    help="arrival form: steps gathered per pass (0: library default)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-fwd-bwd", action="store_true")
-    ap.add_argument("--no-rate-matched", action="store_true")
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="first copy a buffer of this many MiB once (a reference kernel of known "
-                         "traffic for hardware byte counters)")
-    args = ap.parse_args()
-
-    if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the path is single-GPU by design "
-              "(no sharding, no collectives); --gpus %d is not supported" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
+def plain_leg(torch, workload: str, steps, warmup: int, delivery: str = "arrival",
+              block: int = 0, tile=(0, 0), gather: int = 0, with_traffic: bool = True):
+    """One plain workload on the GPU: the network is generated, the untimed first part of the
+    workload's run is stepped (settle, then warm-up), and the last `steps` steps of the run
+    are timed -- so a short timed window measures the state the named run ends in, not its
+    start-up transient.  Returns the leg's figures with the roofline of its dominant kernel."""
     from paper_1511_09325_amd import DELIVERY_ARRIVAL, DELIVERY_PUSH, Simulation
     from paper_1511_09325_amd import workloads as W
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
-    if args.copy_calibration_mib:
-        nb = args.copy_calibration_mib << 20
-        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copied %d MiB for counter calibration" % args.copy_calibration_mib)
-        del src, dst
-    preset_name, default_steps = WORKLOADS[args.workload]
+    preset_name, run_steps = WORKLOADS[workload]
     preset = getattr(W, preset_name)
     p = preset["params"]
-    K = args.steps if args.steps is not None else default_steps
-    delivery = DELIVERY_ARRIVAL if args.delivery == "arrival" else DELIVERY_PUSH
-
+    K = steps if steps is not None else max(1, run_steps - warmup)
+    settle = max(0, run_steps - warmup - K)
+    first, last = settle + warmup, settle + warmup + K - 1
+    total = max(run_steps, last + 1)
     log("generating %s on the GPU" % preset["name"])
     t0 = time.perf_counter()
-    tile = (0, 0) if args.tile == "auto" else tuple(int(x) for x in args.tile.split("x"))
-    sim = Simulation(p, delivery=delivery, block=args.block, tile=tile, gather_steps=args.gather)
+    sim = Simulation(p, delivery=DELIVERY_ARRIVAL if delivery == "arrival" else DELIVERY_PUSH,
+                     block=block, tile=tile, gather_steps=gather)
     launch = sim.get_launch()
     sim.sync()
     t_gen = time.perf_counter() - t0
     log("generated %d neurons, %d synapses in %.1f s (%.1f GB on device)"
         % (sim.n_neurons, sim.n_synapses, t_gen, sim.device_bytes / 1e9))
-
-    sim.step(args.warmup)
+    if settle:
+        sim.step(settle)
+        sim.sync()
+        log("settled %d untimed steps" % settle)
+    sim.step(warmup)
     sim.sync()
-    log("warm-up %d steps done" % args.warmup)
+    log("warm-up %d steps done" % warmup)
     s0 = sim.stats()
     sim.set_timing(True)
     stream = torch.cuda.current_stream()
@@ -327,7 +401,8 @@ def main():
     sim.sync()
     tm = sim.timing()
     s1 = sim.stats()
-    log("timed %d steps in %.1f ms" % (K, wall_ms))
+    sim.set_timing(False)
+    log("timed steps %d-%d in %.1f ms" % (first, last, wall_ms))
 
     e_rec = s1["e_rec"] - s0["e_rec"]
     e_ext = s1["e_ext"] - s0["e_ext"]
@@ -335,55 +410,134 @@ def main():
     streamed = s1["streamed"] - s0["streamed"]
     delivered = s1["delivered"] - s0["delivered"]
     secs = wall_ms / 1e3
-    value = (e_rec + e_ext) / secs
-
-    kern = tm["update"]
-    dom_ms = kern["ms"] / max(kern["launches"], 1)
-    if args.delivery == "push":
-        # in the push form the delivery kernel streams the synapses; the update kernel the neurons
-        dk = tm["deliver"]
-        dom_ms = dk["ms"] / max(dk["launches"], 1)
-        bytes_per_launch = BYTES_PER_SYNAPSE * streamed / K
-        dom_name = "k_deliver_push"
+    N = sim.n_neurons
+    if delivery == "push":
+        # the push form's delivery kernel streams the synapses, its update kernel the neurons
+        kern, dom_name, events = tm["deliver"], "k_deliver_push", streamed
+        per_launch = BYTES_PER_EVENT * events / K
+        rec_per_launch = RECORD_BYTES_PER_SYNAPSE * streamed / K
     else:
-        bytes_per_launch = (BYTES_PER_SYNAPSE * delivered + BYTES_PER_NEURON * sim.n_neurons * K) / K
-        dom_name = "k_step_tile"
-    achieved = bytes_per_launch / (dom_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, args.delivery)
-    copy_gbs = device_copy_gbs(torch)
+        # arrival form: one fused launch per step gathers the step's arriving synapses and
+        # updates every neuron
+        kern, dom_name = tm["update"], "k_step_tile"
+        per_launch = (BYTES_PER_EVENT * delivered + BYTES_PER_NEURON * N * K) / K
+        rec_per_launch = (RECORD_BYTES_PER_SYNAPSE * delivered + RECORD_BYTES_PER_NEURON * N * K) / K
+    dom_ms = kern["ms"] / max(kern["launches"], 1)
+    achieved = per_launch / (dom_ms * 1e-3) / 1e9
+    key = traffic_key(workload, delivery, first, last)
+    traffic = measured_traffic(key) if with_traffic else None
+    roof = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_source": ("profiles/traffic.json [%s]" % key) if traffic else None,
+            "avg_launch_ms": dom_ms, "launches": kern["launches"],
+            "algorithmic_bytes_per_launch": per_launch,
+            "bytes_per_unit": "%d B per recurrent event delivered + %d B per neuron per step"
+                              % (BYTES_PER_EVENT, BYTES_PER_NEURON),
+            "events_delivered_per_launch": delivered / K,
+            "synapse_records_read_per_launch": streamed / K,
+            "record_layout": {"bytes_per_launch": rec_per_launch,
+                              "achieved": rec_per_launch / (dom_ms * 1e-3) / 1e9,
+                              "frac": rec_per_launch / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "bytes_per_unit": "%d B per delivered synapse record + %d B per "
+                                                "neuron per step (the kernel's own layout)"
+                                                % (RECORD_BYTES_PER_SYNAPSE, RECORD_BYTES_PER_NEURON)}}
+    if traffic:
+        roof["traffic_over_algorithmic"] = traffic / per_launch
+        roof["traffic_over_record_layout"] = traffic / rec_per_launch
+    out = {"workload": "%s; timed steps %d-%d of the %d-step run"
+                       % (preset["name"], first, last, total),
+           "grid": workload, "neurons": N, "synapses": sim.n_synapses, "dt_ms": p["dt"],
+           "settle_steps": settle, "first_timed_step": first, "last_timed_step": last,
+           "delivery": delivery, "block": launch["block"], "tile": "%dx%d" % launch["tile"],
+           "gather_steps": launch["gather_steps"],
+           "steps": K, "ms_per_step": wall_ms / K, "events_per_s": (e_rec + e_ext) / secs,
+           "sim_ms_per_wall_s": K * p["dt"] / secs, "recurrent_events_per_s": e_rec / secs,
+           "external_events_per_s": e_ext / secs,
+           "mean_rate_hz": spikes / (N * K * p["dt"] * 1e-3), "generation_s": t_gen,
+           "roofline": roof}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
 
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps, the last of the workload's run (default: all of the run "
+                         "after the warm-up)")
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="96x96", choices=sorted(WORKLOADS))
+    ap.add_argument("--delivery", default="arrival", choices=["arrival", "push"])
+    ap.add_argument("--block", type=int, default=0, help="workgroup size (0: library default)")
+    ap.add_argument("--tile", default="auto", help="arrival tile of target columns, e.g. 4x4")
+    ap.add_argument("--gather", type=int, default=0,
+                    help="arrival form: steps gathered per pass (0: library default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-fwd-bwd", action="store_true")
+    ap.add_argument("--no-rate-matched", action="store_true")
+    ap.add_argument("--no-small-grids", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy a buffer of this many MiB once (a reference kernel of known "
+                         "traffic for hardware byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the path is single-GPU by design "
+              "(no sharding, no collectives); --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d MiB for counter calibration" % args.copy_calibration_mib)
+        del src, dst
+    tile = (0, 0) if args.tile == "auto" else tuple(int(x) for x in args.tile.split("x"))
+    main_leg = plain_leg(torch, args.workload, args.steps, args.warmup, args.delivery,
+                         args.block, tile, args.gather)
+    roof = main_leg.pop("roofline")
+    copy_gbs = device_copy_gbs(torch)
+    roof["device_copy_gbs"] = copy_gbs
+    roof["frac_of_copy"] = roof["achieved"] / copy_gbs
+    K = main_leg["steps"]
     out = {
         "metric": "synaptic events/s (recurrent + external) and sim-ms per wall-s",
-        "value": value,
+        "value": main_leg["events_per_s"],
         "unit": "synaptic events/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
-        "ms_per_step": wall_ms / K,
+        "ms_per_step": main_leg["ms_per_step"],
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": "strong",
         "vs_baseline": None,
         "dtype": "int32 input, f32 state",
         "data": "synthetic (seeded network and Poisson input of the column recipe)",
-        "config": {"workload": preset["name"], "grid": args.workload, "neurons": sim.n_neurons,
-                   "synapses": sim.n_synapses, "dt_ms": p["dt"], "delivery": args.delivery,
-                   "block": launch["block"], "tile": "%dx%d" % launch["tile"],
-                   "gather_steps": launch["gather_steps"],
-                   "parallelism": "single GPU"},
-        "sim_ms_per_wall_s": K * p["dt"] / secs,
-        "recurrent_events_per_s": e_rec / secs,
-        "external_events_per_s": e_ext / secs,
-        "mean_rate_hz": spikes / (sim.n_neurons * K * p["dt"] * 1e-3),
-        "generation_s": t_gen,
-        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "avg_launch_ms": dom_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "synapse_records_read_per_launch": streamed / K,
-                     "device_copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+        "config": dict({k: main_leg[k] for k in (
+            "workload", "grid", "neurons", "synapses", "dt_ms", "settle_steps",
+            "first_timed_step", "last_timed_step", "delivery", "block", "tile",
+            "gather_steps")}, parallelism="single GPU"),
+        "sim_ms_per_wall_s": main_leg["sim_ms_per_wall_s"],
+        "recurrent_events_per_s": main_leg["recurrent_events_per_s"],
+        "external_events_per_s": main_leg["external_events_per_s"],
+        "mean_rate_hz": main_leg["mean_rate_hz"],
+        "generation_s": main_leg["generation_s"],
+        "roofline": roof,
     }
-    del sim
-    torch.cuda.empty_cache()
+    if not args.no_small_grids and args.workload == "96x96":
+        log("small-grid legs: the whole 24x24 (10 s) and 2x2 (1 s) workloads")
+        out["small_grids"] = {w: plain_leg(torch, w, None, args.warmup) for w in ("24x24", "2x2")}
     if not args.no_batched:
         log("batched leg: 64 networks, one launch per step, vs 64 sequential runs")
         out["batched"] = batched_leg(torch)
@@ -394,7 +548,7 @@ def main():
         log("forward+backward leg: 4x4, 500 steps, vs the plain forward")
         out["fwd_bwd"] = fwd_bwd_leg(torch)
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle sample")
+        log("timing the CPU oracle samples")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 

@@ -28,8 +28,8 @@ def build(force: bool = True) -> str:
     srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-Wall", "-o", tmp] + srcs + ["-lm"]
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-o", tmp] + srcs + ["-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _SO)
     return _SO
@@ -72,6 +72,8 @@ def lib():
             P(C.c_double), P(C.c_uint64))
         cp = P(_Cfg)
         sig = {
+            "orc_set_threads": (None, [C.c_int32]),
+            "orc_threads": (C.c_int32, []),
             "orc_philox": (None, [u32p, u32p, u32p]),
             "orc_column_probability": (C.c_double, [cp, C.c_int32, C.c_int32]),
             "orc_pair": (C.c_int, [cp, C.c_int64, C.c_int64, i32p, i16p]),
@@ -114,6 +116,16 @@ def lib():
             fn.argtypes = args
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Host threads of the oracle's loops over independent rows and neurons (results do not
+    depend on it)."""
+    lib().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
 
 
 def _ptr(a, ctype):

@@ -11,6 +11,30 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------------------
+ * Threads.  Loops over independent rows or neurons may run on several host threads
+ * (OpenMP); every result is the same for any thread count, because each row or neuron is
+ * computed on its own and the synaptic input is an integer sum (order independent).
+ * ------------------------------------------------------------------------- */
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
+int32_t orc_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ---------------------------------------------------------------------------
  * Philox4x32-10, from its published definition (Salmon, Moraes, Dror, Shaw,
@@ -144,17 +168,60 @@ int64_t orc_row(const orc_config_t* cfg, int64_t i, int32_t* tgt, uint8_t* dly, 
   return n;
 }
 
+/* The whole network: every row by orc_row.  Rows are independent, so blocks of rows are
+ * built in parallel, each into a buffer of its own, and then laid out in row order. */
 int64_t orc_network(const orc_config_t* cfg, int64_t* row_ptr, int32_t* tgt, uint8_t* dly,
                     int16_t* wq, int64_t cap) {
-  int64_t n = (int64_t)cfg->rows * cfg->cols * cfg->npc;
+  const int64_t n = (int64_t)cfg->rows * cfg->cols * cfg->npc;
+  const int64_t B = 256;                 /* rows per block */
+  const int64_t nb = (n + B - 1) / B;
+  const int64_t row_cap = 9 * (int64_t)cfg->npc;
+  int32_t** btgt = (int32_t**)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int32_t*));
+  uint8_t** bdly = (uint8_t**)calloc((size_t)(nb > 0 ? nb : 1), sizeof(uint8_t*));
+  int16_t** bwq = (int16_t**)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int16_t*));
+  int failed = 0;
   row_ptr[0] = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    int64_t len = orc_row(cfg, i, tgt + row_ptr[i], dly + row_ptr[i], wq + row_ptr[i],
-                          cap - row_ptr[i]);
-    if (len < 0) return -1;
-    row_ptr[i + 1] = row_ptr[i] + len;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t i0 = b * B, i1 = i0 + B < n ? i0 + B : n;
+    const int64_t bcap = (i1 - i0) * row_cap;
+    int32_t* t = (int32_t*)malloc(sizeof(int32_t) * (size_t)bcap);
+    uint8_t* d = (uint8_t*)malloc((size_t)bcap);
+    int16_t* w = (int16_t*)malloc(sizeof(int16_t) * (size_t)bcap);
+    int64_t used = 0;
+    for (int64_t i = i0; i < i1 && t && d && w; ++i) {
+      const int64_t len = orc_row(cfg, i, t + used, d + used, w + used, bcap - used);
+      if (len < 0) break;
+      row_ptr[i + 1] = len;  /* the row's length for now; turned into offsets below */
+      used += len;
+    }
+    btgt[b] = t;
+    bdly[b] = d;
+    bwq[b] = w;
+    if (!t || !d || !w) {
+#pragma omp atomic write
+      failed = 1;
+    }
   }
-  return row_ptr[n];
+  for (int64_t i = 0; i < n && !failed; ++i) row_ptr[i + 1] += row_ptr[i];
+  if (!failed && row_ptr[n] > cap) failed = 1;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t b = 0; b < nb; ++b) {
+    if (!failed) {
+      const int64_t i0 = b * B, i1 = i0 + B < n ? i0 + B : n;
+      const int64_t o = row_ptr[i0], len = row_ptr[i1] - row_ptr[i0];
+      memcpy(tgt + o, btgt[b], sizeof(int32_t) * (size_t)len);
+      memcpy(dly + o, bdly[b], (size_t)len);
+      memcpy(wq + o, bwq[b], sizeof(int16_t) * (size_t)len);
+    }
+    free(btgt[b]);
+    free(bdly[b]);
+    free(bwq[b]);
+  }
+  free(btgt);
+  free(bdly);
+  free(bwq);
+  return failed ? -1 : row_ptr[n];
 }
 
 /* ---------------------------------------------------------------------------
@@ -192,6 +259,7 @@ static uint32_t ext_uniform(const orc_config_t* cfg, int64_t j, int64_t u) {
 void orc_ext_counts(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n, int32_t* out) {
   uint64_t tab[63];
   orc_poisson_table((double)cfg->ext_syn * cfg->ext_rate_hz * cfg->dt * 1e-3, tab);
+#pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < n; ++q) out[q] = orc_poisson_count(tab, ext_uniform(cfg, j0 + q, u));
 }
 
@@ -222,6 +290,7 @@ struct orc_sim {
   uint8_t* ref;
   uint32_t* ring;       /* [D][n]; slot u % D holds the input of step u */
   int64_t now;
+  uint8_t* spiked;      /* [n] spike flags of the step being computed */
   /* raster: spike ids of all steps, with per-step offsets */
   int32_t* sp_ids; int64_t sp_n, sp_cap;
   int64_t* sp_off; int64_t off_cap;
@@ -244,6 +313,7 @@ orc_sim_t* orc_sim_create(const orc_config_t* cfg, int64_t n, const int64_t* row
   s->ca = (float*)calloc((size_t)n, sizeof(float));
   s->ref = (uint8_t*)calloc((size_t)n, 1);
   s->ring = (uint32_t*)calloc((size_t)s->D * (size_t)n, sizeof(uint32_t));
+  s->spiked = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
   for (int64_t j = 0; j < n; ++j) s->v[j] = orc_initial_v(cfg, j);
   s->off_cap = 1024;
   s->sp_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)s->off_cap);
@@ -255,7 +325,7 @@ orc_sim_t* orc_sim_create(const orc_config_t* cfg, int64_t n, const int64_t* row
 
 void orc_sim_destroy(orc_sim_t* s) {
   if (!s) return;
-  free(s->v); free(s->ca); free(s->ref); free(s->ring);
+  free(s->v); free(s->ca); free(s->ref); free(s->ring); free(s->spiked);
   free(s->sp_ids); free(s->sp_off);
   free(s->r_vprev); free(s->r_caprev); free(s->r_vt); free(s->r_s); free(s->r_r);
   free(s->r_in);
@@ -353,6 +423,7 @@ void orc_update_many(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n,
   consts_t k = constants_of(cfg);
   int32_t* n_ext = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
   orc_ext_counts(cfg, u, j0, n, n_ext);
+#pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < n; ++q) {
     float vt; int refr; uint32_t a;
     spk[q] = (uint8_t)neuron_update(&k, (uint32_t)rec_input[q], n_ext[q], &v[q], &ca[q], &ref[q],
@@ -370,6 +441,7 @@ void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets
                      int64_t t_emit_max, const uint8_t* mask, int64_t mask_t0, int64_t mask_steps,
                      int32_t* out) {
   const int64_t n = (int64_t)cfg->rows * cfg->cols * cfg->npc;
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t t = 0; t < nt; ++t) {
     const int64_t j = targets[t];
     const int32_t cj = (int32_t)(j / cfg->npc);
@@ -408,7 +480,10 @@ void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets
  *     outgoing synapse of a spiking neuron is one recurrent event; each external arrival
  *     is one external event);
  *  3. every synapse i->j of delay d of a spiking neuron i adds its efficacy to
- *     ring[(u + d) % D][j]. */
+ *     ring[(u + d) % D][j].
+ * Neurons (1) and spikes (3) are independent of each other, so both loops may run on
+ * several threads; the additions into the ring are atomic and the spike list is collected
+ * in ascending order afterwards. */
 int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
   consts_t k = constants_of(&s->cfg);
   for (int64_t it = 0; it < n_steps; ++it) {
@@ -416,7 +491,9 @@ int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
     int64_t slot = u % s->D;
     uint32_t* in = s->ring + slot * s->n;
     int64_t first = s->sp_n;
+    int64_t consumed = 0, e_ext = 0, e_rec = 0;
     if (s->rec_on) grow_record(s);
+#pragma omp parallel for schedule(static) reduction(+ : consumed, e_ext)
     for (int64_t j = 0; j < s->n; ++j) {
       int32_t next = orc_poisson_count(s->ptab, ext_uniform(&s->cfg, j, u));
       float vprev = s->v[j], caprev = s->ca[j], vt;
@@ -424,24 +501,43 @@ int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
       uint32_t a;
       int spike = neuron_update(&k, in[j], next, &s->v[j], &s->ca[j], &s->ref[j], &vt, &refr, &a);
       in[j] = 0;
-      s->consumed += (int64_t)(int32_t)a;
-      if (spike) push_spike(s, (int32_t)j);
-      s->e_ext += next;
+      consumed += (int64_t)(int32_t)a;
+      s->spiked[j] = (uint8_t)spike;
+      e_ext += next;
       if (s->rec_on) {
         size_t o = (size_t)s->rec_n * (size_t)s->n + (size_t)j;
         s->r_vprev[o] = vprev; s->r_caprev[o] = caprev; s->r_vt[o] = vt;
         s->r_s[o] = (uint8_t)spike; s->r_r[o] = (uint8_t)refr; s->r_in[o] = (int32_t)a;
       }
     }
+    s->consumed += consumed;
+    s->e_ext += e_ext;
+    for (int64_t j = 0; j < s->n; ++j)
+      if (s->spiked[j]) push_spike(s, (int32_t)j);
     if (s->rec_on) s->rec_n += 1;
-    for (int64_t q = first; q < s->sp_n; ++q) {
-      int64_t i = s->sp_ids[q];
-      s->e_rec += s->row_ptr[i + 1] - s->row_ptr[i];
-      for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
-        int64_t dst = ((u + s->dly[e]) % s->D) * s->n + s->tgt[e];
-        s->ring[dst] += (uint32_t)s->w32[e];
+    if (orc_threads() == 1) {
+      for (int64_t q = first; q < s->sp_n; ++q) {
+        int64_t i = s->sp_ids[q];
+        e_rec += s->row_ptr[i + 1] - s->row_ptr[i];
+        for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
+          int64_t dst = ((u + s->dly[e]) % s->D) * s->n + s->tgt[e];
+          s->ring[dst] += (uint32_t)s->w32[e];
+        }
+      }
+    } else {
+      /* the same loop over spikes on several threads, each addition atomic */
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : e_rec)
+      for (int64_t q = first; q < s->sp_n; ++q) {
+        int64_t i = s->sp_ids[q];
+        e_rec += s->row_ptr[i + 1] - s->row_ptr[i];
+        for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
+          int64_t dst = ((u + s->dly[e]) % s->D) * s->n + s->tgt[e];
+#pragma omp atomic update
+          s->ring[dst] += (uint32_t)s->w32[e];
+        }
       }
     }
+    s->e_rec += e_rec;
     s->now += 1;
     if (s->now >= s->off_cap) {
       s->off_cap *= 2;

@@ -65,6 +65,11 @@ typedef struct {
   double j_ext;         /* external synaptic efficacy, mV */
 } orc_config_t;
 
+/* Host threads of the loops over independent rows and neurons (OpenMP); results do not
+ * depend on the thread count. */
+void orc_set_threads(int32_t n);
+int32_t orc_threads(void);
+
 /* Philox4x32-10 block function. */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 

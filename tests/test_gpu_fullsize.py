@@ -1,8 +1,11 @@
-"""Spot-step parity at the full 24x24 and 96x96 grids (needs an MI355X).
+"""Parity at the full 24x24 and 96x96 grids (needs an MI355X).
 
-The oracle cannot run these networks whole (the 96x96 grid has 14.2G synapses), so each
-check uses only what the oracle can compute one by one, in the launch configuration that
-bench.py times (arrival form, default workgroup and tile):
+The 24x24 grid's first 200 steps are compared with the whole oracle (its network of 885M
+synapses is built on every host thread, about 20-40 s).  Beyond that, and at 96x96 (14.2G
+synapses), each check uses only what the oracle can compute one by one, in the launch
+configuration that bench.py times (arrival form, default workgroup and tile), early in the
+run and late in it, where the network fires at its steady rate (tens of Hz, bursty) and the
+gather windows, work-ordered tiles and large per-tile spike counts are all in play:
   * synapse rows of sampled source neurons, bit for bit against the generator's definition;
   * the pending input of sampled target neurons at sampled steps, bit for bit against the
     brute-force sum over every candidate synapse whose source spiked (from the GPU raster);
@@ -73,10 +76,14 @@ def _spot_step(sim, p, u, rng, n_targets):
     return int(spk.sum())
 
 
+LATE_24 = (1000, 1001)   # a gathering step of the window and the light step after it
+LATE_96 = (1500, 1501)
+
+
 @pytest.fixture(scope="module")
 def sim24():
     p = W.PLAIN_24X24["params"]
-    sim = Simulation(p, record_steps=200)
+    sim = Simulation(p, record_steps=LATE_24[-1] + 1)
     yield p, sim
     sim.close()
 
@@ -94,10 +101,40 @@ def test_24x24_spot_steps(sim24, u):
         assert spikes > 0
 
 
+def test_24x24_first_200_steps_equal_the_oracle(sim24):
+    """The whole 24x24 network in the oracle: the GPU raster of steps 0-199 and the state
+    after step 199 (V, Ca, refractory counters, pending input) equal it bit for bit."""
+    import oracle as O
+    p, sim = sim24
+    T = 200
+    assert sim.now <= T
+    sim.step(T - sim.now)
+    ref = O.Sim(p)
+    ref.step(T)
+    got = sim.read_spikes(0, 0, T)
+    for u in range(T):
+        assert np.array_equal(got[u], ref.spikes(u)), u
+    a, b = sim.state(0), ref.state()
+    for k in ("v", "ca", "ref", "pend"):
+        assert np.array_equal(a[k], b[k]), k
+    st, rc = sim.stats(0), ref.counts()
+    assert (st["spikes"], st["e_rec"], st["e_ext"]) == (rc["spikes"], rc["e_rec"], rc["e_ext"])
+    assert rc["spikes"] > 0
+
+
+@pytest.mark.parametrize("u", LATE_24)
+def test_24x24_late_spot_steps(sim24, u):
+    p, sim = sim24
+    launch = sim.get_launch()
+    assert launch["gather_steps"] > 1 and LATE_24[0] % launch["gather_steps"] == 0
+    spikes = _spot_step(sim, p, u, np.random.default_rng(u), 800)
+    assert spikes > 0.002 * sim.n_neurons  # the steady state: some Hz at least
+
+
 @pytest.fixture(scope="module")
 def sim96():
     p = W.PLAIN_96X96["params"]
-    sim = Simulation(p, record_steps=80)
+    sim = Simulation(p, record_steps=LATE_96[-1] + 1)
     yield p, sim
     sim.close()
     import torch
@@ -114,6 +151,17 @@ def test_96x96_spot_steps(sim96, u):
     p, sim = sim96
     spikes = _spot_step(sim, p, u, np.random.default_rng(u), 300)
     assert spikes > 0
+
+
+@pytest.mark.parametrize("u", LATE_96)
+def test_96x96_late_spot_steps(sim96, u):
+    """Step 1500 (a gathering step of the three-step window) and step 1501 (the light step
+    after it), three quarters into the 2 s run: the regime bench.py times."""
+    p, sim = sim96
+    launch = sim.get_launch()
+    assert launch["gather_steps"] > 1 and LATE_96[0] % launch["gather_steps"] == 0
+    spikes = _spot_step(sim, p, u, np.random.default_rng(u), 300)
+    assert spikes > 0.005 * sim.n_neurons  # the steady state fires at tens of Hz
 
 
 def test_batched_workload_members_equal_their_plain_runs():

@@ -280,3 +280,28 @@ def test_bulk_update_matches_the_simulation_step():
         assert np.array_equal(np.flatnonzero(spk), sim.spikes(u))
         assert np.array_equal(v, after["v"]) and np.array_equal(ca, after["ca"])
         assert np.array_equal(ref, after["ref"])
+
+
+def test_thread_count_does_not_change_the_oracle():
+    """The oracle's loops over rows, neurons and spikes may run on several host threads; the
+    network, the raster, the state and the counters are the same bits for one thread and
+    for many (each row and neuron is computed on its own; the input is an integer sum)."""
+    p = W.tiny(3, 3, npc=60, seed=41)
+    T = 150
+    before = oracle.threads()
+    try:
+        out = []
+        for nt in (1, 4):
+            oracle.set_threads(nt)
+            net = oracle.network(p)
+            sim = oracle.Sim(p, net)
+            sim.step(T)
+            out.append((net, sim.raster(0, T), sim.state(), sim.counts()))
+    finally:
+        oracle.set_threads(before)
+    (n1, r1, s1, c1), (n4, r4, s4, c4) = out
+    assert all(np.array_equal(a, b) for a, b in zip(n1, n4))
+    assert all(np.array_equal(a, b) for a, b in zip(r1, r4))
+    for k in ("v", "ca", "ref", "pend"):
+        assert np.array_equal(s1[k], s4[k]), k
+    assert c1 == c4 and c1["spikes"] > 0
