@@ -134,6 +134,15 @@ int sim_sync(sim_t* sim);
 int sim_read_spikes(sim_t* sim, int32_t net, int64_t t0, int64_t t1, int64_t* step_offsets,
                     int32_t* ids, int64_t ids_cap, int64_t* n_ids);
 
+/* sim_read_spikes for callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): same arguments, results and
+ * errors, but no device or host allocation.  Its device scratch is a file-scope array of
+ * 16 MiB per device, held until the process ends, which bounds one call to 24 bytes per step
+ * of [t0, t1) plus 4 bytes per id returned (DPSNN_EINVAL beyond).  Every call on one device
+ * shares that array, so calls that overlap on one device race.  Synchronises. */
+int sim_read_spikes_static(sim_t* sim, int32_t net, int64_t t0, int64_t t1,
+                           int64_t* step_offsets, int32_t* ids, int64_t ids_cap, int64_t* n_ids);
+
 /* Train mode: go back to the state at step 0 (the initial state) and start a new recorded
  * window; counters and per-column spike counts restart from zero. */
 int sim_rewind(sim_t* sim);

@@ -20,6 +20,7 @@ EXPORTS = [
     "sim_read_synapses", "sim_save", "sim_restore", "sim_set_weights", "sim_get_weights",
     "sim_set_params", "sim_get_launch", "sim_set_launch", "sim_set_timing", "sim_get_timing",
     "sim_state_digest", "sim_autotune", "sim_rewind", "sim_column_rates",
+    "sim_read_spikes_static",
 ]
 
 
@@ -87,6 +88,9 @@ def lib():
         "sim_sync": (C.c_int, [vp]),
         "sim_read_spikes": (C.c_int, [vp, C.c_int32, C.c_int64, C.c_int64, P(C.c_int64),
                                       P(C.c_int32), C.c_int64, P(C.c_int64)]),
+        "sim_read_spikes_static": (C.c_int, [vp, C.c_int32, C.c_int64, C.c_int64,
+                                             P(C.c_int64), P(C.c_int32), C.c_int64,
+                                             P(C.c_int64)]),
         "sim_backward": (C.c_int, [vp, vp, vp, P(C.c_double), P(C.c_double)]),
         "sim_last_error": (C.c_char_p, [vp]),
         "sim_get_info": (C.c_int, [vp, P(SimInfo)]),

@@ -215,6 +215,13 @@ __global__ __launch_bounds__(256) void k_raster_take(const int32_t* ras_ids,
   }
 }
 
+// Length of each of those ranges: len[i] = bounds[2i + 1] - bounds[2i].
+__global__ __launch_bounds__(256) void k_raster_lengths(const int64_t* bounds, int64_t nsteps,
+                                                        int64_t* len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nsteps) len[i] = bounds[2 * i + 1] - bounds[2 * i];
+}
+
 }  // namespace
 
 // One network's spikes of steps [t0, t0 + nsteps) from the raster (synchronous): bounds
@@ -233,6 +240,14 @@ hipError_t launch_raster_take(const sim& s, int64_t nsteps, const int64_t* bound
   if (nsteps <= 0 || n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_raster_take, dim3((unsigned)nsteps), dim3(256), 0, s.stream, s.ras_ids,
                      bounds, dst_off, lo, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_lengths(const sim& s, int64_t nsteps, const int64_t* bounds,
+                                 int64_t* len) {
+  if (nsteps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_raster_lengths, dim3((unsigned)((nsteps + 255) / 256)), dim3(256), 0,
+                     s.stream, bounds, nsteps, len);
   return hipGetLastError();
 }
 

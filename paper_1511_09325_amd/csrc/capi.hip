@@ -677,6 +677,7 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     s->nets.assign(cfg->nets, cfg->nets + cfg->n_nets);
     s->cfg.nets = s->nets.data();
     s->stream = (hipStream_t)hip_stream;
+    HIPCHK(hipGetDevice(&s->device));
     s->n_nets = cfg->n_nets;
     s->npc = cfg->npc;
     s->nd = cfg->d_max - cfg->d_min + 1;

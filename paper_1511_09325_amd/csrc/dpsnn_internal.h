@@ -240,6 +240,7 @@ struct sim {
   sim_config_t cfg;
   std::vector<sim_net_t> nets;
   hipStream_t stream = nullptr;
+  int device = 0;                   // HIP device current at creation
   std::string err;
   int sticky = 0;
 
@@ -373,6 +374,8 @@ hipError_t launch_raster_bounds(const sim& s, int64_t t0, int64_t nsteps, int32_
                                 int64_t* bounds);
 hipError_t launch_raster_take(const sim& s, int64_t nsteps, const int64_t* bounds,
                               const int64_t* dst_off, int32_t lo, int64_t n, int32_t* out);
+hipError_t launch_raster_lengths(const sim& s, int64_t nsteps, const int64_t* bounds,
+                                 int64_t* len);
 hipError_t launch_adjoint_window(const sim& s, int64_t top, int64_t lo, const float* grad_rates,
                                  float scale, float beta, int64_t* next);
 bool adjoint_col_fits(int32_t npc, int32_t d_min, int32_t d_max);
