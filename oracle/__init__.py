@@ -107,7 +107,8 @@ def lib():
         sig["orc_adjoint"] = (C.c_int, [
             ap, C.c_int64, C.c_int64, i64p, i32p, u8p, f64p,   # params, n, T, csr, w (mV)
             f64p, f64p, f64p, f64p, u8p,                        # v_prev, ca_prev, v_tilde, s, r
-            f64p, f64p, f64p, f64p])                            # dL/ds, grad_w, grad_pm, grad_gamma
+            f64p, f64p, f64p, f64p, f64p])                      # dL/ds, dL/dV~, grad_w, grad_pm,
+                                                                # grad_gamma
         sig["orc_soft_forward"] = (C.c_int, [
             cp, ap, C.c_int64, C.c_int64, i64p, i32p, u8p, f64p, f64p, f64p, f64p, f64p])
         for name, (res, args) in sig.items():
@@ -379,8 +380,9 @@ def _adj_params(consts: dict, beta: float):
     return a
 
 
-def adjoint(consts: dict, beta: float, net, w_mv, traj: dict, dl_ds):
-    """FP64 reverse recursion over a trajectory; returns (grad_w, grad_pm, grad_gamma)."""
+def adjoint(consts: dict, beta: float, net, w_mv, traj: dict, dl_ds, dl_dvt=None):
+    """FP64 reverse recursion over a trajectory; returns (grad_w, grad_pm, grad_gamma).
+    dl_dvt: optional direct dL/dV~ ([T][n])."""
     row_ptr, tgt, dly = (np.ascontiguousarray(net[0], np.int64),
                          np.ascontiguousarray(net[1], np.int32),
                          np.ascontiguousarray(net[2], np.uint8))
@@ -391,13 +393,15 @@ def adjoint(consts: dict, beta: float, net, w_mv, traj: dict, dl_ds):
     r = np.ascontiguousarray(traj.get("r", np.zeros((T, n), np.uint8)), np.uint8)
     w = f(w_mv)
     dl = f(dl_ds)
+    dv = None if dl_dvt is None else f(dl_dvt)
     gw = np.zeros(len(tgt), np.float64)
     gpm, ggam = C.c_double(), C.c_double()
     k = _adj_params(consts, beta)
     rc = lib().orc_adjoint(C.byref(k), n, T, _ptr(row_ptr, C.c_int64), _ptr(tgt, C.c_int32),
                            _ptr(dly, C.c_uint8), _ptr(w, C.c_double), _ptr(vp, C.c_double),
                            _ptr(cp, C.c_double), _ptr(vt, C.c_double), _ptr(s, C.c_double),
-                           _ptr(r, C.c_uint8), _ptr(dl, C.c_double), _ptr(gw, C.c_double),
+                           _ptr(r, C.c_uint8), _ptr(dl, C.c_double),
+                           None if dv is None else _ptr(dv, C.c_double), _ptr(gw, C.c_double),
                            C.byref(gpm), C.byref(ggam))
     assert rc == 0
     return gw, gpm.value, ggam.value

@@ -25,6 +25,11 @@
  * sigma' is the fast-sigmoid surrogate 1 / (1 + beta |x|)^2.  The same code is the exact
  * gradient of the soft model, whose spike is S(x) = 1/beta + x / (1 + beta |x|) (so that
  * S' = sigma'), with no refractory period.
+ *
+ * A loss may also depend on V~ directly: dl_dvt (nullable) adds dL/dV~(u)|direct inside the
+ * bracket of nu.  With sigma' = 0 (beta -> infinity) and the spikes and refractory flags
+ * held fixed, the recursion is then the exact gradient of the step with a frozen spike mask
+ * (refractory steps hold V at V_reset, reset where s = 1), which finite differences check.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -40,7 +45,8 @@ static double surrogate(double x, double beta) {
 int orc_adjoint(const orc_adj_params_t* k, int64_t n, int64_t T, const int64_t* row_ptr,
                 const int32_t* tgt, const uint8_t* dly, const double* w, const double* v_prev,
                 const double* ca_prev, const double* v_tilde, const double* s, const uint8_t* r,
-                const double* dl_ds, double* grad_w, double* grad_pm, double* grad_gamma) {
+                const double* dl_ds, const double* dl_dvt, double* grad_w, double* grad_pm,
+                double* grad_gamma) {
   int32_t dmax = 0;
   for (int64_t e = 0; e < row_ptr[n]; ++e)
     if (dly[e] > dmax) dmax = dly[e];
@@ -62,7 +68,10 @@ int orc_adjoint(const orc_adj_params_t* k, int64_t n, int64_t T, const int64_t* 
       }
       double ej = dl_ds[o] + gsum + lam[j] * (k->vreset - v_tilde[o]) + k->alpha * mu[j];
       double nuj = 0.0;
-      if (!r[o]) nuj = lam[j] * (1.0 - s[o]) + ej * surrogate(v_tilde[o] - k->theta, k->beta);
+      if (!r[o]) {
+        nuj = lam[j] * (1.0 - s[o]) + ej * surrogate(v_tilde[o] - k->theta, k->beta);
+        if (dl_dvt) nuj = nuj + dl_dvt[o];
+      }
       nu[o] = nuj;
       gpm += v_prev[o] * nuj;
       ggam += -ca_prev[o] * nuj;

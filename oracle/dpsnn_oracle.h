@@ -157,12 +157,14 @@ typedef struct {
 } orc_adj_params_t;
 
 /* Reverse recursion over a recorded trajectory ([T][n] arrays; s may be soft, r = refractory
- * flags).  w in mV per synapse of the CSR.  dl_ds: direct dL/ds, [T][n].  Outputs: dL/dw per
- * synapse, dL/dP_m, dL/dgamma.  Returns 0, or -1 if out of memory. */
+ * flags).  w in mV per synapse of the CSR.  dl_ds: direct dL/ds, [T][n]; dl_dvt (nullable):
+ * direct dL/dV~, [T][n].  Outputs: dL/dw per synapse, dL/dP_m, dL/dgamma.  Returns 0, or -1
+ * if out of memory. */
 int orc_adjoint(const orc_adj_params_t* k, int64_t n, int64_t T, const int64_t* row_ptr,
                 const int32_t* tgt, const uint8_t* dly, const double* w, const double* v_prev,
                 const double* ca_prev, const double* v_tilde, const double* s, const uint8_t* r,
-                const double* dl_ds, double* grad_w, double* grad_pm, double* grad_gamma);
+                const double* dl_ds, const double* dl_dvt, double* grad_w, double* grad_pm,
+                double* grad_gamma);
 
 /* Smooth version of the step in FP64 (soft spike, soft reset and delivery, no refractory
  * period); records the trajectory ([T][n] outputs). */
