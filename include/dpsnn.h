@@ -24,6 +24,8 @@
  *     grid shape, seed and external rate.
  *   - Synaptic input is integer fixed point (int32 at 2^-16 mV, wrap-around addition),
  *     so results do not depend on the order in which spikes are delivered.
+ *   - Each call names the passage of the paper that defines what it computes, or says that
+ *     it is part of the workload contract or of the library's own runtime (not in the paper).
  */
 #ifndef DPSNN_H
 #define DPSNN_H
@@ -96,8 +98,47 @@ typedef struct {
   int64_t n_neurons;     /* all networks */
   int64_t n_synapses;    /* all networks */
   int32_t ring_slots;    /* d_max + 1 */
-  int64_t device_bytes;  /* device memory held */
+  int64_t device_bytes;  /* device memory the library allocated and holds */
+  int64_t caller_bytes;  /* device memory of the caller's buffers (sim_buffers_t) in use */
 } sim_info_t;
+
+/* Sizes of the device memory a configuration needs in the four regions a caller may own
+ * (sim_query_sizes).  Every region is one contiguous buffer, 256-byte aligned; its arrays
+ * sit at 256-byte aligned offsets in a fixed order:
+ *   synapses  the synapse records (uint32, padding included, n_records + 4)
+ *   index     the row starts (int64 [N+1]), the out-degrees (int32 [N]) and the per-part row
+ *             index of the store
+ *   state     V (float32 [N]) at state_v_offset, Ca (float32 [N]) at state_ca_offset and the
+ *             refractory counters (uint8 [N]) at state_ref_offset, N = n_neurons, neurons of
+ *             all networks in network order
+ *   history   the spike history of the last d_max + 1 steps and its per-part entries
+ * The library's other memory (column and tile tables, snapshots, the push ring, train-mode
+ * buffers) it always allocates itself. */
+typedef struct {
+  int64_t n_neurons;       /* all networks */
+  int64_t n_records;       /* records of the synapse store, group padding included */
+  uint64_t synapse_bytes;
+  uint64_t index_bytes;
+  uint64_t state_bytes;
+  uint64_t history_bytes;
+  uint64_t state_v_offset, state_ca_offset, state_ref_offset;  /* bytes into the state region */
+} sim_sizes_t;
+
+/* Caller-owned device memory for sim_create (for example torch tensors): any of the four
+ * regions may be NULL (the library then allocates it); a given region must be 256-byte
+ * aligned and hold at least the bytes sim_query_sizes reports.  The caller keeps the buffers
+ * alive until sim_destroy and must not touch them while the simulation runs, except to read
+ * the state region between synchronising calls. */
+typedef struct {
+  void* synapses;
+  uint64_t synapse_bytes;
+  void* index;
+  uint64_t index_bytes;
+  void* state;
+  uint64_t state_bytes;
+  void* history;
+  uint64_t history_bytes;
+} sim_buffers_t;
 
 /* Per-network counters since creation (or the last restore). */
 typedef struct {
@@ -109,28 +150,43 @@ typedef struct {
   int64_t synapses_delivered; /* arrival form: records that fell into their reader's tile */
 } sim_stats_t;
 
-/* Build the networks on the device (connectivity, delays, weights; the paper's section 2
- * network recipe with integer delays) and set the initial state (V uniform on
- * [0, v_reset), Ca = 0, no pending input).
- * hip_stream: a hipStream_t or NULL.  On success *out receives the handle; on failure it
- * is NULL and sim_last_error(NULL) tells why.  Synchronises. */
-int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out);
+/* Paper section 2 (Methods) and Table 1: the network a configuration defines -- its grid
+ * of columns, the connectivity that decides the size of the synapse store -- measured
+ * without building it: the generator's count pass runs on the current device's null
+ * stream, and the sizes of the four caller-ownable regions of sim_create come back in
+ * *sizes.  DPSNN_EINVAL for a bad configuration (sim_last_error(NULL) tells why).
+ * Synchronises. */
+int sim_query_sizes(const sim_config_t* cfg, sim_sizes_t* sizes);
 
-/* Release everything the handle holds.  NULL is ignored. */
+/* Paper section 2 (Methods), Table 1: build the networks on the device (connectivity,
+ * delays, weights with integer delays) and set the initial state (V uniform on [0, v_reset),
+ * Ca = 0, no pending input).
+ * bufs: NULL, or caller-owned device buffers for some of the regions (sim_buffers_t).
+ * hip_stream: a hipStream_t or NULL.  On success *out receives the handle; on failure it
+ * is NULL and sim_last_error(NULL) tells why (DPSNN_EINVAL also when a caller buffer is
+ * too small or misaligned).  Synchronises. */
+int sim_create(const sim_config_t* cfg, const sim_buffers_t* bufs, void* hip_stream,
+               sim_t** out);
+
+/* Library runtime (not in the paper): release everything the handle holds; the caller's
+ * buffers are left alone.  NULL is ignored. */
 void sim_destroy(sim_t* sim);
 
-/* Advance all networks by n_steps 1 ms steps (section 1: all neurons every step, synapses
- * per spike).  Asynchronous.  A raster overflow is sticky and reported by the next
- * synchronising call as DPSNN_ETRUNC.  In train mode the steps are launched one by one
- * (graph_steps is not used) and the state is checkpointed every ckpt_every steps. */
+/* Paper section 1: advance all networks by n_steps 1 ms steps of the mixed time- and
+ * event-driven simulation (every neuron each step, synaptic work per spike).  Asynchronous.
+ * A raster overflow is sticky and reported by the next synchronising call as DPSNN_ETRUNC.
+ * In train mode the steps are launched one by one (graph_steps is not used) and the state
+ * is checkpointed every ckpt_every steps. */
 int sim_step(sim_t* sim, int64_t n_steps);
 
-/* Wait for the stream; returns a sticky error if one is pending. */
+/* Library runtime (not in the paper): wait for the stream; returns a sticky error if one is
+ * pending. */
 int sim_sync(sim_t* sim);
 
-/* Recorded spikes of network `net` for steps [t0, t1): step_offsets (host, t1-t0+1) and ids
- * (host, network-local neuron ids, ascending within a step).  If ids_cap is too small,
- * returns DPSNN_ETRUNC with the needed count in *n_ids.  Synchronises. */
+/* Paper section 3 and Figure 2's caption (the spikes behind the synaptic events the paper
+ * counts): recorded spikes of network `net` for steps [t0, t1): step_offsets (host,
+ * t1-t0+1) and ids (host, network-local neuron ids, ascending within a step).  If ids_cap
+ * is too small, returns DPSNN_ETRUNC with the needed count in *n_ids.  Synchronises. */
 int sim_read_spikes(sim_t* sim, int32_t net, int64_t t0, int64_t t1, int64_t* step_offsets,
                     int32_t* ids, int64_t ids_cap, int64_t* n_ids);
 
@@ -143,59 +199,82 @@ int sim_read_spikes(sim_t* sim, int32_t net, int64_t t0, int64_t t1, int64_t* st
 int sim_read_spikes_static(sim_t* sim, int32_t net, int64_t t0, int64_t t1,
                            int64_t* step_offsets, int32_t* ids, int64_t ids_cap, int64_t* n_ids);
 
-/* Train mode: go back to the state at step 0 (the initial state) and start a new recorded
- * window; counters and per-column spike counts restart from zero. */
+/* Workload contract (training; not in the paper, whose simulator has no gradients): go
+ * back to the state at step 0 (the initial state) and start a new recorded window; counters
+ * and per-column spike counts restart from zero.  Train mode only. */
 int sim_rewind(sim_t* sim);
 
-/* Mean firing rate of every column since step 0 (or the last rewind), in Hz:
- * R_c = 1000 * spikes_c / (npc * now * dt).  rates: device float32 [n_cols]. Asynchronous. */
+/* Paper section 2 (the per-column firing activity of the grid): mean firing rate of every
+ * column since step 0 (or the last rewind), in Hz: R_c = 1000 * spikes_c / (npc * now * dt).
+ * rates: device float32 [n_cols]. Asynchronous. */
 int sim_column_rates(sim_t* sim, float* rates);
 
-/* Surrogate-gradient backward through the recorded window [0, now) (train mode only).
+/* Workload contract (training; not in the paper): surrogate-gradient backward of the loss
+ * L = (1/C) sum_c (R_c - R*_c)^2 between every column's mean rate since step 0 and its
+ * target, through the recorded window [0, now) of train mode, for the paper's section 2
+ * neuron (LIF with calcium-driven AHP).
+ * target_rates: device float32 [n_cols of all networks], R*_c in Hz.
+ * loss:         device float32 [1] (nullable): L.
+ * grad_w, grad_tau_m, grad_g_ahp: as in sim_backward_rates.
+ * Same costs, state and errors as sim_backward_rates.  Synchronises. */
+int sim_backward(sim_t* sim, const float* target_rates, float* loss, float* grad_w,
+                 double* grad_tau_m, double* grad_g_ahp);
+
+/* Workload contract (training; not in the paper): sim_backward for any loss of the column
+ * rates, given its gradient (for example from torch autograd).
  * grad_rates: device float32 [n_cols of all networks], dL/dR_c of each column's mean rate
  *             R_c = 1000 / (npc * T * dt) * spikes of column c (Hz).
  * grad_w:     device float32 [n_synapses], dL/dw in the canonical synapse order (per
  *             network, per source neuron, sorted by (delay, target)), w in mV.
- * grad_tau_m, grad_g_ahp: host doubles.
+ * grad_tau_m, grad_g_ahp: host doubles (nullable).
  * The reverse pass re-runs each checkpoint segment forward to record its trajectory (all
  * but the last, which the train-mode forward records as it steps, when nothing has
  * interrupted that recording), so it costs up to one forward plus the adjoint; afterwards
  * the state is the end state again.  The result does not depend on ckpt_every.
  * The adjoint (float32; float64 partial sums for the two scalars) follows the surrogate
  * recursion: nu = dL/dV~ = (1 - r)[lambda (1 - s) + e sigma'(V~ - theta)], sigma'(x) =
- * 1/(1 + beta|x|)^2, with lambda = dL/dV and e = dL/ds including the delayed synapses.
+ * 1/(1 + beta|x|)^2, with lambda = dL/dV and e = dL/ds including the delayed synapses, whose
+ * weights are the efficacies the forward delivered (rint(w 2^16) 2^-16 mV: the rounding is
+ * passed straight through to the master weights).
  * Returns DPSNN_ESTATE if not in train mode, if nothing was recorded, or if the window was
  * broken (restore of another window, weight or parameter change after step 0; call
  * sim_rewind).  Synchronises. */
-int sim_backward(sim_t* sim, const float* grad_rates, float* grad_w, double* grad_tau_m,
-                 double* grad_g_ahp);
+int sim_backward_rates(sim_t* sim, const float* grad_rates, float* grad_w, double* grad_tau_m,
+                       double* grad_g_ahp);
 
-/* Error text of the last failing call on `sim`, or of the last failing sim_create of
- * this thread when sim is NULL.  Never NULL. */
+/* Library runtime (not in the paper): error text of the last failing call on `sim`, or of
+ * the last failing sim_create or sim_query_sizes of this thread when sim is NULL.  Never
+ * NULL. */
 const char* sim_last_error(const sim_t* sim);
 
+/* Paper Table 1 (columns, neurons, synapses of a grid): sizes of a created simulation. */
 int sim_get_info(const sim_t* sim, sim_info_t* info);
 
-/* Counters of network `net`.  Synchronises. */
+/* Paper section 3 and Figure 2's caption (the synaptic event: every current from a
+ * recurrent or an external synapse): counters of network `net`.  Synchronises. */
 int sim_get_stats(sim_t* sim, int32_t net, sim_stats_t* stats);
 
-/* Current step number (steps done).  Host-side, no synchronisation. */
+/* Library runtime (not in the paper): current step number (steps done).  Host-side, no
+ * synchronisation. */
 int64_t sim_now(const sim_t* sim);
 
-/* Debug/test view of network `net` (host buffers, n = neurons of the network):
+/* Paper sections 1-2 (the neuron state and the delayed input of the step), a debug/test
+ * view of network `net` (host buffers, n = neurons of the network):
  * v, ca (float32 [n]), ref (uint8 [n]), pend (int32 [ring_slots][n]) where pend[q][j] is
  * the recurrent input already emitted towards neuron j for step now+q (the delivery
  * strategy's internal form is converted to this view).  Any pointer may be NULL.
  * Synchronises. */
 int sim_read_state(sim_t* sim, int32_t net, float* v, float* ca, uint8_t* ref, int32_t* pend);
 
-/* Synapses of network `net`, source neurons [i0, i1), in canonical order: row_ptr (host,
+/* Paper section 2 (Methods: the synapses, their delays and weights), synapses of network
+ * `net`, source neurons [i0, i1), in canonical order: row_ptr (host,
  * i1-i0+1, relative to the first), tgt (int32 network-local), dly (uint8), wq (int16, 2^-14
  * mV).  Returns DPSNN_ETRUNC with row_ptr filled if cap is short.  Synchronises. */
 int sim_read_synapses(sim_t* sim, int32_t net, int64_t i0, int64_t i1, int64_t* row_ptr,
                       int32_t* tgt, uint8_t* dly, int16_t* wq, int64_t cap);
 
-/* Snapshot slots: save or restore the whole dynamic state (V, Ca, refractory counters,
+/* Library runtime (checkpoint/resume; not in the paper): snapshot slots, save or restore the
+ * whole dynamic state (V, Ca, refractory counters,
  * pending input, step counter, event counters, per-column spike counts).  slot in [0, 64).
  * Asynchronous.  In train mode, restoring a state saved in another recorded window (before
  * the last sim_rewind, weight or parameter change) makes sim_backward fail until the next
@@ -203,17 +282,21 @@ int sim_read_synapses(sim_t* sim, int32_t net, int64_t i0, int64_t i1, int64_t* 
 int sim_save(sim_t* sim, int32_t slot);
 int sim_restore(sim_t* sim, int32_t slot);
 
-/* Train mode: master weights (device float32 [n_synapses], mV, canonical order).  The
+/* Workload contract (training; not in the paper): train mode's master weights (device
+ * float32 [n_synapses], mV, canonical order) of the paper's section 2 synapses.  The
  * forward uses rint(w * 2^16) as int32 efficacy.  set copies in, get copies out; both are
  * asynchronous.  Initially the master weights are the generated int16 weights times 2^-14.
  * A set after step 0 of the recorded window breaks the window (see sim_backward). */
 int sim_set_weights(sim_t* sim, const float* w);
 int sim_get_weights(sim_t* sim, float* w);
-/* Change tau_m and g_AHP (the constants are recomputed on the host).  In train mode a
- * change after step 0 of the recorded window breaks the window (see sim_backward). */
+/* Paper section 2 (the LIF neuron's membrane time constant and its calcium-driven AHP):
+ * change tau_m and g_AHP (the constants are recomputed on the host; they reach the next
+ * step, also under graph replay).  In train mode a change after step 0 of the recorded
+ * window breaks the window (see sim_backward). */
 int sim_set_params(sim_t* sim, double tau_m, double g_ahp);
 
-/* Launch configuration of the step: delivery strategy, workgroup size and, for the arrival
+/* Library runtime (not in the paper): launch configuration of the step: delivery strategy,
+ * workgroup size and, for the arrival
  * form, the tile of target columns one workgroup owns (its LDS accumulators must fit in
  * 160 KB: gather_steps * tile_x * tile_y * npc * 4 bytes plus about 20 KB).  The synapse
  * store is split by the tiling chosen at creation; other tilings work but read more. */
@@ -229,17 +312,20 @@ typedef struct {
                               largest that fits the LDS, at most 4 */
 } sim_launch_t;
 
-/* The launch configuration in use (gather_steps: the window in effect). */
+/* Library runtime: the launch configuration in use (gather_steps: the window in effect). */
 int sim_get_launch(const sim_t* sim, sim_launch_t* launch);
-/* Change it between steps (synchronises); results are bit-identical for every choice. */
+/* Library runtime: change it between steps (synchronises); results are bit-identical for
+ * every choice. */
 int sim_set_launch(sim_t* sim, const sim_launch_t* launch);
 
-/* Order-independent 64-bit digest of the dynamic state (V, Ca, refractory counters, spike
+/* Library runtime (determinism checks; not in the paper): order-independent 64-bit digest
+ * of the dynamic state (V, Ca, refractory counters, spike
  * history).  Equal states give equal digests; used to check that launch configurations and
  * resumed runs agree bit for bit.  Synchronises. */
 int sim_state_digest(sim_t* sim, uint64_t* digest);
 
-/* Autotuner.  From the current state (kept in snapshot slot 63), runs `window` steps with
+/* Library runtime (not in the paper): the autotuner.  From the current state (kept in
+ * snapshot slot 63), runs `window` steps with
  * each candidate launch configuration (delivery form, workgroup size, gather window, graph
  * chunk; the arrival form keeps the tiling of creation), timed with HIP events, checks that every candidate reaches the same state digest,
  * restores the state and keeps the fastest.  cache_path (nullable): a JSON-lines file of
@@ -249,7 +335,8 @@ int sim_state_digest(sim_t* sim, uint64_t* digest);
 int sim_autotune(sim_t* sim, int32_t window, const char* cache_path, sim_launch_t* best,
                  double* best_ms_per_step);
 
-/* Per-kernel device time of the last sim_step call, measured with HIP events recorded on
+/* Paper section 3 (time per synaptic event, measured here per kernel): per-kernel device
+ * time of the last sim_step call, measured with HIP events recorded on
  * the simulation's stream around every kernel launch while timing is on.  ms[0..2]: total
  * milliseconds of class 0 (the update kernel; in the arrival form it also gathers the
  * delivered input), class 1 (push delivery) and class 2 (raster recording); ms[3..5]: the

@@ -20,7 +20,7 @@ EXPORTS = [
     "sim_read_synapses", "sim_save", "sim_restore", "sim_set_weights", "sim_get_weights",
     "sim_set_params", "sim_get_launch", "sim_set_launch", "sim_set_timing", "sim_get_timing",
     "sim_state_digest", "sim_autotune", "sim_rewind", "sim_column_rates",
-    "sim_read_spikes_static",
+    "sim_read_spikes_static", "sim_query_sizes", "sim_backward_rates",
 ]
 
 
@@ -59,7 +59,26 @@ class SimLaunch(C.Structure):
 class SimInfo(C.Structure):
     _fields_ = [("n_nets", C.c_int32), ("n_cols", C.c_int32), ("n_neurons", C.c_int64),
                 ("n_synapses", C.c_int64), ("ring_slots", C.c_int32),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("caller_bytes", C.c_int64)]
+
+
+class SimSizes(C.Structure):
+    _fields_ = [("n_neurons", C.c_int64), ("n_records", C.c_int64),
+                ("synapse_bytes", C.c_uint64), ("index_bytes", C.c_uint64),
+                ("state_bytes", C.c_uint64), ("history_bytes", C.c_uint64),
+                ("state_v_offset", C.c_uint64), ("state_ca_offset", C.c_uint64),
+                ("state_ref_offset", C.c_uint64)]
+
+
+class SimBuffers(C.Structure):
+    _fields_ = [("synapses", C.c_void_p), ("synapse_bytes", C.c_uint64),
+                ("index", C.c_void_p), ("index_bytes", C.c_uint64),
+                ("state", C.c_void_p), ("state_bytes", C.c_uint64),
+                ("history", C.c_void_p), ("history_bytes", C.c_uint64)]
+
+#: The four caller-ownable regions: (SimBuffers pointer field, size field, SimSizes field).
+REGIONS = (("synapses", "synapse_bytes"), ("index", "index_bytes"), ("state", "state_bytes"),
+           ("history", "history_bytes"))
 
 
 class SimStats(C.Structure):
@@ -82,7 +101,8 @@ def lib():
     P = C.POINTER
     vp = C.c_void_p
     sigs = {
-        "sim_create": (C.c_int, [P(SimConfig), vp, P(vp)]),
+        "sim_query_sizes": (C.c_int, [P(SimConfig), P(SimSizes)]),
+        "sim_create": (C.c_int, [P(SimConfig), P(SimBuffers), vp, P(vp)]),
         "sim_destroy": (None, [vp]),
         "sim_step": (C.c_int, [vp, C.c_int64]),
         "sim_sync": (C.c_int, [vp]),
@@ -91,7 +111,8 @@ def lib():
         "sim_read_spikes_static": (C.c_int, [vp, C.c_int32, C.c_int64, C.c_int64,
                                              P(C.c_int64), P(C.c_int32), C.c_int64,
                                              P(C.c_int64)]),
-        "sim_backward": (C.c_int, [vp, vp, vp, P(C.c_double), P(C.c_double)]),
+        "sim_backward": (C.c_int, [vp, vp, vp, vp, P(C.c_double), P(C.c_double)]),
+        "sim_backward_rates": (C.c_int, [vp, vp, vp, P(C.c_double), P(C.c_double)]),
         "sim_last_error": (C.c_char_p, [vp]),
         "sim_get_info": (C.c_int, [vp, P(SimInfo)]),
         "sim_get_stats": (C.c_int, [vp, C.c_int32, P(SimStats)]),

@@ -588,6 +588,27 @@ __global__ void k_column_rates(const unsigned long long* col_spk, int32_t n_cols
   if (c < n_cols) rates[c] = (float)((double)col_spk[c] * (double)scale);
 }
 
+// The built-in loss of sim_backward: L = mean over columns of (R_c - R*_c)^2 and its
+// gradient dL/dR_c = 2 (R_c - R*_c) / C.  One workgroup; the loss is summed in double in a
+// fixed order (lane-strided partial sums, then a fixed tree), so it is deterministic.
+__global__ __launch_bounds__(256) void k_rate_loss(const float* rates, const float* targets,
+                                                   int32_t n_cols, float* loss, float* grad) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int32_t c = threadIdx.x; c < n_cols; c += 256) {
+    const double d = (double)rates[c] - (double)targets[c];
+    acc += d * d;
+    grad[c] = (float)(2.0 * d / (double)n_cols);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && loss) *loss = (float)(part[0] / (double)n_cols);
+}
+
 int grid_of(int64_t items, int per_block) {
   int64_t b = (items + per_block - 1) / per_block;
   if (b > 65536) b = 65536;
@@ -728,6 +749,13 @@ hipError_t launch_fill_dly(const sim& s) {
 hipError_t launch_weights_from_records(const sim& s) {
   hipLaunchKernelGGL(k_weights_from_records, dim3(grid_of(s.n_syn_padded, 256)), dim3(256), 0,
                      s.stream, s.syn, s.wf32, s.n_syn_padded);
+  return hipGetLastError();
+}
+
+hipError_t launch_rate_loss(const sim& s, const float* rates, const float* targets, float* loss,
+                            float* grad_rates) {
+  hipLaunchKernelGGL(k_rate_loss, dim3(1), dim3(256), 0, s.stream, rates, targets, s.n_cols,
+                     loss, grad_rates);
   return hipGetLastError();
 }
 

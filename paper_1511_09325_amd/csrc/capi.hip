@@ -52,6 +52,37 @@ void dfree(sim& s, void* p) {
   }
 }
 
+// Caller-owned regions of device memory (sim_buffers_t).  Arrays of a region are carved in
+// a fixed order at 256-byte aligned offsets; region_sizes() gives the same layout's sizes.
+enum { kRegSyn = 0, kRegIndex = 1, kRegState = 2, kRegHist = 3 };
+const char* const kRegionName[4] = {"synapses", "index", "state", "history"};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+void* carve(sim& s, int r, size_t bytes) {
+  if (!s.region_base[r]) return dalloc(s, bytes);
+  const size_t b = align256(bytes ? bytes : 1);
+  if (s.region_used[r] + b > s.region_cap[r])
+    throw Fail{DPSNN_EINVAL, std::string("the caller's ") + kRegionName[r] +
+                                 " buffer is smaller than sim_query_sizes reports"};
+  void* p = s.region_base[r] + s.region_used[r];
+  s.region_used[r] += b;
+  return p;
+}
+
+// Sizes of the four regions for a store of `records` synapse records (padding included).
+void region_sizes(const sim& s, int64_t records, size_t out[4]) {
+  const size_t N = (size_t)s.n_neurons, C = (size_t)s.n_cols, dh = (size_t)s.dh,
+               npc = (size_t)s.npc, P = (size_t)s.n_parts, nd = (size_t)s.nd;
+  out[kRegSyn] = align256(sizeof(uint32_t) * (size_t)(records + 4));
+  out[kRegIndex] = align256(sizeof(int64_t) * (N + 1)) + align256(sizeof(int32_t) * N) +
+                   align256((size_t)s.idxw * (size_t)s.n_idx);
+  out[kRegState] = 2 * align256(sizeof(float) * N) + align256(N);
+  out[kRegHist] = align256(sizeof(int32_t) * dh * C) + align256(sizeof(uint16_t) * dh * C * npc) +
+                  align256(sizeof(uint32_t) * dh * P * npc) +
+                  align256(sizeof(uint16_t) * dh * P * (nd + 1) * npc);
+}
+
 template <typename T>
 T* upload(sim& s, const std::vector<T>& h) {
   T* d = (T*)dalloc(s, sizeof(T) * std::max<size_t>(h.size(), 1));
@@ -506,11 +537,13 @@ void build_tables(sim& s) {
   s.net_ptab = upload(s, ptab);
 }
 
-void generate(sim& s) {
+// Count pass of the generator: records of every row (padding included) and their prefix in
+// row_base; returns the store's size in records.
+int64_t count_records(sim& s, int64_t** part_out, int64_t* plen_out) {
   const int64_t N = s.n_neurons;
   int32_t* row_len = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)N);
-  s.deg = (int32_t*)dalloc(s, sizeof(int32_t) * (size_t)N);
-  s.row_base = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)(N + 1));
+  s.row_base = (int64_t*)carve(s, kRegIndex, sizeof(int64_t) * (size_t)(N + 1));
+  s.deg = (int32_t*)carve(s, kRegIndex, sizeof(int32_t) * (size_t)N);
   const int64_t plen = scan_scratch_len(N);
   int64_t* part = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)plen);
   HIPCHK(launch_gen_count(s, 0, N, row_len));
@@ -518,13 +551,31 @@ void generate(sim& s) {
   int64_t total = 0;
   HIPCHK(hipMemcpyAsync(&total, s.row_base + N, sizeof(int64_t), hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
+  dfree(s, row_len);
+  *part_out = part;
+  *plen_out = plen;
   // the tile kernel addresses 16-byte pieces of the store with 32-bit indices
   if (total / 4 >= ((int64_t)1 << 32))
     throw Fail{DPSNN_EINVAL, "synapse store exceeds 2^34 records"};
+  return total;
+}
+
+void generate(sim& s) {
+  const int64_t N = s.n_neurons;
+  int64_t* part = nullptr;
+  int64_t plen = 0;
+  const int64_t total = count_records(s, &part, &plen);
+  size_t need[4];
+  region_sizes(s, total, need);
+  for (int r = 0; r < 4; ++r)
+    if (s.region_base[r] && s.region_cap[r] < need[r])
+      throw Fail{DPSNN_EINVAL, std::string("the caller's ") + kRegionName[r] + " buffer holds " +
+                                   std::to_string(s.region_cap[r]) + " bytes, the simulation needs " +
+                                   std::to_string(need[r])};
   // one spare uint4 after the last synapse: the delivery kernels may load whole 16-byte
   // words that straddle the end of a segment
-  s.syn = (uint32_t*)dalloc(s, sizeof(uint32_t) * (size_t)(total + 4));
-  s.idx = (uint8_t*)dalloc(s, (size_t)s.idxw * (size_t)s.n_idx);
+  s.syn = (uint32_t*)carve(s, kRegSyn, sizeof(uint32_t) * (size_t)(total + 4));
+  s.idx = (uint8_t*)carve(s, kRegIndex, (size_t)s.idxw * (size_t)s.n_idx);
   HIPCHK(hipMemsetAsync(s.syn + total, 0, 4 * sizeof(uint32_t), s.stream));
   HIPCHK(launch_gen_fill(s, 0, N));
   // the number of synapses (without the padding): scan of the out-degrees
@@ -541,7 +592,6 @@ void generate(sim& s) {
   if (s.cfg.train_mode) s.canon_start = degscan;  // canonical order of the weights
   else dfree(s, degscan);
   dfree(s, part);
-  dfree(s, row_len);
 }
 
 void ensure_ring(sim& s) {
@@ -616,6 +666,8 @@ void setup_train(sim& s) {
   s.adj_mu = (float*)dalloc(s, sizeof(float) * N);
   s.adj_part = (double*)dalloc(s, sizeof(double) * 2 * N);
   s.adj_out = (double*)dalloc(s, sizeof(double) * 2);
+  s.loss_rates = (float*)dalloc(s, sizeof(float) * (size_t)s.n_cols);
+  s.loss_grad = (float*)dalloc(s, sizeof(float) * (size_t)s.n_cols);
   // single-column native tiles: every part of a row holds the synapses into one column, and
   // the reverse gather can run by target column with that column's future nu in LDS
   if (s.native_tx == 1 && s.native_ty == 1 &&
@@ -665,11 +717,18 @@ int finish(sim* s, const Fail& f) {
 
 extern "C" {
 
-int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
+}  // extern "C"
+
+namespace {
+
+// sim_create, or with `sizes` set the size query: everything up to the generator's count
+// pass, then the region sizes, and the simulation is released again.
+int create_impl(const sim_config_t* cfg, const sim_buffers_t* bufs, void* hip_stream,
+                sim_t** out, sim_sizes_t* sizes) {
   if (out) *out = nullptr;
   sim* s = nullptr;
   try {
-    if (!out) throw Fail{DPSNN_EINVAL, "out is NULL"};
+    if (!out && !sizes) throw Fail{DPSNN_EINVAL, "out is NULL"};
     validate(cfg);
     HIPCHK(prepare_step_kernels());
     s = new sim();
@@ -690,15 +749,47 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     choose_native(*s, cfg->tile_x, cfg->tile_y);
     build_parts(*s, s->native_tx, s->native_ty);
     build_tiles(*s, s->native_tx, s->native_ty);
+    if (sizes) {
+      int64_t* part = nullptr;
+      int64_t plen = 0;
+      const int64_t total = count_records(*s, &part, &plen);
+      size_t need[4];
+      region_sizes(*s, total, need);
+      sizes->n_neurons = s->n_neurons;
+      sizes->n_records = total;
+      sizes->synapse_bytes = need[kRegSyn];
+      sizes->index_bytes = need[kRegIndex];
+      sizes->state_bytes = need[kRegState];
+      sizes->history_bytes = need[kRegHist];
+      sizes->state_v_offset = 0;
+      sizes->state_ca_offset = align256(sizeof(float) * (size_t)s->n_neurons);
+      sizes->state_ref_offset = 2 * align256(sizeof(float) * (size_t)s->n_neurons);
+      sim_destroy(s);
+      return DPSNN_OK;
+    }
+    if (bufs) {
+      void* const base[4] = {bufs->synapses, bufs->index, bufs->state, bufs->history};
+      const uint64_t cap[4] = {bufs->synapse_bytes, bufs->index_bytes, bufs->state_bytes,
+                               bufs->history_bytes};
+      for (int r = 0; r < 4; ++r) {
+        if (!base[r]) continue;
+        if ((uintptr_t)base[r] % 256 != 0)
+          throw Fail{DPSNN_EINVAL, std::string("the caller's ") + kRegionName[r] +
+                                       " buffer is not 256-byte aligned"};
+        s->region_base[r] = (unsigned char*)base[r];
+        s->region_cap[r] = (size_t)cap[r];
+        s->caller_bytes += (size_t)cap[r];
+      }
+    }
     generate(*s);
     const size_t N = (size_t)s->n_neurons;
-    s->v = (float*)dalloc(*s, sizeof(float) * N);
-    s->ca = (float*)dalloc(*s, sizeof(float) * N);
-    s->ref = (uint8_t*)dalloc(*s, N);
-    s->hist_cnt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)s->dh * s->n_cols);
-    s->hist_ids = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
-    s->hist_st = (uint32_t*)dalloc(*s, sizeof(uint32_t) * (size_t)s->dh * s->n_parts * s->npc);
-    s->hist_go = (uint16_t*)dalloc(*s, sizeof(uint16_t) * (size_t)s->dh * s->n_parts * (s->nd + 1) * s->npc);
+    s->v = (float*)carve(*s, kRegState, sizeof(float) * N);
+    s->ca = (float*)carve(*s, kRegState, sizeof(float) * N);
+    s->ref = (uint8_t*)carve(*s, kRegState, N);
+    s->hist_cnt = (int32_t*)carve(*s, kRegHist, sizeof(int32_t) * (size_t)s->dh * s->n_cols);
+    s->hist_ids = (uint16_t*)carve(*s, kRegHist, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
+    s->hist_st = (uint32_t*)carve(*s, kRegHist, sizeof(uint32_t) * (size_t)s->dh * s->n_parts * s->npc);
+    s->hist_go = (uint16_t*)carve(*s, kRegHist, sizeof(uint16_t) * (size_t)s->dh * s->n_parts * (s->nd + 1) * s->npc);
     s->net_cnt = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets);
     s->flags = (int32_t*)dalloc(*s, sizeof(int32_t) * 4);
     s->d_now = (int64_t*)dalloc(*s, sizeof(int64_t));
@@ -734,6 +825,22 @@ int sim_create(const sim_config_t* cfg, void* hip_stream, sim_t** out) {
     if (s) sim_destroy(s);
     return DPSNN_ENOMEM;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_query_sizes(const sim_config_t* cfg, sim_sizes_t* sizes) {
+  if (!sizes) {
+    g_create_error = "sizes is NULL";
+    return DPSNN_EINVAL;
+  }
+  return create_impl(cfg, nullptr, nullptr, nullptr, sizes);
+}
+
+int sim_create(const sim_config_t* cfg, const sim_buffers_t* bufs, void* hip_stream, sim_t** out) {
+  return create_impl(cfg, bufs, hip_stream, out, nullptr);
 }
 
 void sim_destroy(sim_t* s) {
@@ -1014,6 +1121,7 @@ int sim_get_info(const sim_t* s, sim_info_t* info) {
   info->n_synapses = s->n_syn;
   info->ring_slots = s->dh;
   info->device_bytes = (int64_t)s->device_bytes;
+  info->caller_bytes = (int64_t)s->caller_bytes;
   return DPSNN_OK;
 }
 
@@ -1358,8 +1466,25 @@ int sim_column_rates(sim_t* s, float* rates) {
 // with the trajectory recorded (the last segment only when the forward's own recording does
 // not hold all of it), and the adjoint recursion runs backwards through it.  The
 // adjoint ring carries nu across segment boundaries.  Finally the end state comes back.
-int sim_backward(sim_t* s, const float* grad_rates, float* grad_w, double* grad_tau_m,
-                 double* grad_g_ahp) {
+int sim_backward(sim_t* s, const float* target_rates, float* loss, float* grad_w,
+                 double* grad_tau_m, double* grad_g_ahp) {
+  if (!s) return DPSNN_EINVAL;
+  if (s->sticky) { s->err = "simulation is in a failed state"; return DPSNN_ESTATE; }
+  try {
+    need_train(*s);
+    if (!target_rates || !grad_w) throw Fail{DPSNN_EINVAL, "target_rates and grad_w are required"};
+    if (s->now == 0) throw Fail{DPSNN_ESTATE, "nothing recorded: no steps since step 0"};
+    const double scale = 1000.0 / ((double)s->npc * (double)s->now * s->cfg.dt);
+    HIPCHK(launch_column_rates(*s, (float)scale, s->loss_rates));
+    HIPCHK(launch_rate_loss(*s, s->loss_rates, target_rates, loss, s->loss_grad));
+  } catch (const Fail& f) {
+    return finish(s, f);
+  }
+  return sim_backward_rates(s, s->loss_grad, grad_w, grad_tau_m, grad_g_ahp);
+}
+
+int sim_backward_rates(sim_t* s, const float* grad_rates, float* grad_w, double* grad_tau_m,
+                       double* grad_g_ahp) {
   if (!s) return DPSNN_EINVAL;
   if (s->sticky) { s->err = "simulation is in a failed state"; return DPSNN_ESTATE; }
   try {

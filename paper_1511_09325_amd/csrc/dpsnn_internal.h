@@ -254,6 +254,14 @@ struct sim {
   // device memory
   std::vector<dpsnn::DevBuf> bufs;
   size_t device_bytes = 0;
+  // caller-owned regions (sim_buffers_t): synapses, index, state, history; base null when
+  // the library allocates that region's arrays itself
+  unsigned char* region_base[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t region_cap[4] = {0, 0, 0, 0};
+  size_t region_used[4] = {0, 0, 0, 0};
+  size_t caller_bytes = 0;
+  float* loss_rates = nullptr;     // train mode: column rates and dL/dR of the built-in loss
+  float* loss_grad = nullptr;
   int32_t *col_net = nullptr, *col_local = nullptr, *col_nbr = nullptr, *col_nn = nullptr;
   int32_t *col_part = nullptr, *col_np = nullptr;
   int64_t* col_pbase = nullptr;
@@ -385,6 +393,8 @@ hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst
 hipError_t launch_canon_perm(const sim& s, uint16_t* rel);
 hipError_t launch_weights_from_records(const sim& s);
 hipError_t launch_column_rates(const sim& s, float scale, float* rates);
+hipError_t launch_rate_loss(const sim& s, const float* rates, const float* targets, float* loss,
+                            float* grad_rates);
 hipError_t launch_fill_entries(const sim& s);
 hipError_t launch_fill_dly(const sim& s);
 int64_t scan_scratch_len(int64_t n);

@@ -54,25 +54,52 @@ def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, b
     return c, nets
 
 
+def query_sizes(params, **options) -> dict:
+    """sim_query_sizes: the device memory of the four caller-ownable regions (bytes) and the
+    state region's offsets, for the configuration make_config(params, **options) builds."""
+    cfg, _nets = make_config(params, **options)
+    sz = L.SimSizes()
+    L.check(L.lib().sim_query_sizes(C.byref(cfg), C.byref(sz)), None)
+    return {name: getattr(sz, name) for name, _ in L.SimSizes._fields_}
+
+
 class Simulation:
     def __init__(self, params, *, delivery: int = L.DELIVERY_AUTO, block: int = 0,
                  tile: tuple[int, int] = (0, 0), record_steps: int = 0,
                  raster_capacity: int | None = None, train_mode: bool = False,
                  ckpt_every: int = 50, surrogate_beta: float = 5.0, gather_steps: int = 0,
-                 stream=None):
+                 stream=None, torch_buffers=()):
+        """torch_buffers: names of the regions ("synapses", "index", "state", "history") whose
+        device memory torch allocates and owns (sized by sim_query_sizes); the rest the
+        library allocates."""
         self.params = params if isinstance(params, list) else [params]
         if raster_capacity is None:
             n = sum(p["rows"] * p["cols"] * p["npc"] for p in self.params)
             raster_capacity = max(1, int(record_steps * n * 0.2)) if record_steps else 0
-        cfg, self._nets = make_config(params, delivery=delivery, block=block, tile=tile,
-                                      record_steps=record_steps, raster_capacity=raster_capacity,
-                                      train_mode=train_mode, ckpt_every=ckpt_every,
-                                      surrogate_beta=surrogate_beta)
+        options = dict(delivery=delivery, block=block, tile=tile, record_steps=record_steps,
+                       raster_capacity=raster_capacity, train_mode=train_mode,
+                       ckpt_every=ckpt_every, surrogate_beta=surrogate_beta)
+        cfg, self._nets = make_config(params, **options)
         self._cfg = cfg
         self.train_mode = bool(train_mode)
         self.lib = L.lib()
+        self.buffers, self.sizes, bufs = {}, None, None
+        if torch_buffers:
+            import torch
+            self.sizes = query_sizes(params, **options)
+            bufs = L.SimBuffers()
+            for name, size_field in L.REGIONS:
+                if name in torch_buffers:
+                    t = torch.empty(int(self.sizes[size_field]), dtype=torch.uint8, device="cuda")
+                    self.buffers[name] = t
+                    setattr(bufs, name, C.c_void_p(t.data_ptr()))
+                    setattr(bufs, size_field, t.numel())
+            unknown = set(torch_buffers) - {n for n, _ in L.REGIONS}
+            if unknown:
+                raise ValueError("unknown regions %s" % sorted(unknown))
         h = C.c_void_p()
-        L.check(self.lib.sim_create(C.byref(cfg), _stream_ptr(stream), C.byref(h)), None)
+        L.check(self.lib.sim_create(C.byref(cfg), C.byref(bufs) if bufs is not None else None,
+                                    _stream_ptr(stream), C.byref(h)), None)
         self.h = h
         info = L.SimInfo()
         L.check(self.lib.sim_get_info(self.h, C.byref(info)), self.h)
@@ -82,15 +109,28 @@ class Simulation:
         self.n_synapses = info.n_synapses
         self.ring_slots = info.ring_slots
         self.device_bytes = info.device_bytes
+        self.caller_bytes = info.caller_bytes
         self.record_steps = record_steps
         if gather_steps:
             self.set_launch(gather_steps=gather_steps)
+
+    def state_tensors(self):
+        """(V, Ca, refractory counters) of all networks as torch views of the caller-owned state
+        region (torch_buffers must include "state"); read them between synchronising calls."""
+        t = self.buffers["state"]
+        n = self.n_neurons
+        v0, c0, r0 = (int(self.sizes[k]) for k in ("state_v_offset", "state_ca_offset",
+                                                   "state_ref_offset"))
+        import torch
+        return (t[v0:v0 + 4 * n].view(torch.float32), t[c0:c0 + 4 * n].view(torch.float32),
+                t[r0:r0 + n])
 
     # -- lifetime -------------------------------------------------------------------------
     def close(self):
         if getattr(self, "h", None):
             self.lib.sim_destroy(self.h)
             self.h = None
+        self.buffers = {}
 
     def __del__(self):
         try:
@@ -259,16 +299,31 @@ class Simulation:
         return r
 
     def backward(self, grad_rates):
-        """Surrogate-gradient backward through [0, now): returns (dL/dw as device float32
-        [n_synapses] in canonical order, dL/dtau_m, dL/dg_AHP)."""
+        """Surrogate-gradient backward through [0, now) for a given dL/dR (sim_backward_rates):
+        returns (dL/dw as device float32 [n_synapses] in canonical order, dL/dtau_m,
+        dL/dg_AHP)."""
         import torch
         gr = grad_rates.detach().to(torch.float32).contiguous()
         gw = torch.empty(self.n_synapses, dtype=torch.float32, device="cuda")
         gt, gg = C.c_double(), C.c_double()
-        L.check(self.lib.sim_backward(self.h, self._dev(gr, "float32", self.n_cols),
+        L.check(self.lib.sim_backward_rates(self.h, self._dev(gr, "float32", self.n_cols),
+                                            self._dev(gw, "float32", self.n_synapses),
+                                            C.byref(gt), C.byref(gg)), self.h)
+        return gw, gt.value, gg.value
+
+    def backward_loss(self, target_rates):
+        """sim_backward: the built-in loss L = mean_c (R_c - R*_c)^2 of the column rates since
+        step 0 against the targets; returns (L, dL/dw, dL/dtau_m, dL/dg_AHP)."""
+        import torch
+        tg = torch.as_tensor(target_rates, dtype=torch.float32, device="cuda").contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        gw = torch.empty(self.n_synapses, dtype=torch.float32, device="cuda")
+        gt, gg = C.c_double(), C.c_double()
+        L.check(self.lib.sim_backward(self.h, self._dev(tg, "float32", self.n_cols),
+                                      self._dev(loss, "float32", 1),
                                       self._dev(gw, "float32", self.n_synapses), C.byref(gt),
                                       C.byref(gg)), self.h)
-        return gw, gt.value, gg.value
+        return float(loss.item()), gw, gt.value, gg.value
 
 
 def _column_rates_fn():

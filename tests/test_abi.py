@@ -56,9 +56,12 @@ _PROBE = r"""
 int main(void) {
   printf("sim_config_t %zu\nsim_net_t %zu\nsim_info_t %zu\nsim_stats_t %zu\n",
          sizeof(sim_config_t), sizeof(sim_net_t), sizeof(sim_info_t), sizeof(sim_stats_t));
+  printf("sim_sizes_t %zu\nsim_buffers_t %zu\n", sizeof(sim_sizes_t), sizeof(sim_buffers_t));
   F(sim_config_t, nets) F(sim_config_t, delivery) F(sim_config_t, record_steps)
   F(sim_config_t, ckpt_every) F(sim_config_t, j_ext) F(sim_net_t, ext_rate_hz)
-  F(sim_info_t, device_bytes)
+  F(sim_info_t, device_bytes) F(sim_info_t, caller_bytes)
+  F(sim_sizes_t, history_bytes) F(sim_sizes_t, state_ref_offset)
+  F(sim_buffers_t, state) F(sim_buffers_t, history_bytes)
   return 0;
 }
 """
@@ -75,7 +78,14 @@ def test_struct_layout_matches_c():
     assert int(got["sim_net_t"]) == C.sizeof(L.SimNet)
     assert int(got["sim_info_t"]) == C.sizeof(L.SimInfo)
     assert int(got["sim_stats_t"]) == C.sizeof(L.SimStats)
+    assert int(got["sim_sizes_t"]) == C.sizeof(L.SimSizes)
+    assert int(got["sim_buffers_t"]) == C.sizeof(L.SimBuffers)
     for key, (cls, field) in {"sim_config_t.nets": (L.SimConfig, "nets"),
+                              "sim_info_t.caller_bytes": (L.SimInfo, "caller_bytes"),
+                              "sim_sizes_t.history_bytes": (L.SimSizes, "history_bytes"),
+                              "sim_sizes_t.state_ref_offset": (L.SimSizes, "state_ref_offset"),
+                              "sim_buffers_t.state": (L.SimBuffers, "state"),
+                              "sim_buffers_t.history_bytes": (L.SimBuffers, "history_bytes"),
                               "sim_config_t.delivery": (L.SimConfig, "delivery"),
                               "sim_config_t.record_steps": (L.SimConfig, "record_steps"),
                               "sim_config_t.ckpt_every": (L.SimConfig, "ckpt_every"),
@@ -95,10 +105,12 @@ def test_invalid_configs_are_rejected_before_device_work(lib, bad):
     p.update(bad)
     cfg, nets = make_config(p)
     h = C.c_void_p(123)
-    rc = lib.sim_create(C.byref(cfg), None, C.byref(h))
+    rc = lib.sim_create(C.byref(cfg), None, None, C.byref(h))
     assert rc == L.EINVAL
     assert h.value is None
     assert lib.sim_last_error(None)
+    sz = L.SimSizes()
+    assert lib.sim_query_sizes(C.byref(cfg), C.byref(sz)) == L.EINVAL
 
 
 def test_null_handles(lib):
@@ -107,4 +119,25 @@ def test_null_handles(lib):
     assert lib.sim_now(None) == -1
     lib.sim_destroy(None)
     h = C.c_void_p(123)
-    assert lib.sim_create(None, None, C.byref(h)) == L.EINVAL
+    assert lib.sim_create(None, None, None, C.byref(h)) == L.EINVAL
+    assert lib.sim_query_sizes(None, None) == L.EINVAL
+
+
+def build_abi_client(td):
+    """Compile tests/abi_client.c with gcc against include/dpsnn.h and link libdpsnn.so."""
+    exe = os.path.join(td, "abi_client")
+    libdir = os.path.dirname(L.LIB_PATH)
+    subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Werror", "-I" + os.path.join(ROOT, "include"),
+                           os.path.join(ROOT, "tests", "abi_client.c"), "-o", exe,
+                           "-L" + libdir, "-ldpsnn", "-Wl,-rpath," + libdir])
+    return exe
+
+
+def test_c_program_links_the_library_and_gets_its_errors(lib):
+    """A plain C program built against the header alone links libdpsnn.so and receives the
+    documented error codes for bad configurations and NULL arguments (no GPU needed)."""
+    with tempfile.TemporaryDirectory() as td:
+        exe = build_abi_client(td)
+        out = subprocess.run([exe, "errors"], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "errors ok"
