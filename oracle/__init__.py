@@ -48,7 +48,15 @@ class _Cfg(C.Structure):
         ("t_ref", C.c_int32),
         ("tau_ca", C.c_double), ("ca_inc", C.c_double), ("g_ahp", C.c_double), ("dt", C.c_double),
         ("ext_rate_hz", C.c_double), ("ext_syn", C.c_int32), ("j_ext", C.c_double),
+        ("neuron_model", C.c_int32), ("tau_na", C.c_double), ("na_inc", C.c_double),
+        ("g_na", C.c_double),
+        ("izh_a_e", C.c_double), ("izh_b_e", C.c_double), ("izh_c_e", C.c_double),
+        ("izh_d_e", C.c_double),
+        ("izh_a_i", C.c_double), ("izh_b_i", C.c_double), ("izh_c_i", C.c_double),
+        ("izh_d_i", C.c_double), ("izh_vpeak", C.c_double),
     ]
+
+NEURON_LIF, NEURON_IZHIKEVICH = 0, 1
 
 
 class _AdjParams(C.Structure):
@@ -82,10 +90,14 @@ def lib():
             "orc_poisson_table": (None, [C.c_double, u64p]),
             "orc_poisson_count": (C.c_int32, [u64p, C.c_uint32]),
             "orc_initial_v": (C.c_float, [cp, C.c_int64]),
+            "orc_initial_state": (None, [cp, C.c_int64, f32p, f32p]),
+            "orc_sim_get_na": (None, [C.c_void_p, f32p]),
+            "orc_sim_set_na": (None, [C.c_void_p, f32p]),
             "orc_ext_counts": (None, [cp, C.c_int64, C.c_int64, C.c_int64, i32p]),
-            "orc_neuron_update": (C.c_int, [cp, C.c_int64, C.c_int64, C.c_int32, f32p, f32p, u8p]),
+            "orc_neuron_update": (C.c_int, [cp, C.c_int64, C.c_int64, C.c_int32, f32p, f32p, u8p,
+                                            f32p]),
             "orc_update_many": (None, [cp, C.c_int64, C.c_int64, C.c_int64, i32p, f32p, f32p,
-                                       u8p, u8p]),
+                                       u8p, u8p, f32p]),
             "orc_input_brute": (None, [cp, C.c_int64, i64p, C.c_int64, C.c_int64, u8p,
                                        C.c_int64, C.c_int64, i32p]),
             "orc_sim_consumed": (C.c_int64, [C.c_void_p]),
@@ -219,28 +231,31 @@ def ext_counts(p: dict, u: int, j0: int = 0, n: int | None = None):
     return out
 
 
-def neuron_update(p: dict, j: int, u: int, rec_input: int, v: float, ca: float, ref: int):
-    """One neuron's step from its state; returns (spike, v, ca, ref)."""
+def neuron_update(p: dict, j: int, u: int, rec_input: int, v: float, ca: float, ref: int,
+                  na: float = 0.0):
+    """One neuron's step from its state; returns (spike, v, ca, ref, na)."""
     cfg = make_config(p)
-    vv, cc, rr = C.c_float(v), C.c_float(ca), C.c_uint8(ref)
+    vv, cc, rr, nn = C.c_float(v), C.c_float(ca), C.c_uint8(ref), C.c_float(na)
     s = lib().orc_neuron_update(C.byref(cfg), j, u, int(rec_input), C.byref(vv), C.byref(cc),
-                                C.byref(rr))
-    return bool(s), np.float32(vv.value), np.float32(cc.value), int(rr.value)
+                                C.byref(rr), C.byref(nn))
+    return (bool(s), np.float32(vv.value), np.float32(cc.value), int(rr.value),
+            np.float32(nn.value))
 
 
-def update_many(p: dict, u: int, rec_input, v, ca, ref, j0: int = 0):
+def update_many(p: dict, u: int, rec_input, v, ca, ref, j0: int = 0, na=None):
     """neuron_update for neurons j0 .. j0+n-1 at step u on copies of the given state;
-    returns (spike flags, v, ca, ref)."""
+    returns (spike flags, v, ca, ref) and, when na is given, the new na as a fifth item."""
     cfg = make_config(p)
     ri = np.ascontiguousarray(rec_input, np.int32)
     v2 = np.array(v, np.float32)
     c2 = np.array(ca, np.float32)
     r2 = np.array(ref, np.uint8)
+    n2 = None if na is None else np.array(na, np.float32)
     spk = np.zeros(len(ri), np.uint8)
     lib().orc_update_many(C.byref(cfg), u, j0, len(ri), _ptr(ri, C.c_int32),
                           _ptr(v2, C.c_float), _ptr(c2, C.c_float), _ptr(r2, C.c_uint8),
-                          _ptr(spk, C.c_uint8))
-    return spk, v2, c2, r2
+                          _ptr(spk, C.c_uint8), None if n2 is None else _ptr(n2, C.c_float))
+    return (spk, v2, c2, r2) if n2 is None else (spk, v2, c2, r2, n2)
 
 
 def input_brute(p: dict, targets, t_arr: int, t_emit_max: int, mask, mask_t0: int):
@@ -260,6 +275,14 @@ def input_brute(p: dict, targets, t_arr: int, t_emit_max: int, mask, mask_t0: in
 def initial_v(p: dict, j: int) -> float:
     cfg = make_config(p)
     return lib().orc_initial_v(C.byref(cfg), j)
+
+
+def initial_state(p: dict, j: int):
+    """(v, ca) of neuron j at step 0 (ca: the Izhikevich recovery variable for that model)."""
+    cfg = make_config(p)
+    v, ca = C.c_float(), C.c_float()
+    lib().orc_initial_state(C.byref(cfg), j, C.byref(v), C.byref(ca))
+    return np.float32(v.value), np.float32(ca.value)
 
 
 # ---------------------------------------------------------------------------------------------
@@ -326,9 +349,11 @@ class Sim:
         pend = np.zeros((self.D, self.n), np.int32)
         lib().orc_sim_get_state(self._h, _ptr(v, C.c_float), _ptr(ca, C.c_float),
                                 _ptr(ref, C.c_uint8), _ptr(pend, C.c_int32))
-        return {"v": v, "ca": ca, "ref": ref, "pend": pend, "now": self.now}
+        na = np.zeros(self.n, np.float32)
+        lib().orc_sim_get_na(self._h, _ptr(na, C.c_float))
+        return {"v": v, "ca": ca, "ref": ref, "pend": pend, "na": na, "now": self.now}
 
-    def set_state(self, now, v, ca, ref, pend):
+    def set_state(self, now, v, ca, ref, pend, na=None):
         v = np.ascontiguousarray(v, np.float32)
         ca = np.ascontiguousarray(ca, np.float32)
         ref = np.ascontiguousarray(ref, np.uint8)
@@ -336,6 +361,9 @@ class Sim:
         assert pend.shape == (self.D, self.n)
         lib().orc_sim_set_state(self._h, now, _ptr(v, C.c_float), _ptr(ca, C.c_float),
                                 _ptr(ref, C.c_uint8), _ptr(pend, C.c_int32))
+        if na is not None:
+            na = np.ascontiguousarray(na, np.float32)
+            lib().orc_sim_set_na(self._h, _ptr(na, C.c_float))
 
     def inject(self, q: int, j: int, value: int):
         lib().orc_sim_inject(self._h, q, j, value)

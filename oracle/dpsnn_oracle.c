@@ -263,12 +263,34 @@ void orc_ext_counts(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n, i
   for (int64_t q = 0; q < n; ++q) out[q] = orc_poisson_count(tab, ext_uniform(cfg, j0 + q, u));
 }
 
-/* Initial potential uniform on [0, v_reset): 24 random bits scaled exactly, times v_reset. */
-float orc_initial_v(const orc_config_t* cfg, int64_t j) {
+/* Initial state.  LIF: potential uniform on [0, v_reset) (24 random bits scaled exactly,
+ * times v_reset), no calcium.  Izhikevich: potential uniform on [c, c + 5) mV around the
+ * reset value and recovery u = b v (the resting relation), in float32. */
+static int is_excitatory(const orc_config_t* cfg, int64_t j) {
+  return (int32_t)(j % cfg->npc) < cfg->n_exc;
+}
+
+void orc_initial_state(const orc_config_t* cfg, int64_t j, float* v, float* ca) {
   uint32_t r[4];
   draw(cfg, (uint32_t)j, 0u, 0u, ORC_STREAM_INIT, r);
   float unit = (float)(r[0] >> 8) * 0x1p-24f;
-  return (float)cfg->v_reset * unit;
+  if (cfg->neuron_model == ORC_NEURON_IZHIKEVICH) {
+    int e = is_excitatory(cfg, j);
+    float c = (float)(e ? cfg->izh_c_e : cfg->izh_c_i);
+    float b = (float)(e ? cfg->izh_b_e : cfg->izh_b_i);
+    float spread = 5.0f * unit;
+    *v = c + spread;
+    *ca = b * *v;
+  } else {
+    *v = (float)cfg->v_reset * unit;
+    *ca = 0.0f;
+  }
+}
+
+float orc_initial_v(const orc_config_t* cfg, int64_t j) {
+  float v, ca;
+  orc_initial_state(cfg, j, &v, &ca);
+  return v;
 }
 
 /* ---------------------------------------------------------------------------
@@ -286,7 +308,8 @@ struct orc_sim {
   int32_t D;            /* ring slots: d_max + 1 */
   uint64_t ptab[63];
   float* v;
-  float* ca;
+  float* ca;            /* calcium (LIF) or recovery variable u (Izhikevich) */
+  float* na;            /* sodium-dependent AHP variable (LIF) */
   uint8_t* ref;
   uint32_t* ring;       /* [D][n]; slot u % D holds the input of step u */
   int64_t now;
@@ -311,10 +334,11 @@ orc_sim_t* orc_sim_create(const orc_config_t* cfg, int64_t n, const int64_t* row
   orc_poisson_table((double)cfg->ext_syn * cfg->ext_rate_hz * cfg->dt * 1e-3, s->ptab);
   s->v = (float*)malloc(sizeof(float) * (size_t)n);
   s->ca = (float*)calloc((size_t)n, sizeof(float));
+  s->na = (float*)calloc((size_t)(n > 0 ? n : 1), sizeof(float));
   s->ref = (uint8_t*)calloc((size_t)n, 1);
   s->ring = (uint32_t*)calloc((size_t)s->D * (size_t)n, sizeof(uint32_t));
   s->spiked = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
-  for (int64_t j = 0; j < n; ++j) s->v[j] = orc_initial_v(cfg, j);
+  for (int64_t j = 0; j < n; ++j) orc_initial_state(cfg, j, &s->v[j], &s->ca[j]);
   s->off_cap = 1024;
   s->sp_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)s->off_cap);
   s->sp_off[0] = 0;
@@ -325,7 +349,7 @@ orc_sim_t* orc_sim_create(const orc_config_t* cfg, int64_t n, const int64_t* row
 
 void orc_sim_destroy(orc_sim_t* s) {
   if (!s) return;
-  free(s->v); free(s->ca); free(s->ref); free(s->ring); free(s->spiked);
+  free(s->v); free(s->ca); free(s->na); free(s->ref); free(s->ring); free(s->spiked);
   free(s->sp_ids); free(s->sp_off);
   free(s->r_vprev); free(s->r_caprev); free(s->r_vt); free(s->r_s); free(s->r_r);
   free(s->r_in);
@@ -355,37 +379,97 @@ static void grow_record(orc_sim_t* s) {
 }
 
 /* Neuron constants, computed in double and rounded once to float. */
-typedef struct { float pm, pc, gam, alpha, theta, vreset; int32_t jfx, tref; } consts_t;
+typedef struct {
+  int32_t model;
+  float pm, pc, gam, alpha, theta, vreset;
+  float pna, gna, alpha_na;        /* sodium-dependent AHP */
+  float ia[2], ib[2], ic[2], id[2], vpeak;  /* Izhikevich: [0] excitatory, [1] inhibitory */
+  int32_t jfx, tref;
+} consts_t;
 
 static consts_t constants_of(const orc_config_t* cfg) {
   consts_t k;
+  k.model = cfg->neuron_model;
   k.pm = (float)exp(-cfg->dt / cfg->tau_m);
   k.pc = (float)exp(-cfg->dt / cfg->tau_ca);
   k.gam = (float)(cfg->g_ahp * cfg->dt);
   k.alpha = (float)cfg->ca_inc;
   k.theta = (float)cfg->theta;
   k.vreset = (float)cfg->v_reset;
+  k.pna = cfg->tau_na > 0.0 ? (float)exp(-cfg->dt / cfg->tau_na) : 0.0f;
+  k.gna = (float)(cfg->g_na * cfg->dt);
+  k.alpha_na = (float)cfg->na_inc;
+  k.ia[0] = (float)cfg->izh_a_e; k.ib[0] = (float)cfg->izh_b_e;
+  k.ic[0] = (float)cfg->izh_c_e; k.id[0] = (float)cfg->izh_d_e;
+  k.ia[1] = (float)cfg->izh_a_i; k.ib[1] = (float)cfg->izh_b_i;
+  k.ic[1] = (float)cfg->izh_c_i; k.id[1] = (float)cfg->izh_d_i;
+  k.vpeak = (float)cfg->izh_vpeak;
   k.jfx = (int32_t)rint(cfg->j_ext * 65536.0);
-  k.tref = cfg->t_ref;
+  k.tref = cfg->neuron_model == ORC_NEURON_IZHIKEVICH ? 0 : cfg->t_ref;
   return k;
 }
 
-/* The neuron part of a step (paper section 2: LIF with calcium-driven AHP):
- *  - the input is A = recurrent input + n_ext * J_ext (int32, wrap-around), I = A 2^-16 mV;
+/* Half a millisecond of the Izhikevich membrane equation (Izhikevich, "Simple model of
+ * spiking neurons", IEEE TNN 2003): v' = 0.04 v^2 + 5 v + 140 - u + I, one Euler step of
+ * 0.5 ms, the terms added from left to right. */
+static float izh_half_step(float v, float u, float cur) {
+  float sq = v * v;
+  float quad = 0.04f * sq;
+  float lin = 5.0f * v;
+  float rhs = quad + lin;
+  rhs = rhs + 140.0f;
+  rhs = rhs - u;
+  rhs = rhs + cur;
+  float half = 0.5f * rhs;
+  return v + half;
+}
+
+/* The neuron part of a step.  The input is A = recurrent input + n_ext * J_ext (int32,
+ * wrap-around), I = A 2^-16 mV.
+ * LIF with spike-frequency adaptation (paper section 2: calcium- and sodium-dependent AHP
+ * currents):
  *  - a refractory neuron counts down, stays at V_reset and discards its input;
- *  - otherwise V~ = ((P_m V) - (gamma Ca)) + I, with P_m = exp(-dt/tau_m) and
- *    gamma = g_AHP dt; a spike is emitted if V~ >= theta, then V <- V_reset and the
- *    refractory counter is set;
- *  - Ca <- P_c Ca + alpha s, with P_c = exp(-dt/tau_Ca).
- * Returns the spike flag; *vt receives V~ (0 when refractory), *refr the refractory flag,
- * *a_out the consumed input. */
-static int neuron_update(const consts_t* k, uint32_t rec_input, int32_t n_ext, float* v, float* ca,
-                         uint8_t* ref, float* vt_out, int* refr_out, uint32_t* a_out) {
+ *  - otherwise V~ = (((P_m V) - (gamma Ca)) - (gamma_Na Na)) + I, with P_m = exp(-dt/tau_m),
+ *    gamma = g_AHP dt and gamma_Na = g_Na dt; a spike is emitted if V~ >= theta, then
+ *    V <- V_reset and the refractory counter is set;
+ *  - Ca <- P_c Ca + alpha s and Na <- P_Na Na + alpha_Na s, P_x = exp(-dt/tau_x).
+ *  With g_Na = 0 the sodium term is an exact zero and the step is the one-variable model.
+ * Izhikevich neurons (the earlier report's RS/FS neurons; Izhikevich, IEEE TNN 2003): two
+ * half-millisecond Euler steps of v' = 0.04 v^2 + 5 v + 140 - u + I, then
+ * u <- u + a (b v - u) with the new v; a spike if v >= v_peak, then v <- c and u <- u + d
+ * (a, b, c, d of the neuron's type: RS for excitatory, FS for inhibitory neurons); no
+ * refractory period.  The recovery variable u lives where LIF keeps Ca.
+ * Returns the spike flag; *vt receives V~ (the potential before the reset; 0 when
+ * refractory), *refr the refractory flag, *a_out the consumed input. */
+static int neuron_update(const consts_t* k, int excit, uint32_t rec_input, int32_t n_ext, float* v,
+                         float* ca, float* na, uint8_t* ref, float* vt_out, int* refr_out,
+                         uint32_t* a_out) {
   uint32_t a = rec_input + (uint32_t)n_ext * (uint32_t)k->jfx;
   float cur = (float)(int32_t)a * 0x1p-16f;
   float vprev = *v, caprev = *ca;
   float vt = 0.0f;
   int spike = 0, refr = 0;
+  if (k->model == ORC_NEURON_IZHIKEVICH) {
+    int t = excit ? 0 : 1;
+    float v1 = izh_half_step(vprev, caprev, cur);
+    float v2 = izh_half_step(v1, caprev, cur);
+    float bv = k->ib[t] * v2;
+    float gap = bv - caprev;
+    float du = k->ia[t] * gap;
+    float unew = caprev + du;
+    vt = v2;
+    if (v2 >= k->vpeak) {
+      spike = 1;
+      *v = k->ic[t];
+      *ca = unew + k->id[t];
+    } else {
+      *v = v2;
+      *ca = unew;
+    }
+    *vt_out = vt; *refr_out = 0; *a_out = a;
+    return spike;
+  }
+  float naprev = na ? *na : 0.0f;
   if (*ref > 0) {
     refr = 1;
     *ref -= 1;
@@ -394,6 +478,8 @@ static int neuron_update(const consts_t* k, uint32_t rec_input, int32_t n_ext, f
     float leak = k->pm * vprev;
     float ahp = k->gam * caprev;
     float drop = leak - ahp;
+    float ahp_na = k->gna * naprev;
+    drop = drop - ahp_na;
     vt = drop + cur;
     if (vt >= k->theta) {
       spike = 1;
@@ -405,29 +491,36 @@ static int neuron_update(const consts_t* k, uint32_t rec_input, int32_t n_ext, f
   }
   float decayed = k->pc * caprev;
   *ca = decayed + (spike ? k->alpha : 0.0f);
+  if (na) {
+    float na_decayed = k->pna * naprev;
+    *na = na_decayed + (spike ? k->alpha_na : 0.0f);
+  }
   *vt_out = vt; *refr_out = refr; *a_out = a;
   return spike;
 }
 
 int orc_neuron_update(const orc_config_t* cfg, int64_t j, int64_t u, int32_t rec_input, float* v,
-                      float* ca, uint8_t* ref) {
+                      float* ca, uint8_t* ref, float* na) {
   consts_t k = constants_of(cfg);
   int32_t n_ext;
   orc_ext_counts(cfg, u, j, 1, &n_ext);
   float vt; int refr; uint32_t a;
-  return neuron_update(&k, (uint32_t)rec_input, n_ext, v, ca, ref, &vt, &refr, &a);
+  return neuron_update(&k, is_excitatory(cfg, j), (uint32_t)rec_input, n_ext, v, ca, na, ref, &vt,
+                       &refr, &a);
 }
 
 void orc_update_many(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n,
-                     const int32_t* rec_input, float* v, float* ca, uint8_t* ref, uint8_t* spk) {
+                     const int32_t* rec_input, float* v, float* ca, uint8_t* ref, uint8_t* spk,
+                     float* na) {
   consts_t k = constants_of(cfg);
   int32_t* n_ext = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
   orc_ext_counts(cfg, u, j0, n, n_ext);
 #pragma omp parallel for schedule(static)
   for (int64_t q = 0; q < n; ++q) {
     float vt; int refr; uint32_t a;
-    spk[q] = (uint8_t)neuron_update(&k, (uint32_t)rec_input[q], n_ext[q], &v[q], &ca[q], &ref[q],
-                                    &vt, &refr, &a);
+    spk[q] = (uint8_t)neuron_update(&k, is_excitatory(cfg, j0 + q), (uint32_t)rec_input[q],
+                                    n_ext[q], &v[q], &ca[q], na ? &na[q] : NULL, &ref[q], &vt,
+                                    &refr, &a);
   }
   free(n_ext);
 }
@@ -499,7 +592,8 @@ int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
       float vprev = s->v[j], caprev = s->ca[j], vt;
       int refr;
       uint32_t a;
-      int spike = neuron_update(&k, in[j], next, &s->v[j], &s->ca[j], &s->ref[j], &vt, &refr, &a);
+      int spike = neuron_update(&k, is_excitatory(&s->cfg, j), in[j], next, &s->v[j], &s->ca[j],
+                                &s->na[j], &s->ref[j], &vt, &refr, &a);
       in[j] = 0;
       consumed += (int64_t)(int32_t)a;
       s->spiked[j] = (uint8_t)spike;
@@ -591,6 +685,14 @@ void orc_sim_set_state(orc_sim_t* s, int64_t now, const float* v, const float* c
     int64_t slot = (now + q) % s->D;
     for (int64_t j = 0; j < s->n; ++j) s->ring[slot * s->n + j] = (uint32_t)pend[q * s->n + j];
   }
+}
+
+void orc_sim_get_na(const orc_sim_t* s, float* na) {
+  memcpy(na, s->na, sizeof(float) * (size_t)s->n);
+}
+
+void orc_sim_set_na(orc_sim_t* s, const float* na) {
+  memcpy(s->na, na, sizeof(float) * (size_t)s->n);
 }
 
 void orc_sim_inject(orc_sim_t* s, int32_t q, int64_t j, int32_t value) {

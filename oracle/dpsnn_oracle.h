@@ -63,7 +63,18 @@ typedef struct {
   double ext_rate_hz;   /* rate of each external synapse */
   int32_t ext_syn;      /* external synapses per neuron */
   double j_ext;         /* external synaptic efficacy, mV */
+  /* neuron model variants (paper section 2: spike-frequency adaptation through calcium- and
+   * sodium-dependent AHP currents; the earlier report's Izhikevich RS/FS neurons) */
+  int32_t neuron_model; /* ORC_NEURON_LIF or ORC_NEURON_IZHIKEVICH */
+  double tau_na;        /* LIF: time constant of the sodium-dependent AHP variable, ms */
+  double na_inc;        /* LIF: its increment per spike */
+  double g_na;          /* LIF: its conductance, mV per unit per ms (0: one AHP variable) */
+  double izh_a_e, izh_b_e, izh_c_e, izh_d_e;  /* Izhikevich, excitatory neurons (RS) */
+  double izh_a_i, izh_b_i, izh_c_i, izh_d_i;  /* Izhikevich, inhibitory neurons (FS) */
+  double izh_vpeak;     /* Izhikevich spike cut-off, mV */
 } orc_config_t;
+
+enum { ORC_NEURON_LIF = 0, ORC_NEURON_IZHIKEVICH = 1 };
 
 /* Host threads of the loops over independent rows and neurons (OpenMP); results do not
  * depend on the thread count. */
@@ -96,14 +107,17 @@ int32_t orc_poisson_count(const uint64_t tab[63], uint32_t x);
 void orc_ext_counts(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n, int32_t* out);
 
 /* Update one neuron at step u from its state and recurrent input (2^-16 mV), drawing its
- * external count; returns the spike flag.  Same arithmetic as a simulation step. */
+ * external count; returns the spike flag.  Same arithmetic as a simulation step.  ca holds
+ * the Izhikevich recovery variable u for that model; na (the sodium-dependent AHP variable)
+ * may be NULL when g_na = 0. */
 int orc_neuron_update(const orc_config_t* cfg, int64_t j, int64_t u, int32_t rec_input, float* v,
-                      float* ca, uint8_t* ref);
+                      float* ca, uint8_t* ref, float* na);
 
 /* orc_neuron_update for neurons j0 .. j0+n-1 at step u (arrays of n, updated in place;
- * spk receives the spike flags). */
+ * spk receives the spike flags; na may be NULL when g_na = 0). */
 void orc_update_many(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n,
-                     const int32_t* rec_input, float* v, float* ca, uint8_t* ref, uint8_t* spk);
+                     const int32_t* rec_input, float* v, float* ca, uint8_t* ref, uint8_t* spk,
+                     float* na);
 
 /* Brute-force recurrent input (2^-16 mV) arriving at step t_arr at each of nt target
  * neurons, from the spikes emitted at steps e <= t_emit_max: mask[e - mask_t0][i] != 0 iff
@@ -112,8 +126,10 @@ void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets
                      int64_t t_emit_max, const uint8_t* mask, int64_t mask_t0, int64_t mask_steps,
                      int32_t* out);
 
-/* Initial membrane potential of neuron j. */
+/* Initial membrane potential of neuron j; orc_initial_state also gives the second state
+ * variable (Ca = 0 for LIF, the recovery variable u = b v for Izhikevich). */
 float orc_initial_v(const orc_config_t* cfg, int64_t j);
+void orc_initial_state(const orc_config_t* cfg, int64_t j, float* v, float* ca);
 
 /* ---- simulation -------------------------------------------------------- */
 typedef struct orc_sim orc_sim_t;
@@ -139,6 +155,9 @@ int64_t orc_sim_consumed(const orc_sim_t* s);
 void orc_sim_get_state(const orc_sim_t* s, float* v, float* ca, uint8_t* ref, int32_t* pend);
 void orc_sim_set_state(orc_sim_t* s, int64_t now, const float* v, const float* ca,
                        const uint8_t* ref, const int32_t* pend);
+/* The sodium-dependent AHP variable of every neuron (n). */
+void orc_sim_get_na(const orc_sim_t* s, float* na);
+void orc_sim_set_na(orc_sim_t* s, const float* na);
 /* Test hook: add value (2^-16 mV) to the input of neuron j at step now+q. */
 void orc_sim_inject(orc_sim_t* s, int32_t q, int64_t j, int32_t value);
 

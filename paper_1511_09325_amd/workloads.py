@@ -25,6 +25,12 @@ COLUMN_RECIPE = dict(
     tau_m=20.0, theta=20.0, v_reset=15.0, t_ref=2,
     tau_ca=300.0, ca_inc=0.05, g_ahp=0.2, dt=1.0,
     ext_rate_hz=3.0, ext_syn=1000, j_ext=0.3,
+    # neuron model variants, off in the column recipe: a second (sodium-dependent) AHP
+    # variable (g_na = 0: one AHP variable) and the Izhikevich RS/FS neurons with their
+    # published parameters (Izhikevich, IEEE TNN 2003)
+    neuron_model=0, tau_na=100.0, na_inc=0.02, g_na=0.0,
+    izh_a_e=0.02, izh_b_e=0.2, izh_c_e=-65.0, izh_d_e=8.0,
+    izh_a_i=0.1, izh_b_i=0.2, izh_c_i=-65.0, izh_d_i=2.0, izh_vpeak=30.0,
 )
 
 
