@@ -305,6 +305,32 @@ def rate_matched_leg(torch, steps=1000, warmup=50):
     return out
 
 
+def models_leg(torch, warmup=50):
+    """The neuron-model variants on the 24x24 grid (1 s each, the default launch): LIF with a
+    second (sodium-dependent) AHP variable and Izhikevich RS/FS neurons, beside the plain LIF
+    network of the same grid over the same steps."""
+    from paper_1511_09325_amd import Simulation
+    from paper_1511_09325_amd import workloads as W
+    out = {}
+    for key, preset in (("plain_lif", dict(W.PLAIN_24X24, steps=1000)),
+                        ("sodium_ahp", W.SODIUM_AHP_24X24), ("izhikevich", W.IZHIKEVICH_24X24)):
+        p, steps = preset["params"], preset["steps"]
+        sim = Simulation(p)
+        sim.step(warmup)
+        sim.sync()
+        t, ev, spk = _timed_run(sim, steps - warmup, torch)
+        out[key] = {"workload": preset["name"] if key != "plain_lif"
+                    else "24x24, LIF with the calcium AHP, 1 s",
+                    "timed_steps": "%d-%d" % (warmup, steps - 1),
+                    "ms_per_step": t * 1e3 / (steps - warmup), "events_per_s": ev / t,
+                    "sim_ms_per_wall_s": (steps - warmup) * p["dt"] / t,
+                    "mean_rate_hz": spk / (sim.n_neurons * (steps - warmup) * p["dt"] * 1e-3)}
+        sim.close()
+        del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def fwd_bwd_leg(torch, iters=3):
     """Forward+backward on the 4x4 grid (19,840 neurons), 500 ms, checkpoints every 50
     steps: loss = mean over columns of (rate - target)^2 with seeded U(2, 8) Hz targets,
@@ -479,6 +505,7 @@ def main():
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--no-rate-matched", action="store_true")
     ap.add_argument("--no-small-grids", action="store_true")
+    ap.add_argument("--no-models", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB once (a reference kernel of known "
                          "traffic for hardware byte counters)")
@@ -538,6 +565,9 @@ def main():
     if not args.no_small_grids and args.workload == "96x96":
         log("small-grid legs: the whole 24x24 (10 s) and 2x2 (1 s) workloads")
         out["small_grids"] = {w: plain_leg(torch, w, None, args.warmup) for w in ("24x24", "2x2")}
+    if not args.no_models and args.workload == "96x96":
+        log("neuron-model legs: 24x24 with the sodium AHP and with Izhikevich neurons")
+        out["models"] = models_leg(torch)
     if not args.no_batched:
         log("batched leg: 64 networks, one launch per step, vs 64 sequential runs")
         out["batched"] = batched_leg(torch)

@@ -44,6 +44,11 @@ extern "C" {
 #define DPSNN_ESTATE (-4) /* call not valid in the current state */
 #define DPSNN_ETRUNC (-5) /* an output buffer is too small (size needed is reported) */
 
+/* Neuron model (section 2: LIF neurons with spike-frequency adaptation through calcium- and
+ * sodium-dependent AHP currents; the Izhikevich RS/FS neurons of the earlier report). */
+#define DPSNN_NEURON_LIF 0
+#define DPSNN_NEURON_IZHIKEVICH 1
+
 /* Spike delivery strategy. Both give bit-identical results. */
 #define DPSNN_DELIVERY_AUTO 0
 #define DPSNN_DELIVERY_ARRIVAL 1 /* per target column: gather arrivals, fused with the update */
@@ -89,6 +94,19 @@ typedef struct {
   int32_t train_mode;    /* 1: float32 master weights, trajectory recording, sim_backward */
   int32_t ckpt_every;    /* train mode: checkpoint interval in steps (>= 1) */
   double surrogate_beta; /* train mode: slope of the fast-sigmoid surrogate, 1/mV (> 0) */
+  /* neuron model variants (section 2 names the sodium-dependent AHP; neither variant is
+   * parameterised in the paper).  LIF: a second AHP variable Na, V~ = ((P_m V - g_AHP dt Ca)
+   * - g_na dt Na) + I, Na <- exp(-dt/tau_na) Na + na_inc s (off when g_na = 0).
+   * Izhikevich (IEEE TNN 2003): two 0.5 ms Euler steps of v' = 0.04 v^2 + 5 v + 140 - u + I,
+   * u <- u + a (b v - u), spike at v >= izh_vpeak, then v <- c, u <- u + d; excitatory
+   * neurons take the _e parameters (RS), inhibitory ones the _i parameters (FS); no
+   * refractory period; u is kept (and read by sim_read_state) where LIF keeps Ca; theta,
+   * v_reset, t_ref, tau_m and the AHP fields are unused.  Train mode needs LIF with g_na = 0. */
+  int32_t neuron_model;  /* DPSNN_NEURON_* */
+  double tau_na, na_inc, g_na;
+  double izh_a_e, izh_b_e, izh_c_e, izh_d_e;
+  double izh_a_i, izh_b_i, izh_c_i, izh_d_i;
+  double izh_vpeak;
 } sim_config_t;
 
 /* Sizes of a created simulation. */
@@ -262,9 +280,11 @@ int64_t sim_now(const sim_t* sim);
  * view of network `net` (host buffers, n = neurons of the network):
  * v, ca (float32 [n]), ref (uint8 [n]), pend (int32 [ring_slots][n]) where pend[q][j] is
  * the recurrent input already emitted towards neuron j for step now+q (the delivery
- * strategy's internal form is converted to this view).  Any pointer may be NULL.
+ * strategy's internal form is converted to this view), na (float32 [n], the sodium AHP
+ * variable; zeros when g_na = 0).  Any pointer may be NULL.
  * Synchronises. */
-int sim_read_state(sim_t* sim, int32_t net, float* v, float* ca, uint8_t* ref, int32_t* pend);
+int sim_read_state(sim_t* sim, int32_t net, float* v, float* ca, uint8_t* ref, int32_t* pend,
+                   float* na);
 
 /* Paper section 2 (Methods: the synapses, their delays and weights), synapses of network
  * `net`, source neurons [i0, i1), in canonical order: row_ptr (host,

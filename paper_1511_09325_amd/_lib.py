@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libdpsnn.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ETRUNC = 0, -1, -2, -3, -4, -5
 DELIVERY_AUTO, DELIVERY_ARRIVAL, DELIVERY_PUSH = 0, 1, 2
+NEURON_LIF, NEURON_IZHIKEVICH = 0, 1
 
 #: Every entry point declared in include/dpsnn.h.
 EXPORTS = [
@@ -47,6 +48,12 @@ class SimConfig(C.Structure):
         ("record_steps", C.c_int64), ("raster_capacity", C.c_int64),
         ("train_mode", C.c_int32), ("ckpt_every", C.c_int32),
         ("surrogate_beta", C.c_double),
+        ("neuron_model", C.c_int32), ("tau_na", C.c_double), ("na_inc", C.c_double),
+        ("g_na", C.c_double),
+        ("izh_a_e", C.c_double), ("izh_b_e", C.c_double), ("izh_c_e", C.c_double),
+        ("izh_d_e", C.c_double),
+        ("izh_a_i", C.c_double), ("izh_b_i", C.c_double), ("izh_c_i", C.c_double),
+        ("izh_d_i", C.c_double), ("izh_vpeak", C.c_double),
     ]
 
 
@@ -118,7 +125,7 @@ def lib():
         "sim_get_stats": (C.c_int, [vp, C.c_int32, P(SimStats)]),
         "sim_now": (C.c_int64, [vp]),
         "sim_read_state": (C.c_int, [vp, C.c_int32, P(C.c_float), P(C.c_float), P(C.c_uint8),
-                                     P(C.c_int32)]),
+                                     P(C.c_int32), P(C.c_float)]),
         "sim_read_synapses": (C.c_int, [vp, C.c_int32, C.c_int64, C.c_int64, P(C.c_int64),
                                         P(C.c_int32), P(C.c_uint8), P(C.c_int16), C.c_int64]),
         "sim_save": (C.c_int, [vp, C.c_int32]),

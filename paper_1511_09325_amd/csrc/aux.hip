@@ -155,7 +155,8 @@ __global__ __launch_bounds__(256) void k_digest(StepArgs a, int64_t now, uint64_
   uint64_t h = 0;
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < nall; j += (int64_t)gridDim.x * 256) {
     const uint64_t v = __float_as_uint(a.v[j]), c = __float_as_uint(a.ca[j]);
-    h += mix64(((uint64_t)j << 2) ^ (v << 32) ^ c ^ ((uint64_t)a.ref[j] << 40));
+    const uint64_t na = a.na ? __float_as_uint(a.na[j]) : 0u;  // sodium AHP variable, if kept
+    h += mix64(((uint64_t)j << 2) ^ (v << 32) ^ c ^ ((uint64_t)a.ref[j] << 40) ^ (na << 7));
     const int32_t g = (int32_t)(j / a.npc), k = (int32_t)(j - (int64_t)g * a.npc);
     for (int back = 1; back <= a.dh - 1; ++back) {
       const int64_t t = now - back;

@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -149,6 +150,18 @@ void validate(const sim_config_t* c) {
   if (c->record_steps < 0 || c->raster_capacity < 0) bad("raster sizes must be >= 0");
   if (c->train_mode && c->ckpt_every < 1) bad("ckpt_every must be >= 1 in train mode");
   if (c->train_mode && !(c->surrogate_beta > 0)) bad("surrogate_beta must be > 0 in train mode");
+  if (c->neuron_model != DPSNN_NEURON_LIF && c->neuron_model != DPSNN_NEURON_IZHIKEVICH)
+    bad("unknown neuron_model");
+  if (c->neuron_model == DPSNN_NEURON_LIF && c->g_na != 0.0 && !(c->tau_na > 0))
+    bad("tau_na must be positive when g_na != 0");
+  if (c->neuron_model == DPSNN_NEURON_IZHIKEVICH &&
+      !(std::isfinite(c->izh_vpeak) && std::isfinite(c->izh_a_e) && std::isfinite(c->izh_b_e) &&
+        std::isfinite(c->izh_c_e) && std::isfinite(c->izh_d_e) && std::isfinite(c->izh_a_i) &&
+        std::isfinite(c->izh_b_i) && std::isfinite(c->izh_c_i) && std::isfinite(c->izh_d_i)))
+    bad("Izhikevich parameters must be finite");
+  if (c->train_mode && (c->neuron_model != DPSNN_NEURON_LIF || c->g_na != 0.0))
+    bad("train mode needs the LIF neuron with g_na = 0 (the adjoint of the other models is not "
+        "defined)");
   int64_t cols = 0;
   for (int n = 0; n < c->n_nets; ++n) {
     const sim_net_t& t = c->nets[n];
@@ -176,6 +189,22 @@ void set_constants(sim& s) {
   s.nk.vreset = (float)c.v_reset;
   s.nk.jfx = (int32_t)rint(c.j_ext * 65536.0);
   s.nk.tref = c.t_ref;
+  s.nk.pna = c.tau_na > 0 ? (float)exp(-c.dt / c.tau_na) : 0.0f;
+  s.nk.gna = (float)(c.g_na * c.dt);
+  s.nk.alpha_na = (float)c.na_inc;
+  s.nk.vpeak = (float)c.izh_vpeak;
+  const double ia[2] = {c.izh_a_e, c.izh_a_i}, ib[2] = {c.izh_b_e, c.izh_b_i},
+               ic[2] = {c.izh_c_e, c.izh_c_i}, id[2] = {c.izh_d_e, c.izh_d_i};
+  for (int t = 0; t < 2; ++t) {
+    s.nk.ia[t] = (float)ia[t];
+    s.nk.ib[t] = (float)ib[t];
+    s.nk.ic[t] = (float)ic[t];
+    s.nk.id[t] = (float)id[t];
+  }
+  s.model = c.neuron_model == DPSNN_NEURON_IZHIKEVICH ? kModelIzh
+            : c.g_na != 0.0                           ? kModelLifNa
+                                                      : kModelLif;
+  if (s.model == kModelIzh) s.nk.tref = 0;  // no refractory period
 }
 
 // Compute units of the current device (256 on an MI355X when the query fails).
@@ -624,10 +653,11 @@ void ring_from_history(sim& s) {
 
 // The dynamic state saved by a snapshot.  The push ring is not part of it: it is rebuilt
 // from the spike history on restore.
-constexpr int kSnapParts = 7;
+constexpr int kSnapParts = 8;
 
 void snapshot_parts(sim& s, size_t* parts, void** ptrs) {
   const size_t N = (size_t)s.n_neurons;
+  parts[7] = s.na ? sizeof(float) * N : 0;                         ptrs[7] = s.na;
   parts[6] = sizeof(unsigned long long) * (size_t)s.n_cols;         ptrs[6] = s.col_spk;
   parts[0] = sizeof(float) * N;                                    ptrs[0] = s.v;
   parts[1] = sizeof(float) * N;                                    ptrs[1] = s.ca;
@@ -786,6 +816,7 @@ int create_impl(const sim_config_t* cfg, const sim_buffers_t* bufs, void* hip_st
     s->v = (float*)carve(*s, kRegState, sizeof(float) * N);
     s->ca = (float*)carve(*s, kRegState, sizeof(float) * N);
     s->ref = (uint8_t*)carve(*s, kRegState, N);
+    if (s->model == kModelLifNa) s->na = (float*)dalloc(*s, sizeof(float) * N);
     s->hist_cnt = (int32_t*)carve(*s, kRegHist, sizeof(int32_t) * (size_t)s->dh * s->n_cols);
     s->hist_ids = (uint16_t*)carve(*s, kRegHist, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
     s->hist_st = (uint32_t*)carve(*s, kRegHist, sizeof(uint32_t) * (size_t)s->dh * s->n_parts * s->npc);
@@ -1146,7 +1177,8 @@ int sim_get_stats(sim_t* s, int32_t net, sim_stats_t* st) {
   }
 }
 
-int sim_read_state(sim_t* s, int32_t net, float* v, float* ca, uint8_t* ref, int32_t* pend) {
+int sim_read_state(sim_t* s, int32_t net, float* v, float* ca, uint8_t* ref, int32_t* pend,
+                   float* na) {
   if (!s) return DPSNN_EINVAL;
   try {
     if (net < 0 || net >= s->n_nets) throw Fail{DPSNN_EINVAL, "net out of range"};
@@ -1157,6 +1189,10 @@ int sim_read_state(sim_t* s, int32_t net, float* v, float* ca, uint8_t* ref, int
     if (v) HIPCHK(hipMemcpy(v, s->v + n0, sizeof(float) * nn, hipMemcpyDeviceToHost));
     if (ca) HIPCHK(hipMemcpy(ca, s->ca + n0, sizeof(float) * nn, hipMemcpyDeviceToHost));
     if (ref) HIPCHK(hipMemcpy(ref, s->ref + n0, nn, hipMemcpyDeviceToHost));
+    if (na) {
+      if (s->na) HIPCHK(hipMemcpy(na, s->na + n0, sizeof(float) * nn, hipMemcpyDeviceToHost));
+      else memset(na, 0, sizeof(float) * nn);
+    }
     if (pend) {
       if (s->delivery == DPSNN_DELIVERY_PUSH) {
         for (int q = 0; q < s->dh; ++q) {

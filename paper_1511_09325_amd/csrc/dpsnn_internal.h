@@ -117,6 +117,12 @@ __device__ __forceinline__ Rand4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   return Rand4{c0, c1, c2, c3};
 }
 
+// Neuron models of the step kernels (a template parameter): LIF with the calcium AHP only,
+// LIF with the calcium and sodium AHP variables, Izhikevich RS/FS.
+constexpr int kModelLif = 0;
+constexpr int kModelLifNa = 1;
+constexpr int kModelIzh = 2;
+
 // Neuron constants, rounded once from double on the host.
 struct NeuronK {
   float pm;      // exp(-dt / tau_m)
@@ -127,12 +133,18 @@ struct NeuronK {
   float vreset;
   int32_t jfx;   // rint(j_ext * 2^16)
   int32_t tref;
+  float pna;     // exp(-dt / tau_na)
+  float gna;     // g_na * dt
+  float alpha_na;  // sodium-variable increment
+  float vpeak;   // Izhikevich spike cut-off
+  float ia[2], ib[2], ic[2], id[2];  // Izhikevich a, b, c, d: [0] excitatory, [1] inhibitory
 };
 
 // Everything the step kernels read or write, by value.
 struct StepArgs {
   // sizes
   int32_t npc, nd, d_min, dh, n_cols, idxw;
+  int32_t n_exc;               // local index k < n_exc: excitatory
   // step numbers: u = u_arg + *now_dev when now_dev is set (replayable graph steps)
   const int64_t* now_dev;
   // column / network tables
@@ -169,7 +181,8 @@ struct StepArgs {
   const int32_t* wfx;         // train mode, else null
   // state
   float* v;
-  float* ca;
+  float* ca;                  // calcium (LIF) or the recovery variable u (Izhikevich)
+  float* na;                  // sodium AHP variable (LIF with g_na != 0), else null
   uint8_t* ref;
   int32_t* hist_cnt;
   uint16_t* hist_ids;
@@ -281,8 +294,9 @@ struct sim {
   uint32_t* syn = nullptr;
   int32_t* wfx = nullptr;
   float* wf32 = nullptr;
-  float *v = nullptr, *ca = nullptr;
+  float *v = nullptr, *ca = nullptr, *na = nullptr;
   uint8_t* ref = nullptr;
+  int32_t model = dpsnn::kModelLif;  // kModel* of the step kernels
   int32_t* hist_cnt = nullptr;
   uint16_t* hist_ids = nullptr;
   uint32_t* hist_st = nullptr;

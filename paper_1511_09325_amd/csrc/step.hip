@@ -98,18 +98,61 @@ __device__ __forceinline__ int32_t poisson_count(const uint64_t* tab, uint32_t x
   return pos;
 }
 
-// One neuron's step from its state and input (no memory access).
+// One neuron's step from its state and input (no memory access).  MODEL (kModel*):
+//   LIF:      refractory: count down, V = V_reset, input discarded; else
+//             V~ = ((P_m V) - (gamma Ca)) + I [- (gamma_Na Na) before adding I with the
+//             sodium variable], spike if V~ >= theta, then V = V_reset and the refractory
+//             counter is set; Ca = P_c Ca + alpha s [Na = P_Na Na + alpha_Na s]
+//   IZH:      two 0.5 ms Euler steps of v' = 0.04 v^2 + 5 v + 140 - u + I, then
+//             u = u + a (b v - u); spike if v >= v_peak, then v = c, u = u + d (a, b, c, d of
+//             the neuron's type; u is kept in the Ca array); no refractory period
+// every operation float32, rounded, in this order (the build turns contraction off).
 struct NeuronOut {
-  float v, ca, vt;
+  float v, ca, na, vt;
   int32_t rf;
   bool spike, refr;
 };
 
+__device__ __forceinline__ float izh_half_step(float v, float u, float cur) {
+  const float sq = v * v;
+  const float quad = 0.04f * sq;
+  const float lin = 5.0f * v;
+  float rhs = quad + lin;
+  rhs = rhs + 140.0f;
+  rhs = rhs - u;
+  rhs = rhs + cur;
+  const float half = 0.5f * rhs;
+  return v + half;
+}
+
+template <int MODEL>
 __device__ __forceinline__ NeuronOut neuron_update(const StepArgs& a, int32_t rec_in, int32_t n_ext,
-                                                  float vprev, float caprev, int32_t rf) {
+                                                  float vprev, float caprev, float naprev,
+                                                  int32_t rf, bool excit) {
   const uint32_t asum = (uint32_t)rec_in + (uint32_t)n_ext * (uint32_t)a.k.jfx;
   const float cur = (float)(int32_t)asum * 0x1p-16f;
-  NeuronOut o{0.0f, 0.0f, 0.0f, rf, false, false};
+  NeuronOut o{0.0f, 0.0f, 0.0f, 0.0f, rf, false, false};
+  if (MODEL == kModelIzh) {
+    const float pa = excit ? a.k.ia[0] : a.k.ia[1], pb = excit ? a.k.ib[0] : a.k.ib[1];
+    const float pc = excit ? a.k.ic[0] : a.k.ic[1], pd = excit ? a.k.id[0] : a.k.id[1];
+    const float v1 = izh_half_step(vprev, caprev, cur);
+    const float v2 = izh_half_step(v1, caprev, cur);
+    const float bv = pb * v2;
+    const float gap = bv - caprev;
+    const float du = pa * gap;
+    const float unew = caprev + du;
+    o.vt = v2;
+    o.rf = 0;
+    if (v2 >= a.k.vpeak) {
+      o.spike = true;
+      o.v = pc;
+      o.ca = unew + pd;
+    } else {
+      o.v = v2;
+      o.ca = unew;
+    }
+    return o;
+  }
   if (rf > 0) {
     o.refr = true;
     o.rf = rf - 1;
@@ -117,7 +160,11 @@ __device__ __forceinline__ NeuronOut neuron_update(const StepArgs& a, int32_t re
   } else {
     const float leak = a.k.pm * vprev;
     const float ahp = a.k.gam * caprev;
-    const float drop = leak - ahp;
+    float drop = leak - ahp;
+    if (MODEL == kModelLifNa) {
+      const float ahp_na = a.k.gna * naprev;
+      drop = drop - ahp_na;
+    }
     o.vt = drop + cur;
     if (o.vt >= a.k.theta) {
       o.spike = true;
@@ -129,16 +176,21 @@ __device__ __forceinline__ NeuronOut neuron_update(const StepArgs& a, int32_t re
   }
   const float decayed = a.k.pc * caprev;
   o.ca = decayed + (o.spike ? a.k.alpha : 0.0f);
+  if (MODEL == kModelLifNa) {
+    const float na_decayed = a.k.pna * naprev;
+    o.na = na_decayed + (o.spike ? a.k.alpha_na : 0.0f);
+  }
   return o;
 }
 
 // Stores a neuron's new state (and its trajectory when recording: REC false compiles the
 // recording out, for kernels that never run with it).
-template <bool REC>
+template <bool REC, int MODEL>
 __device__ __forceinline__ void neuron_store(const StepArgs& a, int64_t j, int64_t u,
                                              const NeuronOut& o, float vprev, float caprev) {
   a.v[j] = o.v;
   a.ca[j] = o.ca;
+  if (MODEL == kModelLifNa) a.na[j] = o.na;
   a.ref[j] = (uint8_t)o.rf;
   if (REC && a.rec_vprev) {
     const int64_t r = (u - a.rec_base) * (int64_t)a.n_cols * a.npc + j;
@@ -149,11 +201,13 @@ __device__ __forceinline__ void neuron_store(const StepArgs& a, int64_t j, int64
   }
 }
 
+template <int MODEL>
 __device__ __forceinline__ bool neuron_step(const StepArgs& a, int64_t j, int64_t u,
                                             int32_t rec_in, int32_t n_ext, float vprev,
-                                            float caprev, int32_t rf) {
-  const NeuronOut o = neuron_update(a, rec_in, n_ext, vprev, caprev, rf);
-  neuron_store<true>(a, j, u, o, vprev, caprev);
+                                            float caprev, int32_t rf, bool excit) {
+  const float naprev = MODEL == kModelLifNa ? a.na[j] : 0.0f;
+  const NeuronOut o = neuron_update<MODEL>(a, rec_in, n_ext, vprev, caprev, naprev, rf, excit);
+  neuron_store<MODEL == kModelLif, MODEL>(a, j, u, o, vprev, caprev);
   return o.spike;
 }
 
@@ -248,7 +302,7 @@ __device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
 // updated in 64-neuron chunks and the spikes compacted per column, in ascending order.
 static_assert(kPoissonEntries <= 64, "one Poisson threshold per lane of the first wave");
 
-template <int BLOCK, bool TRAIN>
+template <int BLOCK, bool TRAIN, int MODEL>
 // At least four waves per SIMD for every workgroup size (at most 128 VGPRs), so that two
 // 512-thread workgroups of the steps inside a window share a compute unit.
 __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc,
@@ -480,7 +534,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
     for (int rd = wave; rd < T * nr; rd += NW) {
       const int col = rd / nr, q0 = (rd - col * nr) * 4;
       const int32_t g = s_col[col];
-      float vv[4], cc[4];
+      float vv[4], cc[4], na4[4];
       int32_t rr[4], nx[4], sv[4];
       bool ok[4];
       // every global load of the round first, so that their latencies overlap: state and, at
@@ -491,12 +545,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         ok[m] = q0 + m < nch && k < npc;
         vv[m] = 0.0f;
         cc[m] = 0.0f;
+        na4[m] = 0.0f;
         rr[m] = 0;
         sv[m] = 0;
         if (ok[m]) {
           const int64_t j = (int64_t)g * npc + k;
           vv[m] = a.v[j];
           cc[m] = a.ca[j];
+          if (MODEL == kModelLifNa) na4[m] = a.na[j];
           rr[m] = a.ref[j];
           if (light) sv[m] = a.acc_save[light_save + j];
         }
@@ -526,7 +582,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         // accumulated recurrent input, to 2^-16 mV (train mode accumulates in those units)
         const uint32_t ai = (uint32_t)acc[col * npc + k] + (uint32_t)sv[m];
         const int32_t in = ok[m] ? (int32_t)(TRAIN ? ai : ai << 2) : 0;
-        o[m] = neuron_update(a, in, nx[m], vv[m], cc[m], rr[m]);
+        o[m] = neuron_update<MODEL>(a, in, nx[m], vv[m], cc[m], na4[m], rr[m], k < a.n_exc);
         o[m].spike = o[m].spike && ok[m];
         if (ok[m]) my_ext += (unsigned long long)nx[m];
       }
@@ -534,7 +590,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
       for (int m = 0; m < 4; ++m) {
         if (q0 + m < nch) {
           const int c = col * nch + q0 + m;
-          if (ok[m]) neuron_store<TRAIN>(a, (int64_t)g * npc + (q0 + m) * 64 + lane, u, o[m], vv[m], cc[m]);
+          if (ok[m])
+            neuron_store<TRAIN, MODEL>(a, (int64_t)g * npc + (q0 + m) * 64 + lane, u, o[m], vv[m], cc[m]);
           const unsigned long long bal = __ballot(o[m].spike);
           if (lane == 0) {
             smask[c] = bal;
@@ -656,7 +713,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
 }
 
 // ---- PUSH: update from the ring, then scatter ------------------------------------------------
-template <int BLOCK>
+template <int BLOCK, int MODEL>
 __global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u_arg) {
   const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
   constexpr int NW = BLOCK / 64;
@@ -687,7 +744,7 @@ __global__ __launch_bounds__(BLOCK) void k_update_push(StepArgs a, int64_t u_arg
         const int32_t x = in[j];
         in[j] = 0;
         const int32_t nx = external_count(a, a.col_local[g], k, u, ptab, key0, key1);
-        sp = neuron_step(a, j, u, x, nx, a.v[j], a.ca[j], a.ref[j]);
+        sp = neuron_step<MODEL>(a, j, u, x, nx, a.v[j], a.ca[j], a.ref[j], k < a.n_exc);
         my_ext += (unsigned long long)nx;
         if (sp) my_rec += (unsigned long long)a.deg[j];
       }
@@ -756,8 +813,10 @@ __global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u_ar
   }
 }
 
-// ---- state initialisation: V uniform on [0, V_reset) from Philox at (j, 0, 0, INIT) --------
-__global__ void k_init_state(StepArgs a) {
+// ---- state initialisation from Philox at (j, 0, 0, INIT) ------------------------------------
+// LIF: V uniform on [0, V_reset), Ca = 0 (Na = 0).  Izhikevich: v uniform on [c, c + 5) mV,
+// u = b v (the resting relation), with c, b of the neuron's type.
+__global__ void k_init_state(StepArgs a, int32_t model) {
   const int64_t nall = (int64_t)a.n_cols * a.npc;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nall;
        j += (int64_t)gridDim.x * blockDim.x) {
@@ -767,8 +826,17 @@ __global__ void k_init_state(StepArgs a) {
     const Rand4 r = philox10((uint32_t)(a.col_local[g] * a.npc + k), 0u, 0u, kStreamInit,
                              a.net_key[2 * net], a.net_key[2 * net + 1]);
     const float unit = (float)(r.x >> 8) * 0x1p-24f;
-    a.v[j] = a.k.vreset * unit;
-    a.ca[j] = 0.0f;
+    if (model == kModelIzh) {
+      const bool excit = k < a.n_exc;
+      const float spread = 5.0f * unit;
+      const float v = (excit ? a.k.ic[0] : a.k.ic[1]) + spread;
+      a.v[j] = v;
+      a.ca[j] = (excit ? a.k.ib[0] : a.k.ib[1]) * v;
+    } else {
+      a.v[j] = a.k.vreset * unit;
+      a.ca[j] = 0.0f;
+    }
+    if (a.na) a.na[j] = 0.0f;
     a.ref[j] = 0;
   }
 }
@@ -776,12 +844,19 @@ __global__ void k_init_state(StepArgs a) {
 template <int BLOCK>
 void launch_tile(const sim& s, const StepArgs& a, int64_t u, int32_t kacc, bool train) {
   const size_t lds = tile_lds_bytes(s, kacc);
-  if (train)
-    hipLaunchKernelGGL((k_step_tile<BLOCK, true>), dim3(s.grid_tiles), dim3(BLOCK), lds,
-                       s.stream, a, u, s.tile_max_cols, kacc);
+  const dim3 grid(s.grid_tiles), block(BLOCK);
+  if (train)  // train mode runs the LIF neuron with one AHP variable only
+    hipLaunchKernelGGL((k_step_tile<BLOCK, true, kModelLif>), grid, block, lds, s.stream, a, u,
+                       s.tile_max_cols, kacc);
+  else if (s.model == kModelLifNa)
+    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelLifNa>), grid, block, lds, s.stream, a,
+                       u, s.tile_max_cols, kacc);
+  else if (s.model == kModelIzh)
+    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelIzh>), grid, block, lds, s.stream, a, u,
+                       s.tile_max_cols, kacc);
   else
-    hipLaunchKernelGGL((k_step_tile<BLOCK, false>), dim3(s.grid_tiles), dim3(BLOCK), lds,
-                       s.stream, a, u, s.tile_max_cols, kacc);
+    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelLif>), grid, block, lds, s.stream, a, u,
+                       s.tile_max_cols, kacc);
 }
 
 template <int BLOCK>
@@ -804,8 +879,17 @@ hipError_t launch_step_b(sim& s, int64_t u, int32_t delivery, int part) {
     }
     return hipGetLastError();
   }
-  if (part != 1)
-    hipLaunchKernelGGL((k_update_push<BLOCK>), dim3(s.grid_cols), dim3(BLOCK), 0, s.stream, a, u);
+  if (part != 1) {
+    if (s.model == kModelLifNa)
+      hipLaunchKernelGGL((k_update_push<BLOCK, kModelLifNa>), dim3(s.grid_cols), dim3(BLOCK), 0,
+                         s.stream, a, u);
+    else if (s.model == kModelIzh)
+      hipLaunchKernelGGL((k_update_push<BLOCK, kModelIzh>), dim3(s.grid_cols), dim3(BLOCK), 0,
+                         s.stream, a, u);
+    else
+      hipLaunchKernelGGL((k_update_push<BLOCK, kModelLif>), dim3(s.grid_cols), dim3(BLOCK), 0,
+                         s.stream, a, u);
+  }
   if (part != 0) {
     if (train)
       hipLaunchKernelGGL((k_deliver_push<BLOCK, true>), dim3(s.n_cols), dim3(BLOCK), 0, s.stream, a, u);
@@ -845,6 +929,7 @@ StepArgs make_step_args(const sim& s) {
   a.dh = s.dh;
   a.n_cols = s.n_cols;
   a.idxw = s.idxw;
+  a.n_exc = s.cfg.n_exc;
   a.now_dev = s.graph_mode ? s.d_now : nullptr;
   a.col_net = s.col_net;
   a.col_local = s.col_local;
@@ -883,6 +968,7 @@ StepArgs make_step_args(const sim& s) {
   a.wfx = s.wfx;
   a.v = s.v;
   a.ca = s.ca;
+  a.na = s.na;
   a.ref = s.ref;
   a.hist_cnt = s.hist_cnt;
   a.hist_ids = s.hist_ids;
@@ -903,11 +989,15 @@ StepArgs make_step_args(const sim& s) {
 template <int BLOCK>
 hipError_t allow_large_lds() {
   const int bytes = (int)(kMaxLds - 16 * 1024);
-  hipError_t e = hipFuncSetAttribute((const void*)k_step_tile<BLOCK, true>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_step_tile<BLOCK, false>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  const void* const fns[] = {(const void*)k_step_tile<BLOCK, true, kModelLif>,
+                             (const void*)k_step_tile<BLOCK, false, kModelLif>,
+                             (const void*)k_step_tile<BLOCK, false, kModelLifNa>,
+                             (const void*)k_step_tile<BLOCK, false, kModelIzh>};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // Allow the tile kernels the dynamic LDS beyond 64 KB (gfx950: 160 KB per workgroup).
@@ -937,7 +1027,7 @@ hipError_t launch_init_state(const sim& s) {
   int64_t blocks = (nall + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_init_state, dim3((unsigned)blocks), dim3(256), 0, s.stream, a);
+  hipLaunchKernelGGL(k_init_state, dim3((unsigned)blocks), dim3(256), 0, s.stream, a, s.model);
   return hipGetLastError();
 }
 

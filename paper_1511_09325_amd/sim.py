@@ -38,11 +38,12 @@ def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, b
         nets[n].seed = int(p["seed"])
         nets[n].ext_rate_hz = float(p["ext_rate_hz"])
     c = L.SimConfig()
-    for name in ("npc", "n_exc", "d_min", "d_max", "t_ref", "ext_syn"):
+    for name in ("npc", "n_exc", "d_min", "d_max", "t_ref", "ext_syn", "neuron_model"):
         setattr(c, name, int(p0[name]))
     for name in ("p_own", "p_remote", "decay_um", "spacing_um", "we_mu", "we_sigma", "wi_mu",
                  "wi_sigma", "tau_m", "theta", "v_reset", "tau_ca", "ca_inc", "g_ahp", "dt",
-                 "j_ext"):
+                 "j_ext", "tau_na", "na_inc", "g_na", "izh_a_e", "izh_b_e", "izh_c_e",
+                 "izh_d_e", "izh_a_i", "izh_b_i", "izh_c_i", "izh_d_i", "izh_vpeak"):
         setattr(c, name, float(p0[name]))
     c.n_nets = len(plist)
     c.nets = C.cast(nets, C.POINTER(L.SimNet))
@@ -185,11 +186,13 @@ class Simulation:
         ca = np.zeros(n, np.float32)
         ref = np.zeros(n, np.uint8)
         pd = np.zeros((self.ring_slots, n), np.int32) if pend else None
+        na = np.zeros(n, np.float32)
         L.check(self.lib.sim_read_state(
             self.h, net, v.ctypes.data_as(C.POINTER(C.c_float)),
             ca.ctypes.data_as(C.POINTER(C.c_float)), ref.ctypes.data_as(C.POINTER(C.c_uint8)),
-            pd.ctypes.data_as(C.POINTER(C.c_int32)) if pend else None), self.h)
-        return {"v": v, "ca": ca, "ref": ref, "pend": pd, "now": self.now}
+            pd.ctypes.data_as(C.POINTER(C.c_int32)) if pend else None,
+            na.ctypes.data_as(C.POINTER(C.c_float))), self.h)
+        return {"v": v, "ca": ca, "ref": ref, "pend": pd, "na": na, "now": self.now}
 
     def synapses(self, net: int = 0, i0: int = 0, i1: int | None = None):
         """(row_ptr, tgt, dly, wq) of source rows [i0, i1) in canonical order."""

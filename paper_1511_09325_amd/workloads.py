@@ -50,6 +50,13 @@ PLAIN_96X96 = dict(params=grid(96, 96, 0), steps=2000, name="plain 96x96 (11,427
 #: tens of Hz of the literal parameters down to a few Hz.
 PLAIN_96X96_RATE_MATCHED = dict(params=grid(96, 96, 0, wi_mu=-1.2, wi_sigma=0.12), steps=2000,
                                 name="plain 96x96, inhibitory weights -N(1.2, 0.12) mV, 2 s")
+#: The neuron-model variants on the 24x24 grid: a second (sodium-dependent) AHP variable,
+#: and Izhikevich RS/FS neurons (external efficacy raised to 1.6 mV so that the network fires
+#: at about 10 Hz).  Neither variant is parameterised in the paper; these are workload choices.
+SODIUM_AHP_24X24 = dict(params=grid(24, 24, 0, g_na=0.1, tau_na=100.0, na_inc=0.02), steps=1000,
+                        name="24x24, LIF with calcium and sodium AHP variables, 1 s")
+IZHIKEVICH_24X24 = dict(params=grid(24, 24, 0, neuron_model=1, j_ext=1.6), steps=1000,
+                        name="24x24, Izhikevich RS/FS neurons, 1 s")
 FWD_BWD_4X4 = dict(params=grid(4, 4, 0), steps=500, ckpt_every=50,
                    name="forward+backward 4x4 (19,840 neurons), 500 ms")
 

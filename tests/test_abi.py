@@ -99,6 +99,7 @@ def test_struct_layout_matches_c():
     dict(npc=0), dict(npc=5000), dict(n_exc=2000), dict(d_min=0), dict(d_max=40),
     dict(d_min=5, d_max=4), dict(wi_mu=-1.9), dict(tau_m=0.0), dict(t_ref=300),
     dict(p_own=0.9, p_remote=0.4), dict(rows=0), dict(ext_rate_hz=50.0),
+    dict(neuron_model=2), dict(g_na=0.1, tau_na=0.0), dict(neuron_model=1, izh_vpeak=float("nan")),
 ])
 def test_invalid_configs_are_rejected_before_device_work(lib, bad):
     p = W.grid(2, 2)
@@ -111,6 +112,16 @@ def test_invalid_configs_are_rejected_before_device_work(lib, bad):
     assert lib.sim_last_error(None)
     sz = L.SimSizes()
     assert lib.sim_query_sizes(C.byref(cfg), C.byref(sz)) == L.EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(neuron_model=1), dict(g_na=0.1)])
+def test_train_mode_needs_the_one_variable_lif(lib, bad):
+    p = W.grid(2, 2)
+    p.update(bad)
+    cfg, nets = make_config(p, train_mode=True)
+    h = C.c_void_p(123)
+    assert lib.sim_create(C.byref(cfg), None, None, C.byref(h)) == L.EINVAL
+    assert b"train mode" in lib.sim_last_error(None)
 
 
 def test_null_handles(lib):
