@@ -54,9 +54,12 @@ class _Cfg(C.Structure):
         ("izh_d_e", C.c_double),
         ("izh_a_i", C.c_double), ("izh_b_i", C.c_double), ("izh_c_i", C.c_double),
         ("izh_d_i", C.c_double), ("izh_vpeak", C.c_double),
+        ("conn_kernel", C.c_int32), ("lateral_amp", C.c_double),
+        ("lateral_sigma_um", C.c_double), ("lateral_cutoff", C.c_double),
     ]
 
 NEURON_LIF, NEURON_IZHIKEVICH = 0, 1
+CONN_EXP3X3, CONN_GAUSS = 0, 1
 
 
 class _AdjParams(C.Structure):
@@ -81,6 +84,7 @@ def lib():
         cp = P(_Cfg)
         sig = {
             "orc_set_threads": (None, [C.c_int32]),
+            "orc_stencil_radius": (C.c_int32, [cp]),
             "orc_threads": (C.c_int32, []),
             "orc_philox": (None, [u32p, u32p, u32p]),
             "orc_column_probability": (C.c_double, [cp, C.c_int32, C.c_int32]),
@@ -181,9 +185,13 @@ def n_neurons(p: dict) -> int:
     return p["rows"] * p["cols"] * p["npc"]
 
 
+def stencil_radius(p: dict) -> int:
+    return int(lib().orc_stencil_radius(C.byref(make_config(p))))
+
+
 def row(p: dict, i: int):
     cfg = make_config(p)
-    cap = 9 * p["npc"] + 1
+    cap = 49 * p["npc"] + 1
     tgt = np.zeros(cap, np.int32)
     dly = np.zeros(cap, np.uint8)
     wq = np.zeros(cap, np.int16)

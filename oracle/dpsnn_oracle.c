@@ -70,13 +70,34 @@ static void draw(const orc_config_t* cfg, uint32_t a, uint32_t b, uint32_t c, ui
  * Network (paper section 2, Methods).  Columns sit on a rows x cols grid, periodic in
  * both directions.  Column c = y*cols + x, neuron j = c*npc + k, k < n_exc excitatory
  * (80 % / 20 % split).  A neuron projects to its own column with pair probability p_own
- * and to the 8 surrounding columns with a total share p_remote of the row, each
- * neighbour weighted by exp(-r/decay) with r its centre distance (1 or sqrt 2 spacings).
+ * and to the columns of a stencil around it with a probability that falls with the
+ * distance r between column centres:
+ *  - the 3x3 kernel: a total share p_remote of the row over the 8 surrounding columns,
+ *    each weighted by exp(-r/decay) (r = 1 or sqrt 2 spacings);
+ *  - the Gaussian kernel (the paper's lateral connectivity): lateral_amp exp(-r^2/2sigma^2)
+ *    for every offset whose exp(-r^2/2sigma^2) reaches the cut-off (1/1000 in the paper,
+ *    which leaves the 7x7 square minus its corners when sigma is the column spacing).
  * When the grid is so small that several stencil offsets land on the same column, the
- * offsets' probabilities are added, in stencil order (dy = -1, 0, 1 outer; dx inner).
+ * offsets' probabilities are added, in stencil order (dy outer, dx inner, both ascending).
  * ------------------------------------------------------------------------- */
+static double gauss_factor(const orc_config_t* cfg, int dy, int dx) {
+  double r2 = (double)(dy * dy + dx * dx) * cfg->spacing_um * cfg->spacing_um;
+  return exp(-r2 / (2.0 * cfg->lateral_sigma_um * cfg->lateral_sigma_um));
+}
+
+int32_t orc_stencil_radius(const orc_config_t* cfg) {
+  if (cfg->conn_kernel != ORC_CONN_GAUSS) return 1;
+  int32_t r = 0;
+  while (r < 3 && gauss_factor(cfg, 0, r + 1) >= cfg->lateral_cutoff) ++r;
+  return r;
+}
+
 static double offset_probability(const orc_config_t* cfg, int dy, int dx) {
   if (dy == 0 && dx == 0) return cfg->p_own;
+  if (cfg->conn_kernel == ORC_CONN_GAUSS) {
+    double g = gauss_factor(cfg, dy, dx);
+    return g >= cfg->lateral_cutoff ? cfg->lateral_amp * g : 0.0;
+  }
   double edge = exp(-(cfg->spacing_um / cfg->decay_um));
   double diag = exp(-(sqrt(2.0) * cfg->spacing_um / cfg->decay_um));
   double norm = 4.0 * edge + 4.0 * diag;
@@ -86,9 +107,10 @@ static double offset_probability(const orc_config_t* cfg, int dy, int dx) {
 
 double orc_column_probability(const orc_config_t* cfg, int32_t src_col, int32_t tgt_col) {
   int sy = src_col / cfg->cols, sx = src_col % cfg->cols;
+  int R = orc_stencil_radius(cfg);
   double p = 0.0;
-  for (int dy = -1; dy <= 1; ++dy) {
-    for (int dx = -1; dx <= 1; ++dx) {
+  for (int dy = -R; dy <= R; ++dy) {
+    for (int dx = -R; dx <= R; ++dx) {
       int ty = ((sy + dy) % cfg->rows + cfg->rows) % cfg->rows;
       int tx = ((sx + dx) % cfg->cols + cfg->cols) % cfg->cols;
       if (ty * cfg->cols + tx == tgt_col) p = p + offset_probability(cfg, dy, dx);
@@ -145,13 +167,33 @@ static int syn_order(const void* a, const void* b) {
   return 0;
 }
 
+/* The distinct columns of the stencil of column c (each once, in stencil order); returns
+ * how many. */
+static int stencil_columns(const orc_config_t* cfg, int32_t c, int32_t out[49]) {
+  int R = orc_stencil_radius(cfg);
+  int y = c / cfg->cols, x = c % cfg->cols, n = 0;
+  for (int dy = -R; dy <= R; ++dy) {
+    for (int dx = -R; dx <= R; ++dx) {
+      if (offset_probability(cfg, dy, dx) <= 0.0 && !(dy == 0 && dx == 0)) continue;
+      int ty = ((y + dy) % cfg->rows + cfg->rows) % cfg->rows;
+      int tx = ((x + dx) % cfg->cols + cfg->cols) % cfg->cols;
+      int32_t t = ty * cfg->cols + tx, dup = 0;
+      for (int q = 0; q < n; ++q) dup |= out[q] == t;
+      if (!dup) out[n++] = t;
+    }
+  }
+  return n;
+}
+
 int64_t orc_row(const orc_config_t* cfg, int64_t i, int32_t* tgt, uint8_t* dly, int16_t* wq,
                 int64_t cap) {
-  int32_t ncol = cfg->rows * cfg->cols;
   int32_t ci = (int32_t)(i / cfg->npc);
-  syn_t* tmp = (syn_t*)malloc(sizeof(syn_t) * (size_t)(9 * cfg->npc + 1));
+  int32_t cols[49];
+  int ncand = stencil_columns(cfg, ci, cols);
+  syn_t* tmp = (syn_t*)malloc(sizeof(syn_t) * (size_t)(ncand * cfg->npc + 1));
   int64_t n = 0;
-  for (int32_t c = 0; c < ncol; ++c) {
+  for (int q = 0; q < ncand; ++q) {
+    int32_t c = cols[q];
     double p = orc_column_probability(cfg, ci, c);
     if (p <= 0.0) continue;
     uint64_t thr = prob_threshold(p);
@@ -175,7 +217,7 @@ int64_t orc_network(const orc_config_t* cfg, int64_t* row_ptr, int32_t* tgt, uin
   const int64_t n = (int64_t)cfg->rows * cfg->cols * cfg->npc;
   const int64_t B = 256;                 /* rows per block */
   const int64_t nb = (n + B - 1) / B;
-  const int64_t row_cap = 9 * (int64_t)cfg->npc;
+  const int64_t row_cap = 49 * (int64_t)cfg->npc;
   int32_t** btgt = (int32_t**)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int32_t*));
   uint8_t** bdly = (uint8_t**)calloc((size_t)(nb > 0 ? nb : 1), sizeof(uint8_t*));
   int16_t** bwq = (int16_t**)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int16_t*));
@@ -528,8 +570,8 @@ void orc_update_many(const orc_config_t* cfg, int64_t u, int64_t j0, int64_t n,
 /* Recurrent input by its definition, without a ring: the sum of the efficacies 4 w_q of
  * every synapse i -> j of delay d whose source spiked at step e = t_arr - d, over the
  * emission steps e <= t_emit_max covered by the spike mask.  The candidate sources are
- * all neurons of the (unique) columns of the 3x3 torus neighbourhood of j's column; each
- * pair is decided again from the generator's definition. */
+ * all neurons of the (unique) columns of the stencil around j's column (the stencil is
+ * symmetric); each pair is decided again from the generator's definition. */
 void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets, int64_t t_arr,
                      int64_t t_emit_max, const uint8_t* mask, int64_t mask_t0, int64_t mask_steps,
                      int32_t* out) {
@@ -538,27 +580,18 @@ void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets
   for (int64_t t = 0; t < nt; ++t) {
     const int64_t j = targets[t];
     const int32_t cj = (int32_t)(j / cfg->npc);
-    const int32_t y = cj / cfg->cols, x = cj % cfg->cols;
-    int32_t cols_seen[9];
-    int nseen = 0;
+    int32_t cols[49];
+    const int nsrc = stencil_columns(cfg, cj, cols);
     uint32_t acc = 0;
-    for (int dy = -1; dy <= 1; ++dy) {
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int32_t sy = ((y + dy) % cfg->rows + cfg->rows) % cfg->rows;
-        const int32_t sx = ((x + dx) % cfg->cols + cfg->cols) % cfg->cols;
-        const int32_t c = sy * cfg->cols + sx;
-        int dup = 0;
-        for (int q = 0; q < nseen; ++q) dup |= cols_seen[q] == c;
-        if (dup) continue;
-        cols_seen[nseen++] = c;
-        for (int32_t k = 0; k < cfg->npc; ++k) {
-          const int64_t i = (int64_t)c * cfg->npc + k;
-          int32_t d; int16_t w;
-          if (!orc_pair(cfg, i, j, &d, &w)) continue;
-          const int64_t e = t_arr - d;
-          if (e > t_emit_max || e < mask_t0 || e >= mask_t0 + mask_steps) continue;
-          if (mask[(size_t)(e - mask_t0) * (size_t)n + (size_t)i]) acc += (uint32_t)(4 * (int32_t)w);
-        }
+    for (int q = 0; q < nsrc; ++q) {
+      const int32_t c = cols[q];
+      for (int32_t k = 0; k < cfg->npc; ++k) {
+        const int64_t i = (int64_t)c * cfg->npc + k;
+        int32_t d; int16_t w;
+        if (!orc_pair(cfg, i, j, &d, &w)) continue;
+        const int64_t e = t_arr - d;
+        if (e > t_emit_max || e < mask_t0 || e >= mask_t0 + mask_steps) continue;
+        if (mask[(size_t)(e - mask_t0) * (size_t)n + (size_t)i]) acc += (uint32_t)(4 * (int32_t)w);
       }
     }
     out[t] = (int32_t)acc;

@@ -72,9 +72,20 @@ typedef struct {
   double izh_a_e, izh_b_e, izh_c_e, izh_d_e;  /* Izhikevich, excitatory neurons (RS) */
   double izh_a_i, izh_b_i, izh_c_i, izh_d_i;  /* Izhikevich, inhibitory neurons (FS) */
   double izh_vpeak;     /* Izhikevich spike cut-off, mV */
+  /* connectivity kernel (paper section 2, Methods): ORC_CONN_EXP3X3 spreads p_remote over the
+   * 8 neighbours by exp(-r / decay_um); ORC_CONN_GAUSS gives every stencil offset at column
+   * distance r the pair probability lateral_amp exp(-r^2 / (2 lateral_sigma_um^2)), the
+   * stencil being the offsets whose exp(-r^2 / (2 sigma^2)) >= lateral_cutoff (the paper's
+   * 1/1000 cut-off: the 7x7 square minus its corners for sigma = the column spacing) */
+  int32_t conn_kernel;
+  double lateral_amp, lateral_sigma_um, lateral_cutoff;
 } orc_config_t;
 
 enum { ORC_NEURON_LIF = 0, ORC_NEURON_IZHIKEVICH = 1 };
+enum { ORC_CONN_EXP3X3 = 0, ORC_CONN_GAUSS = 1 };
+
+/* Half-width of the connectivity stencil in columns (1 for the 3x3 kernel). */
+int32_t orc_stencil_radius(const orc_config_t* cfg);
 
 /* Host threads of the loops over independent rows and neurons (OpenMP); results do not
  * depend on the thread count. */

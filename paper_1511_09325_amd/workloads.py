@@ -31,12 +31,38 @@ COLUMN_RECIPE = dict(
     neuron_model=0, tau_na=100.0, na_inc=0.02, g_na=0.0,
     izh_a_e=0.02, izh_b_e=0.2, izh_c_e=-65.0, izh_d_e=8.0,
     izh_a_i=0.1, izh_b_i=0.2, izh_c_i=-65.0, izh_d_i=2.0, izh_vpeak=30.0,
+    # connectivity kernel: 0 = the 3x3 exponential stencil above; 1 = the paper's Gaussian
+    # lateral kernel (see PAPER_RECIPE)
+    conn_kernel=0, lateral_amp=0.0, lateral_sigma_um=100.0, lateral_cutoff=1e-3,
+)
+
+#: The paper's own column recipe (section 2, Methods; Table 1): pair probability 0.8 inside a
+#: column (about 990 local synapses), lateral probability A exp(-r^2 / 2 alpha^2) with alpha
+#: the 100 um column spacing, cut at 1/1000 (the 7x7 stencil minus its corners), and 540
+#: external synapses per neuron.  The paper's A = 0.05 would give about 327 remote synapses
+#: and 1318 per neuron, against its own 1239-1245; A = 248 / (1240 * 5.2792912) =
+#: 0.03788387 gives the 248 remote synapses that complete 1240 with the 991 local ones.
+#: The paper gives no external rate: 3000 / 540 Hz keeps the mean external count per step
+#: at 3, as in the column recipe.  Inhibitory weights -N(1.2, 0.12) mV bring the rate to a
+#: few Hz (the literal -N(0.8, 0.08) fires at tens of Hz).
+PAPER_RECIPE = dict(
+    COLUMN_RECIPE,
+    p_own=0.8, p_remote=0.0, conn_kernel=1, lateral_amp=0.03788387, lateral_sigma_um=100.0,
+    lateral_cutoff=1e-3, ext_syn=540, ext_rate_hz=3000.0 / 540.0, wi_mu=-1.2, wi_sigma=0.12,
 )
 
 
 def grid(rows: int, cols: int, seed: int = 0, **overrides) -> dict:
     """Parameters of one rows x cols network of the column recipe."""
     p = dict(COLUMN_RECIPE)
+    p.update(rows=rows, cols=cols, seed=seed)
+    p.update(overrides)
+    return p
+
+
+def paper_grid(rows: int, cols: int, seed: int = 0, **overrides) -> dict:
+    """Parameters of one rows x cols network of the paper's own column recipe."""
+    p = dict(PAPER_RECIPE)
     p.update(rows=rows, cols=cols, seed=seed)
     p.update(overrides)
     return p
