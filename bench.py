@@ -42,6 +42,9 @@ WORKLOADS = {
     "96x96": ("PLAIN_96X96", 2000),
     "24x24": ("PLAIN_24X24", 10000),
     "2x2": ("PLAIN_2X2", 1000),
+    "paper96": ("PAPER_96X96", 1000),
+    "paper48": ("PAPER_48X48", 1000),
+    "paper24": ("PAPER_24X24", 1000),
 }
 
 
@@ -506,6 +509,7 @@ def main():
     ap.add_argument("--no-rate-matched", action="store_true")
     ap.add_argument("--no-small-grids", action="store_true")
     ap.add_argument("--no-models", action="store_true")
+    ap.add_argument("--no-paper-recipe", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB once (a reference kernel of known "
                          "traffic for hardware byte counters)")
@@ -565,6 +569,9 @@ def main():
     if not args.no_small_grids and args.workload == "96x96":
         log("small-grid legs: the whole 24x24 (10 s) and 2x2 (1 s) workloads")
         out["small_grids"] = {w: plain_leg(torch, w, None, args.warmup) for w in ("24x24", "2x2")}
+    if not args.no_paper_recipe and args.workload == "96x96":
+        log("paper-recipe leg: the paper's own column recipe on the 96x96 grid")
+        out["paper_recipe"] = plain_leg(torch, "paper96", 500, args.warmup)
     if not args.no_models and args.workload == "96x96":
         log("neuron-model legs: 24x24 with the sodium AHP and with Izhikevich neurons")
         out["models"] = models_leg(torch)

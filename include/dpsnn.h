@@ -49,6 +49,10 @@ extern "C" {
 #define DPSNN_NEURON_LIF 0
 #define DPSNN_NEURON_IZHIKEVICH 1
 
+/* Connectivity kernel (section 2, Methods). */
+#define DPSNN_CONN_EXP3X3 0 /* p_remote of the row over the 8 neighbours by exp(-r/decay_um) */
+#define DPSNN_CONN_GAUSS 1  /* lateral_amp exp(-r^2/2 sigma^2) per pair over the cut stencil */
+
 /* Spike delivery strategy. Both give bit-identical results. */
 #define DPSNN_DELIVERY_AUTO 0
 #define DPSNN_DELIVERY_ARRIVAL 1 /* per target column: gather arrivals, fused with the update */
@@ -107,6 +111,17 @@ typedef struct {
   double izh_a_e, izh_b_e, izh_c_e, izh_d_e;
   double izh_a_i, izh_b_i, izh_c_i, izh_d_i;
   double izh_vpeak;
+  /* connectivity kernel (section 2, Methods: probability falling with the distance r between
+   * column centres, cut at 1/1000).  DPSNN_CONN_EXP3X3 uses p_remote and decay_um over the
+   * 3x3 stencil.  DPSNN_CONN_GAUSS gives every stencil offset other than the own column the
+   * pair probability lateral_amp exp(-r^2 / (2 lateral_sigma_um^2)), the stencil being the
+   * offsets whose exp(...) >= lateral_cutoff, at most 7x7 (the paper: sigma = the column
+   * spacing, cut-off 1e-3, the 7x7 square minus its corners); p_remote and decay_um are
+   * unused.  Offsets that wrap onto one column add their probabilities.  The arrival form
+   * needs a native tiling whose parts hold at most 9 columns and whose source columns touch
+   * at most 16 tiles (3x3, 3x2 or 2x2 tiles for the 7x7 stencil). */
+  int32_t conn_kernel;   /* DPSNN_CONN_* */
+  double lateral_amp, lateral_sigma_um, lateral_cutoff;
 } sim_config_t;
 
 /* Sizes of a created simulation. */

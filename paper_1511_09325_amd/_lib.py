@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libdpsnn.so")
 OK, EINVAL, ENOMEM, EHIP, ESTATE, ETRUNC = 0, -1, -2, -3, -4, -5
 DELIVERY_AUTO, DELIVERY_ARRIVAL, DELIVERY_PUSH = 0, 1, 2
 NEURON_LIF, NEURON_IZHIKEVICH = 0, 1
+CONN_EXP3X3, CONN_GAUSS = 0, 1
 
 #: Every entry point declared in include/dpsnn.h.
 EXPORTS = [
@@ -54,6 +55,8 @@ class SimConfig(C.Structure):
         ("izh_d_e", C.c_double),
         ("izh_a_i", C.c_double), ("izh_b_i", C.c_double), ("izh_c_i", C.c_double),
         ("izh_d_i", C.c_double), ("izh_vpeak", C.c_double),
+        ("conn_kernel", C.c_int32), ("lateral_amp", C.c_double),
+        ("lateral_sigma_um", C.c_double), ("lateral_cutoff", C.c_double),
     ]
 
 

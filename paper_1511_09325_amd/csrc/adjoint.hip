@@ -60,9 +60,10 @@ __device__ __forceinline__ float4 efficacies_mv(int4 q) {
                      (float)q.w * 0x1p-16f);
 }
 
-// One wave per neuron.  The whole row (all parts, contiguous in the store) is streamed 64 x
-// kAdjUnroll records at a time with each record's delay index from the train-mode delay
-// array (one byte per 16-byte word), which selects the slot of the adjoint ring.
+// One wave per neuron.  Each part of the row is streamed 64 x kAdjUnroll records at a time
+// with each record's delay index from the train-mode delay array (one byte per 16-byte
+// word), which selects the slot of the adjoint ring; the part's column table turns each
+// record's rank into its target column.
 __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
   const StepArgs& a = x.a;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -70,11 +71,15 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
   const int64_t j = (int64_t)blockIdx.x * 4 + wv;
   if (j >= nall) return;
   const int32_t g = (int32_t)(j / a.npc);
+  const int32_t kk = (int32_t)(j - (int64_t)g * a.npc);
   const bool spiked = (a.rec_flags[(u - a.rec_base) * nall + j] & 1) != 0;
-  const int64_t rb = a.row_base[j];
-  const int32_t rlen = (int32_t)(a.row_base[j + 1] - rb);
   const int32_t ubase = (int32_t)((u + a.d_min) % a.dh);  // ring slot of delay index 0
   float acc = 0.0f;
+  for (int p = 0; p < a.col_np[g]; ++p) {
+  const uint8_t* ent = idx_entry(a, g, kk, p);
+  const int64_t rb = ent_start(ent);
+  const int32_t rlen = ent_goff(ent)[a.nd];
+  const int32_t* pcol = a.part_col + (int64_t)(a.col_pfirst[g] + p) * kMaxPartCols;
   for (int32_t f0 = 0; f0 < rlen; f0 += 64 * kAdjUnroll) {
     uint32_t w[kAdjUnroll];
     float wf[kAdjUnroll];
@@ -96,7 +101,7 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
     for (int i = 0; i < kAdjUnroll; ++i) {
       nu[i] = 0.0f;
       if (rec_rank(w[i]) != (uint32_t)kDummyRank) {
-        const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w[i])];
+        const int32_t tc = pcol[rec_rank(w[i])];
         int32_t slot = ubase + dd[i];
         if (slot >= a.dh) slot -= a.dh;
         nu[i] = x.nu_ring[slot * nall + (int64_t)tc * a.npc + rec_k(w[i])];
@@ -110,6 +115,7 @@ __global__ __launch_bounds__(256) void k_adj_row(AdjArgs x, int64_t u) {
       acc = acc + prod;
       if (spiked) x.gw[rb + f] = x.gw[rb + f] + nu[i];
     }
+  }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc = acc + __shfl_down(acc, off);
@@ -488,70 +494,72 @@ __global__ __launch_bounds__(1024) void k_reduce_parts(const double* part, int64
 // Canonical synapse order (per source neuron: the real records sorted by (delay, target))
 // <-> the padded device layout.  mode 0: dst_padded[p] = src_canon[c]; mode 1: the reverse;
 // mode 2: rel[p] = c - canon_start[row] (the permutation that k_canon_apply replays).
-// Padding records receive 0 in mode 0.  One wave per neuron: the counts of its synapses per
-// (delay, rank) give the canonical start of every (delay, rank) run; inside a device group
-// (part, delay) the runs of the part's ranks follow each other in rank order.
-__global__ __launch_bounds__(256) void k_canon_map(StepArgs a, const int64_t* canon_start,
-                                                   int mode, const float* src, float* dst,
-                                                   uint16_t* rel) {
-  __shared__ int32_t cnt[4][kMaxDelay * kMaxNbr];
-  __shared__ int64_t cst[4][kMaxDelay * kMaxNbr];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Padding records receive 0 in mode 0.  One wave per neuron (one per workgroup: the counts
+// of the 7x7 stencil fill the LDS): the counts of its synapses per (delay, stencil rank)
+// give the canonical start of every (delay, rank) run; inside a device group (part, delay)
+// the runs of the part's ranks follow each other in rank order (part ranks are ascending
+// stencil ranks, see part_srank).
+__global__ __launch_bounds__(64) void k_canon_map(StepArgs a, const int64_t* canon_start,
+                                                  int mode, const float* src, float* dst,
+                                                  uint16_t* rel) {
+  __shared__ int32_t cnt[kMaxDelay * kMaxNbr];
+  __shared__ int64_t cst[kMaxDelay * kMaxNbr];
+  const int lane = threadIdx.x & 63;
   const int64_t nall = (int64_t)a.n_cols * a.npc;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + wave; i < nall; i += (int64_t)gridDim.x * 4) {
+  for (int64_t i = blockIdx.x; i < nall; i += gridDim.x) {
     const int32_t g = (int32_t)(i / a.npc);
     const int32_t kk = (int32_t)(i - (int64_t)g * a.npc);
     const int np = a.col_np[g], nn = a.col_nn[g];
-    const int32_t* part = a.col_part + g * kMaxNbr;
-    for (int q = lane; q < kMaxDelay * kMaxNbr; q += 64) cnt[wave][q] = 0;
-    __builtin_amdgcn_wave_barrier();
+    for (int q = lane; q < kMaxDelay * kMaxNbr; q += 64) cnt[q] = 0;
+    __syncthreads();
     for (int p = 0; p < np; ++p) {
       const uint8_t* ent = idx_entry(a, g, kk, p);
       const int64_t st = ent_start(ent);
       const uint16_t* go = ent_goff(ent);
+      const int32_t* srank = a.part_srank + (int64_t)(a.col_pfirst[g] + p) * kMaxPartCols;
       for (int dd = 0; dd < a.nd; ++dd)
         for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
-          const uint32_t r = rec_rank(a.syn[st + f]);
-          if (r != (uint32_t)kDummyRank) atomicAdd(&cnt[wave][dd * kMaxNbr + (int)r], 1);
+          const uint32_t q = rec_rank(a.syn[st + f]);
+          if (q != (uint32_t)kDummyRank) atomicAdd(&cnt[dd * kMaxNbr + srank[q]], 1);
         }
     }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
     if (lane == 0) {
       int64_t c = canon_start[i];
       for (int dd = 0; dd < a.nd; ++dd)
         for (int r = 0; r < nn; ++r) {
-          cst[wave][dd * kMaxNbr + r] = c;
-          c += cnt[wave][dd * kMaxNbr + r];
+          cst[dd * kMaxNbr + r] = c;
+          c += cnt[dd * kMaxNbr + r];
         }
     }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
     for (int p = 0; p < np; ++p) {
       const uint8_t* ent = idx_entry(a, g, kk, p);
       const int64_t st = ent_start(ent);
       const uint16_t* go = ent_goff(ent);
+      const int32_t* srank = a.part_srank + (int64_t)(a.col_pfirst[g] + p) * kMaxPartCols;
       for (int dd = 0; dd < a.nd; ++dd)
         for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
-          const uint32_t r = rec_rank(a.syn[st + f]);
-          if (r == (uint32_t)kDummyRank) {
+          const uint32_t q = rec_rank(a.syn[st + f]);
+          if (q == (uint32_t)kDummyRank) {
             if (mode == 0) dst[st + f] = 0.0f;
             continue;
           }
           int32_t run0 = go[dd];
-          for (int r2 = 0; r2 < (int)r; ++r2)
-            if (part[r2] == p) run0 += cnt[wave][dd * kMaxNbr + r2];
-          const int64_t c = cst[wave][dd * kMaxNbr + (int)r] + (f - run0);
+          for (int q2 = 0; q2 < (int)q; ++q2) run0 += cnt[dd * kMaxNbr + srank[q2]];
+          const int64_t c = cst[dd * kMaxNbr + srank[q]] + (f - run0);
           if (mode == 0) dst[st + f] = src[c];
           else if (mode == 1) dst[c] = src[st + f];
           else rel[st + f] = (uint16_t)(c - canon_start[i]);
         }
     }
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
   }
 }
 
 // The same maps from the stored permutation: one wave per row, its padded records in order
-// (the parts of a row are contiguous); rel 0xffff marks padding.
-static_assert((int64_t)kMaxNbr * kMaxNpc < 0xffff, "a row's canonical offsets fit 16 bits");
+// (the parts of a row are contiguous); rel 0xffff marks padding (rows are shorter than
+// 0xffff synapses: checked when train mode is set up).
 __global__ __launch_bounds__(256) void k_canon_apply(const int64_t* row_base,
                                                      const int64_t* canon_start,
                                                      const uint16_t* rel, int64_t n_rows,
@@ -692,14 +700,14 @@ hipError_t launch_adjoint_window(const sim& s, int64_t top, int64_t lo, const fl
   const int32_t d_min = s.cfg.d_min, d_max = s.cfg.d_max;
   const AdjSplit p = adj_split(s.nd, d_min, d_max);
   const int nbw = (s.npc + 16 * kAdjOwnPerWave - 1) / (16 * kAdjOwnPerWave);
-  const int nbq = ((kMaxNbr - 1) * s.npc + 256 * kAdjNbrPerQuad - 1) / (256 * kAdjNbrPerQuad);
+  const int nbq = ((s.max_nn - 1) * s.npc + 256 * kAdjNbrPerQuad - 1) / (256 * kAdjNbrPerQuad);
   const dim3 gc((unsigned)(nbw + nbq), (unsigned)s.n_cols);
   // heavy pass: groups hsplit .. nd - 1 for the kw steps, staged index dd + d_min - 1 - sb - j
   hipLaunchKernelGGL(k_adj_col<1024>, gc, dim3(1024), sizeof(float) * (size_t)p.nst * s.npc,
                      s.stream, x, top, nbw, p.hsplit, s.nd, kw, p.nst, top + 1 + p.sb,
                      d_min - 1 - p.sb);
   // light passes: groups 0 .. hsplit - 1, a quad per part, 64 parts per workgroup
-  const dim3 gl((unsigned)((kMaxNbr * s.npc + 63) / 64), (unsigned)s.n_cols);
+  const dim3 gl((unsigned)((s.max_nn * s.npc + 63) / 64), (unsigned)s.n_cols);
   for (int32_t j = 0; j < kw; ++j) {
     const int64_t t = top - j;
     hipLaunchKernelGGL(k_adj_light, gl, dim3(256), 0, s.stream, x, t, p.hsplit, j);
@@ -728,14 +736,14 @@ hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst
     return hipGetLastError();
   }
   const StepArgs a = make_step_args(s);
-  hipLaunchKernelGGL(k_canon_map, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a,
+  hipLaunchKernelGGL(k_canon_map, dim3(grid_of(s.n_neurons, 1)), dim3(64), 0, s.stream, a,
                      s.canon_start, mode, src, dst, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_canon_perm(const sim& s, uint16_t* rel) {
   const StepArgs a = make_step_args(s);
-  hipLaunchKernelGGL(k_canon_map, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream, a,
+  hipLaunchKernelGGL(k_canon_map, dim3(grid_of(s.n_neurons, 1)), dim3(64), 0, s.stream, a,
                      s.canon_start, 2, nullptr, nullptr, rel);
   return hipGetLastError();
 }

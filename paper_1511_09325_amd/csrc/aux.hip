@@ -79,13 +79,14 @@ __global__ __launch_bounds__(256) void k_pend_arrival(StepArgs a, int64_t now, i
         const uint8_t* ent = idx_entry(a, g, ids[q], p);
         const int64_t st = ent_start(ent);
         const uint16_t* go = ent_goff(ent);
+        const int32_t* pcol = a.part_col + (int64_t)(a.col_pfirst[g] + p) * kMaxPartCols;
         for (int dd = 0; dd < a.nd; ++dd) {
           const int64_t due = t + a.d_min + dd;
           if (due < now) continue;
           for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
             const uint32_t w = a.syn[st + f];
             if (rec_rank(w) == (uint32_t)kDummyRank) continue;
-            const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+            const int32_t tc = pcol[rec_rank(w)];
             const int32_t val = TRAIN ? a.wfx[st + f] : rec_w32(w);
             atomicAdd(&pend[(due - now) * n_net + (int64_t)(tc - g0) * a.npc + rec_k(w)], val);
           }
@@ -110,6 +111,7 @@ __global__ __launch_bounds__(256) void k_export_rows(StepArgs a, int32_t g0, int
       const uint8_t* ent = idx_entry(a, g, k, p);
       const int64_t st = ent_start(ent);
       const uint16_t* go = ent_goff(ent);
+      const int32_t* pcol = a.part_col + (int64_t)(a.col_pfirst[g] + p) * kMaxPartCols;
       for (int dd = 0; dd < a.nd; ++dd) {
         for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
           const uint32_t w = a.syn[st + f];
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(256) void k_export_rows(StepArgs a, int32_t g0, int
             wq[o] = 0;
             continue;
           }
-          const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+          const int32_t tc = pcol[rec_rank(w)];
           tgt[o] = (tc - g0) * a.npc + (int32_t)rec_k(w);
           dly[o] = (uint8_t)(a.d_min + dd);
           wq[o] = (int16_t)(w >> 16);

@@ -91,11 +91,31 @@ T* upload(sim& s, const std::vector<T>& h) {
   return d;
 }
 
-// Probability of one stencil offset: the own column, or a neighbour weighted by
-// exp(-distance / decay) with the remote share spread over the 8 neighbours
-// (section 2, Methods: connectivity decreasing with the distance between columns).
+// Gaussian factor exp(-r^2 / 2 sigma^2) of a stencil offset, r the distance of column centres.
+double gauss_factor(const sim_config_t& c, int dy, int dx) {
+  const double r2 = (double)(dy * dy + dx * dx) * c.spacing_um * c.spacing_um;
+  return exp(-r2 / (2.0 * c.lateral_sigma_um * c.lateral_sigma_um));
+}
+
+// Half-width of the stencil: 1 for the 3x3 kernel; for the Gaussian kernel the largest
+// axis offset (at most 3) whose factor reaches the cut-off.
+int stencil_radius(const sim_config_t& c) {
+  if (c.conn_kernel != DPSNN_CONN_GAUSS) return 1;
+  int r = 0;
+  while (r < 3 && gauss_factor(c, 0, r + 1) >= c.lateral_cutoff) ++r;
+  return r;
+}
+
+// Probability of one stencil offset (section 2, Methods: connectivity decreasing with the
+// distance between columns): the own column; for the 3x3 kernel a neighbour weighted by
+// exp(-distance / decay) with the remote share spread over the 8 neighbours; for the
+// Gaussian kernel A exp(-r^2 / 2 sigma^2) where that factor reaches the cut-off, else 0.
 double offset_prob(const sim_config_t& c, int dy, int dx) {
   if (dy == 0 && dx == 0) return c.p_own;
+  if (c.conn_kernel == DPSNN_CONN_GAUSS) {
+    const double g = gauss_factor(c, dy, dx);
+    return g >= c.lateral_cutoff ? c.lateral_amp * g : 0.0;
+  }
   const double edge = exp(-(c.spacing_um / c.decay_um));
   const double diag = exp(-(sqrt(2.0) * c.spacing_um / c.decay_um));
   const double norm = 4.0 * edge + 4.0 * diag;
@@ -159,6 +179,13 @@ void validate(const sim_config_t* c) {
         std::isfinite(c->izh_c_e) && std::isfinite(c->izh_d_e) && std::isfinite(c->izh_a_i) &&
         std::isfinite(c->izh_b_i) && std::isfinite(c->izh_c_i) && std::isfinite(c->izh_d_i)))
     bad("Izhikevich parameters must be finite");
+  if (c->conn_kernel != DPSNN_CONN_EXP3X3 && c->conn_kernel != DPSNN_CONN_GAUSS)
+    bad("unknown conn_kernel");
+  if (c->conn_kernel == DPSNN_CONN_GAUSS &&
+      !(c->lateral_sigma_um > 0 && c->lateral_cutoff > 0 && c->lateral_cutoff <= 1 &&
+        c->lateral_amp >= 0 && c->lateral_amp <= 1))
+    bad("Gaussian kernel needs lateral_sigma_um > 0, 0 < lateral_cutoff <= 1 and "
+        "0 <= lateral_amp <= 1");
   if (c->train_mode && (c->neuron_model != DPSNN_NEURON_LIF || c->g_na != 0.0))
     bad("train mode needs the LIF neuron with g_na = 0 (the adjoint of the other models is not "
         "defined)");
@@ -249,6 +276,15 @@ static void tile_of(const sim& s, int n, int tx, int ty, int cl, int* txi, int* 
   *tyi = (cl / cols) / tty;
 }
 
+bool compute_parts(const sim& s, int tx, int ty, std::vector<int32_t>& part,
+                   std::vector<int32_t>& np, std::vector<int32_t>& prank);
+
+// Can a tx x ty tiling be the native one: parts within their limits for this stencil?
+bool parts_fit(const sim& s, int tx, int ty) {
+  std::vector<int32_t> part, np, prank;
+  return compute_parts(s, tx, ty, part, np, prank);
+}
+
 // Does a tx x ty tiling fit the LDS of the tile kernel?
 bool tile_fits(sim& s, int tx, int ty) {
   if (tx < 1 || ty < 1 || tx > kMaxTileSide || ty > kMaxTileSide) return false;
@@ -262,15 +298,19 @@ bool tile_fits(sim& s, int tx, int ty) {
   return ok;
 }
 
-// Parts of every source column under the native tx x ty tiling: the ranks whose target
-// columns lie in one tile form one part, parts numbered by first appearance in rank order.
-void build_parts(sim& s, int tx, int ty) {
-  std::vector<int32_t> part((size_t)s.n_cols * kMaxNbr, -1), np(s.n_cols, 0);
-  std::vector<int64_t> pbase((size_t)s.n_cols + 1, 0);
+// Parts of every source column under a tx x ty tiling: the stencil ranks whose target
+// columns lie in one tile form one part, parts numbered by first appearance in rank order;
+// prank is the rank of each column inside its part.  Returns false when a part would hold
+// more than kMaxPartCols columns or a column more than kMaxParts parts.
+bool compute_parts(const sim& s, int tx, int ty, std::vector<int32_t>& part,
+                   std::vector<int32_t>& np, std::vector<int32_t>& prank) {
+  part.assign((size_t)s.n_cols * kMaxNbr, -1);
+  prank.assign((size_t)s.n_cols * kMaxNbr, -1);
+  np.assign((size_t)s.n_cols, 0);
   for (int n = 0; n < s.n_nets; ++n) {
     for (int cl = 0; cl < s.nets[n].rows * s.nets[n].cols; ++cl) {
       const int32_t g = s.net_col0[n] + cl;
-      std::vector<int> seen;
+      std::vector<int> seen, size;
       for (int r = 0; r < s.h_nn[g]; ++r) {
         const int32_t t = s.h_nbr[(size_t)g * kMaxNbr + r] - s.net_col0[n];
         int xi, yi;
@@ -282,27 +322,54 @@ void build_parts(sim& s, int tx, int ty) {
         if (p < 0) {
           p = (int)seen.size();
           seen.push_back(key);
+          size.push_back(0);
         }
         part[(size_t)g * kMaxNbr + r] = p;
+        prank[(size_t)g * kMaxNbr + r] = size[p]++;
+        if (size[p] > kMaxPartCols) return false;
       }
+      if ((int)seen.size() > kMaxParts) return false;
       np[g] = (int32_t)seen.size();
     }
   }
+  return true;
+}
+
+void build_parts(sim& s, int tx, int ty) {
+  std::vector<int32_t> part, np, prank;
+  if (!compute_parts(s, tx, ty, part, np, prank))
+    throw Fail{DPSNN_EINVAL, "the tiling gives a part of more than 9 columns or a column of "
+                             "more than 16 parts for this stencil"};
+  std::vector<int64_t> pbase((size_t)s.n_cols + 1, 0);
   std::vector<int32_t> pfirst((size_t)s.n_cols + 1, 0);
   for (int32_t g = 0; g < s.n_cols; ++g) {
     pbase[g + 1] = pbase[g] + (int64_t)s.npc * np[g];
     pfirst[g + 1] = pfirst[g] + np[g];
   }
   s.n_parts = pfirst[s.n_cols];
+  // the columns of every part by rank, and their stencil ranks
+  std::vector<int32_t> pcol((size_t)std::max(s.n_parts, 1) * kMaxPartCols, -1),
+      psrank((size_t)std::max(s.n_parts, 1) * kMaxPartCols, -1);
+  for (int32_t g = 0; g < s.n_cols; ++g)
+    for (int r = 0; r < s.h_nn[g]; ++r) {
+      const size_t e = (size_t)(pfirst[g] + part[(size_t)g * kMaxNbr + r]) * kMaxPartCols +
+                       prank[(size_t)g * kMaxNbr + r];
+      pcol[e] = s.h_nbr[(size_t)g * kMaxNbr + r];
+      psrank[e] = r;
+    }
   s.col_pfirst = upload(s, pfirst);
   s.h_part = part;
   s.h_np = np;
+  s.h_prank = prank;
   s.n_idx = pbase[s.n_cols];
   s.native_tx = tx;
   s.native_ty = ty;
   s.col_part = upload(s, part);
+  s.col_prank = upload(s, prank);
   s.col_np = upload(s, np);
   s.col_pbase = upload(s, pbase);
+  s.part_col = upload(s, pcol);
+  s.part_srank = upload(s, psrank);
 }
 
 // Tiles of tx x ty target columns (clamped to each network's grid; edge tiles are smaller).
@@ -342,20 +409,24 @@ void build_tiles(sim& s, int tx, int ty) {
           std::vector<uint64_t> packs;
           for (int32_t sc : src) {
             for (int p = 0; p < s.h_np[sc]; ++p) {
-              uint64_t packed = 0;
+              // 5-bit field q: the tile slot of the part's column of rank q; every field
+              // starts at 31 ("not in the tile"), ranks >= 9 (dummies) keep it
+              uint64_t packed = ~(uint64_t)0;
               bool any = false;
-              for (int r = 0; r < kMaxNbr; ++r) {
-                uint64_t slot = kNoSlot;
-                if (r < s.h_nn[sc] && s.h_part[(size_t)sc * kMaxNbr + r] == p) {
-                  const int32_t t = s.h_nbr[(size_t)sc * kMaxNbr + r];
-                  for (size_t z = 0; z < tc.size(); ++z)
-                    if (tc[z] == t) { slot = z; any = true; }
-                }
-                packed |= slot << (5 * r);
+              for (int r = 0; r < s.h_nn[sc]; ++r) {
+                if (s.h_part[(size_t)sc * kMaxNbr + r] != p) continue;
+                const int32_t t = s.h_nbr[(size_t)sc * kMaxNbr + r];
+                const int q = s.h_prank[(size_t)sc * kMaxNbr + r];
+                for (size_t z = 0; z < tc.size(); ++z)
+                  if (tc[z] == t) {
+                    packed &= ~((uint64_t)31 << (5 * q));
+                    packed |= (uint64_t)z << (5 * q);
+                    any = true;
+                  }
               }
               if (any) {
                 pairs.push_back({sc, p});
-                packs.push_back(packed | ~(((uint64_t)1 << (5 * kMaxNbr)) - 1));  // ranks >= 9: 31
+                packs.push_back(packed);
               }
             }
           }
@@ -437,6 +508,9 @@ int64_t tile_count(const sim& s, int tx, int ty) {
 void choose_native(sim& s, int tx, int ty) {
   if (tx || ty) {
     if (!tile_fits(s, tx, ty)) throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4] and fit the LDS"};
+    if (!parts_fit(s, tx, ty))
+      throw Fail{DPSNN_EINVAL, "this tiling gives parts of more than 9 columns or columns of "
+                               "more than 16 parts for the stencil"};
     s.native_tx = tx;
     s.native_ty = ty;
     return;
@@ -445,11 +519,12 @@ void choose_native(sim& s, int tx, int ty) {
   static const int shapes[][2] = {{3, 3}, {3, 2}, {2, 2}, {2, 1}, {1, 1}};
   int last = -1;
   for (int q = 0; q < 5; ++q) {
-    if (!tile_fits(s, shapes[q][0], shapes[q][1])) continue;
+    if (!tile_fits(s, shapes[q][0], shapes[q][1]) || !parts_fit(s, shapes[q][0], shapes[q][1]))
+      continue;
     last = q;
     if (tile_count(s, shapes[q][0], shapes[q][1]) >= 2 * (int64_t)n_cu) break;
   }
-  if (last < 0) throw Fail{DPSNN_EINVAL, "no tile shape fits the LDS"};
+  if (last < 0) throw Fail{DPSNN_EINVAL, "no tile shape fits the LDS and the stencil"};
   s.native_tx = shapes[last][0];
   s.native_ty = shapes[last][1];
 }
@@ -501,14 +576,17 @@ void build_tables(sim& s) {
       col_net[g] = n;
       col_local[g] = cl;
       const int y = cl / cols, x = cl % cols;
-      // distinct target columns, probabilities summed in stencil order
+      // distinct target columns, probabilities summed in stencil order (dy outer, dx
+      // inner); the Gaussian kernel's offsets beyond the cut-off are not in the stencil
       std::vector<std::pair<int, double>> tg;
-      for (int dy = -1; dy <= 1; ++dy) {
-        for (int dx = -1; dx <= 1; ++dx) {
+      const int R = stencil_radius(c);
+      for (int dy = -R; dy <= R; ++dy) {
+        for (int dx = -R; dx <= R; ++dx) {
           const int ty = ((y + dy) % rows + rows) % rows;
           const int tx = ((x + dx) % cols + cols) % cols;
           const int tcl = ty * cols + tx;
           const double p = offset_prob(c, dy, dx);
+          if (c.conn_kernel == DPSNN_CONN_GAUSS && p <= 0.0 && !(dy == 0 && dx == 0)) continue;
           auto it = std::find_if(tg.begin(), tg.end(), [&](const std::pair<int, double>& e) {
             return e.first == tcl;
           });
@@ -518,6 +596,7 @@ void build_tables(sim& s) {
       }
       std::sort(tg.begin(), tg.end());
       nn[g] = (int32_t)tg.size();
+      s.max_nn = std::max(s.max_nn, nn[g]);
       for (size_t r = 0; r < tg.size(); ++r) {
         nbr[(size_t)g * kMaxNbr + r] = s.net_col0[n] + tg[r].first;
         thr[(size_t)g * kMaxNbr + r] = threshold_of(tg[r].second);
@@ -672,6 +751,9 @@ void save_into_ckpt(sim& s, size_t m);
 // Train mode: float32 master weights (initially the int16 weights), their int32 efficacies,
 // the adjoint buffers, trajectory recording for one checkpoint segment, checkpoint 0.
 void setup_train(sim& s) {
+  // the stored canonical permutation keeps each record's offset in its row in 16 bits
+  if ((int64_t)s.max_nn * s.npc >= 0xffff)
+    throw Fail{DPSNN_EINVAL, "train mode needs rows of fewer than 65535 candidate synapses"};
   const size_t sp = (size_t)s.n_syn_padded + 4;
   const size_t N = (size_t)s.n_neurons;
   s.wf32 = (float*)dalloc(s, sizeof(float) * sp);

@@ -6,35 +6,40 @@
 //   synapse store: the canonical order of a row is (delay, target); the device keeps each
 //   row split into parts, one per target tile of the tiling chosen at creation (the
 //   "native" tiling): part p of a source column holds the synapses whose target column
-//   lies in the p-th distinct tile touched by the column's 3x3 neighbourhood.  A part is a
-//   sequence of groups, one per delay; inside a group the targets come in canonical order.
-//   A synapse's target column is identified by its rank r in the source column's sorted
-//   list of distinct neighbour columns (at most 9: the 3x3 torus stencil)
+//   lies in the p-th distinct tile touched by the column's stencil (3x3, or up to 7x7 with
+//   the Gaussian kernel).  A part is a sequence of groups, one per delay; inside a group
+//   the targets come in canonical order.  A synapse's target column is identified by its
+//   rank r inside its part: the part's columns, ascending, are part_col[part][0..8] (at
+//   most 9 columns per part)
 //     idx       idxw bytes per (neuron, part): int64 start of the part, then uint16
 //               goff[nd + 1], then the uint16 count of the part's synapses (without the
 //               padding); group dd (delay d_min + dd) is [start + goff[dd], start +
 //               goff[dd + 1]).  Entry of (column g, neuron k, part p): col_pbase[g] +
 //               k * col_np[g] + p.  The parts of one neuron are contiguous (row_base[i])
 //     syn       uint32[S' + 4]: k (bits 0-11, target index inside its column) | r (bits
-//               12-15) | w_q (bits 16-31, int16 weight at 2^-14 mV).  Every group is padded
+//               12-15, rank in the part) | w_q (bits 16-31, int16 weight at 2^-14 mV).  Every
+//               group is padded
 //               to a multiple of 4 records with dummies (r = 9, weight 0), so parts and
 //               groups start on 16-byte boundaries and are read in whole 16-byte words
 //     deg       int32 [N]    out-degree (records without the padding)
 //     wfx       int32 [S']   train mode only: rint(w_f32 * 2^16) efficacies
-//   column tables
-//     col_nbr   int32 [C][9]   distinct neighbour columns, ascending, -1 padded
-//     col_thr   uint64[C][9]   pair connection threshold from g to col_nbr[g][r]
-//     col_part  int32 [C][9]   part of rank r (-1 padded); col_np int32 [C] parts per
+//   column tables (kMaxNbr = 49 entries per column: the 7x7 stencil)
+//     col_nbr   int32 [C][49]  distinct stencil columns, ascending, -1 padded
+//     col_thr   uint64[C][49]  pair connection threshold from g to col_nbr[g][r]
+//     col_part  int32 [C][49]  part of stencil rank r (-1 padded); col_prank the rank of
+//                              col_nbr[g][r] inside its part; col_np int32 [C] parts per
 //                              column; col_pbase int64 [C+1] first idx entry of the column
+//     part_col  int32 [P][9]   the columns of every part by rank (part_srank: their stencil
+//                              ranks)
 //   tiles (the unit of work of the arrival kernel): up to 4x4 target columns of one network
 //     tile_cinfo  int32x4 [tiles][16] per column of the tile: column (-1 padded), index
 //                                     within its network, parts, first part index
-//     tile_pinfo  int32x2 [tiles][64] every (source column, global part index) with a
+//     tile_pinfo  int32x2 [tiles][128] every (source column, global part index) with a
 //                                     synapse into the tile, -1 padded (one part per source
 //                                     in the native tiling; a part may reach several tiles
 //                                     otherwise)
 //     tile_net    int32 [tiles]       the tile's network
-//     tile_slots  uint64[tiles][64]   for each pair and each rank r of its part, the tile
+//     tile_slots  uint64[tiles][128]  for each pair and each rank r of its part, the tile
 //                                     slot of its target column in bits 5r..5r+4 (31: not
 //                                     in the tile or not in the part); bits 45-63 are set
 //   spike history (shared by both delivery strategies)
@@ -63,19 +68,20 @@
 
 namespace dpsnn {
 
-constexpr int kMaxNbr = 9;          // 3x3 stencil
+constexpr int kMaxNbr = 49;         // distinct columns of a stencil (7x7 at most)
+constexpr int kMaxNbr3x3 = 9;       // of the 3x3 stencil
+constexpr int kMaxPartCols = 9;     // columns of one part (the 4-bit rank field: 0..8)
 constexpr int kMaxNpc = 4096;       // 12-bit target index
 constexpr int kMaxDelay = 32;
 constexpr int kPoissonEntries = 63;
 constexpr int kMaxTileSide = 4;
 constexpr int kMaxTileCols = kMaxTileSide * kMaxTileSide;
-constexpr int kMaxTileSrc = (kMaxTileSide + 2) * (kMaxTileSide + 2);
-constexpr int kMaxTilePairs = 64;   // (source column, part) pairs of one tile
-constexpr int kMaxParts = kMaxNbr;  // parts of one source column (9 with 1x1 tiles)
+constexpr int kMaxTilePairs = 128;  // (source column, part) pairs of one tile
+constexpr int kMaxParts = 16;       // parts of one source column
 constexpr int kNoSlot = 31;
-// dummy records carry rank 9, one past the last neighbour rank: the slot words' fields from
-// the tenth up read 31, so a dummy decodes as "not in the tile" without clamping its rank
-constexpr int kDummyRank = kMaxNbr;
+// dummy records carry rank 9, one past the last part rank: the slot words' fields from the
+// tenth up read 31, so a dummy decodes as "not in the tile" without clamping its rank
+constexpr int kDummyRank = kMaxPartCols;
 constexpr uint32_t kDummyRecord = (uint32_t)kDummyRank << 12;  // k 0, rank 9, weight 0
 constexpr int kCounters = 8;        // per-network counters (see StepArgs::net_cnt)
 constexpr int kAdjWindow = 3;       // reverse steps per window of the column-wise adjoint gather
@@ -156,6 +162,8 @@ struct StepArgs {
   const int32_t* col_part;    // [C][9]: part of each neighbour rank
   const int64_t* col_pbase;   // first row-index entry of each column
   const int32_t* col_pfirst;  // first part index of each column
+  const int32_t* part_col;    // [P][kMaxPartCols]: column of each rank of each part
+  const int32_t* part_srank;  // [P][kMaxPartCols]: its stencil rank in the source column
   int32_t n_parts;
   const int32_t* col_order;   // [grid_cols]: column of workgroup b of per-column kernels
   int32_t grid_cols;
@@ -276,11 +284,13 @@ struct sim {
   float* loss_rates = nullptr;     // train mode: column rates and dL/dR of the built-in loss
   float* loss_grad = nullptr;
   int32_t *col_net = nullptr, *col_local = nullptr, *col_nbr = nullptr, *col_nn = nullptr;
-  int32_t *col_part = nullptr, *col_np = nullptr;
+  int32_t *col_part = nullptr, *col_np = nullptr, *col_prank = nullptr;
   int64_t* col_pbase = nullptr;
   int32_t* col_pfirst = nullptr;
+  int32_t *part_col = nullptr, *part_srank = nullptr;
   int32_t n_parts = 0;
-  std::vector<int32_t> h_part, h_np;  // host copies of the part tables
+  int32_t max_nn = 0;                 // most distinct stencil columns of any column
+  std::vector<int32_t> h_part, h_np, h_prank;  // host copies of the part tables
   int64_t n_idx = 0;                  // row-index entries (neuron, part)
   int32_t native_tx = 0, native_ty = 0;  // tiling of the synapse parts
   int32_t* col_order = nullptr;

@@ -4,7 +4,7 @@
 // 80 % excitatory, each neuron connected to neurons of its own column with a fixed pair
 // probability and to the neighbouring columns with a probability decaying with distance;
 // plus the workload's integer delays and normal weights.  Every pair (i, j) of a source
-// neuron i and a candidate target j in the 3x3 torus neighbourhood of i's column is one
+// neuron i and a candidate target j in the torus stencil around i's column is one
 // Bernoulli trial decided by Philox4x32-10 at counter (j, i, 0, SYN) of the network's key:
 //   connected iff word x < threshold(column pair)       (threshold = floor(p 2^32))
 //   delay      d = d_min + floor(word y * nd / 2^32)
@@ -12,8 +12,9 @@
 //              words at counter (j, i, 1, SYN) - 393210) / 65536, in double, no FMA,
 //              quantised to int16 at 2^-14 mV with round-half-even.
 // Each row is split into parts, one per tile of the native tiling that the source
-// column's neighbourhood touches (the part of each neighbour rank is in col_part); a part
-// holds one group per delay, each record carrying the rank of its target column, targets
+// column's stencil touches (the part of each stencil rank is in col_part); a part holds
+// one group per delay, each record carrying the rank of its target column inside the part
+// (col_prank), targets
 // in canonical order inside a group, and each group padded with dummy records to a
 // multiple of 4 so that 16-byte words never straddle two groups.  Two passes over the
 // candidates: the first counts each row's padded length and out-degree (then an exclusive
@@ -32,6 +33,7 @@ struct GenArgs {
   const int32_t* col_nbr;
   const int32_t* col_nn;
   const int32_t* col_part;
+  const int32_t* col_prank;
   const int32_t* col_np;
   const int64_t* col_pbase;
   const uint64_t* col_thr;
@@ -45,12 +47,12 @@ struct GenArgs {
   int32_t idxw;
 };
 
-constexpr int kGenWaves = 4;  // rows per workgroup (one wave each)
-
-// per-wave LDS of the construction kernels
+// per-wave LDS of the construction kernels, for stencils of at most NBR distinct columns
+// (rows per workgroup: WAVES, one wave each; fewer for the 7x7 stencil's larger tables)
+template <int NBR>
 struct RowLayout {
-  int32_t cnt[kMaxDelay][kMaxNbr];        // synapses of (delay, rank)
-  int32_t seg[kMaxDelay][kMaxNbr];        // fill: first record of (delay, rank) in the row
+  int32_t cnt[kMaxDelay][NBR];            // synapses of (delay, stencil rank)
+  int32_t seg[kMaxDelay][NBR];            // fill: first record of (delay, rank) in the row
   int32_t gst[kMaxParts][kMaxDelay + 1];  // fill: start of group (part, delay); [nd] = end
   int32_t pad[kMaxParts][kMaxDelay];      // fill: first padding record of group (part, delay)
 };
@@ -70,11 +72,12 @@ __device__ __forceinline__ bool decide(const GenArgs& a, int64_t i, int64_t jglo
 }
 
 // Synapse counts of row i per (delay, rank) into L.cnt (one wave).
+template <int NBR>
 __device__ void count_row(const GenArgs& a, int64_t i, int32_t g, uint32_t il, uint32_t k0,
-                          uint32_t k1, RowLayout& L) {
+                          uint32_t k1, RowLayout<NBR>& L) {
   const int lane = threadIdx.x & 63;
   const int nn = a.col_nn[g];
-  for (int q = lane; q < kMaxDelay * kMaxNbr; q += 64) (&L.cnt[0][0])[q] = 0;
+  for (int q = lane; q < kMaxDelay * NBR; q += 64) (&L.cnt[0][0])[q] = 0;
   __builtin_amdgcn_wave_barrier();
   for (int r = 0; r < nn; ++r) {
     const int32_t tc = a.col_nbr[g * kMaxNbr + r];
@@ -99,13 +102,14 @@ __device__ void count_row(const GenArgs& a, int64_t i, int32_t g, uint32_t il, u
 
 __device__ __forceinline__ int32_t padded(int32_t n) { return (n + 3) & ~3; }
 
-__global__ __launch_bounds__(64 * kGenWaves) void k_gen_count(GenArgs a) {
-  __shared__ RowLayout lay[kGenWaves];
+template <int NBR, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gen_count(GenArgs a) {
+  __shared__ RowLayout<NBR> lay[WAVES];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  RowLayout& L = lay[wave];
-  for (int64_t rr = (int64_t)blockIdx.x * kGenWaves + wave; rr < a.rows;
-       rr += (int64_t)gridDim.x * kGenWaves) {
+  RowLayout<NBR>& L = lay[wave];
+  for (int64_t rr = (int64_t)blockIdx.x * WAVES + wave; rr < a.rows;
+       rr += (int64_t)gridDim.x * WAVES) {
     const int64_t i = a.row0 + rr;
     const int32_t g = (int32_t)(i / a.npc);
     const int32_t kk = (int32_t)(i - (int64_t)g * a.npc);
@@ -136,14 +140,15 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_count(GenArgs a) {
   }
 }
 
-__global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
-  __shared__ RowLayout lay[kGenWaves];
+template <int NBR, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gen_fill(GenArgs a) {
+  __shared__ RowLayout<NBR> lay[WAVES];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const unsigned long long lt = lanemask_lt(lane);
-  RowLayout& L = lay[wave];
-  for (int64_t rr = (int64_t)blockIdx.x * kGenWaves + wave; rr < a.rows;
-       rr += (int64_t)gridDim.x * kGenWaves) {
+  RowLayout<NBR>& L = lay[wave];
+  for (int64_t rr = (int64_t)blockIdx.x * WAVES + wave; rr < a.rows;
+       rr += (int64_t)gridDim.x * WAVES) {
     const int64_t i = a.row0 + rr;
     const int32_t g = (int32_t)(i / a.npc);
     const int32_t kk = (int32_t)(i - (int64_t)g * a.npc);
@@ -209,6 +214,7 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
       const int32_t tc = a.col_nbr[g * kMaxNbr + r];
       const uint64_t thr = a.col_thr[g * kMaxNbr + r];
       const uint32_t tl0 = (uint32_t)(a.col_local[tc] * a.npc);
+      const uint32_t prank = (uint32_t)a.col_prank[g * kMaxNbr + r];
       // lane q holds the write cursor of segment (q, r)
       int32_t cursor = lane < a.nd ? L.seg[lane][r] : 0;
       for (int kb = 0; kb < a.npc; kb += 64) {
@@ -234,7 +240,7 @@ __global__ __launch_bounds__(64 * kGenWaves) void k_gen_fill(GenArgs a) {
           const double prod = sigma * z;
           const double w = mu + prod;
           const int16_t wq = (int16_t)__builtin_rint(w * 16384.0);
-          out[pos] = (uint32_t)k | ((uint32_t)r << 12) | ((uint32_t)(uint16_t)wq << 16);
+          out[pos] = (uint32_t)k | (prank << 12) | ((uint32_t)(uint16_t)wq << 16);
         }
       }
     }
@@ -255,6 +261,7 @@ GenArgs gen_args(const sim& s, int64_t row0, int64_t rows) {
   a.col_nbr = s.col_nbr;
   a.col_nn = s.col_nn;
   a.col_part = s.col_part;
+  a.col_prank = s.col_prank;
   a.col_np = s.col_np;
   a.col_pbase = s.col_pbase;
   a.col_thr = s.col_thr;
@@ -271,10 +278,15 @@ GenArgs gen_args(const sim& s, int64_t row0, int64_t rows) {
   return a;
 }
 
-int gen_grid(int64_t rows) {
-  const int64_t wgs = (rows + kGenWaves - 1) / kGenWaves;
+int gen_grid(int64_t rows, int waves) {
+  const int64_t wgs = (rows + waves - 1) / waves;
   return (int)(wgs < 65536 ? wgs : 65536);
 }
+
+// The 3x3 stencil's tables are small enough for four rows per workgroup; the 7x7 stencil's
+// for two.
+constexpr int kGenWaves3x3 = 4;
+constexpr int kGenWavesWide = 2;
 
 // ---- exclusive scan int32 -> int64 (three passes) ------------------------------------
 constexpr int kScanThreads = 256;
@@ -353,13 +365,23 @@ int64_t scan_scratch_len(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1
 hipError_t launch_gen_count(const sim& s, int64_t row0, int64_t rows, int32_t* row_len) {
   GenArgs a = gen_args(s, row0, rows);
   a.row_len = row_len;
-  hipLaunchKernelGGL(k_gen_count, dim3(gen_grid(rows)), dim3(64 * kGenWaves), 0, s.stream, a);
+  if (s.max_nn <= kMaxNbr3x3)
+    hipLaunchKernelGGL((k_gen_count<kMaxNbr3x3, kGenWaves3x3>), dim3(gen_grid(rows, kGenWaves3x3)),
+                       dim3(64 * kGenWaves3x3), 0, s.stream, a);
+  else
+    hipLaunchKernelGGL((k_gen_count<kMaxNbr, kGenWavesWide>), dim3(gen_grid(rows, kGenWavesWide)),
+                       dim3(64 * kGenWavesWide), 0, s.stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_gen_fill(const sim& s, int64_t row0, int64_t rows) {
   GenArgs a = gen_args(s, row0, rows);
-  hipLaunchKernelGGL(k_gen_fill, dim3(gen_grid(rows)), dim3(64 * kGenWaves), 0, s.stream, a);
+  if (s.max_nn <= kMaxNbr3x3)
+    hipLaunchKernelGGL((k_gen_fill<kMaxNbr3x3, kGenWaves3x3>), dim3(gen_grid(rows, kGenWaves3x3)),
+                       dim3(64 * kGenWaves3x3), 0, s.stream, a);
+  else
+    hipLaunchKernelGGL((k_gen_fill<kMaxNbr, kGenWavesWide>), dim3(gen_grid(rows, kGenWavesWide)),
+                       dim3(64 * kGenWavesWide), 0, s.stream, a);
   return hipGetLastError();
 }
 

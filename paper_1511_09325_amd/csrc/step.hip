@@ -797,13 +797,14 @@ __global__ __launch_bounds__(BLOCK) void k_deliver_push(StepArgs a, int64_t u_ar
         const uint8_t* ent = idx_entry(a, g, k, p);
         const int64_t st = ent_start(ent);
         const uint16_t* go = ent_goff(ent);
+        const int32_t* pcol = a.part_col + (int64_t)(a.col_pfirst[g] + p) * kMaxPartCols;
         for (int dd = 0; dd < a.nd; ++dd) {
           int64_t slot = uslot + a.d_min + dd;
           if (slot >= a.dh) slot -= a.dh;
           for (int32_t f = go[dd] + lane; f < go[dd + 1]; f += 64) {
             const uint32_t w = a.syn[st + f];
             if (rec_rank(w) == (uint32_t)kDummyRank) continue;
-            const int32_t tc = a.col_nbr[g * kMaxNbr + rec_rank(w)];
+            const int32_t tc = pcol[rec_rank(w)];
             atomicAdd(&a.ring[slot * nall + (int64_t)tc * a.npc + rec_k(w)],
                       TRAIN ? a.wfx[st + f] : rec_w32(w));
           }
@@ -917,7 +918,14 @@ static size_t tile_static_bytes() {
          (sizeof(int32_t) * 2 + 1 + 5 * sizeof(uint64_t)) * 16 + 64;
 }
 
-bool tile_lds_ok(const sim& s) { return tile_fixed_lds(s, s.gk) + tile_static_bytes() <= kMaxLds; }
+// The static LDS of the tile kernels as the compiler laid it out (the largest of their
+// instantiations), read at set-up; the estimate above until then.
+static size_t g_tile_static_lds = 0;
+
+bool tile_lds_ok(const sim& s) {
+  const size_t fixed = g_tile_static_lds ? g_tile_static_lds : tile_static_bytes() + 1024;
+  return tile_fixed_lds(s, s.gk) + fixed <= kMaxLds;
+}
 
 size_t tile_lds_bytes(const sim& s, int32_t kacc) { return tile_fixed_lds(s, kacc); }
 
@@ -953,6 +961,8 @@ StepArgs make_step_args(const sim& s) {
   a.col_part = s.col_part;
   a.col_pbase = s.col_pbase;
   a.col_pfirst = s.col_pfirst;
+  a.part_col = s.part_col;
+  a.part_srank = s.part_srank;
   a.n_parts = s.n_parts;
   a.hist_st = s.hist_st;
   a.hist_go = s.hist_go;
@@ -986,15 +996,22 @@ StepArgs make_step_args(const sim& s) {
   return a;
 }
 
+// Allow each tile kernel the dynamic LDS that its static LDS leaves of the 160 KB of a
+// workgroup, and record the largest static size.
 template <int BLOCK>
 hipError_t allow_large_lds() {
-  const int bytes = (int)(kMaxLds - 16 * 1024);
   const void* const fns[] = {(const void*)k_step_tile<BLOCK, true, kModelLif>,
                              (const void*)k_step_tile<BLOCK, false, kModelLif>,
                              (const void*)k_step_tile<BLOCK, false, kModelLifNa>,
                              (const void*)k_step_tile<BLOCK, false, kModelIzh>};
   for (const void* f : fns) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, f);
+    if (e != hipSuccess) return e;
+    if (attr.sharedSizeBytes >= kMaxLds) return hipErrorInvalidValue;
+    g_tile_static_lds = std::max(g_tile_static_lds, (size_t)attr.sharedSizeBytes);
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(kMaxLds - attr.sharedSizeBytes));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

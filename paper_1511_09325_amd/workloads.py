@@ -83,6 +83,14 @@ SODIUM_AHP_24X24 = dict(params=grid(24, 24, 0, g_na=0.1, tau_na=100.0, na_inc=0.
                         name="24x24, LIF with calcium and sodium AHP variables, 1 s")
 IZHIKEVICH_24X24 = dict(params=grid(24, 24, 0, neuron_model=1, j_ext=1.6), steps=1000,
                         name="24x24, Izhikevich RS/FS neurons, 1 s")
+#: The paper's own column recipe at its Table 1 sizes (about 1239 recurrent synapses per
+#: neuron, 991 of them local; 540 external synapses).
+PAPER_24X24 = dict(params=paper_grid(24, 24, 0), steps=1000,
+                   name="paper recipe 24x24 (714,240 neurons, Gaussian 7x7 stencil), 1 s")
+PAPER_48X48 = dict(params=paper_grid(48, 48, 0), steps=1000,
+                   name="paper recipe 48x48 (2,856,960 neurons, Gaussian 7x7 stencil), 1 s")
+PAPER_96X96 = dict(params=paper_grid(96, 96, 0), steps=1000,
+                   name="paper recipe 96x96 (11,427,840 neurons, Gaussian 7x7 stencil), 1 s")
 FWD_BWD_4X4 = dict(params=grid(4, 4, 0), steps=500, ckpt_every=50,
                    name="forward+backward 4x4 (19,840 neurons), 500 ms")
 
