@@ -56,6 +56,8 @@ class _Cfg(C.Structure):
         ("izh_d_i", C.c_double), ("izh_vpeak", C.c_double),
         ("conn_kernel", C.c_int32), ("lateral_amp", C.c_double),
         ("lateral_sigma_um", C.c_double), ("lateral_cutoff", C.c_double),
+        ("stdp", C.c_int32), ("stdp_tau_plus", C.c_double), ("stdp_tau_minus", C.c_double),
+        ("stdp_a_plus", C.c_double), ("stdp_a_minus", C.c_double), ("stdp_w_max", C.c_double),
     ]
 
 NEURON_LIF, NEURON_IZHIKEVICH = 0, 1
@@ -96,6 +98,7 @@ def lib():
             "orc_initial_v": (C.c_float, [cp, C.c_int64]),
             "orc_initial_state": (None, [cp, C.c_int64, f32p, f32p]),
             "orc_sim_get_na": (None, [C.c_void_p, f32p]),
+            "orc_sim_get_weights": (None, [C.c_void_p, i16p]),
             "orc_sim_set_na": (None, [C.c_void_p, f32p]),
             "orc_ext_counts": (None, [cp, C.c_int64, C.c_int64, C.c_int64, i32p]),
             "orc_neuron_update": (C.c_int, [cp, C.c_int64, C.c_int64, C.c_int32, f32p, f32p, u8p,
@@ -372,6 +375,12 @@ class Sim:
         if na is not None:
             na = np.ascontiguousarray(na, np.float32)
             lib().orc_sim_set_na(self._h, _ptr(na, C.c_float))
+
+    def weights(self):
+        """Current weights (int16, 2^-14 mV) in CSR order (plasticity changes them)."""
+        wq = np.zeros(max(len(self.tgt), 1), np.int16)
+        lib().orc_sim_get_weights(self._h, _ptr(wq, C.c_int16))
+        return wq[:len(self.tgt)]
 
     def inject(self, q: int, j: int, value: int):
         lib().orc_sim_inject(self._h, q, j, value)

@@ -356,6 +356,15 @@ struct orc_sim {
   uint32_t* ring;       /* [D][n]; slot u % D holds the input of step u */
   int64_t now;
   uint8_t* spiked;      /* [n] spike flags of the step being computed */
+  /* plasticity (cfg.stdp): current weights, traces and the synapses into each neuron */
+  int16_t* q;           /* [S] weights, 2^-14 mV */
+  float* xr;            /* [D][n] presynaptic trace of steps u - D + 1 .. u, slot u % D */
+  float* y;             /* [n] postsynaptic trace after the last step */
+  float* ym;            /* [n] postsynaptic trace decayed to the current step */
+  int32_t* in_now;      /* [n] input of the current step */
+  int64_t* in_ptr;      /* [n+1] incoming synapses of each neuron ... */
+  int64_t* in_syn;      /* ... their CSR indices */
+  int32_t* src_of;      /* [S] source neuron of each synapse */
   /* raster: spike ids of all steps, with per-step offsets */
   int32_t* sp_ids; int64_t sp_n, sp_cap;
   int64_t* sp_off; int64_t off_cap;
@@ -381,6 +390,29 @@ orc_sim_t* orc_sim_create(const orc_config_t* cfg, int64_t n, const int64_t* row
   s->ring = (uint32_t*)calloc((size_t)s->D * (size_t)n, sizeof(uint32_t));
   s->spiked = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
   for (int64_t j = 0; j < n; ++j) orc_initial_state(cfg, j, &s->v[j], &s->ca[j]);
+  if (cfg->stdp) {
+    int64_t S = row_ptr[n];
+    s->q = (int16_t*)malloc(sizeof(int16_t) * (size_t)(S > 0 ? S : 1));
+    for (int64_t e = 0; e < S; ++e) s->q[e] = (int16_t)(w32[e] / 4);
+    s->xr = (float*)calloc((size_t)s->D * (size_t)n, sizeof(float));
+    s->y = (float*)calloc((size_t)n, sizeof(float));
+    s->ym = (float*)calloc((size_t)n, sizeof(float));
+    s->in_now = (int32_t*)calloc((size_t)n, sizeof(int32_t));
+    /* the synapses into each neuron: a counting sort of the CSR by target */
+    s->in_ptr = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    s->in_syn = (int64_t*)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
+    s->src_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)(S > 0 ? S : 1));
+    for (int64_t e = 0; e < S; ++e) s->in_ptr[tgt[e] + 1] += 1;
+    for (int64_t j = 0; j < n; ++j) s->in_ptr[j + 1] += s->in_ptr[j];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t j = 0; j < n; ++j) fill[j] = s->in_ptr[j];
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+        s->src_of[e] = (int32_t)i;
+        s->in_syn[fill[tgt[e]]++] = e;
+      }
+    free(fill);
+  }
   s->off_cap = 1024;
   s->sp_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)s->off_cap);
   s->sp_off[0] = 0;
@@ -392,6 +424,8 @@ orc_sim_t* orc_sim_create(const orc_config_t* cfg, int64_t n, const int64_t* row
 void orc_sim_destroy(orc_sim_t* s) {
   if (!s) return;
   free(s->v); free(s->ca); free(s->na); free(s->ref); free(s->ring); free(s->spiked);
+  free(s->q); free(s->xr); free(s->y); free(s->ym); free(s->in_now); free(s->in_ptr);
+  free(s->in_syn); free(s->src_of);
   free(s->sp_ids); free(s->sp_off);
   free(s->r_vprev); free(s->r_caprev); free(s->r_vt); free(s->r_s); free(s->r_r);
   free(s->r_in);
@@ -609,9 +643,33 @@ void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets
  *     ring[(u + d) % D][j].
  * Neurons (1) and spikes (3) are independent of each other, so both loops may run on
  * several threads; the additions into the ring are atomic and the spike list is collected
- * in ascending order afterwards. */
+ * in ascending order afterwards.
+ *
+ * With plasticity on (spike-timing-dependent plasticity; paper sections 1-2 name it, the
+ * rule is not given there): the all-to-all pair rule with exponential windows, in weight
+ * units of 2^-14 mV, on the synapses of excitatory sources (weights >= 0; inhibitory
+ * weights are negative and stay fixed), bounded to [0, w_max].  Spikes arrive at u = t + d
+ * carrying the weight they find then, so the input is gathered at arrival from the spikes of
+ * the last d_max steps instead of being pushed into the ring at emission.  Step u:
+ *  1. y-(j) = P- y(j), the postsynaptic trace decayed to u (spikes before u);
+ *     every synapse i -> j whose source spiked at u - d adds 4 w to j's input, then is
+ *     depressed: w <- max(0, w - rint(A- y-(j) 2^14));
+ *  2. the neurons are updated as above;
+ *  3. y(j) = y-(j) + s_j(u); x_u(i) = P+ x_{u-1}(i) + s_i(u), the presynaptic trace;
+ *  4. every synapse i -> j (delay d) into a neuron j that spiked at u is potentiated:
+ *     w <- min(w_max, w + rint(A+ x_{u-d}(i) 2^14)), x_{u-d}(i) counting the source's spikes
+ *     up to u - d, i.e. its arrivals up to u.
+ * So every (arrival, postsynaptic spike) pair changes w once: by A+ exp(-(t_post - t_arr) /
+ * tau+) if the spike is not earlier than the arrival, by -A- exp(-(t_arr - t_post) /
+ * tau-) if it is (before rounding and bounds); P+- = exp(-dt / tau+-), float32. */
+static void stdp_step(orc_sim_t* s, const consts_t* k);
+
 int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
   consts_t k = constants_of(&s->cfg);
+  if (s->cfg.stdp) {
+    for (int64_t it = 0; it < n_steps; ++it) stdp_step(s, &k);
+    return 0;
+  }
   for (int64_t it = 0; it < n_steps; ++it) {
     int64_t u = s->now;
     int64_t slot = u % s->D;
@@ -675,6 +733,105 @@ int orc_sim_step(orc_sim_t* s, int64_t n_steps) {
   return 0;
 }
 
+static void next_step_offsets(orc_sim_t* s) {
+  s->now += 1;
+  if (s->now >= s->off_cap) {
+    s->off_cap *= 2;
+    s->sp_off = (int64_t*)realloc(s->sp_off, sizeof(int64_t) * (size_t)s->off_cap);
+  }
+  s->sp_off[s->now] = s->sp_n;
+}
+
+static void stdp_step(orc_sim_t* s, const consts_t* k) {
+  const orc_config_t* c = &s->cfg;
+  const int64_t u = s->now, n = s->n;
+  const float pplus = (float)exp(-c->dt / c->stdp_tau_plus);
+  const float pminus = (float)exp(-c->dt / c->stdp_tau_minus);
+  const float aplus = (float)c->stdp_a_plus, aminus = (float)c->stdp_a_minus;
+  const int32_t qmax = (int32_t)rint(c->stdp_w_max * 16384.0);
+  /* input held in the ring (set by orc_sim_set_state or orc_sim_inject) comes first */
+  uint32_t* ring = s->ring + (u % s->D) * n;
+  for (int64_t j = 0; j < n; ++j) {
+    s->ym[j] = pminus * s->y[j];
+    s->in_now[j] = (int32_t)ring[j];
+    ring[j] = 0;
+  }
+  /* 1. arrivals of the spikes of steps u - d, delivered with the current weight, then
+   *    depression of the excitatory ones */
+  for (int32_t d = c->d_min; d <= c->d_max; ++d) {
+    const int64_t t = u - d;
+    if (t < 0) continue;
+    for (int64_t q = s->sp_off[t]; q < s->sp_off[t + 1]; ++q) {
+      const int64_t i = s->sp_ids[q];
+      for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
+        if (s->dly[e] != d) continue;
+        const int32_t j = s->tgt[e];
+        s->in_now[j] = (int32_t)((uint32_t)s->in_now[j] + 4u * (uint32_t)(int32_t)s->q[e]);
+        if (s->q[e] >= 0) {
+          const float t1 = aminus * s->ym[j];
+          const int32_t dq = (int32_t)rintf(t1 * 16384.0f);
+          const int32_t w = s->q[e] - dq;
+          s->q[e] = (int16_t)(w < 0 ? 0 : w);
+        }
+      }
+    }
+  }
+  /* 2. the neurons */
+  if (s->rec_on) grow_record(s);
+  for (int64_t j = 0; j < n; ++j) {
+    const int32_t next = orc_poisson_count(s->ptab, ext_uniform(c, j, u));
+    const float vprev = s->v[j], caprev = s->ca[j];
+    float vt;
+    int refr;
+    uint32_t a;
+    const int spike = neuron_update(k, is_excitatory(c, j), (uint32_t)s->in_now[j], next,
+                                    &s->v[j], &s->ca[j], &s->na[j], &s->ref[j], &vt, &refr, &a);
+    s->consumed += (int64_t)(int32_t)a;
+    s->e_ext += next;
+    s->spiked[j] = (uint8_t)spike;
+    if (spike) push_spike(s, (int32_t)j);
+    if (s->rec_on) {
+      size_t o = (size_t)s->rec_n * (size_t)n + (size_t)j;
+      s->r_vprev[o] = vprev; s->r_caprev[o] = caprev; s->r_vt[o] = vt;
+      s->r_s[o] = (uint8_t)spike; s->r_r[o] = (uint8_t)refr; s->r_in[o] = (int32_t)a;
+    }
+  }
+  if (s->rec_on) s->rec_n += 1;
+  /* 3. traces */
+  float* xu = s->xr + (u % s->D) * n;
+  const float* xp = s->xr + ((u + s->D - 1) % s->D) * n;
+  for (int64_t j = 0; j < n; ++j) {
+    const float decayed = pplus * xp[j];
+    xu[j] = decayed + (s->spiked[j] ? 1.0f : 0.0f);
+    s->y[j] = s->ym[j] + (s->spiked[j] ? 1.0f : 0.0f);
+  }
+  /* 4. potentiation of the excitatory synapses into the neurons that spiked */
+  for (int64_t j = 0; j < n; ++j) {
+    if (!s->spiked[j]) continue;
+    for (int64_t q = s->in_ptr[j]; q < s->in_ptr[j + 1]; ++q) {
+      const int64_t e = s->in_syn[q];
+      const int64_t t = u - s->dly[e];
+      if (s->q[e] < 0 || t < 0) continue;
+      const float x = s->xr[(t % s->D) * n + s->src_of[e]];
+      const float t1 = aplus * x;
+      const int32_t dq = (int32_t)rintf(t1 * 16384.0f);
+      const int32_t w = s->q[e] + dq;
+      s->q[e] = (int16_t)(w > qmax ? qmax : w);
+    }
+  }
+  /* recurrent events at emission, as without plasticity */
+  for (int64_t q = s->sp_off[u]; q < s->sp_n; ++q) {
+    const int64_t i = s->sp_ids[q];
+    s->e_rec += s->row_ptr[i + 1] - s->row_ptr[i];
+  }
+  next_step_offsets(s);
+}
+
+void orc_sim_get_weights(const orc_sim_t* s, int16_t* wq) {
+  const int64_t S = s->row_ptr[s->n];
+  for (int64_t e = 0; e < S; ++e) wq[e] = s->q ? s->q[e] : (int16_t)(s->w32[e] / 4);
+}
+
 int64_t orc_sim_now(const orc_sim_t* s) { return s->now; }
 int32_t orc_sim_ring_slots(const orc_sim_t* s) { return s->D; }
 
@@ -696,6 +853,27 @@ void orc_sim_get_state(const orc_sim_t* s, float* v, float* ca, uint8_t* ref, in
   memcpy(v, s->v, sizeof(float) * (size_t)s->n);
   memcpy(ca, s->ca, sizeof(float) * (size_t)s->n);
   memcpy(ref, s->ref, (size_t)s->n);
+  if (s->cfg.stdp) {
+    /* the input held in the ring plus what the spikes already emitted will bring at step
+     * now + q, with today's weights */
+    for (int32_t q = 0; q < s->D; ++q) {
+      int64_t slot = (s->now + q) % s->D;
+      for (int64_t j = 0; j < s->n; ++j) pend[q * s->n + j] = (int32_t)s->ring[slot * s->n + j];
+    }
+    for (int64_t t = s->now - s->cfg.d_max; t < s->now; ++t) {
+      if (t < 0) continue;
+      for (int64_t q = s->sp_off[t]; q < s->sp_off[t + 1]; ++q) {
+        const int64_t i = s->sp_ids[q];
+        for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
+          const int64_t due = t + s->dly[e];
+          if (due < s->now) continue;
+          int32_t* p = &pend[(due - s->now) * s->n + s->tgt[e]];
+          *p = (int32_t)((uint32_t)*p + 4u * (uint32_t)(int32_t)s->q[e]);
+        }
+      }
+    }
+    return;
+  }
   for (int32_t q = 0; q < s->D; ++q) {
     int64_t slot = (s->now + q) % s->D;
     for (int64_t j = 0; j < s->n; ++j) pend[q * s->n + j] = (int32_t)s->ring[slot * s->n + j];

@@ -79,6 +79,13 @@ typedef struct {
    * 1/1000 cut-off: the 7x7 square minus its corners for sigma = the column spacing) */
   int32_t conn_kernel;
   double lateral_amp, lateral_sigma_um, lateral_cutoff;
+  /* spike-timing-dependent plasticity (paper sections 1-2 name it; off in its runs): an
+   * all-to-all pair rule with exponential traces on the synapses of excitatory sources
+   * (see orc_sim_step) */
+  int32_t stdp;         /* 0: off */
+  double stdp_tau_plus, stdp_tau_minus;  /* trace time constants, ms */
+  double stdp_a_plus, stdp_a_minus;      /* weight change per unit trace, mV */
+  double stdp_w_max;                     /* upper weight bound, mV */
 } orc_config_t;
 
 enum { ORC_NEURON_LIF = 0, ORC_NEURON_IZHIKEVICH = 1 };
@@ -162,7 +169,10 @@ void orc_sim_counts(const orc_sim_t* s, int64_t* spikes, int64_t* e_rec, int64_t
 int64_t orc_sim_consumed(const orc_sim_t* s);
 
 /* State: V, Ca, ref (n each) and the pending input ring pend[D][n], where pend[q][j] is the
- * input already delivered to neuron j for step now+q. */
+ * input already delivered to neuron j for step now+q.  With plasticity on, pend[q][j] is what
+ * the spikes already emitted will bring with the weights they have now (plus any input set
+ * or injected); orc_sim_set_state forgets the spikes before `now` and keeps the weights and
+ * traces. */
 void orc_sim_get_state(const orc_sim_t* s, float* v, float* ca, uint8_t* ref, int32_t* pend);
 void orc_sim_set_state(orc_sim_t* s, int64_t now, const float* v, const float* ca,
                        const uint8_t* ref, const int32_t* pend);
@@ -171,6 +181,10 @@ void orc_sim_get_na(const orc_sim_t* s, float* na);
 void orc_sim_set_na(orc_sim_t* s, const float* na);
 /* Test hook: add value (2^-16 mV) to the input of neuron j at step now+q. */
 void orc_sim_inject(orc_sim_t* s, int32_t q, int64_t j, int32_t value);
+
+/* Synaptic weights (2^-14 mV) of every synapse in CSR order: the generated ones, changed by
+ * plasticity when it is on. */
+void orc_sim_get_weights(const orc_sim_t* s, int16_t* wq);
 
 /* Trajectory recording: when enabled, every later step stores, per neuron, V before the
  * step, Ca before the step, the pre-threshold potential (0 when refractory), the spike

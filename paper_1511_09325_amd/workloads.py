@@ -34,6 +34,11 @@ COLUMN_RECIPE = dict(
     # connectivity kernel: 0 = the 3x3 exponential stencil above; 1 = the paper's Gaussian
     # lateral kernel (see PAPER_RECIPE)
     conn_kernel=0, lateral_amp=0.0, lateral_sigma_um=100.0, lateral_cutoff=1e-3,
+    # spike-timing-dependent plasticity, off in the paper's measurements (section 2): when on,
+    # the all-to-all pair rule with 20 ms exponential windows, A+ 0.005 mV, A- 0.00525 mV
+    # (slightly depression-dominated), excitatory weights bounded to [0, 0.4] mV
+    stdp=0, stdp_tau_plus=20.0, stdp_tau_minus=20.0, stdp_a_plus=0.005, stdp_a_minus=0.00525,
+    stdp_w_max=0.4,
 )
 
 #: The paper's own column recipe (section 2, Methods; Table 1): pair probability 0.8 inside a
