@@ -122,6 +122,22 @@ typedef struct {
    * at most 16 tiles (3x3, 3x2 or 2x2 tiles for the 7x7 stencil). */
   int32_t conn_kernel;   /* DPSNN_CONN_* */
   double lateral_amp, lateral_sigma_um, lateral_cutoff;
+  /* spike-timing-dependent plasticity (sections 1-2 name it; off in the paper's runs, which
+   * print no rule): with stdp = 1, the all-to-all pair rule with exponential traces on every
+   * synapse of weight >= 0 (the excitatory ones).  Each pair of a spike's arrival at its
+   * target (emission + delay) and a spike of the target changes the weight once: by
+   * +a_plus exp(-(t_post - t_arr) / tau_plus) when the target's spike is not earlier than
+   * the arrival, else by -a_minus exp(-(t_arr - t_post) / tau_minus); each change is
+   * rounded to the 2^-14 mV weight unit where it is applied (depressions at arrival, after
+   * the arriving spike has delivered its weight; potentiations after the update of the
+   * step of the target's spike), and the weight is kept in [0, stdp_w_max].  A spike
+   * delivers the weight it finds at arrival.  Needs the arrival form in the tiling of
+   * creation, one step per gather, train_mode = 0, fewer than 2^24 neurons and 2^35
+   * synapse records.  Snapshots then also hold the weights and traces. */
+  int32_t stdp;          /* 0: off */
+  double stdp_tau_plus, stdp_tau_minus; /* ms, > 0 */
+  double stdp_a_plus, stdp_a_minus;     /* mV, >= 0 */
+  double stdp_w_max;                    /* mV, 0 < w_max < 2 */
 } sim_config_t;
 
 /* Sizes of a created simulation. */
@@ -304,13 +320,15 @@ int sim_read_state(sim_t* sim, int32_t net, float* v, float* ca, uint8_t* ref, i
 /* Paper section 2 (Methods: the synapses, their delays and weights), synapses of network
  * `net`, source neurons [i0, i1), in canonical order: row_ptr (host,
  * i1-i0+1, relative to the first), tgt (int32 network-local), dly (uint8), wq (int16, 2^-14
- * mV).  Returns DPSNN_ETRUNC with row_ptr filled if cap is short.  Synchronises. */
+ * mV; with plasticity on, the weights as they are now).  Returns DPSNN_ETRUNC with row_ptr
+ * filled if cap is short.  Synchronises. */
 int sim_read_synapses(sim_t* sim, int32_t net, int64_t i0, int64_t i1, int64_t* row_ptr,
                       int32_t* tgt, uint8_t* dly, int16_t* wq, int64_t cap);
 
 /* Library runtime (checkpoint/resume; not in the paper): snapshot slots, save or restore the
  * whole dynamic state (V, Ca, refractory counters,
- * pending input, step counter, event counters, per-column spike counts).  slot in [0, 64).
+ * pending input, step counter, event counters, per-column spike counts; with plasticity on
+ * also the weights and the traces).  slot in [0, 64).
  * Asynchronous.  In train mode, restoring a state saved in another recorded window (before
  * the last sim_rewind, weight or parameter change) makes sim_backward fail until the next
  * sim_rewind; slot 63 is used by sim_autotune. */
@@ -350,7 +368,9 @@ typedef struct {
 /* Library runtime: the launch configuration in use (gather_steps: the window in effect). */
 int sim_get_launch(const sim_t* sim, sim_launch_t* launch);
 /* Library runtime: change it between steps (synchronises); results are bit-identical for
- * every choice. */
+ * every choice.  With plasticity on, only the workgroup size and graph_steps may change
+ * (the delivery, the tiling and gather_steps 0 or 1 stay as they are); other requests are
+ * DPSNN_EINVAL. */
 int sim_set_launch(sim_t* sim, const sim_launch_t* launch);
 
 /* Library runtime (determinism checks; not in the paper): order-independent 64-bit digest

@@ -99,6 +99,7 @@ def lib():
             "orc_initial_state": (None, [cp, C.c_int64, f32p, f32p]),
             "orc_sim_get_na": (None, [C.c_void_p, f32p]),
             "orc_sim_get_weights": (None, [C.c_void_p, i16p]),
+            "orc_stdp_synapse": (C.c_int16, [cp, C.c_int64, u8p, u8p, C.c_int32, C.c_int16]),
             "orc_sim_set_na": (None, [C.c_void_p, f32p]),
             "orc_ext_counts": (None, [cp, C.c_int64, C.c_int64, C.c_int64, i32p]),
             "orc_neuron_update": (C.c_int, [cp, C.c_int64, C.c_int64, C.c_int32, f32p, f32p, u8p,
@@ -251,6 +252,16 @@ def neuron_update(p: dict, j: int, u: int, rec_input: int, v: float, ca: float, 
                                 C.byref(rr), C.byref(nn))
     return (bool(s), np.float32(vv.value), np.float32(cc.value), int(rr.value),
             np.float32(nn.value))
+
+
+def stdp_synapse(p: dict, pre, post, d: int, q0: int) -> int:
+    """The plasticity rule on one synapse (delay d, weight q0 at step 0) from its source's and
+    its target's spike flags over steps 0 .. T-1: its weight after step T-1."""
+    pre = np.ascontiguousarray(pre, np.uint8)
+    post = np.ascontiguousarray(post, np.uint8)
+    assert pre.shape == post.shape
+    return int(lib().orc_stdp_synapse(C.byref(make_config(p)), len(pre), _ptr(pre, C.c_uint8),
+                                      _ptr(post, C.c_uint8), int(d), int(q0)))
 
 
 def update_many(p: dict, u: int, rec_input, v, ca, ref, j0: int = 0, na=None):

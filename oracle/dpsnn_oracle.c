@@ -658,7 +658,8 @@ void orc_input_brute(const orc_config_t* cfg, int64_t nt, const int64_t* targets
  *  3. y(j) = y-(j) + s_j(u); x_u(i) = P+ x_{u-1}(i) + s_i(u), the presynaptic trace;
  *  4. every synapse i -> j (delay d) into a neuron j that spiked at u is potentiated:
  *     w <- min(w_max, w + rint(A+ x_{u-d}(i) 2^14)), x_{u-d}(i) counting the source's spikes
- *     up to u - d, i.e. its arrivals up to u.
+ *     up to u - d, i.e. its arrivals up to u; a change that rounds to 0 is none (the bound
+ *     acts on changes only).
  * So every (arrival, postsynaptic spike) pair changes w once: by A+ exp(-(t_post - t_arr) /
  * tau+) if the spike is not earlier than the arrival, by -A- exp(-(t_arr - t_post) /
  * tau-) if it is (before rounding and bounds); P+- = exp(-dt / tau+-), float32. */
@@ -815,6 +816,7 @@ static void stdp_step(orc_sim_t* s, const consts_t* k) {
       const float x = s->xr[(t % s->D) * n + s->src_of[e]];
       const float t1 = aplus * x;
       const int32_t dq = (int32_t)rintf(t1 * 16384.0f);
+      if (dq == 0) continue;  /* no change: a weight above w_max stays until one comes */
       const int32_t w = s->q[e] + dq;
       s->q[e] = (int16_t)(w > qmax ? qmax : w);
     }
@@ -825,6 +827,37 @@ static void stdp_step(orc_sim_t* s, const consts_t* k) {
     s->e_rec += s->row_ptr[i + 1] - s->row_ptr[i];
   }
   next_step_offsets(s);
+}
+
+int16_t orc_stdp_synapse(const orc_config_t* c, int64_t T, const uint8_t* pre,
+                         const uint8_t* post, int32_t d, int16_t q0) {
+  if (q0 < 0 || T <= 0) return q0;
+  const float pplus = (float)exp(-c->dt / c->stdp_tau_plus);
+  const float pminus = (float)exp(-c->dt / c->stdp_tau_minus);
+  const float aplus = (float)c->stdp_a_plus, aminus = (float)c->stdp_a_minus;
+  const int32_t qmax = (int32_t)rint(c->stdp_w_max * 16384.0);
+  float* x = (float*)malloc(sizeof(float) * (size_t)T);
+  float y = 0.0f, xprev = 0.0f;
+  int32_t q = q0;
+  for (int64_t u = 0; u < T; ++u) {
+    const float ym = pminus * y;
+    if (u >= d && pre[u - d]) {  /* an arrival: depression by the target's earlier spikes */
+      const float t1 = aminus * ym;
+      const int32_t w = q - (int32_t)rintf(t1 * 16384.0f);
+      q = w < 0 ? 0 : w;
+    }
+    y = ym + (post[u] ? 1.0f : 0.0f);
+    const float decayed = pplus * xprev;
+    x[u] = decayed + (pre[u] ? 1.0f : 0.0f);
+    xprev = x[u];
+    if (post[u] && u >= d) {     /* a target spike: potentiation by the arrivals up to u */
+      const float t1 = aplus * x[u - d];
+      const int32_t dq = (int32_t)rintf(t1 * 16384.0f);
+      if (dq != 0) q = q + dq > qmax ? qmax : q + dq;
+    }
+  }
+  free(x);
+  return (int16_t)q;
 }
 
 void orc_sim_get_weights(const orc_sim_t* s, int16_t* wq) {

@@ -186,6 +186,12 @@ void orc_sim_inject(orc_sim_t* s, int32_t q, int64_t j, int32_t value);
  * plasticity when it is on. */
 void orc_sim_get_weights(const orc_sim_t* s, int16_t* wq);
 
+/* The plasticity rule of orc_sim_step on one synapse of delay d, given its source's and its
+ * target's spike flags pre[u], post[u] for steps u in [0, T) and its weight q0 at step 0:
+ * the weight after step T - 1 (the same float32 traces and order as the simulation). */
+int16_t orc_stdp_synapse(const orc_config_t* cfg, int64_t T, const uint8_t* pre,
+                         const uint8_t* post, int32_t d, int16_t q0);
+
 /* Trajectory recording: when enabled, every later step stores, per neuron, V before the
  * step, Ca before the step, the pre-threshold potential (0 when refractory), the spike
  * flag, the refractory flag and the consumed int32 input A. */

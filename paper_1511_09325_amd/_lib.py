@@ -57,6 +57,8 @@ class SimConfig(C.Structure):
         ("izh_d_i", C.c_double), ("izh_vpeak", C.c_double),
         ("conn_kernel", C.c_int32), ("lateral_amp", C.c_double),
         ("lateral_sigma_um", C.c_double), ("lateral_cutoff", C.c_double),
+        ("stdp", C.c_int32), ("stdp_tau_plus", C.c_double), ("stdp_tau_minus", C.c_double),
+        ("stdp_a_plus", C.c_double), ("stdp_a_minus", C.c_double), ("stdp_w_max", C.c_double),
     ]
 
 

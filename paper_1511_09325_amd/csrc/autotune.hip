@@ -30,7 +30,8 @@ std::string shape_key(const sim& s) {
   std::ostringstream k;
   k << arch << "|npc" << s.npc << "|nd" << s.nd << "|nets";
   for (const sim_net_t& n : s.nets) k << ":" << n.rows << "x" << n.cols << "@" << n.ext_rate_hz;
-  k << "|train" << (s.wfx ? 1 : 0) << "|model" << s.model << "|conn" << s.cfg.conn_kernel;
+  k << "|train" << (s.wfx ? 1 : 0) << "|model" << s.model << "|conn" << s.cfg.conn_kernel
+    << "|stdp" << s.cfg.stdp;
   return k.str();
 }
 

@@ -151,11 +151,21 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
 }
 
 // Order-independent digest of the dynamic state: V, Ca, refractory counters and the spike
-// history of the last DH steps (which determines every pending input).
-__global__ __launch_bounds__(256) void k_digest(StepArgs a, int64_t now, uint64_t* out) {
+// history of the last DH steps (which determines every pending input); with plasticity also
+// the traces and the n_rec records of the store (the weights).
+__global__ __launch_bounds__(256) void k_digest(StepArgs a, int64_t now, int64_t n_rec,
+                                                uint64_t* out) {
   const int64_t nall = (int64_t)a.n_cols * a.npc;
   uint64_t h = 0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < n_rec; r += (int64_t)gridDim.x * 256)
+    h += mix64(((uint64_t)r << 32) ^ a.syn[r] ^ 0xD6E8FEB86659FD93ull);
   for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < nall; j += (int64_t)gridDim.x * 256) {
+    if (a.sp_y) {
+      h += mix64(((uint64_t)__float_as_uint(a.sp_y[j]) << 32) ^ (uint64_t)j ^ 0xA0761D6478BD642Full);
+      for (int q = 0; q < a.dh; ++q)
+        h += mix64(((uint64_t)__float_as_uint(a.sp_x[(int64_t)q * nall + j]) << 32) ^
+                   ((uint64_t)j << 6) ^ (uint64_t)q ^ 0xE7037ED1A0B428DBull);
+    }
     const uint64_t v = __float_as_uint(a.v[j]), c = __float_as_uint(a.ca[j]);
     const uint64_t na = a.na ? __float_as_uint(a.na[j]) : 0u;  // sodium AHP variable, if kept
     h += mix64(((uint64_t)j << 2) ^ (v << 32) ^ c ^ ((uint64_t)a.ref[j] << 40) ^ (na << 7));
@@ -280,7 +290,9 @@ hipError_t launch_digest(const sim& s, uint64_t* out) {
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s.stream, out);
   int64_t blocks = (s.n_neurons + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(k_digest, dim3((unsigned)blocks), dim3(256), 0, s.stream, a, s.now, out);
+  const int64_t n_rec = s.cfg.stdp ? s.n_syn_padded : 0;
+  hipLaunchKernelGGL(k_digest, dim3((unsigned)blocks), dim3(256), 0, s.stream, a, s.now, n_rec,
+                     out);
   return hipGetLastError();
 }
 

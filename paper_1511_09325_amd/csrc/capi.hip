@@ -189,6 +189,22 @@ void validate(const sim_config_t* c) {
   if (c->train_mode && (c->neuron_model != DPSNN_NEURON_LIF || c->g_na != 0.0))
     bad("train mode needs the LIF neuron with g_na = 0 (the adjoint of the other models is not "
         "defined)");
+  if (c->stdp) {
+    if (!(c->stdp_tau_plus > 0 && c->stdp_tau_minus > 0 && std::isfinite(c->stdp_tau_plus) &&
+          std::isfinite(c->stdp_tau_minus)))
+      bad("stdp_tau_plus and stdp_tau_minus must be positive");
+    if (!(c->stdp_w_max > 0 && c->stdp_w_max < 2.0)) bad("stdp_w_max must be in (0, 2) mV");
+    // a trace never exceeds 1 / (1 - exp(-dt / tau)): the largest change must fit an int32
+    const double xp = 1.0 / (1.0 - exp(-c->dt / c->stdp_tau_plus));
+    const double xm = 1.0 / (1.0 - exp(-c->dt / c->stdp_tau_minus));
+    if (!(c->stdp_a_plus >= 0 && c->stdp_a_minus >= 0 &&
+          c->stdp_a_plus * 16384.0 * xp < 1073741824.0 &&
+          c->stdp_a_minus * 16384.0 * xm < 1073741824.0))
+      bad("stdp_a_plus and stdp_a_minus must be >= 0 with a * 2^14 / (1 - exp(-dt / tau)) "
+          "< 2^30");
+    if (c->train_mode) bad("STDP and train mode exclude each other");
+    if (c->delivery == DPSNN_DELIVERY_PUSH) bad("STDP needs the arrival form");
+  }
   int64_t cols = 0;
   for (int n = 0; n < c->n_nets; ++n) {
     const sim_net_t& t = c->nets[n];
@@ -199,6 +215,7 @@ void validate(const sim_config_t* c) {
     cols += (int64_t)t.rows * t.cols;
   }
   if (cols * c->npc >= ((int64_t)1 << 31)) bad("total neurons must be < 2^31");
+  if (c->stdp && cols * c->npc >= ((int64_t)1 << 24)) bad("STDP needs fewer than 2^24 neurons");
   if (cols * (c->d_max + 1) * c->npc >= ((int64_t)1 << 31)) bad("spike history exceeds 2^31 entries");
 }
 
@@ -542,8 +559,10 @@ constexpr int kAutoGather = 4;
 // kAutoGather), reduced until the accumulators fit the LDS.
 void set_gather(sim& s, int want) {
   if (want < 0 || want > kMaxGather) throw Fail{DPSNN_EINVAL, "gather_steps must be in [0, 8]"};
+  if (s.cfg.stdp && want > 1)
+    throw Fail{DPSNN_EINVAL, "with STDP every step gathers its own input (gather_steps 0 or 1)"};
   const int old = s.gk;
-  int k = want ? want : kAutoGather;
+  int k = want ? want : (s.cfg.stdp ? 1 : kAutoGather);
   for (; k > 1; --k) {
     s.gk = k;
     if (tile_lds_ok(s)) break;
@@ -732,10 +751,15 @@ void ring_from_history(sim& s) {
 
 // The dynamic state saved by a snapshot.  The push ring is not part of it: it is rebuilt
 // from the spike history on restore.
-constexpr int kSnapParts = 8;
+constexpr int kSnapParts = 11;
 
 void snapshot_parts(sim& s, size_t* parts, void** ptrs) {
   const size_t N = (size_t)s.n_neurons;
+  // plasticity: the weights (the whole store) and the traces
+  const bool sp = s.cfg.stdp != 0;
+  parts[8] = sp ? sizeof(uint32_t) * (size_t)(s.n_syn_padded + 4) : 0;   ptrs[8] = s.syn;
+  parts[9] = sp ? sizeof(float) * N : 0;                              ptrs[9] = s.sp_y;
+  parts[10] = sp ? sizeof(float) * (size_t)s.dh * N : 0;              ptrs[10] = s.sp_x;
   parts[7] = s.na ? sizeof(float) * N : 0;                         ptrs[7] = s.na;
   parts[6] = sizeof(unsigned long long) * (size_t)s.n_cols;         ptrs[6] = s.col_spk;
   parts[0] = sizeof(float) * N;                                    ptrs[0] = s.v;
@@ -747,6 +771,33 @@ void snapshot_parts(sim& s, size_t* parts, void** ptrs) {
 }
 
 void save_into_ckpt(sim& s, size_t m);
+
+// Plasticity: zero traces and the index of the plastic synapses into each neuron (a count
+// per target, its scan, then every record written at its target's next free place).
+void setup_stdp(sim& s) {
+  const size_t N = (size_t)s.n_neurons;
+  s.sp_y = (float*)dalloc(s, sizeof(float) * N);
+  s.sp_x = (float*)dalloc(s, sizeof(float) * (size_t)s.dh * N);
+  HIPCHK(hipMemsetAsync(s.sp_y, 0, sizeof(float) * N, s.stream));
+  HIPCHK(hipMemsetAsync(s.sp_x, 0, sizeof(float) * (size_t)s.dh * N, s.stream));
+  int32_t* cnt = (int32_t*)dalloc(s, sizeof(int32_t) * N);
+  HIPCHK(hipMemsetAsync(cnt, 0, sizeof(int32_t) * N, s.stream));
+  HIPCHK(launch_rev_count(s, cnt));
+  s.rev_ptr = (int64_t*)dalloc(s, sizeof(int64_t) * (N + 1));
+  const int64_t plen = scan_scratch_len((int64_t)N);
+  int64_t* part = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)plen);
+  HIPCHK(launch_scan_rows(s, cnt, (int64_t)N, s.rev_ptr, part, plen));
+  HIPCHK(hipMemcpyAsync(&s.n_rev, s.rev_ptr + N, sizeof(int64_t), hipMemcpyDeviceToHost, s.stream));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  dfree(s, part);
+  dfree(s, cnt);
+  s.rev = (uint64_t*)dalloc(s, sizeof(uint64_t) * (size_t)std::max<int64_t>(s.n_rev, 1));
+  unsigned long long* fill = (unsigned long long*)dalloc(s, sizeof(unsigned long long) * N);
+  HIPCHK(hipMemcpyAsync(fill, s.rev_ptr, sizeof(int64_t) * N, hipMemcpyDeviceToDevice, s.stream));
+  HIPCHK(launch_rev_fill(s, fill));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  dfree(s, fill);
+}
 
 // Train mode: float32 master weights (initially the int16 weights), their int32 efficacies,
 // the adjoint buffers, trajectory recording for one checkpoint segment, checkpoint 0.
@@ -926,6 +977,7 @@ int create_impl(const sim_config_t* cfg, const sim_buffers_t* bufs, void* hip_st
     }
     s->snaps.resize(64);
     if (cfg->train_mode) setup_train(*s);
+    if (cfg->stdp) setup_stdp(*s);
     HIPCHK(hipStreamSynchronize(s->stream));
     *out = s;
     return DPSNN_OK;
@@ -1493,6 +1545,10 @@ int sim_set_launch(sim_t* s, const sim_launch_t* l) {
       throw Fail{DPSNN_EINVAL, "graph_steps must be in [0, 4096]"};
     if (l->gather_steps < 0 || l->gather_steps > kMaxGather)
       throw Fail{DPSNN_EINVAL, "gather_steps must be in [0, 8]"};
+    if (s->cfg.stdp && (l->delivery != DPSNN_DELIVERY_ARRIVAL || l->tile_x != s->tile_x ||
+                        l->tile_y != s->tile_y || l->gather_steps > 1))
+      throw Fail{DPSNN_EINVAL, "with STDP the delivery, the tiling and one step per gather are "
+                               "fixed"};
     HIPCHK(hipStreamSynchronize(s->stream));
     drop_graph(*s);
     s->graph_steps = l->graph_steps;

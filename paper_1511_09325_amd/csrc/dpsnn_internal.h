@@ -52,6 +52,11 @@
 //     hist_go   uint16[DH][P][nd+1][npc]  its group offsets (copied from the row index when
 //                                   the neuron spiked, so that the readers of one source
 //                                   column's spikes load them contiguously)
+//   plasticity (only with stdp on; the store is then written by the step kernels)
+//     sp_y      float [N]         postsynaptic trace after the last step
+//     sp_x      float [DH][N]     presynaptic trace of step t in slot t % DH
+//     rev_ptr   int64 [N+1]       the plastic synapses into each neuron ...
+//     rev       uint64 [S+]       ... each as record index | (delay - 1) << 35 | source << 40
 //   push-delivery ring (only with DPSNN_DELIVERY_PUSH)
 //     ring      int32 [DH][N]       input of step t in slot t % DH
 //
@@ -206,6 +211,16 @@ struct StepArgs {
   unsigned long long* net_cnt;  // [n_nets][kCounters]: spikes, e_rec, e_ext, synapse records
                                 // read, synapses delivered (arrival form)
   unsigned long long* col_spk;  // [n_cols]: spikes per column
+  // plasticity (null / unused when off): the store, writable; the postsynaptic trace y and
+  // the presynaptic traces x of the last DH steps; the synapses into each neuron
+  uint32_t* syn_rw;
+  float* sp_y;                // [N] after the last step
+  float* sp_x;                // [DH][N], step t in slot t % DH
+  const int64_t* rev_ptr;     // [N+1]
+  const uint64_t* rev;        // record index (bits 0-34) | delay - 1 (35-39) | source (40-63)
+  float sp_pp, sp_pm;         // exp(-dt / tau_plus), exp(-dt / tau_minus)
+  float sp_ap, sp_am;         // a_plus, a_minus (mV)
+  int32_t sp_qmax;            // rint(w_max * 2^14)
   // train-mode trajectory recording (null when off): [steps][N]
   float* rec_vprev;
   float* rec_caprev;
@@ -318,6 +333,11 @@ struct sim {
   uint32_t* d_gdone = nullptr;     // finished workgroups of a gathering launch
   int32_t* ring = nullptr;
   unsigned long long* net_cnt = nullptr;
+  // plasticity (cfg.stdp)
+  float *sp_y = nullptr, *sp_x = nullptr;
+  int64_t* rev_ptr = nullptr;
+  uint64_t* rev = nullptr;
+  int64_t n_rev = 0;
   // tiles of the current shape
   int32_t tile_x = 0, tile_y = 0, n_tiles = 0, grid_tiles = 0, tile_max_cols = 0;
   int32_t *tile_order = nullptr, *tile_cinfo = nullptr, *tile_ncols = nullptr,
@@ -421,6 +441,9 @@ hipError_t launch_rate_loss(const sim& s, const float* rates, const float* targe
                             float* grad_rates);
 hipError_t launch_fill_entries(const sim& s);
 hipError_t launch_fill_dly(const sim& s);
+hipError_t launch_rev_count(const sim& s, int32_t* cnt);
+hipError_t launch_rev_fill(const sim& s, unsigned long long* fill);
+hipError_t launch_stdp_post(const sim& s, const StepArgs& a, int64_t u);
 int64_t scan_scratch_len(int64_t n);
 
 StepArgs make_step_args(const sim& s);

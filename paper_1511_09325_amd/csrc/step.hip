@@ -302,9 +302,16 @@ __device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
 // updated in 64-neuron chunks and the spikes compacted per column, in ascending order.
 static_assert(kPoissonEntries <= 64, "one Poisson threshold per lane of the first wave");
 
-template <int BLOCK, bool TRAIN, int MODEL>
+template <int BLOCK, bool TRAIN, int MODEL, bool PLAST>
 // At least four waves per SIMD for every workgroup size (at most 128 VGPRs), so that two
 // 512-thread workgroups of the steps inside a window share a compute unit.
+//
+// PLAST (spike-timing-dependent plasticity; one step per gather, native tiling, so that every
+// record read belongs to this tile and is read once): the postsynaptic traces of the tile's
+// neurons, decayed to this step, sit in LDS beside the accumulators; every plastic record
+// (weight >= 0) delivers its weight and is then depressed by rint(a_minus y- 2^14), floored
+// at 0, and its 16-byte piece written back when a weight changed.  The update then writes
+// the traces of this step (y = y- + s, x_u = P+ x_{u-1} + s).
 __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_arg, int32_t maxc,
                                                      int32_t kacc) {
   const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
@@ -329,14 +336,18 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
   const int lane = tid & 63, wave = tid >> 6;
   const int npc = a.npc;
   const int nch = (npc + 63) >> 6;
-  // dynamic LDS: acc[kacc][maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch], kacc the
-  // accumulators this launch has room for (the window's K, or 1 for a light step's launch)
+  // dynamic LDS: acc[kacc][maxc*npc] | spike masks[maxc*nch] | counts[maxc*nch] (| PLAST:
+  // decayed postsynaptic traces[maxc*npc]), kacc the accumulators this launch has room for
+  // (the window's K, or 1 for a light step's launch)
   const int32_t K = a.gk;
   int32_t* acc = (int32_t*)lds;
   size_t off = ((size_t)kacc * maxc * npc * 4 + 15) & ~(size_t)15;
   unsigned long long* smask = (unsigned long long*)(lds + off);
   off += (size_t)maxc * nch * 8;
   int32_t* scnt = (int32_t*)(lds + off);
+  off += ((size_t)maxc * nch * 4 + 15) & ~(size_t)15;
+  float* ym = (float*)(lds + off);
+  (void)ym;
 
   // Steps are gathered in windows of up to K: a gathering step reads, for every spike, the
   // delay groups due at its own step and at the following steps of its window (adjacent in
@@ -380,6 +391,12 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
     const int32_t TN = T * npc;
     for (int e = tid; e < W * TN; e += BLOCK) acc[e] = 0;
     __syncthreads();
+    if (PLAST) {
+      for (int e = tid; e < TN; e += BLOCK) {
+        const int col = e / npc;
+        ym[e] = a.sp_pm * a.sp_y[(int64_t)s_col[col] * npc + (e - col * npc)];
+      }
+    }
     // 1. items (pair, spike age b) and their group counts: spikes x delays read
     const int n_items = ns * NB;
     int32_t carry = 0;
@@ -476,6 +493,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         int32_t v[PIF][4];
         int32_t aoff[PIF];
         uint64_t sw[PIF];
+        uint64_t pc[PIF];
 #pragma unroll
         for (int q = 0; q < PIF; ++q) {
           const int32_t p = p0 + 4 * q;
@@ -485,8 +503,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
           aoff[q] = m3 ? sbq[3] : m2 ? sbq[2] : m1 ? sbq[1] : sbq[0];
           sw[q] = m3 ? slq[3] : m2 ? slq[2] : m1 ? slq[1] : slq[0];
           w[q] = make_uint4(kDummyRecord, kDummyRecord, kDummyRecord, kDummyRecord);
+          pc[q] = 0;
           if (valid) {
             const uint64_t piece = (uint64_t)(b + (uint32_t)p);
+            pc[q] = piece;
             w[q] = *(const uint4*)(a.syn + 4 * piece);
             if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(a.wfx + 4 * piece);
           }
@@ -507,6 +527,28 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
               const uint32_t off = __umul24(sl, npc4) + (uint32_t)aoff[q] + (rec_k(x[e]) << 2);
               atomicAdd((int32_t*)((unsigned char*)acc + off), TRAIN ? v[q][e] : rec_wq(x[e]));
             }
+          }
+          if (PLAST) {
+            // depression of the plastic records just delivered (the piece's records all
+            // belong to this tile; dummies read slot 31)
+            uint32_t nw[4] = {x[0], x[1], x[2], x[3]};
+            bool changed = false;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const uint32_t sl = (uint32_t)(sw[q] >> (5u * rec_rank(x[e]))) & 31u;
+              const int32_t q0 = rec_wq(x[e]);
+              if (sl != (uint32_t)kNoSlot && q0 >= 0) {
+                const float yv = *(const float*)((const unsigned char*)ym + __umul24(sl, npc4) +
+                                                 (rec_k(x[e]) << 2));
+                const float t1 = a.sp_am * yv;
+                const int32_t dq = (int32_t)__builtin_rintf(t1 * 16384.0f);
+                if (dq != 0) {
+                  nw[e] = (x[e] & 0xffffu) | ((uint32_t)max(q0 - dq, 0) << 16);
+                  changed = true;
+                }
+              }
+            }
+            if (changed) *(uint4*)(a.syn_rw + 4 * pc[q]) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
           }
         }
       }
@@ -534,9 +576,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
     for (int rd = wave; rd < T * nr; rd += NW) {
       const int col = rd / nr, q0 = (rd - col * nr) * 4;
       const int32_t g = s_col[col];
-      float vv[4], cc[4], na4[4];
+      float vv[4], cc[4], na4[4], xp[4];
       int32_t rr[4], nx[4], sv[4];
       bool ok[4];
+      const int32_t x_prev_slot = u_slot == 0 ? a.dh - 1 : u_slot - 1;
       // every global load of the round first, so that their latencies overlap: state and, at
       // a light step, the saved input
 #pragma unroll
@@ -546,6 +589,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         vv[m] = 0.0f;
         cc[m] = 0.0f;
         na4[m] = 0.0f;
+        xp[m] = 0.0f;
         rr[m] = 0;
         sv[m] = 0;
         if (ok[m]) {
@@ -555,6 +599,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
           if (MODEL == kModelLifNa) na4[m] = a.na[j];
           rr[m] = a.ref[j];
           if (light) sv[m] = a.acc_save[light_save + j];
+          if (PLAST) xp[m] = a.sp_x[(int64_t)x_prev_slot * nall + j];
         }
       }
       const int32_t cloc = s_cloc[col];
@@ -592,6 +637,14 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
           const int c = col * nch + q0 + m;
           if (ok[m])
             neuron_store<TRAIN, MODEL>(a, (int64_t)g * npc + (q0 + m) * 64 + lane, u, o[m], vv[m], cc[m]);
+          if (PLAST && ok[m]) {
+            const int k = (q0 + m) * 64 + lane;
+            const int64_t j = (int64_t)g * npc + k;
+            const float sp = o[m].spike ? 1.0f : 0.0f;
+            a.sp_y[j] = ym[col * npc + k] + sp;
+            const float decayed = a.sp_pp * xp[m];
+            a.sp_x[(int64_t)u_slot * nall + j] = decayed + sp;
+          }
           const unsigned long long bal = __ballot(o[m].spike);
           if (lane == 0) {
             smask[c] = bal;
@@ -842,22 +895,32 @@ __global__ void k_init_state(StepArgs a, int32_t model) {
   }
 }
 
-template <int BLOCK>
-void launch_tile(const sim& s, const StepArgs& a, int64_t u, int32_t kacc, bool train) {
+template <int BLOCK, bool PLAST>
+void launch_tile_p(const sim& s, const StepArgs& a, int64_t u, int32_t kacc, bool train) {
   const size_t lds = tile_lds_bytes(s, kacc);
   const dim3 grid(s.grid_tiles), block(BLOCK);
   if (train)  // train mode runs the LIF neuron with one AHP variable only
-    hipLaunchKernelGGL((k_step_tile<BLOCK, true, kModelLif>), grid, block, lds, s.stream, a, u,
-                       s.tile_max_cols, kacc);
+    hipLaunchKernelGGL((k_step_tile<BLOCK, true, kModelLif, false>), grid, block, lds, s.stream,
+                       a, u, s.tile_max_cols, kacc);
   else if (s.model == kModelLifNa)
-    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelLifNa>), grid, block, lds, s.stream, a,
-                       u, s.tile_max_cols, kacc);
+    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelLifNa, PLAST>), grid, block, lds,
+                       s.stream, a, u, s.tile_max_cols, kacc);
   else if (s.model == kModelIzh)
-    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelIzh>), grid, block, lds, s.stream, a, u,
-                       s.tile_max_cols, kacc);
+    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelIzh, PLAST>), grid, block, lds, s.stream,
+                       a, u, s.tile_max_cols, kacc);
   else
-    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelLif>), grid, block, lds, s.stream, a, u,
-                       s.tile_max_cols, kacc);
+    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelLif, PLAST>), grid, block, lds, s.stream,
+                       a, u, s.tile_max_cols, kacc);
+}
+
+template <int BLOCK>
+void launch_tile(const sim& s, const StepArgs& a, int64_t u, int32_t kacc, bool train) {
+  if (s.cfg.stdp) {
+    launch_tile_p<BLOCK, true>(s, a, u, kacc, false);
+    (void)launch_stdp_post(s, a, u);
+  } else {
+    launch_tile_p<BLOCK, false>(s, a, u, kacc, train);
+  }
 }
 
 template <int BLOCK>
@@ -909,6 +972,7 @@ static size_t tile_fixed_lds(const sim& s, int32_t kacc) {
   size_t b = ((size_t)std::max(kacc, 1) * s.tile_max_cols * s.npc * 4 + 15) & ~(size_t)15;
   b += (size_t)s.tile_max_cols * nch * 8;
   b += ((size_t)s.tile_max_cols * nch * 4 + 15) & ~(size_t)15;
+  if (s.cfg.stdp) b += (size_t)s.tile_max_cols * s.npc * 4;  // decayed postsynaptic traces
   return b;
 }
 
@@ -992,6 +1056,18 @@ StepArgs make_step_args(const sim& s) {
     a.rec_flags = s.rec_flags;
     a.rec_base = s.rec_base;
   }
+  if (s.cfg.stdp) {
+    a.syn_rw = s.syn;
+    a.sp_y = s.sp_y;
+    a.sp_x = s.sp_x;
+    a.rev_ptr = s.rev_ptr;
+    a.rev = s.rev;
+    a.sp_pp = (float)exp(-s.cfg.dt / s.cfg.stdp_tau_plus);
+    a.sp_pm = (float)exp(-s.cfg.dt / s.cfg.stdp_tau_minus);
+    a.sp_ap = (float)s.cfg.stdp_a_plus;
+    a.sp_am = (float)s.cfg.stdp_a_minus;
+    a.sp_qmax = (int32_t)rint(s.cfg.stdp_w_max * 16384.0);
+  }
   a.k = s.nk;
   return a;
 }
@@ -1000,10 +1076,13 @@ StepArgs make_step_args(const sim& s) {
 // workgroup, and record the largest static size.
 template <int BLOCK>
 hipError_t allow_large_lds() {
-  const void* const fns[] = {(const void*)k_step_tile<BLOCK, true, kModelLif>,
-                             (const void*)k_step_tile<BLOCK, false, kModelLif>,
-                             (const void*)k_step_tile<BLOCK, false, kModelLifNa>,
-                             (const void*)k_step_tile<BLOCK, false, kModelIzh>};
+  const void* const fns[] = {(const void*)k_step_tile<BLOCK, true, kModelLif, false>,
+                             (const void*)k_step_tile<BLOCK, false, kModelLif, false>,
+                             (const void*)k_step_tile<BLOCK, false, kModelLifNa, false>,
+                             (const void*)k_step_tile<BLOCK, false, kModelIzh, false>,
+                             (const void*)k_step_tile<BLOCK, false, kModelLif, true>,
+                             (const void*)k_step_tile<BLOCK, false, kModelLifNa, true>,
+                             (const void*)k_step_tile<BLOCK, false, kModelIzh, true>};
   for (const void* f : fns) {
     hipFuncAttributes attr;
     hipError_t e = hipFuncGetAttributes(&attr, f);

@@ -39,13 +39,14 @@ def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, b
         nets[n].ext_rate_hz = float(p["ext_rate_hz"])
     c = L.SimConfig()
     for name in ("npc", "n_exc", "d_min", "d_max", "t_ref", "ext_syn", "neuron_model",
-                 "conn_kernel"):
+                 "conn_kernel", "stdp"):
         setattr(c, name, int(p0[name]))
     for name in ("p_own", "p_remote", "decay_um", "spacing_um", "we_mu", "we_sigma", "wi_mu",
                  "wi_sigma", "tau_m", "theta", "v_reset", "tau_ca", "ca_inc", "g_ahp", "dt",
                  "j_ext", "tau_na", "na_inc", "g_na", "izh_a_e", "izh_b_e", "izh_c_e",
                  "izh_d_e", "izh_a_i", "izh_b_i", "izh_c_i", "izh_d_i", "izh_vpeak",
-                 "lateral_amp", "lateral_sigma_um", "lateral_cutoff"):
+                 "lateral_amp", "lateral_sigma_um", "lateral_cutoff", "stdp_tau_plus",
+                 "stdp_tau_minus", "stdp_a_plus", "stdp_a_minus", "stdp_w_max"):
         setattr(c, name, float(p0[name]))
     c.n_nets = len(plist)
     c.nets = C.cast(nets, C.POINTER(L.SimNet))

@@ -59,6 +59,7 @@ int main(void) {
   printf("sim_sizes_t %zu\nsim_buffers_t %zu\n", sizeof(sim_sizes_t), sizeof(sim_buffers_t));
   F(sim_config_t, nets) F(sim_config_t, delivery) F(sim_config_t, record_steps)
   F(sim_config_t, ckpt_every) F(sim_config_t, j_ext) F(sim_net_t, ext_rate_hz)
+  F(sim_config_t, stdp) F(sim_config_t, stdp_w_max)
   F(sim_info_t, device_bytes) F(sim_info_t, caller_bytes)
   F(sim_sizes_t, history_bytes) F(sim_sizes_t, state_ref_offset)
   F(sim_buffers_t, state) F(sim_buffers_t, history_bytes)
@@ -90,6 +91,8 @@ def test_struct_layout_matches_c():
                               "sim_config_t.record_steps": (L.SimConfig, "record_steps"),
                               "sim_config_t.ckpt_every": (L.SimConfig, "ckpt_every"),
                               "sim_config_t.j_ext": (L.SimConfig, "j_ext"),
+                              "sim_config_t.stdp": (L.SimConfig, "stdp"),
+                              "sim_config_t.stdp_w_max": (L.SimConfig, "stdp_w_max"),
                               "sim_net_t.ext_rate_hz": (L.SimNet, "ext_rate_hz"),
                               "sim_info_t.device_bytes": (L.SimInfo, "device_bytes")}.items():
         assert int(got[key]) == getattr(cls, field).offset, key
@@ -100,6 +103,9 @@ def test_struct_layout_matches_c():
     dict(d_min=5, d_max=4), dict(wi_mu=-1.9), dict(tau_m=0.0), dict(t_ref=300),
     dict(p_own=0.9, p_remote=0.4), dict(rows=0), dict(ext_rate_hz=50.0),
     dict(neuron_model=2), dict(g_na=0.1, tau_na=0.0), dict(neuron_model=1, izh_vpeak=float("nan")),
+    dict(stdp=1, stdp_tau_plus=0.0), dict(stdp=1, stdp_w_max=2.5), dict(stdp=1, stdp_w_max=0.0),
+    dict(stdp=1, stdp_a_minus=-0.01), dict(stdp=1, stdp_a_plus=float("nan")),
+    dict(stdp=1, stdp_a_plus=100.0, stdp_tau_plus=1000.0),
 ])
 def test_invalid_configs_are_rejected_before_device_work(lib, bad):
     p = W.grid(2, 2)
@@ -122,6 +128,17 @@ def test_train_mode_needs_the_one_variable_lif(lib, bad):
     h = C.c_void_p(123)
     assert lib.sim_create(C.byref(cfg), None, None, C.byref(h)) == L.EINVAL
     assert b"train mode" in lib.sim_last_error(None)
+
+
+@pytest.mark.parametrize("opts,msg", [(dict(train_mode=True), b"train mode"),
+                                      (dict(delivery=2), b"arrival form")])
+def test_stdp_excludes_train_mode_and_push(lib, opts, msg):
+    p = W.grid(2, 2)
+    p.update(stdp=1)
+    cfg, nets = make_config(p, **opts)
+    h = C.c_void_p(123)
+    assert lib.sim_create(C.byref(cfg), None, None, C.byref(h)) == L.EINVAL
+    assert msg in lib.sim_last_error(None)
 
 
 def test_null_handles(lib):

@@ -233,3 +233,25 @@ def test_weights_equal_a_replay_from_the_raster(seed):
     assert changed.sum() > 100                   # the rule did act
     assert np.all(got[net[3] < 0] == net[3][net[3] < 0])
     assert diff.max() <= 3 and (diff == 0).mean() > 0.99, (diff.max(), (diff == 0).mean())
+
+
+def test_single_synapse_replay_equals_the_simulation():
+    """oracle.stdp_synapse, which the full-size GPU checks use one synapse at a time, gives
+    every synapse of a simulated network its final weight bit for bit."""
+    p = W.tiny(2, 2, npc=24, seed=6, ext_rate_hz=3.4, stdp=1, stdp_a_plus=0.03,
+               stdp_a_minus=0.032, stdp_w_max=0.25)
+    net = oracle.network(p)
+    sim = oracle.Sim(p, net)
+    T = 260
+    sim.step(T)
+    n = oracle.n_neurons(p)
+    spk = np.zeros((n, T), np.uint8)
+    for u, ids in enumerate(sim.raster(0, T)):
+        spk[ids, u] = 1
+    row_ptr, tgt, dly, wq = net
+    got = sim.weights()
+    for i in range(n):
+        for e in range(row_ptr[i], row_ptr[i + 1]):
+            want = oracle.stdp_synapse(p, spk[i], spk[tgt[e]], int(dly[e]), int(wq[e]))
+            assert got[e] == want, (i, e)
+    assert (got != wq).sum() > 100 and (got == round(0.25 * Q)).any()
