@@ -334,6 +334,36 @@ def models_leg(torch, warmup=50):
     return out
 
 
+def stdp_leg(torch, warmup=50):
+    """The 24x24 grid with spike-timing-dependent plasticity on (1 s, default launch) beside
+    the same grid without it, over the same steps: the cost of the depression inside the
+    delivery and of the potentiation kernel."""
+    from paper_1511_09325_amd import Simulation
+    from paper_1511_09325_amd import workloads as W
+    out = {}
+    for key, preset in (("static", dict(W.PLAIN_24X24, steps=1000)), ("stdp", W.STDP_24X24)):
+        p, steps = preset["params"], preset["steps"]
+        t0 = time.time()
+        sim = Simulation(p)
+        sim.sync()
+        gen = time.time() - t0
+        sim.step(warmup)
+        sim.sync()
+        t, ev, spk = _timed_run(sim, steps - warmup, torch)
+        out[key] = {"workload": preset["name"] if key == "stdp"
+                    else "24x24, LIF with the calcium AHP, static weights, 1 s",
+                    "timed_steps": "%d-%d" % (warmup, steps - 1), "setup_s": gen,
+                    "device_bytes": sim.device_bytes,
+                    "ms_per_step": t * 1e3 / (steps - warmup), "events_per_s": ev / t,
+                    "sim_ms_per_wall_s": (steps - warmup) * p["dt"] / t,
+                    "mean_rate_hz": spk / (sim.n_neurons * (steps - warmup) * p["dt"] * 1e-3)}
+        sim.close()
+        del sim
+    out["stdp_over_static"] = out["stdp"]["ms_per_step"] / out["static"]["ms_per_step"]
+    torch.cuda.empty_cache()
+    return out
+
+
 def fwd_bwd_leg(torch, iters=3):
     """Forward+backward on the 4x4 grid (19,840 neurons), 500 ms, checkpoints every 50
     steps: loss = mean over columns of (rate - target)^2 with seeded U(2, 8) Hz targets,
@@ -510,6 +540,7 @@ def main():
     ap.add_argument("--no-small-grids", action="store_true")
     ap.add_argument("--no-models", action="store_true")
     ap.add_argument("--no-paper-recipe", action="store_true")
+    ap.add_argument("--no-stdp", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB once (a reference kernel of known "
                          "traffic for hardware byte counters)")
@@ -575,6 +606,9 @@ def main():
     if not args.no_models and args.workload == "96x96":
         log("neuron-model legs: 24x24 with the sodium AHP and with Izhikevich neurons")
         out["models"] = models_leg(torch)
+    if not args.no_stdp and args.workload == "96x96":
+        log("plasticity leg: 24x24 with STDP on, beside static weights")
+        out["stdp"] = stdp_leg(torch)
     if not args.no_batched:
         log("batched leg: 64 networks, one launch per step, vs 64 sequential runs")
         out["batched"] = batched_leg(torch)

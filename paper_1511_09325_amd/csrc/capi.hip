@@ -215,7 +215,8 @@ void validate(const sim_config_t* c) {
     cols += (int64_t)t.rows * t.cols;
   }
   if (cols * c->npc >= ((int64_t)1 << 31)) bad("total neurons must be < 2^31");
-  if (c->stdp && cols * c->npc >= ((int64_t)1 << 24)) bad("STDP needs fewer than 2^24 neurons");
+  if (c->stdp && (cols * c->npc >= ((int64_t)1 << 24) || cols > 16000))
+    bad("STDP needs fewer than 2^24 neurons and at most 16000 columns");
   if (cols * (c->d_max + 1) * c->npc >= ((int64_t)1 << 31)) bad("spike history exceeds 2^31 entries");
 }
 
@@ -797,6 +798,21 @@ void setup_stdp(sim& s) {
   HIPCHK(launch_rev_fill(s, fill));
   HIPCHK(hipStreamSynchronize(s.stream));
   dfree(s, fill);
+  // each target's words sorted by source, in chunks of at most 2^27 words
+  std::vector<int64_t> h_ptr(N + 1);
+  HIPCHK(hipMemcpy(h_ptr.data(), s.rev_ptr, sizeof(int64_t) * (N + 1), hipMemcpyDeviceToHost));
+  const int64_t chunk = std::max<int64_t>(std::min<int64_t>(s.n_rev, (int64_t)1 << 27), 1);
+  const int32_t max_segs = 1 << 21;
+  size_t temp_bytes = 0;
+  HIPCHK(sort_rev_temp_bytes(chunk, max_segs, &temp_bytes));
+  uint64_t* alt = (uint64_t*)dalloc(s, sizeof(uint64_t) * (size_t)chunk);
+  int32_t* off = (int32_t*)dalloc(s, sizeof(int32_t) * ((size_t)max_segs + 1));
+  void* temp = dalloc(s, std::max<size_t>(temp_bytes, 1));
+  HIPCHK(sort_rev(s, chunk, max_segs, alt, off, temp, temp_bytes, h_ptr));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  dfree(s, temp);
+  dfree(s, off);
+  dfree(s, alt);
 }
 
 // Train mode: float32 master weights (initially the int16 weights), their int32 efficacies,

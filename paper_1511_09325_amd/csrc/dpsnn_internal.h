@@ -444,6 +444,9 @@ hipError_t launch_fill_dly(const sim& s);
 hipError_t launch_rev_count(const sim& s, int32_t* cnt);
 hipError_t launch_rev_fill(const sim& s, unsigned long long* fill);
 hipError_t launch_stdp_post(const sim& s, const StepArgs& a, int64_t u);
+hipError_t sort_rev(const sim& s, int64_t chunk, int32_t max_segs, uint64_t* alt, int32_t* off,
+                    void* temp, size_t temp_bytes, const std::vector<int64_t>& h_ptr);
+hipError_t sort_rev_temp_bytes(int64_t chunk, int32_t segs, size_t* bytes);
 int64_t scan_scratch_len(int64_t n);
 
 StepArgs make_step_args(const sim& s);

@@ -15,10 +15,16 @@
 //
 // The potentiation needs the synapses into a neuron.  The store is kept by source (rows split
 // into parts by target tile), so a reverse index is built once at creation: per target
-// neuron, its plastic synapses as 64-bit words (record index | delay - 1 | source id).  A
-// postsynaptic spike then reads its ~1000 words contiguously and updates the records it names
-// in place; the records of one step's spikes are distinct (one target each), so no two lanes
-// touch the same record and no atomics are needed.
+// neuron, its plastic synapses as 64-bit words (record index | delay - 1 | source id), sorted
+// by source, so that the lanes reading one target's sources read neighbouring traces (a
+// target's sources lie in a few columns).  A postsynaptic spike then reads its ~1000 words
+// contiguously and updates the records they name in place; the records of one step's spikes
+// are distinct (one target each), so no two lanes touch the same record and no atomics are
+// needed.
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+
+#include <algorithm>
+
 #include "dpsnn_internal.h"
 
 namespace dpsnn {
@@ -60,34 +66,100 @@ __global__ __launch_bounds__(256) void k_rev_pass(StepArgs a, int32_t* cnt,
   }
 }
 
-// Potentiation after the update of step u: one workgroup per column, each wave one of the
-// column's spikes of step u at a time, its lanes over the spiking neuron's index words.
-__global__ __launch_bounds__(256) void k_stdp_post(StepArgs a, int64_t u_arg) {
+// Potentiation after the update of step u.  The step's spikes are spread over the whole
+// grid: every workgroup turns the per-column spike counts into a prefix in LDS, then its
+// waves take work items in a fixed stride over the grid's waves, an item being a quarter
+// of one spike's index words (item q: spike q / 4, located by binary search over the
+// prefix).  A lane holds four words in flight: their traces are loaded together, then the
+// records whose change is not zero are read and written back.  Bursting columns therefore do
+// not serialise on one workgroup.
+constexpr int kPostBlock = 256;
+constexpr int kPostSplit = 4;
+constexpr int kPostInFlight = 4;
+
+__global__ __launch_bounds__(kPostBlock) void k_stdp_post(StepArgs a, int64_t u_arg) {
+  extern __shared__ int32_t pref[];  // [n_cols + 1]
+  __shared__ int32_t wsum[kPostBlock / 64];
   const int64_t u = u_arg + (a.now_dev ? *a.now_dev : 0);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t slot = u % a.dh;
   const int64_t nall = (int64_t)a.n_cols * a.npc;
-  for (int32_t g = blockIdx.x; g < a.n_cols; g += gridDim.x) {
-    const int64_t hb = slot * a.n_cols + g;
-    const int32_t cnt = a.hist_cnt[hb];
-    for (int32_t pos = wave; pos < cnt; pos += 4) {
-      const int64_t j = (int64_t)g * a.npc + a.hist_ids[hb * a.npc + pos];
-      const int64_t e1 = a.rev_ptr[j + 1];
-      for (int64_t e = a.rev_ptr[j] + lane; e < e1; e += 64) {
-        const uint64_t r = a.rev[e];
-        const int64_t t = u - (int64_t)((r >> 35) & 31u) - 1;
-        if (t < 0) continue;
-        const float x = a.sp_x[(t % a.dh) * nall + (int64_t)(r >> 40)];
+  const int32_t* cnt = a.hist_cnt + slot * a.n_cols;
+  // exclusive prefix of the column counts
+  int32_t carry = 0;
+  for (int32_t c0 = 0; c0 < a.n_cols; c0 += kPostBlock) {
+    const int32_t c = c0 + tid;
+    const int32_t x = c < a.n_cols ? cnt[c] : 0;
+    int32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int32_t t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int32_t before = carry;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (c < a.n_cols) pref[c] = before + incl - x;
+    for (int w = 0; w < kPostBlock / 64; ++w) carry += wsum[w];
+    __syncthreads();
+  }
+  if (tid == 0) pref[a.n_cols] = carry;
+  __syncthreads();
+  const int64_t items = (int64_t)carry * kPostSplit;
+  const int64_t waves = (int64_t)gridDim.x * (kPostBlock / 64);
+  for (int64_t it = (int64_t)blockIdx.x * (kPostBlock / 64) + wave; it < items; it += waves) {
+    const int32_t q = (int32_t)(it / kPostSplit), part = (int32_t)(it - (int64_t)q * kPostSplit);
+    int lo = 0, hi = a.n_cols;  // the column g with pref[g] <= q < pref[g + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pref[mid] <= q) lo = mid;
+      else hi = mid;
+    }
+    const int32_t g = lo, pos = q - pref[lo];
+    const int64_t j = (int64_t)g * a.npc + a.hist_ids[(slot * a.n_cols + g) * a.npc + pos];
+    const int64_t b0 = a.rev_ptr[j], len = a.rev_ptr[j + 1] - b0;
+    const int64_t e_lo = b0 + len * part / kPostSplit, e1 = b0 + len * (part + 1) / kPostSplit;
+    for (int64_t e0 = e_lo + lane; e0 < e1; e0 += 64 * kPostInFlight) {
+      uint64_t r[kPostInFlight];
+      bool ok[kPostInFlight];
+#pragma unroll
+      for (int k = 0; k < kPostInFlight; ++k) {
+        const int64_t e = e0 + 64 * k;
+        r[k] = e < e1 ? a.rev[e] : 0ull;
+        const int64_t t = u - (int64_t)((r[k] >> 35) & 31u) - 1;
+        ok[k] = e < e1 && t >= 0;
+      }
+      int32_t dq[kPostInFlight];
+#pragma unroll
+      for (int k = 0; k < kPostInFlight; ++k) {
+        float x = 0.0f;
+        if (ok[k]) {
+          const int64_t t = u - (int64_t)((r[k] >> 35) & 31u) - 1;
+          x = a.sp_x[(t % a.dh) * nall + (int64_t)(r[k] >> 40)];
+        }
         const float t1 = a.sp_ap * x;
-        const int32_t dq = (int32_t)__builtin_rintf(t1 * 16384.0f);
-        if (dq == 0) continue;
-        uint32_t* rec = a.syn_rw + (r & kRevRecMask);
-        const uint32_t old = *rec;
-        const int32_t w = min(rec_wq(old) + dq, a.sp_qmax);
-        *rec = (old & 0xffffu) | ((uint32_t)w << 16);
+        dq[k] = ok[k] ? (int32_t)__builtin_rintf(t1 * 16384.0f) : 0;
+      }
+      // the records whose weight changes (a source that spiked recently): read, then written
+      uint32_t old[kPostInFlight];
+#pragma unroll
+      for (int k = 0; k < kPostInFlight; ++k) old[k] = dq[k] != 0 ? a.syn_rw[r[k] & kRevRecMask] : 0u;
+#pragma unroll
+      for (int k = 0; k < kPostInFlight; ++k) {
+        if (dq[k] != 0) {
+          const int32_t w = min(rec_wq(old[k]) + dq[k], a.sp_qmax);
+          a.syn_rw[r[k] & kRevRecMask] = (old[k] & 0xffffu) | ((uint32_t)w << 16);
+        }
       }
     }
   }
+}
+
+// Offsets of the segments of targets [j0, j0 + n) relative to the first one's start.
+__global__ void k_rev_offsets(const int64_t* rev_ptr, int64_t j0, int32_t n, int32_t* off) {
+  const int32_t t = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (t <= n) off[t] = (int32_t)(rev_ptr[j0 + t] - rev_ptr[j0]);
 }
 
 int64_t grid_waves(int64_t n) {
@@ -112,9 +184,54 @@ hipError_t launch_rev_fill(const sim& s, unsigned long long* fill) {
   return hipGetLastError();
 }
 
+// The grid: four workgroups per compute unit of an MI355X (or fewer for small networks).
 hipError_t launch_stdp_post(const sim& s, const StepArgs& a, int64_t u) {
-  hipLaunchKernelGGL(k_stdp_post, dim3((unsigned)s.n_cols), dim3(256), 0, s.stream, a, u);
+  const unsigned grid = (unsigned)std::min<int64_t>(1024, std::max<int64_t>(s.n_cols * 4, 1));
+  hipLaunchKernelGGL(k_stdp_post, dim3(grid), dim3(kPostBlock),
+                     sizeof(int32_t) * ((size_t)s.n_cols + 1), s.stream, a, u);
   return hipGetLastError();
+}
+
+// Sort every target's index words by source (bits 40-63), in chunks of whole targets of at
+// most `chunk` words: a segmented radix sort per chunk through a buffer of that size.  Order
+// within a target does not change results, only which traces neighbouring lanes read.
+hipError_t sort_rev(const sim& s, int64_t chunk, int32_t max_segs, uint64_t* alt, int32_t* off,
+                    void* temp, size_t temp_bytes, const std::vector<int64_t>& h_ptr) {
+  const int64_t N = s.n_neurons;
+  int64_t j0 = 0;
+  while (j0 < N) {
+    int64_t j1 = j0;
+    while (j1 < N && j1 - j0 < max_segs && h_ptr[(size_t)j1 + 1] - h_ptr[(size_t)j0] <= chunk) ++j1;
+    if (j1 == j0) return hipErrorInvalidValue;  // a target with more words than a chunk
+    const int32_t nseg = (int32_t)(j1 - j0);
+    const int64_t items = h_ptr[(size_t)j1] - h_ptr[(size_t)j0];
+    hipLaunchKernelGGL(k_rev_offsets, dim3((unsigned)((nseg + 256) / 256)), dim3(256), 0, s.stream,
+                       s.rev_ptr, j0, nseg, off);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    uint64_t* keys = s.rev + h_ptr[(size_t)j0];
+    rocprim::double_buffer<uint64_t> db(keys, alt);
+    size_t tb = temp_bytes;
+    e = rocprim::segmented_radix_sort_keys(temp, tb, db, (unsigned int)items, (unsigned int)nseg,
+                                           off, off + 1, 40, 64, s.stream);
+    if (e != hipSuccess) return e;
+    if (db.current() != keys) {
+      e = hipMemcpyAsync(keys, db.current(), sizeof(uint64_t) * (size_t)items,
+                         hipMemcpyDeviceToDevice, s.stream);
+      if (e != hipSuccess) return e;
+    }
+    j0 = j1;
+  }
+  return hipSuccess;
+}
+
+// Temporary storage the sort needs for chunks of at most `chunk` words and `segs` segments.
+hipError_t sort_rev_temp_bytes(int64_t chunk, int32_t segs, size_t* bytes) {
+  rocprim::double_buffer<uint64_t> db(nullptr, nullptr);
+  *bytes = 0;
+  return rocprim::segmented_radix_sort_keys(nullptr, *bytes, db, (unsigned int)chunk,
+                                            (unsigned int)segs, (int32_t*)nullptr,
+                                            (int32_t*)nullptr + 1, 40, 64, (hipStream_t)0);
 }
 
 }  // namespace dpsnn

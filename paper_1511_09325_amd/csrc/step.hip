@@ -431,19 +431,20 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
     // loads in flight per lane, and adds the synapses into the LDS accumulators.
     const int quad0 = lane & ~3, ql = lane & 3;
     const uint32_t npc4 = (uint32_t)npc * 4u;
-    uint32_t dwave = 0;  // records delivered by the wave (uniform)
+    uint32_t dlane = 0;  // records delivered by this lane (a register add per record)
     // exact small-integer quotients through float reciprocals (operands < 2^16)
     const float inv_nb = 1.0f / (float)NB;
-    for (int32_t bt = wave; bt * 64 < total;) {
-      // the wave's next batch, taken now so that the atomic's latency hides under this one
-      int32_t bt_next = 0;
-      if (lane == 0) bt_next = atomicAdd(&s_next_bt, 1);
+    // A lane's group of a batch: its pair, the step offset of its accumulator, its spike's
+    // part start and the group's first and end offsets within the part (the three loads).
+    // The next batch is located (and its loads issued) before the current one is streamed,
+    // so that the two latencies overlap.
+    struct Located {
+      int32_t si, gsb, g0, g1;
+      uint32_t st;
+    };
+    auto locate = [&](int32_t bt) {
+      Located L{0, 0, 0, 0, 0u};
       const int32_t qq = bt * 64 + lane;
-      // this lane's group: first 16-byte piece, length in pieces, the offset of the
-      // accumulator of its step and its pair's slot word
-      uint32_t gpc = 0;
-      int32_t glen = 0, gsb = 0;
-      uint64_t gsl = ~(uint64_t)0;
       if (qq < total) {
         int lo = 0, hi = n_items;
         while (hi - lo > 1) {
@@ -462,12 +463,29 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         if (slot < 0) slot += a.dh;
         const int64_t pid = (int64_t)slot * a.n_parts + s_part[si];
         const uint16_t* go = a.hist_go + (pid * (a.nd + 1) + (d - a.d_min)) * npc + pos;
-        const int32_t g0 = go[0], g1 = go[npc];
-        gpc = a.hist_st[pid * npc + pos] + ((uint32_t)g0 >> 2);
-        glen = (g1 - g0) >> 2;
-        gsb = (d - ag) * TN * 4;
-        gsl = s_slots[si];
+        L.si = si;
+        L.gsb = (d - ag) * TN * 4;
+        L.g0 = go[0];
+        L.g1 = go[npc];
+        L.st = a.hist_st[pid * npc + pos];
       }
+      return L;
+    };
+    int32_t bt = wave;
+    Located cur = locate(bt);
+    while (bt * 64 < total) {
+      // the wave's next batch (the atomic's latency hides under the search), located now
+      int32_t bt_next = 0;
+      if (lane == 0) bt_next = atomicAdd(&s_next_bt, 1);
+      bt_next = __shfl(bt_next, 0);
+      const Located nxt = locate(bt_next);
+      // this lane's group: first 16-byte piece, length in pieces, the offset of the
+      // accumulator of its step and its pair's slot word
+      const bool has = bt * 64 + lane < total;
+      const uint32_t gpc = cur.st + ((uint32_t)cur.g0 >> 2);
+      const int32_t glen = has ? (cur.g1 - cur.g0) >> 2 : 0;
+      const int32_t gsb = cur.gsb;
+      const uint64_t gsl = has ? s_slots[cur.si] : ~(uint64_t)0;
       streamed += (unsigned long long)(glen * 4);
       // the quad streams the pieces of its four groups: piece p of the quad lies in group m
       // where pref[m] <= p < pref[m + 1], at piece index bias[m] + p; sbq is the byte offset
@@ -514,7 +532,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         // tile slot of each record from its pair's slot word (rank r in bits 5r..5r+4; the
         // bits from the tenth field up are set, so dummies and absent ranks read 31); the
         // weights are added in their 2^-14 mV units (train mode: the float efficacies, in
-        // 2^-16 mV), the wave's delivered records counted from the ballot
+        // 2^-16 mV), each lane counting the records it delivers
 #pragma unroll
         for (int q = 0; q < PIF; ++q) {
           const uint32_t x[4] = {w[q].x, w[q].y, w[q].z, w[q].w};
@@ -522,7 +540,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
           for (int e = 0; e < 4; ++e) {
             const uint32_t sl = (uint32_t)(sw[q] >> (5u * rec_rank(x[e]))) & 31u;
             const bool in = sl != (uint32_t)kNoSlot;
-            dwave += (uint32_t)__popcll(__ballot(in));
+            dlane += in ? 1u : 0u;
             if (in) {
               const uint32_t off = __umul24(sl, npc4) + (uint32_t)aoff[q] + (rec_k(x[e]) << 2);
               atomicAdd((int32_t*)((unsigned char*)acc + off), TRAIN ? v[q][e] : rec_wq(x[e]));
@@ -552,9 +570,10 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
           }
         }
       }
-      bt = __shfl(bt_next, 0);
+      bt = bt_next;
+      cur = nxt;
     }
-    delivered = lane == 0 ? dwave : 0u;
+    delivered = dlane;
     __syncthreads();
     // the accumulators of the later steps of the window, for their light steps
     for (int w = 1; w < W; ++w) {

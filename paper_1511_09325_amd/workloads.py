@@ -88,6 +88,8 @@ SODIUM_AHP_24X24 = dict(params=grid(24, 24, 0, g_na=0.1, tau_na=100.0, na_inc=0.
                         name="24x24, LIF with calcium and sodium AHP variables, 1 s")
 IZHIKEVICH_24X24 = dict(params=grid(24, 24, 0, neuron_model=1, j_ext=1.6), steps=1000,
                         name="24x24, Izhikevich RS/FS neurons, 1 s")
+STDP_24X24 = dict(params=grid(24, 24, 0, stdp=1), steps=1000,
+                  name="24x24, LIF with pair-based STDP on the excitatory synapses, 1 s")
 #: The paper's own column recipe at its Table 1 sizes (about 1239 recurrent synapses per
 #: neuron, 991 of them local; 540 external synapses).
 PAPER_24X24 = dict(params=paper_grid(24, 24, 0), steps=1000,
