@@ -45,6 +45,7 @@ WORKLOADS = {
     "paper96": ("PAPER_96X96", 1000),
     "paper48": ("PAPER_48X48", 1000),
     "paper24": ("PAPER_24X24", 1000),
+    "stdp24": ("STDP_24X24", 1000),
 }
 
 
@@ -479,6 +480,8 @@ def plain_leg(torch, workload: str, steps, warmup: int, delivery: str = "arrival
         # arrival form: one fused launch per step gathers the step's arriving synapses and
         # updates every neuron
         kern, dom_name = tm["update"], "k_step_tile"
+        if p.get("stdp"):  # the step's launches also hold the potentiation kernel
+            dom_name = "k_step_tile + k_stdp_post"
         per_launch = (BYTES_PER_EVENT * delivered + BYTES_PER_NEURON * N * K) / K
         rec_per_launch = (RECORD_BYTES_PER_SYNAPSE * delivered + RECORD_BYTES_PER_NEURON * N * K) / K
     dom_ms = kern["ms"] / max(kern["launches"], 1)
