@@ -133,7 +133,8 @@ typedef struct {
    * step of the target's spike), and the weight is kept in [0, stdp_w_max].  A spike
    * delivers the weight it finds at arrival.  Needs the arrival form in the tiling of
    * creation, one step per gather, train_mode = 0, fewer than 2^24 neurons in at most 16000
-   * columns.  Snapshots then also hold the weights and traces. */
+   * columns and fewer than 2^35 synapse records.  Snapshots then also hold the weights and
+   * traces. */
   int32_t stdp;          /* 0: off */
   double stdp_tau_plus, stdp_tau_minus; /* ms, > 0 */
   double stdp_a_plus, stdp_a_minus;     /* mV, >= 0 */

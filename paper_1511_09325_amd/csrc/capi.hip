@@ -80,7 +80,7 @@ void region_sizes(const sim& s, int64_t records, size_t out[4]) {
                    align256((size_t)s.idxw * (size_t)s.n_idx);
   out[kRegState] = 2 * align256(sizeof(float) * N) + align256(N);
   out[kRegHist] = align256(sizeof(int32_t) * dh * C) + align256(sizeof(uint16_t) * dh * C * npc) +
-                  align256(sizeof(uint32_t) * dh * P * npc) +
+                  align256(sizeof(uint64_t) * dh * P * npc) +
                   align256(sizeof(uint16_t) * dh * P * (nd + 1) * npc);
 }
 
@@ -394,6 +394,8 @@ void build_parts(sim& s, int tx, int ty) {
 // For each tile: its columns, every (source column, part) with synapses into it, and per
 // pair the tile slot of each rank of the part.  Tiles are ordered like the columns: strips
 // of each network per XCD.
+void set_tile_bases(sim& s);
+
 void build_tiles(sim& s, int tx, int ty) {
   if (tx < 1 || ty < 1 || tx > kMaxTileSide || ty > kMaxTileSide)
     throw Fail{DPSNN_EINVAL, "tile sides must be in [1, 4]"};
@@ -401,6 +403,7 @@ void build_tiles(sim& s, int tx, int ty) {
   std::vector<int32_t> pfirst((size_t)s.n_cols + 1, 0);
   for (int32_t g = 0; g < s.n_cols; ++g) pfirst[g + 1] = pfirst[g] + s.h_np[g];
   std::vector<uint64_t> tslots;
+  std::vector<int32_t> tsrc;
   std::vector<std::vector<int32_t>> lanes(8);
   int rot = 0, maxc = 0;
   for (int n = 0; n < s.n_nets; ++n) {
@@ -421,6 +424,8 @@ void build_tiles(sim& s, int tx, int ty) {
             for (int r = 0; r < s.h_nn[g]; ++r) src.push_back(s.h_nbr[(size_t)g * kMaxNbr + r]);
           std::sort(src.begin(), src.end());
           src.erase(std::unique(src.begin(), src.end()), src.end());
+          tsrc.push_back(src.empty() ? tc[0] : src.front());
+          tsrc.push_back(src.empty() ? tc[0] : src.back());
           // the source columns of the tile are the columns whose neighbourhood meets it
           // (the stencil is symmetric); each contributes the parts that reach the tile
           std::vector<std::pair<int32_t, int32_t>> pairs;
@@ -491,6 +496,8 @@ void build_tiles(sim& s, int tx, int ty) {
   release(s, s.tile_npairs);
   release(s, s.tile_slots);
   release(s, s.tile_work);
+  release(s, s.tile_base);
+  s.tile_base = nullptr;
   const std::vector<int32_t> order = interleave(lanes);
   s.tile_x = tx;
   s.tile_y = ty;
@@ -504,8 +511,25 @@ void build_tiles(sim& s, int tx, int ty) {
   s.tile_npairs = upload(s, npairs);
   s.tile_slots = upload(s, tslots);
   s.tile_work = upload(s, std::vector<uint32_t>((size_t)s.n_tiles, 0u));
+  s.h_tile_src = tsrc;
   // when every tile has its own compute unit the order does not matter
   s.order_by_work = s.n_tiles > device_cu_count();
+  if (!s.h_colrow.empty()) set_tile_bases(s);
+}
+
+// Per tile, the first 16-byte piece of its source columns' rows (rows are stored in neuron
+// order, so the source columns lowest..highest span one range); every piece the tile reads
+// must lie within 2^32 pieces of it.
+void set_tile_bases(sim& s) {
+  std::vector<int64_t> base((size_t)s.n_tiles);
+  for (int32_t t = 0; t < s.n_tiles; ++t) {
+    const int32_t lo = s.h_tile_src[2 * (size_t)t], hi = s.h_tile_src[2 * (size_t)t + 1];
+    base[t] = s.h_colrow[lo] >> 2;
+    if ((s.h_colrow[(size_t)hi + 1] >> 2) - base[t] >= ((int64_t)1 << 32))
+      throw Fail{DPSNN_EINVAL, "the rows of one tile's source columns exceed 2^34 records"};
+  }
+  release(s, s.tile_base);
+  s.tile_base = upload(s, base);
 }
 
 int64_t tile_count(const sim& s, int tx, int ty) {
@@ -682,9 +706,6 @@ int64_t count_records(sim& s, int64_t** part_out, int64_t* plen_out) {
   dfree(s, row_len);
   *part_out = part;
   *plen_out = plen;
-  // the tile kernel addresses 16-byte pieces of the store with 32-bit indices
-  if (total / 4 >= ((int64_t)1 << 32))
-    throw Fail{DPSNN_EINVAL, "synapse store exceeds 2^34 records"};
   return total;
 }
 
@@ -720,6 +741,13 @@ void generate(sim& s) {
   if (s.cfg.train_mode) s.canon_start = degscan;  // canonical order of the weights
   else dfree(s, degscan);
   dfree(s, part);
+  // the first record of every column's rows (row_base at every npc-th neuron), for the
+  // tiles' piece bases
+  s.h_colrow.assign((size_t)s.n_cols + 1, 0);
+  HIPCHK(hipMemcpy2D(s.h_colrow.data(), sizeof(int64_t), s.row_base,
+                     sizeof(int64_t) * (size_t)s.npc, sizeof(int64_t), (size_t)s.n_cols + 1,
+                     hipMemcpyDeviceToHost));
+  set_tile_bases(s);
 }
 
 void ensure_ring(sim& s) {
@@ -777,6 +805,8 @@ void save_into_ckpt(sim& s, size_t m);
 // per target, its scan, then every record written at its target's next free place).
 void setup_stdp(sim& s) {
   const size_t N = (size_t)s.n_neurons;
+  if (s.n_syn_padded + 4 > ((int64_t)1 << 35))
+    throw Fail{DPSNN_EINVAL, "STDP needs fewer than 2^35 synapse records"};
   s.sp_y = (float*)dalloc(s, sizeof(float) * N);
   s.sp_x = (float*)dalloc(s, sizeof(float) * (size_t)s.dh * N);
   HIPCHK(hipMemsetAsync(s.sp_y, 0, sizeof(float) * N, s.stream));
@@ -968,7 +998,7 @@ int create_impl(const sim_config_t* cfg, const sim_buffers_t* bufs, void* hip_st
     if (s->model == kModelLifNa) s->na = (float*)dalloc(*s, sizeof(float) * N);
     s->hist_cnt = (int32_t*)carve(*s, kRegHist, sizeof(int32_t) * (size_t)s->dh * s->n_cols);
     s->hist_ids = (uint16_t*)carve(*s, kRegHist, sizeof(uint16_t) * (size_t)s->dh * s->n_cols * s->npc);
-    s->hist_st = (uint32_t*)carve(*s, kRegHist, sizeof(uint32_t) * (size_t)s->dh * s->n_parts * s->npc);
+    s->hist_st = (uint64_t*)carve(*s, kRegHist, sizeof(uint64_t) * (size_t)s->dh * s->n_parts * s->npc);
     s->hist_go = (uint16_t*)carve(*s, kRegHist, sizeof(uint16_t) * (size_t)s->dh * s->n_parts * (s->nd + 1) * s->npc);
     s->net_cnt = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * kCounters * (size_t)s->n_nets);
     s->flags = (int32_t*)dalloc(*s, sizeof(int32_t) * 4);

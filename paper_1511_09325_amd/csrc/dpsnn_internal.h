@@ -39,16 +39,20 @@
 //                                     in the native tiling; a part may reach several tiles
 //                                     otherwise)
 //     tile_net    int32 [tiles]       the tile's network
+//     tile_base   int64 [tiles]       the first 16-byte piece of the rows of the tile's source
+//                                     columns: the tile kernel addresses pieces relative to
+//                                     it in 32 bits (a tile's sources lie within a few grid
+//                                     rows of columns, far less than 2^32 pieces)
 //     tile_slots  uint64[tiles][128]  for each pair and each rank r of its part, the tile
 //                                     slot of its target column in bits 5r..5r+4 (31: not
 //                                     in the tile or not in the part); bits 45-63 are set
 //   spike history (shared by both delivery strategies)
 //     hist_cnt  int32 [DH][C]       spikes of column g at step t, in slot t % DH
 //     hist_ids  uint16[DH][C][npc]  their local indices, ascending
-//     hist_st   uint32 [DH][P][npc] per part (P = parts of all columns, part q of column g
+//     hist_st   uint64 [DH][P][npc] per part (P = parts of all columns, part q of column g
 //                                   is col_pfirst[g] + q) and spike position: the start of
 //                                   the spiking neuron's part in 16-byte pieces (parts start
-//                                   on 16-byte boundaries; fewer than 2^32 pieces)
+//                                   on 16-byte boundaries)
 //     hist_go   uint16[DH][P][nd+1][npc]  its group offsets (copied from the row index when
 //                                   the neuron spiked, so that the readers of one source
 //                                   column's spikes load them contiguously)
@@ -184,6 +188,7 @@ struct StepArgs {
   const int32_t* tile_ncols;
   const int2* tile_pinfo;
   const int32_t* tile_net;
+  const int64_t* tile_base;   // [n_tiles] first piece of the tile's source rows
   const int32_t* tile_npairs;
   const uint64_t* tile_slots;
   // synapses
@@ -199,7 +204,7 @@ struct StepArgs {
   uint8_t* ref;
   int32_t* hist_cnt;
   uint16_t* hist_ids;
-  uint32_t* hist_st;
+  uint64_t* hist_st;
   uint16_t* hist_go;
   // arrival form: steps gathered per window, accumulators of later steps, last gathering
   // step, finished-workgroup counter
@@ -248,7 +253,7 @@ __device__ __forceinline__ void write_entries(const StepArgs& a, int32_t g, int3
   for (int p = 0; p < np; ++p) {
     const uint8_t* ent = idx_entry(a, g, k, p);
     const int64_t pid = (int64_t)slot * a.n_parts + a.col_pfirst[g] + p;
-    a.hist_st[pid * a.npc + pos] = (uint32_t)(ent_start(ent) >> 2);
+    a.hist_st[pid * a.npc + pos] = (uint64_t)(ent_start(ent) >> 2);
     const uint16_t* go = ent_goff(ent);
     uint16_t* out = a.hist_go + pid * (int64_t)(a.nd + 1) * a.npc + pos;
     for (int dd = 0; dd <= a.nd; ++dd) out[(int64_t)dd * a.npc] = go[dd];
@@ -324,7 +329,7 @@ struct sim {
   int32_t model = dpsnn::kModelLif;  // kModel* of the step kernels
   int32_t* hist_cnt = nullptr;
   uint16_t* hist_ids = nullptr;
-  uint32_t* hist_st = nullptr;
+  uint64_t* hist_st = nullptr;
   uint16_t* hist_go = nullptr;
   int32_t gk = 1;                  // steps gathered per window (arrival form)
   int32_t gather_req = 0;          // requested gather_steps (0: automatic)
@@ -343,6 +348,9 @@ struct sim {
   int32_t *tile_order = nullptr, *tile_cinfo = nullptr, *tile_ncols = nullptr,
           *tile_pinfo = nullptr, *tile_net = nullptr, *tile_npairs = nullptr;
   uint64_t* tile_slots = nullptr;
+  int64_t* tile_base = nullptr;    // [n_tiles] first piece of each tile's source rows
+  std::vector<int32_t> h_tile_src;  // [n_tiles][2] lowest and highest source column of a tile
+  std::vector<int64_t> h_colrow;    // [C + 1] first record of each column's rows (after generation)
   uint32_t* tile_work = nullptr;   // [n_tiles] records read per tile at the last gathering step
   int32_t order_by_work = 0;       // more tiles than compute units: order them by work
   // raster

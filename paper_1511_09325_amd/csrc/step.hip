@@ -369,6 +369,13 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
     const int32_t tile = a.tile_order[b];
     if (tile < 0) continue;
     const int T = a.tile_ncols[tile];
+    // the tile's pieces, addressed relative to the first piece of its source rows
+    const int64_t tbase = a.tile_base[tile];
+    const uint32_t* syn_t = a.syn + 4 * tbase;
+    const int32_t* wfx_t = TRAIN ? a.wfx + 4 * tbase : nullptr;
+    uint32_t* syn_rw_t = PLAST ? a.syn_rw + 4 * tbase : nullptr;
+    (void)wfx_t;
+    (void)syn_rw_t;
     const int ns = a.tile_npairs[tile];
     if (tid < kMaxTileCols) {
       const int4 ci = a.tile_cinfo[tile * kMaxTileCols + tid];
@@ -467,7 +474,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
         L.gsb = (d - ag) * TN * 4;
         L.g0 = go[0];
         L.g1 = go[npc];
-        L.st = a.hist_st[pid * npc + pos];
+        L.st = (uint32_t)(a.hist_st[pid * npc + pos] - (uint64_t)tbase);
       }
       return L;
     };
@@ -525,8 +532,8 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
           if (valid) {
             const uint64_t piece = (uint64_t)(b + (uint32_t)p);
             pc[q] = piece;
-            w[q] = *(const uint4*)(a.syn + 4 * piece);
-            if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(a.wfx + 4 * piece);
+            w[q] = *(const uint4*)(syn_t + 4 * piece);
+            if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(wfx_t + 4 * piece);
           }
         }
         // tile slot of each record from its pair's slot word (rank r in bits 5r..5r+4; the
@@ -566,7 +573,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
                 }
               }
             }
-            if (changed) *(uint4*)(a.syn_rw + 4 * pc[q]) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
+            if (changed) *(uint4*)(syn_rw_t + 4 * pc[q]) = make_uint4(nw[0], nw[1], nw[2], nw[3]);
           }
         }
       }
@@ -736,7 +743,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
 #pragma unroll
       for (int q = 0; q < kIdxWords; ++q) buf[q] = ent[q < nw ? q : nw - 1];
       const int64_t pid = (int64_t)slot_u * a.n_parts + s_cpf[col] + p;
-      a.hist_st[pid * npc + pos] = (uint32_t)(*(const int64_t*)&buf[0] >> 2);
+      a.hist_st[pid * npc + pos] = (uint64_t)(*(const int64_t*)&buf[0] >> 2);
       const uint16_t* go = (const uint16_t*)&buf[0] + 4;
       uint16_t* out = a.hist_go + pid * (int64_t)(a.nd + 1) * npc + pos;
 #pragma unroll
@@ -1039,6 +1046,7 @@ StepArgs make_step_args(const sim& s) {
   a.tile_ncols = s.tile_ncols;
   a.tile_pinfo = (const int2*)s.tile_pinfo;
   a.tile_net = s.tile_net;
+  a.tile_base = s.tile_base;
   a.tile_npairs = s.tile_npairs;
   a.col_np = s.col_np;
   a.col_part = s.col_part;
