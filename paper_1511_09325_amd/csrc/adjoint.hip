@@ -558,16 +558,19 @@ __global__ __launch_bounds__(64) void k_canon_map(StepArgs a, const int64_t* can
 }
 
 // The same maps from the stored permutation: one wave per row, its padded records in order
-// (the parts of a row are contiguous); rel 0xffff marks padding (rows are shorter than
+// (the parts of a row are contiguous, and the rows of one column follow each other; the last
+// row of a column ends at the column's end); rel 0xffff marks padding (rows are shorter than
 // 0xffff synapses: checked when train mode is set up).
 __global__ __launch_bounds__(256) void k_canon_apply(const int64_t* row_base,
+                                                     const int64_t* col_end, int32_t npc,
                                                      const int64_t* canon_start,
                                                      const uint16_t* rel, int64_t n_rows,
                                                      int mode, const float* src, float* dst) {
   const int lane = threadIdx.x & 63;
   for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n_rows;
        i += (int64_t)gridDim.x * 4) {
-    const int64_t r0 = row_base[i], r1 = row_base[i + 1], c0 = canon_start[i];
+    const int64_t r0 = row_base[i], c0 = canon_start[i];
+    const int64_t r1 = (i + 1) % npc == 0 ? col_end[i / npc] : row_base[i + 1];
     for (int64_t q = r0 + lane; q < r1; q += 64) {
       const uint32_t o = rel[q];
       if (o == 0xffffu) {
@@ -732,7 +735,8 @@ hipError_t launch_reduce_parts(const sim& s, double* out) {
 hipError_t launch_canon_map(const sim& s, int mode, const float* src, float* dst) {
   if (s.canon_rel) {
     hipLaunchKernelGGL(k_canon_apply, dim3(grid_of(s.n_neurons, 4)), dim3(256), 0, s.stream,
-                       s.row_base, s.canon_start, s.canon_rel, s.n_neurons, mode, src, dst);
+                       s.row_base, s.col_end, s.npc, s.canon_start, s.canon_rel, s.n_neurons,
+                       mode, src, dst);
     return hipGetLastError();
   }
   const StepArgs a = make_step_args(s);

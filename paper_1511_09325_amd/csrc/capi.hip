@@ -403,7 +403,7 @@ void build_tiles(sim& s, int tx, int ty) {
   std::vector<int32_t> pfirst((size_t)s.n_cols + 1, 0);
   for (int32_t g = 0; g < s.n_cols; ++g) pfirst[g + 1] = pfirst[g] + s.h_np[g];
   std::vector<uint64_t> tslots;
-  std::vector<int32_t> tsrc;
+  std::vector<int32_t> tsrc, tsrc_off(1, 0);
   std::vector<std::vector<int32_t>> lanes(8);
   int rot = 0, maxc = 0;
   for (int n = 0; n < s.n_nets; ++n) {
@@ -424,8 +424,8 @@ void build_tiles(sim& s, int tx, int ty) {
             for (int r = 0; r < s.h_nn[g]; ++r) src.push_back(s.h_nbr[(size_t)g * kMaxNbr + r]);
           std::sort(src.begin(), src.end());
           src.erase(std::unique(src.begin(), src.end()), src.end());
-          tsrc.push_back(src.empty() ? tc[0] : src.front());
-          tsrc.push_back(src.empty() ? tc[0] : src.back());
+          tsrc.insert(tsrc.end(), src.begin(), src.end());
+          tsrc_off.push_back((int32_t)tsrc.size());
           // the source columns of the tile are the columns whose neighbourhood meets it
           // (the stencil is symmetric); each contributes the parts that reach the tile
           std::vector<std::pair<int32_t, int32_t>> pairs;
@@ -512,24 +512,66 @@ void build_tiles(sim& s, int tx, int ty) {
   s.tile_slots = upload(s, tslots);
   s.tile_work = upload(s, std::vector<uint32_t>((size_t)s.n_tiles, 0u));
   s.h_tile_src = tsrc;
+  s.h_tile_src_off = tsrc_off;
   // when every tile has its own compute unit the order does not matter
   s.order_by_work = s.n_tiles > device_cu_count();
-  if (!s.h_colrow.empty()) set_tile_bases(s);
+  if (!s.h_colstart.empty()) set_tile_bases(s);
 }
 
-// Per tile, the first 16-byte piece of its source columns' rows (rows are stored in neuron
-// order, so the source columns lowest..highest span one range); every piece the tile reads
-// must lie within 2^32 pieces of it.
+// Per tile, the first 16-byte piece of its source columns' rows; every piece the tile reads
+// must lie within 2^32 pieces of it (the folded row order keeps a tile's sources within a
+// few grid rows of columns).
 void set_tile_bases(sim& s) {
   std::vector<int64_t> base((size_t)s.n_tiles);
   for (int32_t t = 0; t < s.n_tiles; ++t) {
-    const int32_t lo = s.h_tile_src[2 * (size_t)t], hi = s.h_tile_src[2 * (size_t)t + 1];
-    base[t] = s.h_colrow[lo] >> 2;
-    if ((s.h_colrow[(size_t)hi + 1] >> 2) - base[t] >= ((int64_t)1 << 32))
-      throw Fail{DPSNN_EINVAL, "the rows of one tile's source columns exceed 2^34 records"};
+    int64_t lo = INT64_MAX, hi = 0;
+    for (int32_t q = s.h_tile_src_off[t]; q < s.h_tile_src_off[t + 1]; ++q) {
+      lo = std::min(lo, s.h_colstart[s.h_tile_src[q]]);
+      hi = std::max(hi, s.h_colend[s.h_tile_src[q]]);
+    }
+    if (lo > hi) lo = hi = 0;
+    base[t] = lo >> 2;
+    if ((hi >> 2) - base[t] >= ((int64_t)1 << 32))
+      throw Fail{DPSNN_EINVAL, "the rows of one tile's source columns span more than 2^34 "
+                               "records"};
   }
   release(s, s.tile_base);
   s.tile_base = upload(s, base);
+}
+
+// After the count pass: move the columns' rows into folded row order (per network, grid rows
+// 0, R-1, 1, R-2, ...), so that the rows of stencil neighbours, across the wrap of the torus
+// too, lie near each other; record every column's range for the tiles' piece bases.
+void fold_rows(sim& s) {
+  const int32_t C = s.n_cols;
+  std::vector<int64_t> old_start((size_t)C + 1);
+  HIPCHK(hipMemcpy2D(old_start.data(), sizeof(int64_t), s.row_base,
+                     sizeof(int64_t) * (size_t)s.npc, sizeof(int64_t), (size_t)C + 1,
+                     hipMemcpyDeviceToHost));
+  std::vector<int64_t> new_start((size_t)C);
+  int64_t at = 0;
+  for (int n = 0; n < s.n_nets; ++n) {
+    const int rows = s.nets[n].rows, cols = s.nets[n].cols;
+    for (int pos = 0; pos < rows; ++pos) {
+      const int y = (pos & 1) ? rows - 1 - pos / 2 : pos / 2;
+      for (int x = 0; x < cols; ++x) {
+        const int32_t g = s.net_col0[n] + y * cols + x;
+        new_start[g] = at;
+        at += old_start[(size_t)g + 1] - old_start[g];
+      }
+    }
+  }
+  s.h_colstart = new_start;
+  s.h_colend.resize((size_t)C);
+  for (int32_t g = 0; g < C; ++g) s.h_colend[g] = new_start[g] + (old_start[(size_t)g + 1] - old_start[g]);
+  int64_t* d_old = upload(s, old_start);
+  int64_t* d_new = upload(s, new_start);
+  HIPCHK(launch_fold_rows(s, d_old, d_new));
+  HIPCHK(hipStreamSynchronize(s.stream));
+  dfree(s, d_new);
+  dfree(s, d_old);
+  release(s, s.col_end);
+  s.col_end = upload(s, s.h_colend);
 }
 
 int64_t tile_count(const sim& s, int tx, int ty) {
@@ -700,6 +742,7 @@ int64_t count_records(sim& s, int64_t** part_out, int64_t* plen_out) {
   int64_t* part = (int64_t*)dalloc(s, sizeof(int64_t) * (size_t)plen);
   HIPCHK(launch_gen_count(s, 0, N, row_len));
   HIPCHK(launch_scan_rows(s, row_len, N, s.row_base, part, plen));
+  fold_rows(s);
   int64_t total = 0;
   HIPCHK(hipMemcpyAsync(&total, s.row_base + N, sizeof(int64_t), hipMemcpyDeviceToHost, s.stream));
   HIPCHK(hipStreamSynchronize(s.stream));
@@ -741,12 +784,6 @@ void generate(sim& s) {
   if (s.cfg.train_mode) s.canon_start = degscan;  // canonical order of the weights
   else dfree(s, degscan);
   dfree(s, part);
-  // the first record of every column's rows (row_base at every npc-th neuron), for the
-  // tiles' piece bases
-  s.h_colrow.assign((size_t)s.n_cols + 1, 0);
-  HIPCHK(hipMemcpy2D(s.h_colrow.data(), sizeof(int64_t), s.row_base,
-                     sizeof(int64_t) * (size_t)s.npc, sizeof(int64_t), (size_t)s.n_cols + 1,
-                     hipMemcpyDeviceToHost));
   set_tile_bases(s);
 }
 
@@ -1414,10 +1451,16 @@ int sim_read_synapses(sim_t* s, int32_t net, int64_t i0, int64_t i1, int64_t* ro
     if (total == 0) return DPSNN_OK;
     if (!tgt || !dly || !wq) throw Fail{DPSNN_EINVAL, "NULL output"};
     // export the padded rows, then drop the padding (delay 0) on the host
+    // padded row lengths: the rows of one column follow each other, the last ends at the
+    // column's end (columns are stored in folded row order)
     std::vector<int64_t> rb(nr + 1);
     HIPCHK(hipMemcpy(rb.data(), s->row_base + g0, sizeof(int64_t) * rb.size(), hipMemcpyDeviceToHost));
-    std::vector<int64_t> poff(nr + 1);
-    for (size_t q = 0; q <= nr; ++q) poff[q] = rb[q] - rb[0];
+    std::vector<int64_t> poff(nr + 1, 0);
+    for (size_t q = 0; q < nr; ++q) {
+      const int64_t i = g0 + (int64_t)q;
+      const int64_t end = (i + 1) % s->npc == 0 ? s->h_colend[(size_t)(i / s->npc)] : rb[q + 1];
+      poff[q + 1] = poff[q] + (end - rb[q]);
+    }
     const int64_t ptotal = poff[nr];
     int32_t* dt = (int32_t*)dalloc(*s, sizeof(int32_t) * (size_t)ptotal);
     uint8_t* dd = (uint8_t*)dalloc(*s, (size_t)ptotal);

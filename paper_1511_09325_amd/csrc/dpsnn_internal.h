@@ -3,7 +3,11 @@
 // Device data layout (all networks of a simulation concatenated column by column; the
 // global neuron index is g*npc + k for global column g and local index k):
 //
-//   synapse store: the canonical order of a row is (delay, target); the device keeps each
+//   synapse store: rows are stored column by column, the columns of a network in folded
+//   row order (grid rows 0, R-1, 1, R-2, 2, ...; inside a row by x; inside a column by
+//   neuron), so that the rows of stencil neighbours -- across the torus' wrap included --
+//   lie within a few grid rows of each other (row_base[i] gives any row's start).
+//   The canonical order of a row is (delay, target); the device keeps each
 //   row split into parts, one per target tile of the tiling chosen at creation (the
 //   "native" tiling): part p of a source column holds the synapses whose target column
 //   lies in the p-th distinct tile touched by the column's stencil (3x3, or up to 7x7 with
@@ -349,8 +353,11 @@ struct sim {
           *tile_pinfo = nullptr, *tile_net = nullptr, *tile_npairs = nullptr;
   uint64_t* tile_slots = nullptr;
   int64_t* tile_base = nullptr;    // [n_tiles] first piece of each tile's source rows
-  std::vector<int32_t> h_tile_src;  // [n_tiles][2] lowest and highest source column of a tile
-  std::vector<int64_t> h_colrow;    // [C + 1] first record of each column's rows (after generation)
+  std::vector<int32_t> h_tile_src;  // source columns of every tile, from h_tile_src_off[t]
+  std::vector<int32_t> h_tile_src_off;  // [n_tiles + 1]
+  std::vector<int64_t> h_colstart;  // [C] first record of each column's rows (after the count
+  std::vector<int64_t> h_colend;    // [C]   pass) and one past its last
+  int64_t* col_end = nullptr;       // [C] device copy of h_colend
   uint32_t* tile_work = nullptr;   // [n_tiles] records read per tile at the last gathering step
   int32_t order_by_work = 0;       // more tiles than compute units: order them by work
   // raster
@@ -416,6 +423,7 @@ hipError_t launch_gen_count(const sim& s, int64_t row0, int64_t rows, int32_t* r
 hipError_t launch_gen_fill(const sim& s, int64_t row0, int64_t rows);
 hipError_t launch_scan_rows(const sim& s, const int32_t* row_len, int64_t n, int64_t* out,
                             int64_t* scratch, int64_t scratch_len);
+hipError_t launch_fold_rows(const sim& s, const int64_t* old_start, const int64_t* new_start);
 hipError_t launch_init_state(const sim& s);
 // part: -1 the whole step, 0 the update (fused with the gather in the arrival form),
 // 1 the push delivery

@@ -386,6 +386,26 @@ hipError_t launch_gen_fill(const sim& s, int64_t row0, int64_t rows) {
 }
 
 // out[0..n] = exclusive prefix of in[0..n), out[n] = total.
+// Row starts moved column by column: row i of column g starts at new_start[g] plus its
+// offset inside the column (its scanned start minus the column's first).
+__global__ __launch_bounds__(256) void k_fold_rows(int64_t* row_base, int64_t n, int32_t npc,
+                                                   const int64_t* old_start,
+                                                   const int64_t* new_start) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int64_t g = i / npc;
+    row_base[i] = new_start[g] + (row_base[i] - old_start[g]);
+  }
+}
+
+hipError_t launch_fold_rows(const sim& s, const int64_t* old_start, const int64_t* new_start) {
+  int64_t blocks = (s.n_neurons + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)blocks), dim3(256), 0, s.stream, s.row_base,
+                     s.n_neurons, s.npc, old_start, new_start);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan_rows(const sim& s, const int32_t* in, int64_t n, int64_t* out,
                             int64_t* part, int64_t part_len) {
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
