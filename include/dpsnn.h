@@ -391,6 +391,20 @@ int sim_state_digest(sim_t* sim, uint64_t* digest);
 int sim_autotune(sim_t* sim, int32_t window, const char* cache_path, sim_launch_t* best,
                  double* best_ms_per_step);
 
+/* Library runtime (not in the paper): choose the arrival form's native tiling (the tile shape
+ * the synapse store is split for, fixed at creation) by measurement.  For every shape of
+ * 3x3, 3x2, 2x3, 2x2, 2x1, 1x2 and 1x1 that the configuration admits (that fits the LDS,
+ * the stencil's part limits and the device memory), one at a time: the
+ * simulation is created with that native tiling (cfg's tile fields and raster options are
+ * replaced, everything else kept), steps `settle` untimed steps, then `window` steps timed
+ * with HIP events on its stream, and is destroyed.  Every shape must reach the same state
+ * digest (DPSNN_ESTATE otherwise).  tile_x, tile_y receive the fastest shape and
+ * ms_per_step (nullable) its time per step.  Needs the device memory of one simulation at
+ * a time; synchronises.  Errors (NULL pointers, settle < 0, window < 1, no admissible shape)
+ * are reported by sim_last_error(NULL). */
+int sim_tune_tiling(const sim_config_t* cfg, int32_t settle, int32_t window, int32_t* tile_x,
+                    int32_t* tile_y, double* ms_per_step);
+
 /* Paper section 3 (time per synaptic event, measured here per kernel): per-kernel device
  * time of the last sim_step call, measured with HIP events recorded on
  * the simulation's stream around every kernel launch while timing is on.  ms[0..2]: total

@@ -22,7 +22,7 @@ EXPORTS = [
     "sim_read_synapses", "sim_save", "sim_restore", "sim_set_weights", "sim_get_weights",
     "sim_set_params", "sim_get_launch", "sim_set_launch", "sim_set_timing", "sim_get_timing",
     "sim_state_digest", "sim_autotune", "sim_rewind", "sim_column_rates",
-    "sim_read_spikes_static", "sim_query_sizes", "sim_backward_rates",
+    "sim_read_spikes_static", "sim_query_sizes", "sim_backward_rates", "sim_tune_tiling",
 ]
 
 
@@ -144,6 +144,8 @@ def lib():
         "sim_get_timing": (C.c_int, [vp, P(C.c_double), C.c_int32]),
         "sim_state_digest": (C.c_int, [vp, P(C.c_uint64)]),
         "sim_autotune": (C.c_int, [vp, C.c_int32, C.c_char_p, P(SimLaunch), P(C.c_double)]),
+        "sim_tune_tiling": (C.c_int, [P(SimConfig), C.c_int32, C.c_int32, P(C.c_int32),
+                                      P(C.c_int32), P(C.c_double)]),
         "sim_rewind": (C.c_int, [vp]),
         "sim_column_rates": (C.c_int, [vp, vp]),
     }

@@ -175,3 +175,96 @@ extern "C" int sim_autotune(sim_t* s, int32_t window, const char* cache_path, si
   if (best_ms_per_step) *best_ms_per_step = per_step;
   return DPSNN_OK;
 }
+
+// Creation-time choice of the native tiling: each admissible shape is built, settled, timed
+// and destroyed in turn (one simulation's device memory at a time); all must agree bit for
+// bit (state digest).
+extern "C" int sim_tune_tiling(const sim_config_t* cfg, int32_t settle, int32_t window,
+                               int32_t* tile_x, int32_t* tile_y, double* ms_per_step) {
+  if (!cfg || !tile_x || !tile_y) {
+    dpsnn::set_create_error("cfg, tile_x and tile_y are required");
+    return DPSNN_EINVAL;
+  }
+  if (settle < 0 || window < 1) {
+    dpsnn::set_create_error("settle must be >= 0 and window >= 1");
+    return DPSNN_EINVAL;
+  }
+  static const int shapes[][2] = {{3, 3}, {3, 2}, {2, 3}, {2, 2}, {2, 1}, {1, 2}, {1, 1}};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    dpsnn::set_create_error("hipEventCreate failed");
+    return DPSNN_EHIP;
+  }
+  bool have = false;
+  uint64_t ref = 0;
+  double best_ms = 0;
+  int bx = 0, by = 0, rc = DPSNN_OK;
+  std::string last_refusal = "no tile shape is admissible for this configuration";
+  for (const auto& sh : shapes) {
+    sim_config_t c = *cfg;
+    c.tile_x = sh[0];
+    c.tile_y = sh[1];
+    c.record_steps = 0;
+    c.raster_capacity = 0;
+    sim_t* s = nullptr;
+    const int crc = sim_create(&c, nullptr, nullptr, &s);
+    if (crc == DPSNN_EINVAL || crc == DPSNN_ENOMEM) {
+      // the shape does not fit the LDS or the stencil, or its store does not fit the device
+      last_refusal = sim_last_error(nullptr);
+      (void)hipGetLastError();
+      continue;
+    }
+    if (crc != DPSNN_OK) {
+      rc = crc;
+      break;
+    }
+    float ms = 0;
+    uint64_t d = 0;
+    int src = sim_step(s, settle);
+    if (src == DPSNN_OK) src = sim_sync(s);
+    if (src == DPSNN_OK) {
+      (void)hipEventRecord(e0, s->stream);
+      src = sim_step(s, window);
+      (void)hipEventRecord(e1, s->stream);
+    }
+    if (src == DPSNN_OK) src = sim_sync(s);
+    if (src == DPSNN_OK) {
+      (void)hipEventSynchronize(e1);
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      src = sim_state_digest(s, &d);
+    }
+    if (src != DPSNN_OK) dpsnn::set_create_error(std::string("tiling ") + std::to_string(sh[0]) +
+                                                 "x" + std::to_string(sh[1]) + ": " +
+                                                 sim_last_error(s));
+    sim_destroy(s);
+    if (src != DPSNN_OK) {
+      rc = src;
+      break;
+    }
+    if (have && d != ref) {
+      dpsnn::set_create_error(std::string("tiling ") + std::to_string(sh[0]) + "x" +
+                              std::to_string(sh[1]) + " reached a different state");
+      rc = DPSNN_ESTATE;
+      break;
+    }
+    ref = d;
+    const double per = (double)ms / window;
+    if (!have || per < best_ms) {
+      best_ms = per;
+      bx = sh[0];
+      by = sh[1];
+    }
+    have = true;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != DPSNN_OK) return rc;
+  if (!have) {
+    dpsnn::set_create_error(last_refusal);
+    return DPSNN_EINVAL;
+  }
+  *tile_x = bx;
+  *tile_y = by;
+  if (ms_per_step) *ms_per_step = best_ms;
+  return DPSNN_OK;
+}

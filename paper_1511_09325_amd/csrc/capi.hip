@@ -1361,6 +1361,14 @@ const char* sim_last_error(const sim_t* s) {
   return s ? s->err.c_str() : g_create_error.c_str();
 }
 
+}  // extern "C"
+
+namespace dpsnn {
+void set_create_error(const std::string& msg) { g_create_error = msg; }
+}  // namespace dpsnn
+
+extern "C" {
+
 int sim_get_info(const sim_t* s, sim_info_t* info) {
   if (!s || !info) return DPSNN_EINVAL;
   info->n_nets = s->n_nets;

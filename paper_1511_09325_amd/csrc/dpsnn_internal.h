@@ -466,5 +466,7 @@ hipError_t sort_rev_temp_bytes(int64_t chunk, int32_t segs, size_t* bytes);
 int64_t scan_scratch_len(int64_t n);
 
 StepArgs make_step_args(const sim& s);
+// the message sim_last_error(NULL) returns (calls that have no simulation handle)
+void set_create_error(const std::string& msg);
 
 }  // namespace dpsnn

@@ -58,6 +58,17 @@ def make_config(params: dict | list[dict], *, delivery: int = L.DELIVERY_AUTO, b
     return c, nets
 
 
+def tune_tiling(params, settle: int = 50, window: int = 100, **options):
+    """sim_tune_tiling: the native tiling (tile_x, tile_y) measured fastest for this
+    configuration, and its time per step in ms.  Builds one simulation per admissible shape in
+    turn (the device memory of one at a time)."""
+    cfg, _nets = make_config(params, **options)
+    tx, ty, ms = C.c_int32(), C.c_int32(), C.c_double()
+    L.check(L.lib().sim_tune_tiling(C.byref(cfg), int(settle), int(window), C.byref(tx),
+                                    C.byref(ty), C.byref(ms)), None)
+    return (tx.value, ty.value), ms.value
+
+
 def query_sizes(params, **options) -> dict:
     """sim_query_sizes: the device memory of the four caller-ownable regions (bytes) and the
     state region's offsets, for the configuration make_config(params, **options) builds."""

@@ -141,6 +141,16 @@ def test_stdp_excludes_train_mode_and_push(lib, opts, msg):
     assert msg in lib.sim_last_error(None)
 
 
+def test_tune_tiling_refuses_bad_arguments_before_device_work(lib):
+    cfg, nets = make_config(W.grid(2, 2))
+    tx, ty, ms = C.c_int32(), C.c_int32(), C.c_double()
+    assert lib.sim_tune_tiling(None, 0, 10, C.byref(tx), C.byref(ty), None) == L.EINVAL
+    assert lib.sim_tune_tiling(C.byref(cfg), 0, 10, None, C.byref(ty), None) == L.EINVAL
+    assert lib.sim_tune_tiling(C.byref(cfg), -1, 10, C.byref(tx), C.byref(ty), None) == L.EINVAL
+    assert lib.sim_tune_tiling(C.byref(cfg), 0, 0, C.byref(tx), C.byref(ty), C.byref(ms)) == L.EINVAL
+    assert b"window" in lib.sim_last_error(None)
+
+
 def test_null_handles(lib):
     assert lib.sim_step(None, 1) == L.EINVAL
     assert lib.sim_sync(None) == L.EINVAL

@@ -182,3 +182,21 @@ def test_read_spikes_through_the_abi(nets):
     assert off[0] == 0 and off[-1] == len(want)
     for u in range(t0, t1):
         assert np.array_equal(ids[off[u - t0]:off[u - t0 + 1]], ref.spikes(u)), u
+
+
+def test_tune_tiling_picks_an_admissible_shape_that_stays_bit_exact():
+    """sim_tune_tiling builds the network once per admissible native tiling; the shapes must
+    agree bit for bit (the call checks their digests), and the one it returns runs the
+    oracle's raster."""
+    from paper_1511_09325_amd import sim as S
+    p = W.tiny(4, 5, npc=36, seed=21)
+    (tx, ty), ms = S.tune_tiling(p, settle=20, window=30)
+    assert (tx, ty) in {(3, 3), (3, 2), (2, 3), (2, 2), (2, 1), (1, 2), (1, 1)} and ms > 0
+    T = 80
+    sim = Simulation(p, record_steps=T, tile=(tx, ty))
+    assert sim.get_launch()["tile"] == (tx, ty)
+    sim.step(T)
+    ref = oracle.Sim(p)
+    ref.step(T)
+    got = sim.read_spikes(0, 0, T)
+    assert all(np.array_equal(got[u], ref.spikes(u)) for u in range(T))
