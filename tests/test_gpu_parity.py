@@ -137,7 +137,10 @@ def test_save_restore_and_switching_delivery():
     dict(npc=1, n_exc=1, rows=1, cols=1),                 # one neuron, no synapse
     dict(n_exc=0),                                        # all inhibitory
     dict(d_min=1, d_max=32),                              # the longest ring
-], ids=["silent", "one-delay", "tref0", "lambda20", "one-neuron", "all-inh", "dmax32"])
+    dict(npc=4096, n_exc=3277, rows=1, cols=1),           # the largest column (12-bit index);
+                                                          # on a 1x1 torus every pair connects
+], ids=["silent", "one-delay", "tref0", "lambda20", "one-neuron", "all-inh", "dmax32",
+        "npc4096"])
 @pytest.mark.parametrize("delivery", [DELIVERY_ARRIVAL, DELIVERY_PUSH], ids=["arrival", "push"])
 def test_edge_cases(over, delivery):
     p = W.tiny(2, 2, npc=40, seed=7)
