@@ -890,6 +890,9 @@ void setup_train(sim& s) {
     throw Fail{DPSNN_EINVAL, "train mode needs rows of fewer than 65535 candidate synapses"};
   const size_t sp = (size_t)s.n_syn_padded + 4;
   const size_t N = (size_t)s.n_neurons;
+  // the train-mode step kernel addresses 16-byte pieces from the store's start in 32 bits
+  if ((s.n_syn_padded + 4) / 4 >= ((int64_t)1 << 32))
+    throw Fail{DPSNN_EINVAL, "train mode needs a store of fewer than 2^34 synapse records"};
   s.wf32 = (float*)dalloc(s, sizeof(float) * sp);
   s.wfx = (int32_t*)dalloc(s, sizeof(int32_t) * sp);
   s.gw = (float*)dalloc(s, sizeof(float) * sp);

@@ -369,12 +369,11 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
     const int32_t tile = a.tile_order[b];
     if (tile < 0) continue;
     const int T = a.tile_ncols[tile];
-    // the tile's pieces, addressed relative to the first piece of its source rows
-    const int64_t tbase = a.tile_base[tile];
+    // the tile's pieces, addressed relative to the first piece of its source rows (train
+    // mode, whose stores stay below 2^32 pieces, addresses them from the store's start)
+    const int64_t tbase = TRAIN ? 0 : a.tile_base[tile];
     const uint32_t* syn_t = a.syn + 4 * tbase;
-    const int32_t* wfx_t = TRAIN ? a.wfx + 4 * tbase : nullptr;
     uint32_t* syn_rw_t = PLAST ? a.syn_rw + 4 * tbase : nullptr;
-    (void)wfx_t;
     (void)syn_rw_t;
     const int ns = a.tile_npairs[tile];
     if (tid < kMaxTileCols) {
@@ -533,7 +532,7 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
             const uint64_t piece = (uint64_t)(b + (uint32_t)p);
             pc[q] = piece;
             w[q] = *(const uint4*)(syn_t + 4 * piece);
-            if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(wfx_t + 4 * piece);
+            if (TRAIN) *(int4*)&v[q][0] = *(const int4*)(a.wfx + 4 * piece);
           }
         }
         // tile slot of each record from its pair's slot word (rank r in bits 5r..5r+4; the
