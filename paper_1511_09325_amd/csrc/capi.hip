@@ -1191,6 +1191,15 @@ int sim_step(sim_t* s, int64_t n_steps) {
   if (!s) return DPSNN_EINVAL;
   if (n_steps < 0) { s->err = "n_steps < 0"; return DPSNN_EINVAL; }
   if (s->sticky) { s->err = "simulation is in a failed state"; return DPSNN_ESTATE; }
+  // every table the step kernels read must be in place (a missing one is a host error, never
+  // a launch)
+  if (s->delivery == DPSNN_DELIVERY_ARRIVAL &&
+      (!s->tile_order || !s->tile_cinfo || !s->tile_ncols || !s->tile_pinfo || !s->tile_net ||
+       !s->tile_base || !s->tile_npairs || !s->tile_slots || !s->tile_work || !s->hist_st ||
+       !s->hist_go || !s->d_gath || !s->d_gdone || (s->cfg.stdp && (!s->rev || !s->sp_x)))) {
+    s->err = "step tables are missing";
+    return DPSNN_ESTATE;
+  }
   try {
     // with timing on, every kernel launch of the step loop is bracketed by HIP events on
     // the simulation's stream; class 0 = update (fused with delivery in the arrival form),
