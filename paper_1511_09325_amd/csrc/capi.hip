@@ -1046,8 +1046,8 @@ int create_impl(const sim_config_t* cfg, const sim_buffers_t* bufs, void* hip_st
     s->d_digest = (uint64_t*)dalloc(*s, sizeof(uint64_t));
     s->col_spk = (unsigned long long*)dalloc(*s, sizeof(unsigned long long) * (size_t)s->n_cols);
     s->d_gath = (int64_t*)dalloc(*s, sizeof(int64_t));
-    s->d_gdone = (uint32_t*)dalloc(*s, sizeof(uint32_t));
-    HIPCHK(hipMemsetAsync(s->d_gdone, 0, sizeof(uint32_t), s->stream));
+    s->d_gdone = (uint32_t*)dalloc(*s, sizeof(uint32_t) * 2);
+    HIPCHK(hipMemsetAsync(s->d_gdone, 0, sizeof(uint32_t) * 2, s->stream));
     set_gather(*s, 0);
     HIPCHK(hipMemsetAsync(s->col_spk, 0, sizeof(unsigned long long) * (size_t)s->n_cols, s->stream));
     HIPCHK(hipMemsetAsync(s->hist_cnt, 0, sizeof(int32_t) * (size_t)s->dh * s->n_cols, s->stream));

@@ -211,7 +211,7 @@ struct StepArgs {
   uint64_t* hist_st;
   uint16_t* hist_go;
   // arrival form: steps gathered per window, accumulators of later steps, last gathering
-  // step, finished-workgroup counter
+  // step, finished workgroups and next tile of a tile launch
   int32_t gk;
   int32_t* acc_save;          // [gk][N]
   int64_t* gath;
@@ -339,7 +339,7 @@ struct sim {
   int32_t gather_req = 0;          // requested gather_steps (0: automatic)
   int32_t* acc_save = nullptr;     // [gk][N] accumulators of the later steps of a window
   int64_t* d_gath = nullptr;       // last gathering step, -1 when acc_save is not valid
-  uint32_t* d_gdone = nullptr;     // finished workgroups of a gathering launch
+  uint32_t* d_gdone = nullptr;     // [0] finished workgroups of a tile launch, [1] next tile
   int32_t* ring = nullptr;
   unsigned long long* net_cnt = nullptr;
   // plasticity (cfg.stdp)

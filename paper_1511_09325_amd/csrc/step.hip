@@ -23,6 +23,9 @@
 //            that scatters each spiking row into ring[(u + d) % DH][target] with
 //            device-scope integer atomics.
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "dpsnn_internal.h"
 
@@ -244,14 +247,14 @@ __device__ __forceinline__ int32_t item_delays(const StepArgs& a, bool light, in
   return hi >= lo ? hi - lo + 1 : 0;
 }
 
-// Workgroup order of the tile kernel: tiles by decreasing synapse records read at the last
-// gathering step.  Workgroups start in index order as compute units free up, so the largest
-// tiles start first and the smallest fill the end (longest-first list scheduling); the spread
-// of work between tiles follows the spatial spread of firing rates.  A counting sort over
-// BLOCK buckets of the work scaled to the largest.  Workgroup b runs on XCD b mod 8, so the
-// ranks are dealt to the XCDs in a snake (ranks 8k .. 8k + 7 to XCDs 0..7 for even k, 7..0
-// for odd k), which keeps their shares of the work even.  Run by one workgroup, after every
-// other workgroup of the launch has finished; the results do not depend on the order.
+// Order of the tile kernel's tiles: by decreasing synapse records read at the last gathering
+// step, so that the largest tiles start first and the smallest fill the end (longest-first
+// list scheduling); the spread of work between tiles follows the spatial spread of firing
+// rates.  A counting sort over BLOCK buckets of the work scaled to the largest.  Workgroup b
+// of a launch starts on XCD b mod 8, so the ranks are dealt to the XCDs in a snake (ranks
+// 8k .. 8k + 7 to XCDs 0..7 for even k, 7..0 for odd k), which keeps their shares of the
+// work even.  Run by one workgroup, after every other workgroup of the launch has finished;
+// the results do not depend on the order.
 template <int BLOCK>
 __device__ void order_tiles(const StepArgs& a, int32_t* cnt, int32_t* wsum) {
   constexpr int NW = BLOCK / 64;
@@ -365,7 +368,23 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
   const int64_t nall = (int64_t)a.n_cols * npc;
   const int32_t u_slot = (int32_t)(u % a.dh);
   const int64_t light_save = light ? (u % K) * nall : 0;  // this step's saved accumulator
-  for (int32_t b = blockIdx.x; b < a.grid_tiles; b += gridDim.x) {
+  // Workgroup b runs entry b of tile_order.  With more tiles than the device holds
+  // workgroups at once, the launch has only as many workgroups, and each one that finishes
+  // takes the next entry from a device counter (gdone[1]): every compute unit takes the next
+  // tile as soon as it is free, whichever XCD it sits in (list scheduling, largest measured
+  // work first; the first round needs no counter, so that the launch does not start with
+  // every workgroup contending for one address).  The last workgroup to finish resets it.
+  const bool handout = (int32_t)gridDim.x < a.grid_tiles;
+  __shared__ int32_t s_b;
+  for (int32_t b_own = blockIdx.x;; b_own += gridDim.x) {
+    int32_t b = b_own;
+    if (handout && b_own >= (int32_t)gridDim.x) {
+      if (tid == 0) s_b = (int32_t)gridDim.x + (int32_t)atomicAdd(a.gdone + 1, 1u);
+      __syncthreads();
+      b = s_b;
+      __syncthreads();
+    }
+    if (b >= a.grid_tiles) break;
     const int32_t tile = a.tile_order[b];
     if (tile < 0) continue;
     const int T = a.tile_ncols[tile];
@@ -772,21 +791,24 @@ __global__ __launch_bounds__(BLOCK, 4) void k_step_tile(StepArgs a, int64_t u_ar
     }
     __syncthreads();
   }
-  // The last workgroup to finish a gathering step records it (every workgroup has read
-  // *gath) and orders the tiles by the work just measured for the following steps.
-  if (!light) {
+  // The last workgroup to finish resets the tile counter; after a gathering step it also
+  // records the step (every workgroup has read *gath) and orders the tiles by the work just
+  // measured for the following steps, which the other workgroups' release fences publish.
+  // A light step without the counter needs none of this.
+  if (!light || handout) {
     __shared__ int32_t s_last;
     if (tid == 0) {
-      __threadfence();
+      if (!light) __threadfence();
       s_last = atomicAdd(a.gdone, 1u) == gridDim.x - 1;
       if (s_last) {
-        if (full_window) *a.gath = u;
-        *a.gdone = 0u;
+        if (!light && full_window) *a.gath = u;
+        a.gdone[1] = 0u;
+        a.gdone[0] = 0u;
         __threadfence();
       }
     }
     __syncthreads();
-    if (s_last && a.order_by_work) order_tiles<BLOCK>(a, it_pref, wsum);
+    if (!light && s_last && a.order_by_work) order_tiles<BLOCK>(a, it_pref, wsum);
   }
 }
 
@@ -920,22 +942,45 @@ __global__ void k_init_state(StepArgs a, int32_t model) {
   }
 }
 
+// Workgroups of one kernel that device `dev` holds at once: its compute units times the
+// workgroups of `block` threads with `lds` bytes of dynamic LDS that fit on one (cached per
+// device, kernel and LDS size; 0 when the query fails).
+static int resident_workgroups(int dev, const void* fn, int block, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, size_t>, int> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(dev, fn, lds);
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, n_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    per_cu = 0;
+    n_cu = 0;
+  }
+  return cache[key] = std::max(per_cu, 0) * std::max(n_cu, 0);
+}
+
+template <int BLOCK, bool TRAIN, int MODEL, bool PLAST>
+void launch_tile_k(const sim& s, const StepArgs& a, int64_t u, int32_t kacc, size_t lds) {
+  const void* fn = (const void*)k_step_tile<BLOCK, TRAIN, MODEL, PLAST>;
+  const int res = resident_workgroups(s.device, fn, BLOCK, lds);
+  const int32_t nwg = res > 0 ? std::min(s.grid_tiles, res) : s.grid_tiles;
+  hipLaunchKernelGGL((k_step_tile<BLOCK, TRAIN, MODEL, PLAST>), dim3(std::max(nwg, 1)), dim3(BLOCK),
+                     lds, s.stream, a, u, s.tile_max_cols, kacc);
+}
+
 template <int BLOCK, bool PLAST>
 void launch_tile_p(const sim& s, const StepArgs& a, int64_t u, int32_t kacc, bool train) {
   const size_t lds = tile_lds_bytes(s, kacc);
-  const dim3 grid(s.grid_tiles), block(BLOCK);
   if (train)  // train mode runs the LIF neuron with one AHP variable only
-    hipLaunchKernelGGL((k_step_tile<BLOCK, true, kModelLif, false>), grid, block, lds, s.stream,
-                       a, u, s.tile_max_cols, kacc);
+    launch_tile_k<BLOCK, true, kModelLif, false>(s, a, u, kacc, lds);
   else if (s.model == kModelLifNa)
-    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelLifNa, PLAST>), grid, block, lds,
-                       s.stream, a, u, s.tile_max_cols, kacc);
+    launch_tile_k<BLOCK, false, kModelLifNa, PLAST>(s, a, u, kacc, lds);
   else if (s.model == kModelIzh)
-    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelIzh, PLAST>), grid, block, lds, s.stream,
-                       a, u, s.tile_max_cols, kacc);
+    launch_tile_k<BLOCK, false, kModelIzh, PLAST>(s, a, u, kacc, lds);
   else
-    hipLaunchKernelGGL((k_step_tile<BLOCK, false, kModelLif, PLAST>), grid, block, lds, s.stream,
-                       a, u, s.tile_max_cols, kacc);
+    launch_tile_k<BLOCK, false, kModelLif, PLAST>(s, a, u, kacc, lds);
 }
 
 template <int BLOCK>
