@@ -225,3 +225,23 @@ def test_gather_window_interrupted():
     sim.set_launch(gather_steps=3, graph_steps=0)
     sim.step(T - 117)
     _check_run(sim, ref, T)
+
+
+@pytest.mark.parametrize("graph", [0, 9], ids=["direct", "graph9"])
+def test_more_tiles_than_resident_workgroups(graph):
+    """576 tiles (a 24x24 grid of 1x1 tiles) in 1024-thread workgroups, one per compute unit,
+    and 512-thread ones at the steps inside a window, two per compute unit: more tiles than
+    the device holds workgroups at once, so every launch hands tiles out from its device
+    counter (direct launches and graph chunks that cross gather windows)."""
+    import torch
+    assert 576 > 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    p = W.tiny(24, 24, npc=40, seed=23)
+    T = 300
+    ref = oracle.Sim(p)
+    ref.step(T)
+    sim = Simulation(p, block=1024, tile=(1, 1), record_steps=T, gather_steps=4)
+    if graph:
+        sim.set_launch(graph_steps=graph)
+    sim.step(T)
+    assert ref.counts()["spikes"] > 10000
+    _check_run(sim, ref, T)
