@@ -14,11 +14,12 @@
 //   delivery each synapse (delay d) of a spike at step u contributes at step u + d
 //
 // Two delivery strategies, bit-identical because the input is an integer sum:
-//   ARRIVAL  one workgroup per tile of up to 4x4 target columns.  At step u it gathers,
-//            from the spike history of every column with synapses into the tile, the delay
-//            group (i, d) of every neuron i that spiked at u - d, keeps the synapses whose
-//            target lies in the tile, accumulates them in LDS with integer atomics, then
-//            updates the tile's neurons -- one fused kernel, no ring in HBM.
+//   ARRIVAL  a workgroup works on one tile of up to 4x4 target columns at a time (and takes
+//            further tiles when there are more than the device holds workgroups).  At step
+//            u it gathers, from the spike history of every column with synapses into the
+//            tile, the delay group (i, d) of every neuron i that spiked at u - d, keeps the
+//            synapses whose target lies in the tile, accumulates them in LDS with integer
+//            atomics, then updates the tile's neurons -- one fused kernel, no ring in HBM.
 //   PUSH     update kernel reading a delay ring ring[u % DH][j], then a delivery kernel
 //            that scatters each spiking row into ring[(u + d) % DH][target] with
 //            device-scope integer atomics.
