@@ -94,6 +94,22 @@ def test_paper_recipe_foreign_tiling_and_batched():
         _same(sim, p, T, net=n)
 
 
+def test_paper_recipe_more_tiles_than_resident_workgroups():
+    """The 7x7 stencil launched over 600 single-column tiles (a 20x30 grid, a tiling other
+    than the store's) in 1024-thread workgroups: more tiles than the device holds workgroups
+    at once at both launch shapes (one per compute unit gathering, two inside a window), so
+    tiles come from the launch's device counter."""
+    import torch
+    assert 600 > 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    p = _tiny(20, 30, npc=24, seed=29)
+    T = 150
+    sim = Simulation(p, record_steps=T, block=1024)
+    sim.set_launch(tile=(1, 1), gather_steps=3)
+    assert sim.get_launch()["tile"] == (1, 1) and sim.get_launch()["gather_steps"] == 3
+    sim.step(T)
+    assert _same(sim, p, T) > 1000
+
+
 def test_tiling_with_parts_of_more_than_nine_columns_is_refused():
     p = _tiny(8, 8, npc=20)
     with pytest.raises(RuntimeError, match="9 columns"):
