@@ -945,7 +945,8 @@ __global__ void k_init_state(StepArgs a, int32_t model) {
 
 // Workgroups of one kernel that device `dev` holds at once: its compute units times the
 // workgroups of `block` threads with `lds` bytes of dynamic LDS that fit on one (cached per
-// device, kernel and LDS size; 0 when the query fails).
+// device, kernel and LDS size; 0 when the query fails, which is not cached, so that a later
+// call asks again).
 static int resident_workgroups(int dev, const void* fn, int block, size_t lds) {
   static std::mutex mu;
   static std::map<std::tuple<int, const void*, size_t>, int> cache;
@@ -955,11 +956,12 @@ static int resident_workgroups(int dev, const void* fn, int block, size_t lds) {
   if (it != cache.end()) return it->second;
   int per_cu = 0, n_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, lds) != hipSuccess ||
-      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-    per_cu = 0;
-    n_cu = 0;
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      per_cu <= 0 || n_cu <= 0) {
+    (void)hipGetLastError();  // a failed query leaves no error for the launch to report
+    return 0;
   }
-  return cache[key] = std::max(per_cu, 0) * std::max(n_cu, 0);
+  return cache[key] = per_cu * n_cu;
 }
 
 template <int BLOCK, bool TRAIN, int MODEL, bool PLAST>
