@@ -227,15 +227,20 @@ def test_gather_window_interrupted():
     _check_run(sim, ref, T)
 
 
-@pytest.mark.parametrize("graph", [0, 9], ids=["direct", "graph9"])
-def test_more_tiles_than_resident_workgroups(graph):
-    """576 tiles (a 24x24 grid of 1x1 tiles) in 1024-thread workgroups, one per compute unit,
-    and 512-thread ones at the steps inside a window, two per compute unit: more tiles than
-    the device holds workgroups at once, so every launch hands tiles out from its device
-    counter (direct launches and graph chunks that cross gather windows)."""
+@pytest.mark.parametrize("rows,cols,graph", [(24, 24, 0), (24, 24, 9), (15, 20, 0)],
+                         ids=["576-direct", "576-graph9", "300-direct"])
+def test_more_tiles_than_resident_workgroups(rows, cols, graph):
+    """Grids of 1x1 tiles in 1024-thread workgroups, one per compute unit, and 512-thread ones
+    at the steps inside a window, two per compute unit.  576 tiles are more than the device
+    holds workgroups at once for either launch, so every launch hands tiles out from its
+    device counter (direct launches and graph chunks that cross gather windows); 300 tiles
+    are more only for the gathering launches, whose counter then alternates with light
+    launches of one workgroup per tile."""
     import torch
-    assert 576 > 2 * torch.cuda.get_device_properties(0).multi_processor_count
-    p = W.tiny(24, 24, npc=40, seed=23)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    assert rows * cols > n_cu
+    assert (rows * cols > 2 * n_cu) == (rows * cols == 576)
+    p = W.tiny(rows, cols, npc=40, seed=23)
     T = 300
     ref = oracle.Sim(p)
     ref.step(T)
